@@ -1,0 +1,205 @@
+/*
+ * clod.h -- C ABI of libclod, the MI355X (gfx950) render path of CLoD-GS
+ * (continuous level of detail for 3D Gaussian splatting, arXiv 2510.09997).
+ *
+ * Conventions for every call
+ *   - Pointers are DEVICE pointers owned by the caller unless a comment says "host".  The
+ *     library never allocates, frees or retains device memory; it carves the two caller
+ *     workspaces described by clod_batch.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = default stream) and
+ *     returns before it completes.  Only clod_bin_sort with a non-NULL `n_dup_host` and
+ *     clod_read_info synchronise the stream.
+ *   - Argument errors are detected on the host before anything is launched and return
+ *     CLOD_E_ARG; clod_last_error() then names the argument.  A HIP launch failure returns
+ *     CLOD_E_HIP.  Duplicate-buffer overflow is detected on the device; see clod_bin_sort.
+ *   - Every floating-point step follows the binary32 arithmetic contract (operation order,
+ *     fused multiply-adds only where specified, correctly rounded division and square root,
+ *     a fixed polynomial exponential), so integer results (keys, order, ranges, counts,
+ *     last-contributor indices) are reproducible bit for bit.
+ *   - One clod_batch (and its workspaces) per stream at a time; the library keeps no other
+ *     state, except the thread-local error message.
+ *
+ * Layouts ("plane-major" structure of arrays, n = number of Gaussians):
+ *   mean [3][n], log_scale [3][n], quat [4][n] (w, x, y, z), opacity [n] (logit),
+ *   decay [n] (sigma_d), sh [(deg+1)^2][3][n].  Gradients use the same layout.
+ *   Images of a batch of views are concatenated: view v starts at pixel offset
+ *   P_v = sum_{u<v} H_u W_u; rgb holds [3][H_v][W_v] at 3 P_v, T and last hold [H_v][W_v] at P_v.
+ */
+#ifndef CLOD_H
+#define CLOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CLOD_ABI_VERSION 1
+#define CLOD_MAX_VIEWS 1024
+
+typedef enum {
+  CLOD_OK = 0,
+  CLOD_E_ARG = -1,       /* invalid argument (host check, nothing launched)           */
+  CLOD_E_CAPACITY = -2,  /* more tile duplicates than the duplicate buffer holds       */
+  CLOD_E_HIP = -3,       /* a HIP runtime call or kernel launch failed                  */
+  CLOD_E_UNSUPPORTED = -4
+} clod_status;
+
+/* A scene: n Gaussians (Sec. 3.1: mean, covariance from scale and rotation, opacity, SH
+   colour coefficients) plus the one extra learnable decay factor sigma_d of Sec. 3.2. */
+typedef struct clod_scene {
+  int64_t n;              /* >= 0 */
+  int32_t sh_degree;      /* 0..3 */
+  int32_t reserved;
+  const float *mean, *log_scale, *quat, *opacity, *decay, *sh;
+} clod_scene;
+
+/* Gradient planes, same layout as clod_scene; all must be non-NULL. */
+typedef struct clod_scene_grad {
+  float *mean, *log_scale, *quat, *opacity, *decay, *sh;
+} clod_scene_grad;
+
+/* One view: a pinhole camera (OpenCV axes: x right, y down, z forward; pixel (i, j) covers
+   [i, i+1) x [j, j+1) and is sampled at its centre) and the virtual distance scale s_v >= 1
+   of Sec. 3.2 (it strengthens the decay and the mask threshold; it does not move the camera).
+   96 bytes. */
+typedef struct clod_view {
+  float W[9];             /* world-to-camera rotation, row-major */
+  float t[3];             /* world-to-camera translation */
+  float c[3];             /* camera centre (the c of d_i = |mu_i - c|, Sec. 3.2); must equal -W^T t to 1e-4 relative */
+  float fx, fy, cx, cy;   /* intrinsics in pixels */
+  int32_t width, height;  /* 1..16384 */
+  float s_v;              /* virtual distance scale, finite, >= 1 */
+  float reserved[2];
+} clod_view;
+
+/* Constants the paper leaves open (readings; defaults in parentheses). */
+typedef struct clod_params {
+  float tau;              /* base threshold of the mask alpha'' > tau s_v (1/255), >= 0 */
+  float eps;              /* epsilon of Eq. (2) (1e-6), > 0 */
+  float near_z;           /* frustum near plane (0.2), > 0 */
+  float guard;            /* frustum widening of the half field-of-view tangents (1.3), > 0 */
+  float dilation;         /* EWA screen-space dilation in px^2 (0.3), >= 0 */
+  float bg[3];            /* background colour (0) */
+} clod_params;
+
+/* A batch of views rendered together (continuous batching and multi-view training use
+   n_views > 1; resolutions may differ).  All fields are host values except the device
+   pointers marked so. */
+typedef struct clod_batch {
+  int64_t n;                       /* Gaussians of the scene this batch renders (= scene->n) */
+  int32_t n_views;                 /* 1..CLOD_MAX_VIEWS */
+  int32_t reserved;
+  const clod_view *views_host;     /* host: n_views entries (validation, launch geometry) */
+  const clod_view *views_dev;      /* device: the same n_views entries, read by the kernels;
+                                      poses and s_v may be rewritten between graph replays,
+                                      width/height must stay equal to views_host */
+  clod_params params;
+  void *ws;  size_t ws_bytes;      /* device workspace, >= clod_ws_bytes(), 256-byte aligned */
+  void *dup; size_t dup_bytes;     /* device duplicate buffer, clod_dup_bytes(capacity) */
+} clod_batch;
+
+/* Bytes of the per-Gaussian / per-view / per-tile workspace for n Gaussians and these views. */
+size_t clod_ws_bytes(int64_t n, int32_t n_views, const clod_view *views_host);
+
+/* Bytes of a duplicate buffer holding `capacity` (tile, Gaussian) pairs (keys, values,
+   ping-pong copies and radix histograms). */
+size_t clod_dup_bytes(int64_t capacity);
+
+/* Largest capacity that fits in dup_bytes. */
+int64_t clod_dup_capacity(size_t dup_bytes);
+
+/* Sec. 3.2 and Sec. 3.1 (projection): for every view and Gaussian, camera distance d_i, the
+   frustum set N_view and its maximum distance (argmax = lowest index among equals; an empty
+   frustum uses 1), normalised distance d'_i, attenuated opacity of Eq. (2), LoD mask
+   M_i = alpha''_i > tau s_v, and for M_i and in-frustum Gaussians the EWA projection, cull,
+   16x16-tile rectangle and SH colour.  counts_dev (nullable, device int64 [n_views][3])
+   receives {n_frustum, n_mask, n_rendered}; eta_actual of Sec. 3.3 is n_mask / n.
+   The results stay in batch->ws for the calls below. */
+clod_status clod_project(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
+                         void *stream);
+
+/* Sec. 3.1 ("sorted by depth"): exclusive scan of tiles touched, one key per (rendered
+   Gaussian, covered tile) emitted in Gaussian-index order, key = (tile_base[view] + tile) << 32
+   | bits(depth), stable LSD radix sort of the keys, and per-tile [start, end) ranges of the
+   sorted list.  If more pairs exist than the duplicate buffer holds, nothing is written beyond
+   it, the overflow is recorded in ws and later calls on this batch are no-ops; with
+   n_dup_host != NULL the call synchronises `stream`, stores the pair count D (also on
+   overflow) and returns CLOD_E_CAPACITY on overflow (enlarge batch->dup and call again; the
+   clod_project results stay valid). */
+clod_status clod_bin_sort(const clod_batch *batch, int64_t *n_dup_host, void *stream);
+
+/* Sec. 3.1, Eq. (1): per pixel, front-to-back blending of its tile's sorted list with
+   alpha'_i = alpha''_i G2D_i (clamped to 0.99, skipped below 1/255), stopping before the
+   entry that would bring transmittance below 1e-4.  Writes rgb (colour + T * bg), the final
+   transmittance T and last = 1 + position (within the tile's list) of the last blended entry
+   (0 if none).  pairs_dev (nullable, device int64 [1]) is incremented by the number of
+   (pixel, entry) pairs evaluated. */
+clod_status clod_render_fwd(const clod_batch *batch, float *rgb, float *T, uint32_t *last,
+                            int64_t *pairs_dev, void *stream);
+
+/* Adjoint of clod_project + clod_render_fwd (the method is end-to-end differentiable,
+   Sec. 1 and Sec. 3.2).  Given dL/drgb (same layout as rgb) and optionally dL/deta
+   (device float [n_views]: the straight-through gradient of the point-count term, applied
+   as d eta / d alpha''_i = 1 / n for every Gaussian), recomputes each pixel's blend
+   back-to-front from its stored last index and T, and writes (accumulate = 0) or adds
+   (accumulate != 0) the gradients of all parameter planes, including the decay factor and the
+   normalised distance through the virtual distance scale and the frustum maximum.
+   Requires the same scene and batch as the preceding clod_project / clod_bin_sort /
+   clod_render_fwd. */
+clod_status clod_render_bwd(const clod_scene *scene, const clod_batch *batch, const float *T,
+                            const uint32_t *last, const float *dL_drgb, const float *dL_deta,
+                            int32_t accumulate, const clod_scene_grad *grad, void *stream);
+
+/* Sec. 3.2 mask and Sec. 3.3 eta_actual for many views without rendering: counts_dev
+   (device int64 [n_views][3]) receives {n_frustum, n_mask, n_rendered} per view, with the
+   same decisions as clod_project.  Uses batch->ws (per-view area only; clod_ws_bytes with
+   n = 0 suffices); batch->dup is not used. */
+clod_status clod_lod_count(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
+                           void *stream);
+
+/* Sec. 3.3, Eq. (3)-(5) with L_render = L1: per view v,
+   L1_v = mean |rgb - target| over 3 H W, eta_v = n_mask / batch->n (from the last clod_project),
+   eta_target = s_v^-1.5, L_reg = (s_v - 1)^2 ReLU(eta_v - eta_target)^2,
+   w_s = (1 - 0.5 s_v / s_max)^2, L_v = w_s (L1_v + lambda L_reg).
+   Writes loss_dev (device float [n_views]), dL_drgb = w_s sign(rgb - target) / (3 H W)
+   (sign(0) = 0) and dL_deta_dev (device float [n_views]) = w_s lambda dL_reg/deta. */
+clod_status clod_loss(const clod_batch *batch, const float *rgb, const float *target,
+                      float s_max, float lambda_reg, float *loss_dev, float *dL_drgb,
+                      float *dL_deta_dev, void *stream);
+
+/* Synchronises `stream` and copies to host info[4] = {D (tile pairs of the last
+   clod_bin_sort), overflow flag, duplicate capacity, radix passes}. */
+clod_status clod_read_info(const clod_batch *batch, int64_t *info_host, void *stream);
+
+/* Read-only views of intermediate results (for inspection and tests).  Stores the device
+   address of the section and its element count; nothing is launched or copied.
+     CLOD_SEC_KEYS     uint64 sorted (tile, depth) keys   (count = duplicate capacity; the
+                       first D are valid, D from clod_bin_sort or clod_read_info)
+     CLOD_SEC_VALUES   uint32 sorted record indices v*n + i (count as above)
+     CLOD_SEC_RANGES   uint32 pairs [start, end) per tile of the batch (count = tiles)
+     CLOD_SEC_REC0/1/2 float4 records per (view, Gaussian): (u, v, alpha'', depth),
+                       (conic A, B, C, radius), (r, g, b, 0)  (count = n_views * n)
+     CLOD_SEC_FLAGS    uint8 per (view, Gaussian): bit0 frustum, bit1 mask, bit2 rendered,
+                       bits 3..5 colour clamped
+     CLOD_SEC_DMAX     uint64 per view: bits(d_max) << 32 | (2^32 - 1 - argmax), 0 if empty
+     CLOD_SEC_RECT     uint32 pairs per (view, Gaussian): x0 | x1 << 16, y0 | y1 << 16
+     CLOD_SEC_GSCREEN  float [9][n_views * n] screen-space partials of the last backward */
+enum {
+  CLOD_SEC_KEYS = 0, CLOD_SEC_VALUES = 1, CLOD_SEC_RANGES = 2, CLOD_SEC_REC0 = 3, CLOD_SEC_REC1 = 4,
+  CLOD_SEC_REC2 = 5, CLOD_SEC_FLAGS = 6, CLOD_SEC_DMAX = 7, CLOD_SEC_RECT = 8, CLOD_SEC_GSCREEN = 9
+};
+clod_status clod_inspect(const clod_batch *batch, int32_t section, const void **dev_ptr,
+                         int64_t *count);
+
+/* Message of the last error on this thread ("" if none). */
+const char *clod_last_error(void);
+
+int32_t clod_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLOD_H */

@@ -37,7 +37,8 @@ DEFAULT_PARAMS = dict(tau=1.0 / 255.0, eps=1e-6, near=0.2, guard=1.3, dilation=0
                       bg=(0.0, 0.0, 0.0))
 SKIP_ALPHA = 1.0 / 255.0
 T_MIN = 1e-4
-ALPHA_CLAMP = 0.99
+# The clamp value is the binary32 number 0.99f of the contract; the FP64 replay uses it too.
+ALPHA_CLAMP = float(np.float32(0.99))
 
 
 def build(force: bool = False) -> str:
@@ -420,7 +421,11 @@ def fp64_grads(scene: dict, view, vp: dict, dL_drgb: np.ndarray, dL_deta: float,
 
 
 def grad_rel_error(g: np.ndarray, r: np.ndarray) -> float:
-    """max_i |g_i - r_i| / max(|r_i|, 1e-3 max_j |r_j|)  (per parameter plane set)."""
+    """Relative error of a gradient tensor in the max norm: max_i |g_i - r_i| / max_j |r_j|.
+
+    An element-wise relative error is not meaningful for gradients that are sums of many
+    binary32 terms of both signs: the rounding bound of such a sum scales with sum |terms|,
+    not with the (possibly much smaller) result."""
     g = np.asarray(g, dtype=np.float64).ravel()
     r = np.asarray(r, dtype=np.float64).ravel()
     if r.size == 0:
@@ -428,8 +433,15 @@ def grad_rel_error(g: np.ndarray, r: np.ndarray) -> float:
     scale = np.abs(r).max()
     if scale == 0.0:
         return float(np.abs(g).max())
-    den = np.maximum(np.abs(r), 1e-3 * scale)
-    return float((np.abs(g - r) / den).max())
+    return float(np.abs(g - r).max() / scale)
+
+
+def grad_l2_error(g: np.ndarray, r: np.ndarray) -> float:
+    """||g - r||_2 / ||r||_2."""
+    g = np.asarray(g, dtype=np.float64).ravel()
+    r = np.asarray(r, dtype=np.float64).ravel()
+    nr = np.linalg.norm(r)
+    return float(np.linalg.norm(g - r) / nr) if nr > 0 else float(np.linalg.norm(g))
 
 
 def num_threads() -> int:

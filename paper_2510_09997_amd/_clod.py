@@ -1,0 +1,234 @@
+"""ctypes binding of libclod (include/clod.h).  Argument marshalling only: every step of the
+render path runs in the HIP library; torch supplies device memory and streams.
+
+The functions keep the C names; they take torch tensors (device memory) and raise
+``ClodError`` on a non-zero status.  Importing this module does not load the library;
+the first call does, and fails loudly if libclod.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libclod.so")
+
+CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
+MAX_VIEWS = 1024
+ABI_VERSION = 1
+
+
+class ClodError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libclod status {status}: {msg}")
+        self.status = status
+
+
+class CapacityError(ClodError):
+    pass
+
+
+P = ctypes.c_void_p
+
+
+class clod_scene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mean", P), ("log_scale", P), ("quat", P), ("opacity", P), ("decay", P), ("sh", P)]
+
+
+class clod_scene_grad(ctypes.Structure):
+    _fields_ = [("mean", P), ("log_scale", P), ("quat", P), ("opacity", P), ("decay", P), ("sh", P)]
+
+
+class clod_view(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("c", ctypes.c_float * 3),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("s_v", ctypes.c_float),
+                ("reserved", ctypes.c_float * 2)]
+
+
+class clod_params(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_float), ("eps", ctypes.c_float), ("near_z", ctypes.c_float),
+                ("guard", ctypes.c_float), ("dilation", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+
+
+class clod_batch(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_views", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("views_host", P), ("views_dev", P), ("params", clod_params),
+                ("ws", P), ("ws_bytes", ctypes.c_size_t), ("dup", P), ("dup_bytes", ctypes.c_size_t)]
+
+
+assert ctypes.sizeof(clod_view) == 96
+
+EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project", "clod_bin_sort",
+           "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
+           "clod_inspect", "clod_last_error", "clod_abi_version"]
+
+SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC0, SEC_REC1, SEC_REC2, SEC_FLAGS, SEC_DMAX, SEC_RECT, SEC_GSCREEN = range(10)
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libclod.so (no fallback: raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2510_09997_amd/build.py "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(path)
+    i64, i32, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    L.clod_ws_bytes.argtypes = [i64, i32, P]; L.clod_ws_bytes.restype = sz
+    L.clod_dup_bytes.argtypes = [i64]; L.clod_dup_bytes.restype = sz
+    L.clod_dup_capacity.argtypes = [sz]; L.clod_dup_capacity.restype = i64
+    L.clod_project.argtypes = [P, P, P, P]; L.clod_project.restype = i32
+    L.clod_bin_sort.argtypes = [P, P, P]; L.clod_bin_sort.restype = i32
+    L.clod_render_fwd.argtypes = [P, P, P, P, P, P]; L.clod_render_fwd.restype = i32
+    L.clod_render_bwd.argtypes = [P, P, P, P, P, P, i32, P, P]; L.clod_render_bwd.restype = i32
+    L.clod_lod_count.argtypes = [P, P, P, P]; L.clod_lod_count.restype = i32
+    L.clod_loss.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, P, P, P, P]; L.clod_loss.restype = i32
+    L.clod_read_info.argtypes = [P, P, P]; L.clod_read_info.restype = i32
+    L.clod_inspect.argtypes = [P, i32, P, P]; L.clod_inspect.restype = i32
+    L.clod_last_error.argtypes = []; L.clod_last_error.restype = ctypes.c_char_p
+    L.clod_abi_version.argtypes = []; L.clod_abi_version.restype = i32
+    if L.clod_abi_version() != ABI_VERSION:
+        raise RuntimeError("libclod ABI version mismatch")
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != CLOD_OK:
+        msg = load().clod_last_error().decode()
+        if status == CLOD_E_CAPACITY:
+            raise CapacityError(status, msg)
+        raise ClodError(status, msg)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return t.data_ptr()
+    return int(t)
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+# ------------------------------------------------------------------------------- structs
+
+def make_scene(planes: dict) -> clod_scene:
+    """planes: dict of contiguous float32 device tensors in the C layout (see clod.h)."""
+    s = clod_scene()
+    s.n = int(planes["n"])
+    s.sh_degree = int(planes["sh_degree"])
+    for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh"):
+        setattr(s, k, _ptr(planes[k]))
+    return s
+
+
+def make_grad(planes: dict) -> clod_scene_grad:
+    g = clod_scene_grad()
+    for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh"):
+        setattr(g, k, _ptr(planes[k]))
+    return g
+
+
+def make_views(views) -> ctypes.Array:
+    """Host array of clod_view from objects with W, t, c, fx, fy, cx, cy, width, height, s_v."""
+    arr = (clod_view * len(views))()
+    for j, v in enumerate(views):
+        cv = arr[j]
+        W = np.asarray(v.W, dtype=np.float32).reshape(9)
+        for k in range(9):
+            cv.W[k] = float(W[k])
+        for k in range(3):
+            cv.t[k] = float(np.float32(v.t[k]))
+            cv.c[k] = float(np.float32(v.c[k]))
+        cv.fx, cv.fy, cv.cx, cv.cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
+        cv.width, cv.height = int(v.width), int(v.height)
+        cv.s_v = float(v.s_v)
+    return arr
+
+
+def views_to_device(arr: ctypes.Array, device="cuda") -> torch.Tensor:
+    raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+    return torch.from_numpy(raw).to(device)
+
+
+def make_params(tau=1.0 / 255.0, eps=1e-6, near=0.2, guard=1.3, dilation=0.3, bg=(0.0, 0.0, 0.0)) -> clod_params:
+    p = clod_params()
+    p.tau, p.eps, p.near_z, p.guard, p.dilation = tau, eps, near, guard, dilation
+    for k in range(3):
+        p.bg[k] = float(bg[k])
+    return p
+
+
+# ------------------------------------------------------------------------------- entry points
+
+def clod_ws_bytes(n: int, views_host) -> int:
+    return int(load().clod_ws_bytes(n, len(views_host), ctypes.cast(views_host, P)))
+
+
+def clod_dup_bytes(capacity: int) -> int:
+    return int(load().clod_dup_bytes(capacity))
+
+
+def clod_dup_capacity(nbytes: int) -> int:
+    return int(load().clod_dup_capacity(nbytes))
+
+
+def clod_project(scene: clod_scene, batch: clod_batch, counts=None, stream=None):
+    _check(load().clod_project(ctypes.byref(scene), ctypes.byref(batch), _ptr(counts), _stream(stream)))
+
+
+def clod_bin_sort(batch: clod_batch, sync_count: bool = False, stream=None) -> int | None:
+    n = ctypes.c_int64(0)
+    _check(load().clod_bin_sort(ctypes.byref(batch), ctypes.byref(n) if sync_count else None, _stream(stream)))
+    return int(n.value) if sync_count else None
+
+
+def clod_render_fwd(batch: clod_batch, rgb, T, last, pairs=None, stream=None):
+    _check(load().clod_render_fwd(ctypes.byref(batch), _ptr(rgb), _ptr(T), _ptr(last), _ptr(pairs),
+                                  _stream(stream)))
+
+
+def clod_render_bwd(scene: clod_scene, batch: clod_batch, T, last, dL_drgb, dL_deta, accumulate: bool,
+                    grad: clod_scene_grad, stream=None):
+    _check(load().clod_render_bwd(ctypes.byref(scene), ctypes.byref(batch), _ptr(T), _ptr(last),
+                                  _ptr(dL_drgb), _ptr(dL_deta), int(bool(accumulate)), ctypes.byref(grad),
+                                  _stream(stream)))
+
+
+def clod_lod_count(scene: clod_scene, batch: clod_batch, counts, stream=None):
+    _check(load().clod_lod_count(ctypes.byref(scene), ctypes.byref(batch), _ptr(counts), _stream(stream)))
+
+
+def clod_loss(batch: clod_batch, rgb, target, s_max: float, lambda_reg: float, loss, dL_drgb, dL_deta,
+              stream=None):
+    _check(load().clod_loss(ctypes.byref(batch), _ptr(rgb), _ptr(target), float(s_max), float(lambda_reg),
+                            _ptr(loss), _ptr(dL_drgb), _ptr(dL_deta), _stream(stream)))
+
+
+def clod_read_info(batch: clod_batch, stream=None) -> dict:
+    out = (ctypes.c_int64 * 4)()
+    _check(load().clod_read_info(ctypes.byref(batch), out, _stream(stream)))
+    return dict(n_dup=int(out[0]), overflow=bool(out[1]), capacity=int(out[2]), passes=int(out[3]))
+
+
+def clod_inspect(batch: clod_batch, section: int) -> tuple[int, int]:
+    """(device address, element count) of an intermediate section (see clod.h)."""
+    ptr = ctypes.c_void_p(0)
+    cnt = ctypes.c_int64(0)
+    _check(load().clod_inspect(ctypes.byref(batch), int(section), ctypes.byref(ptr), ctypes.byref(cnt)))
+    return int(ptr.value or 0), int(cnt.value)

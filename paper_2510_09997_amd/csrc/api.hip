@@ -1,0 +1,427 @@
+// C ABI of libclod: host-side validation, workspace carving and launch sequencing.
+// Nothing here allocates device memory; both workspaces belong to the caller.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "clod_internal.h"
+
+namespace clod {
+
+static thread_local char g_err[512] = "";
+
+static clod_status fail(clod_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+static clod_status hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(CLOD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  return CLOD_OK;
+}
+
+#define HIP_TRY(expr, what)                                   \
+  do {                                                        \
+    clod_status _st = hip_check((expr), (what));              \
+    if (_st != CLOD_OK) return _st;                           \
+  } while (0)
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool finite_f(float x) { return isfinite(x) != 0; }
+
+int sort_passes(uint32_t tiles_total) {
+  int tb = 0;
+  uint32_t m = tiles_total > 0 ? tiles_total - 1 : 0;
+  while (m) { ++tb; m >>= 1; }
+  return (32 + tb + 7) / 8;
+}
+
+int sort_blocks(int64_t cap) {
+  int64_t g = (cap + kSortTile - 1) / kSortTile;
+  if (g < 1) g = 1;
+  if (g > kMaxSortBlocks) g = kMaxSortBlocks;
+  return (int)g;
+}
+
+DupLayout dup_layout(int64_t cap) {
+  DupLayout D;
+  D.cap = cap;
+  size_t o = 0;
+  D.keys0 = o; o = align256(o + (size_t)cap * 8);
+  D.vals0 = o; o = align256(o + (size_t)cap * 4);
+  D.keys1 = o; o = align256(o + (size_t)cap * 8);
+  D.vals1 = o; o = align256(o + (size_t)cap * 4);
+  D.hist = o; o = align256(o + ((size_t)256 * sort_blocks(cap) + 256) * 4);
+  D.total = o;
+  return D;
+}
+
+static clod_status host_views(int32_t V, const clod_view* vh, HostView* hv, uint32_t& tiles_total,
+                              int64_t& pixels_total, uint32_t& loss_blocks) {
+  uint64_t tb = 0, pb = 0, lb = 0;
+  for (int v = 0; v < V; ++v) {
+    const clod_view& c = vh[v];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+      return fail(CLOD_E_ARG, "view %d: width/height must be in 1..16384", v);
+    HostView& h = hv[v];
+    h.width = c.width;
+    h.height = c.height;
+    h.tiles_x = (c.width + kTile - 1) / kTile;
+    h.tiles_y = (c.height + kTile - 1) / kTile;
+    h.tile_base = (uint32_t)tb;
+    h.pix_base = (uint32_t)pb;
+    h.loss_block_base = (uint32_t)lb;
+    h.loss_blocks = (uint32_t)((3ull * c.width * c.height + kLossChunk - 1) / kLossChunk);
+    tb += (uint64_t)h.tiles_x * h.tiles_y;
+    pb += (uint64_t)c.width * c.height;
+    lb += h.loss_blocks;
+    if (tb >= 0xFFFFFFFFull || pb >= 0xFFFFFFFFull) return fail(CLOD_E_ARG, "batch too large (tiles or pixels exceed 2^32)");
+  }
+  tiles_total = (uint32_t)tb;
+  pixels_total = (int64_t)pb;
+  loss_blocks = (uint32_t)lb;
+  return CLOD_OK;
+}
+
+static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pixels_total) {
+  Layout L;
+  L.n = n;
+  L.V = V;
+  L.VN = n * (int64_t)V;
+  L.tiles_total = tiles_total;
+  L.pixels_total = pixels_total;
+  L.scan_blocks = (int32_t)((L.VN + kScanChunk - 1) / kScanChunk);
+  size_t o = 0;
+  L.hdr = o; o = align256(o + kHdrWords * 8);
+  L.vinfo = o; o = align256(o + (size_t)V * sizeof(DevView));
+  L.dmax_key = o; o = align256(o + (size_t)V * 8);
+  L.counts = o; o = align256(o + (size_t)V * 3 * 8);
+  L.gdmax = o; o = align256(o + (size_t)V * 4);
+  L.loss_acc = o; o = align256(o + (size_t)V * 4);
+  L.flags = o; o = align256(o + (size_t)L.VN);
+  L.rec = o; o = align256(o + (size_t)L.VN * 3 * 16);
+  L.rect = o; o = align256(o + (size_t)L.VN * 8);
+  L.tiles = o; o = align256(o + (size_t)L.VN * 4);
+  L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4);
+  L.ranges = o; o = align256(o + (size_t)tiles_total * 8);
+  L.gscreen = o; o = align256(o + (size_t)L.VN * kGscreen * 4);
+  L.total = o;
+  return L;
+}
+
+static clod_status check_params(const clod_params& p) {
+  if (!(finite_f(p.tau) && p.tau >= 0.f)) return fail(CLOD_E_ARG, "params.tau must be finite and >= 0");
+  if (!(finite_f(p.eps) && p.eps > 0.f)) return fail(CLOD_E_ARG, "params.eps must be finite and > 0");
+  if (!(finite_f(p.near_z) && p.near_z > 0.f)) return fail(CLOD_E_ARG, "params.near_z must be finite and > 0");
+  if (!(finite_f(p.guard) && p.guard > 0.f)) return fail(CLOD_E_ARG, "params.guard must be finite and > 0");
+  if (!(finite_f(p.dilation) && p.dilation >= 0.f)) return fail(CLOD_E_ARG, "params.dilation must be finite and >= 0");
+  for (int j = 0; j < 3; ++j)
+    if (!finite_f(p.bg[j])) return fail(CLOD_E_ARG, "params.bg must be finite");
+  return CLOD_OK;
+}
+
+static clod_status check_view(const clod_view& c, int v) {
+  for (int j = 0; j < 9; ++j)
+    if (!finite_f(c.W[j])) return fail(CLOD_E_ARG, "view %d: W not finite", v);
+  for (int j = 0; j < 3; ++j)
+    if (!finite_f(c.t[j]) || !finite_f(c.c[j])) return fail(CLOD_E_ARG, "view %d: t or c not finite", v);
+  if (!(finite_f(c.fx) && c.fx > 0.f && finite_f(c.fy) && c.fy > 0.f && finite_f(c.cx) && finite_f(c.cy)))
+    return fail(CLOD_E_ARG, "view %d: intrinsics must be finite with fx, fy > 0", v);
+  if (!(finite_f(c.s_v) && c.s_v >= 1.0f)) return fail(CLOD_E_ARG, "view %d: s_v must be finite and >= 1", v);
+  double scale = 1.0;
+  for (int j = 0; j < 3; ++j) scale = fmax(scale, fabs((double)c.c[j]));
+  for (int j = 0; j < 3; ++j) {
+    const double cj = -((double)c.W[j] * c.t[0] + (double)c.W[3 + j] * c.t[1] + (double)c.W[6 + j] * c.t[2]);
+    if (fabs(cj - (double)c.c[j]) > 1e-4 * scale)
+      return fail(CLOD_E_ARG, "view %d: camera centre c differs from -W^T t", v);
+  }
+  return CLOD_OK;
+}
+
+struct Ctx {
+  Layout L;
+  HostView hv[CLOD_MAX_VIEWS];
+  uint32_t loss_blocks = 0;
+};
+
+static clod_status prepare(const clod_batch* b, bool need_full_ws, Ctx& cx) {
+  if (!b) return fail(CLOD_E_ARG, "batch is NULL");
+  if (b->n_views < 1 || b->n_views > CLOD_MAX_VIEWS) return fail(CLOD_E_ARG, "n_views must be in 1..%d", CLOD_MAX_VIEWS);
+  if (!b->views_host || !b->views_dev) return fail(CLOD_E_ARG, "views_host and views_dev must be non-NULL");
+  if (!b->ws) return fail(CLOD_E_ARG, "ws is NULL");
+  if (((uintptr_t)b->ws & 255) != 0) return fail(CLOD_E_ARG, "ws must be 256-byte aligned");
+  clod_status st = check_params(b->params);
+  if (st != CLOD_OK) return st;
+  for (int v = 0; v < b->n_views; ++v) {
+    st = check_view(b->views_host[v], v);
+    if (st != CLOD_OK) return st;
+  }
+  uint32_t tiles_total;
+  int64_t pixels_total;
+  st = host_views(b->n_views, b->views_host, cx.hv, tiles_total, pixels_total, cx.loss_blocks);
+  if (st != CLOD_OK) return st;
+  const int64_t n = b->n;
+  if (n < 0) return fail(CLOD_E_ARG, "batch->n must be >= 0");
+  if (n * (int64_t)b->n_views >= 0xFFFFFFFFll) return fail(CLOD_E_ARG, "n * n_views must be < 2^32");
+  cx.L = make_layout(need_full_ws ? n : 0, b->n_views, tiles_total, pixels_total);
+  if (need_full_ws) cx.L.n = n;
+  const size_t need = need_full_ws ? cx.L.total : cx.L.flags;
+  if (b->ws_bytes < need) return fail(CLOD_E_ARG, "ws_bytes %zu < required %zu", b->ws_bytes, need);
+  return CLOD_OK;
+}
+
+static clod_status check_scene(const clod_scene* s) {
+  if (!s) return fail(CLOD_E_ARG, "scene is NULL");
+  if (s->n < 0) return fail(CLOD_E_ARG, "scene.n must be >= 0");
+  if (s->sh_degree < 0 || s->sh_degree > 3) return fail(CLOD_E_ARG, "scene.sh_degree must be in 0..3");
+  if (s->n > 0 && (!s->mean || !s->log_scale || !s->quat || !s->opacity || !s->decay || !s->sh))
+    return fail(CLOD_E_ARG, "scene planes must be non-NULL");
+  return CLOD_OK;
+}
+
+static clod_status dup_check(const clod_batch* b, DupLayout& D) {
+  if (!b->dup) return fail(CLOD_E_ARG, "dup is NULL");
+  if (((uintptr_t)b->dup & 255) != 0) return fail(CLOD_E_ARG, "dup must be 256-byte aligned");
+  const int64_t cap = clod_dup_capacity(b->dup_bytes);
+  if (cap < 1) return fail(CLOD_E_ARG, "dup_bytes too small");
+  D = dup_layout(cap);
+  return CLOD_OK;
+}
+
+}  // namespace clod
+
+using namespace clod;
+
+extern "C" {
+
+int32_t clod_abi_version(void) { return CLOD_ABI_VERSION; }
+
+const char* clod_last_error(void) { return g_err; }
+
+size_t clod_ws_bytes(int64_t n, int32_t n_views, const clod_view* views_host) {
+  if (n < 0 || n_views < 1 || n_views > CLOD_MAX_VIEWS || !views_host) return 0;
+  HostView hv[CLOD_MAX_VIEWS];
+  uint32_t tiles_total, lb;
+  int64_t pixels_total;
+  if (host_views(n_views, views_host, hv, tiles_total, pixels_total, lb) != CLOD_OK) return 0;
+  return make_layout(n, n_views, tiles_total, pixels_total).total;
+}
+
+size_t clod_dup_bytes(int64_t capacity) {
+  if (capacity < 1) capacity = 1;
+  return dup_layout(capacity).total;
+}
+
+int64_t clod_dup_capacity(size_t dup_bytes) {
+  // Largest capacity whose layout fits; the layout grows by ~24 bytes per entry.
+  int64_t lo = 0, hi = (int64_t)(dup_bytes / 24) + 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (mid >= 0xFFFFFFFFll || dup_layout(mid).total > dup_bytes) hi = mid - 1; else lo = mid;
+  }
+  return lo;
+}
+
+clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64_t* counts_dev,
+                         void* stream) {
+  g_err[0] = 0;
+  clod_status st = check_scene(scene);
+  if (st != CLOD_OK) return st;
+  Ctx cx;
+  st = prepare(batch, true, cx);
+  if (st != CLOD_OK) return st;
+  if (scene->n != batch->n) return fail(CLOD_E_ARG, "scene->n (%lld) != batch->n (%lld)", (long long)scene->n, (long long)batch->n);
+  hipStream_t s = (hipStream_t)stream;
+  const Layout& L = cx.L;
+  char* w = (char*)batch->ws;
+  DevView* vinfo = (DevView*)(w + L.vinfo);
+  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, s), "view setup");
+  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.hdr), 0u, kHdrWords * 2, s), "clear header");
+  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.dmax_key), 0u, 2 * (int64_t)L.V, s), "clear dmax");
+  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.counts), 0u, 6 * (int64_t)L.V, s), "clear counts");
+  HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.dmax_key), s),
+          "frustum max");
+  HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
+                         (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags), (float4*)(w + L.rec),
+                         (uint2*)(w + L.rect), (uint32_t*)(w + L.tiles), s),
+          "project");
+  if (counts_dev)
+    HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
+  return CLOD_OK;
+}
+
+clod_status clod_bin_sort(const clod_batch* batch, int64_t* n_dup_host, void* stream) {
+  g_err[0] = 0;
+  Ctx cx;
+  clod_status st = prepare(batch, true, cx);
+  if (st != CLOD_OK) return st;
+  DupLayout D;
+  st = dup_check(batch, D);
+  if (st != CLOD_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Layout& L = cx.L;
+  char* w = (char*)batch->ws;
+  if (L.scan_blocks == 0)
+    HIP_TRY(launch_fill_u32((uint32_t*)(w + L.hdr), 0u, 4, s), "clear header");
+  else
+    HIP_TRY(launch_scan_dup(L, batch->ws, D, batch->dup, s), "scan/duplicate");
+  HIP_TRY(launch_radix_sort(L, batch->ws, D, batch->dup, s), "radix sort");
+  HIP_TRY(launch_ranges(L, batch->ws, D, batch->dup, sort_passes(L.tiles_total) & 1, s), "ranges");
+  if (n_dup_host) {
+    unsigned long long h[2];
+    HIP_TRY(hipMemcpyAsync(h, w + L.hdr, sizeof(h), hipMemcpyDeviceToHost, s), "read count");
+    HIP_TRY(hipStreamSynchronize(s), "synchronise");
+    *n_dup_host = (int64_t)h[0];
+    if (h[1]) return fail(CLOD_E_CAPACITY, "%lld tile pairs exceed the duplicate capacity %lld",
+                          (long long)h[0], (long long)D.cap);
+  }
+  return CLOD_OK;
+}
+
+static const uint32_t* sorted_vals(const clod_batch* b, const Layout& L, const DupLayout& D) {
+  return (const uint32_t*)((const char*)b->dup + ((sort_passes(L.tiles_total) & 1) ? D.vals1 : D.vals0));
+}
+
+clod_status clod_render_fwd(const clod_batch* batch, float* rgb, float* T, uint32_t* last,
+                            int64_t* pairs_dev, void* stream) {
+  g_err[0] = 0;
+  Ctx cx;
+  clod_status st = prepare(batch, true, cx);
+  if (st != CLOD_OK) return st;
+  DupLayout D;
+  st = dup_check(batch, D);
+  if (st != CLOD_OK) return st;
+  if (!rgb || !T || !last) return fail(CLOD_E_ARG, "rgb, T and last must be non-NULL");
+  HIP_TRY(launch_blend_fwd(cx.L, batch->ws, sorted_vals(batch, cx.L, D), batch->params, rgb, T, last,
+                           pairs_dev, (hipStream_t)stream),
+          "blend forward");
+  return CLOD_OK;
+}
+
+clod_status clod_render_bwd(const clod_scene* scene, const clod_batch* batch, const float* T,
+                            const uint32_t* last, const float* dL_drgb, const float* dL_deta,
+                            int32_t accumulate, const clod_scene_grad* grad, void* stream) {
+  g_err[0] = 0;
+  clod_status st = check_scene(scene);
+  if (st != CLOD_OK) return st;
+  Ctx cx;
+  st = prepare(batch, true, cx);
+  if (st != CLOD_OK) return st;
+  if (scene->n != batch->n) return fail(CLOD_E_ARG, "scene->n != batch->n");
+  DupLayout D;
+  st = dup_check(batch, D);
+  if (st != CLOD_OK) return st;
+  if (!T || !last || !dL_drgb) return fail(CLOD_E_ARG, "T, last and dL_drgb must be non-NULL");
+  if (!grad || (scene->n > 0 && (!grad->mean || !grad->log_scale || !grad->quat || !grad->opacity ||
+                                 !grad->decay || !grad->sh)))
+    return fail(CLOD_E_ARG, "gradient planes must be non-NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const Layout& L = cx.L;
+  char* w = (char*)batch->ws;
+  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.gscreen), 0u, (int64_t)kGscreen * L.VN, s), "clear gscreen");
+  HIP_TRY(launch_blend_bwd(L, batch->ws, sorted_vals(batch, L, D), batch->params, T, last, dL_drgb, s),
+          "blend backward");
+  HIP_TRY(launch_gauss_bwd(*scene, L, batch->ws, batch->params, dL_deta, accumulate, *grad, s),
+          "gaussian backward");
+  return CLOD_OK;
+}
+
+clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int64_t* counts_dev,
+                           void* stream) {
+  g_err[0] = 0;
+  clod_status st = check_scene(scene);
+  if (st != CLOD_OK) return st;
+  Ctx cx;
+  st = prepare(batch, false, cx);
+  if (st != CLOD_OK) return st;
+  if (!counts_dev) return fail(CLOD_E_ARG, "counts_dev must be non-NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const Layout& L = cx.L;
+  char* w = (char*)batch->ws;
+  DevView* vinfo = (DevView*)(w + L.vinfo);
+  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, s), "view setup");
+  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.dmax_key), 0u, 2 * (int64_t)L.V, s), "clear dmax");
+  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.counts), 0u, 6 * (int64_t)L.V, s), "clear counts");
+  HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.dmax_key), s),
+          "frustum max");
+  HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
+                           (unsigned long long*)(w + L.counts), s),
+          "lod count");
+  HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
+  return CLOD_OK;
+}
+
+clod_status clod_loss(const clod_batch* batch, const float* rgb, const float* target, float s_max,
+                      float lambda_reg, float* loss_dev, float* dL_drgb, float* dL_deta_dev,
+                      void* stream) {
+  g_err[0] = 0;
+  Ctx cx;
+  clod_status st = prepare(batch, true, cx);
+  if (st != CLOD_OK) return st;
+  if (!rgb || !target || !loss_dev || !dL_drgb) return fail(CLOD_E_ARG, "rgb, target, loss and dL_drgb must be non-NULL");
+  if (!(finite_f(s_max) && s_max >= 1.0f)) return fail(CLOD_E_ARG, "s_max must be finite and >= 1");
+  if (!(finite_f(lambda_reg) && lambda_reg >= 0.0f)) return fail(CLOD_E_ARG, "lambda_reg must be finite and >= 0");
+  for (int v = 0; v < batch->n_views; ++v)
+    if (batch->views_host[v].s_v > s_max) return fail(CLOD_E_ARG, "view %d: s_v exceeds s_max", v);
+  HIP_TRY(launch_loss(cx.L, batch->ws, batch->n, rgb, target, s_max, lambda_reg, loss_dev, dL_drgb,
+                      dL_deta_dev, cx.loss_blocks, (hipStream_t)stream),
+          "loss");
+  return CLOD_OK;
+}
+
+clod_status clod_read_info(const clod_batch* batch, int64_t* info_host, void* stream) {
+  g_err[0] = 0;
+  Ctx cx;
+  clod_status st = prepare(batch, true, cx);
+  if (st != CLOD_OK) return st;
+  if (!info_host) return fail(CLOD_E_ARG, "info_host is NULL");
+  unsigned long long h[2];
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(h, (const char*)batch->ws + cx.L.hdr, sizeof(h), hipMemcpyDeviceToHost, s), "read header");
+  HIP_TRY(hipStreamSynchronize(s), "synchronise");
+  info_host[0] = (int64_t)h[0];
+  info_host[1] = (int64_t)h[1];
+  info_host[2] = batch->dup ? clod_dup_capacity(batch->dup_bytes) : 0;
+  info_host[3] = sort_passes(cx.L.tiles_total);
+  return CLOD_OK;
+}
+
+clod_status clod_inspect(const clod_batch* batch, int32_t section, const void** dev_ptr,
+                         int64_t* count) {
+  g_err[0] = 0;
+  Ctx cx;
+  clod_status st = prepare(batch, true, cx);
+  if (st != CLOD_OK) return st;
+  if (!dev_ptr || !count) return fail(CLOD_E_ARG, "dev_ptr and count must be non-NULL");
+  const Layout& L = cx.L;
+  const char* w = (const char*)batch->ws;
+  if (section == CLOD_SEC_KEYS || section == CLOD_SEC_VALUES) {
+    DupLayout D;
+    st = dup_check(batch, D);
+    if (st != CLOD_OK) return st;
+    const bool odd = (sort_passes(L.tiles_total) & 1) != 0;
+    const size_t off = section == CLOD_SEC_KEYS ? (odd ? D.keys1 : D.keys0) : (odd ? D.vals1 : D.vals0);
+    *dev_ptr = (const char*)batch->dup + off;
+    *count = D.cap;
+    return CLOD_OK;
+  }
+  switch (section) {
+    case CLOD_SEC_RANGES: *dev_ptr = w + L.ranges; *count = L.tiles_total; break;
+    case CLOD_SEC_REC0: *dev_ptr = w + L.rec; *count = L.VN; break;
+    case CLOD_SEC_REC1: *dev_ptr = w + L.rec + (size_t)L.VN * 16; *count = L.VN; break;
+    case CLOD_SEC_REC2: *dev_ptr = w + L.rec + (size_t)L.VN * 32; *count = L.VN; break;
+    case CLOD_SEC_FLAGS: *dev_ptr = w + L.flags; *count = L.VN; break;
+    case CLOD_SEC_DMAX: *dev_ptr = w + L.dmax_key; *count = L.V; break;
+    case CLOD_SEC_RECT: *dev_ptr = w + L.rect; *count = L.VN; break;
+    case CLOD_SEC_GSCREEN: *dev_ptr = w + L.gscreen; *count = L.VN; break;
+    default: return fail(CLOD_E_ARG, "unknown section %d", section);
+  }
+  return CLOD_OK;
+}
+
+}  // extern "C"

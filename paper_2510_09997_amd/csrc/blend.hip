@@ -1,0 +1,276 @@
+// Per-tile front-to-back blending (Sec. 3.1, Eq. (1)) and its adjoint.
+//
+// One 256-thread workgroup (4 wave64) per 16x16 tile, one pixel per thread.  The tile's
+// sorted list is walked in batches of 256 entries that the workgroup stages in LDS (one
+// entry per thread, coalesced gather of the records); every thread then reads the batch as
+// LDS broadcasts.  The workgroup stops as soon as all its pixels are saturated
+// (__syncthreads_count).  Blocks are mapped to tiles XCD-aware: the 8 XCDs take contiguous
+// tile ranges, so neighbouring tiles (which share Gaussians) hit the same L2.
+#include "clod_internal.h"
+
+namespace clod {
+
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  const int per = (nblocks + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_t tile) {
+  int lo = 0, hi = V - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct BlendEntry {
+  float u, v, hA, nB, hC, a2, r, g, b;
+};
+
+__global__ __launch_bounds__(kBlock) void k_blend_fwd(
+    const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
+    const float4* __restrict__ rec, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ svals, const unsigned long long* __restrict__ hdr,
+    float bg0, float bg1, float bg2, float* __restrict__ rgb, float* __restrict__ Tout,
+    uint32_t* __restrict__ lastout, int64_t* __restrict__ pairs) {
+  __shared__ float4 s0[kBlock];   // u, v, hA, nB
+  __shared__ float4 s1[kBlock];   // hC, alpha'', r, g
+  __shared__ float s2[kBlock];    // b
+  const int tile_i = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile_i >= (int)tiles_total) return;
+  if (hdr[kHdrOverflow]) return;
+  const int v = view_of_tile(views, V, (uint32_t)tile_i);
+  const DevView& Vw = views[v];
+  const int local = tile_i - (int)Vw.tile_base;
+  const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
+  const int px = tx * kTile + (threadIdx.x & 15);
+  const int py = ty * kTile + (threadIdx.x >> 4);
+  const bool inside = px < Vw.width && py < Vw.height;
+  const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
+  const uint2 rg = ranges[tile_i];
+  const float kSkip = 0.0039215688593685627f;   // fl(1/255)
+  const float kTmin = 9.99999974737875163e-05f; // fl(1e-4)
+  float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  uint32_t last = 0, evaluated = 0;
+  bool done = !inside;
+  for (uint32_t start = rg.x; start < rg.y; start += kBlock) {
+    if (__syncthreads_count(done) == kBlock) break;
+    const uint32_t j = start + threadIdx.x;
+    if (j < rg.y) {
+      uint32_t f = svals[j];
+      if ((int64_t)f >= VN) f = 0;   // defensive: the sort only emits indices < V*n
+      const float4 g0 = rec[f];
+      const float4 g1 = rec[VN + f];
+      const float4 g2 = rec[2 * VN + f];
+      s0[threadIdx.x] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
+      s1[threadIdx.x] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
+      s2[threadIdx.x] = g2.z;
+    }
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)kBlock, rg.y - start);
+    for (int k = 0; k < cnt; ++k) {
+      if (done) break;
+      const float4 a = s0[k];
+      const float4 c = s1[k];
+      ++evaluated;
+      const float dx = a.x - pcx, dy = a.y - pcy;
+      const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
+      if (power > 0.0f) continue;
+      // exp(power) < fl(1/255) for power < -5.6 and alpha'' <= 1: the entry is skipped
+      // whatever the polynomial returns, so it is not evaluated.
+      if (power < -5.6f) continue;
+      const float prod = c.y * cexp(power);
+      const float al = fminf(0.99f, prod);
+      if (al < kSkip) continue;
+      const float Tn = T * (1.0f - al);
+      if (Tn < kTmin) { done = true; break; }
+      const float w = al * T;
+      cr = fmaf_(c.z, w, cr);
+      cg = fmaf_(c.w, w, cg);
+      cb = fmaf_(s2[k], w, cb);
+      T = Tn;
+      last = (uint32_t)(start - rg.x) + (uint32_t)k + 1u;
+    }
+  }
+  if (inside) {
+    const int64_t P = (int64_t)Vw.pix_base;
+    const int64_t HW = (int64_t)Vw.width * Vw.height;
+    const int64_t p = (int64_t)py * Vw.width + px;
+    rgb[3 * P + p] = fmaf_(T, bg0, cr);
+    rgb[3 * P + HW + p] = fmaf_(T, bg1, cg);
+    rgb[3 * P + 2 * HW + p] = fmaf_(T, bg2, cb);
+    Tout[P + p] = T;
+    lastout[P + p] = last;
+  }
+  if (pairs) {
+    unsigned long long e = wave_sum((unsigned long long)evaluated);
+    if (lane_id() == 0 && e) atomicAdd((unsigned long long*)pairs, e);
+  }
+}
+
+hipError_t launch_blend_fwd(const Layout& L, const void* ws, const uint32_t* sorted_vals,
+                            clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
+                            hipStream_t s) {
+  if (L.tiles_total == 0) return hipSuccess;
+  const char* w = (const char*)ws;
+  const int nb = (int)(((L.tiles_total + 7) / 8) * 8);
+  hipLaunchKernelGGL(k_blend_fwd, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
+                     L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
+                     sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
+                     prm.bg[2], rgb, T, last, pairs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- adjoint
+// Back-to-front over each pixel's blended entries (positions < last), recomputing every
+// decision exactly as the forward; transmittance is recovered by division
+// (T_k = T_{k+1} / (1 - a_k)); the normalised colour of everything behind entry k obeys
+// R_{k-1} = c_k a_k + (1 - a_k) R_k with R = background after the last entry, so
+// dC/da_k = T_k (c_k - R_k).  Per entry the 9 screen-space partials are reduced over the
+// wave, summed over the 4 waves in LDS, and added to the global accumulator once per tile.
+__global__ __launch_bounds__(kBlock) void k_blend_bwd(
+    const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
+    const float4* __restrict__ rec, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ svals, const unsigned long long* __restrict__ hdr,
+    float bg0, float bg1, float bg2, const float* __restrict__ Tin,
+    const uint32_t* __restrict__ lastin, const float* __restrict__ dL_drgb,
+    float* __restrict__ gscreen) {
+  __shared__ float4 s0[kBlock];
+  __shared__ float4 s1[kBlock];
+  __shared__ float s2[kBlock];
+  __shared__ float acc[kGscreen][kBlock];
+  __shared__ uint32_t sidx[kBlock];
+  __shared__ uint32_t smax[4];
+  const int tile_i = xcd_tile(blockIdx.x, gridDim.x);
+  if (tile_i >= (int)tiles_total) return;
+  if (hdr[kHdrOverflow]) return;
+  const int v = view_of_tile(views, V, (uint32_t)tile_i);
+  const DevView& Vw = views[v];
+  const int local = tile_i - (int)Vw.tile_base;
+  const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
+  const int px = tx * kTile + (threadIdx.x & 15);
+  const int py = ty * kTile + (threadIdx.x >> 4);
+  const bool inside = px < Vw.width && py < Vw.height;
+  const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
+  const uint2 rg = ranges[tile_i];
+  const float kSkip = 0.0039215688593685627f;
+  const int64_t P = (int64_t)Vw.pix_base;
+  const int64_t HW = (int64_t)Vw.width * Vw.height;
+  const int64_t p = (int64_t)py * Vw.width + px;
+  uint32_t last = 0;
+  float T = 1.0f, g0c = 0.f, g1c = 0.f, g2c = 0.f;
+  if (inside) {
+    last = lastin[P + p];
+    T = Tin[P + p];
+    g0c = dL_drgb[3 * P + p];
+    g1c = dL_drgb[3 * P + HW + p];
+    g2c = dL_drgb[3 * P + 2 * HW + p];
+  }
+  float R0 = bg0, R1 = bg1, R2 = bg2;
+  // Largest last in the tile bounds the walk.
+  uint32_t m = last;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) { const uint32_t q = __shfl_xor(m, o, 64); m = q > m ? q : m; }
+  if (lane_id() == 0) smax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  const uint32_t tmax = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
+  const uint32_t end = rg.x + tmax;   // exclusive
+  const int wave = threadIdx.x >> 6;
+  for (uint32_t hi = end; hi > rg.x;) {
+    const uint32_t lo = hi > rg.x + kBlock ? hi - kBlock : rg.x;
+    const int cnt = (int)(hi - lo);
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      uint32_t f = svals[lo + threadIdx.x];
+      if ((int64_t)f >= VN) f = 0;   // defensive: the sort only emits indices < V*n
+      const float4 a0 = rec[f];
+      const float4 a1 = rec[VN + f];
+      const float4 a2 = rec[2 * VN + f];
+      s0[threadIdx.x] = make_float4(a0.x, a0.y, a1.x, a1.y);   // u, v, A, B
+      s1[threadIdx.x] = make_float4(a1.z, a0.z, a2.x, a2.y);   // C, alpha'', r, g
+      s2[threadIdx.x] = a2.z;
+      sidx[threadIdx.x] = f;
+    }
+#pragma unroll
+    for (int q = 0; q < kGscreen; ++q) acc[q][threadIdx.x] = 0.0f;
+    __syncthreads();
+    for (int k = cnt - 1; k >= 0; --k) {
+      const uint32_t pos = lo - rg.x + (uint32_t)k;
+      bool contrib = false;
+      float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, ga2 = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
+      if (pos < last) {
+        const float4 a = s0[k];
+        const float4 c = s1[k];
+        const float cb_ = s2[k];
+        const float dx = a.x - pcx, dy = a.y - pcy;
+        const float hA = -0.5f * a.z, nB = -a.w, hC = -0.5f * c.x;
+        const float power = fmaf_(hA * dx, dx, fmaf_(hC * dy, dy, (nB * dx) * dy));
+        if (power <= 0.0f && power >= -5.6f) {
+          const float G = cexp(power);
+          const float prod = c.y * G;
+          const float al = fminf(0.99f, prod);
+          if (al >= kSkip) {
+            contrib = true;
+            const float oma = 1.0f - al;
+            const float Tk = T / oma;
+            const float wgt = al * Tk;
+            gr = g0c * wgt;
+            gg = g1c * wgt;
+            gb = g2c * wgt;
+            const float dLda = Tk * (g0c * (c.z - R0) + g1c * (c.w - R1) + g2c * (cb_ - R2));
+            R0 = c.z * al + oma * R0;
+            R1 = c.w * al + oma * R1;
+            R2 = cb_ * al + oma * R2;
+            T = Tk;
+            if (prod <= 0.99f) {
+              ga2 = dLda * G;
+              const float gp = dLda * prod;
+              gu = -gp * (a.z * dx + a.w * dy);
+              gv = -gp * (c.x * dy + a.w * dx);
+              gA = -0.5f * gp * dx * dx;
+              gB = -gp * dx * dy;
+              gC = -0.5f * gp * dy * dy;
+            }
+          }
+        }
+      }
+      if (ballot64(contrib) != 0ull) {
+        gu = wave_sum(gu); gv = wave_sum(gv); gA = wave_sum(gA); gB = wave_sum(gB);
+        gC = wave_sum(gC); ga2 = wave_sum(ga2); gr = wave_sum(gr); gg = wave_sum(gg);
+        gb = wave_sum(gb);
+        if (lane_id() == 0) {
+          atomicAdd(&acc[0][k], gu); atomicAdd(&acc[1][k], gv); atomicAdd(&acc[2][k], gA);
+          atomicAdd(&acc[3][k], gB); atomicAdd(&acc[4][k], gC); atomicAdd(&acc[5][k], ga2);
+          atomicAdd(&acc[6][k], gr); atomicAdd(&acc[7][k], gg); atomicAdd(&acc[8][k], gb);
+        }
+      }
+    }
+    (void)wave;
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      const uint32_t f = sidx[threadIdx.x];
+#pragma unroll
+      for (int q = 0; q < kGscreen; ++q) {
+        const float val = acc[q][threadIdx.x];
+        if (val != 0.0f) atomicAdd(gscreen + (int64_t)q * VN + f, val);
+      }
+    }
+    hi = lo;
+  }
+}
+
+hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_vals, clod_params prm,
+                            const float* T, const uint32_t* last, const float* dL_drgb,
+                            hipStream_t s) {
+  if (L.tiles_total == 0) return hipSuccess;
+  char* w = (char*)ws;
+  const int nb = (int)(((L.tiles_total + 7) / 8) * 8);
+  hipLaunchKernelGGL(k_blend_bwd, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
+                     L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
+                     sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
+                     prm.bg[2], T, last, dL_drgb, (float*)(w + L.gscreen));
+  return hipGetLastError();
+}
+
+}  // namespace clod

@@ -1,0 +1,317 @@
+// Internal declarations of libclod: device view table, workspace layout, binary32 contract
+// arithmetic for gfx950, and the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/clod.h"
+
+namespace clod {
+
+constexpr int kTile = 16;                  // 16x16-pixel tiles
+constexpr int kBlock = 256;                // threads per workgroup (4 wave64)
+constexpr int kScanItems = 16;             // items per thread in the tiles-touched scan
+constexpr int kScanChunk = kBlock * kScanItems;
+constexpr int kSortItems = 8;              // keys per thread per radix tile
+constexpr int kSortTile = kBlock * kSortItems;   // 2048 keys per radix tile
+constexpr int kMaxSortBlocks = 1024;
+constexpr int kGscreen = 9;                // du, dv, dA, dB, dC, dalpha'', dr, dg, db
+
+// Per-view constants derived on the device from clod_view (k_view_setup).
+struct DevView {
+  float W[9], t[3], c[3];
+  float fx, fy, cx, cy;
+  float s_v, limx, limy, tau_sv;
+  int32_t width, height, tiles_x, tiles_y;
+  uint32_t tile_base, pix_base, loss_block_base, pad0;
+};
+
+// Workspace header words (uint64).
+enum : int { kHdrDup = 0, kHdrOverflow = 1, kHdrWords = 8 };
+
+struct Layout {
+  int64_t n = 0;
+  int32_t V = 0;
+  int64_t VN = 0;
+  uint32_t tiles_total = 0;   // sum over views of tiles_x * tiles_y
+  int64_t pixels_total = 0;
+  int32_t scan_blocks = 0;
+  // byte offsets into ws
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, flags, rec, rect, tiles, scan_part,
+      ranges, gscreen, total;
+};
+
+// Host-side per-view geometry (must agree with k_view_setup).
+struct HostView {
+  int32_t width, height, tiles_x, tiles_y;
+  uint32_t tile_base, pix_base, loss_blocks, loss_block_base;
+};
+
+constexpr int kLossItems = 8;
+constexpr int kLossChunk = kBlock * kLossItems;
+
+struct DupLayout {
+  int64_t cap = 0;
+  size_t keys0, vals0, keys1, vals1, hist, total;
+};
+
+DupLayout dup_layout(int64_t cap);
+int sort_passes(uint32_t tiles_total);
+int sort_blocks(int64_t cap);
+
+// ----------------------------------------------------------------------------------------
+// Binary32 contract arithmetic (device).  The translation units are compiled with
+// -ffp-contract=off, so a*b+c stays two roundings; fused steps use __builtin_fmaf.
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ float fmaf_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Contract exponential: Cody-Waite reduction with a 16-bit head of ln 2, degree-7 Taylor
+// polynomial (1/j! rounded to binary32) in Horner form, scale by 2^k; zero below -86.
+__device__ __forceinline__ float cexp(float x) {
+  constexpr float kL2E = 1.44269502162933349609375f;          // fl(1/ln 2)
+  constexpr float kLn2Hi = 0.693145751953125f;                // floor(ln2 * 2^16) / 2^16
+  constexpr float kLn2Lo = 1.428606765330187045037746429443359375e-06f;  // fl(ln2 - hi)
+  constexpr float c7 = 1.98412701138295233249664306640625e-04f;   // fl(1/5040)
+  constexpr float c6 = 1.388888922519981861114501953125e-03f;     // fl(1/720)
+  constexpr float c5 = 8.3333337679505348205566406250e-03f;       // fl(1/120)
+  constexpr float c4 = 4.1666667908430099487304687500e-02f;       // fl(1/24)
+  constexpr float c3 = 1.6666667163372039794921875000e-01f;       // fl(1/6)
+  if (x != x) return x;
+  if (x < -86.0f) return 0.0f;
+  if (x > 88.0f) return __builtin_inff();
+  float k = __builtin_rintf(x * kL2E);
+  float r = fmaf_(-k, kLn2Hi, x);
+  r = fmaf_(-k, kLn2Lo, r);
+  float p = c7;
+  p = fmaf_(p, r, c6);
+  p = fmaf_(p, r, c5);
+  p = fmaf_(p, r, c4);
+  p = fmaf_(p, r, c3);
+  p = fmaf_(p, r, 0.5f);
+  p = fmaf_(p, r, 1.0f);
+  p = fmaf_(p, r, 1.0f);
+  int ki = (int)k;
+  return p * __uint_as_float((uint32_t)(ki + 127) << 23);
+}
+
+// Real spherical harmonics, l <= 3, order l = 0..3, m = -l..l (Cartesian forms on the unit
+// sphere).  Constants: closed-form normalisations rounded to binary32.
+struct SHK {
+  static constexpr float k0 = 0.282094791773878143f;   // 1/(2 sqrt(pi))
+  static constexpr float k1 = 0.488602511902919921f;   // sqrt(3/(4 pi))
+  static constexpr float k2a = 1.09254843059207907f;   // sqrt(15/pi)/2
+  static constexpr float k2b = 0.315391565252520002f;  // sqrt(5/pi)/4
+  static constexpr float k2c = 0.546274215296039535f;  // sqrt(15/pi)/4
+  static constexpr float k3a = 0.590043589926643520f;  // sqrt(35/(2 pi))/4
+  static constexpr float k3b = 2.89061144264055405f;   // sqrt(105/pi)/2
+  static constexpr float k3c = 0.457045799464465739f;  // sqrt(21/(2 pi))/4
+  static constexpr float k3d = 0.373176332590115391f;  // sqrt(7/pi)/4
+  static constexpr float k3e = 1.44530572132027702f;   // sqrt(105/pi)/4
+};
+
+__device__ __forceinline__ void sh_basis(int deg, float X, float Y, float Z, float* y) {
+  y[0] = SHK::k0;
+  if (deg < 1) return;
+  y[1] = SHK::k1 * Y;
+  y[2] = SHK::k1 * Z;
+  y[3] = SHK::k1 * X;
+  if (deg < 2) return;
+  const float xx = X * X, yy = Y * Y, zz = Z * Z;
+  const float xy = X * Y, yz = Y * Z, xz = X * Z;
+  y[4] = SHK::k2a * xy;
+  y[5] = SHK::k2a * yz;
+  y[6] = SHK::k2b * ((2.0f * zz - xx) - yy);
+  y[7] = SHK::k2a * xz;
+  y[8] = SHK::k2c * (xx - yy);
+  if (deg < 3) return;
+  const float t4 = (4.0f * zz - xx) - yy;
+  y[9] = SHK::k3a * (Y * (3.0f * xx - yy));
+  y[10] = SHK::k3b * (xy * Z);
+  y[11] = SHK::k3c * (Y * t4);
+  y[12] = SHK::k3d * (Z * ((2.0f * zz - 3.0f * xx) - 3.0f * yy));
+  y[13] = SHK::k3c * (X * t4);
+  y[14] = SHK::k3e * (Z * (xx - yy));
+  y[15] = SHK::k3a * (X * (xx - 3.0f * yy));
+}
+
+// Camera-space position (rows of W applied with the fused order of the contract).
+__device__ __forceinline__ void to_camera(const DevView& V, float mx, float my, float mz,
+                                          float& x, float& y, float& z) {
+  x = fmaf_(V.W[0], mx, fmaf_(V.W[1], my, fmaf_(V.W[2], mz, V.t[0])));
+  y = fmaf_(V.W[3], mx, fmaf_(V.W[4], my, fmaf_(V.W[5], mz, V.t[1])));
+  z = fmaf_(V.W[6], mx, fmaf_(V.W[7], my, fmaf_(V.W[8], mz, V.t[2])));
+}
+
+__device__ __forceinline__ bool in_frustum(const DevView& V, float x, float y, float z, float near_z) {
+  return (z > near_z) && (fabsf(x) <= V.limx * z) && (fabsf(y) <= V.limy * z);
+}
+
+__device__ __forceinline__ float cam_distance(const DevView& V, float mx, float my, float mz,
+                                              float& ex, float& ey, float& ez) {
+  ex = mx - V.c[0];
+  ey = my - V.c[1];
+  ez = mz - V.c[2];
+  return __builtin_sqrtf(fmaf_(ex, ex, fmaf_(ey, ey, ez * ez)));
+}
+
+__device__ __forceinline__ float sigmoid_c(float o) { return 1.0f / (1.0f + cexp(-o)); }
+
+// Attenuated opacity of Eq. (2) (also returns alpha and q for the adjoint).
+__device__ __forceinline__ float attenuated(float d, float dmax, float s_v, float decay, float opac,
+                                            float eps, float& alpha, float& q) {
+  const float dn = d / dmax;
+  const float u = dn * s_v;
+  const float num = u * u;
+  const float r = fmaxf(decay, 0.0f);
+  const float den = fmaf_(2.0f * r, r, eps);
+  q = num / den;
+  alpha = sigmoid_c(opac);
+  return alpha * cexp(-q);
+}
+
+// EWA projection of one Gaussian.  Returns false when culled (det <= 0 or empty rect).
+struct Proj {
+  float u, v, A, B, C, rad;
+  float ca, cb, cc, det;
+  int x0, x1, y0, y1;
+};
+
+__device__ __forceinline__ void quat_rot(float qw, float qx, float qy, float qz, float* R,
+                                         float& w_, float& x_, float& y_, float& z_, float& rn) {
+  const float n2 = fmaf_(qw, qw, fmaf_(qx, qx, fmaf_(qy, qy, qz * qz)));
+  if (n2 > 0.0f) {
+    rn = 1.0f / __builtin_sqrtf(n2);
+    w_ = qw * rn; x_ = qx * rn; y_ = qy * rn; z_ = qz * rn;
+  } else {
+    rn = 0.0f;
+    w_ = 1.0f; x_ = y_ = z_ = 0.0f;
+  }
+  const float xx = x_ * x_, yy = y_ * y_, zz = z_ * z_;
+  const float xy = x_ * y_, xz = x_ * z_, yz = y_ * z_;
+  const float wx = w_ * x_, wy = w_ * y_, wz = w_ * z_;
+  R[0] = 1.0f - 2.0f * (yy + zz); R[1] = 2.0f * (xy - wz);        R[2] = 2.0f * (xz + wy);
+  R[3] = 2.0f * (xy + wz);        R[4] = 1.0f - 2.0f * (xx + zz); R[5] = 2.0f * (yz - wx);
+  R[6] = 2.0f * (xz - wy);        R[7] = 2.0f * (yz + wx);        R[8] = 1.0f - 2.0f * (xx + yy);
+}
+
+__device__ __forceinline__ void cov3(const float* R, float s0, float s1, float s2, float* S) {
+  float M[9];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    M[3 * j + 0] = R[3 * j + 0] * s0;
+    M[3 * j + 1] = R[3 * j + 1] * s1;
+    M[3 * j + 2] = R[3 * j + 2] * s2;
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = j; k < 3; ++k) {
+      const float v = fmaf_(M[3 * j], M[3 * k], fmaf_(M[3 * j + 1], M[3 * k + 1], M[3 * j + 2] * M[3 * k + 2]));
+      S[3 * j + k] = v;
+      S[3 * k + j] = v;
+    }
+}
+
+// Projected 2D covariance (with dilation), conic, radius and rectangle.
+__device__ __forceinline__ bool ewa(const DevView& V, float x, float y, float z, const float* S,
+                                    float dil, Proj& P) {
+  const float iz = 1.0f / z;
+  const float tx = x * iz, ty = y * iz;
+  const float j00 = V.fx * iz, j02 = -(V.fx * tx) * iz;
+  const float j11 = V.fy * iz, j12 = -(V.fy * ty) * iz;
+  float T[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T[k] = fmaf_(j00, V.W[k], j02 * V.W[6 + k]);
+    T[3 + k] = fmaf_(j11, V.W[3 + k], j12 * V.W[6 + k]);
+  }
+  float U[6];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      U[3 * r + k] = fmaf_(T[3 * r], S[k], fmaf_(T[3 * r + 1], S[3 + k], T[3 * r + 2] * S[6 + k]));
+  const float ca = fmaf_(U[0], T[0], fmaf_(U[1], T[1], U[2] * T[2])) + dil;
+  const float cb = fmaf_(U[0], T[3], fmaf_(U[1], T[4], U[2] * T[5]));
+  const float cc = fmaf_(U[3], T[3], fmaf_(U[4], T[4], U[5] * T[5])) + dil;
+  const float det = fmaf_(ca, cc, -(cb * cb));
+  P.ca = ca; P.cb = cb; P.cc = cc; P.det = det;
+  if (!(det > 0.0f)) return false;
+  const float idet = 1.0f / det;
+  P.A = cc * idet;
+  P.B = -cb * idet;
+  P.C = ca * idet;
+  const float mid = 0.5f * (ca + cc);
+  const float lam = mid + __builtin_sqrtf(fmaxf(0.0f, fmaf_(mid, mid, -det)));
+  const float rad = __builtin_ceilf(3.0f * __builtin_sqrtf(lam));
+  P.rad = rad;
+  P.u = fmaf_(V.fx, tx, V.cx);
+  P.v = fmaf_(V.fy, ty, V.cy);
+  const float TWf = (float)V.tiles_x, THf = (float)V.tiles_y;
+  float fx0 = __builtin_floorf((P.u - rad) * 0.0625f), fx1 = __builtin_floorf((P.u + rad) * 0.0625f) + 1.0f;
+  float fy0 = __builtin_floorf((P.v - rad) * 0.0625f), fy1 = __builtin_floorf((P.v + rad) * 0.0625f) + 1.0f;
+  fx0 = fminf(fmaxf(fx0, 0.0f), TWf); fx1 = fminf(fmaxf(fx1, 0.0f), TWf);
+  fy0 = fminf(fmaxf(fy0, 0.0f), THf); fy1 = fminf(fmaxf(fy1, 0.0f), THf);
+  P.x0 = (int)fx0; P.x1 = (int)fx1; P.y0 = (int)fy0; P.y1 = (int)fy1;
+  return P.x0 < P.x1 && P.y0 < P.y1;
+}
+
+// Record written by the projection for each (view, Gaussian):
+//   g0 = (u, v, alpha'', depth), g1 = (A, B, C, radius), g2 = (r, g, b, 0).
+// flags: bit0 F, bit1 M, bit2 rendered, bits3..5 colour clamp per channel.
+
+__device__ __forceinline__ float dmax_from_key(unsigned long long key) {
+  return key == 0ull ? 1.0f : __uint_as_float((uint32_t)(key >> 32));
+}
+
+// Wave64 helpers.
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ----------------------------------------------------------------------------------------
+// Launchers (each returns hipGetLastError()).
+// ----------------------------------------------------------------------------------------
+hipError_t launch_view_setup(const clod_view* views_dev, int V, clod_params prm, DevView* vinfo,
+                             hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V, float near_z,
+                              unsigned long long* dmax_key, hipStream_t s);
+hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
+                          const unsigned long long* dmax_key, unsigned long long* counts,
+                          uint8_t* flags, float4* rec, uint2* rect, uint32_t* tiles, hipStream_t s);
+hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
+                            const unsigned long long* dmax_key, unsigned long long* counts,
+                            hipStream_t s);
+hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s);
+
+hipError_t launch_scan_dup(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s);
+hipError_t launch_radix_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s);
+hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
+                         hipStream_t s);
+
+hipError_t launch_blend_fwd(const Layout& L, const void* ws, const uint32_t* sorted_vals,
+                            clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
+                            hipStream_t s);
+hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_vals, clod_params prm,
+                            const float* T, const uint32_t* last, const float* dL_drgb,
+                            hipStream_t s);
+hipError_t launch_gauss_bwd(const clod_scene& sc, const Layout& L, void* ws, clod_params prm,
+                            const float* dL_deta, int accumulate, const clod_scene_grad& g,
+                            hipStream_t s);
+hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, const float* target,
+                       float s_max, float lambda_reg, float* loss, float* dL_drgb, float* dL_deta,
+                       uint32_t loss_blocks, hipStream_t s);
+
+}  // namespace clod

@@ -1,0 +1,275 @@
+// Per-Gaussian adjoint: screen-space partials (u, v, conic, alpha'', colour) are chained back
+// to the scene parameters through the EWA projection, the SH colour, the attenuated opacity
+// of Eq. (2) (opacity logit, decay factor, normalised distance and so the mean) and the
+// point-count regulariser's straight-through term (d eta / d alpha''_i = 1/n, Sec. 3.3).
+// The normalised distance also depends on the frustum maximum (Sec. 3.2); its partial is
+// reduced per view here and applied to the argmax Gaussian by k_dmax_fix.
+//
+// One thread per Gaussian loops over the batch's views and writes each gradient plane once
+// (coalesced, no atomics).  Forward intermediates are recomputed with the same contract
+// arithmetic as the projection.
+#include "clod_internal.h"
+
+namespace clod {
+
+// dY_k/d(X, Y, Z) of the basis polynomials in sh_basis (independent coordinates).
+__device__ __forceinline__ void sh_basis_grad(int deg, float X, float Y, float Z, const float* gY,
+                                              float& gX, float& gYo, float& gZ) {
+  gX = 0.f; gYo = 0.f; gZ = 0.f;
+  if (deg < 1) return;
+  gYo += SHK::k1 * gY[1];
+  gZ += SHK::k1 * gY[2];
+  gX += SHK::k1 * gY[3];
+  if (deg < 2) return;
+  gX += SHK::k2a * Y * gY[4]; gYo += SHK::k2a * X * gY[4];
+  gYo += SHK::k2a * Z * gY[5]; gZ += SHK::k2a * Y * gY[5];
+  gX += -2.f * SHK::k2b * X * gY[6]; gYo += -2.f * SHK::k2b * Y * gY[6]; gZ += 4.f * SHK::k2b * Z * gY[6];
+  gX += SHK::k2a * Z * gY[7]; gZ += SHK::k2a * X * gY[7];
+  gX += 2.f * SHK::k2c * X * gY[8]; gYo += -2.f * SHK::k2c * Y * gY[8];
+  if (deg < 3) return;
+  const float xx = X * X, yy = Y * Y, zz = Z * Z;
+  gX += 6.f * SHK::k3a * X * Y * gY[9]; gYo += SHK::k3a * (3.f * xx - 3.f * yy) * gY[9];
+  gX += SHK::k3b * Y * Z * gY[10]; gYo += SHK::k3b * X * Z * gY[10]; gZ += SHK::k3b * X * Y * gY[10];
+  gX += -2.f * SHK::k3c * X * Y * gY[11]; gYo += SHK::k3c * (4.f * zz - xx - 3.f * yy) * gY[11];
+  gZ += 8.f * SHK::k3c * Y * Z * gY[11];
+  gX += -6.f * SHK::k3d * X * Z * gY[12]; gYo += -6.f * SHK::k3d * Y * Z * gY[12];
+  gZ += SHK::k3d * (6.f * zz - 3.f * xx - 3.f * yy) * gY[12];
+  gX += SHK::k3c * (4.f * zz - 3.f * xx - yy) * gY[13]; gYo += -2.f * SHK::k3c * X * Y * gY[13];
+  gZ += 8.f * SHK::k3c * X * Z * gY[13];
+  gX += 2.f * SHK::k3e * X * Z * gY[14]; gYo += -2.f * SHK::k3e * Y * Z * gY[14];
+  gZ += SHK::k3e * (xx - yy) * gY[14];
+  gX += SHK::k3a * (3.f * xx - 3.f * yy) * gY[15]; gYo += -6.f * SHK::k3a * X * Y * gY[15];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gauss_bwd(
+    clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
+    const unsigned long long* __restrict__ dmax_key, const uint8_t* __restrict__ flags,
+    const float* __restrict__ gscreen, int64_t VN, const float* __restrict__ dL_deta,
+    float* __restrict__ gdmax, int accumulate, clod_scene_grad g) {
+  __shared__ float sred[4];
+  const int64_t n = sc.n;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = i < n;
+  const int deg = sc.sh_degree;
+  const int K = (deg + 1) * (deg + 1);
+  const float inv_n = 1.0f / (float)n;
+  float mx = 0.f, my = 0.f, mz = 0.f, op = 0.f, dc = 0.f;
+  if (valid) {
+    mx = sc.mean[i]; my = sc.mean[n + i]; mz = sc.mean[2 * n + i];
+    op = sc.opacity[i]; dc = sc.decay[i];
+  }
+  float gmx = 0.f, gmy = 0.f, gmz = 0.f, gop = 0.f, gdc = 0.f;
+  float gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+  float gsh[48];
+#pragma unroll
+  for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+  bool have_cov = false;
+  float s[3], Rm[9], S[9], qn[4], rn = 0.f;
+  for (int v = 0; v < V; ++v) {
+    const DevView& Vw = views[v];
+    float gdm = 0.f;
+    if (valid) {
+      const int64_t f = (int64_t)v * n + i;
+      const uint8_t fl = flags[f];
+      float x, y, z, ex, ey, ez;
+      to_camera(Vw, mx, my, mz, x, y, z);
+      const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
+      const float dmax = dmax_from_key(dmax_key[v]);
+      float alpha, q;
+      const float a2 = attenuated(d, dmax, Vw.s_v, dc, op, prm.eps, alpha, q);
+      float ga2 = dL_deta ? dL_deta[v] * inv_n : 0.f;
+      float gx = 0.f, gy = 0.f, gz = 0.f;     // camera-space position
+      float gex = 0.f, gey = 0.f, gez = 0.f;  // world offset mu - c
+      if (fl & 4) {
+        const float gu = gscreen[f], gv = gscreen[VN + f];
+        const float gA = gscreen[2 * VN + f], gB = gscreen[3 * VN + f], gC = gscreen[4 * VN + f];
+        ga2 += gscreen[5 * VN + f];
+        const float gcol[3] = {gscreen[6 * VN + f], gscreen[7 * VN + f], gscreen[8 * VN + f]};
+        if (!have_cov) {
+          s[0] = cexp(sc.log_scale[i]); s[1] = cexp(sc.log_scale[n + i]); s[2] = cexp(sc.log_scale[2 * n + i]);
+          quat_rot(sc.quat[i], sc.quat[n + i], sc.quat[2 * n + i], sc.quat[3 * n + i], Rm, qn[0], qn[1], qn[2], qn[3], rn);
+          cov3(Rm, s[0], s[1], s[2], S);
+          have_cov = true;
+        }
+        // Colour: SH coefficients and view direction.
+        const float id = 1.0f / d;
+        const float X = ex * id, Y = ey * id, Z = ez * id;
+        float Yb[16], gY[16];
+        sh_basis(deg, X, Y, Z, Yb);
+        for (int k = 0; k < K; ++k) gY[k] = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          if (fl & (8 << ch)) continue;
+          const float gc = gcol[ch];
+          for (int k = 0; k < K; ++k) {
+            gsh[3 * k + ch] += gc * Yb[k];
+            gY[k] += gc * sc.sh[((int64_t)k * 3 + ch) * n + i];
+          }
+        }
+        float gX, gYd, gZ;
+        sh_basis_grad(deg, X, Y, Z, gY, gX, gYd, gZ);
+        const float dot = X * gX + Y * gYd + Z * gZ;
+        gex += (gX - X * dot) * id;
+        gey += (gYd - Y * dot) * id;
+        gez += (gZ - Z * dot) * id;
+        // Mean in screen space.
+        const float iz = 1.0f / z;
+        gx += gu * Vw.fx * iz;
+        gy += gv * Vw.fy * iz;
+        gz += -(gu * Vw.fx * x + gv * Vw.fy * y) * iz * iz;
+        // Conic -> 2D covariance (a, b, c include the dilation).
+        Proj P;
+        ewa(Vw, x, y, z, S, prm.dilation, P);
+        const float a = P.ca, b = P.cb, c = P.cc;
+        const float id2 = 1.0f / (P.det * P.det);
+        const float ga = (-c * c * gA + b * c * gB - b * b * gC) * id2;
+        const float gb = (2.f * b * c * gA - (a * c + b * b) * gB + 2.f * a * b * gC) * id2;
+        const float gcc = (-b * b * gA + a * b * gB - a * a * gC) * id2;
+        // Sigma' = T Sigma T^T with T = J W; symmetric gradient G' = [[ga, gb/2], [gb/2, gcc]].
+        const float j00 = Vw.fx * iz, j02 = -Vw.fx * x * iz * iz;
+        const float j11 = Vw.fy * iz, j12 = -Vw.fy * y * iz * iz;
+        float T[6];
+        for (int k = 0; k < 3; ++k) {
+          T[k] = j00 * Vw.W[k] + j02 * Vw.W[6 + k];
+          T[3 + k] = j11 * Vw.W[3 + k] + j12 * Vw.W[6 + k];
+        }
+        const float Gp00 = ga, Gp01 = 0.5f * gb, Gp11 = gcc;
+        // TS = T Sigma (2x3)
+        float TS[6];
+        for (int r = 0; r < 2; ++r)
+          for (int k = 0; k < 3; ++k)
+            TS[3 * r + k] = T[3 * r] * S[k] + T[3 * r + 1] * S[3 + k] + T[3 * r + 2] * S[6 + k];
+        // dL/dT = 2 G' T Sigma
+        float gT[6];
+        for (int k = 0; k < 3; ++k) {
+          gT[k] = 2.f * (Gp00 * TS[k] + Gp01 * TS[3 + k]);
+          gT[3 + k] = 2.f * (Gp01 * TS[k] + Gp11 * TS[3 + k]);
+        }
+        // dL/dSigma = T^T G' T (symmetric 3x3)
+        float gS[9];
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k)
+            gS[3 * j + k] = T[j] * (Gp00 * T[k] + Gp01 * T[3 + k]) + T[3 + j] * (Gp01 * T[k] + Gp11 * T[3 + k]);
+        // dL/dJ = dL/dT W^T; J depends on (x, y, z).
+        float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
+        for (int k = 0; k < 3; ++k) {
+          gJ00 += gT[k] * Vw.W[k];
+          gJ02 += gT[k] * Vw.W[6 + k];
+          gJ11 += gT[3 + k] * Vw.W[3 + k];
+          gJ12 += gT[3 + k] * Vw.W[6 + k];
+        }
+        const float iz2 = iz * iz, iz3 = iz2 * iz;
+        gz += -Vw.fx * iz2 * gJ00 + 2.f * Vw.fx * x * iz3 * gJ02 - Vw.fy * iz2 * gJ11 + 2.f * Vw.fy * y * iz3 * gJ12;
+        gx += -Vw.fx * iz2 * gJ02;
+        gy += -Vw.fy * iz2 * gJ12;
+        // Sigma = M M^T, M = R diag(s): dL/dM = 2 gS M.
+        float Mm[9];
+        for (int j = 0; j < 3; ++j)
+          for (int l = 0; l < 3; ++l) Mm[3 * j + l] = Rm[3 * j + l] * s[l];
+        float gM[9];
+        for (int j = 0; j < 3; ++j)
+          for (int l = 0; l < 3; ++l)
+            gM[3 * j + l] = 2.f * (gS[3 * j] * Mm[l] + gS[3 * j + 1] * Mm[3 + l] + gS[3 * j + 2] * Mm[6 + l]);
+        float gR[9];
+        for (int l = 0; l < 3; ++l) {
+          float gs_l = 0.f;
+          for (int j = 0; j < 3; ++j) {
+            gs_l += gM[3 * j + l] * Rm[3 * j + l];
+            gR[3 * j + l] = gM[3 * j + l] * s[l];
+          }
+          gls[l] += gs_l * s[l];
+        }
+        // Rotation matrix of the unit quaternion (w, x, y, z).
+        const float w_ = qn[0], x_ = qn[1], y_ = qn[2], z_ = qn[3];
+        const float gw = 2.f * (-z_ * gR[1] + y_ * gR[2] + z_ * gR[3] - x_ * gR[5] - y_ * gR[6] + x_ * gR[7]);
+        const float gxq = 2.f * (-2.f * x_ * gR[4] - 2.f * x_ * gR[8] + y_ * gR[1] + z_ * gR[2] + y_ * gR[3] - w_ * gR[5] + z_ * gR[6] + w_ * gR[7]);
+        const float gyq = 2.f * (-2.f * y_ * gR[0] - 2.f * y_ * gR[8] + x_ * gR[1] + w_ * gR[2] + x_ * gR[3] + z_ * gR[5] - w_ * gR[6] + z_ * gR[7]);
+        const float gzq = 2.f * (-2.f * z_ * gR[0] - 2.f * z_ * gR[4] - w_ * gR[1] + x_ * gR[2] + w_ * gR[3] + y_ * gR[5] + x_ * gR[6] + y_ * gR[7]);
+        const float qdot = w_ * gw + x_ * gxq + y_ * gyq + z_ * gzq;
+        gq[0] += (gw - w_ * qdot) * rn;
+        gq[1] += (gxq - x_ * qdot) * rn;
+        gq[2] += (gyq - y_ * qdot) * rn;
+        gq[3] += (gzq - z_ * qdot) * rn;
+      }
+      // Eq. (2): alpha'' = sigmoid(o) exp(-q), q = (d' s_v)^2 / (2 relu(sigma)^2 + eps).
+      gop += ga2 * a2 * (1.0f - alpha);
+      const float gqv = -ga2 * a2;
+      const float r = fmaxf(dc, 0.0f);
+      const float den = 2.f * r * r + prm.eps;
+      const float dn = d / dmax;
+      const float uu = dn * Vw.s_v;
+      const float gnum = gqv / den;
+      const float gden = -gqv * q / den;
+      if (dc > 0.0f) gdc += gden * 4.f * r;
+      const float gdn = gnum * 2.f * uu * Vw.s_v;
+      const float gd = gdn / dmax;
+      gdm = -gdn * d / (dmax * dmax);
+      const float id = 1.0f / d;
+      gex += gd * ex * id;
+      gey += gd * ey * id;
+      gez += gd * ez * id;
+      // Camera-space gradient back to the world mean (p = W mu + t).
+      gmx += Vw.W[0] * gx + Vw.W[3] * gy + Vw.W[6] * gz + gex;
+      gmy += Vw.W[1] * gx + Vw.W[4] * gy + Vw.W[7] * gz + gey;
+      gmz += Vw.W[2] * gx + Vw.W[5] * gy + Vw.W[8] * gz + gez;
+    }
+    // Per-view sum of the frustum-maximum partial.
+    gdm = wave_sum(gdm);
+    if (lane_id() == 0) sred[threadIdx.x >> 6] = gdm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const float t = sred[0] + sred[1] + sred[2] + sred[3];
+      if (t != 0.0f && dmax_key[v] != 0ull) atomicAdd(gdmax + v, t);
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+  auto put = [&](float* p, int64_t idx, float val) { p[idx] = accumulate ? p[idx] + val : val; };
+  put(g.mean, i, gmx); put(g.mean, n + i, gmy); put(g.mean, 2 * n + i, gmz);
+  for (int l = 0; l < 3; ++l) put(g.log_scale, l * n + i, gls[l]);
+  for (int l = 0; l < 4; ++l) put(g.quat, l * n + i, gq[l]);
+  put(g.opacity, i, gop);
+  put(g.decay, i, gdc);
+  for (int k = 0; k < K; ++k)
+    for (int ch = 0; ch < 3; ++ch) put(g.sh, ((int64_t)k * 3 + ch) * n + i, gsh[3 * k + ch]);
+}
+
+// Frustum-maximum path: d_max = d_k for the argmax k, so dL/dmu_k += dL/ddmax (mu_k - c) / d_k.
+__global__ void k_dmax_fix(clod_scene sc, const DevView* __restrict__ views, int V,
+                           const unsigned long long* __restrict__ dmax_key,
+                           const float* __restrict__ gdmax, clod_scene_grad g) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t n = sc.n;
+  for (int v = 0; v < V; ++v) {
+    const unsigned long long key = dmax_key[v];
+    if (key == 0ull) continue;
+    const int64_t k = (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+    if (k >= n) continue;
+    const DevView& Vw = views[v];
+    float ex, ey, ez;
+    const float d = cam_distance(Vw, sc.mean[k], sc.mean[n + k], sc.mean[2 * n + k], ex, ey, ez);
+    const float gd = gdmax[v] / d;
+    g.mean[k] += gd * ex;
+    g.mean[n + k] += gd * ey;
+    g.mean[2 * n + k] += gd * ez;
+  }
+}
+
+hipError_t launch_gauss_bwd(const clod_scene& sc, const Layout& L, void* ws, clod_params prm,
+                            const float* dL_deta, int accumulate, const clod_scene_grad& g,
+                            hipStream_t s) {
+  if (sc.n == 0) return hipSuccess;
+  char* w = (char*)ws;
+  float* gdmax = (float*)(w + L.gdmax);
+  hipError_t e = launch_fill_u32((uint32_t*)gdmax, 0u, L.V, s);
+  if (e != hipSuccess) return e;
+  const int grid = (int)((sc.n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_gauss_bwd, dim3(grid), dim3(kBlock), 0, s, sc, (const DevView*)(w + L.vinfo), L.V,
+                     prm, (const unsigned long long*)(w + L.dmax_key), (const uint8_t*)(w + L.flags),
+                     (const float*)(w + L.gscreen), L.VN, dL_deta, gdmax, accumulate, g);
+  hipLaunchKernelGGL(k_dmax_fix, dim3(1), dim3(64), 0, s, sc, (const DevView*)(w + L.vinfo), L.V,
+                     (const unsigned long long*)(w + L.dmax_key), (const float*)gdmax, g);
+  return hipGetLastError();
+}
+
+}  // namespace clod

@@ -1,0 +1,107 @@
+"""Shared test helpers: run the HIP path through the C ABI and the oracle on the same seeded
+inputs, and compare them."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import oracle as O
+from paper_2510_09997_amd import _clod as C
+from paper_2510_09997_amd.render import Batch, Scene
+
+
+def params_struct(p: dict | None):
+    p = {**O.DEFAULT_PARAMS, **(p or {})}
+    return C.make_params(tau=p["tau"], eps=p["eps"], near=p["near"], guard=p["guard"],
+                         dilation=p["dilation"], bg=p["bg"])
+
+
+def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None):
+    """Runs clod_project, clod_bin_sort and clod_render_fwd; returns host copies."""
+    scene = Scene(sc)
+    b = Batch(sc["n"], views, params_struct(params), dup_capacity=dup_capacity)
+    b.project(scene)
+    D = b.bin_sort()
+    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rgb, T, last = b.render_fwd(pairs)
+    torch.cuda.synchronize()
+    out = dict(batch=b, scene=scene, D=D, counts=b.counts.cpu().numpy(), pairs=int(pairs.item()),
+               rgb_flat=rgb, T_flat=T, last_flat=last)
+    out["rgb"] = [t.cpu().numpy() for t in b.split(rgb, 3)]
+    out["T"] = [t.cpu().numpy() for t in b.split(T, 1)]
+    out["last"] = [t.cpu().numpy() for t in b.split(last, 1)]
+    out["keys"] = b.section(C.SEC_KEYS, D).cpu().numpy().view(np.uint64)
+    out["vals"] = b.section(C.SEC_VALUES, D).cpu().numpy().view(np.uint32)
+    out["ranges"] = b.section(C.SEC_RANGES).cpu().numpy().view(np.uint32)
+    out["rec0"] = b.section(C.SEC_REC0).cpu().numpy()
+    out["rec1"] = b.section(C.SEC_REC1).cpu().numpy()
+    out["rec2"] = b.section(C.SEC_REC2).cpu().numpy()
+    out["flags"] = b.section(C.SEC_FLAGS).cpu().numpy()
+    out["dmax"] = b.section(C.SEC_DMAX).cpu().numpy().view(np.uint64)
+    out["rect"] = b.section(C.SEC_RECT).cpu().numpy().view(np.uint32)
+    return out
+
+
+def tile_bases(views):
+    tb = [0]
+    for v in views:
+        tb.append(tb[-1] + ((v.width + 15) // 16) * ((v.height + 15) // 16))
+    return tb
+
+
+def compare_forward(g: dict, sc: dict, views, params: dict | None = None, fp64: bool = False,
+                    check_records: bool = True):
+    """Bit-exact comparison of everything integer (and the binary32 contract values) per view."""
+    n = sc["n"]
+    tb = tile_bases(views)
+    all_keys, all_vals = [], []
+    for v, view in enumerate(views):
+        r = O.render32(sc, view, params)
+        assert np.array_equal(g["counts"][v], r["counts"]), (v, g["counts"][v], r["counts"])
+        key = int(g["dmax"][v])
+        if r["argmax"] < 0:
+            assert key == 0
+        else:
+            assert np.float32(r["dmax"]).view(np.uint32) == (key >> 32), v
+            assert 0xFFFFFFFF - (key & 0xFFFFFFFF) == r["argmax"], v
+        fl = g["flags"][v * n:(v + 1) * n]
+        assert np.array_equal(fl, r["flags"]), v
+        if check_records:
+            rend = (r["flags"] & 4) > 0
+            rec0 = g["rec0"][v * n:(v + 1) * n]
+            rec1 = g["rec1"][v * n:(v + 1) * n]
+            rec2 = g["rec2"][v * n:(v + 1) * n]
+            # alpha'' for every Gaussian, the rest for rendered ones.
+            assert np.array_equal(rec0[:, 2].view(np.uint32), r["rec"][:, 6].view(np.uint32)), v
+            want = r["rec"][rend]
+            got = np.stack([rec0[rend, 0], rec0[rend, 1], rec0[rend, 3], rec1[rend, 0], rec1[rend, 1],
+                            rec1[rend, 2], rec0[rend, 2], rec2[rend, 0], rec2[rend, 1], rec2[rend, 2]], 1)
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), v
+            rc = g["rect"][v * n:(v + 1) * n][rend]
+            rect = np.stack([rc[:, 0] & 0xFFFF, rc[:, 0] >> 16, rc[:, 1] & 0xFFFF, rc[:, 1] >> 16], 1)
+            assert np.array_equal(rect.astype(np.int32), r["rect"][rend]), v
+        # Keys, values and ranges of this view's tiles.
+        all_keys.append(O.sorted_keys(r, tb[v]))
+        all_vals.append(r["entries"].astype(np.uint64) + np.uint64(v * n))
+        T_t = tb[v + 1] - tb[v]
+        rg = g["ranges"][tb[v]:tb[v + 1]]
+        off = r["tile_off"]
+        base = int(sum(len(k) for k in all_keys[:-1]))
+        for t in range(T_t):
+            a, b = int(off[t]), int(off[t + 1])
+            if b > a:
+                assert rg[t, 0] == a + base and rg[t, 1] == b + base, (v, t)
+            else:
+                assert rg[t, 0] == 0 and rg[t, 1] == 0, (v, t)
+        assert np.array_equal(g["last"][v].astype(np.int64), r["last"].astype(np.int64)), v
+        assert np.array_equal(g["T"][v].view(np.uint32), r["T"].view(np.uint32)), v
+        assert np.array_equal(g["rgb"][v].view(np.uint32), r["rgb"].view(np.uint32)), v
+        if fp64:
+            t = O.scene_to_torch64(sc, requires_grad=False)
+            rgb64, T64, _, _ = O.fp64_view_forward(t, view, r, params)
+            assert np.abs(g["rgb"][v] - rgb64.numpy()).max() <= 1e-5, v
+    keys = np.concatenate(all_keys) if all_keys else np.zeros(0, np.uint64)
+    vals = np.concatenate(all_vals) if all_vals else np.zeros(0, np.uint64)
+    assert g["D"] == keys.size
+    assert np.array_equal(g["keys"][:g["D"]], keys)
+    assert np.array_equal(g["vals"][:g["D"]].astype(np.uint64), vals)

@@ -1,0 +1,151 @@
+"""Host-side checks of libclod that need no GPU: the library loads, exports every entry
+point the header declares, sizes its workspaces consistently and rejects invalid
+arguments before launching anything."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_09997_amd import _clod as C, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "clod.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(clod_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = C.load()
+    names = header_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(C.EXPORTS)
+    assert lib.clod_abi_version() == C.ABI_VERSION
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(C.clod_view) == 96
+    assert ctypes.sizeof(C.clod_params) == 32
+    assert ctypes.sizeof(C.clod_scene) == 8 + 4 + 4 + 6 * 8
+    assert C.clod_batch.ws.offset % 8 == 0
+
+
+def test_workspace_sizes_are_consistent():
+    views = C.make_views([synth.look_at((0, 0, -3), width=w, height=h) for w, h in ((256, 256), (100, 75))])
+    a = C.clod_ws_bytes(1000, views)
+    b = C.clod_ws_bytes(2000, views)
+    assert a > 0 and b > a
+    assert C.clod_ws_bytes(0, views) > 0
+    for cap in (1, 1000, 123457, 10 ** 7):
+        nb = C.clod_dup_bytes(cap)
+        assert nb % 256 == 0 and nb >= 24 * cap
+        assert C.clod_dup_capacity(nb) >= cap
+        assert C.clod_dup_capacity(nb - 256) < cap or nb == C.clod_dup_bytes(C.clod_dup_capacity(nb - 256))
+
+
+FAKE = 1 << 20          # never dereferenced: every case below fails validation first
+
+
+def fake_batch(views, n=10, **over):
+    arr = C.make_views(views)
+    b = C.clod_batch()
+    b.n = n
+    b.n_views = len(views)
+    b.views_host = ctypes.cast(arr, C.P)
+    b.views_dev = FAKE
+    b.params = C.make_params()
+    b.ws = FAKE
+    b.ws_bytes = C.clod_ws_bytes(n, arr)
+    b.dup = FAKE
+    b.dup_bytes = C.clod_dup_bytes(1000)
+    for k, v in over.items():
+        setattr(b, k, v)
+    return b, arr
+
+
+def fake_scene(n=10, deg=0):
+    s = C.clod_scene()
+    s.n, s.sh_degree = n, deg
+    for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh"):
+        setattr(s, k, FAKE)
+    return s
+
+
+def call_project(scene, batch):
+    return C.load().clod_project(ctypes.byref(scene), ctypes.byref(batch), None, None)
+
+
+@pytest.mark.parametrize("case", [
+    "sv_below_one", "sv_nan", "n_negative", "degree_4", "null_mean", "zero_views", "eps_zero",
+    "tau_negative", "ws_small", "ws_misaligned", "bad_width", "centre_mismatch", "n_mismatch",
+])
+def test_invalid_arguments_are_rejected_before_launch(case):
+    v = synth.look_at((0, 0, -3), width=64, height=48)
+    scene = fake_scene()
+    views = [v]
+    kw = {}
+    if case == "sv_below_one":
+        views = [synth.look_at((0, 0, -3), width=64, height=48, s_v=0.5)]
+    elif case == "sv_nan":
+        views = [synth.look_at((0, 0, -3), width=64, height=48, s_v=float("nan"))]
+    elif case == "n_negative":
+        scene = fake_scene(n=-1)
+    elif case == "degree_4":
+        scene = fake_scene(deg=4)
+    elif case == "null_mean":
+        scene.mean = None
+    elif case == "bad_width":
+        bad = synth.look_at((0, 0, -3), width=64, height=48)
+        bad.width = 0
+        views = [bad]
+    elif case == "centre_mismatch":
+        bad = synth.look_at((0, 0, -3), width=64, height=48)
+        bad.c = np.array([0.0, 0.0, 3.0], np.float32)
+        views = [bad]
+    batch, arr = fake_batch(views)
+    if case == "zero_views":
+        batch.n_views = 0
+    elif case == "eps_zero":
+        batch.params.eps = 0.0
+    elif case == "tau_negative":
+        batch.params.tau = -1.0
+    elif case == "ws_small":
+        batch.ws_bytes = 16
+    elif case == "ws_misaligned":
+        batch.ws = FAKE + 4
+    elif case == "n_mismatch":
+        batch.n = 11
+    st = call_project(scene, batch)
+    assert st == C.CLOD_E_ARG, (case, st)
+    assert C.load().clod_last_error().decode() != ""
+
+
+def test_other_entry_points_validate_arguments():
+    v = synth.look_at((0, 0, -3), width=64, height=48, s_v=0.9)
+    batch, arr = fake_batch([v])
+    lib = C.load()
+    n = ctypes.c_int64(0)
+    assert lib.clod_bin_sort(ctypes.byref(batch), ctypes.byref(n), None) == C.CLOD_E_ARG
+    assert lib.clod_render_fwd(ctypes.byref(batch), FAKE, FAKE, FAKE, None, None) == C.CLOD_E_ARG
+    g = C.clod_scene_grad()
+    assert lib.clod_render_bwd(ctypes.byref(fake_scene()), ctypes.byref(batch), FAKE, FAKE, FAKE, None, 0,
+                               ctypes.byref(g), None) == C.CLOD_E_ARG
+    assert lib.clod_lod_count(ctypes.byref(fake_scene()), ctypes.byref(batch), FAKE, None) == C.CLOD_E_ARG
+    assert lib.clod_loss(ctypes.byref(batch), FAKE, FAKE, ctypes.c_float(8.0), ctypes.c_float(1.0), FAKE, FAKE,
+                         FAKE, None) == C.CLOD_E_ARG
+    ok_batch, arr2 = fake_batch([synth.look_at((0, 0, -3), width=64, height=48, s_v=4.0)])
+    # s_max below a view's s_v is an argument error.
+    assert lib.clod_loss(ctypes.byref(ok_batch), FAKE, FAKE, ctypes.c_float(2.0), ctypes.c_float(1.0), FAKE,
+                         FAKE, FAKE, None) == C.CLOD_E_ARG
+    # Missing gradient planes.
+    assert lib.clod_render_bwd(ctypes.byref(fake_scene()), ctypes.byref(ok_batch), FAKE, FAKE, FAKE, None, 0,
+                               ctypes.byref(g), None) == C.CLOD_E_ARG
+    # Unknown inspection section.
+    p, c = ctypes.c_void_p(0), ctypes.c_int64(0)
+    assert lib.clod_inspect(ctypes.byref(ok_batch), 99, ctypes.byref(p), ctypes.byref(c)) == C.CLOD_E_ARG

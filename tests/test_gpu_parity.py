@@ -1,0 +1,268 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on seeded inputs.
+
+Integer results (counts, frustum argmax, flags, tile rectangles, keys, sort order, ranges,
+last-contributor indices) and the binary32 contract values (records, T, colour) must be
+bit-identical; colour is also checked within 1e-5 of the FP64 replay, gradients within 1e-4
+relative of FP64 autograd per parameter plane (max-norm: max|g - r| / max|r|; also
+L2-relative <= 1e-4)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2510_09997_amd import _clod as C, synth
+from paper_2510_09997_amd.render import Batch, ClodRender, Scene
+
+from helpers import compare_forward, gpu_forward, params_struct
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    C.load()
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def test_config1_forward_bitexact():
+    """10,000 Gaussians in [-1,1]^3, degree 0, camera at distance 3, 256x256, s_v = 1."""
+    log("case: config1 forward")
+    sc = synth.make_scene(10000, 0, "uniform", seed=0)
+    v = synth.look_at((0, 0, -3), width=256, height=256, s_v=1.0)
+    g = gpu_forward(sc, [v])
+    compare_forward(g, sc, [v], fp64=True)
+    r = O.render32(sc, v)
+    assert g["pairs"] == r["pairs"]
+
+
+def test_multiview_ragged_forward_bitexact():
+    """Three views of different (ragged) resolutions and LoD scales in one batch."""
+    log("case: multiview ragged")
+    sc = synth.make_scene(20000, 3, "mixture", seed=1)
+    views = [synth.look_at((0.0, 1.0, -9.0), width=100, height=75, s_v=1.0),
+             synth.look_at((7.0, 2.0, 5.0), width=257, height=130, s_v=2.5),
+             synth.look_at((-6.0, -3.0, 6.0), width=64, height=64, s_v=6.0)]
+    g = gpu_forward(sc, views)
+    compare_forward(g, sc, views, fp64=True)
+
+
+def test_edge_cases_empty_scene_frustum_and_mask():
+    log("case: edges")
+    bg = dict(bg=(0.1, 0.2, 0.3))
+    # n = 0: background only.
+    sc0 = synth.make_scene(0, 0, "uniform", seed=0)
+    v = synth.look_at((0, 0, -3), width=40, height=24)
+    g = gpu_forward(sc0, [v], bg)
+    assert g["D"] == 0 and np.all(g["last"][0] == 0) and np.all(g["T"][0] == 1.0)
+    assert np.allclose(g["rgb"][0].reshape(3, -1), np.array([[0.1], [0.2], [0.3]], np.float32))
+    # Camera looking away from every Gaussian: empty frustum, d_max = 1.
+    sc = synth.make_scene(500, 1, "uniform", seed=2)
+    away = synth.look_at((0, 0, -3), target=(0, 0, -10), width=48, height=40)
+    g = gpu_forward(sc, [away], bg)
+    compare_forward(g, sc, [away], bg)
+    assert g["counts"][0, 0] == 0 and g["dmax"][0] == 0
+    # A huge s_v masks everything out.
+    far = synth.look_at((0, 0, -3), width=48, height=40, s_v=1e4)
+    g = gpu_forward(sc, [far], bg)
+    compare_forward(g, sc, [far], bg)
+    assert g["counts"][0, 1] == 0 and g["D"] == 0
+    # One Gaussian.
+    sc1 = synth.make_scene(1, 2, "uniform", seed=3, log_scale_mean=-1.5)
+    sc1["decay"][:] = 2.0
+    one = synth.look_at((0, 0, -3), width=33, height=17)
+    g = gpu_forward(sc1, [one])
+    compare_forward(g, sc1, [one], fp64=True)
+
+
+def test_reduction_to_plain_3dgs_when_decay_vanishes():
+    """sigma_d -> infinity and tau = 0: every in-frustum Gaussian is rendered with its plain
+    opacity; the GPU equals the oracle bit for bit."""
+    log("case: plain 3dgs")
+    sc = synth.make_scene(5000, 1, "uniform", seed=4)
+    sc["decay"][:] = 1e15
+    v = synth.look_at((0.3, 0.2, -3), width=128, height=96, s_v=5.0)
+    p = dict(tau=0.0)
+    g = gpu_forward(sc, [v], p)
+    compare_forward(g, sc, [v], p)
+    alpha = 1.0 / (1.0 + np.exp(-sc["opacity"].astype(np.float64)))
+    a2 = g["rec0"][:, 2]
+    assert np.allclose(a2, alpha, rtol=3e-7)
+
+
+def test_lod_count_sixty_four_views_bitexact_and_monotone_in_sv():
+    """Many views in one launch: counts equal the oracle's.  Along the virtual scale sweep
+    at a fixed pose the mask counts never rise."""
+    log("case: lod count")
+    sc = synth.make_scene(200000, 3, "mixture", seed=5)
+    ds = synth.sweep_distances(64, 2.0, 200.0)
+    ray = [synth.look_at((0, 0, -float(d)), width=1920, height=1080) for d in ds]
+    svs = [synth.look_at((0, 0, -2.0), width=1920, height=1080, s_v=float(d / 2.0)) for d in ds]
+    scene = Scene(sc)
+    for views in (ray, svs):
+        b = Batch(sc["n"], views, params_struct(None))
+        cnt = b.lod_count(scene).cpu().numpy()
+        for v, view in enumerate(views):
+            vp = O.view_pass(sc, view)
+            assert np.array_equal(cnt[v], vp["counts"]), (v, cnt[v], vp["counts"])
+    assert np.all(np.diff(cnt[:, 1]) <= 0) and np.all(np.diff(cnt[:, 2]) <= 0)
+    assert cnt[0, 1] > cnt[-1, 1]
+
+
+def test_determinism_two_runs_identical():
+    log("case: determinism")
+    sc = synth.make_scene(30000, 3, "mixture", seed=6)
+    v = synth.look_at((3.0, 2.0, -8.0), width=320, height=200, s_v=1.5)
+    a = gpu_forward(sc, [v])
+    b = gpu_forward(sc, [v])
+    for k in ("keys", "vals", "ranges"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["last"][0], b["last"][0]) and np.array_equal(a["rgb"][0], b["rgb"][0])
+
+
+def test_capacity_overflow_is_reported_and_retry_succeeds():
+    log("case: capacity")
+    sc = synth.make_scene(8000, 0, "uniform", seed=7)
+    v = synth.look_at((0, 0, -3), width=200, height=160)
+    scene = Scene(sc)
+    b = Batch(sc["n"], [v], params_struct(None), dup_capacity=100)
+    b.project(scene)
+    with pytest.raises(C.CapacityError):
+        C.clod_bin_sort(b.c_struct(), sync_count=True)
+    info = C.clod_read_info(b.c_struct())
+    assert info["overflow"] and info["n_dup"] > 100
+    D = b.bin_sort()                       # grows the duplicate buffer and re-runs
+    assert D == info["n_dup"]
+    g = gpu_forward(sc, [v])
+    rgb, T, last = b.render_fwd()
+    assert torch.equal(last, g["last_flat"]) and torch.equal(rgb, g["rgb_flat"])
+
+
+# --------------------------------------------------------------------------- gradients
+
+def _grad_case(sc, views, seed=0, dL_deta=None):
+    scene = Scene(sc)
+    b = Batch(sc["n"], views, params_struct(None))
+    b.project(scene)
+    b.bin_sort()
+    rgb, T, last = b.render_fwd()
+    rng = np.random.default_rng(seed)
+    g_rgb = rng.normal(size=3 * b.pixels).astype(np.float32)
+    eta_g = None if dL_deta is None else torch.tensor(dL_deta, dtype=torch.float32, device="cuda")
+    grads = b.render_bwd(scene, T, last, torch.from_numpy(g_rgb).cuda(), eta_g)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in grads.items()}
+    want = None
+    for v, view in enumerate(views):
+        r = O.render32(sc, view)
+        a = int(b.pix_base[v])
+        h, w = view.height, view.width
+        gv = g_rgb[3 * a:3 * a + 3 * h * w].reshape(3, h, w)
+        ref = O.fp64_grads(sc, view, r, gv, 0.0 if dL_deta is None else float(dL_deta[v]))
+        if want is None:
+            want = {k: ref[k].copy() for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")}
+        else:
+            for k in want:
+                want[k] += ref[k]
+    return got, want
+
+
+@pytest.mark.parametrize("deg", [0, 3])
+def test_gradients_match_fp64_oracle(deg):
+    """All parameter planes, two views, random upstream colour gradient and a point-count
+    gradient (straight-through), within 1e-4 relative of FP64 autograd."""
+    log(f"case: gradients deg {deg}")
+    sc = synth.make_scene(3000, deg, "uniform", seed=8 + deg, log_scale_mean=-3.5)
+    views = [synth.look_at((0.4, 0.3, -3.2), width=96, height=64, s_v=1.3),
+             synth.look_at((2.5, -1.0, -2.0), width=80, height=80, s_v=2.0)]
+    got, want = _grad_case(sc, views, seed=1, dL_deta=[0.3, -0.2])
+    for k in want:
+        err = O.grad_rel_error(got[k], want[k])
+        l2 = O.grad_l2_error(got[k], want[k])
+        log(f"  {k}: max-norm rel err {err:.3e}  l2 rel err {l2:.3e}")
+        assert err <= 1e-4 and l2 <= 1e-4, (k, err, l2)
+
+
+def test_autograd_function_matches_direct_backward():
+    log("case: autograd")
+    sc = synth.make_scene(2000, 2, "uniform", seed=12, log_scale_mean=-3.5)
+    views = [synth.look_at((0.2, 0.1, -3.0), width=64, height=48, s_v=1.7)]
+    scene = Scene(sc)
+    leaves = {k: scene.t[k].clone().requires_grad_(True) for k in scene.t}
+    b = Batch(sc["n"], views, params_struct(None))
+    rgb, eta, T, last = ClodRender.apply(leaves["mean"], leaves["log_scale"], leaves["quat"], leaves["opacity"],
+                                         leaves["decay"], leaves["sh"], b, sc["sh_degree"])
+    gr = torch.linspace(-1, 1, rgb.numel(), device="cuda")
+    (rgb * gr).sum().add_(0.5 * eta.sum()).backward()
+    got, want = _grad_case(sc, views, seed=0, dL_deta=None)
+    direct = b.render_bwd(scene, T, last, gr, torch.full((1,), 0.5, device="cuda"))
+    for k in leaves:
+        assert torch.allclose(leaves[k].grad, direct[k], rtol=0, atol=0), k
+    assert abs(float(eta[0]) - float(b.counts[0, 1]) / sc["n"]) < 1e-7
+
+
+def test_loss_matches_closed_forms():
+    """Eq. (3)-(5) with L1: loss per view, dL/drgb and dL/deta against FP64 formulas."""
+    log("case: loss")
+    sc = synth.make_scene(4000, 1, "uniform", seed=13)
+    views = [synth.look_at((0, 0, -3), width=70, height=50, s_v=3.0),
+             synth.look_at((1, 1, -3), width=33, height=65, s_v=1.0)]
+    scene = Scene(sc)
+    b = Batch(sc["n"], views, params_struct(None))
+    b.project(scene)
+    b.bin_sort()
+    rgb, T, last = b.render_fwd()
+    rng = np.random.default_rng(3)
+    target = torch.from_numpy(rng.uniform(size=rgb.numel()).astype(np.float32)).cuda()
+    loss, dL, deta = b.loss(rgb, target, s_max=8.0, lambda_reg=1.0)
+    cnt = b.counts.cpu().numpy()
+    rgb_h, tgt = rgb.cpu().numpy().astype(np.float64), target.cpu().numpy().astype(np.float64)
+    for v, view in enumerate(views):
+        a = 3 * int(b.pix_base[v])
+        m = 3 * view.width * view.height
+        diff = rgb_h[a:a + m] - tgt[a:a + m]
+        l1 = np.abs(diff).mean()
+        eta = cnt[v, 1] / sc["n"]
+        ref = O.total_loss(l1, view.s_v, eta, 8.0)
+        assert abs(float(loss[v]) - ref) <= 1e-5 * max(1.0, abs(ref)), (v, float(loss[v]), ref)
+        ws = O.w_s(view.s_v, 8.0)
+        np.testing.assert_allclose(dL[a:a + m].cpu().numpy(), ws * np.sign(diff) / m, rtol=1e-6)
+        deta_ref = ws * 2 * (view.s_v - 1) ** 2 * max(eta - O.eta_target(view.s_v), 0.0)
+        assert abs(float(deta[v]) - deta_ref) <= 1e-5 * max(1.0, abs(deta_ref))
+
+
+# --------------------------------------------------------------------------- full size
+
+def test_serving_size_sampled_parity():
+    """3,000,000 Gaussians (degree 3, 64-cluster mixture) at 1920x1080: counts bit-exact; on
+    32 sampled tiles the sorted lists, ranges, last indices, T and colour bit-exact."""
+    log("case: 3M 1080p sampled")
+    sc = synth.make_scene(3_000_000, 3, "mixture", seed=0)
+    v = synth.look_at((4.0, 3.0, -9.0), width=1920, height=1080, s_v=2.0)
+    g = gpu_forward(sc, [v])
+    r = O.render32(sc, v)
+    assert np.array_equal(g["counts"][0], r["counts"])
+    assert g["D"] == r["entries"].size
+    rng = np.random.default_rng(0)
+    T_t = r["tile_off"].size - 1
+    tiles = rng.choice(T_t, size=32, replace=False)
+    TW = (v.width + 15) // 16
+    for t in tiles:
+        a, b_ = int(r["tile_off"][t]), int(r["tile_off"][t + 1])
+        rg = g["ranges"][t]
+        if b_ > a:
+            assert rg[0] == a and rg[1] == b_
+            assert np.array_equal(g["vals"][a:b_].astype(np.int64), r["entries"][a:b_].astype(np.int64))
+        ty, tx = divmod(int(t), TW)
+        sl = (slice(ty * 16, min(ty * 16 + 16, v.height)), slice(tx * 16, min(tx * 16 + 16, v.width)))
+        assert np.array_equal(g["last"][0][sl], r["last"][sl])
+        assert np.array_equal(g["T"][0][sl].view(np.uint32), r["T"][sl].view(np.uint32))
+        assert np.array_equal(g["rgb"][0][(slice(None),) + sl].view(np.uint32), r["rgb"][(slice(None),) + sl].view(np.uint32))
+    # The whole image, too (the oracle has it anyway).
+    assert np.array_equal(g["last"][0], r["last"])
+    assert np.abs(g["rgb"][0] - r["rgb"]).max() == 0.0
