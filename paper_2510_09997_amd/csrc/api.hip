@@ -103,6 +103,8 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.counts = o; o = align256(o + (size_t)V * 3 * 8);
   L.gdmax = o; o = align256(o + (size_t)V * 4);
   L.loss_acc = o; o = align256(o + (size_t)V * 4);
+  L.kpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 8);
+  L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 3 * 4);
   L.flags = o; o = align256(o + (size_t)L.VN);
   L.rec = o; o = align256(o + (size_t)L.VN * 3 * 16);
   L.rect = o; o = align256(o + (size_t)L.VN * 8);
@@ -170,7 +172,7 @@ static clod_status prepare(const clod_batch* b, bool need_full_ws, Ctx& cx) {
   if (n * (int64_t)b->n_views >= 0xFFFFFFFFll) return fail(CLOD_E_ARG, "n * n_views must be < 2^32");
   cx.L = make_layout(need_full_ws ? n : 0, b->n_views, tiles_total, pixels_total);
   if (need_full_ws) cx.L.n = n;
-  const size_t need = need_full_ws ? cx.L.total : cx.L.flags;
+  const size_t need = need_full_ws ? cx.L.total : cx.L.flags;   // per-view area precedes the rest
   if (b->ws_bytes < need) return fail(CLOD_E_ARG, "ws_bytes %zu < required %zu", b->ws_bytes, need);
   return CLOD_OK;
 }
@@ -242,13 +244,12 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
   DevView* vinfo = (DevView*)(w + L.vinfo);
   HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, s), "view setup");
   HIP_TRY(launch_fill_u32((uint32_t*)(w + L.hdr), 0u, kHdrWords * 2, s), "clear header");
-  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.dmax_key), 0u, 2 * (int64_t)L.V, s), "clear dmax");
-  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.counts), 0u, 6 * (int64_t)L.V, s), "clear counts");
-  HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.dmax_key), s),
+  HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.kpart),
+                             (unsigned long long*)(w + L.dmax_key), s),
           "frustum max");
   HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
-                         (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags), (float4*)(w + L.rec),
-                         (uint2*)(w + L.rect), (uint32_t*)(w + L.tiles), s),
+                         (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags),
+                         (float4*)(w + L.rec), (uint2*)(w + L.rect), (uint32_t*)(w + L.tiles), s),
           "project");
   if (counts_dev)
     HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
@@ -345,12 +346,11 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
   char* w = (char*)batch->ws;
   DevView* vinfo = (DevView*)(w + L.vinfo);
   HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, s), "view setup");
-  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.dmax_key), 0u, 2 * (int64_t)L.V, s), "clear dmax");
-  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.counts), 0u, 6 * (int64_t)L.V, s), "clear counts");
-  HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.dmax_key), s),
+  HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.kpart),
+                             (unsigned long long*)(w + L.dmax_key), s),
           "frustum max");
   HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
-                           (unsigned long long*)(w + L.counts), s),
+                           (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), s),
           "lod count");
   HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
   return CLOD_OK;

@@ -24,10 +24,36 @@ __device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_
   return lo;
 }
 
-struct BlendEntry {
-  float u, v, hA, nB, hC, a2, r, g, b;
-};
+// Conservative per-quadrant cull of a staged entry.  A pixel centre p farther than
+// 1.2 * rad + 0.5 from the 2D mean has exact quadratic form d^T Q d > 12.96 (rad >= 3
+// sqrt(lambda_max)), i.e. power < -6.48.  The binary32 evaluation of power errs by at most
+// 6u (A dx^2 + C dy^2) <= 12u * (AC / (AC - B^2)) * d^T Q d (u = 2^-24), and the conic's own
+// rounding adds a comparable term; with AC / (AC - B^2) <= 5e4 both stay below 8%, so the
+// evaluated power is below -5.6 and the contract skips the entry.  Culled entries are
+// therefore exactly the ones the pixel loop would have skipped.  Entries with a worse
+// conditioned conic are never culled.
+__device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float A, float B, float C, float rad,
+                                                  float x0, float y0) {
+  const float ac = A * C;
+  const float det = ac - B * B;
+  if (!(det > 2e-5f * ac) || !(rad < 1e6f)) return 0xFu;
+  const float rc = 1.2f * rad + 0.5f;
+  const float rc2 = rc * rc;
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float qx = x0 + (float)((q & 1) * 8), qy = y0 + (float)((q >> 1) * 8);
+    const float ddx = fmaxf(0.0f, fmaxf(qx + 0.5f - u, u - (qx + 7.5f)));
+    const float ddy = fmaxf(0.0f, fmaxf(qy + 0.5f - v, v - (qy + 7.5f)));
+    if (ddx * ddx + ddy * ddy <= rc2) m |= 1u << q;
+  }
+  return m;
+}
 
+// Forward blend.  Wave w of the workgroup covers the 8x8 quadrant (w & 1, w >> 1) of the
+// tile, lane l the pixel (l & 7, l >> 3) in it.  Each staged batch of 256 entries is
+// compacted per quadrant (ballot prefix sums keep the sorted order), so a wave walks only the
+// entries that can touch its quadrant.
 __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
     const float4* __restrict__ rec, const uint2* __restrict__ ranges,
@@ -37,6 +63,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
   __shared__ float4 s0[kBlock];   // u, v, hA, nB
   __shared__ float4 s1[kBlock];   // hC, alpha'', r, g
   __shared__ float s2[kBlock];    // b
+  __shared__ uint16_t list[4][kBlock];
+  __shared__ uint32_t wc[4][4];   // [quadrant][staging wave] counts
   const int tile_i = xcd_tile(blockIdx.x, gridDim.x);
   if (tile_i >= (int)tiles_total) return;
   if (hdr[kHdrOverflow]) return;
@@ -44,19 +72,24 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
   const DevView& Vw = views[v];
   const int local = tile_i - (int)Vw.tile_base;
   const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
-  const int px = tx * kTile + (threadIdx.x & 15);
-  const int py = ty * kTile + (threadIdx.x >> 4);
+  const int wave = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  const int px = tx * kTile + (wave & 1) * 8 + (int)(lane & 7);
+  const int py = ty * kTile + (wave >> 1) * 8 + (int)(lane >> 3);
   const bool inside = px < Vw.width && py < Vw.height;
   const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
+  const float tx0 = (float)(tx * kTile), ty0 = (float)(ty * kTile);
   const uint2 rg = ranges[tile_i];
   const float kSkip = 0.0039215688593685627f;   // fl(1/255)
   const float kTmin = 9.99999974737875163e-05f; // fl(1e-4)
+  const uint64_t lt = lanemask_lt();
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-  uint32_t last = 0, evaluated = 0;
+  uint32_t last = 0, term = 0xFFFFFFFFu;
   bool done = !inside;
   for (uint32_t start = rg.x; start < rg.y; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
     const uint32_t j = start + threadIdx.x;
+    uint32_t qm = 0;
     if (j < rg.y) {
       uint32_t f = svals[j];
       if ((int64_t)f >= VN) f = 0;   // defensive: the sort only emits indices < V*n
@@ -66,31 +99,48 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
       s0[threadIdx.x] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
       s1[threadIdx.x] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
       s2[threadIdx.x] = g2.z;
+      qm = quadrant_mask(g0.x, g0.y, g1.x, g1.y, g1.z, g1.w, tx0, ty0);
+    }
+    uint32_t pre[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t b = ballot64((qm >> q) & 1u);
+      pre[q] = (uint32_t)__popcll(b & lt);
+      if (lane == 0) wc[q][wave] = (uint32_t)__popcll(b);
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)kBlock, rg.y - start);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if ((qm >> q) & 1u) {
+        uint32_t off = pre[q];
+        for (int w = 0; w < wave; ++w) off += wc[q][w];
+        list[q][off] = (uint16_t)threadIdx.x;
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)(wc[wave][0] + wc[wave][1] + wc[wave][2] + wc[wave][3]);
     for (int k = 0; k < cnt; ++k) {
       if (done) break;
-      const float4 a = s0[k];
-      const float4 c = s1[k];
-      ++evaluated;
+      const int e = list[wave][k];
+      const float4 a = s0[e];
+      const float4 c = s1[e];
       const float dx = a.x - pcx, dy = a.y - pcy;
       const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
       if (power > 0.0f) continue;
-      // exp(power) < fl(1/255) for power < -5.6 and alpha'' <= 1: the entry is skipped
-      // whatever the polynomial returns, so it is not evaluated.
+      // exp(power) < fl(1/255) for power < -5.6 and alpha'' <= 1: skipped either way.
       if (power < -5.6f) continue;
       const float prod = c.y * cexp(power);
       const float al = fminf(0.99f, prod);
       if (al < kSkip) continue;
       const float Tn = T * (1.0f - al);
-      if (Tn < kTmin) { done = true; break; }
+      const uint32_t pos = start - rg.x + (uint32_t)e;
+      if (Tn < kTmin) { done = true; term = pos; break; }
       const float w = al * T;
       cr = fmaf_(c.z, w, cr);
       cg = fmaf_(c.w, w, cg);
-      cb = fmaf_(s2[k], w, cb);
+      cb = fmaf_(s2[e], w, cb);
       T = Tn;
-      last = (uint32_t)(start - rg.x) + (uint32_t)k + 1u;
+      last = pos + 1u;
     }
   }
   if (inside) {
@@ -104,8 +154,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     lastout[P + p] = last;
   }
   if (pairs) {
-    unsigned long long e = wave_sum((unsigned long long)evaluated);
-    if (lane_id() == 0 && e) atomicAdd((unsigned long long*)pairs, e);
+    // Pairs the contract's per-pixel loop evaluates: up to and including the terminating
+    // entry, else the whole list.
+    const unsigned long long ev = !inside ? 0ull : (term != 0xFFFFFFFFu ? (unsigned long long)term + 1ull
+                                                                         : (unsigned long long)(rg.y - rg.x));
+    const unsigned long long e = wave_sum(ev);
+    if (lane == 0 && e) atomicAdd((unsigned long long*)pairs, e);
   }
 }
 
@@ -127,8 +181,10 @@ hipError_t launch_blend_fwd(const Layout& L, const void* ws, const uint32_t* sor
 // decision exactly as the forward; transmittance is recovered by division
 // (T_k = T_{k+1} / (1 - a_k)); the normalised colour of everything behind entry k obeys
 // R_{k-1} = c_k a_k + (1 - a_k) R_k with R = background after the last entry, so
-// dC/da_k = T_k (c_k - R_k).  Per entry the 9 screen-space partials are reduced over the
-// wave, summed over the 4 waves in LDS, and added to the global accumulator once per tile.
+// dC/da_k = T_k (c_k - R_k).  Same quadrant mapping and per-quadrant compaction as the
+// forward (culled entries are ones the forward skipped).  Per entry the 9 screen-space
+// partials are reduced over the wave, summed over the 4 waves in LDS, and added to the
+// global accumulator once per tile.
 __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
     const float4* __restrict__ rec, const uint2* __restrict__ ranges,
@@ -136,11 +192,13 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     float bg0, float bg1, float bg2, const float* __restrict__ Tin,
     const uint32_t* __restrict__ lastin, const float* __restrict__ dL_drgb,
     float* __restrict__ gscreen) {
-  __shared__ float4 s0[kBlock];
-  __shared__ float4 s1[kBlock];
-  __shared__ float s2[kBlock];
+  __shared__ float4 s0[kBlock];   // u, v, A, B
+  __shared__ float4 s1[kBlock];   // C, alpha'', r, g
+  __shared__ float s2[kBlock];    // b
   __shared__ float acc[kGscreen][kBlock];
   __shared__ uint32_t sidx[kBlock];
+  __shared__ uint16_t list[4][kBlock];
+  __shared__ uint32_t wc[4][4];
   __shared__ uint32_t smax[4];
   const int tile_i = xcd_tile(blockIdx.x, gridDim.x);
   if (tile_i >= (int)tiles_total) return;
@@ -149,15 +207,19 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   const DevView& Vw = views[v];
   const int local = tile_i - (int)Vw.tile_base;
   const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
-  const int px = tx * kTile + (threadIdx.x & 15);
-  const int py = ty * kTile + (threadIdx.x >> 4);
+  const int wave = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  const int px = tx * kTile + (wave & 1) * 8 + (int)(lane & 7);
+  const int py = ty * kTile + (wave >> 1) * 8 + (int)(lane >> 3);
   const bool inside = px < Vw.width && py < Vw.height;
   const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
+  const float tx0 = (float)(tx * kTile), ty0 = (float)(ty * kTile);
   const uint2 rg = ranges[tile_i];
   const float kSkip = 0.0039215688593685627f;
   const int64_t P = (int64_t)Vw.pix_base;
   const int64_t HW = (int64_t)Vw.width * Vw.height;
   const int64_t p = (int64_t)py * Vw.width + px;
+  const uint64_t lt = lanemask_lt();
   uint32_t last = 0;
   float T = 1.0f, g0c = 0.f, g1c = 0.f, g2c = 0.f;
   if (inside) {
@@ -172,30 +234,49 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   uint32_t m = last;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) { const uint32_t q = __shfl_xor(m, o, 64); m = q > m ? q : m; }
-  if (lane_id() == 0) smax[threadIdx.x >> 6] = m;
+  if (lane == 0) smax[wave] = m;
   __syncthreads();
   const uint32_t tmax = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
   const uint32_t end = rg.x + tmax;   // exclusive
-  const int wave = threadIdx.x >> 6;
   for (uint32_t hi = end; hi > rg.x;) {
     const uint32_t lo = hi > rg.x + kBlock ? hi - kBlock : rg.x;
     const int cnt = (int)(hi - lo);
     __syncthreads();
+    uint32_t qm = 0;
     if ((int)threadIdx.x < cnt) {
       uint32_t f = svals[lo + threadIdx.x];
       if ((int64_t)f >= VN) f = 0;   // defensive: the sort only emits indices < V*n
       const float4 a0 = rec[f];
       const float4 a1 = rec[VN + f];
       const float4 a2 = rec[2 * VN + f];
-      s0[threadIdx.x] = make_float4(a0.x, a0.y, a1.x, a1.y);   // u, v, A, B
-      s1[threadIdx.x] = make_float4(a1.z, a0.z, a2.x, a2.y);   // C, alpha'', r, g
+      s0[threadIdx.x] = make_float4(a0.x, a0.y, a1.x, a1.y);
+      s1[threadIdx.x] = make_float4(a1.z, a0.z, a2.x, a2.y);
       s2[threadIdx.x] = a2.z;
       sidx[threadIdx.x] = f;
+      qm = quadrant_mask(a0.x, a0.y, a1.x, a1.y, a1.z, a1.w, tx0, ty0);
     }
 #pragma unroll
     for (int q = 0; q < kGscreen; ++q) acc[q][threadIdx.x] = 0.0f;
+    uint32_t pre[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t b = ballot64((qm >> q) & 1u);
+      pre[q] = (uint32_t)__popcll(b & lt);
+      if (lane == 0) wc[q][wave] = (uint32_t)__popcll(b);
+    }
     __syncthreads();
-    for (int k = cnt - 1; k >= 0; --k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if ((qm >> q) & 1u) {
+        uint32_t off = pre[q];
+        for (int w = 0; w < wave; ++w) off += wc[q][w];
+        list[q][off] = (uint16_t)threadIdx.x;
+      }
+    }
+    __syncthreads();
+    const int qcnt = (int)(wc[wave][0] + wc[wave][1] + wc[wave][2] + wc[wave][3]);
+    for (int kk = qcnt - 1; kk >= 0; --kk) {
+      const int k = list[wave][kk];
       const uint32_t pos = lo - rg.x + (uint32_t)k;
       bool contrib = false;
       float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, ga2 = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
@@ -239,14 +320,13 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
         gu = wave_sum(gu); gv = wave_sum(gv); gA = wave_sum(gA); gB = wave_sum(gB);
         gC = wave_sum(gC); ga2 = wave_sum(ga2); gr = wave_sum(gr); gg = wave_sum(gg);
         gb = wave_sum(gb);
-        if (lane_id() == 0) {
+        if (lane == 0) {
           atomicAdd(&acc[0][k], gu); atomicAdd(&acc[1][k], gv); atomicAdd(&acc[2][k], gA);
           atomicAdd(&acc[3][k], gB); atomicAdd(&acc[4][k], gC); atomicAdd(&acc[5][k], ga2);
           atomicAdd(&acc[6][k], gr); atomicAdd(&acc[7][k], gg); atomicAdd(&acc[8][k], gb);
         }
       }
     }
-    (void)wave;
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
       const uint32_t f = sidx[threadIdx.x];

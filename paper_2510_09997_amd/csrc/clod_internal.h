@@ -16,6 +16,7 @@ constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kSortItems = 8;              // keys per thread per radix tile
 constexpr int kSortTile = kBlock * kSortItems;   // 2048 keys per radix tile
 constexpr int kMaxSortBlocks = 1024;
+constexpr int kMaxProjBlocks = 2048;      // per-block partial reductions of the per-Gaussian passes
 constexpr int kGscreen = 9;                // du, dv, dA, dB, dC, dalpha'', dr, dg, db
 
 // Per-view constants derived on the device from clod_view (k_view_setup).
@@ -38,8 +39,8 @@ struct Layout {
   int64_t pixels_total = 0;
   int32_t scan_blocks = 0;
   // byte offsets into ws
-  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, flags, rec, rect, tiles, scan_part,
-      ranges, gscreen, total;
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, flags, rec, rect, tiles,
+      scan_part, ranges, gscreen, total;
 };
 
 // Host-side per-view geometry (must agree with k_view_setup).
@@ -286,13 +287,14 @@ __device__ __forceinline__ T wave_sum(T v) {
 hipError_t launch_view_setup(const clod_view* views_dev, int V, clod_params prm, DevView* vinfo,
                              hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+int proj_blocks(int64_t n);
 hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V, float near_z,
-                              unsigned long long* dmax_key, hipStream_t s);
+                              unsigned long long* kpart, unsigned long long* dmax_key, hipStream_t s);
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                          const unsigned long long* dmax_key, unsigned long long* counts,
+                          const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                           uint8_t* flags, float4* rec, uint2* rect, uint32_t* tiles, hipStream_t s);
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                            const unsigned long long* dmax_key, unsigned long long* counts,
+                            const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             hipStream_t s);
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s);
 

@@ -45,118 +45,187 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
     p[i] = value;
 }
 
+// Per-block partials instead of global atomics: block b owns the contiguous chunk
+// [b*C, (b+1)*C) of Gaussians and writes one partial per view (the frustum-max key, the three
+// counts); k_reduce_partials folds them per view.  Same-address atomics from every wave
+// serialise in L2 and would dominate these otherwise bandwidth-bound kernels.
+__device__ __forceinline__ void block_chunk(int64_t n, int64_t& lo, int64_t& hi) {
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  lo = (int64_t)blockIdx.x * per;
+  hi = lo + per;
+  if (lo > n) lo = n;
+  if (hi > n) hi = n;
+}
+
 // Frustum maximum of d per view: key = bits(d) << 32 | (2^32 - 1 - i), so the 64-bit
 // maximum is the largest distance and, among equal distances, the lowest index.
 __global__ __launch_bounds__(kBlock) void k_frustum_max(
     const float* __restrict__ mean, int64_t n, const DevView* __restrict__ views, int V,
-    float near_z, unsigned long long* __restrict__ dmax_key) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = i < n;
-  float mx = 0.f, my = 0.f, mz = 0.f;
-  if (valid) { mx = mean[i]; my = mean[n + i]; mz = mean[2 * n + i]; }
+    float near_z, unsigned long long* __restrict__ part /* [G][V] */) {
+  __shared__ unsigned long long sm[4];
+  int64_t lo, hi;
+  block_chunk(n, lo, hi);
   for (int v = 0; v < V; ++v) {
     const DevView& Vw = views[v];
     unsigned long long key = 0ull;
-    if (valid) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+      const float mx = mean[i], my = mean[n + i], mz = mean[2 * n + i];
       float x, y, z, ex, ey, ez;
       to_camera(Vw, mx, my, mz, x, y, z);
       if (in_frustum(Vw, x, y, z, near_z)) {
         const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
-        key = ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+        const unsigned long long k =
+            ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+        key = k > key ? k : key;
       }
     }
-    // Wave maximum, then one atomic per wave.
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const unsigned long long other = __shfl_xor(key, o, 64);
       key = other > key ? other : key;
     }
-    if (lane_id() == 0 && key != 0ull) atomicMax(dmax_key + v, key);
+    if (lane_id() == 0) sm[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long m = sm[0];
+      for (int w = 1; w < 4; ++w) m = sm[w] > m ? sm[w] : m;
+      part[(int64_t)blockIdx.x * V + v] = m;
+    }
+    __syncthreads();
   }
-}
-
-__device__ __forceinline__ void wave_count_add(unsigned long long* dst, bool pred) {
-  const uint64_t b = ballot64(pred);
-  if (lane_id() == 0 && b) atomicAdd(dst, (unsigned long long)__popcll(b));
 }
 
 template <bool kWriteRecords>
 __global__ __launch_bounds__(kBlock) void k_project(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
-    const unsigned long long* __restrict__ dmax_key, unsigned long long* __restrict__ counts,
+    const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
     uint8_t* __restrict__ flags_out, float4* __restrict__ rec, uint2* __restrict__ rect_out,
     uint32_t* __restrict__ tiles_out) {
+  extern __shared__ uint32_t scnt[];   // [V][3]
   const int64_t n = sc.n;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = i < n;
   const int deg = sc.sh_degree;
   const int K = (deg + 1) * (deg + 1);
-  float mx = 0.f, my = 0.f, mz = 0.f, op = 0.f, dc = 0.f;
-  if (valid) {
-    mx = sc.mean[i]; my = sc.mean[n + i]; mz = sc.mean[2 * n + i];
-    op = sc.opacity[i]; dc = sc.decay[i];
-  }
-  // Rotation and 3D covariance are view independent: computed on first use.
-  bool have_cov = false;
-  float S[9];
-  for (int v = 0; v < V; ++v) {
-    const DevView& Vw = views[v];
-    const int64_t f = (int64_t)v * n + i;
-    bool F = false, M = false, R = false;
-    uint8_t fl = 0;
+  for (int j = threadIdx.x; j < 3 * V; j += kBlock) scnt[j] = 0;
+  __syncthreads();
+  int64_t lo, hi;
+  block_chunk(n, lo, hi);
+  // Every lane of the block runs the same number of iterations (ballots stay uniform).
+  const int64_t iters = (hi - lo + kBlock - 1) / kBlock;
+  for (int64_t it = 0; it < iters; ++it) {
+    const int64_t i = lo + it * kBlock + threadIdx.x;
+    const bool valid = i < hi;
+    float mx = 0.f, my = 0.f, mz = 0.f, op = 0.f, dc = 0.f;
     if (valid) {
-      float x, y, z, ex, ey, ez;
-      to_camera(Vw, mx, my, mz, x, y, z);
-      F = in_frustum(Vw, x, y, z, prm.near_z);
-      const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
-      const float dmax = dmax_from_key(dmax_key[v]);
-      float alpha, q;
-      const float a2 = attenuated(d, dmax, Vw.s_v, dc, op, prm.eps, alpha, q);
-      M = a2 > Vw.tau_sv;
-      fl = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
-      float4 g0 = make_float4(0.f, 0.f, a2, 0.f);
-      if (F && M) {
-        if (!have_cov) {
-          const float s0 = cexp(sc.log_scale[i]), s1 = cexp(sc.log_scale[n + i]), s2 = cexp(sc.log_scale[2 * n + i]);
-          float Rm[9], w_, x_, y_, z_, rn;
-          quat_rot(sc.quat[i], sc.quat[n + i], sc.quat[2 * n + i], sc.quat[3 * n + i], Rm, w_, x_, y_, z_, rn);
-          cov3(Rm, s0, s1, s2, S);
-          have_cov = true;
-        }
-        Proj P;
-        if (ewa(Vw, x, y, z, S, prm.dilation, P)) {
-          R = true;
-          if (kWriteRecords) {
-            const float id = 1.0f / d;
-            float Yb[16];
-            sh_basis(deg, ex * id, ey * id, ez * id, Yb);
-            float col[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-              float acc = sc.sh[(int64_t)ch * n + i] * Yb[0];
-              for (int k = 1; k < K; ++k) acc = fmaf_(sc.sh[((int64_t)k * 3 + ch) * n + i], Yb[k], acc);
-              const float cv = acc + 0.5f;
-              if (!(cv > 0.0f)) fl |= (uint8_t)(8 << ch);
-              col[ch] = fmaxf(cv, 0.0f);
-            }
-            g0 = make_float4(P.u, P.v, a2, z);
-            rec[(int64_t)V * n + f] = make_float4(P.A, P.B, P.C, P.rad);
-            rec[2 * (int64_t)V * n + f] = make_float4(col[0], col[1], col[2], 0.f);
-            rect_out[f] = make_uint2((uint32_t)P.x0 | ((uint32_t)P.x1 << 16), (uint32_t)P.y0 | ((uint32_t)P.y1 << 16));
-            tiles_out[f] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+      mx = sc.mean[i]; my = sc.mean[n + i]; mz = sc.mean[2 * n + i];
+      op = sc.opacity[i]; dc = sc.decay[i];
+    }
+    // Rotation and 3D covariance are view independent: computed on first use.
+    bool have_cov = false;
+    float S[9];
+    for (int v = 0; v < V; ++v) {
+      const DevView& Vw = views[v];
+      const int64_t f = (int64_t)v * n + i;
+      bool F = false, M = false, R = false;
+      uint8_t fl = 0;
+      if (valid) {
+        float x, y, z, ex, ey, ez;
+        to_camera(Vw, mx, my, mz, x, y, z);
+        F = in_frustum(Vw, x, y, z, prm.near_z);
+        const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
+        const float dmax = dmax_from_key(dmax_key[v]);
+        float alpha, q;
+        const float a2 = attenuated(d, dmax, Vw.s_v, dc, op, prm.eps, alpha, q);
+        M = a2 > Vw.tau_sv;
+        fl = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
+        float4 g0 = make_float4(0.f, 0.f, a2, 0.f);
+        if (F && M) {
+          if (!have_cov) {
+            const float s0 = cexp(sc.log_scale[i]), s1 = cexp(sc.log_scale[n + i]), s2 = cexp(sc.log_scale[2 * n + i]);
+            float Rm[9], w_, x_, y_, z_, rn;
+            quat_rot(sc.quat[i], sc.quat[n + i], sc.quat[2 * n + i], sc.quat[3 * n + i], Rm, w_, x_, y_, z_, rn);
+            cov3(Rm, s0, s1, s2, S);
+            have_cov = true;
           }
-          fl |= 4;
+          Proj P;
+          if (ewa(Vw, x, y, z, S, prm.dilation, P)) {
+            R = true;
+            if (kWriteRecords) {
+              const float id = 1.0f / d;
+              float Yb[16];
+              sh_basis(deg, ex * id, ey * id, ez * id, Yb);
+              float col[3];
+#pragma unroll
+              for (int ch = 0; ch < 3; ++ch) {
+                float acc = sc.sh[(int64_t)ch * n + i] * Yb[0];
+                for (int k = 1; k < K; ++k) acc = fmaf_(sc.sh[((int64_t)k * 3 + ch) * n + i], Yb[k], acc);
+                const float cv = acc + 0.5f;
+                if (!(cv > 0.0f)) fl |= (uint8_t)(8 << ch);
+                col[ch] = fmaxf(cv, 0.0f);
+              }
+              g0 = make_float4(P.u, P.v, a2, z);
+              rec[(int64_t)V * n + f] = make_float4(P.A, P.B, P.C, P.rad);
+              rec[2 * (int64_t)V * n + f] = make_float4(col[0], col[1], col[2], 0.f);
+              rect_out[f] = make_uint2((uint32_t)P.x0 | ((uint32_t)P.x1 << 16), (uint32_t)P.y0 | ((uint32_t)P.y1 << 16));
+              tiles_out[f] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+            }
+            fl |= 4;
+          }
+        }
+        if (kWriteRecords) {
+          rec[f] = g0;
+          if (!R) tiles_out[f] = 0u;
+          flags_out[f] = fl;
         }
       }
-      if (kWriteRecords) {
-        rec[f] = g0;
-        if (!R) tiles_out[f] = 0u;
-        flags_out[f] = fl;
+      const uint64_t bF = ballot64(F), bM = ballot64(M), bR = ballot64(R);
+      if (lane_id() == 0) {
+        if (bF) atomicAdd(&scnt[3 * v + 0], (uint32_t)__popcll(bF));
+        if (bM) atomicAdd(&scnt[3 * v + 1], (uint32_t)__popcll(bM));
+        if (bR) atomicAdd(&scnt[3 * v + 2], (uint32_t)__popcll(bR));
       }
     }
-    wave_count_add(counts + 3 * v + 0, F);
-    wave_count_add(counts + 3 * v + 1, M);
-    wave_count_add(counts + 3 * v + 2, R);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < 3 * V; j += kBlock) cpart[(int64_t)blockIdx.x * 3 * V + j] = scnt[j];
+}
+
+// Block v folds the G partials of view v: the frustum-max key (max) and the counts (sum).
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const unsigned long long* __restrict__ kpart,
+                                                            const uint32_t* __restrict__ cpart, int G, int V,
+                                                            unsigned long long* __restrict__ dmax_key,
+                                                            unsigned long long* __restrict__ counts) {
+  __shared__ unsigned long long sm[4][4];
+  const int v = blockIdx.x;
+  unsigned long long key = 0ull, c0 = 0, c1 = 0, c2 = 0;
+  for (int b = threadIdx.x; b < G; b += kBlock) {
+    if (kpart) {
+      const unsigned long long k = kpart[(int64_t)b * V + v];
+      key = k > key ? k : key;
+    }
+    if (cpart) {
+      c0 += cpart[((int64_t)b * V + v) * 3 + 0];
+      c1 += cpart[((int64_t)b * V + v) * 3 + 1];
+      c2 += cpart[((int64_t)b * V + v) * 3 + 2];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long ok = __shfl_xor(key, o, 64);
+    key = ok > key ? ok : key;
+    c0 += __shfl_xor(c0, o, 64);
+    c1 += __shfl_xor(c1, o, 64);
+    c2 += __shfl_xor(c2, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) { sm[w][0] = key; sm[w][1] = c0; sm[w][2] = c1; sm[w][3] = c2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 1; j < 4; ++j) {
+      key = sm[j][0] > key ? sm[j][0] : key;
+      c0 += sm[j][1]; c1 += sm[j][2]; c2 += sm[j][3];
+    }
+    if (kpart) dmax_key[v] = key;
+    if (cpart) { counts[3 * v] = c0; counts[3 * v + 1] = c1; counts[3 * v + 2] = c2; }
   }
 }
 
@@ -165,7 +234,12 @@ __global__ void k_counts_out(const unsigned long long* __restrict__ c, int V, in
   if (j < 3 * V) out[j] = (int64_t)c[j];
 }
 
-static int grid_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+int proj_blocks(int64_t n) {
+  int64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
+  if (g < 1) g = 1;
+  if (g > kMaxProjBlocks) g = kMaxProjBlocks;
+  return (int)g;
+}
 
 hipError_t launch_view_setup(const clod_view* views_dev, int V, clod_params prm, DevView* vinfo,
                              hipStream_t s) {
@@ -182,29 +256,38 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 }
 
 hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V, float near_z,
-                              unsigned long long* dmax_key, hipStream_t s) {
-  if (sc.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_frustum_max, dim3(grid_for(sc.n)), dim3(kBlock), 0, s, sc.mean, sc.n, vinfo,
-                     V, near_z, dmax_key);
+                              unsigned long long* kpart, unsigned long long* dmax_key, hipStream_t s) {
+  if (sc.n == 0) return launch_fill_u32((uint32_t*)dmax_key, 0u, 2 * (int64_t)V, s);
+  const int G = proj_blocks(sc.n);
+  hipLaunchKernelGGL(k_frustum_max, dim3(G), dim3(kBlock), 0, s, sc.mean, sc.n, vinfo, V, near_z, kpart);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)kpart,
+                     (const uint32_t*)nullptr, G, V, dmax_key, (unsigned long long*)nullptr);
+  return hipGetLastError();
+}
+
+template <bool kWrite>
+static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
+                               const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
+                               uint8_t* flags, float4* rec, uint2* rect, uint32_t* tiles, hipStream_t s) {
+  if (sc.n == 0) return launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
+  const int G = proj_blocks(sc.n);
+  hipLaunchKernelGGL(k_project<kWrite>, dim3(G), dim3(kBlock), (size_t)(3 * V * sizeof(uint32_t)), s, sc, vinfo,
+                     V, prm, dmax_key, cpart, flags, rec, rect, tiles);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
+                     (const uint32_t*)cpart, G, V, (unsigned long long*)nullptr, counts);
   return hipGetLastError();
 }
 
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                          const unsigned long long* dmax_key, unsigned long long* counts,
+                          const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                           uint8_t* flags, float4* rec, uint2* rect, uint32_t* tiles, hipStream_t s) {
-  if (sc.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_project<true>, dim3(grid_for(sc.n)), dim3(kBlock), 0, s, sc, vinfo, V, prm,
-                     dmax_key, counts, flags, rec, rect, tiles);
-  return hipGetLastError();
+  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, flags, rec, rect, tiles, s);
 }
 
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                            const unsigned long long* dmax_key, unsigned long long* counts,
+                            const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             hipStream_t s) {
-  if (sc.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_project<false>, dim3(grid_for(sc.n)), dim3(kBlock), 0, s, sc, vinfo, V, prm,
-                     dmax_key, counts, nullptr, nullptr, nullptr, nullptr);
-  return hipGetLastError();
+  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, nullptr, s);
 }
 
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s) {
