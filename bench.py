@@ -76,7 +76,7 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     cap = int(dmax * 1.1) + 4096
     b._alloc_dup(cap)
     log(f"[bench] max pairs per 5-frame step {dmax}, capacity {cap}")
-    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pairs = torch.zeros(3, dtype=torch.int64, device="cuda")
     rgb = torch.empty(3 * b.pixels, device="cuda")
     T = torch.empty(b.pixels, device="cuda")
     last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
@@ -117,10 +117,12 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     frames = len(SV_SWEEP) * K
     res = dict(total_ms=total_ms, ms_per_step=total_ms / K, fps=frames / (total_ms / 1e3),
                stage_ms=dict(project=proj_ms, bin_sort=sort_ms, blend_fwd=blend_ms),
-               pairs_per_step=int(pairs.item()) / K, max_dup=dmax)
+               pairs_per_step=(pairs.cpu().numpy() / K).tolist(), max_dup=dmax, blend_launches=K)
     # Per-view kept counts of the last step (mask counts fall with s_v).
     res["counts_last_step"] = b.counts.cpu().numpy().tolist()
 
+    if args.no_plain:
+        return res, scene, b, steps
     # Plain per-request path: one view per pass, same frames.
     single = [Batch(n, [steps[0][i]], dup_capacity=cap) for i in range(len(SV_SWEEP))]
     singles_host = [[C.make_views([v]) for v in vs] for vs in steps]
@@ -212,18 +214,51 @@ def run_train(args, torch, C, Batch, Scene, synth):
                 bwd_ms=bwd_ms, max_dup=dmax)
 
 
-def cpu_baseline(steps, n_frames=1):
-    """The oracle (binary32 contract, OpenMP) on one frame of the headline workload."""
+def run_serve_stream(args, torch, Scene, synth):
+    """Poisson stream at 200 req/s over the 3M scene, mixed resolutions {720p, 1080p, 4K},
+    s_v log-uniform in [1, 16]: continuous batching and the plain path, p50/p99 latency."""
+    from paper_2510_09997_amd.serve import serve, summarize
+    n = 3_000_000
+    sc = synth.make_scene(n, 3, "mixture", seed=0)
+    scene = Scene(sc)
+    del sc
+    warm = args.serve_warmup
+    reqs = synth.poisson_requests(1, warm + args.serve_requests, rate_hz=200.0)
+    out = {}
+    for mode in ("continuous", "plain"):
+        recs, ex, sch = serve(scene, reqs, mode=mode, budget_bytes=24 << 30, max_batch=8, max_inflight=3)
+        s = summarize(recs, first=warm)
+        s["retries"] = ex.retries
+        s["batches"] = sch.batches
+        s["peak_hbm_gib"] = round(sch.peak_in_use / 2 ** 30, 3)
+        out[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+        log(f"[bench] serve {mode}: {out[mode]}")
+    return out
+
+
+def cpu_baseline(steps, sv_index=(0, 2, 4)):
+    """The oracle (binary32 contract, OpenMP over tiles) on a bounded sample of the headline
+    workload: three of the five LoD frames of the first timed pose."""
     from oracle import oracle as O
     from paper_2510_09997_amd import synth
     sc = synth.make_scene(3_000_000, 3, "mixture", seed=0)
-    view = steps[0][0]
+    frames = [steps[0][i] for i in sv_index]
     t0 = time.perf_counter()
-    for _ in range(n_frames):
+    for view in frames:
         O.render32(sc, view)
     dt = time.perf_counter() - t0
-    return dict(value=n_frames / dt, unit="frames/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{n_frames} frame(s): pose 0 at s_v=1, 1920x1080, 3M Gaussians ({dt:.1f} s)")
+    svs = ", ".join(f"{v.s_v:g}" for v in frames)
+    return dict(value=round(len(frames) / dt, 4), unit="frames/s", cores=O.num_threads(), kind="oracle",
+                sample=f"{len(frames)} frames of 1920x1080 at 3M Gaussians (pose 0, s_v = {svs}): {dt:.1f} s")
+
+
+# Algorithmic work of the blend's per-pixel loop (binary32 contract), flops per pair class:
+# every evaluated pair 12 (offsets 2, quadratic form 8 with fma = 2, two comparisons),
+# pairs whose exponential is evaluated 24 more (exponential 21, product, clamp, skip test),
+# blended pairs 10 more (1 - a, T update, termination test, weight, three fused colour
+# updates).
+FLOPS_EVAL, FLOPS_EXP, FLOPS_BLEND = 12, 24, 10
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def main():
@@ -234,6 +269,12 @@ def main():
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-request comparison path")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run a 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -251,8 +292,12 @@ def main():
     if not args.no_train:
         train = run_train(args, torch, C, Batch, Scene, synth)
         log(f"[bench] train: {train['ms_per_iter']:.2f} ms/iter")
-    # Roofline of the dominant forward kernel (blend): algorithmic ALU work per evaluated pair.
+    # Roofline of the dominant kernel of the headline workload (the forward blend, one launch
+    # per step, timed with events around its own launch on the stream it runs on).
     blend_ms = serve["stage_ms"]["blend_fwd"]
+    e, x, bl = serve["pairs_per_step"]
+    flops = FLOPS_EVAL * e + FLOPS_EXP * x + FLOPS_BLEND * bl
+    achieved = flops / (blend_ms * 1e-3) / 1e12
     out = {
         "metric": "1080p frames/s at 3M Gaussians across LoD distances; fwd+bwd ms/iter; p99 ms",
         "value": round(serve["fps"], 2),
@@ -269,9 +314,13 @@ def main():
         "config": {"workload": "serve-1080p-3M-lod-sweep", "gaussians": 3_000_000, "sh_degree": 3,
                    "resolution": [1920, 1080], "s_v": list(SV_SWEEP), "frames_per_step": len(SV_SWEEP),
                    "pose_radius": [3.0, 30.0]},
-        "plain_path_fps": round(serve["plain_fps"], 2),
+        "plain_path_fps": round(serve["plain_fps"], 2) if "plain_fps" in serve else None,
         "stage_ms": {k: round(v, 4) for k, v in serve["stage_ms"].items()},
-        "pairs_per_step": serve["pairs_per_step"],
+        "pairs_per_step": {"evaluated": e, "exp": x, "blended": bl},
+        "roofline": {"kernel": "k_blend_fwd", "bound": "alu", "achieved": round(achieved, 3),
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "avg_launch_ms": round(blend_ms, 4)},
     }
     if train is not None:
         out["fwd_bwd_ms_per_iter"] = round(train["ms_per_iter"], 3)
@@ -279,6 +328,20 @@ def main():
         out["fwd_bwd_p99_ms"] = round(train["p99_ms"], 3)
         out["train_config"] = {"gaussians": 1_000_000, "sh_degree": 3, "resolution": [1297, 840],
                                "s_v": "log-uniform [1, 8]", "loss": "L1 + point-count regulariser"}
+    if args.probe_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        st = run_serve_stream(args, torch, Scene, synth)
+        out["serve_stream"] = {"rate_hz": 200.0, "requests": args.serve_requests,
+                               "resolutions": ["1280x720", "1920x1080", "3840x2160"], "s_v": "log-uniform [1, 16]",
+                               **st}
+        out["p99_ms"] = st["continuous"]["p99_ms"]
+        out["p50_ms"] = st["continuous"]["p50_ms"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(steps)
     print(json.dumps(out), flush=True)

@@ -134,8 +134,9 @@ clod_status clod_bin_sort(const clod_batch *batch, int64_t *n_dup_host, void *st
    alpha'_i = alpha''_i G2D_i (clamped to 0.99, skipped below 1/255), stopping before the
    entry that would bring transmittance below 1e-4.  Writes rgb (colour + T * bg), the final
    transmittance T and last = 1 + position (within the tile's list) of the last blended entry
-   (0 if none).  pairs_dev (nullable, device int64 [1]) is incremented by the number of
-   (pixel, entry) pairs evaluated. */
+   (0 if none).  pairs_dev (nullable, device int64 [3]) is incremented by the work of the
+   per-pixel loop: {pairs evaluated (entries visited up to and including the terminating one),
+   pairs whose exponential is evaluated (power in [-5.6, 0]), pairs blended}. */
 clod_status clod_render_fwd(const clod_batch *batch, float *rgb, float *T, uint32_t *last,
                             int64_t *pairs_dev, void *stream);
 
@@ -185,10 +186,13 @@ clod_status clod_read_info(const clod_batch *batch, int64_t *info_host, void *st
                        bits 3..5 colour clamped
      CLOD_SEC_DMAX     uint64 per view: bits(d_max) << 32 | (2^32 - 1 - argmax), 0 if empty
      CLOD_SEC_RECT     uint32 pairs per (view, Gaussian): x0 | x1 << 16, y0 | y1 << 16
-     CLOD_SEC_GSCREEN  float [9][n_views * n] screen-space partials of the last backward */
+     CLOD_SEC_GSCREEN  float [9][n_views * n] screen-space partials of the last backward
+     CLOD_SEC_HEADER   uint64 [2] = {D of the last clod_bin_sort, overflow flag} (count = 2);
+                       an asynchronous copy of it avoids the synchronisation of clod_read_info */
 enum {
   CLOD_SEC_KEYS = 0, CLOD_SEC_VALUES = 1, CLOD_SEC_RANGES = 2, CLOD_SEC_REC0 = 3, CLOD_SEC_REC1 = 4,
-  CLOD_SEC_REC2 = 5, CLOD_SEC_FLAGS = 6, CLOD_SEC_DMAX = 7, CLOD_SEC_RECT = 8, CLOD_SEC_GSCREEN = 9
+  CLOD_SEC_REC2 = 5, CLOD_SEC_FLAGS = 6, CLOD_SEC_DMAX = 7, CLOD_SEC_RECT = 8, CLOD_SEC_GSCREEN = 9,
+  CLOD_SEC_HEADER = 10
 };
 clod_status clod_inspect(const clod_batch *batch, int32_t section, const void **dev_ptr,
                          int64_t *count);

@@ -420,8 +420,22 @@ int64_t oracle_tile_lists(int64_t n, const uint8_t *flags, const float *rec, con
 /* status (nullable) receives per list position: 0 skipped / not reached, 1 blended,      */
 /* 2 blended with the 0.99 clamp active.                                                  */
 /* ------------------------------------------------------------------------------------ */
+static int64_t blend_pixel_counts(int px, int py, const float *rec, const int32_t *list, int64_t len,
+                                  float *out_rgb, float *out_T, int32_t *out_last, uint8_t *status,
+                                  int64_t *nexp_out, int64_t *nblend_out);
 static int64_t blend_pixel(int px, int py, const float *rec, const int32_t *list, int64_t len,
                            float *out_rgb, float *out_T, int32_t *out_last, uint8_t *status) {
+    int64_t a, b;
+    return blend_pixel_counts(px, py, rec, list, len, out_rgb, out_T, out_last, status, &a, &b);
+}
+
+/* Also counts the pairs whose exponential is needed (power in [-5.6, 0]; below -5.6 the
+   product with alpha'' <= 1 is under 1/255 whatever the exponential returns) and the pairs
+   blended. */
+static int64_t blend_pixel_counts(int px, int py, const float *rec, const int32_t *list, int64_t len,
+                                  float *out_rgb, float *out_T, int32_t *out_last, uint8_t *status,
+                                  int64_t *nexp_out, int64_t *nblend_out) {
+    int64_t nexp = 0, nblend = 0;
     const float skip = (float)(1.0 / 255.0);
     const float tmin = 1e-4f;
     float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
@@ -435,11 +449,13 @@ static int64_t blend_pixel(int px, int py, const float *rec, const int32_t *list
         float hA = -0.5f * g[3], hC = -0.5f * g[5], nB = -g[4];
         float power = fmaf(hA * dx, dx, fmaf(hC * dy, dy, (nB * dx) * dy));
         if (power > 0.0f) continue;
+        if (power >= -5.6f) ++nexp;
         float prod = g[6] * cexp32(power);
         float a = fminf(0.99f, prod);
         if (a < skip) continue;
         float Tn = T * (1.0f - a);
         if (Tn < tmin) break;
+        ++nblend;
         float wgt = a * T;
         cr = fmaf(g[7], wgt, cr);
         cg = fmaf(g[8], wgt, cg);
@@ -451,17 +467,19 @@ static int64_t blend_pixel(int px, int py, const float *rec, const int32_t *list
     out_rgb[0] = cr; out_rgb[1] = cg; out_rgb[2] = cb;
     *out_T = T;
     *out_last = last;
+    *nexp_out = nexp;
+    *nblend_out = nblend;
     return evaluated;
 }
 
 /* Full image: rgb [3][h][w] (colour plus T * bg), T [h][w], last [h][w].
    Returns the number of (pixel, entry) pairs evaluated. */
 int64_t oracle_blend(int w, int h, const float *rec, const int64_t *tile_off, const int32_t *entries,
-                     const float *bg3, float *rgb, float *Tout, int32_t *last) {
+                     const float *bg3, float *rgb, float *Tout, int32_t *last, int64_t *classes) {
     const int TW = (w + 15) / 16, TH = (h + 15) / 16;
-    int64_t pairs = 0;
+    int64_t pairs = 0, nx = 0, nb = 0;
     const int64_t HW = (int64_t)w * h;
-#pragma omp parallel for schedule(dynamic, 4) reduction(+ : pairs)
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : pairs, nx, nb)
     for (int64_t t = 0; t < (int64_t)TW * TH; ++t) {
         int tx = (int)(t % TW), ty = (int)(t / TW);
         for (int ly = 0; ly < 16; ++ly)
@@ -470,7 +488,11 @@ int64_t oracle_blend(int w, int h, const float *rec, const int64_t *tile_off, co
                 if (px >= w || py >= h) continue;
                 float c[3], T;
                 int32_t l;
-                pairs += blend_pixel(px, py, rec, entries + tile_off[t], tile_off[t + 1] - tile_off[t], c, &T, &l, NULL);
+                int64_t ex, bl;
+                pairs += blend_pixel_counts(px, py, rec, entries + tile_off[t], tile_off[t + 1] - tile_off[t], c, &T,
+                                            &l, NULL, &ex, &bl);
+                nx += ex;
+                nb += bl;
                 int64_t p = (int64_t)py * w + px;
                 rgb[p] = fmaf(T, bg3[0], c[0]);
                 rgb[HW + p] = fmaf(T, bg3[1], c[1]);
@@ -479,6 +501,7 @@ int64_t oracle_blend(int w, int h, const float *rec, const int64_t *tile_off, co
                 last[p] = l;
             }
     }
+    if (classes) { classes[0] = pairs; classes[1] = nx; classes[2] = nb; }
     return pairs;
 }
 

@@ -68,7 +68,7 @@ def lib():
         L.oracle_view_pass.argtypes = [i64, ctypes.c_int] + [P] * 8 + [P] * 7
         L.oracle_tile_lists.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_int, P, P, i64]
         L.oracle_tile_lists.restype = i64
-        L.oracle_blend.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P]
+        L.oracle_blend.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P]
         L.oracle_blend.restype = i64
         L.oracle_tile_status.argtypes = [ctypes.c_int, ctypes.c_int, i64, P, P, P, i64, P]
         L.oracle_blend_one.argtypes = [ctypes.c_int, ctypes.c_int, P, P, i64, P, P, P]
@@ -158,22 +158,23 @@ def tile_lists(vp: dict):
 
 def blend(vp: dict, off: np.ndarray, ent: np.ndarray, params: dict | None = None):
     """Eq. (1) per pixel over its tile list.  Returns rgb [3][H][W], T [H][W], last [H][W],
-    and the number of (pixel, entry) pairs evaluated."""
+    and the pair counts {evaluated, exponential needed, blended}."""
     w, h = vp["width"], vp["height"]
     bg = pack_params(params)[5:8].copy()
     rgb = np.zeros((3, h, w), dtype=np.float32)
     T = np.zeros((h, w), dtype=np.float32)
     last = np.zeros((h, w), dtype=np.int32)
     ent_c = np.ascontiguousarray(ent if ent.size else np.zeros(1, np.int32))
-    pairs = lib().oracle_blend(w, h, _p(vp["rec"]), _p(off), _p(ent_c), _p(bg), _p(rgb), _p(T), _p(last))
-    return rgb, T, last, int(pairs)
+    classes = np.zeros(3, np.int64)
+    lib().oracle_blend(w, h, _p(vp["rec"]), _p(off), _p(ent_c), _p(bg), _p(rgb), _p(T), _p(last), _p(classes))
+    return rgb, T, last, classes
 
 
 def render32(scene: dict, view, params: dict | None = None) -> dict:
     vp = view_pass(scene, view, params)
     off, ent = tile_lists(vp)
-    rgb, T, last, pairs = blend(vp, off, ent, params)
-    vp.update(tile_off=off, entries=ent, rgb=rgb, T=T, last=last, pairs=pairs)
+    rgb, T, last, classes = blend(vp, off, ent, params)
+    vp.update(tile_off=off, entries=ent, rgb=rgb, T=T, last=last, pairs=int(classes[0]), pair_classes=classes)
     return vp
 
 

@@ -67,7 +67,8 @@ EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
            "clod_inspect", "clod_last_error", "clod_abi_version"]
 
-SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC0, SEC_REC1, SEC_REC2, SEC_FLAGS, SEC_DMAX, SEC_RECT, SEC_GSCREEN = range(10)
+(SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC0, SEC_REC1, SEC_REC2, SEC_FLAGS, SEC_DMAX, SEC_RECT, SEC_GSCREEN,
+ SEC_HEADER) = range(11)
 
 _lib = None
 

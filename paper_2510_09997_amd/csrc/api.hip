@@ -419,6 +419,7 @@ clod_status clod_inspect(const clod_batch* batch, int32_t section, const void** 
     case CLOD_SEC_DMAX: *dev_ptr = w + L.dmax_key; *count = L.V; break;
     case CLOD_SEC_RECT: *dev_ptr = w + L.rect; *count = L.VN; break;
     case CLOD_SEC_GSCREEN: *dev_ptr = w + L.gscreen; *count = L.VN; break;
+    case CLOD_SEC_HEADER: *dev_ptr = w + L.hdr; *count = 2; break;
     default: return fail(CLOD_E_ARG, "unknown section %d", section);
   }
   return CLOD_OK;

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
   const float kTmin = 9.99999974737875163e-05f; // fl(1e-4)
   const uint64_t lt = lanemask_lt();
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-  uint32_t last = 0, term = 0xFFFFFFFFu;
+  uint32_t last = 0, term = 0xFFFFFFFFu, nexp = 0, nblend = 0;
   bool done = !inside;
   for (uint32_t start = rg.x; start < rg.y; start += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
@@ -129,12 +129,14 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
       if (power > 0.0f) continue;
       // exp(power) < fl(1/255) for power < -5.6 and alpha'' <= 1: skipped either way.
       if (power < -5.6f) continue;
+      ++nexp;
       const float prod = c.y * cexp(power);
       const float al = fminf(0.99f, prod);
       if (al < kSkip) continue;
       const float Tn = T * (1.0f - al);
       const uint32_t pos = start - rg.x + (uint32_t)e;
       if (Tn < kTmin) { done = true; term = pos; break; }
+      ++nblend;
       const float w = al * T;
       cr = fmaf_(c.z, w, cr);
       cg = fmaf_(c.w, w, cg);
@@ -159,7 +161,13 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     const unsigned long long ev = !inside ? 0ull : (term != 0xFFFFFFFFu ? (unsigned long long)term + 1ull
                                                                          : (unsigned long long)(rg.y - rg.x));
     const unsigned long long e = wave_sum(ev);
-    if (lane == 0 && e) atomicAdd((unsigned long long*)pairs, e);
+    const unsigned long long x = wave_sum((unsigned long long)nexp);
+    const unsigned long long bl = wave_sum((unsigned long long)nblend);
+    if (lane == 0) {
+      if (e) atomicAdd((unsigned long long*)pairs, e);
+      if (x) atomicAdd((unsigned long long*)pairs + 1, x);
+      if (bl) atomicAdd((unsigned long long*)pairs + 2, bl);
+    }
   }
 }
 

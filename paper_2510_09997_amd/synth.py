@@ -3,8 +3,8 @@
 This module only draws inputs.  It holds none of the render method's arithmetic and is the
 one piece shared by the HIP path and the CPU oracle (both read the float32 arrays it makes).
 
-Every array is drawn in float64 with ``numpy.random.default_rng(seed)`` (PCG64) and cast
-to float32.  Scene draw order: means, log-scales, quaternions, opacity logits, SH
+Every array is drawn with ``numpy.random.default_rng(seed)`` (PCG64): the large SH planes
+directly in float32, everything else in float64 and cast to float32.  Scene draw order: means, log-scales, quaternions, opacity logits, SH
 coefficients, decay parameters.  Cameras and requests use ``default_rng(seed + 1000)``.
 
 Shapes follow the paper's scenes (Sec. 4.1 and the per-scene tables: 0.4M-8.6M Gaussians,
@@ -57,10 +57,10 @@ def make_scene(n: int, sh_degree: int, layout: str = "uniform", seed: int = 0,
     q /= np.maximum(np.linalg.norm(q, axis=0, keepdims=True), 1e-30)
     opacity = rng.normal(0.0, 1.0, size=n)
     K = (sh_degree + 1) ** 2
-    sh = np.empty((K, 3, n))
-    sh[0] = rng.normal(0.0, DC_STD, size=(3, n))
+    sh = np.empty((K, 3, n), dtype=np.float32)
+    sh[0] = rng.standard_normal(size=(3, n), dtype=np.float32) * np.float32(DC_STD)
     if K > 1:
-        sh[1:] = rng.normal(0.0, HIGHER_SH_STD, size=(K - 1, 3, n))
+        sh[1:] = rng.standard_normal(size=(K - 1, 3, n), dtype=np.float32) * np.float32(HIGHER_SH_STD)
     decay = rng.normal(0.0, decay_std, size=n)
     f = lambda a: np.ascontiguousarray(a, dtype=np.float32)
     return dict(n=n, sh_degree=sh_degree, mean=f(mean), log_scale=f(log_scale), quat=f(q),

@@ -22,10 +22,10 @@ def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None):
     b = Batch(sc["n"], views, params_struct(params), dup_capacity=dup_capacity)
     b.project(scene)
     D = b.bin_sort()
-    pairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pairs = torch.zeros(3, dtype=torch.int64, device="cuda")
     rgb, T, last = b.render_fwd(pairs)
     torch.cuda.synchronize()
-    out = dict(batch=b, scene=scene, D=D, counts=b.counts.cpu().numpy(), pairs=int(pairs.item()),
+    out = dict(batch=b, scene=scene, D=D, counts=b.counts.cpu().numpy(), pairs=pairs.cpu().numpy(),
                rgb_flat=rgb, T_flat=T, last_flat=last)
     out["rgb"] = [t.cpu().numpy() for t in b.split(rgb, 3)]
     out["T"] = [t.cpu().numpy() for t in b.split(T, 1)]

@@ -38,7 +38,7 @@ def test_config1_forward_bitexact():
     g = gpu_forward(sc, [v])
     compare_forward(g, sc, [v], fp64=True)
     r = O.render32(sc, v)
-    assert g["pairs"] == r["pairs"]
+    assert np.array_equal(g["pairs"], r["pair_classes"])
 
 
 def test_multiview_ragged_forward_bitexact():
@@ -199,11 +199,12 @@ def test_autograd_function_matches_direct_backward():
                                          leaves["decay"], leaves["sh"], b, sc["sh_degree"])
     gr = torch.linspace(-1, 1, rgb.numel(), device="cuda")
     (rgb * gr).sum().add_(0.5 * eta.sum()).backward()
-    got, want = _grad_case(sc, views, seed=0, dL_deta=None)
     direct = b.render_bwd(scene, T, last, gr, torch.full((1,), 0.5, device="cuda"))
+    # The adjoint sums with FP32 atomics, whose order differs from run to run.
     for k in leaves:
-        assert torch.allclose(leaves[k].grad, direct[k], rtol=0, atol=0), k
-    assert abs(float(eta[0]) - float(b.counts[0, 1]) / sc["n"]) < 1e-7
+        err = O.grad_rel_error(leaves[k].grad.cpu().numpy(), direct[k].cpu().numpy())
+        assert err <= 1e-5, (k, err)
+    assert abs(float(eta.detach()[0]) - float(b.counts[0, 1]) / sc["n"]) < 1e-7
 
 
 def test_loss_matches_closed_forms():
