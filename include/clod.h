@@ -136,7 +136,8 @@ clod_status clod_bin_sort(const clod_batch *batch, int64_t *n_dup_host, void *st
    transmittance T and last = 1 + position (within the tile's list) of the last blended entry
    (0 if none).  pairs_dev (nullable, device int64 [3]) is incremented by the work of the
    per-pixel loop: {pairs evaluated (entries visited up to and including the terminating one),
-   pairs whose exponential is evaluated (power in [-5.6, 0]), pairs blended}. */
+   exponentials evaluated (pairs that are not provably skipped before it), pairs blended}.
+   The first and last are properties of the contract; the middle one of this implementation. */
 clod_status clod_render_fwd(const clod_batch *batch, float *rgb, float *T, uint32_t *last,
                             int64_t *pairs_dev, void *stream);
 

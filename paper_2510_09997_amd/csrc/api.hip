@@ -105,12 +105,14 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.loss_acc = o; o = align256(o + (size_t)V * 4);
   L.kpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 8);
   L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 3 * 4);
+  L.gpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4);
   L.flags = o; o = align256(o + (size_t)L.VN);
   L.rec = o; o = align256(o + (size_t)L.VN * 3 * 16);
   L.rect = o; o = align256(o + (size_t)L.VN * 8);
   L.tiles = o; o = align256(o + (size_t)L.VN * 4);
   L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4);
   L.ranges = o; o = align256(o + (size_t)tiles_total * 8);
+  L.pair_part = o; o = align256(o + (size_t)tiles_total * 3 * 8);
   L.gscreen = o; o = align256(o + (size_t)L.VN * kGscreen * 4);
   L.total = o;
   return L;

@@ -24,20 +24,30 @@ __device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_
   return lo;
 }
 
+// Per-entry power cut.  An entry contributes to a pixel only if alpha'' E(power) >= fl(1/255).
+// E(p) <= 1 for p <= 0 and E never decreases by more than 2^-23 relative between neighbouring
+// inputs, so for power < cut = ln(1 / (255 alpha'')) - 0.01 the product is below
+// (1/255) e^-0.01 (1 + 3 2^-23) < 1/255: the contract skips the pair.  The 0.01 margin also
+// absorbs the error of logf.  cut > 0 means the entry is skipped at every pixel.
+__device__ __forceinline__ float entry_cut(float a2) {
+  return logf(0.0039215686274509803f / a2) - 0.01f;
+}
+
 // Conservative per-quadrant cull of a staged entry.  A pixel centre p farther than
-// 1.2 * rad + 0.5 from the 2D mean has exact quadratic form d^T Q d > 12.96 (rad >= 3
-// sqrt(lambda_max)), i.e. power < -6.48.  The binary32 evaluation of power errs by at most
-// 6u (A dx^2 + C dy^2) <= 12u * (AC / (AC - B^2)) * d^T Q d (u = 2^-24), and the conic's own
-// rounding adds a comparable term; with AC / (AC - B^2) <= 5e4 both stay below 8%, so the
-// evaluated power is below -5.6 and the contract skips the entry.  Culled entries are
-// therefore exactly the ones the pixel loop would have skipped.  Entries with a worse
-// conditioned conic are never culled.
+// sqrt(2.4 |cut|) rad / 3 + 0.5 from the 2D mean has exact quadratic form
+// d^T Q d > 2.4 |cut| (rad >= 3 sqrt(lambda_max)), i.e. exact power < -1.2 |cut|.  The binary32
+// power differs from the exact one by a factor common to the conic (the rounding of det,
+// <= 2u r) plus independent roundings amplified by at most r = AC / (AC - B^2); with
+// r <= 5e4 the total stays below 4%, so the evaluated power is below cut and the pair is
+// skipped.  Culled pairs are therefore exactly pairs the pixel loop would have skipped.
+// Entries with a worse conditioned conic are never culled spatially.
 __device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float A, float B, float C, float rad,
-                                                  float x0, float y0) {
+                                                  float cut, float x0, float y0) {
+  if (cut > 0.0f) return 0u;
   const float ac = A * C;
   const float det = ac - B * B;
   if (!(det > 2e-5f * ac) || !(rad < 1e6f)) return 0xFu;
-  const float rc = 1.2f * rad + 0.5f;
+  const float rc = __builtin_sqrtf(2.4f * -cut) * rad * (1.0f / 3.0f) + 0.5f;
   const float rc2 = rc * rc;
   uint32_t m = 0;
 #pragma unroll
@@ -50,21 +60,34 @@ __device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float A, flo
   return m;
 }
 
-// Forward blend.  Wave w of the workgroup covers the 8x8 quadrant (w & 1, w >> 1) of the
-// tile, lane l the pixel (l & 7, l >> 3) in it.  Each staged batch of 256 entries is
-// compacted per quadrant (ballot prefix sums keep the sorted order), so a wave walks only the
-// entries that can touch its quadrant.
+// The same test for one 8x8 pixel block with corner (x0, y0): 1 if the entry may touch it.
+__device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, float B, float C, float rad,
+                                                   float cut, float x0, float y0) {
+  if (cut > 0.0f) return 0u;
+  const float ac = A * C;
+  const float det = ac - B * B;
+  if (!(det > 2e-5f * ac) || !(rad < 1e6f)) return 1u;
+  const float rc = __builtin_sqrtf(2.4f * -cut) * rad * (1.0f / 3.0f) + 0.5f;
+  const float ddx = fmaxf(0.0f, fmaxf(x0 + 0.5f - u, u - (x0 + 7.5f)));
+  const float ddy = fmaxf(0.0f, fmaxf(y0 + 0.5f - v, v - (y0 + 7.5f)));
+  return ddx * ddx + ddy * ddy <= rc * rc ? 1u : 0u;
+}
+
+// Forward blend.  Each wave owns one 8x8 quadrant of a tile (lane l: pixel (l & 7, l >> 3))
+// and runs on its own: it stages 64 entries of the tile's sorted list at a time in its
+// private LDS slice (one entry per lane, a coalesced gather), keeps the ones that can touch
+// its quadrant as a ballot mask, and walks the mask in list order with the next entry's
+// LDS reads issued before the current entry's arithmetic.  A wave stops as soon as its 64
+// pixels are saturated, independently of the other quadrants; the only block barrier is the
+// final reduction of the optional pair counters.
 __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
     const float4* __restrict__ rec, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ svals, const unsigned long long* __restrict__ hdr,
     float bg0, float bg1, float bg2, float* __restrict__ rgb, float* __restrict__ Tout,
-    uint32_t* __restrict__ lastout, int64_t* __restrict__ pairs) {
-  __shared__ float4 s0[kBlock];   // u, v, hA, nB
-  __shared__ float4 s1[kBlock];   // hC, alpha'', r, g
-  __shared__ float s2[kBlock];    // b
-  __shared__ uint16_t list[4][kBlock];
-  __shared__ uint32_t wc[4][4];   // [quadrant][staging wave] counts
+    uint32_t* __restrict__ lastout, unsigned long long* __restrict__ pair_part) {
+  __shared__ float4 st[4][3][64];   // per wave: (u, v, hA, nB), (hC, alpha'', r, g), (b, cut, -, -)
+  __shared__ unsigned long long sp[4][3];
   const int tile_i = xcd_tile(blockIdx.x, gridDim.x);
   if (tile_i >= (int)tiles_total) return;
   if (hdr[kHdrOverflow]) return;
@@ -74,75 +97,79 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
   const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
   const int wave = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
-  const int px = tx * kTile + (wave & 1) * 8 + (int)(lane & 7);
-  const int py = ty * kTile + (wave >> 1) * 8 + (int)(lane >> 3);
+  const int qx0 = tx * kTile + (wave & 1) * 8, qy0 = ty * kTile + (wave >> 1) * 8;
+  const int px = qx0 + (int)(lane & 7);
+  const int py = qy0 + (int)(lane >> 3);
   const bool inside = px < Vw.width && py < Vw.height;
   const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
-  const float tx0 = (float)(tx * kTile), ty0 = (float)(ty * kTile);
+  const float fqx = (float)qx0, fqy = (float)qy0;
   const uint2 rg = ranges[tile_i];
   const float kSkip = 0.0039215688593685627f;   // fl(1/255)
   const float kTmin = 9.99999974737875163e-05f; // fl(1e-4)
-  const uint64_t lt = lanemask_lt();
+  float4* s0 = st[wave][0];
+  float4* s1 = st[wave][1];
+  float4* s2 = st[wave][2];
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
   uint32_t last = 0, term = 0xFFFFFFFFu, nexp = 0, nblend = 0;
   bool done = !inside;
-  for (uint32_t start = rg.x; start < rg.y; start += kBlock) {
-    if (__syncthreads_count(done) == kBlock) break;
-    const uint32_t j = start + threadIdx.x;
-    uint32_t qm = 0;
+  for (uint32_t base = rg.x; base < rg.y; base += 64) {
+    if (ballot64(!done) == 0ull) break;
+    const uint32_t j = base + lane;
+    bool rel = false;
     if (j < rg.y) {
       uint32_t f = svals[j];
       if ((int64_t)f >= VN) f = 0;   // defensive: the sort only emits indices < V*n
       const float4 g0 = rec[f];
       const float4 g1 = rec[VN + f];
       const float4 g2 = rec[2 * VN + f];
-      s0[threadIdx.x] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
-      s1[threadIdx.x] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
-      s2[threadIdx.x] = g2.z;
-      qm = quadrant_mask(g0.x, g0.y, g1.x, g1.y, g1.z, g1.w, tx0, ty0);
+      const float cut = entry_cut(g0.z);
+      s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
+      s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
+      s2[lane] = make_float4(g2.z, cut, 0.f, 0.f);
+      rel = (quadrant_mask1(g0.x, g0.y, g1.x, g1.y, g1.z, g1.w, cut, fqx, fqy)) != 0u;
     }
-    uint32_t pre[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t b = ballot64((qm >> q) & 1u);
-      pre[q] = (uint32_t)__popcll(b & lt);
-      if (lane == 0) wc[q][wave] = (uint32_t)__popcll(b);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if ((qm >> q) & 1u) {
-        uint32_t off = pre[q];
-        for (int w = 0; w < wave; ++w) off += wc[q][w];
-        list[q][off] = (uint16_t)threadIdx.x;
+    uint64_t mask = ballot64(rel);
+    // The staged entries are read by other lanes of this wave: wait for the LDS writes.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (mask == 0ull) continue;
+    int e = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    float4 a = s0[e], c = s1[e], bc = s2[e];
+    for (;;) {
+      const bool more = mask != 0ull;
+      const int en = more ? __builtin_ctzll(mask) : e;
+      mask &= mask - 1;
+      const float4 an = s0[en], cn = s1[en], bn = s2[en];
+      if (!done) {
+        const float dx = a.x - pcx, dy = a.y - pcy;
+        const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
+        // Below the entry's cut (or above 0) the contract skips the pair whatever E returns.
+        if (power <= 0.0f && power >= bc.y) {
+          ++nexp;
+          const float prod = c.y * cexp(power);
+          const float al = fminf(0.99f, prod);
+          if (al >= kSkip) {
+            const float Tn = T * (1.0f - al);
+            const uint32_t pos = base - rg.x + (uint32_t)e;
+            if (Tn < kTmin) {
+              done = true;
+              term = pos;
+            } else {
+              ++nblend;
+              const float w = al * T;
+              cr = fmaf_(c.z, w, cr);
+              cg = fmaf_(c.w, w, cg);
+              cb = fmaf_(bc.x, w, cb);
+              T = Tn;
+              last = pos + 1u;
+            }
+          }
+        }
       }
-    }
-    __syncthreads();
-    const int cnt = (int)(wc[wave][0] + wc[wave][1] + wc[wave][2] + wc[wave][3]);
-    for (int k = 0; k < cnt; ++k) {
-      if (done) break;
-      const int e = list[wave][k];
-      const float4 a = s0[e];
-      const float4 c = s1[e];
-      const float dx = a.x - pcx, dy = a.y - pcy;
-      const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
-      if (power > 0.0f) continue;
-      // exp(power) < fl(1/255) for power < -5.6 and alpha'' <= 1: skipped either way.
-      if (power < -5.6f) continue;
-      ++nexp;
-      const float prod = c.y * cexp(power);
-      const float al = fminf(0.99f, prod);
-      if (al < kSkip) continue;
-      const float Tn = T * (1.0f - al);
-      const uint32_t pos = start - rg.x + (uint32_t)e;
-      if (Tn < kTmin) { done = true; term = pos; break; }
-      ++nblend;
-      const float w = al * T;
-      cr = fmaf_(c.z, w, cr);
-      cg = fmaf_(c.w, w, cg);
-      cb = fmaf_(s2[e], w, cb);
-      T = Tn;
-      last = pos + 1u;
+      if (!more || ballot64(!done) == 0ull) break;
+      e = en; a = an; c = cn; bc = bn;
     }
   }
   if (inside) {
@@ -155,32 +182,54 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     Tout[P + p] = T;
     lastout[P + p] = last;
   }
-  if (pairs) {
+  if (pair_part) {
     // Pairs the contract's per-pixel loop evaluates: up to and including the terminating
-    // entry, else the whole list.
+    // entry, else the whole list.  One partial per tile (no same-address atomics).
     const unsigned long long ev = !inside ? 0ull : (term != 0xFFFFFFFFu ? (unsigned long long)term + 1ull
                                                                          : (unsigned long long)(rg.y - rg.x));
-    const unsigned long long e = wave_sum(ev);
+    const unsigned long long es = wave_sum(ev);
     const unsigned long long x = wave_sum((unsigned long long)nexp);
     const unsigned long long bl = wave_sum((unsigned long long)nblend);
-    if (lane == 0) {
-      if (e) atomicAdd((unsigned long long*)pairs, e);
-      if (x) atomicAdd((unsigned long long*)pairs + 1, x);
-      if (bl) atomicAdd((unsigned long long*)pairs + 2, bl);
-    }
+    if (lane == 0) { sp[wave][0] = es; sp[wave][1] = x; sp[wave][2] = bl; }
+    __syncthreads();
+    if (threadIdx.x < 3)
+      pair_part[3 * (int64_t)tile_i + threadIdx.x] =
+          sp[0][threadIdx.x] + sp[1][threadIdx.x] + sp[2][threadIdx.x] + sp[3][threadIdx.x];
   }
 }
 
-hipError_t launch_blend_fwd(const Layout& L, const void* ws, const uint32_t* sorted_vals,
+// Sums the per-tile pair partials into the caller's counters (one block, three atomics).
+__global__ __launch_bounds__(kBlock) void k_reduce_pairs(const unsigned long long* __restrict__ part,
+                                                         uint32_t tiles, unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long sm[4][3];
+  unsigned long long a = 0, b = 0, c = 0;
+  for (uint32_t t = threadIdx.x; t < tiles; t += kBlock) {
+    a += part[3 * (int64_t)t]; b += part[3 * (int64_t)t + 1]; c += part[3 * (int64_t)t + 2];
+  }
+  a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
+  if (lane_id() == 0) { sm[threadIdx.x >> 6][0] = a; sm[threadIdx.x >> 6][1] = b; sm[threadIdx.x >> 6][2] = c; }
+  __syncthreads();
+  if (threadIdx.x < 3) atomicAdd(out + threadIdx.x, sm[0][threadIdx.x] + sm[1][threadIdx.x] + sm[2][threadIdx.x] + sm[3][threadIdx.x]);
+}
+
+hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals,
                             clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
                             hipStream_t s) {
   if (L.tiles_total == 0) return hipSuccess;
-  const char* w = (const char*)ws;
+  char* w = (char*)ws;
   const int nb = (int)(((L.tiles_total + 7) / 8) * 8);
+  unsigned long long* part = pairs ? (unsigned long long*)(w + L.pair_part) : nullptr;
+  if (part) {
+    hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_blend_fwd, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
                      L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
                      sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
-                     prm.bg[2], rgb, T, last, pairs);
+                     prm.bg[2], rgb, T, last, part);
+  if (part)
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlock), 0, s, (const unsigned long long*)part, L.tiles_total,
+                       (unsigned long long*)pairs);
   return hipGetLastError();
 }
 
@@ -202,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     float* __restrict__ gscreen) {
   __shared__ float4 s0[kBlock];   // u, v, A, B
   __shared__ float4 s1[kBlock];   // C, alpha'', r, g
-  __shared__ float s2[kBlock];    // b
+  __shared__ float2 s2[kBlock];   // b, power cut
   __shared__ float acc[kGscreen][kBlock];
   __shared__ uint32_t sidx[kBlock];
   __shared__ uint16_t list[4][kBlock];
@@ -257,11 +306,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
       const float4 a0 = rec[f];
       const float4 a1 = rec[VN + f];
       const float4 a2 = rec[2 * VN + f];
+      const float cut = entry_cut(a0.z);
       s0[threadIdx.x] = make_float4(a0.x, a0.y, a1.x, a1.y);
       s1[threadIdx.x] = make_float4(a1.z, a0.z, a2.x, a2.y);
-      s2[threadIdx.x] = a2.z;
+      s2[threadIdx.x] = make_float2(a2.z, cut);
       sidx[threadIdx.x] = f;
-      qm = quadrant_mask(a0.x, a0.y, a1.x, a1.y, a1.z, a1.w, tx0, ty0);
+      qm = quadrant_mask(a0.x, a0.y, a1.x, a1.y, a1.z, a1.w, cut, tx0, ty0);
     }
 #pragma unroll
     for (int q = 0; q < kGscreen; ++q) acc[q][threadIdx.x] = 0.0f;
@@ -291,11 +341,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
       if (pos < last) {
         const float4 a = s0[k];
         const float4 c = s1[k];
-        const float cb_ = s2[k];
+        const float2 bc = s2[k];
+        const float cb_ = bc.x;
         const float dx = a.x - pcx, dy = a.y - pcy;
         const float hA = -0.5f * a.z, nB = -a.w, hC = -0.5f * c.x;
         const float power = fmaf_(hA * dx, dx, fmaf_(hC * dy, dy, (nB * dx) * dy));
-        if (power <= 0.0f && power >= -5.6f) {
+        if (power <= 0.0f && power >= bc.y) {
           const float G = cexp(power);
           const float prod = c.y * G;
           const float al = fminf(0.99f, prod);

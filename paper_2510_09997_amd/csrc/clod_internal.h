@@ -39,8 +39,8 @@ struct Layout {
   int64_t pixels_total = 0;
   int32_t scan_blocks = 0;
   // byte offsets into ws
-  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, flags, rec, rect, tiles,
-      scan_part, ranges, gscreen, total;
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, flags, rec, rect,
+      tiles, scan_part, ranges, pair_part, gscreen, total;
 };
 
 // Host-side per-view geometry (must agree with k_view_setup).
@@ -266,6 +266,15 @@ __device__ __forceinline__ float dmax_from_key(unsigned long long key) {
   return key == 0ull ? 1.0f : __uint_as_float((uint32_t)(key >> 32));
 }
 
+// Contiguous chunk [lo, hi) of n items owned by this block (grids capped at kMaxProjBlocks).
+__device__ __forceinline__ void block_chunk(int64_t n, int64_t& lo, int64_t& hi) {
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  lo = (int64_t)blockIdx.x * per;
+  hi = lo + per;
+  if (lo > n) lo = n;
+  if (hi > n) hi = n;
+}
+
 // Wave64 helpers.
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -303,7 +312,7 @@ hipError_t launch_radix_sort(const Layout& L, void* ws, const DupLayout& D, void
 hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
                          hipStream_t s);
 
-hipError_t launch_blend_fwd(const Layout& L, const void* ws, const uint32_t* sorted_vals,
+hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals,
                             clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
                             hipStream_t s);
 hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_vals, clod_params prm,

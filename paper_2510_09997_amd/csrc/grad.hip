@@ -41,18 +41,29 @@ __device__ __forceinline__ void sh_basis_grad(int deg, float X, float Y, float Z
   gX += SHK::k3a * (3.f * xx - 3.f * yy) * gY[15]; gYo += -6.f * SHK::k3a * X * Y * gY[15];
 }
 
+template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
     const unsigned long long* __restrict__ dmax_key, const uint8_t* __restrict__ flags,
     const float* __restrict__ gscreen, int64_t VN, const float* __restrict__ dL_deta,
-    float* __restrict__ gdmax, int accumulate, clod_scene_grad g) {
-  __shared__ float sred[4];
+    float* __restrict__ gpart /* [G][V] */, int accumulate, clod_scene_grad g) {
+  // Dynamic LDS: [3K][256] SH-gradient accumulators (one column per thread, so the 48
+  // accumulators of degree 3 do not occupy registers), then [V] per-block sums of the
+  // frustum-maximum partial.
+  extern __shared__ float lds[];
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  float* gshl = lds;
+  float* gsum = lds + 3 * K * kBlock;
   const int64_t n = sc.n;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = i < n;
-  const int deg = sc.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
   const float inv_n = 1.0f / (float)n;
+  for (int v = threadIdx.x; v < V; v += kBlock) gsum[v] = 0.f;
+  __syncthreads();
+  int64_t lo, hi;
+  block_chunk(n, lo, hi);
+  const int64_t iters = (hi - lo + kBlock - 1) / kBlock;
+  for (int64_t it = 0; it < iters; ++it) {
+  const int64_t i = lo + it * kBlock + threadIdx.x;
+  const bool valid = i < hi;
   float mx = 0.f, my = 0.f, mz = 0.f, op = 0.f, dc = 0.f;
   if (valid) {
     mx = sc.mean[i]; my = sc.mean[n + i]; mz = sc.mean[2 * n + i];
@@ -60,9 +71,8 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
   }
   float gmx = 0.f, gmy = 0.f, gmz = 0.f, gop = 0.f, gdc = 0.f;
   float gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
-  float gsh[48];
 #pragma unroll
-  for (int k = 0; k < 48; ++k) gsh[k] = 0.f;
+  for (int k = 0; k < 3 * K; ++k) gshl[k * kBlock + threadIdx.x] = 0.f;
   bool have_cov = false;
   float s[3], Rm[9], S[9], qn[4], rn = 0.f;
   for (int v = 0; v < V; ++v) {
@@ -95,19 +105,24 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
         const float id = 1.0f / d;
         const float X = ex * id, Y = ey * id, Z = ez * id;
         float Yb[16], gY[16];
-        sh_basis(deg, X, Y, Z, Yb);
-        for (int k = 0; k < K; ++k) gY[k] = 0.f;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          if (fl & (8 << ch)) continue;
-          const float gc = gcol[ch];
-          for (int k = 0; k < K; ++k) {
-            gsh[3 * k + ch] += gc * Yb[k];
-            gY[k] += gc * sc.sh[((int64_t)k * 3 + ch) * n + i];
-          }
+        sh_basis(DEG, X, Y, Z, Yb);
+        const float gc0 = (fl & 8) ? 0.f : gcol[0];
+        const float gc1 = (fl & 16) ? 0.f : gcol[1];
+        const float gc2 = (fl & 32) ? 0.f : gcol[2];
+        // One coefficient triple at a time keeps few values live.
+#pragma unroll 4
+        for (int k = 0; k < K; ++k) {
+          const float yk = Yb[k];
+          const float c0 = sc.sh[((int64_t)k * 3 + 0) * n + i];
+          const float c1 = sc.sh[((int64_t)k * 3 + 1) * n + i];
+          const float c2 = sc.sh[((int64_t)k * 3 + 2) * n + i];
+          gshl[(3 * k + 0) * kBlock + threadIdx.x] += gc0 * yk;
+          gshl[(3 * k + 1) * kBlock + threadIdx.x] += gc1 * yk;
+          gshl[(3 * k + 2) * kBlock + threadIdx.x] += gc2 * yk;
+          gY[k] = gc0 * c0 + gc1 * c1 + gc2 * c2;
         }
         float gX, gYd, gZ;
-        sh_basis_grad(deg, X, Y, Z, gY, gX, gYd, gZ);
+        sh_basis_grad(DEG, X, Y, Z, gY, gX, gYd, gZ);
         const float dot = X * gX + Y * gYd + Z * gZ;
         gex += (gX - X * dot) * id;
         gey += (gYd - Y * dot) * id;
@@ -213,32 +228,46 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
       gmy += Vw.W[1] * gx + Vw.W[4] * gy + Vw.W[7] * gz + gey;
       gmz += Vw.W[2] * gx + Vw.W[5] * gy + Vw.W[8] * gz + gez;
     }
-    // Per-view sum of the frustum-maximum partial.
+    // Per-view, per-block sum of the frustum-maximum partial (LDS, one add per wave).
     gdm = wave_sum(gdm);
-    if (lane_id() == 0) sred[threadIdx.x >> 6] = gdm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const float t = sred[0] + sred[1] + sred[2] + sred[3];
-      if (t != 0.0f && dmax_key[v] != 0ull) atomicAdd(gdmax + v, t);
-    }
-    __syncthreads();
+    if (lane_id() == 0 && gdm != 0.f) atomicAdd(&gsum[v], gdm);
   }
-  if (!valid) return;
-  auto put = [&](float* p, int64_t idx, float val) { p[idx] = accumulate ? p[idx] + val : val; };
-  put(g.mean, i, gmx); put(g.mean, n + i, gmy); put(g.mean, 2 * n + i, gmz);
-  for (int l = 0; l < 3; ++l) put(g.log_scale, l * n + i, gls[l]);
-  for (int l = 0; l < 4; ++l) put(g.quat, l * n + i, gq[l]);
-  put(g.opacity, i, gop);
-  put(g.decay, i, gdc);
-  for (int k = 0; k < K; ++k)
-    for (int ch = 0; ch < 3; ++ch) put(g.sh, ((int64_t)k * 3 + ch) * n + i, gsh[3 * k + ch]);
+  if (valid) {
+    auto put = [&](float* p, int64_t idx, float val) { p[idx] = accumulate ? p[idx] + val : val; };
+    put(g.mean, i, gmx); put(g.mean, n + i, gmy); put(g.mean, 2 * n + i, gmz);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) put(g.log_scale, l * n + i, gls[l]);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) put(g.quat, l * n + i, gq[l]);
+    put(g.opacity, i, gop);
+    put(g.decay, i, gdc);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) put(g.sh, ((int64_t)k * 3 + ch) * n + i, gshl[(3 * k + ch) * kBlock + threadIdx.x]);
+  }
+  }
+  __syncthreads();
+  for (int v = threadIdx.x; v < V; v += kBlock) gpart[(int64_t)blockIdx.x * V + v] = gsum[v];
 }
 
 // Frustum-maximum path: d_max = d_k for the argmax k, so dL/dmu_k += dL/ddmax (mu_k - c) / d_k.
-__global__ void k_dmax_fix(clod_scene sc, const DevView* __restrict__ views, int V,
+// One block: sums the per-block partials of each view, then thread 0 applies them.
+__global__ __launch_bounds__(kBlock) void k_dmax_fix(clod_scene sc, const DevView* __restrict__ views, int V,
                            const unsigned long long* __restrict__ dmax_key,
-                           const float* __restrict__ gdmax, clod_scene_grad g) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+                           const float* __restrict__ gpart, int G, float* __restrict__ gdmax,
+                           clod_scene_grad g) {
+  __shared__ float sred[4];
+  for (int v = 0; v < V; ++v) {
+    float t = 0.f;
+    for (int b = threadIdx.x; b < G; b += kBlock) t += gpart[(int64_t)b * V + v];
+    t = wave_sum(t);
+    if (lane_id() == 0) sred[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) gdmax[v] = sred[0] + sred[1] + sred[2] + sred[3];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
   const int64_t n = sc.n;
   for (int v = 0; v < V; ++v) {
     const unsigned long long key = dmax_key[v];
@@ -261,14 +290,23 @@ hipError_t launch_gauss_bwd(const clod_scene& sc, const Layout& L, void* ws, clo
   if (sc.n == 0) return hipSuccess;
   char* w = (char*)ws;
   float* gdmax = (float*)(w + L.gdmax);
-  hipError_t e = launch_fill_u32((uint32_t*)gdmax, 0u, L.V, s);
-  if (e != hipSuccess) return e;
-  const int grid = (int)((sc.n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_gauss_bwd, dim3(grid), dim3(kBlock), 0, s, sc, (const DevView*)(w + L.vinfo), L.V,
+  float* gpart = (float*)(w + L.gpart);
+  // One partial per block and view: the grid is capped and each block walks a chunk.
+  const int grid = proj_blocks(sc.n);
+  const int K = (sc.sh_degree + 1) * (sc.sh_degree + 1);
+  const size_t lds = ((size_t)3 * K * kBlock + (size_t)L.V) * sizeof(float);
+  auto kern = k_gauss_bwd<3>;
+  switch (sc.sh_degree) {
+    case 0: kern = k_gauss_bwd<0>; break;
+    case 1: kern = k_gauss_bwd<1>; break;
+    case 2: kern = k_gauss_bwd<2>; break;
+    default: kern = k_gauss_bwd<3>; break;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, sc, (const DevView*)(w + L.vinfo), L.V,
                      prm, (const unsigned long long*)(w + L.dmax_key), (const uint8_t*)(w + L.flags),
-                     (const float*)(w + L.gscreen), L.VN, dL_deta, gdmax, accumulate, g);
-  hipLaunchKernelGGL(k_dmax_fix, dim3(1), dim3(64), 0, s, sc, (const DevView*)(w + L.vinfo), L.V,
-                     (const unsigned long long*)(w + L.dmax_key), (const float*)gdmax, g);
+                     (const float*)(w + L.gscreen), L.VN, dL_deta, gpart, accumulate, g);
+  hipLaunchKernelGGL(k_dmax_fix, dim3(1), dim3(kBlock), 0, s, sc, (const DevView*)(w + L.vinfo), L.V,
+                     (const unsigned long long*)(w + L.dmax_key), (const float*)gpart, grid, gdmax, g);
   return hipGetLastError();
 }
 

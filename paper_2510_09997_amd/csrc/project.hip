@@ -49,13 +49,6 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
 // [b*C, (b+1)*C) of Gaussians and writes one partial per view (the frustum-max key, the three
 // counts); k_reduce_partials folds them per view.  Same-address atomics from every wave
 // serialise in L2 and would dominate these otherwise bandwidth-bound kernels.
-__device__ __forceinline__ void block_chunk(int64_t n, int64_t& lo, int64_t& hi) {
-  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-  lo = (int64_t)blockIdx.x * per;
-  hi = lo + per;
-  if (lo > n) lo = n;
-  if (hi > n) hi = n;
-}
 
 // Frustum maximum of d per view: key = bits(d) << 32 | (2^32 - 1 - i), so the 64-bit
 // maximum is the largest distance and, among equal distances, the lowest index.
