@@ -112,6 +112,7 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.tiles = o; o = align256(o + (size_t)L.VN * 4);
   L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4);
   L.ranges = o; o = align256(o + (size_t)tiles_total * 8);
+  L.order = o; o = align256(o + (size_t)tiles_total * 4);
   L.pair_part = o; o = align256(o + (size_t)tiles_total * 3 * 8);
   L.gscreen = o; o = align256(o + (size_t)L.VN * kGscreen * 4);
   L.total = o;

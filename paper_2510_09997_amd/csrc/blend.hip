@@ -1,19 +1,14 @@
 // Per-tile front-to-back blending (Sec. 3.1, Eq. (1)) and its adjoint.
 //
-// One 256-thread workgroup (4 wave64) per 16x16 tile, one pixel per thread.  The tile's
-// sorted list is walked in batches of 256 entries that the workgroup stages in LDS (one
-// entry per thread, coalesced gather of the records); every thread then reads the batch as
-// LDS broadcasts.  The workgroup stops as soon as all its pixels are saturated
-// (__syncthreads_count).  Blocks are mapped to tiles XCD-aware: the 8 XCDs take contiguous
-// tile ranges, so neighbouring tiles (which share Gaussians) hit the same L2.
+// One 256-thread workgroup (4 wave64) per 16x16 tile; wave w owns the 8x8 quadrant
+// (w & 1, w >> 1) and lane l its pixel (l & 7, l >> 3).  Entries of the tile's sorted list
+// are staged in LDS (one per lane or thread, a coalesced gather of the records) and read back
+// as LDS broadcasts; entries that provably cannot reach a quadrant are dropped for it (see
+// quadrant_mask).  Blocks take tiles longest list first (the order clod_bin_sort computes),
+// so the long tiles, not stragglers, start the launch.
 #include "clod_internal.h"
 
 namespace clod {
-
-__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
-  const int per = (nblocks + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
-}
 
 __device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_t tile) {
   int lo = 0, hi = V - 1;
@@ -85,11 +80,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     const float4* __restrict__ rec, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ svals, const unsigned long long* __restrict__ hdr,
     float bg0, float bg1, float bg2, float* __restrict__ rgb, float* __restrict__ Tout,
-    uint32_t* __restrict__ lastout, unsigned long long* __restrict__ pair_part) {
+    uint32_t* __restrict__ lastout, unsigned long long* __restrict__ pair_part,
+    const uint32_t* __restrict__ order) {
   __shared__ float4 st[4][3][64];   // per wave: (u, v, hA, nB), (hC, alpha'', r, g), (b, cut, -, -)
   __shared__ unsigned long long sp[4][3];
-  const int tile_i = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile_i >= (int)tiles_total) return;
+  if (blockIdx.x >= tiles_total) return;
+  const int tile_i = (int)order[blockIdx.x];
   if (hdr[kHdrOverflow]) return;
   const int v = view_of_tile(views, V, (uint32_t)tile_i);
   const DevView& Vw = views[v];
@@ -217,7 +213,7 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
                             hipStream_t s) {
   if (L.tiles_total == 0) return hipSuccess;
   char* w = (char*)ws;
-  const int nb = (int)(((L.tiles_total + 7) / 8) * 8);
+  const int nb = (int)L.tiles_total;
   unsigned long long* part = pairs ? (unsigned long long*)(w + L.pair_part) : nullptr;
   if (part) {
     hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, s);
@@ -226,7 +222,7 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
   hipLaunchKernelGGL(k_blend_fwd, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
                      L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
                      sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
-                     prm.bg[2], rgb, T, last, part);
+                     prm.bg[2], rgb, T, last, part, (const uint32_t*)(w + L.order));
   if (part)
     hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlock), 0, s, (const unsigned long long*)part, L.tiles_total,
                        (unsigned long long*)pairs);
@@ -248,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     const uint32_t* __restrict__ svals, const unsigned long long* __restrict__ hdr,
     float bg0, float bg1, float bg2, const float* __restrict__ Tin,
     const uint32_t* __restrict__ lastin, const float* __restrict__ dL_drgb,
-    float* __restrict__ gscreen) {
+    float* __restrict__ gscreen, const uint32_t* __restrict__ order) {
   __shared__ float4 s0[kBlock];   // u, v, A, B
   __shared__ float4 s1[kBlock];   // C, alpha'', r, g
   __shared__ float2 s2[kBlock];   // b, power cut
@@ -257,8 +253,9 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   __shared__ uint16_t list[4][kBlock];
   __shared__ uint32_t wc[4][4];
   __shared__ uint32_t smax[4];
-  const int tile_i = xcd_tile(blockIdx.x, gridDim.x);
-  if (tile_i >= (int)tiles_total) return;
+  if (blockIdx.x >= tiles_total) return;
+  const int tile_i = (int)order[blockIdx.x];
+  
   if (hdr[kHdrOverflow]) return;
   const int v = view_of_tile(views, V, (uint32_t)tile_i);
   const DevView& Vw = views[v];
@@ -404,11 +401,11 @@ hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_va
                             hipStream_t s) {
   if (L.tiles_total == 0) return hipSuccess;
   char* w = (char*)ws;
-  const int nb = (int)(((L.tiles_total + 7) / 8) * 8);
+  const int nb = (int)L.tiles_total;
   hipLaunchKernelGGL(k_blend_bwd, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
                      L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
                      sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
-                     prm.bg[2], T, last, dL_drgb, (float*)(w + L.gscreen));
+                     prm.bg[2], T, last, dL_drgb, (float*)(w + L.gscreen), (const uint32_t*)(w + L.order));
   return hipGetLastError();
 }
 

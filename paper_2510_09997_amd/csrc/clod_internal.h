@@ -40,7 +40,7 @@ struct Layout {
   int32_t scan_blocks = 0;
   // byte offsets into ws
   size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, flags, rec, rect,
-      tiles, scan_part, ranges, pair_part, gscreen, total;
+      tiles, scan_part, ranges, order, pair_part, gscreen, total;
 };
 
 // Host-side per-view geometry (must agree with k_view_setup).

@@ -325,6 +325,36 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const unsigned long long* __r
   }
 }
 
+// Longest-list-first order of the tiles (by bit length of the list, ties in any order):
+// the blend's running time is dominated by long lists, and starting them first keeps the
+// end of the launch from being a few long tiles on an otherwise idle chip.  One block.
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, uint32_t tiles,
+                                                     const unsigned long long* __restrict__ hdr,
+                                                     uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[33];
+  __shared__ uint32_t off[33];
+  if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const bool ovf = hdr[kHdrOverflow] != 0ull;
+  for (uint32_t t = threadIdx.x; t < tiles; t += blockDim.x) {
+    const uint2 r = ranges[t];
+    const uint32_t len = ovf ? 0u : r.y - r.x;
+    atomicAdd(&cnt[len ? 32 - __clz(len) : 0], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 32; b >= 0; --b) { off[b] = run; run += cnt[b]; }
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < tiles; t += blockDim.x) {
+    const uint2 r = ranges[t];
+    const uint32_t len = ovf ? 0u : r.y - r.x;
+    const uint32_t pos = atomicAdd(&off[len ? 32 - __clz(len) : 0], 1u);
+    order[pos] = t;
+  }
+}
+
 hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
                          hipStream_t s) {
   char* w = (char*)ws;
@@ -337,6 +367,9 @@ hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* du
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)g), dim3(kBlock), 0, s, keys,
                      (const unsigned long long*)(w + L.hdr), L.tiles_total, (uint2*)(w + L.ranges));
+  if (L.tiles_total > 0)
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, (const uint2*)(w + L.ranges), L.tiles_total,
+                       (const unsigned long long*)(w + L.hdr), (uint32_t*)(w + L.order));
   return hipGetLastError();
 }
 
