@@ -88,16 +88,19 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
   }
 }
 
-template <bool kWriteRecords>
+// Two phases per Gaussian and group of up to 32 views: (1) geometry for every view (frustum,
+// Eq. (2), mask, EWA, rectangle), remembering which views render the Gaussian; (2) only if
+// some view does, its SH coefficients are loaded once (all loads in flight together) and the
+// colour of each rendering view is evaluated.
+template <int DEG, bool kWriteRecords>
 __global__ __launch_bounds__(kBlock) void k_project(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
     const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
     uint8_t* __restrict__ flags_out, float4* __restrict__ rec, uint2* __restrict__ rect_out,
     uint32_t* __restrict__ tiles_out) {
   extern __shared__ uint32_t scnt[];   // [V][3]
+  constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t n = sc.n;
-  const int deg = sc.sh_degree;
-  const int K = (deg + 1) * (deg + 1);
   for (int j = threadIdx.x; j < 3 * V; j += kBlock) scnt[j] = 0;
   __syncthreads();
   int64_t lo, hi;
@@ -115,66 +118,91 @@ __global__ __launch_bounds__(kBlock) void k_project(
     // Rotation and 3D covariance are view independent: computed on first use.
     bool have_cov = false;
     float S[9];
-    for (int v = 0; v < V; ++v) {
-      const DevView& Vw = views[v];
-      const int64_t f = (int64_t)v * n + i;
-      bool F = false, M = false, R = false;
-      uint8_t fl = 0;
-      if (valid) {
-        float x, y, z, ex, ey, ez;
-        to_camera(Vw, mx, my, mz, x, y, z);
-        F = in_frustum(Vw, x, y, z, prm.near_z);
-        const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
-        const float dmax = dmax_from_key(dmax_key[v]);
-        float alpha, q;
-        const float a2 = attenuated(d, dmax, Vw.s_v, dc, op, prm.eps, alpha, q);
-        M = a2 > Vw.tau_sv;
-        fl = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
-        float4 g0 = make_float4(0.f, 0.f, a2, 0.f);
-        if (F && M) {
-          if (!have_cov) {
-            const float s0 = cexp(sc.log_scale[i]), s1 = cexp(sc.log_scale[n + i]), s2 = cexp(sc.log_scale[2 * n + i]);
-            float Rm[9], w_, x_, y_, z_, rn;
-            quat_rot(sc.quat[i], sc.quat[n + i], sc.quat[2 * n + i], sc.quat[3 * n + i], Rm, w_, x_, y_, z_, rn);
-            cov3(Rm, s0, s1, s2, S);
-            have_cov = true;
-          }
-          Proj P;
-          if (ewa(Vw, x, y, z, S, prm.dilation, P)) {
-            R = true;
-            if (kWriteRecords) {
-              const float id = 1.0f / d;
-              float Yb[16];
-              sh_basis(deg, ex * id, ey * id, ez * id, Yb);
-              float col[3];
-#pragma unroll
-              for (int ch = 0; ch < 3; ++ch) {
-                float acc = sc.sh[(int64_t)ch * n + i] * Yb[0];
-                for (int k = 1; k < K; ++k) acc = fmaf_(sc.sh[((int64_t)k * 3 + ch) * n + i], Yb[k], acc);
-                const float cv = acc + 0.5f;
-                if (!(cv > 0.0f)) fl |= (uint8_t)(8 << ch);
-                col[ch] = fmaxf(cv, 0.0f);
-              }
-              g0 = make_float4(P.u, P.v, a2, z);
-              rec[(int64_t)V * n + f] = make_float4(P.A, P.B, P.C, P.rad);
-              rec[2 * (int64_t)V * n + f] = make_float4(col[0], col[1], col[2], 0.f);
-              rect_out[f] = make_uint2((uint32_t)P.x0 | ((uint32_t)P.x1 << 16), (uint32_t)P.y0 | ((uint32_t)P.y1 << 16));
-              tiles_out[f] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+    for (int v0 = 0; v0 < V; v0 += 32) {
+      const int vn = V - v0 < 32 ? V - v0 : 32;
+      uint32_t rmask = 0, fm_bits0 = 0, fm_bits1 = 0;   // rendered views; F and M per view
+      for (int vv = 0; vv < vn; ++vv) {
+        const int v = v0 + vv;
+        const DevView& Vw = views[v];
+        const int64_t f = (int64_t)v * n + i;
+        bool F = false, M = false, R = false;
+        if (valid) {
+          float x, y, z, ex, ey, ez;
+          to_camera(Vw, mx, my, mz, x, y, z);
+          F = in_frustum(Vw, x, y, z, prm.near_z);
+          const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
+          const float dmax = dmax_from_key(dmax_key[v]);
+          float alpha, q;
+          const float a2 = attenuated(d, dmax, Vw.s_v, dc, op, prm.eps, alpha, q);
+          M = a2 > Vw.tau_sv;
+          float4 g0 = make_float4(0.f, 0.f, a2, 0.f);
+          if (F && M) {
+            if (!have_cov) {
+              const float s0 = cexp(sc.log_scale[i]), s1 = cexp(sc.log_scale[n + i]), s2 = cexp(sc.log_scale[2 * n + i]);
+              float Rm[9], w_, x_, y_, z_, rn;
+              quat_rot(sc.quat[i], sc.quat[n + i], sc.quat[2 * n + i], sc.quat[3 * n + i], Rm, w_, x_, y_, z_, rn);
+              cov3(Rm, s0, s1, s2, S);
+              have_cov = true;
             }
-            fl |= 4;
+            Proj P;
+            if (ewa(Vw, x, y, z, S, prm.dilation, P)) {
+              R = true;
+              if (kWriteRecords) {
+                g0 = make_float4(P.u, P.v, a2, z);
+                rec[(int64_t)V * n + f] = make_float4(P.A, P.B, P.C, P.rad);
+                rect_out[f] = make_uint2((uint32_t)P.x0 | ((uint32_t)P.x1 << 16), (uint32_t)P.y0 | ((uint32_t)P.y1 << 16));
+                tiles_out[f] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+              }
+            }
+          }
+          if (kWriteRecords) {
+            rec[f] = g0;
+            if (!R) {
+              tiles_out[f] = 0u;
+              flags_out[f] = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
+            }
           }
         }
-        if (kWriteRecords) {
-          rec[f] = g0;
-          if (!R) tiles_out[f] = 0u;
-          flags_out[f] = fl;
+        rmask |= (R ? 1u : 0u) << vv;
+        fm_bits0 |= (F ? 1u : 0u) << vv;
+        fm_bits1 |= (M ? 1u : 0u) << vv;
+        const uint64_t bF = ballot64(F), bM = ballot64(M), bR = ballot64(R);
+        if (lane_id() == 0) {
+          if (bF) atomicAdd(&scnt[3 * v + 0], (uint32_t)__popcll(bF));
+          if (bM) atomicAdd(&scnt[3 * v + 1], (uint32_t)__popcll(bM));
+          if (bR) atomicAdd(&scnt[3 * v + 2], (uint32_t)__popcll(bR));
         }
       }
-      const uint64_t bF = ballot64(F), bM = ballot64(M), bR = ballot64(R);
-      if (lane_id() == 0) {
-        if (bF) atomicAdd(&scnt[3 * v + 0], (uint32_t)__popcll(bF));
-        if (bM) atomicAdd(&scnt[3 * v + 1], (uint32_t)__popcll(bM));
-        if (bR) atomicAdd(&scnt[3 * v + 2], (uint32_t)__popcll(bR));
+      if (kWriteRecords && rmask) {
+        float shc[3 * K];
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) shc[k] = sc.sh[(int64_t)k * n + i];
+        uint32_t m = rmask;
+        while (m) {
+          const int vv = __builtin_ctz(m);
+          m &= m - 1;
+          const int v = v0 + vv;
+          const DevView& Vw = views[v];
+          const int64_t f = (int64_t)v * n + i;
+          float ex, ey, ez;
+          const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
+          const float id = 1.0f / d;
+          float Yb[16];
+          sh_basis(DEG, ex * id, ey * id, ez * id, Yb);
+          uint8_t fl = (uint8_t)(((fm_bits0 >> vv) & 1u) | (((fm_bits1 >> vv) & 1u) << 1) | 4u);
+          float col[3];
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            float acc = shc[ch] * Yb[0];
+#pragma unroll
+            for (int k = 1; k < K; ++k) acc = fmaf_(shc[3 * k + ch], Yb[k], acc);
+            const float cv = acc + 0.5f;
+            if (!(cv > 0.0f)) fl |= (uint8_t)(8 << ch);
+            col[ch] = fmaxf(cv, 0.0f);
+          }
+          rec[2 * (int64_t)V * n + f] = make_float4(col[0], col[1], col[2], 0.f);
+          flags_out[f] = fl;
+        }
       }
     }
   }
@@ -264,7 +292,14 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
                                uint8_t* flags, float4* rec, uint2* rect, uint32_t* tiles, hipStream_t s) {
   if (sc.n == 0) return launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
   const int G = proj_blocks(sc.n);
-  hipLaunchKernelGGL(k_project<kWrite>, dim3(G), dim3(kBlock), (size_t)(3 * V * sizeof(uint32_t)), s, sc, vinfo,
+  auto kern = k_project<3, kWrite>;
+  switch (sc.sh_degree) {
+    case 0: kern = k_project<0, kWrite>; break;
+    case 1: kern = k_project<1, kWrite>; break;
+    case 2: kern = k_project<2, kWrite>; break;
+    default: break;
+  }
+  hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), (size_t)(3 * V * sizeof(uint32_t)), s, sc, vinfo,
                      V, prm, dmax_key, cpart, flags, rec, rect, tiles);
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
                      (const uint32_t*)cpart, G, V, (unsigned long long*)nullptr, counts);

@@ -96,13 +96,20 @@ __global__ __launch_bounds__(kBlock) void k_scan_dup(
   uint32_t off = part[blockIdx.x] + block_exclusive_scan(s, sm, total);
   const bool overflow = hdr[kHdrOverflow] != 0ull;
   if (overflow) return;
+  // Keys of one (view, Gaussian) go to [off_k, off_k + cnt_k) in row-major tile order,
+  // whoever writes them.  Small rectangles are written by their own thread; rectangles of
+  // more than kCoop tiles are written by the whole wave, one rectangle at a time, so a few
+  // large on-screen Gaussians do not serialise their wave.
+  constexpr uint32_t kCoop = 16;
+  uint32_t bigmask = 0;
 #pragma unroll 1
   for (int k = 0; k < kScanItems; ++k) {
     const uint32_t cnt = loc[k];
-    if (cnt) {
+    if (cnt > kCoop) {
+      bigmask |= 1u << k;
+    } else if (cnt) {
       const int64_t f = base + (int64_t)threadIdx.x * kScanItems + k;
-      const int v = (int)(f / n);
-      const DevView& Vw = views[v];
+      const DevView& Vw = views[(int)(f / n)];
       const uint2 rc = rect[f];
       const int x0 = rc.x & 0xFFFF, x1 = rc.x >> 16, y0 = rc.y & 0xFFFF, y1 = rc.y >> 16;
       const unsigned long long dbits = (unsigned long long)__float_as_uint(rec0[f].w);
@@ -116,7 +123,37 @@ __global__ __launch_bounds__(kBlock) void k_scan_dup(
           }
           ++o;
         }
-      off += cnt;
+    }
+    loc[k] = off;          // from here on loc[k] holds the item's first output position
+    off += cnt;
+  }
+  // Cooperative pass over the wave's large rectangles.
+  const uint32_t lane = lane_id();
+  for (;;) {
+    const uint64_t who = ballot64(bigmask != 0u);
+    if (who == 0ull) break;
+    const int src = __builtin_ctzll(who);
+    const int kk = __shfl(bigmask != 0u ? __builtin_ctz(bigmask) : 0, src, 64);
+    if ((int)lane == src) bigmask &= bigmask - 1;
+    const int64_t f = base + (int64_t)((threadIdx.x & ~63u) + (uint32_t)src) * kScanItems + kk;
+    uint32_t o0 = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) o0 = (k == kk) ? loc[k] : o0;
+    o0 = __shfl(o0, src, 64);
+    const DevView& Vw = views[(int)(f / n)];
+    const uint2 rc = rect[f];
+    const int x0 = rc.x & 0xFFFF, x1 = rc.x >> 16, y0 = rc.y & 0xFFFF, y1 = rc.y >> 16;
+    const int wdt = x1 - x0;
+    const uint32_t cnt = (uint32_t)(wdt * (y1 - y0));
+    const unsigned long long dbits = (unsigned long long)__float_as_uint(rec0[f].w);
+    for (uint32_t q = lane; q < cnt; q += 64) {
+      const int ty = y0 + (int)(q / (uint32_t)wdt), tx = x0 + (int)(q % (uint32_t)wdt);
+      const uint32_t tile = Vw.tile_base + (uint32_t)(ty * Vw.tiles_x + tx);
+      const uint32_t o = o0 + q;
+      if ((int64_t)o < cap) {
+        keys[o] = ((unsigned long long)tile << 32) | dbits;
+        vals[o] = (uint32_t)f;
+      }
     }
   }
 }
