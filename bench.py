@@ -214,6 +214,96 @@ def run_train(args, torch, C, Batch, Scene, synth):
                 bwd_ms=bwd_ms, max_dup=dmax)
 
 
+def run_multiview_train(args, torch, C, Scene, synth):
+    """16 views per step (resolutions among 640x480, 1297x840, 1920x1080, fixed per view slot;
+    poses radius U(4, 6), s_v log-uniform [1, 8] redrawn every step), 2M Gaussians, forward +
+    loss + backward captured once in a graph and replayed."""
+    from paper_2510_09997_amd.train import MultiViewTrainer
+    n = 2_000_000
+    sc = synth.make_scene(n, 3, "mixture", seed=0)
+    scene = Scene(sc)
+    del sc
+    res = ((640, 480), (1297, 840), (1920, 1080))
+    K, W = args.train_steps, 2
+    first = synth.random_views(7, 16, radius=(4.0, 6.0), resolutions=res, sv_range=(1.0, 8.0))
+    slots = [(v.width, v.height) for v in first]
+    sets = [first]
+    for j in range(1, K + W):
+        vs = synth.random_views(7 + 31 * j, 16, radius=(4.0, 6.0), resolutions=((640, 480),), sv_range=(1.0, 8.0))
+        sets.append([synth.look_at(v.c, width=w, height=h, s_v=v.s_v) for v, (w, h) in zip(vs, slots)])
+    tr = MultiViewTrainer(scene, first, s_max=8.0, dup_capacity=1)
+    dmax = tr.size_capacity(sets)
+    tables = [C.views_to_device(C.make_views(vs), "cuda") for vs in sets]
+    tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0)))
+    tr.capture()
+    for j in range(W):
+        tr.set_views_dev(tables[j])
+        tr.step()
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    evs[0].record()
+    for k in range(K):
+        tr.set_views_dev(tables[W + k])
+        tr.step()
+        evs[k + 1].record()
+    torch.cuda.synchronize()
+    per = [evs[k].elapsed_time(evs[k + 1]) for k in range(K)]
+    assert not tr.overflowed(), "duplicate buffer overflow inside the timed region"
+    return dict(ms_per_step=float(np.mean(per)), p50_ms=float(np.percentile(per, 50)),
+                p99_ms=float(np.percentile(per, 99)), views=16, gaussians=n, max_dup=dmax,
+                pixels_per_step=tr.batch.pixels)
+
+
+def run_lod_sweep(args, torch, C, Batch, Scene, synth):
+    """6M Gaussians, 1920x1080, 64 camera distances log-spaced in [2, 200] along one ray
+    (looking at the origin from -z): kept-primitive counts of all 64 views in one launch, and
+    frames/s of the forward render at each distance; also the virtual sweep s_v = D_k / 2 at
+    the nearest pose."""
+    n = 6_000_000
+    sc = synth.make_scene(n, 3, "mixture", seed=0)
+    scene = Scene(sc)
+    del sc
+    ds = synth.sweep_distances(64, 2.0, 200.0)
+    ray = [synth.look_at((0.0, 0.0, -float(d)), width=1920, height=1080) for d in ds]
+    virt = [synth.look_at((0.0, 0.0, -2.0), width=1920, height=1080, s_v=float(d / 2.0)) for d in ds]
+    out = {"distances": [round(float(d), 3) for d in ds]}
+    for name, views in (("ray", ray), ("virtual", virt)):
+        b = Batch(n, views)
+        b.lod_count(scene)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cnt = b.lod_count(scene)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_counts_ms"] = round(e0.elapsed_time(e1), 4)
+        out[name + "_counts"] = cnt.cpu().numpy().tolist()
+        del b
+    # Frames per distance (one view per pass), capacity sized per pose.
+    fps = []
+    b = Batch(n, [ray[0]])
+    rgb = torch.empty(3 * b.pixels, device="cuda")
+    T = torch.empty(b.pixels, device="cuda")
+    last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
+    for k, v in enumerate(ray):
+        b.update_views([v])
+        b.project(scene)
+        b.bin_sort()
+        bs = b.c_struct()
+        reps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            C.clod_project(scene.c_struct(), bs, None)
+            C.clod_bin_sort(bs, sync_count=False)
+            C.clod_render_fwd(bs, rgb, T, last, None)
+        e1.record()
+        torch.cuda.synchronize()
+        fps.append(round(reps / (e0.elapsed_time(e1) / 1e3), 2))
+    out["ray_fps"] = fps
+    return out
+
+
 def run_serve_stream(args, torch, Scene, synth):
     """Poisson stream at 200 req/s over the 3M scene, mixed resolutions {720p, 1080p, 4K},
     s_v log-uniform in [1, 16]: continuous batching and the plain path, p50/p99 latency."""
@@ -268,6 +358,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-multiview", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-request comparison path")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a 1 GiB device copy (calibrates HBM byte counters)")
@@ -327,6 +419,16 @@ def main():
         out["fwd_bwd_p99_ms"] = round(train["p99_ms"], 3)
         out["train_config"] = {"gaussians": 1_000_000, "sh_degree": 3, "resolution": [1297, 840],
                                "s_v": "log-uniform [1, 8]", "loss": "L1 + point-count regulariser"}
+    if not args.no_multiview:
+        torch.cuda.empty_cache()
+        mv = run_multiview_train(args, torch, C, Scene, synth)
+        log(f"[bench] 16-view train step: {mv['ms_per_step']:.2f} ms")
+        out["multiview_train"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in mv.items()}
+    if not args.no_sweep:
+        torch.cuda.empty_cache()
+        sw = run_lod_sweep(args, torch, C, Batch, Scene, synth)
+        log(f"[bench] LoD sweep fps (k=0,21,42,63): {[sw['ray_fps'][k] for k in (0, 21, 42, 63)]}")
+        out["lod_sweep"] = sw
     if args.probe_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -395,11 +395,12 @@ def fp64_view_forward(sc: dict, view, vp: dict, params: dict | None = None,
         rows_rgb.append(cpix + Tfin[:, None] * bg[None, :])
         rows_T.append(Tfin)
         idx_pix.append(pix_flat)
-    allpix = torch.from_numpy(np.concatenate(idx_pix))
-    rgb_flat = torch.zeros(H * Wd, 3, dtype=torch.float64).index_copy(0, allpix, torch.cat(rows_rgb))
-    T_flat = torch.ones(H * Wd, dtype=torch.float64).index_copy(0, allpix, torch.cat(rows_T))
-    if tiles is None:
-        pass
+    rgb_flat = torch.zeros(H * Wd, 3, dtype=torch.float64)
+    T_flat = torch.ones(H * Wd, dtype=torch.float64)
+    if idx_pix:
+        allpix = torch.from_numpy(np.concatenate(idx_pix))
+        rgb_flat = rgb_flat.index_copy(0, allpix, torch.cat(rows_rgb))
+        T_flat = T_flat.index_copy(0, allpix, torch.cat(rows_T))
     rgb = rgb_flat.T.reshape(3, H, Wd)
     Tim = T_flat.reshape(H, Wd)
     return rgb, Tim, eta, alpha2
@@ -415,7 +416,8 @@ def fp64_grads(scene: dict, view, vp: dict, dL_drgb: np.ndarray, dL_deta: float,
     g = torch.from_numpy(np.asarray(dL_drgb, dtype=np.float64))
     L = (rgb * g).sum() + dL_deta * eta
     L.backward()
-    out = {k: sc[k].grad.detach().numpy().copy() for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")}
+    out = {k: (sc[k].grad.detach().numpy().copy() if sc[k].grad is not None else np.zeros(sc[k].shape))
+           for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")}
     out["rgb"] = rgb.detach().numpy()
     out["T"] = T.detach().numpy()
     return out
