@@ -91,7 +91,7 @@ def run_serving(args, torch, C, Batch, Scene, synth):
         C.clod_bin_sort(bs, sync_count=False)
         if ev is not None:
             ev[1].record()
-        C.clod_render_fwd(bs, rgb, T, last, pairs if ev is not None else None)
+        C.clod_render_fwd(bs, rgb, T, last, None)
         if ev is not None:
             ev[2].record()
 
@@ -115,9 +115,24 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     sort_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / K
     blend_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / K
     frames = len(SV_SWEEP) * K
+    # Work counters of the blend, from an untimed re-run of the timed steps (the timed
+    # launches carry no counters, so their duration is the blend kernel alone).
+    pairs_per_step = None
+    dups = []
+    if not args.no_count:
+        for k in range(K):
+            b.views_host, b.views_dev = tables.host[W + k], tables.dev[W + k]
+            bs = cs()
+            C.clod_project(scene.c_struct(), bs, b.counts)
+            C.clod_bin_sort(bs, sync_count=False)
+            C.clod_render_fwd(bs, rgb, T, last, pairs)
+            dups.append(C.clod_read_info(bs)["n_dup"])
+        torch.cuda.synchronize()
+        pairs_per_step = (pairs.cpu().numpy() / K).tolist()
     res = dict(total_ms=total_ms, ms_per_step=total_ms / K, fps=frames / (total_ms / 1e3),
                stage_ms=dict(project=proj_ms, bin_sort=sort_ms, blend_fwd=blend_ms),
-               pairs_per_step=(pairs.cpu().numpy() / K).tolist(), max_dup=dmax, blend_launches=K)
+               pairs_per_step=pairs_per_step, max_dup=dmax, blend_launches=K,
+               dup_per_step=float(np.mean(dups)) if dups else None, pixels_per_step=b.pixels)
     # Per-view kept counts of the last step (mask counts fall with s_v).
     res["counts_last_step"] = b.counts.cpu().numpy().tolist()
 
@@ -158,7 +173,7 @@ def run_train(args, torch, C, Batch, Scene, synth):
     sc = synth.make_scene(n, 3, "mixture", seed=0)
     scene = Scene(sc)
     del sc
-    K, W = args.train_steps, 2
+    K, W = args.train_steps, 5
     views = synth.random_views(0, K + W, radius=(4.0, 6.0), resolutions=((1297, 840),), sv_range=(1.0, 8.0))
     hosts = [C.make_views([v]) for v in views]
     devs = [C.views_to_device(h, "cuda") for h in hosts]
@@ -224,7 +239,7 @@ def run_multiview_train(args, torch, C, Scene, synth):
     scene = Scene(sc)
     del sc
     res = ((640, 480), (1297, 840), (1920, 1080))
-    K, W = args.train_steps, 2
+    K, W = args.train_steps, 5
     first = synth.random_views(7, 16, radius=(4.0, 6.0), resolutions=res, sv_range=(1.0, 8.0))
     slots = [(v.width, v.height) for v in first]
     sets = [first]
@@ -347,6 +362,10 @@ def cpu_baseline(steps, sv_index=(0, 2, 4)):
 # oracle's).  FP32 vector peak of MI355X: 256 CUs x 128 lanes x 2 flops x 2.4 GHz.
 FLOPS_PER_PAIR = 18
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE on the
+# default command (profiles/k_blend_fwd_serve1080p_3M_hbm.txt), each scaled by the reading of
+# the same counter for a 1 GiB device copy.  Set to None whenever the kernel changes.
+TRAFFIC = {"k_blend_fwd": 1515528767}
 
 
 def main():
@@ -354,17 +373,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--train-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-multiview", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-request comparison path")
+    ap.add_argument("--no-count", action="store_true", help="skip the untimed work-counting re-run")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -386,9 +406,14 @@ def main():
     # Roofline of the dominant kernel of the headline workload (the forward blend, one launch
     # per step, timed with events around its own launch on the stream it runs on).
     blend_ms = serve["stage_ms"]["blend_fwd"]
-    e, x, bl = serve["pairs_per_step"]
+    e, x, bl = serve["pairs_per_step"] or (float("nan"),) * 3
     flops = FLOPS_PER_PAIR * e
     achieved = flops / (blend_ms * 1e-3) / 1e12
+    # Bytes the blend must move per launch: 40 B per tile pair (record fields and sorted index),
+    # 8 B per tile range, 20 B per pixel of output (colour, T, last index).
+    alg_bytes = None
+    if serve["dup_per_step"] is not None:
+        alg_bytes = int(40 * serve["dup_per_step"] + 8 * 5 * 8160 + 20 * serve["pixels_per_step"])
     out = {
         "metric": "1080p frames/s at 3M Gaussians across LoD distances; fwd+bwd ms/iter; p99 ms",
         "value": round(serve["fps"], 2),
@@ -408,10 +433,14 @@ def main():
         "plain_path_fps": round(serve["plain_fps"], 2) if "plain_fps" in serve else None,
         "stage_ms": {k: round(v, 4) for k, v in serve["stage_ms"].items()},
         "pairs_per_step": {"evaluated": e, "exp_evaluated": x, "blended": bl},
-        "roofline": {"kernel": "k_blend_fwd", "bound": "alu", "achieved": round(achieved, 3),
+        "roofline": {"kernel": "k_blend_fwd", "bound": "alu",
+                     "achieved": None if math.isnan(achieved) else round(achieved, 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": None if math.isnan(achieved) else round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": TRAFFIC.get("k_blend_fwd"),
+                     "algorithmic_bytes": alg_bytes,
                      "avg_launch_ms": round(blend_ms, 4)},
+        "dup_per_step": serve["dup_per_step"],
     }
     if train is not None:
         out["fwd_bwd_ms_per_iter"] = round(train["ms_per_iter"], 3)

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class ClodError(RuntimeError):
@@ -67,7 +67,7 @@ EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
            "clod_inspect", "clod_last_error", "clod_abi_version"]
 
-(SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC0, SEC_REC1, SEC_REC2, SEC_FLAGS, SEC_DMAX, SEC_RECT, SEC_GSCREEN,
+(SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC, SEC_ALPHA, SEC_DEPTH, SEC_FLAGS, SEC_DMAX, SEC_RECT, SEC_GSCREEN,
  SEC_HEADER) = range(11)
 
 _lib = None

@@ -107,7 +107,9 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 3 * 4);
   L.gpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4);
   L.flags = o; o = align256(o + (size_t)L.VN);
-  L.rec = o; o = align256(o + (size_t)L.VN * 3 * 16);
+  L.alpha = o; o = align256(o + (size_t)L.VN * 4);
+  L.depth = o; o = align256(o + (size_t)L.VN * 4);
+  L.rec = o; o = align256(o + (size_t)L.VN * kRecBytes);
   L.rect = o; o = align256(o + (size_t)L.VN * 8);
   L.tiles = o; o = align256(o + (size_t)L.VN * 4);
   L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4);
@@ -252,7 +254,7 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
           "frustum max");
   HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
                          (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags),
-                         (float4*)(w + L.rec), (uint2*)(w + L.rect), (uint32_t*)(w + L.tiles), s),
+                         (float*)(w + L.alpha), (float*)(w + L.depth), (float4*)(w + L.rec), (uint2*)(w + L.rect), (uint32_t*)(w + L.tiles), s),
           "project");
   if (counts_dev)
     HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
@@ -415,9 +417,9 @@ clod_status clod_inspect(const clod_batch* batch, int32_t section, const void** 
   }
   switch (section) {
     case CLOD_SEC_RANGES: *dev_ptr = w + L.ranges; *count = L.tiles_total; break;
-    case CLOD_SEC_REC0: *dev_ptr = w + L.rec; *count = L.VN; break;
-    case CLOD_SEC_REC1: *dev_ptr = w + L.rec + (size_t)L.VN * 16; *count = L.VN; break;
-    case CLOD_SEC_REC2: *dev_ptr = w + L.rec + (size_t)L.VN * 32; *count = L.VN; break;
+    case CLOD_SEC_REC: *dev_ptr = w + L.rec; *count = L.VN; break;
+    case CLOD_SEC_ALPHA: *dev_ptr = w + L.alpha; *count = L.VN; break;
+    case CLOD_SEC_DEPTH: *dev_ptr = w + L.depth; *count = L.VN; break;
     case CLOD_SEC_FLAGS: *dev_ptr = w + L.flags; *count = L.VN; break;
     case CLOD_SEC_DMAX: *dev_ptr = w + L.dmax_key; *count = L.V; break;
     case CLOD_SEC_RECT: *dev_ptr = w + L.rect; *count = L.VN; break;

@@ -115,14 +115,14 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     if (j < rg.y) {
       uint32_t f = svals[j];
       if ((int64_t)f >= VN) f = 0;   // defensive: the sort only emits indices < V*n
-      const float4 g0 = rec[f];
-      const float4 g1 = rec[VN + f];
-      const float4 g2 = rec[2 * VN + f];
+      const float4 g0 = rec[kRecQuads * (int64_t)f];       // u, v, alpha'', radius
+      const float4 g1 = rec[kRecQuads * (int64_t)f + 1];   // conic A, B, C
+      const float4 g2 = rec[kRecQuads * (int64_t)f + 2];   // r, g, b
       const float cut = entry_cut(g0.z);
       s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
       s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
       s2[lane] = make_float4(g2.z, cut, 0.f, 0.f);
-      rel = (quadrant_mask1(g0.x, g0.y, g1.x, g1.y, g1.z, g1.w, cut, fqx, fqy)) != 0u;
+      rel = (quadrant_mask1(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, fqx, fqy)) != 0u;
     }
     uint64_t mask = ballot64(rel);
     // The staged entries are read by other lanes of this wave: wait for the LDS writes.
@@ -300,15 +300,15 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     if ((int)threadIdx.x < cnt) {
       uint32_t f = svals[lo + threadIdx.x];
       if ((int64_t)f >= VN) f = 0;   // defensive: the sort only emits indices < V*n
-      const float4 a0 = rec[f];
-      const float4 a1 = rec[VN + f];
-      const float4 a2 = rec[2 * VN + f];
+      const float4 a0 = rec[kRecQuads * (int64_t)f];
+      const float4 a1 = rec[kRecQuads * (int64_t)f + 1];
+      const float4 a2 = rec[kRecQuads * (int64_t)f + 2];
       const float cut = entry_cut(a0.z);
       s0[threadIdx.x] = make_float4(a0.x, a0.y, a1.x, a1.y);
       s1[threadIdx.x] = make_float4(a1.z, a0.z, a2.x, a2.y);
       s2[threadIdx.x] = make_float2(a2.z, cut);
       sidx[threadIdx.x] = f;
-      qm = quadrant_mask(a0.x, a0.y, a1.x, a1.y, a1.z, a1.w, cut, tx0, ty0);
+      qm = quadrant_mask(a0.x, a0.y, a1.x, a1.y, a1.z, a0.w, cut, tx0, ty0);
     }
 #pragma unroll
     for (int q = 0; q < kGscreen; ++q) acc[q][threadIdx.x] = 0.0f;

@@ -11,6 +11,10 @@ namespace clod {
 
 constexpr int kTile = 16;                  // 16x16-pixel tiles
 constexpr int kBlock = 256;                // threads per workgroup (4 wave64)
+// One 64-byte record per (view, Gaussian), so the blend's gather of an entry touches one
+// aligned 64-byte segment: (u, v, alpha'', radius), (conic A, B, C, 0), (r, g, b, 0), unused.
+constexpr int kRecQuads = 4;
+constexpr int kRecBytes = kRecQuads * 16;
 constexpr int kScanItems = 16;             // items per thread in the tiles-touched scan
 constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kSortItems = 8;              // keys per thread per radix tile
@@ -39,8 +43,8 @@ struct Layout {
   int64_t pixels_total = 0;
   int32_t scan_blocks = 0;
   // byte offsets into ws
-  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, flags, rec, rect,
-      tiles, scan_part, ranges, order, pair_part, gscreen, total;
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, flags, alpha, depth, rec,
+      rect, tiles, scan_part, ranges, order, pair_part, gscreen, total;
 };
 
 // Host-side per-view geometry (must agree with k_view_setup).
@@ -301,7 +305,8 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
                               unsigned long long* kpart, unsigned long long* dmax_key, hipStream_t s);
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                          uint8_t* flags, float4* rec, uint2* rect, uint32_t* tiles, hipStream_t s);
+                          uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
+                          uint32_t* tiles, hipStream_t s);
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             hipStream_t s);

@@ -96,7 +96,8 @@ template <int DEG, bool kWriteRecords>
 __global__ __launch_bounds__(kBlock) void k_project(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
     const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
-    uint8_t* __restrict__ flags_out, float4* __restrict__ rec, uint2* __restrict__ rect_out,
+    uint8_t* __restrict__ flags_out, float* __restrict__ alpha_out, float* __restrict__ depth_out,
+    float4* __restrict__ rec, uint2* __restrict__ rect_out,
     uint32_t* __restrict__ tiles_out) {
   extern __shared__ uint32_t scnt[];   // [V][3]
   constexpr int K = (DEG + 1) * (DEG + 1);
@@ -135,7 +136,6 @@ __global__ __launch_bounds__(kBlock) void k_project(
           float alpha, q;
           const float a2 = attenuated(d, dmax, Vw.s_v, dc, op, prm.eps, alpha, q);
           M = a2 > Vw.tau_sv;
-          float4 g0 = make_float4(0.f, 0.f, a2, 0.f);
           if (F && M) {
             if (!have_cov) {
               const float s0 = cexp(sc.log_scale[i]), s1 = cexp(sc.log_scale[n + i]), s2 = cexp(sc.log_scale[2 * n + i]);
@@ -148,15 +148,16 @@ __global__ __launch_bounds__(kBlock) void k_project(
             if (ewa(Vw, x, y, z, S, prm.dilation, P)) {
               R = true;
               if (kWriteRecords) {
-                g0 = make_float4(P.u, P.v, a2, z);
-                rec[(int64_t)V * n + f] = make_float4(P.A, P.B, P.C, P.rad);
+                rec[kRecQuads * f] = make_float4(P.u, P.v, a2, P.rad);
+                rec[kRecQuads * f + 1] = make_float4(P.A, P.B, P.C, 0.f);
+                depth_out[f] = z;
                 rect_out[f] = make_uint2((uint32_t)P.x0 | ((uint32_t)P.x1 << 16), (uint32_t)P.y0 | ((uint32_t)P.y1 << 16));
                 tiles_out[f] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
               }
             }
           }
           if (kWriteRecords) {
-            rec[f] = g0;
+            alpha_out[f] = a2;
             if (!R) {
               tiles_out[f] = 0u;
               flags_out[f] = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_project(
             if (!(cv > 0.0f)) fl |= (uint8_t)(8 << ch);
             col[ch] = fmaxf(cv, 0.0f);
           }
-          rec[2 * (int64_t)V * n + f] = make_float4(col[0], col[1], col[2], 0.f);
+          rec[kRecQuads * f + 2] = make_float4(col[0], col[1], col[2], 0.f);
           flags_out[f] = fl;
         }
       }
@@ -289,7 +290,8 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
 template <bool kWrite>
 static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                                const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                               uint8_t* flags, float4* rec, uint2* rect, uint32_t* tiles, hipStream_t s) {
+                               uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
+                               uint32_t* tiles, hipStream_t s) {
   if (sc.n == 0) return launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
   const int G = proj_blocks(sc.n);
   auto kern = k_project<3, kWrite>;
@@ -300,7 +302,7 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
     default: break;
   }
   hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), (size_t)(3 * V * sizeof(uint32_t)), s, sc, vinfo,
-                     V, prm, dmax_key, cpart, flags, rec, rect, tiles);
+                     V, prm, dmax_key, cpart, flags, alpha, depth, rec, rect, tiles);
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
                      (const uint32_t*)cpart, G, V, (unsigned long long*)nullptr, counts);
   return hipGetLastError();
@@ -308,14 +310,16 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
 
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                          uint8_t* flags, float4* rec, uint2* rect, uint32_t* tiles, hipStream_t s) {
-  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, flags, rec, rect, tiles, s);
+                          uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
+                          uint32_t* tiles, hipStream_t s) {
+  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, flags, alpha, depth, rec, rect, tiles, s);
 }
 
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             hipStream_t s) {
-  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, nullptr, s);
+  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, s);
 }
 
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s) {

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__
 // then every rendered (view, Gaussian) emits its keys in row-major tile order.
 __global__ __launch_bounds__(kBlock) void k_scan_dup(
     const uint32_t* __restrict__ tiles, int64_t count, const uint32_t* __restrict__ part,
-    const float4* __restrict__ rec0, const uint2* __restrict__ rect, const DevView* __restrict__ views,
+    const float* __restrict__ depth, const uint2* __restrict__ rect, const DevView* __restrict__ views,
     int64_t n, const unsigned long long* __restrict__ hdr, int64_t cap,
     unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ uint32_t sm[4];
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_dup(
       const DevView& Vw = views[(int)(f / n)];
       const uint2 rc = rect[f];
       const int x0 = rc.x & 0xFFFF, x1 = rc.x >> 16, y0 = rc.y & 0xFFFF, y1 = rc.y >> 16;
-      const unsigned long long dbits = (unsigned long long)__float_as_uint(rec0[f].w);
+      const unsigned long long dbits = (unsigned long long)__float_as_uint(depth[f]);
       uint32_t o = off;
       for (int ty = y0; ty < y1; ++ty)
         for (int tx = x0; tx < x1; ++tx) {
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_dup(
     const int x0 = rc.x & 0xFFFF, x1 = rc.x >> 16, y0 = rc.y & 0xFFFF, y1 = rc.y >> 16;
     const int wdt = x1 - x0;
     const uint32_t cnt = (uint32_t)(wdt * (y1 - y0));
-    const unsigned long long dbits = (unsigned long long)__float_as_uint(rec0[f].w);
+    const unsigned long long dbits = (unsigned long long)__float_as_uint(depth[f]);
     for (uint32_t q = lane; q < cnt; q += 64) {
       const int ty = y0 + (int)(q / (uint32_t)wdt), tx = x0 + (int)(q % (uint32_t)wdt);
       const uint32_t tile = Vw.tile_base + (uint32_t)(ty * Vw.tiles_x + tx);
@@ -169,7 +169,7 @@ hipError_t launch_scan_dup(const Layout& L, void* ws, const DupLayout& D, void* 
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, tiles, L.VN, part);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, part, nb, hdr, D.cap);
   hipLaunchKernelGGL(k_scan_dup, dim3(nb), dim3(kBlock), 0, s, tiles, L.VN, part,
-                     (const float4*)(w + L.rec), (const uint2*)(w + L.rect), (const DevView*)(w + L.vinfo),
+                     (const float*)(w + L.depth), (const uint2*)(w + L.rect), (const DevView*)(w + L.vinfo),
                      L.n, hdr, D.cap, (unsigned long long*)(dp + D.keys0), (uint32_t*)(dp + D.vals0));
   return hipGetLastError();
 }

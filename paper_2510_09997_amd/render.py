@@ -140,8 +140,8 @@ class Batch:
         ptr, n = C.clod_inspect(self.c_struct(), section)
         if count is not None:
             n = min(n, int(count))
-        elem = {C.SEC_KEYS: 8, C.SEC_VALUES: 4, C.SEC_RANGES: 8, C.SEC_REC0: 16, C.SEC_REC1: 16,
-                C.SEC_REC2: 16, C.SEC_FLAGS: 1, C.SEC_DMAX: 8, C.SEC_RECT: 8, C.SEC_GSCREEN: 36}[section]
+        elem = {C.SEC_KEYS: 8, C.SEC_VALUES: 4, C.SEC_RANGES: 8, C.SEC_REC: 64, C.SEC_ALPHA: 4,
+                C.SEC_DEPTH: 4, C.SEC_FLAGS: 1, C.SEC_DMAX: 8, C.SEC_RECT: 8, C.SEC_GSCREEN: 36}[section]
         base = self.dup if section in (C.SEC_KEYS, C.SEC_VALUES) else self.ws
         off = ptr - base.data_ptr()
         assert 0 <= off and off + n * elem <= base.numel()
@@ -151,10 +151,12 @@ class Batch:
             vn = n
             raw = base[off:off + 9 * vn * 4].clone()
             return raw.view(torch.float32).view(9, vn)
-        dt = {8: torch.int64, 4: torch.int32, 16: torch.float32, 1: torch.uint8}[elem]
+        dt = {8: torch.int64, 4: torch.int32, 64: torch.float32, 1: torch.uint8}[elem]
+        if section in (C.SEC_ALPHA, C.SEC_DEPTH):
+            dt = torch.float32
         t = raw.view(dt)
-        if section in (C.SEC_REC0, C.SEC_REC1, C.SEC_REC2):
-            t = t.view(n, 4)
+        if section == C.SEC_REC:
+            t = t.view(n, 4, 4)
         if section in (C.SEC_RANGES, C.SEC_RECT):
             t = raw.view(torch.int32).view(n, 2)
         return t

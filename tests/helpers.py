@@ -33,9 +33,9 @@ def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None):
     out["keys"] = b.section(C.SEC_KEYS, D).cpu().numpy().view(np.uint64)
     out["vals"] = b.section(C.SEC_VALUES, D).cpu().numpy().view(np.uint32)
     out["ranges"] = b.section(C.SEC_RANGES).cpu().numpy().view(np.uint32)
-    out["rec0"] = b.section(C.SEC_REC0).cpu().numpy()
-    out["rec1"] = b.section(C.SEC_REC1).cpu().numpy()
-    out["rec2"] = b.section(C.SEC_REC2).cpu().numpy()
+    out["rec"] = b.section(C.SEC_REC).cpu().numpy()
+    out["alpha"] = b.section(C.SEC_ALPHA).cpu().numpy()
+    out["depth"] = b.section(C.SEC_DEPTH).cpu().numpy()
     out["flags"] = b.section(C.SEC_FLAGS).cpu().numpy()
     out["dmax"] = b.section(C.SEC_DMAX).cpu().numpy().view(np.uint64)
     out["rect"] = b.section(C.SEC_RECT).cpu().numpy().view(np.uint32)
@@ -68,14 +68,14 @@ def compare_forward(g: dict, sc: dict, views, params: dict | None = None, fp64: 
         assert np.array_equal(fl, r["flags"]), v
         if check_records:
             rend = (r["flags"] & 4) > 0
-            rec0 = g["rec0"][v * n:(v + 1) * n]
-            rec1 = g["rec1"][v * n:(v + 1) * n]
-            rec2 = g["rec2"][v * n:(v + 1) * n]
+            rec = g["rec"][v * n:(v + 1) * n][rend]
+            depth = g["depth"][v * n:(v + 1) * n][rend]
             # alpha'' for every Gaussian, the rest for rendered ones.
-            assert np.array_equal(rec0[:, 2].view(np.uint32), r["rec"][:, 6].view(np.uint32)), v
+            alpha = g["alpha"][v * n:(v + 1) * n]
+            assert np.array_equal(alpha.view(np.uint32), r["rec"][:, 6].view(np.uint32)), v
             want = r["rec"][rend]
-            got = np.stack([rec0[rend, 0], rec0[rend, 1], rec0[rend, 3], rec1[rend, 0], rec1[rend, 1],
-                            rec1[rend, 2], rec0[rend, 2], rec2[rend, 0], rec2[rend, 1], rec2[rend, 2]], 1)
+            got = np.stack([rec[:, 0, 0], rec[:, 0, 1], depth, rec[:, 1, 0], rec[:, 1, 1],
+                            rec[:, 1, 2], rec[:, 0, 2], rec[:, 2, 0], rec[:, 2, 1], rec[:, 2, 2]], 1)
             assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), v
             rc = g["rect"][v * n:(v + 1) * n][rend]
             rect = np.stack([rc[:, 0] & 0xFFFF, rc[:, 0] >> 16, rc[:, 1] & 0xFFFF, rc[:, 1] >> 16], 1)

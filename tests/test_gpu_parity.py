@@ -94,7 +94,7 @@ def test_reduction_to_plain_3dgs_when_decay_vanishes():
     g = gpu_forward(sc, [v], p)
     compare_forward(g, sc, [v], p)
     alpha = 1.0 / (1.0 + np.exp(-sc["opacity"].astype(np.float64)))
-    a2 = g["rec0"][:, 2]
+    a2 = g["alpha"]
     assert np.allclose(a2, alpha, rtol=3e-7)
 
 
