@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   __shared__ float4 s0[kBlock];   // u, v, A, B
   __shared__ float4 s1[kBlock];   // C, alpha'', r, g
   __shared__ float2 s2[kBlock];   // b, power cut
-  __shared__ float acc[kGscreen][kBlock];
+  __shared__ float acc[kGscreen][kBlock + 1];   // padded: the 9 partials of one entry hit 9 banks
   __shared__ uint32_t sidx[kBlock];
   __shared__ uint16_t list[4][kBlock];
   __shared__ uint32_t wc[4][4];
@@ -373,13 +373,14 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
         }
       }
       if (ballot64(contrib) != 0ull) {
-        gu = wave_sum(gu); gv = wave_sum(gv); gA = wave_sum(gA); gB = wave_sum(gB);
-        gC = wave_sum(gC); ga2 = wave_sum(ga2); gr = wave_sum(gr); gg = wave_sum(gg);
-        gb = wave_sum(gb);
-        if (lane == 0) {
-          atomicAdd(&acc[0][k], gu); atomicAdd(&acc[1][k], gv); atomicAdd(&acc[2][k], gA);
-          atomicAdd(&acc[3][k], gB); atomicAdd(&acc[4][k], gC); atomicAdd(&acc[5][k], ga2);
-          atomicAdd(&acc[6][k], gr); atomicAdd(&acc[7][k], gg); atomicAdd(&acc[8][k], gb);
+        // Wave totals (uniform), then lane q adds partial q: one LDS atomic instruction.
+        const float s0_ = wave_sum_dpp(gu), s1_ = wave_sum_dpp(gv), s2_ = wave_sum_dpp(gA);
+        const float s3_ = wave_sum_dpp(gB), s4_ = wave_sum_dpp(gC), s5_ = wave_sum_dpp(ga2);
+        const float s6_ = wave_sum_dpp(gr), s7_ = wave_sum_dpp(gg), s8_ = wave_sum_dpp(gb);
+        if (lane < (uint32_t)kGscreen) {
+          const float val = lane == 0 ? s0_ : lane == 1 ? s1_ : lane == 2 ? s2_ : lane == 3 ? s3_ :
+                            lane == 4 ? s4_ : lane == 5 ? s5_ : lane == 6 ? s6_ : lane == 7 ? s7_ : s8_;
+          atomicAdd(&acc[lane][k], val);
         }
       }
     }

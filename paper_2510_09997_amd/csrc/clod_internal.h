@@ -294,6 +294,26 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_read(float x) {
+  // Lanes of rows outside kRowMask receive 0.
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, kRowMask, 0xF, false));
+}
+
+// Sum over the 64 lanes of a wave with DPP lane moves fused into the adds (no LDS traffic):
+// quad swaps give quad sums, the half-row and row mirrors give row (16-lane) sums, and the
+// two row broadcasts fold rows 0-2 into row 3.  Returns the total as a wave-uniform value.
+// Every lane of the wave must be active.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_read<0xB1, 0xF>(v);    // quad_perm (1, 0, 3, 2)
+  v += dpp_read<0x4E, 0xF>(v);    // quad_perm (2, 3, 0, 1)
+  v += dpp_read<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_read<0x140, 0xF>(v);   // row_mirror
+  v += dpp_read<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_read<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // ----------------------------------------------------------------------------------------
 // Launchers (each returns hipGetLastError()).
 // ----------------------------------------------------------------------------------------
