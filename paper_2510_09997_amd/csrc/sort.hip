@@ -68,92 +68,64 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__
   }
 }
 
-// Per block: exclusive offsets of its chunk (blocked: thread t owns items t*16 .. t*16+15),
-// then every rendered (view, Gaussian) emits its keys in row-major tile order.
+// Per block: exclusive offsets of its chunk of items (blocked: thread t owns items
+// t*16 .. t*16+15), kept in LDS; then the block's output positions are walked in order, 256 at
+// a time, so the key and value stores are coalesced whatever the rectangle sizes.  Output o
+// of the block belongs to the last item whose offset is <= o (binary search; items with no
+// tiles share their successor's offset and are never selected) and is that item's
+// (o - offset)-th covered tile in row-major order.
 __global__ __launch_bounds__(kBlock) void k_scan_dup(
     const uint32_t* __restrict__ tiles, int64_t count, const uint32_t* __restrict__ part,
     const float* __restrict__ depth, const uint2* __restrict__ rect, const DevView* __restrict__ views,
     int64_t n, const unsigned long long* __restrict__ hdr, int64_t cap,
     unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ uint32_t sm[4];
-  __shared__ uint32_t tbuf[kScanChunk];
+  __shared__ uint32_t loff[kScanChunk];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  // Coalesced load of the chunk into LDS, then blocked reads.
+  const int t = threadIdx.x;
+  // Coalesced load of the chunk's counts into LDS, then blocked reads.
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-    tbuf[k * kBlock + threadIdx.x] = j < count ? tiles[j] : 0u;
+    const int64_t j = base + (int64_t)k * kBlock + t;
+    loff[k * kBlock + t] = j < count ? tiles[j] : 0u;
   }
   __syncthreads();
   uint32_t loc[kScanItems];
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    loc[k] = tbuf[threadIdx.x * kScanItems + k];
+    loc[k] = loff[t * kScanItems + k];
     s += loc[k];
   }
   uint32_t total;
-  uint32_t off = part[blockIdx.x] + block_exclusive_scan(s, sm, total);
-  const bool overflow = hdr[kHdrOverflow] != 0ull;
-  if (overflow) return;
-  // Keys of one (view, Gaussian) go to [off_k, off_k + cnt_k) in row-major tile order,
-  // whoever writes them.  Small rectangles are written by their own thread; rectangles of
-  // more than kCoop tiles are written by the whole wave, one rectangle at a time, so a few
-  // large on-screen Gaussians do not serialise their wave.
-  constexpr uint32_t kCoop = 16;
-  uint32_t bigmask = 0;
-#pragma unroll 1
-  for (int k = 0; k < kScanItems; ++k) {
-    const uint32_t cnt = loc[k];
-    if (cnt > kCoop) {
-      bigmask |= 1u << k;
-    } else if (cnt) {
-      const int64_t f = base + (int64_t)threadIdx.x * kScanItems + k;
-      const DevView& Vw = views[(int)(f / n)];
-      const uint2 rc = rect[f];
-      const int x0 = rc.x & 0xFFFF, x1 = rc.x >> 16, y0 = rc.y & 0xFFFF, y1 = rc.y >> 16;
-      const unsigned long long dbits = (unsigned long long)__float_as_uint(depth[f]);
-      uint32_t o = off;
-      for (int ty = y0; ty < y1; ++ty)
-        for (int tx = x0; tx < x1; ++tx) {
-          const uint32_t tile = Vw.tile_base + (uint32_t)(ty * Vw.tiles_x + tx);
-          if ((int64_t)o < cap) {
-            keys[o] = ((unsigned long long)tile << 32) | dbits;
-            vals[o] = (uint32_t)f;
-          }
-          ++o;
-        }
-    }
-    loc[k] = off;          // from here on loc[k] holds the item's first output position
-    off += cnt;
-  }
-  // Cooperative pass over the wave's large rectangles.
-  const uint32_t lane = lane_id();
-  for (;;) {
-    const uint64_t who = ballot64(bigmask != 0u);
-    if (who == 0ull) break;
-    const int src = __builtin_ctzll(who);
-    const int kk = __shfl(bigmask != 0u ? __builtin_ctz(bigmask) : 0, src, 64);
-    if ((int)lane == src) bigmask &= bigmask - 1;
-    const int64_t f = base + (int64_t)((threadIdx.x & ~63u) + (uint32_t)src) * kScanItems + kk;
-    uint32_t o0 = 0;
+  uint32_t off = block_exclusive_scan(s, sm, total);   // its barriers also end the reads above
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) o0 = (k == kk) ? loc[k] : o0;
-    o0 = __shfl(o0, src, 64);
-    const DevView& Vw = views[(int)(f / n)];
+  for (int k = 0; k < kScanItems; ++k) {
+    loff[t * kScanItems + k] = off;
+    off += loc[k];
+  }
+  __syncthreads();
+  if (hdr[kHdrOverflow] != 0ull) return;
+  const int64_t out0 = (int64_t)part[blockIdx.x];
+  const uint32_t nn = (uint32_t)n;
+  for (uint32_t o = (uint32_t)t; o < total; o += kBlock) {
+    int lo = 0, hi = kScanChunk - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (loff[mid] <= o) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t rel = o - loff[lo];
+    const uint32_t f = (uint32_t)base + (uint32_t)lo;
+    const DevView& Vw = views[f / nn];
     const uint2 rc = rect[f];
-    const int x0 = rc.x & 0xFFFF, x1 = rc.x >> 16, y0 = rc.y & 0xFFFF, y1 = rc.y >> 16;
-    const int wdt = x1 - x0;
-    const uint32_t cnt = (uint32_t)(wdt * (y1 - y0));
-    const unsigned long long dbits = (unsigned long long)__float_as_uint(depth[f]);
-    for (uint32_t q = lane; q < cnt; q += 64) {
-      const int ty = y0 + (int)(q / (uint32_t)wdt), tx = x0 + (int)(q % (uint32_t)wdt);
-      const uint32_t tile = Vw.tile_base + (uint32_t)(ty * Vw.tiles_x + tx);
-      const uint32_t o = o0 + q;
-      if ((int64_t)o < cap) {
-        keys[o] = ((unsigned long long)tile << 32) | dbits;
-        vals[o] = (uint32_t)f;
-      }
+    const uint32_t x0 = rc.x & 0xFFFFu, x1 = rc.x >> 16, y0 = rc.y & 0xFFFFu;
+    const uint32_t w = x1 - x0;
+    const uint32_t ty = y0 + rel / w, tx = x0 + rel % w;
+    const uint32_t tile = Vw.tile_base + ty * (uint32_t)Vw.tiles_x + tx;
+    const int64_t og = out0 + (int64_t)o;
+    if (og < cap) {
+      keys[og] = ((unsigned long long)tile << 32) | (unsigned long long)__float_as_uint(depth[f]);
+      vals[og] = f;
     }
   }
 }
@@ -202,23 +174,30 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
 __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const unsigned long long* __restrict__ keys,
                                                           const unsigned long long* __restrict__ hdr,
                                                           int G, int shift, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t cnt[256];
+  __shared__ uint32_t cnt[4][256];   // per-wave digit counts
   if (hdr[kHdrOverflow]) return;
   const int64_t D = (int64_t)hdr[kHdrDup];
-  cnt[threadIdx.x] = 0;
+  const int t = threadIdx.x;
+  const int wave = t >> 6;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) cnt[w][t] = 0;
   __syncthreads();
   int64_t lo, hi;
   sort_chunk(D, G, blockIdx.x, lo, hi);
-  for (int64_t base = lo; base < hi; base += kBlock) {
-    const int64_t j = base + threadIdx.x;
-    const bool valid = j < hi;
-    const uint32_t d = valid ? (uint32_t)(keys[j] >> shift) & 255u : 0u;
-    const uint64_t active = ballot64(valid);
-    const uint64_t m = match_digit(d, active);
-    if (valid && (m & lanemask_lt()) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
+  // kSortItems keys per thread per step, all loads issued before any is used.
+  for (int64_t base = lo; base < hi; base += kSortTile) {
+    uint32_t d8[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const int64_t idx = base + (int64_t)j * kBlock + t;
+      d8[j] = idx < hi ? (uint32_t)(keys[idx] >> shift) & 255u : 256u;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j)
+      if (d8[j] < 256u) atomicAdd(&cnt[wave][d8[j]], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * G + blockIdx.x] = cnt[threadIdx.x];
+  hist[(int64_t)t * G + blockIdx.x] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
 }
 
 // Block d: exclusive scan of digit d's per-block counts hist[d*G .. d*G+G) in place, and
