@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 2
+#define CLOD_ABI_VERSION 3
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -120,10 +120,12 @@ int64_t clod_dup_capacity(size_t dup_bytes);
 clod_status clod_project(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
                          void *stream);
 
-/* Sec. 3.1 ("sorted by depth"): exclusive scan of tiles touched, one key per (rendered
-   Gaussian, covered tile) emitted in Gaussian-index order, key = (tile_base[view] + tile) << 32
-   | bits(depth), stable LSD radix sort of the keys, and per-tile [start, end) ranges of the
-   sorted list.  If more pairs exist than the duplicate buffer holds, nothing is written beyond
+/* Sec. 3.1 (splats sorted by depth per tile): the (rendered Gaussian, covered tile) pairs in
+   the stable order of the keys (tile_base[view] + tile) << 32 | bits(depth) emitted per
+   rendered Gaussian in index order and per covered tile in row-major order -- i.e. ordered by
+   (view, tile, depth, Gaussian index) -- and per-tile [start, end) ranges of the sorted list.
+   Built as a radix sort of the rendered records by depth followed by a stable radix sort of
+   the pairs, emitted in that depth order, by tile id.  If more pairs exist than the duplicate buffer holds, nothing is written beyond
    it, the overflow is recorded in ws and later calls on this batch are no-ops; with
    n_dup_host != NULL the call synchronises `stream`, stores the pair count D (also on
    overflow) and returns CLOD_E_CAPACITY on overflow (enlarge batch->dup and call again; the
@@ -177,7 +179,7 @@ clod_status clod_read_info(const clod_batch *batch, int64_t *info_host, void *st
 
 /* Read-only views of intermediate results (for inspection and tests).  Stores the device
    address of the section and its element count; nothing is launched or copied.
-     CLOD_SEC_KEYS     uint64 sorted (tile, depth) keys   (count = duplicate capacity; the
+     CLOD_SEC_KEYS     uint32 tile ids of the sorted pairs (count = duplicate capacity; the
                        first D are valid, D from clod_bin_sort or clod_read_info)
      CLOD_SEC_VALUES   uint32 sorted record indices v*n + i (count as above)
      CLOD_SEC_RANGES   uint32 pairs [start, end) per tile of the batch (count = tiles)

@@ -34,12 +34,9 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static bool finite_f(float x) { return isfinite(x) != 0; }
 
-int sort_passes(uint32_t tiles_total) {
-  int tb = 0;
-  uint32_t m = tiles_total > 0 ? tiles_total - 1 : 0;
-  while (m) { ++tb; m >>= 1; }
-  return (32 + tb + 7) / 8;
-}
+// Radix passes of clod_bin_sort: 4 over the depth keys of the rendered records, then the
+// tile-id passes over the pairs.
+static int sort_passes(uint32_t tiles_total) { return 4 + tile_passes(tiles_total); }
 
 int sort_blocks(int64_t cap) {
   int64_t g = (cap + kSortTile - 1) / kSortTile;
@@ -52,11 +49,12 @@ DupLayout dup_layout(int64_t cap) {
   DupLayout D;
   D.cap = cap;
   size_t o = 0;
-  D.keys0 = o; o = align256(o + (size_t)cap * 8);
+  D.keys0 = o; o = align256(o + (size_t)cap * 4);
   D.vals0 = o; o = align256(o + (size_t)cap * 4);
-  D.keys1 = o; o = align256(o + (size_t)cap * 8);
+  D.keys1 = o; o = align256(o + (size_t)cap * 4);
   D.vals1 = o; o = align256(o + (size_t)cap * 4);
   D.hist = o; o = align256(o + ((size_t)256 * sort_blocks(cap) + 256) * 4);
+  D.owner = o; o = align256(o + ((size_t)(cap + kEmitTile - 1) / kEmitTile + 1) * 4);
   D.total = o;
   return D;
 }
@@ -112,9 +110,10 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.rec = o; o = align256(o + (size_t)L.VN * kRecBytes);
   L.rect = o; o = align256(o + (size_t)L.VN * 8);
   L.tiles = o; o = align256(o + (size_t)L.VN * 4);
-  L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4);
+  L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4 * 3);   // pairs, records, emission
   L.ranges = o; o = align256(o + (size_t)tiles_total * 8);
   L.order = o; o = align256(o + (size_t)tiles_total * 4);
+  L.tord = o; o = align256(o + (size_t)kTileOrderWords * 4);
   L.pair_part = o; o = align256(o + (size_t)tiles_total * 3 * 8);
   L.gscreen = o; o = align256(o + (size_t)L.VN * kGscreen * 4);
   L.total = o;
@@ -225,8 +224,8 @@ size_t clod_dup_bytes(int64_t capacity) {
 }
 
 int64_t clod_dup_capacity(size_t dup_bytes) {
-  // Largest capacity whose layout fits; the layout grows by ~24 bytes per entry.
-  int64_t lo = 0, hi = (int64_t)(dup_bytes / 24) + 1;
+  // Largest capacity whose layout fits; the layout grows by 16 bytes per entry.
+  int64_t lo = 0, hi = (int64_t)(dup_bytes / 16) + 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi + 1) / 2;
     if (mid >= 0xFFFFFFFFll || dup_layout(mid).total > dup_bytes) hi = mid - 1; else lo = mid;
@@ -272,12 +271,8 @@ clod_status clod_bin_sort(const clod_batch* batch, int64_t* n_dup_host, void* st
   hipStream_t s = (hipStream_t)stream;
   const Layout& L = cx.L;
   char* w = (char*)batch->ws;
-  if (L.scan_blocks == 0)
-    HIP_TRY(launch_fill_u32((uint32_t*)(w + L.hdr), 0u, 4, s), "clear header");
-  else
-    HIP_TRY(launch_scan_dup(L, batch->ws, D, batch->dup, s), "scan/duplicate");
-  HIP_TRY(launch_radix_sort(L, batch->ws, D, batch->dup, s), "radix sort");
-  HIP_TRY(launch_ranges(L, batch->ws, D, batch->dup, sort_passes(L.tiles_total) & 1, s), "ranges");
+  HIP_TRY(launch_bin_sort(L, batch->ws, D, batch->dup, s), "binning sort");
+  HIP_TRY(launch_ranges(L, batch->ws, D, batch->dup, sorted_buffer(L.tiles_total), s), "ranges");
   if (n_dup_host) {
     unsigned long long h[2];
     HIP_TRY(hipMemcpyAsync(h, w + L.hdr, sizeof(h), hipMemcpyDeviceToHost, s), "read count");
@@ -290,7 +285,7 @@ clod_status clod_bin_sort(const clod_batch* batch, int64_t* n_dup_host, void* st
 }
 
 static const uint32_t* sorted_vals(const clod_batch* b, const Layout& L, const DupLayout& D) {
-  return (const uint32_t*)((const char*)b->dup + ((sort_passes(L.tiles_total) & 1) ? D.vals1 : D.vals0));
+  return (const uint32_t*)((const char*)b->dup + (sorted_buffer(L.tiles_total) ? D.vals1 : D.vals0));
 }
 
 clod_status clod_render_fwd(const clod_batch* batch, float* rgb, float* T, uint32_t* last,
@@ -409,7 +404,7 @@ clod_status clod_inspect(const clod_batch* batch, int32_t section, const void** 
     DupLayout D;
     st = dup_check(batch, D);
     if (st != CLOD_OK) return st;
-    const bool odd = (sort_passes(L.tiles_total) & 1) != 0;
+    const bool odd = sorted_buffer(L.tiles_total) != 0;
     const size_t off = section == CLOD_SEC_KEYS ? (odd ? D.keys1 : D.keys0) : (odd ? D.vals1 : D.vals0);
     *dev_ptr = (const char*)batch->dup + off;
     *count = D.cap;

@@ -17,6 +17,11 @@ constexpr int kRecQuads = 4;
 constexpr int kRecBytes = kRecQuads * 16;
 constexpr int kScanItems = 16;             // items per thread in the tiles-touched scan
 constexpr int kScanChunk = kBlock * kScanItems;
+// Tile ordering by list length: 33 bucket counts + 33 bucket cursors (u32).
+constexpr int kEmitTile = 2048;            // tile pairs per output chunk of the emission
+constexpr int kTileBuckets = 33;
+constexpr int kTileOrderWords = 2 * kTileBuckets;
+constexpr int kTileOrderChunk = 1024;       // tiles per block in the ordering kernels
 constexpr int kSortItems = 8;              // keys per thread per radix tile
 constexpr int kSortTile = kBlock * kSortItems;   // 2048 keys per radix tile
 constexpr int kMaxSortBlocks = 1024;
@@ -33,7 +38,7 @@ struct DevView {
 };
 
 // Workspace header words (uint64).
-enum : int { kHdrDup = 0, kHdrOverflow = 1, kHdrWords = 8 };
+enum : int { kHdrDup = 0, kHdrOverflow = 1, kHdrRend = 2, kHdrWords = 8 };
 
 struct Layout {
   int64_t n = 0;
@@ -44,7 +49,7 @@ struct Layout {
   int32_t scan_blocks = 0;
   // byte offsets into ws
   size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, flags, alpha, depth, rec,
-      rect, tiles, scan_part, ranges, order, pair_part, gscreen, total;
+      rect, tiles, scan_part, ranges, order, tord, pair_part, gscreen, total;
 };
 
 // Host-side per-view geometry (must agree with k_view_setup).
@@ -58,12 +63,13 @@ constexpr int kLossChunk = kBlock * kLossItems;
 
 struct DupLayout {
   int64_t cap = 0;
-  size_t keys0, vals0, keys1, vals1, hist, total;
+  size_t keys0, vals0, keys1, vals1, hist, owner, total;
 };
 
 DupLayout dup_layout(int64_t cap);
-int sort_passes(uint32_t tiles_total);
 int sort_blocks(int64_t cap);
+int tile_passes(uint32_t tiles_total);     // radix passes of the tile-id sort
+int sorted_buffer(uint32_t tiles_total);   // ping-pong buffer (0/1) holding the sorted pairs
 
 // ----------------------------------------------------------------------------------------
 // Binary32 contract arithmetic (device).  The translation units are compiled with
@@ -332,8 +338,7 @@ hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, c
                             hipStream_t s);
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s);
 
-hipError_t launch_scan_dup(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s);
-hipError_t launch_radix_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s);
+hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s);
 hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
                          hipStream_t s);
 

@@ -1,11 +1,20 @@
-// Tile binning (Sec. 3.1, "sorted by depth"): exclusive scan of tiles touched, emission of
-// one (tile, depth) key per covered tile, stable LSD radix sort, per-tile ranges.
+// Tile binning (Sec. 3.1, splats sorted by depth per tile).  The order produced is the
+// stable order of the keys (tile << 32 | bits(depth)) emitted per rendered (view, Gaussian)
+// in index order, i.e. (tile, depth, index); it is built in two sorts that move far fewer
+// bytes than one sort of the 64-bit pair keys:
 //
-// Everything is device-driven: the pair count D lives in the workspace header and the sort
-// kernels read it, so no host synchronisation is needed between the stages (and the whole
-// sequence can be captured in a graph).  Counting uses wave64 ballots: a lane's rank among
-// lanes with the same digit is popcount(match & lanemask_lt), where match is the AND of
-// eight ballots over the digit bits.
+//   1. compaction of the rendered records f = v*n + i in index order, keyed by bits(depth);
+//   2. stable LSD radix sort of these R records by their 32-bit depth key;
+//   3. emission, in that depth order, of one (tile id, f) pair per covered tile (a
+//      load-balanced expansion over equal output chunks: every store is coalesced);
+//   4. stable LSD radix sort of the D pairs by the tile id only.
+//
+// Step 4 is stable and its input is in (depth, index) order within every tile, so the result
+// is ordered by (tile, depth, index), exactly the order of the single 64-bit sort.  Rendered
+// records each cover at least one tile, so R <= D and the record sort runs inside the pair
+// buffers.  Everything is device-driven: R and D live in the workspace header and every kernel
+// reads them, so no host synchronisation is needed between the stages and the whole sequence
+// can be captured in a graph.
 #include "clod_internal.h"
 
 namespace clod {
@@ -31,133 +40,134 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
   return wbase + inc - v;
 }
 
-// --------------------------------------------------------------- tiles-touched scan + dup
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ tiles, int64_t count,
-                                                        uint32_t* __restrict__ part) {
-  __shared__ uint32_t sm[4];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+// Loads a chunk of kScanChunk uint32 counts (coalesced) into LDS and replaces them by their
+// block-exclusive offsets (blocked: thread t owns items t*16 .. t*16+15).  Returns the total.
+__device__ __forceinline__ uint32_t chunk_offsets(uint32_t* loff, uint32_t* sm, uint32_t (&loc)[kScanItems]) {
+  __syncthreads();
   uint32_t s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-    if (j < count) s += tiles[j];
+    loc[k] = loff[threadIdx.x * kScanItems + k];
+    s += loc[k];
   }
-  s = wave_sum(s);
-  if (lane_id() == 0) sm[threadIdx.x >> 6] = s;
+  uint32_t total;
+  uint32_t off = block_exclusive_scan(s, sm, total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    loff[threadIdx.x * kScanItems + k] = off;
+    off += loc[k];
+  }
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+  return total;
 }
 
-// Single block: exclusive scan of the block partials; D and the overflow flag to the header.
-__global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__ part, int nparts,
-                                                          unsigned long long* __restrict__ hdr,
+// Largest k with loff[k] <= o (loff[0] = 0 <= o); with o below the chunk total this is the
+// item that output o belongs to (items with no outputs share their successor's offset).
+__device__ __forceinline__ int owner_of(const uint32_t* loff, uint32_t o) {
+  int lo = 0, hi = kScanChunk - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (loff[mid] <= o) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------ step 1: counts and compaction
+// Per chunk of records: tile pairs (sum of tiles touched) and rendered records (tiles > 0).
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ tiles, int64_t count,
+                                                        uint32_t* __restrict__ partD, uint32_t* __restrict__ partR) {
+  __shared__ uint32_t sm[2][4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint32_t s = 0, r = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
+    const uint32_t c = j < count ? tiles[j] : 0u;
+    s += c;
+    r += c ? 1u : 0u;
+  }
+  s = wave_sum(s);
+  r = wave_sum(r);
+  if (lane_id() == 0) { sm[0][threadIdx.x >> 6] = s; sm[1][threadIdx.x >> 6] = r; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partD[blockIdx.x] = sm[0][0] + sm[0][1] + sm[0][2] + sm[0][3];
+    partR[blockIdx.x] = sm[1][0] + sm[1][1] + sm[1][2] + sm[1][3];
+  }
+}
+
+// Single block: exclusive scans of both partial arrays; D, R and the overflow flag to the
+// header (D is summed in 64 bits, so an overflowing total is still detected).
+__global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__ partD, uint32_t* __restrict__ partR,
+                                                          int nparts, unsigned long long* __restrict__ hdr,
                                                           int64_t cap) {
   __shared__ uint32_t sm[4];
   unsigned long long carry = 0;
+  uint32_t rcarry = 0;
   for (int base = 0; base < nparts; base += kBlock) {
     const int j = base + threadIdx.x;
-    const uint32_t v = j < nparts ? part[j] : 0u;
     uint32_t total;
+    const uint32_t v = j < nparts ? partD[j] : 0u;
     const uint32_t ex = block_exclusive_scan(v, sm, total);
-    if (j < nparts) part[j] = (uint32_t)carry + ex;
+    if (j < nparts) partD[j] = (uint32_t)carry + ex;
     carry += total;
+    const uint32_t rv = j < nparts ? partR[j] : 0u;
+    const uint32_t rex = block_exclusive_scan(rv, sm, total);
+    if (j < nparts) partR[j] = rcarry + rex;
+    rcarry += total;
   }
   if (threadIdx.x == 0) {
     hdr[kHdrDup] = carry;
     hdr[kHdrOverflow] = (long long)carry > cap ? 1ull : 0ull;
+    hdr[kHdrRend] = rcarry;
   }
 }
 
-// Per block: exclusive offsets of its chunk of items (blocked: thread t owns items
-// t*16 .. t*16+15), kept in LDS; then the block's output positions are walked in order, 256 at
-// a time, so the key and value stores are coalesced whatever the rectangle sizes.  Output o
-// of the block belongs to the last item whose offset is <= o (binary search; items with no
-// tiles share their successor's offset and are never selected) and is that item's
-// (o - offset)-th covered tile in row-major order.
-__global__ __launch_bounds__(kBlock) void k_scan_dup(
-    const uint32_t* __restrict__ tiles, int64_t count, const uint32_t* __restrict__ part,
-    const float* __restrict__ depth, const uint2* __restrict__ rect, const DevView* __restrict__ views,
-    int64_t n, const unsigned long long* __restrict__ hdr, int64_t cap,
-    unsigned long long* __restrict__ keys, uint32_t* __restrict__ vals) {
+// Rendered records of the chunk, in index order, to [partR[b], ...): key bits(depth), value f.
+// Positions are formed in LDS so the stores are coalesced.
+__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ tiles, int64_t count,
+                                                    const uint32_t* __restrict__ partR,
+                                                    const float* __restrict__ depth,
+                                                    const unsigned long long* __restrict__ hdr,
+                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   __shared__ uint32_t sm[4];
   __shared__ uint32_t loff[kScanChunk];
+  __shared__ uint32_t sf[kScanChunk];
+  if (hdr[kHdrOverflow] != 0ull) return;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   const int t = threadIdx.x;
-  // Coalesced load of the chunk's counts into LDS, then blocked reads.
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t j = base + (int64_t)k * kBlock + t;
-    loff[k * kBlock + t] = j < count ? tiles[j] : 0u;
+    loff[k * kBlock + t] = (j < count && tiles[j] != 0u) ? 1u : 0u;
   }
-  __syncthreads();
   uint32_t loc[kScanItems];
-  uint32_t s = 0;
+  const uint32_t total = chunk_offsets(loff, sm, loc);
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    loc[k] = loff[t * kScanItems + k];
-    s += loc[k];
-  }
-  uint32_t total;
-  uint32_t off = block_exclusive_scan(s, sm, total);   // its barriers also end the reads above
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    loff[t * kScanItems + k] = off;
-    off += loc[k];
-  }
+  for (int k = 0; k < kScanItems; ++k)
+    if (loc[k]) sf[loff[t * kScanItems + k]] = (uint32_t)(base + t * kScanItems + k);
   __syncthreads();
-  if (hdr[kHdrOverflow] != 0ull) return;
-  const int64_t out0 = (int64_t)part[blockIdx.x];
-  const uint32_t nn = (uint32_t)n;
+  const int64_t out0 = (int64_t)partR[blockIdx.x];
   for (uint32_t o = (uint32_t)t; o < total; o += kBlock) {
-    int lo = 0, hi = kScanChunk - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (loff[mid] <= o) lo = mid; else hi = mid - 1;
-    }
-    const uint32_t rel = o - loff[lo];
-    const uint32_t f = (uint32_t)base + (uint32_t)lo;
-    const DevView& Vw = views[f / nn];
-    const uint2 rc = rect[f];
-    const uint32_t x0 = rc.x & 0xFFFFu, x1 = rc.x >> 16, y0 = rc.y & 0xFFFFu;
-    const uint32_t w = x1 - x0;
-    const uint32_t ty = y0 + rel / w, tx = x0 + rel % w;
-    const uint32_t tile = Vw.tile_base + ty * (uint32_t)Vw.tiles_x + tx;
-    const int64_t og = out0 + (int64_t)o;
-    if (og < cap) {
-      keys[og] = ((unsigned long long)tile << 32) | (unsigned long long)__float_as_uint(depth[f]);
-      vals[og] = f;
-    }
+    const uint32_t f = sf[o];
+    kout[out0 + o] = __float_as_uint(depth[f]);
+    vout[out0 + o] = f;
   }
-}
-
-hipError_t launch_scan_dup(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s) {
-  char* w = (char*)ws;
-  char* dp = (char*)dup;
-  const uint32_t* tiles = (const uint32_t*)(w + L.tiles);
-  uint32_t* part = (uint32_t*)(w + L.scan_part);
-  unsigned long long* hdr = (unsigned long long*)(w + L.hdr);
-  const int nb = L.scan_blocks;
-  if (nb == 0) return launch_fill_u32((uint32_t*)hdr, 0u, 4, s);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, tiles, L.VN, part);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, part, nb, hdr, D.cap);
-  hipLaunchKernelGGL(k_scan_dup, dim3(nb), dim3(kBlock), 0, s, tiles, L.VN, part,
-                     (const float*)(w + L.depth), (const uint2*)(w + L.rect), (const DevView*)(w + L.vinfo),
-                     L.n, hdr, D.cap, (unsigned long long*)(dp + D.keys0), (uint32_t*)(dp + D.vals0));
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------- radix sort
-// Reduce-then-scan LSD radix sort with 8-bit digits.  Block b of G owns the contiguous
-// chunk [b*C, (b+1)*C) of the D keys (C a multiple of the 2048-key tile), so the stable
-// order across blocks is the block order.
+// Reduce-then-scan LSD radix sort of (uint32 key, uint32 value) pairs with 8-bit digits; the
+// element count is header word `cw`.  Block b of G owns the contiguous chunk
+// [b*C, (b+1)*C) (C a multiple of the 2048-key tile), so the stable order across blocks is the
+// block order.
 
-__device__ __forceinline__ void sort_chunk(int64_t D, int G, int b, int64_t& lo, int64_t& hi) {
-  const int64_t tiles_total = (D + kSortTile - 1) / kSortTile;
+__device__ __forceinline__ void sort_chunk(int64_t N, int G, int b, int64_t& lo, int64_t& hi) {
+  const int64_t tiles_total = (N + kSortTile - 1) / kSortTile;
   const int64_t per = (tiles_total + G - 1) / G;
   lo = (int64_t)b * per * kSortTile;
   hi = lo + per * kSortTile;
-  if (lo > D) lo = D;
-  if (hi > D) hi = D;
+  if (lo > N) lo = N;
+  if (hi > N) hi = N;
 }
 
 // Lanes of this wave holding the same 8-bit digit (restricted to `active`).
@@ -171,26 +181,26 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
   return m;
 }
 
-__global__ __launch_bounds__(kBlock) void k_radix_upsweep(const unsigned long long* __restrict__ keys,
-                                                          const unsigned long long* __restrict__ hdr,
+__global__ __launch_bounds__(kBlock) void k_radix_upsweep(const uint32_t* __restrict__ keys,
+                                                          const unsigned long long* __restrict__ hdr, int cw,
                                                           int G, int shift, uint32_t* __restrict__ hist) {
   __shared__ uint32_t cnt[4][256];   // per-wave digit counts
   if (hdr[kHdrOverflow]) return;
-  const int64_t D = (int64_t)hdr[kHdrDup];
+  const int64_t N = (int64_t)hdr[cw];
   const int t = threadIdx.x;
   const int wave = t >> 6;
 #pragma unroll
   for (int w = 0; w < 4; ++w) cnt[w][t] = 0;
   __syncthreads();
   int64_t lo, hi;
-  sort_chunk(D, G, blockIdx.x, lo, hi);
+  sort_chunk(N, G, blockIdx.x, lo, hi);
   // kSortItems keys per thread per step, all loads issued before any is used.
   for (int64_t base = lo; base < hi; base += kSortTile) {
     uint32_t d8[kSortItems];
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       const int64_t idx = base + (int64_t)j * kBlock + t;
-      d8[j] = idx < hi ? (uint32_t)(keys[idx] >> shift) & 255u : 256u;
+      d8[j] = idx < hi ? (keys[idx] >> shift) & 255u : 256u;
     }
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j)
@@ -220,19 +230,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t* __restric
 }
 
 __global__ __launch_bounds__(kBlock) void k_radix_downsweep(
-    const unsigned long long* __restrict__ kin, const uint32_t* __restrict__ vin,
-    unsigned long long* __restrict__ kout, uint32_t* __restrict__ vout,
-    const uint32_t* __restrict__ hist, const unsigned long long* __restrict__ hdr, int G, int shift) {
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ hist, const unsigned long long* __restrict__ hdr,
+    int cw, int G, int shift) {
   __shared__ uint32_t running[256];      // global output position of the next key per digit
   __shared__ uint32_t wcnt[4][256];      // per-wave digit counts within the tile
   __shared__ uint32_t tstart[256];       // tile-local start of each digit
   __shared__ uint32_t sm[4];
-  __shared__ unsigned long long skey[kSortTile];
+  __shared__ uint32_t skey[kSortTile];
   __shared__ uint32_t sval[kSortTile];
   if (hdr[kHdrOverflow]) return;
-  const int64_t D = (int64_t)hdr[kHdrDup];
+  const int64_t N = (int64_t)hdr[cw];
   int64_t lo, hi;
-  sort_chunk(D, G, blockIdx.x, lo, hi);
+  sort_chunk(N, G, blockIdx.x, lo, hi);
   const int t = threadIdx.x;
   const int wave = t >> 6;
   const uint32_t lane = lane_id();
@@ -245,16 +255,20 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(
   for (int64_t base = lo; base < hi; base += kSortTile) {
     wcnt[0][t] = 0; wcnt[1][t] = 0; wcnt[2][t] = 0; wcnt[3][t] = 0;
     __syncthreads();
-    unsigned long long k8[kSortItems];
-    uint32_t v8[kSortItems], d8[kSortItems], r8[kSortItems];
+    uint32_t k8[kSortItems], v8[kSortItems], d8[kSortItems], r8[kSortItems];
     // Wave w owns keys [base + w*512, base + (w+1)*512), slot j holds base + w*512 + j*64 + lane.
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
       const int64_t idx = base + (int64_t)wave * (64 * kSortItems) + j * 64 + lane;
       const bool valid = idx < hi;
-      k8[j] = valid ? kin[idx] : 0ull;
+      k8[j] = valid ? kin[idx] : 0u;
       v8[j] = valid ? vin[idx] : 0u;
-      const uint32_t d = valid ? (uint32_t)(k8[j] >> shift) & 255u : 256u;
+    }
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+      const int64_t idx = base + (int64_t)wave * (64 * kSortItems) + j * 64 + lane;
+      const bool valid = idx < hi;
+      const uint32_t d = valid ? (k8[j] >> shift) & 255u : 256u;
       d8[j] = d;
       const uint64_t active = ballot64(valid);
       const uint64_t m = match_digit(d & 255u, active);
@@ -292,10 +306,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(
     for (int j = 0; j < kSortItems; ++j) {
       const int p = j * kBlock + t;
       if (p < nvalid) {
-        const unsigned long long k = skey[p];
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t k = skey[p];
+        const uint32_t d = (k >> shift) & 255u;
         const uint32_t out = running[d] + (uint32_t)p - tstart[d];
-        if ((int64_t)out < D) {
+        if ((int64_t)out < N) {
           kout[out] = k;
           vout[out] = sval[p];
         }
@@ -307,67 +321,254 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(
   }
 }
 
-hipError_t launch_radix_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s) {
-  char* w = (char*)ws;
-  char* dp = (char*)dup;
-  const unsigned long long* hdr = (const unsigned long long*)(w + L.hdr);
-  const int G = sort_blocks(D.cap);
-  const int passes = sort_passes(L.tiles_total);
-  unsigned long long* k[2] = {(unsigned long long*)(dp + D.keys0), (unsigned long long*)(dp + D.keys1)};
-  uint32_t* v[2] = {(uint32_t*)(dp + D.vals0), (uint32_t*)(dp + D.vals1)};
-  uint32_t* hist = (uint32_t*)(dp + D.hist);
+static void radix_passes(const unsigned long long* hdr, int cw, int G, int first_shift, int passes,
+                         uint32_t* const k[2], uint32_t* const v[2], int src0, uint32_t* hist, hipStream_t s) {
   for (int p = 0; p < passes; ++p) {
-    const int src = p & 1, dst = src ^ 1;
-    const int shift = 8 * p;
-    hipLaunchKernelGGL(k_radix_upsweep, dim3(G), dim3(kBlock), 0, s, k[src], hdr, G, shift, hist);
+    const int src = (src0 + p) & 1, dst = src ^ 1;
+    const int shift = first_shift + 8 * p;
+    hipLaunchKernelGGL(k_radix_upsweep, dim3(G), dim3(kBlock), 0, s, k[src], hdr, cw, G, shift, hist);
     hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(kBlock), 0, s, hist, G, hdr);
     hipLaunchKernelGGL(k_radix_downsweep, dim3(G), dim3(kBlock), 0, s, k[src], v[src], k[dst], v[dst],
-                       hist, hdr, G, shift);
+                       hist, hdr, cw, G, shift);
   }
+}
+
+// ---------------------------------------------------------------- step 3: ordered emission
+// Per chunk of the depth-sorted records: tile pairs of the chunk.
+__global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restrict__ sorted_f,
+                                                        const uint32_t* __restrict__ tiles,
+                                                        const unsigned long long* __restrict__ hdr,
+                                                        uint32_t* __restrict__ partE) {
+  __shared__ uint32_t sm[4];
+  if (hdr[kHdrOverflow] != 0ull) return;
+  const int64_t R = (int64_t)hdr[kHdrRend];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  if (base >= R) return;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
+    if (j < R) s += tiles[sorted_f[j]];
+  }
+  s = wave_sum(s);
+  if (lane_id() == 0) sm[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partE[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+}
+
+// Single block: exclusive scan of the chunk totals (ceil(R / chunk) of them).
+__global__ __launch_bounds__(kBlock) void k_emit_partials(uint32_t* __restrict__ partE,
+                                                          const unsigned long long* __restrict__ hdr) {
+  __shared__ uint32_t sm[4];
+  if (hdr[kHdrOverflow] != 0ull) return;
+  const int nparts = (int)(((int64_t)hdr[kHdrRend] + kScanChunk - 1) / kScanChunk);
+  uint32_t carry = 0;
+  for (int base = 0; base < nparts; base += kBlock) {
+    const int j = base + threadIdx.x;
+    const uint32_t v = j < nparts ? partE[j] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(v, sm, total);
+    if (j < nparts) partE[j] = carry + ex;
+    carry += total;
+  }
+}
+
+// Per chunk of the depth-sorted records: each record's first output position (the global
+// exclusive scan of their tile counts, over the R positions of the record keys, which the
+// sort no longer needs), and for every output chunk of kEmitTile pairs the record that owns
+// its first position.
+__global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restrict__ sorted_f,
+                                                         const uint32_t* __restrict__ tiles,
+                                                         const uint32_t* __restrict__ partE,
+                                                         const unsigned long long* __restrict__ hdr,
+                                                         uint32_t* __restrict__ eoff, uint32_t* __restrict__ owner) {
+  __shared__ uint32_t sm[4];
+  __shared__ uint32_t loff[kScanChunk];
+  if (hdr[kHdrOverflow] != 0ull) return;
+  const int64_t R = (int64_t)hdr[kHdrRend];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  if (base >= R) return;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t j = base + (int64_t)k * kBlock + t;
+    loff[k * kBlock + t] = j < R ? tiles[sorted_f[j]] : 0u;
+  }
+  uint32_t loc[kScanItems];
+  const uint32_t total = chunk_offsets(loff, sm, loc);
+  const uint32_t cb = partE[blockIdx.x];
+  for (int i = t; i < kScanChunk; i += kBlock) {
+    const int64_t j = base + i;
+    if (j >= R) break;
+    const uint32_t first = cb + loff[i];
+    const uint32_t end = cb + (i + 1 < kScanChunk ? loff[i + 1] : total);
+    eoff[j] = first;
+    for (uint32_t q = (first + kEmitTile - 1) / kEmitTile; q * (uint64_t)kEmitTile < end; ++q) owner[q] = (uint32_t)j;
+  }
+}
+
+// Output chunk q (pairs [q*M, q*M + M), M = kEmitTile) is produced by the records between
+// the owner of its first pair and the owner of the next chunk's first pair (at most M + 1
+// of them, since every record has at least one pair); their offsets and indices are staged
+// in LDS, and pair o belongs to the last staged record whose offset is <= o, as that
+// record's (o - offset)-th covered tile in row-major order.  Chunks are equal-sized whatever
+// the rectangle sizes, and every store is coalesced.
+__global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ sorted_f,
+                                                 const uint32_t* __restrict__ eoff,
+                                                 const uint32_t* __restrict__ owner,
+                                                 const uint2* __restrict__ rect, const DevView* __restrict__ views,
+                                                 int64_t n, const unsigned long long* __restrict__ hdr,
+                                                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+  __shared__ uint32_t se[kEmitTile + 1];
+  __shared__ uint32_t sf[kEmitTile + 1];
+  if (hdr[kHdrOverflow] != 0ull) return;
+  const int64_t R = (int64_t)hdr[kHdrRend];
+  const int64_t D = (int64_t)hdr[kHdrDup];
+  const int64_t nch = (D + kEmitTile - 1) / kEmitTile;
+  const uint32_t nn = (uint32_t)n;
+  for (int64_t q = blockIdx.x; q < nch; q += gridDim.x) {
+    const int64_t k0 = owner[q];
+    const int64_t k1 = q + 1 < nch ? (int64_t)owner[q + 1] : R - 1;
+    int cnt = (int)(k1 - k0 + 1);
+    if (cnt > kEmitTile + 1) cnt = kEmitTile + 1;   // cannot happen (see above); keeps LDS in bounds
+    for (int i = threadIdx.x; i < cnt; i += kBlock) {
+      se[i] = eoff[k0 + i];
+      sf[i] = sorted_f[k0 + i];
+    }
+    __syncthreads();
+    const int64_t o0 = q * kEmitTile;
+    const int64_t o1 = o0 + kEmitTile < D ? o0 + kEmitTile : D;
+    for (int64_t og = o0 + threadIdx.x; og < o1; og += kBlock) {
+      const uint32_t o = (uint32_t)og;
+      int lo = 0, hi = cnt - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (se[mid] <= o) lo = mid; else hi = mid - 1;
+      }
+      const uint32_t rel = o - se[lo];
+      const uint32_t f = sf[lo];
+      const DevView& Vw = views[f / nn];
+      const uint2 rc = rect[f];
+      const uint32_t x0 = rc.x & 0xFFFFu, x1 = rc.x >> 16, y0 = rc.y & 0xFFFFu;
+      const uint32_t w = x1 - x0;
+      const uint32_t ty = y0 + rel / w, tx = x0 + rel % w;
+      kout[og] = Vw.tile_base + ty * (uint32_t)Vw.tiles_x + tx;
+      vout[og] = f;
+    }
+    __syncthreads();
+  }
+}
+
+int tile_passes(uint32_t tiles_total) {
+  int tb = 0;
+  uint32_t m = tiles_total > 0 ? tiles_total - 1 : 0;
+  while (m) { ++tb; m >>= 1; }
+  return (tb + 7) / 8;
+}
+
+int sorted_buffer(uint32_t tiles_total) { return (tile_passes(tiles_total) & 1) ? 0 : 1; }
+
+hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s) {
+  char* w = (char*)ws;
+  char* dp = (char*)dup;
+  unsigned long long* hdr = (unsigned long long*)(w + L.hdr);
+  uint32_t* const k[2] = {(uint32_t*)(dp + D.keys0), (uint32_t*)(dp + D.keys1)};
+  uint32_t* const v[2] = {(uint32_t*)(dp + D.vals0), (uint32_t*)(dp + D.vals1)};
+  uint32_t* hist = (uint32_t*)(dp + D.hist);
+  const int nb = L.scan_blocks;
+  if (nb == 0) return launch_fill_u32((uint32_t*)hdr, 0u, 2 * kHdrWords, s);
+  uint32_t* partD = (uint32_t*)(w + L.scan_part);
+  uint32_t* partR = partD + (nb + 1);
+  uint32_t* partE = partR + (nb + 1);
+  const uint32_t* tiles = (const uint32_t*)(w + L.tiles);
+  const int G = sort_blocks(D.cap);
+  // 1. counts, D, R, overflow; compaction of the rendered records into buffer 0.
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, tiles, L.VN, partD, partR);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partD, partR, nb, hdr, D.cap);
+  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(kBlock), 0, s, tiles, L.VN, (const uint32_t*)partR,
+                     (const float*)(w + L.depth), (const unsigned long long*)hdr, k[0], v[0]);
+  // 2. depth sort of the R records: 4 passes, back in buffer 0.
+  radix_passes(hdr, kHdrRend, G, 0, 4, k, v, 0, hist, s);
+  // 3. emission in depth order into buffer 1.
+  hipLaunchKernelGGL(k_emit_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], tiles,
+                     (const unsigned long long*)hdr, partE);
+  hipLaunchKernelGGL(k_emit_partials, dim3(1), dim3(kBlock), 0, s, partE, (const unsigned long long*)hdr);
+  uint32_t* owner = (uint32_t*)(dp + D.owner);
+  hipLaunchKernelGGL(k_emit_offsets, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], tiles,
+                     (const uint32_t*)partE, (const unsigned long long*)hdr, k[0], owner);
+  int64_t ge = (D.cap + kEmitTile - 1) / kEmitTile;
+  if (ge > 4096) ge = 4096;
+  if (ge < 1) ge = 1;
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)ge), dim3(kBlock), 0, s, (const uint32_t*)v[0], (const uint32_t*)k[0],
+                     (const uint32_t*)owner, (const uint2*)(w + L.rect), (const DevView*)(w + L.vinfo), L.n,
+                     (const unsigned long long*)hdr, k[1], v[1]);
+  // 4. stable sort of the D pairs by tile id.
+  radix_passes(hdr, kHdrDup, G, 0, tile_passes(L.tiles_total), k, v, 1, hist, s);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------- ranges
-__global__ __launch_bounds__(kBlock) void k_ranges(const unsigned long long* __restrict__ keys,
+__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ keys,
                                                    const unsigned long long* __restrict__ hdr,
                                                    uint32_t tiles_total, uint2* __restrict__ ranges) {
   if (hdr[kHdrOverflow]) return;
   const int64_t D = (int64_t)hdr[kHdrDup];
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < D; i += (int64_t)gridDim.x * kBlock) {
-    const uint32_t t = (uint32_t)(keys[i] >> 32);
+    const uint32_t t = keys[i];
     if (t >= tiles_total) continue;
-    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (uint32_t)i;
-    if (i == D - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (uint32_t)(i + 1);
+    if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
+    if (i == D - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
   }
 }
 
-// Longest-list-first order of the tiles (by bit length of the list, ties in any order):
-// the blend's running time is dominated by long lists, and starting them first keeps the
-// end of the launch from being a few long tiles on an otherwise idle chip.  One block.
-__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, uint32_t tiles,
-                                                     const unsigned long long* __restrict__ hdr,
-                                                     uint32_t* __restrict__ order) {
-  __shared__ uint32_t cnt[33];
-  __shared__ uint32_t off[33];
-  if (threadIdx.x < 33) cnt[threadIdx.x] = 0;
+// Longest-list-first order of the tiles: a counting sort of the tiles by the bit length of
+// their list length, longest first (order within a bucket is arbitrary: tiles are
+// independent).  The blend's running time is dominated by long lists, and starting them first
+// keeps the end of the launch from being a few long tiles on an otherwise idle chip.
+__device__ __forceinline__ uint32_t len_bucket(const uint2 r, bool ovf) {
+  const uint32_t len = ovf ? 0u : r.y - r.x;
+  return len ? 32u - (uint32_t)__clz(len) : 0u;
+}
+
+// Bucket totals: per-block LDS counts, then one global atomic per non-empty bucket.
+__global__ __launch_bounds__(kBlock) void k_tile_count(const uint2* __restrict__ ranges, uint32_t tiles,
+                                                       const unsigned long long* __restrict__ hdr,
+                                                       uint32_t* __restrict__ tord) {
+  __shared__ uint32_t cnt[kTileBuckets];
+  if (threadIdx.x < kTileBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
   const bool ovf = hdr[kHdrOverflow] != 0ull;
-  for (uint32_t t = threadIdx.x; t < tiles; t += blockDim.x) {
-    const uint2 r = ranges[t];
-    const uint32_t len = ovf ? 0u : r.y - r.x;
-    atomicAdd(&cnt[len ? 32 - __clz(len) : 0], 1u);
+  const uint32_t t0 = blockIdx.x * kTileOrderChunk;
+  for (uint32_t t = t0 + threadIdx.x; t < tiles && t < t0 + kTileOrderChunk; t += kBlock)
+    atomicAdd(&cnt[len_bucket(ranges[t], ovf)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kTileBuckets && cnt[threadIdx.x]) atomicAdd(&tord[threadIdx.x], cnt[threadIdx.x]);
+}
+
+// Scatter: bucket b starts after all longer buckets; each block reserves its slice of every
+// bucket with one global atomic (tord[33 + b]) and places its tiles with LDS cursors.
+__global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint2* __restrict__ ranges, uint32_t tiles,
+                                                         const unsigned long long* __restrict__ hdr,
+                                                         uint32_t* __restrict__ tord, uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[kTileBuckets];
+  __shared__ uint32_t cur[kTileBuckets];
+  if (threadIdx.x < kTileBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const bool ovf = hdr[kHdrOverflow] != 0ull;
+  const uint32_t t0 = blockIdx.x * kTileOrderChunk;
+  for (uint32_t t = t0 + threadIdx.x; t < tiles && t < t0 + kTileOrderChunk; t += kBlock)
+    atomicAdd(&cnt[len_bucket(ranges[t], ovf)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kTileBuckets) {
+    const uint32_t b = threadIdx.x;
+    uint32_t start = 0;
+    for (uint32_t c = b + 1; c < (uint32_t)kTileBuckets; ++c) start += tord[c];
+    cur[b] = cnt[b] ? start + atomicAdd(&tord[kTileBuckets + b], cnt[b]) : 0u;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = 32; b >= 0; --b) { off[b] = run; run += cnt[b]; }
-  }
-  __syncthreads();
-  for (uint32_t t = threadIdx.x; t < tiles; t += blockDim.x) {
-    const uint2 r = ranges[t];
-    const uint32_t len = ovf ? 0u : r.y - r.x;
-    const uint32_t pos = atomicAdd(&off[len ? 32 - __clz(len) : 0], 1u);
-    order[pos] = t;
+  for (uint32_t t = t0 + threadIdx.x; t < tiles && t < t0 + kTileOrderChunk; t += kBlock) {
+    const uint32_t pos = atomicAdd(&cur[len_bucket(ranges[t], ovf)], 1u);
+    if (pos < tiles) order[pos] = t;
   }
 }
 
@@ -377,15 +578,22 @@ hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* du
   char* dp = (char*)dup;
   hipError_t e = launch_fill_u32((uint32_t*)(w + L.ranges), 0u, 2 * (int64_t)L.tiles_total, s);
   if (e != hipSuccess) return e;
-  const unsigned long long* keys = (const unsigned long long*)(dp + (parity ? D.keys1 : D.keys0));
+  const uint32_t* keys = (const uint32_t*)(dp + (parity ? D.keys1 : D.keys0));
   int64_t g = (D.cap + kBlock - 1) / kBlock;
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)g), dim3(kBlock), 0, s, keys,
                      (const unsigned long long*)(w + L.hdr), L.tiles_total, (uint2*)(w + L.ranges));
-  if (L.tiles_total > 0)
-    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, (const uint2*)(w + L.ranges), L.tiles_total,
-                       (const unsigned long long*)(w + L.hdr), (uint32_t*)(w + L.order));
+  if (L.tiles_total > 0) {
+    uint32_t* tord = (uint32_t*)(w + L.tord);
+    e = launch_fill_u32(tord, 0u, kTileOrderWords, s);
+    if (e != hipSuccess) return e;
+    const unsigned nb = (L.tiles_total + kTileOrderChunk - 1) / kTileOrderChunk;
+    hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(kBlock), 0, s, (const uint2*)(w + L.ranges), L.tiles_total,
+                       (const unsigned long long*)(w + L.hdr), tord);
+    hipLaunchKernelGGL(k_tile_scatter, dim3(nb), dim3(kBlock), 0, s, (const uint2*)(w + L.ranges), L.tiles_total,
+                       (const unsigned long long*)(w + L.hdr), tord, (uint32_t*)(w + L.order));
+  }
   return hipGetLastError();
 }
 

@@ -140,7 +140,7 @@ class Batch:
         ptr, n = C.clod_inspect(self.c_struct(), section)
         if count is not None:
             n = min(n, int(count))
-        elem = {C.SEC_KEYS: 8, C.SEC_VALUES: 4, C.SEC_RANGES: 8, C.SEC_REC: 64, C.SEC_ALPHA: 4,
+        elem = {C.SEC_KEYS: 4, C.SEC_VALUES: 4, C.SEC_RANGES: 8, C.SEC_REC: 64, C.SEC_ALPHA: 4,
                 C.SEC_DEPTH: 4, C.SEC_FLAGS: 1, C.SEC_DMAX: 8, C.SEC_RECT: 8, C.SEC_GSCREEN: 36}[section]
         base = self.dup if section in (C.SEC_KEYS, C.SEC_VALUES) else self.ws
         off = ptr - base.data_ptr()

@@ -134,12 +134,13 @@ class GpuExecutor:
         self.retries = 0
         self.t0_event = None
 
-    # Device bytes of one request while in flight: per-(view, Gaussian) records, outputs and
-    # an estimate of its duplicate keys.
+    # Device bytes of one request while in flight: per-(view, Gaussian) workspace (flags,
+    # alpha'', depth, 64-byte record, rectangle, tiles touched, backward partials), outputs
+    # and an estimate of its tile pairs (16 bytes each).
     def cost(self, req) -> int:
         n = self.scene.n
         px = req.view.width * req.view.height
-        return int(n * 97 + px * (20 + 12) + 24 * self.dup_per_pixel * px)
+        return int(n * 121 + px * (20 + 12) + 16 * self.dup_per_pixel * px)
 
     def start(self):
         torch = self.torch

@@ -30,12 +30,16 @@ def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None):
     out["rgb"] = [t.cpu().numpy() for t in b.split(rgb, 3)]
     out["T"] = [t.cpu().numpy() for t in b.split(T, 1)]
     out["last"] = [t.cpu().numpy() for t in b.split(last, 1)]
-    out["keys"] = b.section(C.SEC_KEYS, D).cpu().numpy().view(np.uint64)
+    out["tile_ids"] = b.section(C.SEC_KEYS, D).cpu().numpy().view(np.uint32)
     out["vals"] = b.section(C.SEC_VALUES, D).cpu().numpy().view(np.uint32)
     out["ranges"] = b.section(C.SEC_RANGES).cpu().numpy().view(np.uint32)
     out["rec"] = b.section(C.SEC_REC).cpu().numpy()
     out["alpha"] = b.section(C.SEC_ALPHA).cpu().numpy()
     out["depth"] = b.section(C.SEC_DEPTH).cpu().numpy()
+    # The sorted pairs as (tile << 32 | bits(depth)) keys, from the tile ids and the depth of
+    # each pair's record.
+    dbits = out["depth"].view(np.uint32).astype(np.uint64)
+    out["keys"] = (out["tile_ids"].astype(np.uint64) << np.uint64(32)) | dbits[out["vals"].astype(np.int64)]
     out["flags"] = b.section(C.SEC_FLAGS).cpu().numpy()
     out["dmax"] = b.section(C.SEC_DMAX).cpu().numpy().view(np.uint64)
     out["rect"] = b.section(C.SEC_RECT).cpu().numpy().view(np.uint32)
