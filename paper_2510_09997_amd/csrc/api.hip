@@ -104,6 +104,8 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.kpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 8);
   L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 3 * 4);
   L.gpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4);
+  L.lcount = o; o = align256(o + (size_t)kMaxProjBlocks * 2 * 4);   // work-list segment counts, offsets
+  L.list = o; o = align256(o + (size_t)n * 4);                        // work list of the projection
   L.flags = o; o = align256(o + (size_t)L.VN);
   L.alpha = o; o = align256(o + (size_t)L.VN * 4);
   L.depth = o; o = align256(o + (size_t)L.VN * 4);
@@ -253,7 +255,9 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
           "frustum max");
   HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
                          (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags),
-                         (float*)(w + L.alpha), (float*)(w + L.depth), (float4*)(w + L.rec), (uint2*)(w + L.rect), (uint32_t*)(w + L.tiles), s),
+                         (float*)(w + L.alpha), (float*)(w + L.depth), (float4*)(w + L.rec), (uint2*)(w + L.rect),
+                         (uint32_t*)(w + L.tiles), (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount),
+                         (unsigned long long*)(w + L.hdr), s),
           "project");
   if (counts_dev)
     HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
@@ -350,7 +354,8 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
                              (unsigned long long*)(w + L.dmax_key), s),
           "frustum max");
   HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
-                           (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), s),
+                           (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts),
+                           (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), (unsigned long long*)(w + L.hdr), s),
           "lod count");
   HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
   return CLOD_OK;

@@ -38,7 +38,7 @@ struct DevView {
 };
 
 // Workspace header words (uint64).
-enum : int { kHdrDup = 0, kHdrOverflow = 1, kHdrRend = 2, kHdrWords = 8 };
+enum : int { kHdrDup = 0, kHdrOverflow = 1, kHdrRend = 2, kHdrList = 3, kHdrWords = 8 };
 
 struct Layout {
   int64_t n = 0;
@@ -48,7 +48,7 @@ struct Layout {
   int64_t pixels_total = 0;
   int32_t scan_blocks = 0;
   // byte offsets into ws
-  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, flags, alpha, depth, rec,
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, lcount, list, flags, alpha, depth, rec,
       rect, tiles, scan_part, ranges, order, tord, pair_part, gscreen, total;
 };
 
@@ -332,10 +332,11 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                           uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
-                          uint32_t* tiles, hipStream_t s);
+                          uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
+                          hipStream_t s);
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                            hipStream_t s);
+                            uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s);
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s);
 
 hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s);

@@ -88,29 +88,141 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
   }
 }
 
-// Two phases per Gaussian and group of up to 32 views: (1) geometry for every view (frustum,
-// Eq. (2), mask, EWA, rectangle), remembering which views render the Gaussian; (2) only if
-// some view does, its SH coefficients are loaded once (all loads in flight together) and the
-// colour of each rendering view is evaluated.
-template <int DEG, bool kWriteRecords>
-__global__ __launch_bounds__(kBlock) void k_project(
+// Pass 1 over every Gaussian (block b owns the chunk [b*C, (b+1)*C)): per view the frustum
+// flag, Eq. (2) and the LoD mask (alpha'' and the F/M flags written for every (view,
+// Gaussian), tiles touched zeroed), F and M counts, and the Gaussians that are in some view's
+// frustum and kept by its mask appended to the block's segment of the work list (order
+// within a segment is arbitrary).  Outside those, nothing else is computed, so the heavy
+// pass below runs on full waves instead of the ~40% of lanes a whole-scene pass keeps busy.
+template <bool kWrite>
+__global__ __launch_bounds__(kBlock) void k_classify(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
     const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
-    uint8_t* __restrict__ flags_out, float* __restrict__ alpha_out, float* __restrict__ depth_out,
-    float4* __restrict__ rec, uint2* __restrict__ rect_out,
-    uint32_t* __restrict__ tiles_out) {
-  extern __shared__ uint32_t scnt[];   // [V][3]
-  constexpr int K = (DEG + 1) * (DEG + 1);
+    uint8_t* __restrict__ flags_out, float* __restrict__ alpha_out, uint32_t* __restrict__ tiles_out,
+    uint32_t* __restrict__ list /* [n] */, uint32_t* __restrict__ lcount /* [G] */) {
+  extern __shared__ uint32_t scnt[];   // [V][2]
+  __shared__ uint32_t sbase;
   const int64_t n = sc.n;
-  for (int j = threadIdx.x; j < 3 * V; j += kBlock) scnt[j] = 0;
+  for (int j = threadIdx.x; j < 2 * V; j += kBlock) scnt[j] = 0;
+  if (threadIdx.x == 0) sbase = 0;
   __syncthreads();
   int64_t lo, hi;
   block_chunk(n, lo, hi);
-  // Every lane of the block runs the same number of iterations (ballots stay uniform).
+  const uint64_t lt = lanemask_lt();
   const int64_t iters = (hi - lo + kBlock - 1) / kBlock;
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t i = lo + it * kBlock + threadIdx.x;
     const bool valid = i < hi;
+    float mx = 0.f, my = 0.f, mz = 0.f, op = 0.f, dc = 0.f;
+    if (valid) {
+      mx = sc.mean[i]; my = sc.mean[n + i]; mz = sc.mean[2 * n + i];
+      op = sc.opacity[i]; dc = sc.decay[i];
+    }
+    bool any = false;
+    for (int v = 0; v < V; ++v) {
+      const DevView& Vw = views[v];
+      bool F = false, M = false;
+      if (valid) {
+        float x, y, z, ex, ey, ez;
+        to_camera(Vw, mx, my, mz, x, y, z);
+        F = in_frustum(Vw, x, y, z, prm.near_z);
+        const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
+        float alpha, q;
+        const float a2 = attenuated(d, dmax_from_key(dmax_key[v]), Vw.s_v, dc, op, prm.eps, alpha, q);
+        M = a2 > Vw.tau_sv;
+        if (kWrite) {
+          const int64_t f = (int64_t)v * n + i;
+          alpha_out[f] = a2;
+          flags_out[f] = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
+          tiles_out[f] = 0u;
+        }
+      }
+      any = any || (F && M);
+      const uint64_t bF = ballot64(F), bM = ballot64(M);
+      if (lane_id() == 0) {
+        if (bF) atomicAdd(&scnt[2 * v + 0], (uint32_t)__popcll(bF));
+        if (bM) atomicAdd(&scnt[2 * v + 1], (uint32_t)__popcll(bM));
+      }
+    }
+    const uint64_t bw = ballot64(any);
+    uint32_t wbase = 0;
+    if (lane_id() == 0 && bw) wbase = atomicAdd(&sbase, (uint32_t)__popcll(bw));
+    wbase = __shfl(wbase, 0, 64);
+    if (any) list[lo + wbase + (uint32_t)__popcll(bw & lt)] = (uint32_t)i;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < V; j += kBlock) {
+    cpart[((int64_t)blockIdx.x * V + j) * 3 + 0] = scnt[2 * j];
+    cpart[((int64_t)blockIdx.x * V + j) * 3 + 1] = scnt[2 * j + 1];
+  }
+  if (threadIdx.x == 0) lcount[blockIdx.x] = sbase;
+}
+
+// Single block: lcount[G] -> exclusive offsets loff[G] and the list length into the header.
+__global__ __launch_bounds__(kBlock) void k_list_scan(const uint32_t* __restrict__ lcount, int G,
+                                                      uint32_t* __restrict__ loff,
+                                                      unsigned long long* __restrict__ hdr) {
+  __shared__ uint32_t sm[4];
+  uint32_t carry = 0;
+  for (int base = 0; base < G; base += kBlock) {
+    const int j = base + threadIdx.x;
+    uint32_t v = j < G ? lcount[j] : 0u;
+    // Inclusive scan over the wave, then across the four waves.
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t up = __shfl_up(inc, o, 64);
+      if (lane_id() >= (uint32_t)o) inc += up;
+    }
+    if (lane_id() == 63) sm[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    uint32_t wb = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wb += sm[w];
+    const uint32_t tot = sm[0] + sm[1] + sm[2] + sm[3];
+    __syncthreads();
+    if (j < G) loff[j] = carry + wb + inc - v;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) hdr[kHdrList] = carry;
+}
+
+// Pass 2 over the work list (entries spread evenly over the blocks): per listed Gaussian the
+// geometry of every view again (cheap), then for in-frustum kept views the EWA projection,
+// cull and rectangle, remembering which views render it; then its SH coefficients are
+// loaded once and the colour of each rendering view is evaluated.  Records, depth, rectangle
+// and tiles touched are written for rendered (view, Gaussian) pairs only.
+template <int DEG, bool kWriteRecords>
+__global__ __launch_bounds__(kBlock) void k_project(
+    clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
+    const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ loff, const unsigned long long* __restrict__ hdr,
+    uint8_t* __restrict__ flags_out, float* __restrict__ depth_out, float4* __restrict__ rec,
+    uint2* __restrict__ rect_out, uint32_t* __restrict__ tiles_out) {
+  extern __shared__ uint32_t sdyn[];   // [G] segment offsets, then [V] rendered counts
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t n = sc.n;
+  const int G = gridDim.x;
+  uint32_t* soff = sdyn;
+  uint32_t* scnt = sdyn + G;
+  for (int j = threadIdx.x; j < G; j += kBlock) soff[j] = loff[j];
+  for (int j = threadIdx.x; j < V; j += kBlock) scnt[j] = 0;
+  __syncthreads();
+  const int64_t L = (int64_t)hdr[kHdrList];
+  const int64_t per = (n + G - 1) / G;   // chunk length of the first pass
+  const int64_t stride = (int64_t)G * kBlock;
+  // Every lane of the block runs the same number of rounds (ballots stay uniform).
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < L; base += stride) {
+    const int64_t e = base + threadIdx.x;
+    const bool valid = e < L;
+    int64_t i = 0;
+    if (valid) {
+      int blo = 0, bhi = G - 1;   // last segment whose offset is <= e
+      while (blo < bhi) {
+        const int mid = (blo + bhi + 1) >> 1;
+        if ((int64_t)soff[mid] <= e) blo = mid; else bhi = mid - 1;
+      }
+      i = (int64_t)list[(int64_t)blo * per + (e - (int64_t)soff[blo])];
+    }
     float mx = 0.f, my = 0.f, mz = 0.f, op = 0.f, dc = 0.f;
     if (valid) {
       mx = sc.mean[i]; my = sc.mean[n + i]; mz = sc.mean[2 * n + i];
@@ -121,22 +233,19 @@ __global__ __launch_bounds__(kBlock) void k_project(
     float S[9];
     for (int v0 = 0; v0 < V; v0 += 32) {
       const int vn = V - v0 < 32 ? V - v0 : 32;
-      uint32_t rmask = 0, fm_bits0 = 0, fm_bits1 = 0;   // rendered views; F and M per view
+      uint32_t rmask = 0;   // rendered views of the group
       for (int vv = 0; vv < vn; ++vv) {
         const int v = v0 + vv;
         const DevView& Vw = views[v];
-        const int64_t f = (int64_t)v * n + i;
-        bool F = false, M = false, R = false;
+        bool R = false;
         if (valid) {
           float x, y, z, ex, ey, ez;
           to_camera(Vw, mx, my, mz, x, y, z);
-          F = in_frustum(Vw, x, y, z, prm.near_z);
+          const bool F = in_frustum(Vw, x, y, z, prm.near_z);
           const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
-          const float dmax = dmax_from_key(dmax_key[v]);
           float alpha, q;
-          const float a2 = attenuated(d, dmax, Vw.s_v, dc, op, prm.eps, alpha, q);
-          M = a2 > Vw.tau_sv;
-          if (F && M) {
+          const float a2 = attenuated(d, dmax_from_key(dmax_key[v]), Vw.s_v, dc, op, prm.eps, alpha, q);
+          if (F && a2 > Vw.tau_sv) {
             if (!have_cov) {
               const float s0 = cexp(sc.log_scale[i]), s1 = cexp(sc.log_scale[n + i]), s2 = cexp(sc.log_scale[2 * n + i]);
               float Rm[9], w_, x_, y_, z_, rn;
@@ -148,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_project(
             if (ewa(Vw, x, y, z, S, prm.dilation, P)) {
               R = true;
               if (kWriteRecords) {
+                const int64_t f = (int64_t)v * n + i;
                 rec[kRecQuads * f] = make_float4(P.u, P.v, a2, P.rad);
                 rec[kRecQuads * f + 1] = make_float4(P.A, P.B, P.C, 0.f);
                 depth_out[f] = z;
@@ -156,23 +266,10 @@ __global__ __launch_bounds__(kBlock) void k_project(
               }
             }
           }
-          if (kWriteRecords) {
-            alpha_out[f] = a2;
-            if (!R) {
-              tiles_out[f] = 0u;
-              flags_out[f] = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
-            }
-          }
         }
         rmask |= (R ? 1u : 0u) << vv;
-        fm_bits0 |= (F ? 1u : 0u) << vv;
-        fm_bits1 |= (M ? 1u : 0u) << vv;
-        const uint64_t bF = ballot64(F), bM = ballot64(M), bR = ballot64(R);
-        if (lane_id() == 0) {
-          if (bF) atomicAdd(&scnt[3 * v + 0], (uint32_t)__popcll(bF));
-          if (bM) atomicAdd(&scnt[3 * v + 1], (uint32_t)__popcll(bM));
-          if (bR) atomicAdd(&scnt[3 * v + 2], (uint32_t)__popcll(bR));
-        }
+        const uint64_t bR = ballot64(R);
+        if (lane_id() == 0 && bR) atomicAdd(&scnt[v], (uint32_t)__popcll(bR));
       }
       if (kWriteRecords && rmask) {
         float shc[3 * K];
@@ -190,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_project(
           const float id = 1.0f / d;
           float Yb[16];
           sh_basis(DEG, ex * id, ey * id, ez * id, Yb);
-          uint8_t fl = (uint8_t)(((fm_bits0 >> vv) & 1u) | (((fm_bits1 >> vv) & 1u) << 1) | 4u);
+          uint8_t fl = 1u | 2u | 4u;   // rendered implies in frustum and kept
           float col[3];
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) {
@@ -208,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_project(
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < 3 * V; j += kBlock) cpart[(int64_t)blockIdx.x * 3 * V + j] = scnt[j];
+  for (int j = threadIdx.x; j < V; j += kBlock) cpart[((int64_t)blockIdx.x * V + j) * 3 + 2] = scnt[j];
 }
 
 // Block v folds the G partials of view v: the frustum-max key (max) and the counts (sum).
@@ -291,9 +388,14 @@ template <bool kWrite>
 static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                                const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                                uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
-                               uint32_t* tiles, hipStream_t s) {
+                               uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
+                               hipStream_t s) {
   if (sc.n == 0) return launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
   const int G = proj_blocks(sc.n);
+  uint32_t* loff = lcount + G;
+  hipLaunchKernelGGL(k_classify<kWrite>, dim3(G), dim3(kBlock), (size_t)(2 * V * sizeof(uint32_t)), s, sc, vinfo,
+                     V, prm, dmax_key, cpart, flags, alpha, tiles, list, lcount);
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(kBlock), 0, s, (const uint32_t*)lcount, G, loff, hdr);
   auto kern = k_project<3, kWrite>;
   switch (sc.sh_degree) {
     case 0: kern = k_project<0, kWrite>; break;
@@ -301,8 +403,9 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
     case 2: kern = k_project<2, kWrite>; break;
     default: break;
   }
-  hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), (size_t)(3 * V * sizeof(uint32_t)), s, sc, vinfo,
-                     V, prm, dmax_key, cpart, flags, alpha, depth, rec, rect, tiles);
+  hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), (size_t)((G + V) * sizeof(uint32_t)), s, sc, vinfo, V, prm,
+                     dmax_key, cpart, (const uint32_t*)list, (const uint32_t*)loff,
+                     (const unsigned long long*)hdr, flags, depth, rec, rect, tiles);
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
                      (const uint32_t*)cpart, G, V, (unsigned long long*)nullptr, counts);
   return hipGetLastError();
@@ -311,15 +414,17 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                           uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
-                          uint32_t* tiles, hipStream_t s) {
-  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, flags, alpha, depth, rec, rect, tiles, s);
+                          uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
+                          hipStream_t s) {
+  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, flags, alpha, depth, rec, rect, tiles,
+                            list, lcount, hdr, s);
 }
 
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                            hipStream_t s) {
-  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, nullptr, nullptr,
-                             nullptr, s);
+                            uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s) {
+  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, nullptr,
+                             nullptr, nullptr, list, lcount, hdr, s);
 }
 
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s) {

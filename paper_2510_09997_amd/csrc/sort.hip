@@ -104,17 +104,44 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__
   __shared__ uint32_t sm[4];
   unsigned long long carry = 0;
   uint32_t rcarry = 0;
-  for (int base = 0; base < nparts; base += kBlock) {
-    const int j = base + threadIdx.x;
-    uint32_t total;
-    const uint32_t v = j < nparts ? partD[j] : 0u;
-    const uint32_t ex = block_exclusive_scan(v, sm, total);
-    if (j < nparts) partD[j] = (uint32_t)carry + ex;
-    carry += total;
-    const uint32_t rv = j < nparts ? partR[j] : 0u;
-    const uint32_t rex = block_exclusive_scan(rv, sm, total);
-    if (j < nparts) partR[j] = rcarry + rex;
-    rcarry += total;
+  // kScanItems consecutive partials per thread per round (one block scan per array per round).
+  for (int base = 0; base < nparts; base += kScanChunk) {
+    const int j0 = base + (int)threadIdx.x * kScanItems;
+    uint32_t d[kScanItems], r[kScanItems];
+    unsigned long long sd = 0;
+    uint32_t sr = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      d[k] = j0 + k < nparts ? partD[j0 + k] : 0u;
+      r[k] = j0 + k < nparts ? partR[j0 + k] : 0u;
+      sd += d[k];
+      sr += r[k];
+    }
+    // Thread sums of pair counts may exceed 32 bits only when the total does; the overflow
+    // flag below is computed from the 64-bit total either way.
+    uint32_t totd, totr;
+    uint32_t exd = block_exclusive_scan((uint32_t)sd, sm, totd);
+    uint32_t exr = block_exclusive_scan(sr, sm, totr);
+    unsigned long long wide = 0;   // 64-bit block total of the pair counts
+    {
+      __shared__ unsigned long long sw[4];
+      const unsigned long long ws = wave_sum(sd);
+      if (lane_id() == 0) sw[threadIdx.x >> 6] = ws;
+      __syncthreads();
+      wide = sw[0] + sw[1] + sw[2] + sw[3];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      if (j0 + k < nparts) {
+        partD[j0 + k] = (uint32_t)carry + exd;
+        partR[j0 + k] = rcarry + exr;
+      }
+      exd += d[k];
+      exr += r[k];
+    }
+    carry += wide;
+    rcarry += totr;
   }
   if (threadIdx.x == 0) {
     hdr[kHdrDup] = carry;
