@@ -10,7 +10,9 @@
  *   - Sec. 3.2: camera distance d_i = |mu_i - c|, normalised by the maximum distance over the
  *     Gaussians inside the view frustum; Eq. (2) attenuated opacity
  *     alpha''_i = alpha_i * exp(-(d'_i s_v)^2 / (2 ReLU(sigma_d,i)^2 + eps));
- *     LoD mask M_i = alpha''_i > tau * s_v; only masked-in Gaussians are rendered.
+ *     LoD mask M_i = alpha''_i > tau * s_v; only masked-in Gaussians are rendered.  For the
+ *     primitive-budget selection of the Sec. 4 comparisons (the Gaussians of highest
+ *     attenuated opacity) the caller passes the mask instead (oracle.py forms it).
  *   - The 3DGS projection the paper builds on (Sec. 3.1 "projected onto the 2D image
  *     plane"; Sec. 4.1 "built on the official 3DGS implementation"): EWA splatting with a
  *     0.3 px^2 dilation, 3-sigma screen radius, 16x16 tiles.
@@ -210,7 +212,7 @@ void oracle_sh_basis(const float *dirs, int64_t n, int deg, float *out) {
 /* ------------------------------------------------------------------------------------ */
 void oracle_view_pass(int64_t n, int deg, const float *mean, const float *lsc, const float *quat,
                       const float *opac, const float *decay, const float *sh,
-                      const float *view24, const float *par8,
+                      const float *view24, const float *par8, const uint8_t *mask_in,
                       uint8_t *flags, float *rec, int32_t *rect, float *aux,
                       float *dmax_out, int64_t *argmax_out, int64_t *counts) {
     oracle_init();
@@ -259,7 +261,8 @@ void oracle_view_pass(int64_t n, int deg, const float *mean, const float *lsc, c
         float q = num / den;
         float alpha = 1.0f / (1.0f + cexp32(-opac[i]));
         float a2 = alpha * cexp32(-q);
-        int M = a2 > tau * V.sv;
+        /* The mask: the threshold of Sec. 3.2, or a given selection (budgeted LoD). */
+        int M = mask_in ? (mask_in[i] != 0) : (a2 > tau * V.sv);
 
         uint8_t fl = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
         nF += F;

@@ -65,7 +65,7 @@ def lib():
         L.oracle_exp.argtypes = [P, P, i64]
         L.oracle_exp_scan.argtypes = [ctypes.c_float, ctypes.c_float, P]
         L.oracle_sh_basis.argtypes = [P, i64, ctypes.c_int, P]
-        L.oracle_view_pass.argtypes = [i64, ctypes.c_int] + [P] * 8 + [P] * 7
+        L.oracle_view_pass.argtypes = [i64, ctypes.c_int] + [P] * 9 + [P] * 7
         L.oracle_tile_lists.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_int, P, P, i64]
         L.oracle_tile_lists.restype = i64
         L.oracle_blend.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P]
@@ -126,8 +126,28 @@ def sh_basis32(dirs: np.ndarray, deg: int) -> np.ndarray:
     return out
 
 
+def budget_mask(alpha2: np.ndarray, budget: int) -> np.ndarray:
+    """Primitive-budget LoD selection (the Sec. 4 comparisons keep the Gaussians with the
+    highest attenuated opacity): the `budget` largest alpha'', lower index first among equal
+    values (the tie reading).  A plain sort of (-alpha'', index)."""
+    n = alpha2.shape[0]
+    m = np.zeros(n, dtype=np.uint8)
+    order = np.lexsort((np.arange(n), -alpha2.astype(np.float64)))
+    m[order[:min(int(budget), n)]] = 1
+    return m
+
+
 def view_pass(scene: dict, view, params: dict | None = None) -> dict:
-    """Per-Gaussian binary32 pass for one view (Sec. 3.2 and the EWA projection)."""
+    """Per-Gaussian binary32 pass for one view (Sec. 3.2 and the EWA projection).  A view with
+    budget K > 0 keeps the K largest alpha'' (a first pass computes alpha'' for all Gaussians)."""
+    budget = int(getattr(view, "budget", 0))
+    mask = None
+    if budget > 0:
+        mask = budget_mask(_view_pass(scene, view, params, None)["rec"][:, 6], budget)
+    return _view_pass(scene, view, params, mask)
+
+
+def _view_pass(scene: dict, view, params: dict | None, mask) -> dict:
     n, deg = scene["n"], scene["sh_degree"]
     flags = np.zeros(n, dtype=np.uint8)
     rec = np.zeros((n, 10), dtype=np.float32)
@@ -137,8 +157,10 @@ def view_pass(scene: dict, view, params: dict | None = None) -> dict:
     arg = np.zeros(1, dtype=np.int64)
     counts = np.zeros(3, dtype=np.int64)
     v24, p8 = pack_view(view), pack_params(params)
+    mask_c = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)   # alive across the call
     lib().oracle_view_pass(n, deg, _p(scene["mean"]), _p(scene["log_scale"]), _p(scene["quat"]),
                            _p(scene["opacity"]), _p(scene["decay"]), _p(scene["sh"]), _p(v24), _p(p8),
+                           None if mask_c is None else _p(mask_c),
                            _p(flags), _p(rec), _p(rect), _p(aux), _p(dmax), _p(arg), _p(counts))
     return dict(flags=flags, rec=rec, rect=rect, aux=aux, dmax=float(dmax[0]), argmax=int(arg[0]),
                 counts=counts, width=view.width, height=view.height)

@@ -464,3 +464,73 @@ def test_storage_overhead_matches_paper_table():
         mem = row["gaussians_k"] * 1000 * row["bytes_per_gaussian"] / 2 ** 20
         assert abs(mem - row["mem_mb"]) < 0.5e3 * row["bytes_per_gaussian"] / 2 ** 20, row
     assert round(4 / 248 * 100, 1) == 1.6
+
+
+# ---------------------------------------------------------------------------------------
+# Budgeted LoD selection (the Sec. 4 comparisons keep the Gaussians of highest attenuated
+# opacity): pinned against a brute-force rank definition and against the threshold mask.
+# ---------------------------------------------------------------------------------------
+
+def _with_budget(view, k):
+    import dataclasses
+    return dataclasses.replace(view, budget=int(k))
+
+
+def test_budget_mask_equals_brute_force_rank_with_ties():
+    """Kept iff fewer than K Gaussians precede it in (alpha'' descending, index ascending),
+    counted pair by pair; duplicated Gaussians make equal alpha'' values."""
+    sc = synth.make_scene(300, 1, "uniform", seed=21)
+    for dst, src in ((9, 5), (40, 5), (77, 120)):
+        for key in ("mean", "log_scale", "quat", "sh"):
+            sc[key][..., dst] = sc[key][..., src]
+        sc["opacity"][dst] = sc["opacity"][src]
+        sc["decay"][dst] = sc["decay"][src]
+    view = synth.look_at((0.2, -0.1, -3.0), width=96, height=80, s_v=2.0)
+    a2 = O.view_pass(sc, view)["rec"][:, 6].astype(np.float64)
+    assert a2[9] == a2[5] == a2[40] and a2[77] == a2[120]
+    n = sc["n"]
+    before = np.array([np.sum((a2 > a2[i]) | ((a2 == a2[i]) & (np.arange(n) < i))) for i in range(n)])
+    for k in (1, 2, 17, 150, int(before[9]), int(before[9]) + 1, n - 1, n, n + 5):
+        vp = O.view_pass(sc, _with_budget(view, k))
+        kept = (vp["flags"] & 2) > 0
+        assert np.array_equal(kept, before < k), k
+        assert vp["counts"][1] == min(k, n)
+
+
+def test_budget_mask_equals_threshold_mask_between_consecutive_values():
+    """With no tie at the cut, keeping the K largest alpha'' is the threshold mask for any
+    tau * s_v strictly between the K-th and (K+1)-th largest values; every output agrees."""
+    sc = synth.make_scene(2000, 3, "mixture", seed=22)
+    view = synth.look_at((1.0, 0.5, -7.0), width=128, height=96, s_v=1.0)
+    a2 = np.sort(O.view_pass(sc, view)["rec"][:, 6])[::-1]
+    checked = 0
+    for k in (50, 150, 300, 500, 800):   # 916 of the 2000 alpha'' are non-zero here
+        hi, lo = a2[k - 1], a2[k]
+        if not hi > lo:
+            continue
+        tau = np.float32((np.float64(hi) + np.float64(lo)) / 2)
+        if not (lo < tau < hi):
+            continue
+        p = dict(tau=float(tau))
+        a = O.render32(sc, view, p)
+        b = O.render32(sc, _with_budget(view, k), p)
+        assert np.array_equal(a["flags"], b["flags"]), k
+        assert np.array_equal(a["rec"].view(np.uint32), b["rec"].view(np.uint32)), k
+        assert np.array_equal(a["rgb"].view(np.uint32), b["rgb"].view(np.uint32)), k
+        assert np.array_equal(a["last"], b["last"]), k
+        checked += 1
+    assert checked >= 3
+
+
+def test_budget_masks_nest_as_the_budget_grows():
+    sc = synth.make_scene(1500, 0, "uniform", seed=23)
+    view = synth.look_at((0.0, 0.0, -3.0), width=64, height=64, s_v=3.0)
+    prev = None
+    for k in (0, 1, 10, 100, 700, 1499, 1500):
+        if k == 0:
+            continue
+        kept = (O.view_pass(sc, _with_budget(view, k))["flags"] & 2) > 0
+        assert kept.sum() == k
+        if prev is not None:
+            assert np.all(kept[prev])
+        prev = kept
