@@ -269,6 +269,40 @@ def run_multiview_train(args, torch, C, Scene, synth):
                 pixels_per_step=tr.batch.pixels)
 
 
+def run_budget_sweep(args, torch, C, Batch, scene, pose):
+    """Primitive budget -> frames/s: one 1080p view (a headline pose, s_v = 1) rendered with
+    the K largest alpha'' kept, K from 25,000 to all 3,000,000 (the selection of the paper's
+    quality/speed comparisons)."""
+    import dataclasses
+    n = scene.n
+    out = {"budgets": [], "kept": [], "rendered": [], "fps": []}
+    budgets = [25_000, 50_000, 100_000, 200_000, 400_000, 800_000, 1_600_000, n]
+    b = Batch(n, [dataclasses.replace(pose, budget=budgets[0])])
+    rgb = torch.empty(3 * b.pixels, device="cuda")
+    T = torch.empty(b.pixels, device="cuda")
+    last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
+    for k in budgets:
+        b.update_views([dataclasses.replace(pose, budget=k)])
+        b.project(scene)
+        b.bin_sort()
+        bs = b.c_struct()
+        reps = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            C.clod_project(scene.c_struct(), bs, b.counts)
+            C.clod_bin_sort(bs, sync_count=False)
+            C.clod_render_fwd(bs, rgb, T, last, None)
+        e1.record()
+        torch.cuda.synchronize()
+        cnt = b.counts.cpu().numpy()[0]
+        out["budgets"].append(int(k))
+        out["kept"].append(int(cnt[1]))
+        out["rendered"].append(int(cnt[2]))
+        out["fps"].append(round(reps / (e0.elapsed_time(e1) / 1e3), 2))
+    return out
+
+
 def run_lod_sweep(args, torch, C, Batch, Scene, synth):
     """6M Gaussians, 1920x1080, 64 camera distances log-spaced in [2, 200] along one ray
     (looking at the origin from -z): kept-primitive counts of all 64 views in one launch, and
@@ -379,6 +413,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-multiview", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-budget", action="store_true", help="skip the primitive-budget sweep")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-request comparison path")
     ap.add_argument("--no-count", action="store_true", help="skip the untimed work-counting re-run")
     ap.add_argument("--probe-copy", action="store_true",
@@ -397,6 +432,10 @@ def main():
     serve, scene, b, steps = run_serving(args, torch, C, Batch, Scene, synth)
     log(f"[bench] serving: {serve['fps']:.1f} frames/s batched, {serve.get('plain_fps', float('nan')):.1f} plain; "
         f"stages {serve['stage_ms']}")
+    budget = None
+    if not args.no_budget:
+        budget = run_budget_sweep(args, torch, C, Batch, scene, steps[min(10, len(steps) - 1)][0])
+        log(f"[bench] budget sweep fps: {dict(zip(budget['budgets'], budget['fps']))}")
     del scene, b
     torch.cuda.empty_cache()
     train = None
@@ -448,6 +487,8 @@ def main():
         out["fwd_bwd_p99_ms"] = round(train["p99_ms"], 3)
         out["train_config"] = {"gaussians": 1_000_000, "sh_degree": 3, "resolution": [1297, 840],
                                "s_v": "log-uniform [1, 8]", "loss": "L1 + point-count regulariser"}
+    if budget is not None:
+        out["budget_sweep"] = budget
     if not args.no_multiview:
         torch.cuda.empty_cache()
         mv = run_multiview_train(args, torch, C, Scene, synth)

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 3
+#define CLOD_ABI_VERSION 4
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -71,7 +71,9 @@ typedef struct clod_view {
   float fx, fy, cx, cy;   /* intrinsics in pixels */
   int32_t width, height;  /* 1..16384 */
   float s_v;              /* virtual distance scale, finite, >= 1 */
-  float reserved[2];
+  int64_t budget;         /* LoD selection: 0 keeps alpha'' > tau * s_v (Sec. 3.2); K > 0 keeps the
+                             K Gaussians of largest alpha'' (lower index first among equal values),
+                             the primitive-budget selection of the Sec. 4 comparisons */
 } clod_view;
 
 /* Constants the paper leaves open (readings; defaults in parentheses). */
@@ -158,8 +160,9 @@ clod_status clod_render_bwd(const clod_scene *scene, const clod_batch *batch, co
 
 /* Sec. 3.2 mask and Sec. 3.3 eta_actual for many views without rendering: counts_dev
    (device int64 [n_views][3]) receives {n_frustum, n_mask, n_rendered} per view, with the
-   same decisions as clod_project.  Uses batch->ws (per-view area only; clod_ws_bytes with
-   n = 0 suffices); batch->dup is not used. */
+   same decisions as clod_project.  Uses the leading part of batch->ws (per-view data and a
+   work list of n entries; a workspace of clod_ws_bytes(n, ...) bytes always suffices, and a
+   shorter one is rejected with CLOD_E_ARG); batch->dup is not used. */
 clod_status clod_lod_count(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
                            void *stream);
 

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class ClodError(RuntimeError):
@@ -47,7 +47,7 @@ class clod_view(ctypes.Structure):
     _fields_ = [("W", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("c", ctypes.c_float * 3),
                 ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("s_v", ctypes.c_float),
-                ("reserved", ctypes.c_float * 2)]
+                ("budget", ctypes.c_int64)]
 
 
 class clod_params(ctypes.Structure):
@@ -146,7 +146,8 @@ def make_grad(planes: dict) -> clod_scene_grad:
 
 
 def make_views(views) -> ctypes.Array:
-    """Host array of clod_view from objects with W, t, c, fx, fy, cx, cy, width, height, s_v."""
+    """Host array of clod_view from objects with W, t, c, fx, fy, cx, cy, width, height, s_v
+    (and optionally budget)."""
     arr = (clod_view * len(views))()
     for j, v in enumerate(views):
         cv = arr[j]
@@ -159,6 +160,7 @@ def make_views(views) -> ctypes.Array:
         cv.fx, cv.fy, cv.cx, cv.cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
         cv.width, cv.height = int(v.width), int(v.height)
         cv.s_v = float(v.s_v)
+        cv.budget = int(getattr(v, "budget", 0))
     return arr
 
 

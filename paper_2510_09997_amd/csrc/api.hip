@@ -86,8 +86,9 @@ static clod_status host_views(int32_t V, const clod_view* vh, HostView* hv, uint
   return CLOD_OK;
 }
 
-static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pixels_total) {
+static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pixels_total, bool any_budget) {
   Layout L;
+  L.any_budget = any_budget;
   L.n = n;
   L.V = V;
   L.VN = n * (int64_t)V;
@@ -104,6 +105,8 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.kpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 8);
   L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 3 * 4);
   L.gpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4);
+  L.sel_state = o; o = align256(o + (size_t)V * sizeof(SelState));
+  L.sel_hist = o; o = align256(o + (L.any_budget ? (size_t)V * kSelBlocks * 256 * 4 : 0));
   L.lcount = o; o = align256(o + (size_t)kMaxProjBlocks * 2 * 4);   // work-list segment counts, offsets
   L.list = o; o = align256(o + (size_t)n * 4);                        // work list of the projection
   L.flags = o; o = align256(o + (size_t)L.VN);
@@ -141,6 +144,7 @@ static clod_status check_view(const clod_view& c, int v) {
   if (!(finite_f(c.fx) && c.fx > 0.f && finite_f(c.fy) && c.fy > 0.f && finite_f(c.cx) && finite_f(c.cy)))
     return fail(CLOD_E_ARG, "view %d: intrinsics must be finite with fx, fy > 0", v);
   if (!(finite_f(c.s_v) && c.s_v >= 1.0f)) return fail(CLOD_E_ARG, "view %d: s_v must be finite and >= 1", v);
+  if (c.budget < 0) return fail(CLOD_E_ARG, "view %d: budget must be >= 0", v);
   double scale = 1.0;
   for (int j = 0; j < 3; ++j) scale = fmax(scale, fabs((double)c.c[j]));
   for (int j = 0; j < 3; ++j) {
@@ -176,9 +180,11 @@ static clod_status prepare(const clod_batch* b, bool need_full_ws, Ctx& cx) {
   const int64_t n = b->n;
   if (n < 0) return fail(CLOD_E_ARG, "batch->n must be >= 0");
   if (n * (int64_t)b->n_views >= 0xFFFFFFFFll) return fail(CLOD_E_ARG, "n * n_views must be < 2^32");
-  cx.L = make_layout(need_full_ws ? n : 0, b->n_views, tiles_total, pixels_total);
-  if (need_full_ws) cx.L.n = n;
-  const size_t need = need_full_ws ? cx.L.total : cx.L.flags;   // per-view area precedes the rest
+  bool any_budget = false;
+  for (int v = 0; v < b->n_views; ++v) any_budget = any_budget || b->views_host[v].budget > 0;
+  cx.L = make_layout(n, b->n_views, tiles_total, pixels_total, any_budget);
+  // The per-view area and the projection work list precede the per-(view, Gaussian) planes.
+  const size_t need = need_full_ws ? cx.L.total : cx.L.flags;
   if (b->ws_bytes < need) return fail(CLOD_E_ARG, "ws_bytes %zu < required %zu", b->ws_bytes, need);
   return CLOD_OK;
 }
@@ -217,7 +223,9 @@ size_t clod_ws_bytes(int64_t n, int32_t n_views, const clod_view* views_host) {
   uint32_t tiles_total, lb;
   int64_t pixels_total;
   if (host_views(n_views, views_host, hv, tiles_total, pixels_total, lb) != CLOD_OK) return 0;
-  return make_layout(n, n_views, tiles_total, pixels_total).total;
+  bool any_budget = false;
+  for (int v = 0; v < n_views; ++v) any_budget = any_budget || views_host[v].budget > 0;
+  return make_layout(n, n_views, tiles_total, pixels_total, any_budget).total;
 }
 
 size_t clod_dup_bytes(int64_t capacity) {
@@ -253,6 +261,10 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
   HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.kpart),
                              (unsigned long long*)(w + L.dmax_key), s),
           "frustum max");
+  if (L.any_budget)
+    HIP_TRY(launch_lod_select(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
+                              (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
+            "budget select");
   HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
                          (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags),
                          (float*)(w + L.alpha), (float*)(w + L.depth), (float4*)(w + L.rec), (uint2*)(w + L.rect),
@@ -353,6 +365,10 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
   HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.kpart),
                              (unsigned long long*)(w + L.dmax_key), s),
           "frustum max");
+  if (L.any_budget)
+    HIP_TRY(launch_lod_select(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
+                              (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
+            "budget select");
   HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
                            (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts),
                            (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), (unsigned long long*)(w + L.hdr), s),

@@ -35,7 +35,16 @@ struct DevView {
   float s_v, limx, limy, tau_sv;
   int32_t width, height, tiles_x, tiles_y;
   uint32_t tile_base, pix_base, loss_block_base, pad0;
+  int64_t budget;                // 0: threshold mask; K > 0: the K largest selection keys
+  unsigned long long mkey;       // K > 0: smallest kept selection key (set by the radix select)
 };
+
+// Radix select of the budgeted mask: per view, the threshold prefix found so far and the rank
+// (1-based, from the largest key) still to find among keys that share it.
+struct SelState {
+  unsigned long long prefix, rank;
+};
+constexpr int kSelBlocks = 128;   // blocks per view of the select histograms
 
 // Workspace header words (uint64).
 enum : int { kHdrDup = 0, kHdrOverflow = 1, kHdrRend = 2, kHdrList = 3, kHdrWords = 8 };
@@ -47,8 +56,9 @@ struct Layout {
   uint32_t tiles_total = 0;   // sum over views of tiles_x * tiles_y
   int64_t pixels_total = 0;
   int32_t scan_blocks = 0;
+  bool any_budget = false;    // some view selects by budget (allocates the select histograms)
   // byte offsets into ws
-  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, lcount, list, flags, alpha, depth, rec,
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, sel_state, sel_hist, lcount, list, flags, alpha, depth, rec,
       rect, tiles, scan_part, ranges, order, tord, pair_part, gscreen, total;
 };
 
@@ -320,6 +330,19 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// LoD selection key of a (view, Gaussian): larger alpha'' first, then lower index (alpha'' >= 0,
+// so its bit pattern is monotone).  Keys are distinct, so keeping the keys >= the K-th largest
+// keeps exactly K Gaussians.
+__device__ __forceinline__ unsigned long long lod_key(float a2, int64_t i) {
+  return ((unsigned long long)__float_as_uint(a2) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+}
+
+// The LoD mask M of a (view, Gaussian): alpha'' > tau s_v (Sec. 3.2), or membership in the view's
+// budget of largest alpha''.
+__device__ __forceinline__ bool lod_kept(const DevView& Vw, float a2, int64_t i) {
+  return Vw.budget > 0 ? lod_key(a2, i) >= Vw.mkey : a2 > Vw.tau_sv;
+}
+
 // ----------------------------------------------------------------------------------------
 // Launchers (each returns hipGetLastError()).
 // ----------------------------------------------------------------------------------------
@@ -338,6 +361,8 @@ hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, c
                             const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s);
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s);
+hipError_t launch_lod_select(const clod_scene& sc, DevView* vinfo, int V, clod_params prm,
+                             const unsigned long long* dmax_key, SelState* state, uint32_t* hist, hipStream_t s);
 
 hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s);
 hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,

@@ -32,6 +32,8 @@ __global__ void k_view_setup(const clod_view* __restrict__ views, int V, clod_pa
     d.pix_base = pix_base;
     d.loss_block_base = loss_base;
     d.pad0 = 0;
+    d.budget = cv.budget;
+    d.mkey = 0ull;
     tile_base += (uint32_t)(d.tiles_x * d.tiles_y);
     pix_base += (uint32_t)(cv.width * cv.height);
     loss_base += (uint32_t)((3u * (uint32_t)(cv.width * cv.height) + kLossChunk - 1) / kLossChunk);
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(
         const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
         float alpha, q;
         const float a2 = attenuated(d, dmax_from_key(dmax_key[v]), Vw.s_v, dc, op, prm.eps, alpha, q);
-        M = a2 > Vw.tau_sv;
+        M = lod_kept(Vw, a2, i);
         if (kWrite) {
           const int64_t f = (int64_t)v * n + i;
           alpha_out[f] = a2;
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_project(
           const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
           float alpha, q;
           const float a2 = attenuated(d, dmax_from_key(dmax_key[v]), Vw.s_v, dc, op, prm.eps, alpha, q);
-          if (F && a2 > Vw.tau_sv) {
+          if (F && lod_kept(Vw, a2, i)) {
             if (!have_cov) {
               const float s0 = cexp(sc.log_scale[i]), s1 = cexp(sc.log_scale[n + i]), s2 = cexp(sc.log_scale[2 * n + i]);
               float Rm[9], w_, x_, y_, z_, rn;
@@ -306,6 +308,90 @@ __global__ __launch_bounds__(kBlock) void k_project(
   }
   __syncthreads();
   for (int j = threadIdx.x; j < V; j += kBlock) cpart[((int64_t)blockIdx.x * V + j) * 3 + 2] = scnt[j];
+}
+
+// Budgeted LoD (a view with budget K, 0 < K < n): the K-th largest selection key, by an MSD
+// radix select over the eight bytes of the 64-bit key.  Pass p histograms byte p (from the top)
+// of the keys that share the prefix found so far (k_select_hist, one histogram per block and
+// view; alpha'' is recomputed from the scene exactly as the projection computes it), then
+// k_select_pick finds the byte value holding the wanted rank and narrows the prefix.  After
+// eight passes the prefix is the threshold key.  K >= n keeps everything (threshold 0).
+__global__ __launch_bounds__(kBlock) void k_select_hist(clod_scene sc, const DevView* __restrict__ views,
+                                                        clod_params prm,
+                                                        const unsigned long long* __restrict__ dmax_key,
+                                                        const SelState* __restrict__ state, int pass,
+                                                        uint32_t* __restrict__ hist /* [V][kSelBlocks][256] */) {
+  __shared__ uint32_t h[256];
+  const int v = blockIdx.y;
+  const DevView& Vw = views[v];
+  const int64_t n = sc.n;
+  if (Vw.budget <= 0 || Vw.budget >= n) return;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int shift = 56 - 8 * pass;
+  const unsigned long long pre = pass == 0 ? 0ull : state[v].prefix >> (shift + 8);
+  const float dmax = dmax_from_key(dmax_key[v]);
+  int64_t lo, hi;
+  block_chunk(n, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    float ex, ey, ez;
+    const float d = cam_distance(Vw, sc.mean[i], sc.mean[n + i], sc.mean[2 * n + i], ex, ey, ez);
+    float alpha, q;
+    const float a2 = attenuated(d, dmax, Vw.s_v, sc.decay[i], sc.opacity[i], prm.eps, alpha, q);
+    const unsigned long long key = lod_key(a2, i);
+    if (pass == 0 || (key >> (shift + 8)) == pre) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[((int64_t)v * kSelBlocks + blockIdx.x) * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_select_pick(DevView* __restrict__ views, int64_t n, int pass,
+                                                        SelState* __restrict__ state,
+                                                        const uint32_t* __restrict__ hist) {
+  __shared__ uint32_t sm[4];
+  const int v = blockIdx.x;
+  DevView& Vw = views[v];
+  if (Vw.budget <= 0) return;
+  if (Vw.budget >= n) {
+    if (threadIdx.x == 0) Vw.mkey = 0ull;
+    return;
+  }
+  const unsigned long long rank = pass == 0 ? (unsigned long long)Vw.budget : state[v].rank;
+  const unsigned long long prefix = pass == 0 ? 0ull : state[v].prefix;
+  // Thread t takes byte value d = 255 - t, so an inclusive scan over t counts the keys whose
+  // byte is >= d.
+  const uint32_t d = 255u - threadIdx.x;
+  uint32_t c = 0;
+  for (int b = 0; b < kSelBlocks; ++b) c += hist[((int64_t)v * kSelBlocks + b) * 256 + d];
+  uint32_t inc = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t up = __shfl_up(inc, o, 64);
+    if (lane_id() >= (uint32_t)o) inc += up;
+  }
+  if (lane_id() == 63) sm[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) inc += sm[w];
+  const uint32_t excl = inc - c;
+  if (excl < rank && rank <= inc) {
+    const int shift = 56 - 8 * pass;
+    const unsigned long long np = prefix | ((unsigned long long)d << shift);
+    state[v].prefix = np;
+    state[v].rank = rank - excl;
+    if (pass == 7) Vw.mkey = np;
+  }
+}
+
+hipError_t launch_lod_select(const clod_scene& sc, DevView* vinfo, int V, clod_params prm,
+                             const unsigned long long* dmax_key, SelState* state, uint32_t* hist, hipStream_t s) {
+  if (sc.n == 0) return hipSuccess;
+  for (int pass = 0; pass < 8; ++pass) {
+    hipLaunchKernelGGL(k_select_hist, dim3(kSelBlocks, V), dim3(kBlock), 0, s, sc, (const DevView*)vinfo, prm,
+                       dmax_key, (const SelState*)state, pass, hist);
+    hipLaunchKernelGGL(k_select_pick, dim3(V), dim3(kBlock), 0, s, vinfo, sc.n, pass, state,
+                       (const uint32_t*)hist);
+  }
+  return hipGetLastError();
 }
 
 // Block v folds the G partials of view v: the frustum-max key (max) and the counts (sum).

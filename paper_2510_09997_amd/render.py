@@ -94,6 +94,9 @@ class Batch:
         self.views = list(views)
         self.views_host = C.make_views(self.views)
         self.views_dev.copy_(C.views_to_device(self.views_host, self.device))
+        need = C.clod_ws_bytes(self.n, self.views_host)   # a budget view needs select histograms
+        if need > self.ws.numel():
+            self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
 
     def split(self, flat: torch.Tensor, channels: int):
         out = []

@@ -72,7 +72,8 @@ class View:
     """A pinhole camera (OpenCV axes: x right, y down, z forward) plus its LoD scale.
 
     ``W`` is the row-major world-to-camera rotation, ``t`` the translation, ``c`` the camera
-    centre; a pixel (i, j) covers [i, i+1) x [j, j+1).  ``s_v`` is the virtual distance scale.
+    centre; a pixel (i, j) covers [i, i+1) x [j, j+1).  ``s_v`` is the virtual distance scale;
+    ``budget`` selects the LoD rule (0: alpha'' > tau s_v; K > 0: the K largest alpha'').
     """
     W: np.ndarray
     t: np.ndarray
@@ -84,6 +85,7 @@ class View:
     width: int
     height: int
     s_v: float = 1.0
+    budget: int = 0   # 0: threshold mask; K > 0: keep the K largest alpha''
 
 
 def look_at(pos, target=(0.0, 0.0, 0.0), width=256, height=256, fov_deg=60.0, s_v=1.0) -> View:
