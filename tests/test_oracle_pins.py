@@ -534,3 +534,46 @@ def test_budget_masks_nest_as_the_budget_grows():
         if prev is not None:
             assert np.all(kept[prev])
         prev = kept
+
+
+# ---------------------------------------------------------------------------------------
+# Optimiser step (Sec. 4.1: 3DGS Adam recipe with the decay factor as one more parameter).
+# ---------------------------------------------------------------------------------------
+
+def test_adam_binary32_matches_textbook_fp64_within_rounding():
+    from oracle import train_oracle as TO
+    rng = np.random.default_rng(40)
+    n = 20000
+    p = rng.normal(size=n).astype(np.float32)
+    m = np.zeros(n, np.float32)
+    v = np.zeros(n, np.float32)
+    p64, m64, v64 = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    S = np.zeros(n)   # running sum of the magnitudes of the terms of m (its rounding scale)
+    for t in range(1, 6):
+        g = (rng.normal(size=n) * 10.0 ** rng.uniform(-6, 1, size=n)).astype(np.float32)
+        p, m, v = TO.adam_step32(p, g, m, v, 1e-2, t)
+        p64, m64, v64 = TO.adam_step64(p64, g, m64, v64, 1e-2, t)
+        S = 0.9 * S + 0.1 * np.abs(g.astype(np.float64))
+        # Each step moves p by at most lr (|m_hat| <= sqrt(v_hat)); binary32 adds a few ulps.
+        assert np.max(np.abs(p - p64)) <= 1e-6 * t
+        assert np.all(np.abs(m - m64) <= 2.0 ** -21 * t * S)
+        assert np.all(np.abs(v - v64) <= 2.0 ** -20 * t * v64 + 1e-45)
+
+
+def test_adam_first_step_is_lr_times_sign_and_zero_gradient_is_a_no_op():
+    from oracle import train_oracle as TO
+    g = np.array([3.0, -0.5, 1e-3, -2e-6, 0.0], np.float32)
+    p = np.ones(5, np.float32)
+    z = np.zeros(5, np.float32)
+    p1, m1, v1 = TO.adam_step32(p, g, z, z, 0.01, 1)
+    # t = 1: m_hat = g and v_hat = g^2, so the step is lr * g / (|g| + eps).
+    want = 1.0 - 0.01 * g.astype(np.float64) / (np.abs(g.astype(np.float64)) + 1e-15)
+    assert np.allclose(p1, want, rtol=0, atol=2e-7)
+    assert p1[4] == 1.0 and m1[4] == 0.0 and v1[4] == 0.0
+
+
+def test_position_lr_schedule_endpoints_and_log_linearity():
+    from oracle import train_oracle as TO
+    assert math.isclose(TO.position_lr(0), 1.6e-4, rel_tol=1e-12)
+    assert math.isclose(TO.position_lr(30000), 1.6e-6, rel_tol=1e-12)
+    assert math.isclose(TO.position_lr(15000), math.sqrt(1.6e-4 * 1.6e-6), rel_tol=1e-12)
