@@ -12,8 +12,10 @@ Adam (Kingma and Ba, 2015) per element, step t = 1, 2, ...:
     p <- p - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 
 `adam_step32` evaluates it in IEEE binary32 in this exact operation order (each numpy float32
-operation is one correctly rounded binary32 operation, no fused multiply-add):
-    c1 = fl(1 - b1), c2 = fl(1 - b2), bc1 = fl(1 - b1^t), bc2 = fl(1 - b2^t)   (from float64)
+operation is one correctly rounded binary32 operation, no fused multiply-add); b1, b2, lr and
+eps are the binary32 roundings of the hyperparameters:
+    c1 = 1 - b1, c2 = 1 - b2 (binary32);  bc1 = fl(1 - b1^t), bc2 = fl(1 - b2^t) (from the
+    float64 hyperparameters, rounded once)
     m' = b1*m + c1*g;  v' = b2*v + c2*(g*g);  mh = m'/bc1;  vh = v'/bc2;
     p' = p - lr*(mh/(sqrt(vh) + eps)).
 `adam_step64` is the textbook update in float64, the pin for the binary32 version.
@@ -38,7 +40,7 @@ def adam_step32(p, g, m, v, lr: float, t: int, b1: float = 0.9, b2: float = 0.99
     """One binary32 Adam step on float32 arrays; returns (p', m', v')."""
     p, g, m, v = (np.asarray(a, dtype=F32) for a in (p, g, m, v))
     b1f, b2f, lrf, epsf = F32(b1), F32(b2), F32(lr), F32(eps)
-    c1, c2 = F32(1.0 - b1), F32(1.0 - b2)
+    c1, c2 = F32(1.0) - b1f, F32(1.0) - b2f
     bc1, bc2 = bias_corrections(t, b1, b2)
     m2 = b1f * m + c1 * g
     v2 = b2f * v + c2 * (g * g)
