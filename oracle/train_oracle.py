@@ -14,8 +14,8 @@ Adam (Kingma and Ba, 2015) per element, step t = 1, 2, ...:
 `adam_step32` evaluates it in IEEE binary32 in this exact operation order (each numpy float32
 operation is one correctly rounded binary32 operation, no fused multiply-add); b1, b2, lr and
 eps are the binary32 roundings of the hyperparameters:
-    c1 = 1 - b1, c2 = 1 - b2 (binary32);  bc1 = fl(1 - b1^t), bc2 = fl(1 - b2^t) (from the
-    float64 hyperparameters, rounded once)
+    c1 = 1 - b1, c2 = 1 - b2 (binary32);  bc1 = fl(1 - b1^t), bc2 = fl(1 - b2^t) (evaluated in
+    float64 from the binary32 b1, b2, rounded once)
     m' = b1*m + c1*g;  v' = b2*v + c2*(g*g);  mh = m'/bc1;  vh = v'/bc2;
     p' = p - lr*(mh/(sqrt(vh) + eps)).
 `adam_step64` is the textbook update in float64, the pin for the binary32 version.
@@ -33,7 +33,8 @@ GROUPS = ("mean", "log_scale", "quat", "opacity", "decay", "sh_dc", "sh_rest")
 
 
 def bias_corrections(t: int, b1: float, b2: float):
-    return F32(1.0 - b1 ** t), F32(1.0 - b2 ** t)
+    b1d, b2d = float(F32(b1)), float(F32(b2))
+    return F32(1.0 - b1d ** t), F32(1.0 - b2d ** t)
 
 
 def adam_step32(p, g, m, v, lr: float, t: int, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-15):

@@ -552,7 +552,9 @@ def test_adam_binary32_matches_textbook_fp64_within_rounding():
     for t in range(1, 6):
         g = (rng.normal(size=n) * 10.0 ** rng.uniform(-6, 1, size=n)).astype(np.float32)
         p, m, v = TO.adam_step32(p, g, m, v, 1e-2, t)
-        p64, m64, v64 = TO.adam_step64(p64, g, m64, v64, 1e-2, t)
+        # The textbook update with the binary32 hyperparameters the binary32 step uses.
+        f = lambda x: float(np.float32(x))
+        p64, m64, v64 = TO.adam_step64(p64, g, m64, v64, f(1e-2), t, b1=f(0.9), b2=f(0.999), eps=f(1e-15))
         S = 0.9 * S + 0.1 * np.abs(g.astype(np.float64))
         # Each step moves p by at most lr (|m_hat| <= sqrt(v_hat)); binary32 adds a few ulps.
         assert np.max(np.abs(p - p64)) <= 1e-6 * t
