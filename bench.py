@@ -264,9 +264,27 @@ def run_multiview_train(args, torch, C, Scene, synth):
     torch.cuda.synchronize()
     per = [evs[k].elapsed_time(evs[k + 1]) for k in range(K)]
     assert not tr.overflowed(), "duplicate buffer overflow inside the timed region"
+    # Fused Adam over all 2M x 60 parameters (one launch per step, outside the graph since its
+    # learning rates and bias corrections change every step).
+    from paper_2510_09997_amd.train import DEFAULT_LRS, FusedAdam
+    opt = FusedAdam(scene)
+    for _ in range(3):
+        opt.step(tr.grads, DEFAULT_LRS)
+    torch.cuda.synchronize()
+    reps = 20
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record()
+    for _ in range(reps):
+        opt.step(tr.grads, DEFAULT_LRS)
+    a1.record()
+    torch.cuda.synchronize()
+    adam_ms = a0.elapsed_time(a1) / reps
+    nparam = sum(v.numel() for v in scene.t.values())
+    adam_bytes = 28 * nparam   # read parameter, gradient, m, v; write parameter, m, v
     return dict(ms_per_step=float(np.mean(per)), p50_ms=float(np.percentile(per, 50)),
                 p99_ms=float(np.percentile(per, 99)), views=16, gaussians=n, max_dup=dmax,
-                pixels_per_step=tr.batch.pixels)
+                pixels_per_step=tr.batch.pixels, adam_ms=adam_ms, adam_params=nparam,
+                adam_hbm_frac=adam_bytes / (adam_ms * 1e-3) / 8e12)
 
 
 def run_budget_sweep(args, torch, C, Batch, scene, pose):

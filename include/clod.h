@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 4
+#define CLOD_ABI_VERSION 5
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -175,6 +175,26 @@ clod_status clod_lod_count(const clod_scene *scene, const clod_batch *batch, int
 clod_status clod_loss(const clod_batch *batch, const float *rgb, const float *target,
                       float s_max, float lambda_reg, float *loss_dev, float *dL_drgb,
                       float *dL_deta_dev, void *stream);
+
+/* Hyperparameters of one Adam step (binary32). */
+typedef struct clod_adam {
+  float lr[7];            /* learning rates of the groups mean, log_scale, quat, opacity, decay,
+                             SH degree 0 (sh[0 .. 3n)), SH degree >= 1 (sh[3n ..)); >= 0 */
+  float beta1, beta2;     /* in [0, 1) */
+  float eps;              /* > 0 */
+  float bias1, bias2;     /* 1 - beta1^t and 1 - beta2^t of step t >= 1, in (0, 1] */
+} clod_adam;
+
+/* Sec. 4.1 (training follows the 3DGS recipe, with sigma_d as one more per-Gaussian parameter
+   and its own learning rate): one fused Adam step over every parameter plane of a scene of n
+   Gaussians of SH degree sh_degree.  param, grad, m and v are device planes in the clod_scene
+   layout (grad is only read; param, m and v are updated in place; all non-NULL when n > 0).
+   Per element, in binary32 and this order: m = beta1*m + (1-beta1)*g;
+   v = beta2*v + (1-beta2)*(g*g); p = p - lr*((m/bias1) / (sqrt(v/bias2) + eps)).
+   Asynchronous on `stream`. */
+clod_status clod_adam_step(int64_t n, int32_t sh_degree, const clod_scene_grad *param,
+                           const clod_scene_grad *grad, const clod_scene_grad *m,
+                           const clod_scene_grad *v, const clod_adam *hp, void *stream);
 
 /* Synchronises `stream` and copies to host info[4] = {D (tile pairs of the last
    clod_bin_sort), overflow flag, duplicate capacity, radix passes}. */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class ClodError(RuntimeError):
@@ -50,6 +50,11 @@ class clod_view(ctypes.Structure):
                 ("budget", ctypes.c_int64)]
 
 
+class clod_adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 7), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("bias1", ctypes.c_float), ("bias2", ctypes.c_float)]
+
+
 class clod_params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_float), ("eps", ctypes.c_float), ("near_z", ctypes.c_float),
                 ("guard", ctypes.c_float), ("dilation", ctypes.c_float), ("bg", ctypes.c_float * 3)]
@@ -65,7 +70,7 @@ assert ctypes.sizeof(clod_view) == 96
 
 EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project", "clod_bin_sort",
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
-           "clod_inspect", "clod_last_error", "clod_abi_version"]
+           "clod_inspect", "clod_last_error", "clod_abi_version", "clod_adam_step"]
 
 (SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC, SEC_ALPHA, SEC_DEPTH, SEC_FLAGS, SEC_DMAX, SEC_RECT, SEC_GSCREEN,
  SEC_HEADER) = range(11)
@@ -93,6 +98,7 @@ def load(path: str = LIB_PATH):
     L.clod_lod_count.argtypes = [P, P, P, P]; L.clod_lod_count.restype = i32
     L.clod_loss.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, P, P, P, P]; L.clod_loss.restype = i32
     L.clod_read_info.argtypes = [P, P, P]; L.clod_read_info.restype = i32
+    L.clod_adam_step.argtypes = [i64, i32, P, P, P, P, P, P]; L.clod_adam_step.restype = i32
     L.clod_inspect.argtypes = [P, i32, P, P]; L.clod_inspect.restype = i32
     L.clod_last_error.argtypes = []; L.clod_last_error.restype = ctypes.c_char_p
     L.clod_abi_version.argtypes = []; L.clod_abi_version.restype = i32
@@ -215,6 +221,29 @@ def clod_render_bwd(scene: clod_scene, batch: clod_batch, T, last, dL_drgb, dL_d
 
 def clod_lod_count(scene: clod_scene, batch: clod_batch, counts, stream=None):
     _check(load().clod_lod_count(ctypes.byref(scene), ctypes.byref(batch), _ptr(counts), _stream(stream)))
+
+
+ADAM_GROUPS = ("mean", "log_scale", "quat", "opacity", "decay", "sh_dc", "sh_rest")
+
+
+def make_adam(lrs: dict, t: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15) -> clod_adam:
+    """Hyperparameters of step t >= 1: binary32 roundings of beta1, beta2, eps and the group
+    learning rates; the bias corrections 1 - beta^t evaluated in float64 from the binary32
+    betas and rounded once."""
+    hp = clod_adam()
+    for j, k in enumerate(ADAM_GROUPS):
+        hp.lr[j] = float(lrs[k])
+    b1, b2 = float(np.float32(beta1)), float(np.float32(beta2))
+    hp.beta1, hp.beta2, hp.eps = b1, b2, float(eps)
+    hp.bias1 = float(np.float32(1.0 - b1 ** t))
+    hp.bias2 = float(np.float32(1.0 - b2 ** t))
+    return hp
+
+
+def clod_adam_step(n: int, sh_degree: int, param: clod_scene_grad, grad: clod_scene_grad, m: clod_scene_grad,
+                   v: clod_scene_grad, hp: clod_adam, stream=None):
+    _check(load().clod_adam_step(int(n), int(sh_degree), ctypes.byref(param), ctypes.byref(grad), ctypes.byref(m),
+                                 ctypes.byref(v), ctypes.byref(hp), _stream(stream)))
 
 
 def clod_loss(batch: clod_batch, rgb, target, s_max: float, lambda_reg: float, loss, dL_drgb, dL_deta,

@@ -395,6 +395,46 @@ clod_status clod_loss(const clod_batch* batch, const float* rgb, const float* ta
   return CLOD_OK;
 }
 
+clod_status clod_adam_step(int64_t n, int32_t sh_degree, const clod_scene_grad* param,
+                           const clod_scene_grad* grad, const clod_scene_grad* m,
+                           const clod_scene_grad* v, const clod_adam* hp, void* stream) {
+  g_err[0] = 0;
+  if (n < 0) return fail(CLOD_E_ARG, "n must be >= 0");
+  if (sh_degree < 0 || sh_degree > 3) return fail(CLOD_E_ARG, "sh_degree must be in 0..3");
+  if (!param || !grad || !m || !v || !hp) return fail(CLOD_E_ARG, "param, grad, m, v and hp must be non-NULL");
+  for (int j = 0; j < kAdamGroups; ++j)
+    if (!(finite_f(hp->lr[j]) && hp->lr[j] >= 0.f)) return fail(CLOD_E_ARG, "hp->lr[%d] must be finite and >= 0", j);
+  if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f))
+    return fail(CLOD_E_ARG, "betas must be in [0, 1)");
+  if (!(finite_f(hp->eps) && hp->eps > 0.f)) return fail(CLOD_E_ARG, "eps must be finite and > 0");
+  if (!(hp->bias1 > 0.f && hp->bias1 <= 1.f && hp->bias2 > 0.f && hp->bias2 <= 1.f))
+    return fail(CLOD_E_ARG, "bias corrections must be in (0, 1]");
+  if (n == 0) return CLOD_OK;
+  const clod_scene_grad* planes[4] = {param, grad, m, v};
+  for (const clod_scene_grad* q : planes)
+    if (!q->mean || !q->log_scale || !q->quat || !q->opacity || !q->decay || !q->sh)
+      return fail(CLOD_E_ARG, "every parameter plane must be non-NULL");
+  const int64_t K = (int64_t)(sh_degree + 1) * (sh_degree + 1);
+  AdamSegs S;
+  auto seg = [&](int j, float* (clod_scene_grad::*f), int64_t off, int64_t count) {
+    S.s[j].p = param->*f + off;
+    S.s[j].g = grad->*f + off;
+    S.s[j].m = m->*f + off;
+    S.s[j].v = v->*f + off;
+    S.s[j].count = count;
+    S.s[j].lr = hp->lr[j];
+  };
+  seg(0, &clod_scene_grad::mean, 0, 3 * n);
+  seg(1, &clod_scene_grad::log_scale, 0, 3 * n);
+  seg(2, &clod_scene_grad::quat, 0, 4 * n);
+  seg(3, &clod_scene_grad::opacity, 0, n);
+  seg(4, &clod_scene_grad::decay, 0, n);
+  seg(5, &clod_scene_grad::sh, 0, 3 * n);
+  seg(6, &clod_scene_grad::sh, 3 * n, 3 * (K - 1) * n);
+  HIP_TRY(launch_adam(S, hp->beta1, hp->beta2, hp->eps, hp->bias1, hp->bias2, (hipStream_t)stream), "adam");
+  return CLOD_OK;
+}
+
 clod_status clod_read_info(const clod_batch* batch, int64_t* info_host, void* stream) {
   g_err[0] = 0;
   Ctx cx;

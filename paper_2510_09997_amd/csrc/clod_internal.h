@@ -361,6 +361,21 @@ hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, c
                             const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s);
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s);
+
+// Fused Adam: one segment per learning-rate group.
+constexpr int kAdamGroups = 7;
+struct AdamSeg {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t count;
+  float lr;
+};
+struct AdamSegs {
+  AdamSeg s[kAdamGroups];
+};
+hipError_t launch_adam(const AdamSegs& segs, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t launch_lod_select(const clod_scene& sc, DevView* vinfo, int V, clod_params prm,
                              const unsigned long long* dmax_key, SelState* state, uint32_t* hist, hipStream_t s);
 

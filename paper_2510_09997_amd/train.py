@@ -115,3 +115,76 @@ class MultiViewTrainer:
 
     def total_loss(self) -> float:
         return float(self.loss.sum().item())
+
+
+# ---------------------------------------------------------------------------------------------
+# Optimiser and schedule (Sec. 4.1)
+# ---------------------------------------------------------------------------------------------
+
+# 3DGS learning rates per parameter group; sigma_d uses 1e-2 (Sec. 4.1).  The position rate
+# decays log-linearly over training (position_lr); SH degrees >= 1 use 1/20 of the DC rate.
+DEFAULT_LRS = dict(mean=1.6e-4, log_scale=5e-3, quat=1e-3, opacity=2.5e-2, decay=1e-2, sh_dc=2.5e-3,
+                   sh_rest=2.5e-3 / 20.0)
+
+
+def position_lr(step: int, lr_init: float = 1.6e-4, lr_final: float = 1.6e-6, max_steps: int = 30000,
+                extent: float = 1.0) -> float:
+    t = min(max(step / max_steps, 0.0), 1.0)
+    return float(np.exp(np.log(lr_init * extent) * (1 - t) + np.log(lr_final * extent) * t))
+
+
+class FusedAdam:
+    """Adam over every per-Gaussian parameter plane of a Scene in one launch (clod_adam_step):
+    first and second moments in HBM beside the parameters, one read and one write per element."""
+
+    def __init__(self, scene: Scene, betas=(0.9, 0.999), eps: float = 1e-15):
+        self.scene = scene
+        self.m = {k: torch.zeros_like(v) for k, v in scene.t.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in scene.t.items()}
+        self.betas = betas
+        self.eps = eps
+        self.t = 0
+        self._p = C.make_grad(scene.t)
+        self._m = C.make_grad(self.m)
+        self._v = C.make_grad(self.v)
+
+    def step(self, grads: dict, lrs: dict, stream=None):
+        self.t += 1
+        hp = C.make_adam(lrs, self.t, self.betas[0], self.betas[1], self.eps)
+        C.clod_adam_step(self.scene.n, self.scene.sh_degree, self._p, C.make_grad(grads), self._m, self._v, hp,
+                         stream)
+
+
+class LodSchedule:
+    """Per-iteration training settings (Sec. 3.3 and Sec. 4.1): before `enable_at` the LoD
+    mechanism is off (s_v = 1, no regulariser, sigma_d frozen); from then on every view draws
+    its virtual distance scale from U(1, s_max) (log-uniform if law == "log") and the
+    regulariser weight is lambda_reg.  The position learning rate decays over `total` steps."""
+
+    def __init__(self, s_max: float, enable_at: int = 5000, total: int = 30000, lambda_reg: float = 1.0,
+                 law: str = "uniform", lrs: dict | None = None, seed: int = 0):
+        if law not in ("uniform", "log"):
+            raise ValueError(law)
+        self.s_max, self.enable_at, self.total, self.lambda_reg, self.law = s_max, enable_at, total, lambda_reg, law
+        self.lrs = dict(DEFAULT_LRS if lrs is None else lrs)
+        self.rng = np.random.default_rng(seed)
+
+    def active(self, it: int) -> bool:
+        return it >= self.enable_at
+
+    def sample_sv(self, it: int, k: int) -> np.ndarray:
+        if not self.active(it):
+            return np.ones(k)
+        if self.law == "uniform":
+            return self.rng.uniform(1.0, self.s_max, size=k)
+        return np.exp(self.rng.uniform(0.0, np.log(self.s_max), size=k))
+
+    def lambda_at(self, it: int) -> float:
+        return self.lambda_reg if self.active(it) else 0.0
+
+    def lrs_at(self, it: int) -> dict:
+        lr = dict(self.lrs)
+        lr["mean"] = position_lr(it, lr_init=self.lrs["mean"], lr_final=self.lrs["mean"] / 100.0, max_steps=self.total)
+        if not self.active(it):
+            lr["decay"] = 0.0
+        return lr

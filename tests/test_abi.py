@@ -149,3 +149,41 @@ def test_other_entry_points_validate_arguments():
     # Unknown inspection section.
     p, c = ctypes.c_void_p(0), ctypes.c_int64(0)
     assert lib.clod_inspect(ctypes.byref(ok_batch), 99, ctypes.byref(p), ctypes.byref(c)) == C.CLOD_E_ARG
+
+
+def _fake_planes():
+    g = C.clod_scene_grad()
+    for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh"):
+        setattr(g, k, FAKE)
+    return g
+
+
+@pytest.mark.parametrize("case", ["n_negative", "degree_4", "null_hp", "lr_negative", "lr_nan", "beta_one",
+                                  "eps_zero", "bias_zero", "null_plane"])
+def test_adam_step_rejects_invalid_arguments_before_launch(case):
+    lib = C.load()
+    p, g, m, v = (_fake_planes() for _ in range(4))
+    hp = C.make_adam({k: 1e-3 for k in C.ADAM_GROUPS}, t=1)
+    n, deg = 10, 3
+    if case == "n_negative":
+        n = -1
+    elif case == "degree_4":
+        deg = 4
+    elif case == "lr_negative":
+        hp.lr[3] = -1.0
+    elif case == "lr_nan":
+        hp.lr[0] = float("nan")
+    elif case == "beta_one":
+        hp.beta2 = 1.0
+    elif case == "eps_zero":
+        hp.eps = 0.0
+    elif case == "bias_zero":
+        hp.bias1 = 0.0
+    elif case == "null_plane":
+        m.sh = None
+    hp_ref = None if case == "null_hp" else ctypes.byref(hp)
+    st = lib.clod_adam_step(n, deg, ctypes.byref(p), ctypes.byref(g), ctypes.byref(m), ctypes.byref(v), hp_ref, None)
+    assert st == C.CLOD_E_ARG, (case, st)
+    # n = 0 is a valid no-op (nothing launched).
+    assert lib.clod_adam_step(0, 3, ctypes.byref(p), ctypes.byref(g), ctypes.byref(m), ctypes.byref(v),
+                              ctypes.byref(C.make_adam({k: 1e-3 for k in C.ADAM_GROUPS}, t=1)), None) == C.CLOD_OK
