@@ -579,3 +579,46 @@ def test_position_lr_schedule_endpoints_and_log_linearity():
     assert math.isclose(TO.position_lr(0), 1.6e-4, rel_tol=1e-12)
     assert math.isclose(TO.position_lr(30000), 1.6e-6, rel_tol=1e-12)
     assert math.isclose(TO.position_lr(15000), math.sqrt(1.6e-4 * 1.6e-6), rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------------------------------
+# D-SSIM part of L_render (Eq. (5): the 3DGS weighted sum of L1 and D-SSIM).
+# ---------------------------------------------------------------------------------------
+
+def test_ssim_two_implementations_agree():
+    from oracle import ssim_oracle as SO
+    rng = np.random.default_rng(60)
+    x = rng.uniform(size=(3, 37, 29))
+    y = np.clip(x + rng.normal(scale=0.1, size=x.shape), 0, 1)
+    a = SO.ssim64(x, y)
+    b = 1.0 - float(SO.dssim_torch64(torch.from_numpy(x), torch.from_numpy(y)))
+    assert abs(a - b) < 1e-12
+
+
+def test_ssim_identical_images_is_one_and_constant_images_closed_form():
+    from oracle import ssim_oracle as SO
+    rng = np.random.default_rng(61)
+    x = rng.uniform(size=(3, 24, 30))
+    assert np.allclose(SO.ssim_map64(x, x), 1.0, atol=1e-12)
+    # Constant images a and b: away from the zero padding every variance vanishes and
+    # S = (2ab + C1) / (a^2 + b^2 + C1).
+    a, b = 0.7, 0.2
+    m = SO.ssim_map64(np.full((1, 30, 30), a), np.full((1, 30, 30), b))
+    want = (2 * a * b + SO.C1) / (a * a + b * b + SO.C1)
+    assert np.allclose(m[0, 5:-5, 5:-5], want, rtol=1e-12)
+    assert abs(SO.window1d().sum() - 1.0) < 1e-15 and np.allclose(SO.window1d(), SO.window1d()[::-1])
+
+
+def test_render_loss_gradient_matches_central_differences():
+    from oracle import ssim_oracle as SO
+    rng = np.random.default_rng(62)
+    x = rng.uniform(0.1, 0.9, size=(3, 14, 17))
+    y = rng.uniform(size=x.shape)
+    _, g = SO.render_loss64(x, y)
+    h = 1e-6
+    for idx in [(0, 0, 0), (1, 7, 8), (2, 13, 16), (0, 3, 12), (2, 9, 1)]:
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (SO.render_loss64(xp, y)[0] - SO.render_loss64(xm, y)[0]) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-7 * max(1.0, abs(fd)), idx
