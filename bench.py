@@ -264,6 +264,18 @@ def run_multiview_train(args, torch, C, Scene, synth):
     torch.cuda.synchronize()
     per = [evs[k].elapsed_time(evs[k + 1]) for k in range(K)]
     assert not tr.overflowed(), "duplicate buffer overflow inside the timed region"
+    # The same step with the full 3DGS rendering loss (0.8 L1 + 0.2 D-SSIM), re-captured.
+    tr.lambda_dssim = 0.2
+    tr.capture()
+    torch.cuda.synchronize()
+    d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    d0.record()
+    for k in range(K):
+        tr.set_views_dev(tables[W + k])
+        tr.step()
+    d1.record()
+    torch.cuda.synchronize()
+    dssim_ms = d0.elapsed_time(d1) / K
     # Fused Adam over all 2M x 60 parameters (one launch per step, outside the graph since its
     # learning rates and bias corrections change every step).
     from paper_2510_09997_amd.train import DEFAULT_LRS, FusedAdam
@@ -283,7 +295,7 @@ def run_multiview_train(args, torch, C, Scene, synth):
     adam_bytes = 28 * nparam   # read parameter, gradient, m, v; write parameter, m, v
     return dict(ms_per_step=float(np.mean(per)), p50_ms=float(np.percentile(per, 50)),
                 p99_ms=float(np.percentile(per, 99)), views=16, gaussians=n, max_dup=dmax,
-                pixels_per_step=tr.batch.pixels, adam_ms=adam_ms, adam_params=nparam,
+                pixels_per_step=tr.batch.pixels, ms_per_step_with_dssim=dssim_ms, adam_ms=adam_ms, adam_params=nparam,
                 adam_hbm_frac=adam_bytes / (adam_ms * 1e-3) / 8e12)
 
 

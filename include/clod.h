@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 5
+#define CLOD_ABI_VERSION 6
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -166,14 +166,23 @@ clod_status clod_render_bwd(const clod_scene *scene, const clod_batch *batch, co
 clod_status clod_lod_count(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
                            void *stream);
 
-/* Sec. 3.3, Eq. (3)-(5) with L_render = L1: per view v,
-   L1_v = mean |rgb - target| over 3 H W, eta_v = n_mask / batch->n (from the last clod_project),
-   eta_target = s_v^-1.5, L_reg = (s_v - 1)^2 ReLU(eta_v - eta_target)^2,
-   w_s = (1 - 0.5 s_v / s_max)^2, L_v = w_s (L1_v + lambda L_reg).
-   Writes loss_dev (device float [n_views]), dL_drgb = w_s sign(rgb - target) / (3 H W)
-   (sign(0) = 0) and dL_deta_dev (device float [n_views]) = w_s lambda dL_reg/deta. */
+/* Sec. 3.3, Eq. (3)-(5), with L_render the 3DGS rendering loss, a weighted sum of L1 and
+   D-SSIM: per view v,
+     L1_v = mean |rgb - target| over 3 H W,
+     SSIM_v = mean over pixels and channels of the SSIM map (11 x 11 Gaussian window, sigma 1.5,
+              zero padding, C1 = 0.01^2, C2 = 0.03^2),
+     L_render = (1 - lambda_dssim) L1_v + lambda_dssim (1 - SSIM_v),
+     eta_v = n_mask / batch->n (from the last clod_project), eta_target = s_v^-1.5,
+     L_reg = (s_v - 1)^2 ReLU(eta_v - eta_target)^2, w_s = (1 - 0.5 s_v / s_max)^2,
+     L_v = w_s (L_render + lambda_reg L_reg).
+   Writes loss_dev (device float [n_views]), dL_drgb (the gradient of L_v with respect to the
+   view's rgb; sign(0) = 0) and dL_deta_dev (device float [n_views], nullable) = w_s lambda_reg
+   dL_reg/deta.  lambda_dssim in [0, 1]; when it is > 0, ssim_scratch is a device buffer of at
+   least 36 bytes per pixel of the batch (per-pixel SSIM derivatives); with 0 it may be NULL and
+   L_render = L1. */
 clod_status clod_loss(const clod_batch *batch, const float *rgb, const float *target,
-                      float s_max, float lambda_reg, float *loss_dev, float *dL_drgb,
+                      float s_max, float lambda_reg, float lambda_dssim, float *ssim_scratch,
+                      size_t ssim_scratch_bytes, float *loss_dev, float *dL_drgb,
                       float *dL_deta_dev, void *stream);
 
 /* Hyperparameters of one Adam step (binary32). */

@@ -80,4 +80,4 @@ def render_loss64(x: np.ndarray, y: np.ndarray, lambda_dssim: float = LAMBDA_DSS
     l1 = (xt - yt).abs().mean()
     loss = (1.0 - lambda_dssim) * l1 + lambda_dssim * dssim_torch64(xt, yt)
     loss.backward()
-    return float(loss), xt.grad.numpy()
+    return float(loss.detach()), xt.grad.numpy()

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class ClodError(RuntimeError):
@@ -96,7 +96,8 @@ def load(path: str = LIB_PATH):
     L.clod_render_fwd.argtypes = [P, P, P, P, P, P]; L.clod_render_fwd.restype = i32
     L.clod_render_bwd.argtypes = [P, P, P, P, P, P, i32, P, P]; L.clod_render_bwd.restype = i32
     L.clod_lod_count.argtypes = [P, P, P, P]; L.clod_lod_count.restype = i32
-    L.clod_loss.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, P, P, P, P]; L.clod_loss.restype = i32
+    L.clod_loss.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, sz, P, P, P, P]
+    L.clod_loss.restype = i32
     L.clod_read_info.argtypes = [P, P, P]; L.clod_read_info.restype = i32
     L.clod_adam_step.argtypes = [i64, i32, P, P, P, P, P, P]; L.clod_adam_step.restype = i32
     L.clod_inspect.argtypes = [P, i32, P, P]; L.clod_inspect.restype = i32
@@ -247,9 +248,11 @@ def clod_adam_step(n: int, sh_degree: int, param: clod_scene_grad, grad: clod_sc
 
 
 def clod_loss(batch: clod_batch, rgb, target, s_max: float, lambda_reg: float, loss, dL_drgb, dL_deta,
-              stream=None):
+              stream=None, lambda_dssim: float = 0.0, ssim_scratch=None):
+    nbytes = 0 if ssim_scratch is None else ssim_scratch.numel() * ssim_scratch.element_size()
     _check(load().clod_loss(ctypes.byref(batch), _ptr(rgb), _ptr(target), float(s_max), float(lambda_reg),
-                            _ptr(loss), _ptr(dL_drgb), _ptr(dL_deta), _stream(stream)))
+                            float(lambda_dssim), _ptr(ssim_scratch), nbytes, _ptr(loss), _ptr(dL_drgb),
+                            _ptr(dL_deta), _stream(stream)))
 
 
 def clod_read_info(batch: clod_batch, stream=None) -> dict:

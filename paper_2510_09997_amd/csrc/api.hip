@@ -102,6 +102,7 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.counts = o; o = align256(o + (size_t)V * 3 * 8);
   L.gdmax = o; o = align256(o + (size_t)V * 4);
   L.loss_acc = o; o = align256(o + (size_t)V * 4);
+  L.ssim_acc = o; o = align256(o + (size_t)V * 4);
   L.kpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 8);
   L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 3 * 4);
   L.gpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4);
@@ -378,8 +379,8 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
 }
 
 clod_status clod_loss(const clod_batch* batch, const float* rgb, const float* target, float s_max,
-                      float lambda_reg, float* loss_dev, float* dL_drgb, float* dL_deta_dev,
-                      void* stream) {
+                      float lambda_reg, float lambda_dssim, float* ssim_scratch, size_t ssim_scratch_bytes,
+                      float* loss_dev, float* dL_drgb, float* dL_deta_dev, void* stream) {
   g_err[0] = 0;
   Ctx cx;
   clod_status st = prepare(batch, true, cx);
@@ -387,10 +388,17 @@ clod_status clod_loss(const clod_batch* batch, const float* rgb, const float* ta
   if (!rgb || !target || !loss_dev || !dL_drgb) return fail(CLOD_E_ARG, "rgb, target, loss and dL_drgb must be non-NULL");
   if (!(finite_f(s_max) && s_max >= 1.0f)) return fail(CLOD_E_ARG, "s_max must be finite and >= 1");
   if (!(finite_f(lambda_reg) && lambda_reg >= 0.0f)) return fail(CLOD_E_ARG, "lambda_reg must be finite and >= 0");
+  if (!(lambda_dssim >= 0.0f && lambda_dssim <= 1.0f)) return fail(CLOD_E_ARG, "lambda_dssim must be in [0, 1]");
+  if (lambda_dssim > 0.0f) {
+    if (!ssim_scratch) return fail(CLOD_E_ARG, "ssim_scratch must be non-NULL when lambda_dssim > 0");
+    if (ssim_scratch_bytes < (size_t)cx.L.pixels_total * 36)
+      return fail(CLOD_E_ARG, "ssim_scratch_bytes %zu < 36 * pixels = %zu", ssim_scratch_bytes,
+                  (size_t)cx.L.pixels_total * 36);
+  }
   for (int v = 0; v < batch->n_views; ++v)
     if (batch->views_host[v].s_v > s_max) return fail(CLOD_E_ARG, "view %d: s_v exceeds s_max", v);
-  HIP_TRY(launch_loss(cx.L, batch->ws, batch->n, rgb, target, s_max, lambda_reg, loss_dev, dL_drgb,
-                      dL_deta_dev, cx.loss_blocks, (hipStream_t)stream),
+  HIP_TRY(launch_loss(cx.L, batch->ws, batch->n, rgb, target, s_max, lambda_reg, lambda_dssim, ssim_scratch,
+                      loss_dev, dL_drgb, dL_deta_dev, cx.loss_blocks, (hipStream_t)stream),
           "loss");
   return CLOD_OK;
 }

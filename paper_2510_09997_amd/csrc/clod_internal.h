@@ -58,7 +58,7 @@ struct Layout {
   int32_t scan_blocks = 0;
   bool any_budget = false;    // some view selects by budget (allocates the select histograms)
   // byte offsets into ws
-  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, sel_state, sel_hist, lcount, list, flags, alpha, depth, rec,
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, ssim_acc, sel_state, sel_hist, lcount, list, flags, alpha, depth, rec,
       rect, tiles, scan_part, ranges, order, tord, pair_part, gscreen, total;
 };
 
@@ -330,6 +330,17 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Weight of Eq. (5): w_s = (1 - 0.5 s_v / max(s_v))^2.
+__device__ __forceinline__ float w_s_weight(float s_v, float s_max) {
+  const float t = 1.0f - 0.5f * s_v / s_max;
+  return t * t;
+}
+
+// 11-tap normalised Gaussian window (sigma 1.5) of the SSIM term.
+struct SsimWindow {
+  float g[11];
+};
+
 // LoD selection key of a (view, Gaussian): larger alpha'' first, then lower index (alpha'' >= 0,
 // so its bit pattern is monotone).  Keys are distinct, so keeping the keys >= the K-th largest
 // keeps exactly K Gaussians.
@@ -393,7 +404,9 @@ hipError_t launch_gauss_bwd(const clod_scene& sc, const Layout& L, void* ws, clo
                             const float* dL_deta, int accumulate, const clod_scene_grad& g,
                             hipStream_t s);
 hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, const float* target,
-                       float s_max, float lambda_reg, float* loss, float* dL_drgb, float* dL_deta,
-                       uint32_t loss_blocks, hipStream_t s);
+                       float s_max, float lambda_reg, float lambda_dssim, float* ssim_scratch, float* loss,
+                       float* dL_drgb, float* dL_deta, uint32_t loss_blocks, hipStream_t s);
+hipError_t launch_ssim(const Layout& L, void* ws, const float* rgb, const float* target, float lambda,
+                       float s_max, float* coef, float* ssim_acc, float* dL_drgb, hipStream_t s);
 
 }  // namespace clod

@@ -1,21 +1,17 @@
-// Training loss of Sec. 3.3 with L_render = L1: per view the mean absolute error, its
-// gradient w_s sign(rgb - target) / (3 H W), the point-count regulariser of Eq. (4) on
-// eta = n_mask / n with target s_v^-1.5 (Eq. 3), and the weighted total of Eq. (5).
+// Training loss of Sec. 3.3: L_render = (1 - lambda_dssim) L1 + lambda_dssim (1 - SSIM) (the 3DGS
+// rendering loss; the SSIM part is in ssim.hip), per view the mean absolute error and its
+// gradient (1 - lambda_dssim) w_s sign(rgb - target) / (3 H W), the point-count regulariser of
+// Eq. (4) on eta = n_mask / n with target s_v^-1.5 (Eq. 3), and the weighted total of Eq. (5).
 #include "clod_internal.h"
 
 namespace clod {
-
-__device__ __forceinline__ float w_s(float s_v, float s_max) {
-  const float t = 1.0f - 0.5f * s_v / s_max;
-  return t * t;
-}
 
 // Blocks are assigned to views by loss_block_base; each block covers kLossChunk values of
 // one view's [3][H][W] image.
 __global__ __launch_bounds__(kBlock) void k_loss_l1(const DevView* __restrict__ views, int V,
                                                     const float* __restrict__ rgb,
                                                     const float* __restrict__ target, float s_max,
-                                                    float* __restrict__ dL_drgb,
+                                                    float l1_weight, float* __restrict__ dL_drgb,
                                                     float* __restrict__ l1_acc) {
   __shared__ float sred[4];
   int lo = 0, hi = V - 1;
@@ -27,8 +23,8 @@ __global__ __launch_bounds__(kBlock) void k_loss_l1(const DevView* __restrict__ 
   const int64_t cnt = 3ll * Vw.width * Vw.height;
   const int64_t base = 3ll * Vw.pix_base;
   const int64_t j0 = (int64_t)(blockIdx.x - Vw.loss_block_base) * kLossChunk;
-  const float ws = w_s(Vw.s_v, s_max);
-  const float scale = ws / (float)cnt;
+  const float ws = w_s_weight(Vw.s_v, s_max);
+  const float scale = l1_weight * ws / (float)cnt;
   float s = 0.f;
 #pragma unroll
   for (int k = 0; k < kLossItems; ++k) {
@@ -47,37 +43,47 @@ __global__ __launch_bounds__(kBlock) void k_loss_l1(const DevView* __restrict__ 
 
 __global__ void k_loss_scalars(const DevView* __restrict__ views, int V, int64_t n,
                                const unsigned long long* __restrict__ counts,
-                               const float* __restrict__ l1_acc, float s_max, float lambda_reg,
+                               const float* __restrict__ l1_acc, const float* __restrict__ ssim_acc,
+                               float s_max, float lambda_reg, float lambda_dssim,
                                float* __restrict__ loss, float* __restrict__ dL_deta) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   const DevView& Vw = views[v];
   const float sv = Vw.s_v;
-  const float l1 = l1_acc[v] / (3.0f * (float)Vw.width * (float)Vw.height);
+  const float cnt = 3.0f * (float)Vw.width * (float)Vw.height;
+  const float l1 = l1_acc[v] / cnt;
+  const float lr = lambda_dssim > 0.f ? (1.0f - lambda_dssim) * l1 + lambda_dssim * (1.0f - ssim_acc[v] / cnt) : l1;
   const float eta = n > 0 ? (float)counts[3 * v + 1] / (float)n : 0.f;
   const float eta_t = 1.0f / (sv * sqrtf(sv));
   const float ex = fmaxf(eta - eta_t, 0.f);
   const float w = (sv - 1.0f) * (sv - 1.0f);
   const float lreg = w * ex * ex;
-  const float ws = w_s(sv, s_max);
-  loss[v] = ws * (l1 + lambda_reg * lreg);
+  const float ws = w_s_weight(sv, s_max);
+  loss[v] = ws * (lr + lambda_reg * lreg);
   if (dL_deta) dL_deta[v] = ws * lambda_reg * 2.0f * w * ex;
 }
 
 hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, const float* target,
-                       float s_max, float lambda_reg, float* loss, float* dL_drgb, float* dL_deta,
-                       uint32_t loss_blocks, hipStream_t s) {
+                       float s_max, float lambda_reg, float lambda_dssim, float* ssim_scratch, float* loss,
+                       float* dL_drgb, float* dL_deta, uint32_t loss_blocks, hipStream_t s) {
   char* w = (char*)ws;
   float* acc = (float*)(w + L.loss_acc);
+  float* sacc = (float*)(w + L.ssim_acc);
   hipError_t e = launch_fill_u32((uint32_t*)acc, 0u, L.V, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_u32((uint32_t*)sacc, 0u, L.V, s);
   if (e != hipSuccess) return e;
   const DevView* views = (const DevView*)(w + L.vinfo);
   if (loss_blocks > 0)
     hipLaunchKernelGGL(k_loss_l1, dim3(loss_blocks), dim3(kBlock), 0, s, views, L.V, rgb, target, s_max,
-                       dL_drgb, acc);
+                       1.0f - lambda_dssim, dL_drgb, acc);
+  if (lambda_dssim > 0.f) {
+    e = launch_ssim(L, ws, rgb, target, lambda_dssim, s_max, ssim_scratch, sacc, dL_drgb, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_loss_scalars, dim3((L.V + 63) / 64), dim3(64), 0, s, views, L.V, n,
-                     (const unsigned long long*)(w + L.counts), (const float*)acc, s_max, lambda_reg,
-                     loss, dL_deta);
+                     (const unsigned long long*)(w + L.counts), (const float*)acc, (const float*)sacc, s_max,
+                     lambda_reg, lambda_dssim, loss, dL_deta);
   return hipGetLastError();
 }
 

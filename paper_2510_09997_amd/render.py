@@ -169,11 +169,13 @@ class Batch:
         C.clod_lod_count(scene.c_struct(), self.c_struct(), out)
         return out
 
-    def loss(self, rgb, target, s_max: float, lambda_reg: float = 1.0):
+    def loss(self, rgb, target, s_max: float, lambda_reg: float = 1.0, lambda_dssim: float = 0.0):
         loss = torch.empty(len(self.views), dtype=torch.float32, device=self.device)
         dL_drgb = torch.empty_like(rgb)
         dL_deta = torch.empty(len(self.views), dtype=torch.float32, device=self.device)
-        C.clod_loss(self.c_struct(), rgb, target, s_max, lambda_reg, loss, dL_drgb, dL_deta)
+        scratch = torch.empty(9 * self.pixels, dtype=torch.float32, device=self.device) if lambda_dssim > 0 else None
+        C.clod_loss(self.c_struct(), rgb, target, s_max, lambda_reg, loss, dL_drgb, dL_deta,
+                    lambda_dssim=lambda_dssim, ssim_scratch=scratch)
         return loss, dL_drgb, dL_deta
 
 

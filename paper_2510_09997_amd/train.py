@@ -21,10 +21,11 @@ from .render import PLANES, Batch, Scene
 
 class MultiViewTrainer:
     def __init__(self, scene: Scene, views, s_max: float, lambda_reg: float = 1.0, params=None,
-                 dup_capacity: int | None = None):
+                 dup_capacity: int | None = None, lambda_dssim: float = 0.0):
         self.scene = scene
         self.s_max = float(s_max)
         self.lambda_reg = float(lambda_reg)
+        self.lambda_dssim = float(lambda_dssim)   # 0.2 gives the 3DGS L_render = 0.8 L1 + 0.2 D-SSIM
         self.batch = Batch(scene.n, views, params, dup_capacity=dup_capacity or 1)
         b = self.batch
         dev = "cuda"
@@ -37,6 +38,8 @@ class MultiViewTrainer:
         self.deta = torch.empty(len(views), device=dev)
         self.grads = {k: torch.zeros_like(v) for k, v in scene.t.items()}
         self.hdr = torch.empty(16, dtype=torch.uint8, pin_memory=True)
+        # Per-pixel SSIM derivatives (36 B per pixel), only when the D-SSIM term is on.
+        self.ssim_scratch = torch.empty(9 * b.pixels, device=dev) if self.lambda_dssim > 0 else None
         self.graph = None
         if dup_capacity is None:
             self.size_capacity()
@@ -78,7 +81,10 @@ class MultiViewTrainer:
         C.clod_project(s, bs, b.counts)
         C.clod_bin_sort(bs, sync_count=False)
         C.clod_render_fwd(bs, self.rgb, self.T, self.last, None)
-        C.clod_loss(bs, self.rgb, self.target, self.s_max, self.lambda_reg, self.loss, self.dL, self.deta)
+        if self.lambda_dssim > 0 and self.ssim_scratch is None:
+            self.ssim_scratch = torch.empty(9 * b.pixels, device=self.rgb.device)
+        C.clod_loss(bs, self.rgb, self.target, self.s_max, self.lambda_reg, self.loss, self.dL, self.deta,
+                    lambda_dssim=self.lambda_dssim, ssim_scratch=self.ssim_scratch)
         C.clod_render_bwd(s, bs, self.T, self.last, self.dL, self.deta, False, C.make_grad(self.grads))
         ptr, _ = C.clod_inspect(bs, C.SEC_HEADER)
         off = ptr - b.ws.data_ptr()

@@ -137,12 +137,17 @@ def test_other_entry_points_validate_arguments():
     assert lib.clod_render_bwd(ctypes.byref(fake_scene()), ctypes.byref(batch), FAKE, FAKE, FAKE, None, 0,
                                ctypes.byref(g), None) == C.CLOD_E_ARG
     assert lib.clod_lod_count(ctypes.byref(fake_scene()), ctypes.byref(batch), FAKE, None) == C.CLOD_E_ARG
-    assert lib.clod_loss(ctypes.byref(batch), FAKE, FAKE, ctypes.c_float(8.0), ctypes.c_float(1.0), FAKE, FAKE,
-                         FAKE, None) == C.CLOD_E_ARG
+    assert lib.clod_loss(ctypes.byref(batch), FAKE, FAKE, ctypes.c_float(8.0), ctypes.c_float(1.0),
+                         ctypes.c_float(0.0), None, 0, FAKE, FAKE, FAKE, None) == C.CLOD_E_ARG
     ok_batch, arr2 = fake_batch([synth.look_at((0, 0, -3), width=64, height=48, s_v=4.0)])
     # s_max below a view's s_v is an argument error.
-    assert lib.clod_loss(ctypes.byref(ok_batch), FAKE, FAKE, ctypes.c_float(2.0), ctypes.c_float(1.0), FAKE,
-                         FAKE, FAKE, None) == C.CLOD_E_ARG
+    assert lib.clod_loss(ctypes.byref(ok_batch), FAKE, FAKE, ctypes.c_float(2.0), ctypes.c_float(1.0),
+                         ctypes.c_float(0.0), None, 0, FAKE, FAKE, FAKE, None) == C.CLOD_E_ARG
+    ok8, arr3 = fake_batch([synth.look_at((0, 0, -3), width=64, height=48, s_v=1.0)])
+    # D-SSIM weight outside [0, 1], or a positive weight without a large enough scratch buffer.
+    for lam, scratch, nbytes in ((1.5, FAKE, 1 << 30), (0.2, None, 0), (0.2, FAKE, 36 * 64 * 48 - 4)):
+        assert lib.clod_loss(ctypes.byref(ok8), FAKE, FAKE, ctypes.c_float(8.0), ctypes.c_float(1.0),
+                             ctypes.c_float(lam), scratch, nbytes, FAKE, FAKE, FAKE, None) == C.CLOD_E_ARG, lam
     # Missing gradient planes.
     assert lib.clod_render_bwd(ctypes.byref(fake_scene()), ctypes.byref(ok_batch), FAKE, FAKE, FAKE, None, 0,
                                ctypes.byref(g), None) == C.CLOD_E_ARG
