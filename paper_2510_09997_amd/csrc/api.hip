@@ -103,6 +103,7 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.gdmax = o; o = align256(o + (size_t)V * 4);
   L.loss_acc = o; o = align256(o + (size_t)V * 4);
   L.ssim_acc = o; o = align256(o + (size_t)V * 4);
+  L.loss_part = o; o = align256(o + ((size_t)tiles_total * 3 + (size_t)pixels_total * 3 / kLossChunk + V) * 4);
   L.kpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 8);
   L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 3 * 4);
   L.gpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4);

@@ -58,7 +58,7 @@ struct Layout {
   int32_t scan_blocks = 0;
   bool any_budget = false;    // some view selects by budget (allocates the select histograms)
   // byte offsets into ws
-  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, ssim_acc, sel_state, sel_hist, lcount, list, flags, alpha, depth, rec,
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, ssim_acc, loss_part, sel_state, sel_hist, lcount, list, flags, alpha, depth, rec,
       rect, tiles, scan_part, ranges, order, tord, pair_part, gscreen, total;
 };
 
@@ -407,6 +407,6 @@ hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, c
                        float s_max, float lambda_reg, float lambda_dssim, float* ssim_scratch, float* loss,
                        float* dL_drgb, float* dL_deta, uint32_t loss_blocks, hipStream_t s);
 hipError_t launch_ssim(const Layout& L, void* ws, const float* rgb, const float* target, float lambda,
-                       float s_max, float* coef, float* ssim_acc, float* dL_drgb, hipStream_t s);
+                       float s_max, float* coef, float* ssim_part, float* dL_drgb, hipStream_t s);
 
 }  // namespace clod

@@ -12,7 +12,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_l1(const DevView* __restrict__ 
                                                     const float* __restrict__ rgb,
                                                     const float* __restrict__ target, float s_max,
                                                     float l1_weight, float* __restrict__ dL_drgb,
-                                                    float* __restrict__ l1_acc) {
+                                                    float* __restrict__ l1_part) {
   __shared__ float sred[4];
   int lo = 0, hi = V - 1;
   while (lo < hi) {
@@ -38,7 +38,34 @@ __global__ __launch_bounds__(kBlock) void k_loss_l1(const DevView* __restrict__ 
   s = wave_sum(s);
   if (lane_id() == 0) sred[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(l1_acc + lo, sred[0] + sred[1] + sred[2] + sred[3]);
+  if (threadIdx.x == 0) l1_part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+// Block v folds view v's partial sums: its L1 blocks and, with the D-SSIM term, the three
+// channel partials of each of its tiles.
+__global__ __launch_bounds__(kBlock) void k_loss_reduce(const DevView* __restrict__ views, int V,
+                                                        uint32_t loss_blocks, const float* __restrict__ l1_part,
+                                                        const float* __restrict__ ssim_part, int with_ssim,
+                                                        float* __restrict__ l1_acc, float* __restrict__ ssim_acc) {
+  __shared__ float sm[2][4];
+  const int v = blockIdx.x;
+  const DevView& Vw = views[v];
+  const uint32_t b0 = Vw.loss_block_base;
+  const uint32_t b1 = v + 1 < V ? views[v + 1].loss_block_base : loss_blocks;
+  float a = 0.f, s = 0.f;
+  for (uint32_t j = b0 + threadIdx.x; j < b1; j += kBlock) a += l1_part[j];
+  if (with_ssim) {
+    const int64_t t0 = 3ll * Vw.tile_base, t1 = t0 + 3ll * Vw.tiles_x * Vw.tiles_y;
+    for (int64_t j = t0 + threadIdx.x; j < t1; j += kBlock) s += ssim_part[j];
+  }
+  a = wave_sum(a);
+  s = wave_sum(s);
+  if (lane_id() == 0) { sm[0][threadIdx.x >> 6] = a; sm[1][threadIdx.x >> 6] = s; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    l1_acc[v] = sm[0][0] + sm[0][1] + sm[0][2] + sm[0][3];
+    ssim_acc[v] = sm[1][0] + sm[1][1] + sm[1][2] + sm[1][3];
+  }
 }
 
 __global__ void k_loss_scalars(const DevView* __restrict__ views, int V, int64_t n,
@@ -69,18 +96,18 @@ hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, c
   char* w = (char*)ws;
   float* acc = (float*)(w + L.loss_acc);
   float* sacc = (float*)(w + L.ssim_acc);
-  hipError_t e = launch_fill_u32((uint32_t*)acc, 0u, L.V, s);
-  if (e != hipSuccess) return e;
-  e = launch_fill_u32((uint32_t*)sacc, 0u, L.V, s);
-  if (e != hipSuccess) return e;
+  float* spart = (float*)(w + L.loss_part);                   // [tiles][3] SSIM partials
+  float* lpart = spart + 3 * (int64_t)L.tiles_total;          // [loss blocks] L1 partials
   const DevView* views = (const DevView*)(w + L.vinfo);
   if (loss_blocks > 0)
     hipLaunchKernelGGL(k_loss_l1, dim3(loss_blocks), dim3(kBlock), 0, s, views, L.V, rgb, target, s_max,
-                       1.0f - lambda_dssim, dL_drgb, acc);
+                       1.0f - lambda_dssim, dL_drgb, lpart);
   if (lambda_dssim > 0.f) {
-    e = launch_ssim(L, ws, rgb, target, lambda_dssim, s_max, ssim_scratch, sacc, dL_drgb, s);
+    hipError_t e = launch_ssim(L, ws, rgb, target, lambda_dssim, s_max, ssim_scratch, spart, dL_drgb, s);
     if (e != hipSuccess) return e;
   }
+  hipLaunchKernelGGL(k_loss_reduce, dim3(L.V), dim3(kBlock), 0, s, views, L.V, loss_blocks, (const float*)lpart,
+                     (const float*)spart, lambda_dssim > 0.f ? 1 : 0, acc, sacc);
   hipLaunchKernelGGL(k_loss_scalars, dim3((L.V + 63) / 64), dim3(64), 0, s, views, L.V, n,
                      (const unsigned long long*)(w + L.counts), (const float*)acc, (const float*)sacc, s_max,
                      lambda_reg, lambda_dssim, loss, dL_deta);

@@ -2,7 +2,9 @@
 // L1 and D-SSIM): SSIM per colour channel with an 11 x 11 Gaussian window (sigma 1.5), zero
 // padding, C1 = 0.01^2, C2 = 0.03^2, averaged over all pixels and channels of a view.
 //
-// One 256-thread block per (16 x 16 tile, channel), one thread per output pixel.  Forward:
+// One 256-thread block per (16 x 16 tile, channel), one thread per output pixel; per-tile
+// partial sums of the SSIM map (no same-address atomics), folded per view by the loss.
+// The window sums use fused multiply-adds (this term is compared within a tolerance).  Forward:
 // the tile and a 5-pixel halo of both images are staged in LDS, the five window moments
 // (E[x], E[y], E[x^2], E[y^2], E[xy]) are filtered separably (rows, then columns), and per
 // pixel the SSIM value and its derivatives with respect to the three moments that depend on
@@ -32,7 +34,7 @@ __device__ __forceinline__ int view_of_tile_s(const DevView* views, int V, uint3
 __global__ __launch_bounds__(kBlock) void k_ssim_fwd(const DevView* __restrict__ views, int V,
                                                      const float* __restrict__ rgb, const float* __restrict__ target,
                                                      SsimWindow win, float lambda, float s_max,
-                                                     float* __restrict__ coef, float* __restrict__ ssim_acc) {
+                                                     float* __restrict__ coef, float* __restrict__ ssim_part) {
   __shared__ float sx[kSpan][kSpan + 1], sy[kSpan][kSpan + 1];
   __shared__ float hm[5][kSpan][kTile + 1];
   __shared__ float sred[4];
@@ -59,11 +61,11 @@ __global__ __launch_bounds__(kBlock) void k_ssim_fwd(const DevView* __restrict__
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       const float g = win.g[k], xv = sx[r][c + k], yv = sy[r][c + k];
-      a += g * xv;
-      b += g * yv;
-      aa += g * (xv * xv);
-      bb += g * (yv * yv);
-      ab += g * (xv * yv);
+      a = fmaf(g, xv, a);
+      b = fmaf(g, yv, b);
+      aa = fmaf(g, xv * xv, aa);
+      bb = fmaf(g, yv * yv, bb);
+      ab = fmaf(g, xv * yv, ab);
     }
     hm[0][r][c] = a; hm[1][r][c] = b; hm[2][r][c] = aa; hm[3][r][c] = bb; hm[4][r][c] = ab;
   }
@@ -73,11 +75,11 @@ __global__ __launch_bounds__(kBlock) void k_ssim_fwd(const DevView* __restrict__
 #pragma unroll
   for (int k = 0; k < kWin; ++k) {
     const float g = win.g[k];
-    mx += g * hm[0][r + k][c];
-    my += g * hm[1][r + k][c];
-    exx += g * hm[2][r + k][c];
-    eyy += g * hm[3][r + k][c];
-    exy += g * hm[4][r + k][c];
+    mx = fmaf(g, hm[0][r + k][c], mx);
+    my = fmaf(g, hm[1][r + k][c], my);
+    exx = fmaf(g, hm[2][r + k][c], exx);
+    eyy = fmaf(g, hm[3][r + k][c], eyy);
+    exy = fmaf(g, hm[4][r + k][c], exy);
   }
   const int px = x0 + c, py = y0 + r;
   float s = 0.f;
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_ssim_fwd(const DevView* __restrict__
   s = wave_sum(s);
   if (lane_id() == 0) sred[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(ssim_acc + v, sred[0] + sred[1] + sred[2] + sred[3]);
+  if (threadIdx.x == 0) ssim_part[3 * (int64_t)tile + ch] = sred[0] + sred[1] + sred[2] + sred[3];
 }
 
 __global__ __launch_bounds__(kBlock) void k_ssim_bwd(const DevView* __restrict__ views, int V,
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_ssim_bwd(const DevView* __restrict__
     for (int j = 0; j < 3; ++j) {
       float a = 0.f;
 #pragma unroll
-      for (int k = 0; k < kWin; ++k) a += win.g[k] * sc[j][r][c + k];
+      for (int k = 0; k < kWin; ++k) a = fmaf(win.g[k], sc[j][r][c + k], a);
       hm[j][r][c] = a;
     }
   }
@@ -146,9 +148,9 @@ __global__ __launch_bounds__(kBlock) void k_ssim_bwd(const DevView* __restrict__
 #pragma unroll
     for (int k = 0; k < kWin; ++k) {
       const float g = win.g[k];
-      fa += g * hm[0][r + k][c];
-      fb += g * hm[1][r + k][c];
-      fc += g * hm[2][r + k][c];
+      fa = fmaf(g, hm[0][r + k][c], fa);
+      fb = fmaf(g, hm[1][r + k][c], fb);
+      fc = fmaf(g, hm[2][r + k][c], fc);
     }
     const int64_t q = 3ll * Vw.pix_base + (int64_t)ch * HW + (int64_t)py * W + px;
     dL_drgb[q] += fa + 2.f * rgb[q] * fb + target[q] * fc;
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_ssim_bwd(const DevView* __restrict__
 }
 
 hipError_t launch_ssim(const Layout& L, void* ws, const float* rgb, const float* target, float lambda,
-                       float s_max, float* coef, float* ssim_acc, float* dL_drgb, hipStream_t s) {
+                       float s_max, float* coef, float* ssim_part, float* dL_drgb, hipStream_t s) {
   if (L.tiles_total == 0) return hipSuccess;
   SsimWindow win;
   double g[kWin], sum = 0.0;
@@ -168,7 +170,7 @@ hipError_t launch_ssim(const Layout& L, void* ws, const float* rgb, const float*
   for (int k = 0; k < kWin; ++k) win.g[k] = (float)(g[k] / sum);
   const DevView* views = (const DevView*)((char*)ws + L.vinfo);
   hipLaunchKernelGGL(k_ssim_fwd, dim3(L.tiles_total, 3), dim3(kBlock), 0, s, views, L.V, rgb, target, win, lambda,
-                     s_max, coef, ssim_acc);
+                     s_max, coef, ssim_part);
   hipLaunchKernelGGL(k_ssim_bwd, dim3(L.tiles_total, 3), dim3(kBlock), 0, s, views, L.V, rgb, target, win,
                      (const float*)coef, dL_drgb);
   return hipGetLastError();
