@@ -45,6 +45,7 @@ def render(scene: dict, view, params: dict | None = None) -> dict:
     mu = scene["mean"].astype(np.float64)                 # [3, n]
     pc = W @ mu + t[:, None]
     x, y, z = pc
+    assert not getattr(view, "frame_width", 0), "the brute force renders whole frames only"
     w_img, h_img = view.width, view.height
     tanx = p["guard"] * (0.5 * w_img) / view.fx
     tany = p["guard"] * (0.5 * h_img) / view.fy

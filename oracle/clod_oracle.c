@@ -29,8 +29,12 @@
  * Layouts (all planes contiguous, plane-major "structure of arrays"):
  *   mean [3][n], log_scale [3][n], quat [4][n] as (w,x,y,z), opacity logit [n], decay [n],
  *   sh [(deg+1)^2][3][n].
- *   view: 24 floats = W[9] (row-major world->camera rotation), t[3], c[3] (camera centre),
- *         fx, fy, cx, cy, width, height, s_v, (unused).
+ *   view: 28 floats = W[9] (row-major world->camera rotation), t[3], c[3] (camera centre),
+ *         fx, fy, cx, cy, width, height, s_v, frame width, frame height, viewport x, viewport y,
+ *         (unused x2).  A view may render a viewport (a width x height window at (x, y), both
+ *         multiples of 16) of a larger frame: the frustum and the frustum maximum of Sec. 3.2
+ *         are the frame's, pixel coordinates are the frame's, and the tile rectangles are the
+ *         frame's clipped to the viewport.  Frame size 0 means the frame is the view.
  *   params: 8 floats = tau, eps, near_z, guard, dilation, bg[3].
  */
 #include <math.h>
@@ -131,6 +135,7 @@ typedef struct {
     float fx, fy, cx, cy;
     int w, h;
     float sv;
+    int fw, fh, vx, vy;   /* frame size and viewport origin (pixels) */
 } oview;
 
 static void unpack_view(const float *v, oview *o) {
@@ -139,6 +144,8 @@ static void unpack_view(const float *v, oview *o) {
     memcpy(o->c, v + 12, 3 * sizeof(float));
     o->fx = v[15]; o->fy = v[16]; o->cx = v[17]; o->cy = v[18];
     o->w = (int)v[19]; o->h = (int)v[20]; o->sv = v[21];
+    o->fw = (int)v[22]; o->fh = (int)v[23]; o->vx = (int)v[24]; o->vy = (int)v[25];
+    if (o->fw == 0 && o->fh == 0) { o->fw = o->w; o->fh = o->h; o->vx = 0; o->vy = 0; }
 }
 
 void oracle_init(void) { contract_init(); sh_init(); }
@@ -220,9 +227,11 @@ void oracle_view_pass(int64_t n, int deg, const float *mean, const float *lsc, c
     unpack_view(view24, &V);
     const float tau = par8[0], eps = par8[1], nearz = par8[2], guard = par8[3], dil = par8[4];
     const int K = (deg + 1) * (deg + 1);
-    const int TW = (V.w + 15) / 16, TH = (V.h + 15) / 16;
-    const float limx = guard * ((0.5f * (float)V.w) / V.fx);
-    const float limy = guard * ((0.5f * (float)V.h) / V.fy);
+    const int TW = (V.w + 15) / 16, TH = (V.h + 15) / 16;          /* viewport tiles */
+    const int FTW = (V.fw + 15) / 16, FTH = (V.fh + 15) / 16;      /* frame tiles */
+    const int TOX = V.vx / 16, TOY = V.vy / 16;                     /* viewport origin, tiles */
+    const float limx = guard * ((0.5f * (float)V.fw) / V.fx);
+    const float limy = guard * ((0.5f * (float)V.fh) / V.fy);
 
     /* Pass 1: frustum and distance; maximum over the frustum, lowest index on ties. */
     float dmax = 0.0f;
@@ -335,9 +344,12 @@ void oracle_view_pass(int64_t n, int deg, const float *mean, const float *lsc, c
                 float u = fmaf(V.fx, tx, V.cx), v = fmaf(V.fy, ty, V.cy);
                 float fx0 = floorf((u - rad) * 0.0625f), fx1 = floorf((u + rad) * 0.0625f) + 1.0f;
                 float fy0 = floorf((v - rad) * 0.0625f), fy1 = floorf((v + rad) * 0.0625f) + 1.0f;
-                fx0 = fminf(fmaxf(fx0, 0.0f), (float)TW); fx1 = fminf(fmaxf(fx1, 0.0f), (float)TW);
-                fy0 = fminf(fmaxf(fy0, 0.0f), (float)TH); fy1 = fminf(fmaxf(fy1, 0.0f), (float)TH);
+                fx0 = fminf(fmaxf(fx0, 0.0f), (float)FTW); fx1 = fminf(fmaxf(fx1, 0.0f), (float)FTW);
+                fy0 = fminf(fmaxf(fy0, 0.0f), (float)FTH); fy1 = fminf(fmaxf(fy1, 0.0f), (float)FTH);
+                /* The frame's rectangle clipped to the viewport, in viewport tiles. */
                 int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+                x0 = (x0 > TOX ? x0 : TOX) - TOX; x1 = (x1 < TOX + TW ? x1 : TOX + TW) - TOX;
+                y0 = (y0 > TOY ? y0 : TOY) - TOY; y1 = (y1 < TOY + TH ? y1 : TOY + TH) - TOY;
                 if (x0 < x1 && y0 < y1) {
                     /* View-dependent colour. */
                     float id = 1.0f / d;
@@ -477,8 +489,9 @@ static int64_t blend_pixel_counts(int px, int py, const float *rec, const int32_
 
 /* Full image: rgb [3][h][w] (colour plus T * bg), T [h][w], last [h][w].
    Returns the number of (pixel, entry) pairs evaluated. */
-int64_t oracle_blend(int w, int h, const float *rec, const int64_t *tile_off, const int32_t *entries,
-                     const float *bg3, float *rgb, float *Tout, int32_t *last, int64_t *classes) {
+int64_t oracle_blend(int w, int h, int vx, int vy, const float *rec, const int64_t *tile_off,
+                     const int32_t *entries, const float *bg3, float *rgb, float *Tout, int32_t *last,
+                     int64_t *classes) {
     const int TW = (w + 15) / 16, TH = (h + 15) / 16;
     int64_t pairs = 0, nx = 0, nb = 0;
     const int64_t HW = (int64_t)w * h;
@@ -492,8 +505,9 @@ int64_t oracle_blend(int w, int h, const float *rec, const int64_t *tile_off, co
                 float c[3], T;
                 int32_t l;
                 int64_t ex, bl;
-                pairs += blend_pixel_counts(px, py, rec, entries + tile_off[t], tile_off[t + 1] - tile_off[t], c, &T,
-                                            &l, NULL, &ex, &bl);
+                /* Pixel centres in frame coordinates (viewport origin added). */
+                pairs += blend_pixel_counts(vx + px, vy + py, rec, entries + tile_off[t], tile_off[t + 1] - tile_off[t],
+                                            c, &T, &l, NULL, &ex, &bl);
                 nx += ex;
                 nb += bl;
                 int64_t p = (int64_t)py * w + px;
@@ -509,7 +523,7 @@ int64_t oracle_blend(int w, int h, const float *rec, const int64_t *tile_off, co
 }
 
 /* Blend decisions of one tile for the FP64 replay: status[256][lmax] (row = ly*16+lx). */
-void oracle_tile_status(int w, int h, int64_t tile, const float *rec, const int64_t *tile_off,
+void oracle_tile_status(int w, int h, int vx, int vy, int64_t tile, const float *rec, const int64_t *tile_off,
                         const int32_t *entries, int64_t lmax, uint8_t *status) {
     const int TW = (w + 15) / 16;
     int tx = (int)(tile % TW), ty = (int)(tile / TW);
@@ -522,7 +536,8 @@ void oracle_tile_status(int w, int h, int64_t tile, const float *rec, const int6
             if (px >= w || py >= h) continue;
             float c[3], T;
             int32_t l;
-            blend_pixel(px, py, rec, entries + tile_off[tile], len, c, &T, &l, status + (int64_t)(ly * 16 + lx) * lmax);
+            blend_pixel(vx + px, vy + py, rec, entries + tile_off[tile], len, c, &T, &l,
+                        status + (int64_t)(ly * 16 + lx) * lmax);
         }
 }
 

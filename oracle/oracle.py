@@ -68,9 +68,9 @@ def lib():
         L.oracle_view_pass.argtypes = [i64, ctypes.c_int] + [P] * 9 + [P] * 7
         L.oracle_tile_lists.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_int, P, P, i64]
         L.oracle_tile_lists.restype = i64
-        L.oracle_blend.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, P]
+        L.oracle_blend.argtypes = [ctypes.c_int] * 4 + [P, P, P, P, P, P, P, P]
         L.oracle_blend.restype = i64
-        L.oracle_tile_status.argtypes = [ctypes.c_int, ctypes.c_int, i64, P, P, P, i64, P]
+        L.oracle_tile_status.argtypes = [ctypes.c_int] * 4 + [i64, P, P, P, i64, P]
         L.oracle_blend_one.argtypes = [ctypes.c_int, ctypes.c_int, P, P, i64, P, P, P]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_init()
@@ -83,8 +83,16 @@ def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def viewport_of(view):
+    """(frame width, frame height, x, y) of a view's viewport; a plain view is its own frame."""
+    fw, fh = int(getattr(view, "frame_width", 0)), int(getattr(view, "frame_height", 0))
+    if fw == 0 and fh == 0:
+        return view.width, view.height, 0, 0
+    return fw, fh, int(view.vx), int(view.vy)
+
+
 def pack_view(view) -> np.ndarray:
-    v = np.zeros(24, dtype=np.float32)
+    v = np.zeros(28, dtype=np.float32)
     v[0:9] = np.asarray(view.W, dtype=np.float32).reshape(9)
     v[9:12] = view.t
     v[12:15] = view.c
@@ -92,6 +100,7 @@ def pack_view(view) -> np.ndarray:
     v[19] = view.width
     v[20] = view.height
     v[21] = view.s_v
+    v[22:26] = viewport_of(view)
     return v
 
 
@@ -162,8 +171,9 @@ def _view_pass(scene: dict, view, params: dict | None, mask) -> dict:
                            _p(scene["opacity"]), _p(scene["decay"]), _p(scene["sh"]), _p(v24), _p(p8),
                            None if mask_c is None else _p(mask_c),
                            _p(flags), _p(rec), _p(rect), _p(aux), _p(dmax), _p(arg), _p(counts))
+    _, _, vx, vy = viewport_of(view)
     return dict(flags=flags, rec=rec, rect=rect, aux=aux, dmax=float(dmax[0]), argmax=int(arg[0]),
-                counts=counts, width=view.width, height=view.height)
+                counts=counts, width=view.width, height=view.height, vx=vx, vy=vy)
 
 
 def tile_lists(vp: dict):
@@ -188,7 +198,8 @@ def blend(vp: dict, off: np.ndarray, ent: np.ndarray, params: dict | None = None
     last = np.zeros((h, w), dtype=np.int32)
     ent_c = np.ascontiguousarray(ent if ent.size else np.zeros(1, np.int32))
     classes = np.zeros(3, np.int64)
-    lib().oracle_blend(w, h, _p(vp["rec"]), _p(off), _p(ent_c), _p(bg), _p(rgb), _p(T), _p(last), _p(classes))
+    lib().oracle_blend(w, h, vp["vx"], vp["vy"], _p(vp["rec"]), _p(off), _p(ent_c), _p(bg), _p(rgb), _p(T), _p(last),
+                       _p(classes))
     return rgb, T, last, classes
 
 
@@ -211,7 +222,7 @@ def sorted_keys(vp: dict, tile_base: int = 0) -> np.ndarray:
 def tile_status(vp: dict, tile: int, lmax: int) -> np.ndarray:
     st = np.zeros((256, max(lmax, 1)), dtype=np.uint8)
     ent_c = np.ascontiguousarray(vp["entries"] if vp["entries"].size else np.zeros(1, np.int32))
-    lib().oracle_tile_status(vp["width"], vp["height"], tile, _p(vp["rec"]), _p(vp["tile_off"]),
+    lib().oracle_tile_status(vp["width"], vp["height"], vp["vx"], vp["vy"], tile, _p(vp["rec"]), _p(vp["tile_off"]),
                              _p(ent_c), max(lmax, 1), _p(st))
     return st[:, :lmax]
 
@@ -225,7 +236,7 @@ def blend_pixel(vp: dict, px: int, py: int):
     rgb = np.zeros(3, np.float32)
     T = np.zeros(1, np.float32)
     last = np.zeros(1, np.int32)
-    lib().oracle_blend_one(px, py, _p(vp["rec"]), _p(lst), b - a, _p(rgb), _p(T), _p(last))
+    lib().oracle_blend_one(px + vp["vx"], py + vp["vy"], _p(vp["rec"]), _p(lst), b - a, _p(rgb), _p(T), _p(last))
     return rgb, float(T[0]), int(last[0])
 
 
@@ -399,8 +410,8 @@ def fp64_view_forward(sc: dict, view, vp: dict, params: dict | None = None,
         st = tile_status(vp, tile, lmax)[valid]          # [P, L] 0/1/2
         gidx = ent[off[tile]: off[tile] + lmax].astype(np.int64)
         gpos = torch.from_numpy(pos_of[gidx])            # [L]
-        pcx = torch.from_numpy(pxs[valid].astype(np.float64) + 0.5)[:, None]
-        pcy = torch.from_numpy(pys[valid].astype(np.float64) + 0.5)[:, None]
+        pcx = torch.from_numpy(pxs[valid].astype(np.float64) + vp.get("vx", 0) + 0.5)[:, None]
+        pcy = torch.from_numpy(pys[valid].astype(np.float64) + vp.get("vy", 0) + 0.5)[:, None]
         dx = u[gpos][None, :] - pcx
         dy = v[gpos][None, :] - pcy
         power = -0.5 * (A[gpos][None, :] * dx * dx + C[gpos][None, :] * dy * dy) - B[gpos][None, :] * dx * dy

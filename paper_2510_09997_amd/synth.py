@@ -86,6 +86,10 @@ class View:
     height: int
     s_v: float = 1.0
     budget: int = 0   # 0: threshold mask; K > 0: keep the K largest alpha''
+    frame_width: int = 0    # > 0: this view renders a viewport of a larger frame
+    frame_height: int = 0
+    vx: int = 0             # viewport origin in the frame (multiples of 16)
+    vy: int = 0
 
 
 def look_at(pos, target=(0.0, 0.0, 0.0), width=256, height=256, fov_deg=60.0, s_v=1.0) -> View:
@@ -107,6 +111,28 @@ def look_at(pos, target=(0.0, 0.0, 0.0), width=256, height=256, fov_deg=60.0, s_
                 fx=float(np.float32(focal)), fy=float(np.float32(focal)),
                 cx=float(width) / 2.0, cy=float(height) / 2.0,
                 width=int(width), height=int(height), s_v=float(np.float32(s_v)))
+
+
+def viewport(view: View, x: int, y: int, width: int, height: int, s_v: float | None = None,
+             budget: int | None = None) -> View:
+    """The window [x, x + width) x [y, y + height) of `view`'s image as a view of its own (x, y
+    multiples of 16), optionally with its own virtual distance scale and budget: the frustum,
+    its maximum distance and the pixel coordinates stay those of the whole frame."""
+    fw = view.frame_width or view.width
+    fh = view.frame_height or view.height
+    return dataclasses.replace(view, width=int(width), height=int(height), frame_width=fw, frame_height=fh,
+                               vx=view.vx + int(x), vy=view.vy + int(y),
+                               s_v=view.s_v if s_v is None else float(np.float32(s_v)),
+                               budget=view.budget if budget is None else int(budget))
+
+
+def strips(view: View, s_values) -> list[View]:
+    """Vertical strips of equal tile-aligned width covering `view`, strip r at s_values[r]
+    (spatially varying virtual distance scale)."""
+    k = len(s_values)
+    tiles = (view.width + 15) // 16
+    edges = [16 * ((tiles * r) // k) for r in range(k)] + [view.width]
+    return [viewport(view, edges[r], 0, edges[r + 1] - edges[r], view.height, s_v=s_values[r]) for r in range(k)]
 
 
 def unit_vectors(rng, k: int) -> np.ndarray:

@@ -622,3 +622,47 @@ def test_render_loss_gradient_matches_central_differences():
         xm[idx] -= h
         fd = (SO.render_loss64(xp, y)[0] - SO.render_loss64(xm, y)[0]) / (2 * h)
         assert abs(fd - g[idx]) <= 1e-7 * max(1.0, abs(fd)), idx
+
+
+# ---------------------------------------------------------------------------------------
+# Viewports of a frame (spatially varying s_v, the strips of the Sec. 4 DLoD/CLoD comparison):
+# a viewport renders exactly the frame's pixels under its own s_v.
+# ---------------------------------------------------------------------------------------
+
+def _crop(img, v):
+    return img[..., v.vy:v.vy + v.height, v.vx:v.vx + v.width]
+
+
+def test_viewport_strips_stitch_to_the_whole_frame_bit_exact():
+    sc = synth.make_scene(4000, 1, "mixture", seed=80)
+    frame = synth.look_at((2.0, 1.0, -9.0), width=200, height=130, s_v=2.0)
+    full = O.render32(sc, frame)
+    for v in synth.strips(frame, [2.0, 2.0, 2.0, 2.0]):
+        r = O.render32(sc, v)
+        assert np.array_equal(r["rgb"].view(np.uint32), _crop(full["rgb"], v).view(np.uint32))
+        assert np.array_equal(r["T"].view(np.uint32), _crop(full["T"], v).view(np.uint32))
+        assert np.array_equal(r["last"], _crop(full["last"], v))
+        assert r["dmax"] == full["dmax"] and r["argmax"] == full["argmax"]
+        assert np.array_equal(r["counts"][:2], full["counts"][:2])
+
+
+def test_viewport_strips_at_different_sv_equal_uniform_renders_at_each_sv():
+    sc = synth.make_scene(6000, 3, "mixture", seed=81)
+    frame = synth.look_at((-3.0, 2.0, -8.0), width=160, height=96)
+    svs = [8.0, 4.0, 2.0, 1.0]
+    for v, s in zip(synth.strips(frame, svs), svs):
+        import dataclasses
+        uni = O.render32(sc, dataclasses.replace(frame, s_v=s))
+        r = O.render32(sc, v)
+        assert np.array_equal(r["rgb"].view(np.uint32), _crop(uni["rgb"], v).view(np.uint32)), s
+        assert np.array_equal(r["last"], _crop(uni["last"], v)), s
+
+
+def test_viewport_window_offset_on_both_axes():
+    sc = synth.make_scene(3000, 0, "uniform", seed=82)
+    frame = synth.look_at((0.2, -0.1, -3.0), width=150, height=120, s_v=1.5)
+    full = O.render32(sc, frame)
+    v = synth.viewport(frame, 32, 48, 70, 41)
+    r = O.render32(sc, v)
+    assert np.array_equal(r["rgb"].view(np.uint32), _crop(full["rgb"], v).view(np.uint32))
+    assert np.array_equal(r["last"], _crop(full["last"], v))
