@@ -333,6 +333,39 @@ def run_budget_sweep(args, torch, C, Batch, scene, pose):
     return out
 
 
+def run_strips(args, torch, C, Batch, scene, pose, synth):
+    """Spatially varying s_v: a 1080p frame rendered as four vertical strips at s_v = 8, 4, 2, 1
+    (the layout of the paper's DLoD/CLoD comparison), as one batch of viewports, against the
+    whole frame at s_v = 1.  Frames/s and per-strip kept counts."""
+    out = {}
+    for name, views in (("uniform", [pose]), ("strips", synth.strips(pose, [8.0, 4.0, 2.0, 1.0]))):
+        b = Batch(scene.n, views)
+        b.project(scene)
+        b.bin_sort()
+        rgb = torch.empty(3 * b.pixels, device="cuda")
+        T = torch.empty(b.pixels, device="cuda")
+        last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
+        bs = b.c_struct()
+        reps = 10
+        for _ in range(2):
+            C.clod_project(scene.c_struct(), bs, b.counts)
+            C.clod_bin_sort(bs, sync_count=False)
+            C.clod_render_fwd(bs, rgb, T, last, None)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            C.clod_project(scene.c_struct(), bs, b.counts)
+            C.clod_bin_sort(bs, sync_count=False)
+            C.clod_render_fwd(bs, rgb, T, last, None)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_fps"] = round(reps / (e0.elapsed_time(e1) / 1e3), 2)
+        out[name + "_kept"] = b.counts.cpu().numpy()[:, 1].tolist()
+        del b
+    out["strip_s_v"] = [8.0, 4.0, 2.0, 1.0]
+    return out
+
+
 def run_lod_sweep(args, torch, C, Batch, Scene, synth):
     """6M Gaussians, 1920x1080, 64 camera distances log-spaced in [2, 200] along one ray
     (looking at the origin from -z): kept-primitive counts of all 64 views in one launch, and
@@ -429,7 +462,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE on the
 # default command (profiles/k_blend_fwd_serve1080p_3M_hbm.txt), each scaled by the reading of
 # the same counter for a 1 GiB device copy.  Set to None whenever the kernel changes.
-TRAFFIC = {"k_blend_fwd": 1515528767}
+TRAFFIC = {}
 
 
 def main():
@@ -466,6 +499,10 @@ def main():
     if not args.no_budget:
         budget = run_budget_sweep(args, torch, C, Batch, scene, steps[min(10, len(steps) - 1)][0])
         log(f"[bench] budget sweep fps: {dict(zip(budget['budgets'], budget['fps']))}")
+    strips = None
+    if not args.no_budget:
+        strips = run_strips(args, torch, C, Batch, scene, steps[min(10, len(steps) - 1)][0], synth)
+        log(f"[bench] strips: {strips}")
     del scene, b
     torch.cuda.empty_cache()
     train = None
@@ -519,6 +556,8 @@ def main():
                                "s_v": "log-uniform [1, 8]", "loss": "L1 + point-count regulariser"}
     if budget is not None:
         out["budget_sweep"] = budget
+    if strips is not None:
+        out["spatial_sv_strips"] = strips
     if not args.no_multiview:
         torch.cuda.empty_cache()
         mv = run_multiview_train(args, torch, C, Scene, synth)

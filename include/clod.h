@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 6
+#define CLOD_ABI_VERSION 7
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -63,7 +63,7 @@ typedef struct clod_scene_grad {
 /* One view: a pinhole camera (OpenCV axes: x right, y down, z forward; pixel (i, j) covers
    [i, i+1) x [j, j+1) and is sampled at its centre) and the virtual distance scale s_v >= 1
    of Sec. 3.2 (it strengthens the decay and the mask threshold; it does not move the camera).
-   96 bytes. */
+   112 bytes. */
 typedef struct clod_view {
   float W[9];             /* world-to-camera rotation, row-major */
   float t[3];             /* world-to-camera translation */
@@ -74,6 +74,12 @@ typedef struct clod_view {
   int64_t budget;         /* LoD selection: 0 keeps alpha'' > tau * s_v (Sec. 3.2); K > 0 keeps the
                              K Gaussians of largest alpha'' (lower index first among equal values),
                              the primitive-budget selection of the Sec. 4 comparisons */
+  int32_t frame_width;    /* 0: the view is its own frame.  > 0: the view renders the viewport */
+  int32_t frame_height;   /*   [vx, vx + width) x [vy, vy + height) of a frame_width x frame_height */
+  int32_t vx, vy;         /*   image (vx, vy multiples of 16): frustum, frustum maximum and pixel
+                               coordinates are the frame's, tile rectangles the frame's clipped to
+                               the viewport -- spatially varying s_v renders a frame as viewports
+                               with their own s_v (the strips of the Sec. 4 DLoD comparison) */
 } clod_view;
 
 /* Constants the paper leaves open (readings; defaults in parentheses). */

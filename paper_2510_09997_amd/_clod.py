@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 
 class ClodError(RuntimeError):
@@ -47,7 +47,8 @@ class clod_view(ctypes.Structure):
     _fields_ = [("W", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("c", ctypes.c_float * 3),
                 ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("s_v", ctypes.c_float),
-                ("budget", ctypes.c_int64)]
+                ("budget", ctypes.c_int64), ("frame_width", ctypes.c_int32), ("frame_height", ctypes.c_int32),
+                ("vx", ctypes.c_int32), ("vy", ctypes.c_int32)]
 
 
 class clod_adam(ctypes.Structure):
@@ -66,7 +67,7 @@ class clod_batch(ctypes.Structure):
                 ("ws", P), ("ws_bytes", ctypes.c_size_t), ("dup", P), ("dup_bytes", ctypes.c_size_t)]
 
 
-assert ctypes.sizeof(clod_view) == 96
+assert ctypes.sizeof(clod_view) == 112
 
 EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project", "clod_bin_sort",
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
@@ -168,6 +169,9 @@ def make_views(views) -> ctypes.Array:
         cv.width, cv.height = int(v.width), int(v.height)
         cv.s_v = float(v.s_v)
         cv.budget = int(getattr(v, "budget", 0))
+        cv.frame_width = int(getattr(v, "frame_width", 0))
+        cv.frame_height = int(getattr(v, "frame_height", 0))
+        cv.vx, cv.vy = int(getattr(v, "vx", 0)), int(getattr(v, "vy", 0))
     return arr
 
 

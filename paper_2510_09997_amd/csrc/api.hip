@@ -30,6 +30,8 @@ static clod_status hip_check(hipError_t e, const char* what) {
     if (_st != CLOD_OK) return _st;                           \
   } while (0)
 
+static_assert(sizeof(clod_view) == 112, "clod_view layout");
+
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static bool finite_f(float x) { return isfinite(x) != 0; }
@@ -147,6 +149,16 @@ static clod_status check_view(const clod_view& c, int v) {
     return fail(CLOD_E_ARG, "view %d: intrinsics must be finite with fx, fy > 0", v);
   if (!(finite_f(c.s_v) && c.s_v >= 1.0f)) return fail(CLOD_E_ARG, "view %d: s_v must be finite and >= 1", v);
   if (c.budget < 0) return fail(CLOD_E_ARG, "view %d: budget must be >= 0", v);
+  if (c.frame_width != 0 || c.frame_height != 0) {
+    if (c.frame_width < 1 || c.frame_height < 1 || c.frame_width > 16384 || c.frame_height > 16384)
+      return fail(CLOD_E_ARG, "view %d: frame size must be in 1..16384", v);
+    if (c.vx < 0 || c.vy < 0 || (c.vx & 15) || (c.vy & 15))
+      return fail(CLOD_E_ARG, "view %d: viewport origin must be non-negative multiples of 16", v);
+    if ((int64_t)c.vx + c.width > c.frame_width || (int64_t)c.vy + c.height > c.frame_height)
+      return fail(CLOD_E_ARG, "view %d: viewport exceeds the frame", v);
+  } else if (c.vx != 0 || c.vy != 0) {
+    return fail(CLOD_E_ARG, "view %d: a viewport origin needs a frame size", v);
+  }
   double scale = 1.0;
   for (int j = 0; j < 3; ++j) scale = fmax(scale, fabs((double)c.c[j]));
   for (int j = 0; j < 3; ++j) {

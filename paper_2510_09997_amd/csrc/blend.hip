@@ -97,8 +97,9 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
   const int px = qx0 + (int)(lane & 7);
   const int py = qy0 + (int)(lane >> 3);
   const bool inside = px < Vw.width && py < Vw.height;
-  const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
-  const float fqx = (float)qx0, fqy = (float)qy0;
+  // Pixel centres and quadrant corners in frame coordinates (the viewport origin added).
+  const float pcx = (float)(px + Vw.vx) + 0.5f, pcy = (float)(py + Vw.vy) + 0.5f;
+  const float fqx = (float)(qx0 + Vw.vx), fqy = (float)(qy0 + Vw.vy);
   const uint2 rg = ranges[tile_i];
   const float kSkip = 0.0039215688593685627f;   // fl(1/255)
   const float kTmin = 9.99999974737875163e-05f; // fl(1e-4)
@@ -266,8 +267,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   const int px = tx * kTile + (wave & 1) * 8 + (int)(lane & 7);
   const int py = ty * kTile + (wave >> 1) * 8 + (int)(lane >> 3);
   const bool inside = px < Vw.width && py < Vw.height;
-  const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
-  const float tx0 = (float)(tx * kTile), ty0 = (float)(ty * kTile);
+  const float pcx = (float)(px + Vw.vx) + 0.5f, pcy = (float)(py + Vw.vy) + 0.5f;
+  const float tx0 = (float)(tx * kTile + Vw.vx), ty0 = (float)(ty * kTile + Vw.vy);
   const uint2 rg = ranges[tile_i];
   const float kSkip = 0.0039215688593685627f;
   const int64_t P = (int64_t)Vw.pix_base;

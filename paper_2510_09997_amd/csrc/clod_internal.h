@@ -35,6 +35,8 @@ struct DevView {
   float s_v, limx, limy, tau_sv;
   int32_t width, height, tiles_x, tiles_y;
   uint32_t tile_base, pix_base, loss_block_base, pad0;
+  int32_t ftiles_x, ftiles_y;    // tiles of the frame (the view's own when it is not a viewport)
+  int32_t vx, vy;                // viewport origin in the frame, pixels (multiples of 16)
   int64_t budget;                // 0: threshold mask; K > 0: the K largest selection keys
   unsigned long long mkey;       // K > 0: smallest kept selection key (set by the radix select)
 };
@@ -269,17 +271,20 @@ __device__ __forceinline__ bool ewa(const DevView& V, float x, float y, float z,
   P.rad = rad;
   P.u = fmaf_(V.fx, tx, V.cx);
   P.v = fmaf_(V.fy, ty, V.cy);
-  const float TWf = (float)V.tiles_x, THf = (float)V.tiles_y;
+  // Rectangle in frame tiles, clamped to the frame, then clipped to the viewport (viewport tiles).
+  const float TWf = (float)V.ftiles_x, THf = (float)V.ftiles_y;
   float fx0 = __builtin_floorf((P.u - rad) * 0.0625f), fx1 = __builtin_floorf((P.u + rad) * 0.0625f) + 1.0f;
   float fy0 = __builtin_floorf((P.v - rad) * 0.0625f), fy1 = __builtin_floorf((P.v + rad) * 0.0625f) + 1.0f;
   fx0 = fminf(fmaxf(fx0, 0.0f), TWf); fx1 = fminf(fmaxf(fx1, 0.0f), TWf);
   fy0 = fminf(fmaxf(fy0, 0.0f), THf); fy1 = fminf(fmaxf(fy1, 0.0f), THf);
-  P.x0 = (int)fx0; P.x1 = (int)fx1; P.y0 = (int)fy0; P.y1 = (int)fy1;
+  const int tox = V.vx >> 4, toy = V.vy >> 4;
+  P.x0 = max((int)fx0, tox) - tox; P.x1 = min((int)fx1, tox + V.tiles_x) - tox;
+  P.y0 = max((int)fy0, toy) - toy; P.y1 = min((int)fy1, toy + V.tiles_y) - toy;
   return P.x0 < P.x1 && P.y0 < P.y1;
 }
 
-// Record written by the projection for each (view, Gaussian):
-//   g0 = (u, v, alpha'', depth), g1 = (A, B, C, radius), g2 = (r, g, b, 0).
+// Record written by the projection for each rendered (view, Gaussian), kRecQuads float4:
+//   (u, v, alpha'', radius), (A, B, C, 0), (r, g, b, 0), unused; (u, v) in frame pixels.
 // flags: bit0 F, bit1 M, bit2 rendered, bits3..5 colour clamp per channel.
 
 __device__ __forceinline__ float dmax_from_key(unsigned long long key) {

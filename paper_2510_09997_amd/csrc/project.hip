@@ -21,8 +21,15 @@ __global__ void k_view_setup(const clod_view* __restrict__ views, int V, clod_pa
     for (int j = 0; j < 3; ++j) { d.t[j] = cv.t[j]; d.c[j] = cv.c[j]; }
     d.fx = cv.fx; d.fy = cv.fy; d.cx = cv.cx; d.cy = cv.cy;
     d.s_v = cv.s_v;
-    d.limx = prm.guard * ((0.5f * (float)cv.width) / cv.fx);
-    d.limy = prm.guard * ((0.5f * (float)cv.height) / cv.fy);
+    // A viewport keeps its frame's frustum: the limits come from the frame size.
+    const bool vp = cv.frame_width > 0 || cv.frame_height > 0;
+    const int fw = vp ? cv.frame_width : cv.width, fh = vp ? cv.frame_height : cv.height;
+    d.limx = prm.guard * ((0.5f * (float)fw) / cv.fx);
+    d.limy = prm.guard * ((0.5f * (float)fh) / cv.fy);
+    d.ftiles_x = (fw + kTile - 1) / kTile;
+    d.ftiles_y = (fh + kTile - 1) / kTile;
+    d.vx = vp ? cv.vx : 0;
+    d.vy = vp ? cv.vy : 0;
     d.tau_sv = prm.tau * cv.s_v;
     d.width = cv.width;
     d.height = cv.height;

@@ -109,3 +109,30 @@ def compare_forward(g: dict, sc: dict, views, params: dict | None = None, fp64: 
     assert g["D"] == keys.size
     assert np.array_equal(g["keys"][:g["D"]], keys)
     assert np.array_equal(g["vals"][:g["D"]].astype(np.uint64), vals)
+
+
+def _grad_case(sc, views, seed=0, dL_deta=None):
+    scene = Scene(sc)
+    b = Batch(sc["n"], views, params_struct(None))
+    b.project(scene)
+    b.bin_sort()
+    rgb, T, last = b.render_fwd()
+    rng = np.random.default_rng(seed)
+    g_rgb = rng.normal(size=3 * b.pixels).astype(np.float32)
+    eta_g = None if dL_deta is None else torch.tensor(dL_deta, dtype=torch.float32, device="cuda")
+    grads = b.render_bwd(scene, T, last, torch.from_numpy(g_rgb).cuda(), eta_g)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in grads.items()}
+    want = None
+    for v, view in enumerate(views):
+        r = O.render32(sc, view)
+        a = int(b.pix_base[v])
+        h, w = view.height, view.width
+        gv = g_rgb[3 * a:3 * a + 3 * h * w].reshape(3, h, w)
+        ref = O.fp64_grads(sc, view, r, gv, 0.0 if dL_deta is None else float(dL_deta[v]))
+        if want is None:
+            want = {k: ref[k].copy() for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")}
+        else:
+            for k in want:
+                want[k] += ref[k]
+    return got, want

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_entry_point():
 
 
 def test_struct_sizes_match_header_layout():
-    assert ctypes.sizeof(C.clod_view) == 96
+    assert ctypes.sizeof(C.clod_view) == 112
     assert ctypes.sizeof(C.clod_params) == 32
     assert ctypes.sizeof(C.clod_scene) == 8 + 4 + 4 + 6 * 8
     assert C.clod_batch.ws.offset % 8 == 0
@@ -84,6 +84,7 @@ def call_project(scene, batch):
 @pytest.mark.parametrize("case", [
     "sv_below_one", "sv_nan", "n_negative", "degree_4", "null_mean", "zero_views", "eps_zero",
     "tau_negative", "ws_small", "ws_misaligned", "bad_width", "centre_mismatch", "n_mismatch",
+    "viewport_unaligned", "viewport_exceeds_frame", "origin_without_frame", "negative_budget",
 ])
 def test_invalid_arguments_are_rejected_before_launch(case):
     v = synth.look_at((0, 0, -3), width=64, height=48)
@@ -107,6 +108,18 @@ def test_invalid_arguments_are_rejected_before_launch(case):
     elif case == "centre_mismatch":
         bad = synth.look_at((0, 0, -3), width=64, height=48)
         bad.c = np.array([0.0, 0.0, 3.0], np.float32)
+        views = [bad]
+    if case == "viewport_unaligned":
+        views = [synth.viewport(synth.look_at((0, 0, -3), width=128, height=96), 8, 0, 64, 48)]
+    elif case == "viewport_exceeds_frame":
+        views = [synth.viewport(synth.look_at((0, 0, -3), width=128, height=96), 96, 0, 64, 48)]
+    elif case == "origin_without_frame":
+        bad = synth.look_at((0, 0, -3), width=64, height=48)
+        bad.vx = 16
+        views = [bad]
+    elif case == "negative_budget":
+        bad = synth.look_at((0, 0, -3), width=64, height=48)
+        bad.budget = -1
         views = [bad]
     batch, arr = fake_batch(views)
     if case == "zero_views":
