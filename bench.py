@@ -460,9 +460,9 @@ def cpu_baseline(steps, sv_index=(0, 2, 4)):
 FLOPS_PER_PAIR = 18
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE on the
-# default command (profiles/k_blend_fwd_serve1080p_3M_hbm.txt), each scaled by the reading of
-# the same counter for a 1 GiB device copy.  Set to None whenever the kernel changes.
-TRAFFIC = {}
+# same launches as the default run (profiles/k_blend_fwd_serve1080p_3M_hbm.txt), each scaled by
+# the same counter's reading for a 1 GiB device copy.  Emptied whenever the kernel changes.
+TRAFFIC = {"k_blend_fwd": 1520966466}
 
 
 def main():
