@@ -131,42 +131,52 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (mask == 0ull) continue;
-    int e = __builtin_ctzll(mask);
-    mask &= mask - 1;
-    float4 a = s0[e], c = s1[e], bc = s2[e];
-    for (;;) {
-      const bool more = mask != 0ull;
-      const int en = more ? __builtin_ctzll(mask) : e;
-      mask &= mask - 1;
-      const float4 an = s0[en], cn = s1[en], bn = s2[en];
-      if (!done) {
-        const float dx = a.x - pcx, dy = a.y - pcy;
-        const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
-        // Below the entry's cut (or above 0) the contract skips the pair whatever E returns.
-        if (power <= 0.0f && power >= bc.y) {
-          ++nexp;
-          const float prod = c.y * cexp(power);
-          const float al = fminf(0.99f, prod);
-          if (al >= kSkip) {
-            const float Tn = T * (1.0f - al);
-            const uint32_t pos = base - rg.x + (uint32_t)e;
-            if (Tn < kTmin) {
-              done = true;
-              term = pos;
-            } else {
-              ++nblend;
-              const float w = al * T;
-              cr = fmaf_(c.z, w, cr);
-              cg = fmaf_(c.w, w, cg);
-              cb = fmaf_(bc.x, w, cb);
-              T = Tn;
-              last = pos + 1u;
-            }
-          }
-        }
+    // One entry: the contract's skip, exponential, clamp, termination and blend, as
+    // straight-line code under per-lane predicates.  Below the entry's cut (or above 0) the
+    // contract skips the pair whatever E returns; live pairs have power in [cut, 0] with
+    // cut >= ln(1/255) - 0.01, inside cexp_core's range (other lanes' values are discarded).
+    auto pair = [&](const float4& a, const float4& c, const float4& bc, int e) {
+      const float dx = a.x - pcx, dy = a.y - pcy;
+      const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
+      const bool live = !done && power <= 0.0f && power >= bc.y;
+      if (ballot64(live) != 0ull) {
+        const float prod = c.y * cexp_core(power);
+        const float al = fminf(0.99f, prod);
+        const bool use = live && al >= kSkip;
+        const float Tn = T * (1.0f - al);
+        const bool stop = use && Tn < kTmin;
+        const bool blend = use && !stop;
+        const uint32_t pos = base - rg.x + (uint32_t)e;
+        const float w = al * T;
+        cr = blend ? fmaf_(c.z, w, cr) : cr;
+        cg = blend ? fmaf_(c.w, w, cg) : cg;
+        cb = blend ? fmaf_(bc.x, w, cb) : cb;
+        T = blend ? Tn : T;
+        last = blend ? pos + 1u : last;
+        term = stop ? pos : term;
+        done = done || stop;
+        nexp += live ? 1u : 0u;
+        nblend += blend ? 1u : 0u;
       }
+    };
+    // Two register sets in alternation: the LDS reads of the next entry are in flight while
+    // the current one is evaluated, with no copies between iterations.
+    int e0 = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    float4 a0 = s0[e0], c0 = s1[e0], b0 = s2[e0];
+    for (;;) {
+      bool more = mask != 0ull;
+      const int e1 = more ? __builtin_ctzll(mask) : e0;
+      mask &= mask - 1;
+      const float4 a1 = s0[e1], c1 = s1[e1], b1 = s2[e1];
+      pair(a0, c0, b0, e0);
+      if (!more) break;
+      more = mask != 0ull;
+      e0 = more ? __builtin_ctzll(mask) : e1;
+      mask &= mask - 1;
+      a0 = s0[e0]; c0 = s1[e0]; b0 = s2[e0];
+      pair(a1, c1, b1, e1);
       if (!more || ballot64(!done) == 0ull) break;
-      e = en; a = an; c = cn; bc = bn;
     }
   }
   if (inside) {

@@ -91,7 +91,9 @@ __device__ __forceinline__ float fmaf_(float a, float b, float c) { return __bui
 
 // Contract exponential: Cody-Waite reduction with a 16-bit head of ln 2, degree-7 Taylor
 // polynomial (1/j! rounded to binary32) in Horner form, scale by 2^k; zero below -86.
-__device__ __forceinline__ float cexp(float x) {
+// The contract exponential for x in [-86, 88] (no range or NaN handling): cexp below adds
+// those; the blend calls this directly on arguments it has already bounded.
+__device__ __forceinline__ float cexp_core(float x) {
   constexpr float kL2E = 1.44269502162933349609375f;          // fl(1/ln 2)
   constexpr float kLn2Hi = 0.693145751953125f;                // floor(ln2 * 2^16) / 2^16
   constexpr float kLn2Lo = 1.428606765330187045037746429443359375e-06f;  // fl(ln2 - hi)
@@ -100,9 +102,6 @@ __device__ __forceinline__ float cexp(float x) {
   constexpr float c5 = 8.3333337679505348205566406250e-03f;       // fl(1/120)
   constexpr float c4 = 4.1666667908430099487304687500e-02f;       // fl(1/24)
   constexpr float c3 = 1.6666667163372039794921875000e-01f;       // fl(1/6)
-  if (x != x) return x;
-  if (x < -86.0f) return 0.0f;
-  if (x > 88.0f) return __builtin_inff();
   float k = __builtin_rintf(x * kL2E);
   float r = fmaf_(-k, kLn2Hi, x);
   r = fmaf_(-k, kLn2Lo, r);
@@ -116,6 +115,13 @@ __device__ __forceinline__ float cexp(float x) {
   p = fmaf_(p, r, 1.0f);
   int ki = (int)k;
   return p * __uint_as_float((uint32_t)(ki + 127) << 23);
+}
+
+__device__ __forceinline__ float cexp(float x) {
+  if (x != x) return x;
+  if (x < -86.0f) return 0.0f;
+  if (x > 88.0f) return __builtin_inff();
+  return cexp_core(x);
 }
 
 // Real spherical harmonics, l <= 3, order l = 0..3, m = -l..l (Cartesian forms on the unit
