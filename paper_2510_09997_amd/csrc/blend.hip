@@ -28,6 +28,30 @@ __device__ __forceinline__ float entry_cut(float a2) {
   return logf(0.0039215686274509803f / a2) - 0.01f;
 }
 
+// Minimum over the box [X0, X1] x [Y0, Y1] of q(dx, dy) = A dx^2 + 2 B dx dy + C dy^2 (the
+// conic's quadratic form, positive definite): 0 if the box holds the origin, else the least of
+// the four edge minima (each a clamped 1-D vertex).
+__device__ __forceinline__ float box_qmin(float A, float B, float C, float X0, float X1, float Y0, float Y1) {
+  if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return 0.0f;
+  const float bc = B / C, ba = B / A;
+  auto qf = [&](float dx, float dy) { return fmaf(A * dx, dx, fmaf(C * dy, dy, 2.0f * B * dx * dy)); };
+  const float yx0 = fminf(fmaxf(-bc * X0, Y0), Y1), yx1 = fminf(fmaxf(-bc * X1, Y0), Y1);
+  const float xy0 = fminf(fmaxf(-ba * Y0, X0), X1), xy1 = fminf(fmaxf(-ba * Y1, X0), X1);
+  return fminf(fminf(qf(X0, yx0), qf(X1, yx1)), fminf(qf(xy0, Y0), qf(xy1, Y1)));
+}
+
+// Second, tighter test for a quadrant: the entry is dropped if the quadratic form stays above
+// 2.5 |cut| over the box of the quadrant's pixel centres (widened by 1e-3 px for the rounding
+// of the box edges).  With AC / (AC - B^2) <= 5e4 the binary32 evaluation is within 1.2 % of
+// the exact form (and the vertex rounding is negligible), so the exact minimum exceeds
+// 2.4 |cut| and the same argument as the circle test applies.
+__device__ __forceinline__ bool ellipse_reaches(float u, float v, float A, float B, float C, float cut,
+                                                float x0, float y0) {
+  const float X0 = (x0 + 0.499f) - u, X1 = (x0 + 7.501f) - u;
+  const float Y0 = (y0 + 0.499f) - v, Y1 = (y0 + 7.501f) - v;
+  return box_qmin(A, B, C, X0, X1, Y0, Y1) < 2.5f * -cut;
+}
+
 // Conservative per-quadrant cull of a staged entry.  A pixel centre p farther than
 // sqrt(2.4 |cut|) rad / 3 + 0.5 from the 2D mean has exact quadratic form
 // d^T Q d > 2.4 |cut| (rad >= 3 sqrt(lambda_max)), i.e. exact power < -1.2 |cut|.  The binary32
@@ -50,7 +74,7 @@ __device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float A, flo
     const float qx = x0 + (float)((q & 1) * 8), qy = y0 + (float)((q >> 1) * 8);
     const float ddx = fmaxf(0.0f, fmaxf(qx + 0.5f - u, u - (qx + 7.5f)));
     const float ddy = fmaxf(0.0f, fmaxf(qy + 0.5f - v, v - (qy + 7.5f)));
-    if (ddx * ddx + ddy * ddy <= rc2) m |= 1u << q;
+    if (ddx * ddx + ddy * ddy <= rc2 && ellipse_reaches(u, v, A, B, C, cut, qx, qy)) m |= 1u << q;
   }
   return m;
 }
@@ -65,7 +89,7 @@ __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, fl
   const float rc = __builtin_sqrtf(2.4f * -cut) * rad * (1.0f / 3.0f) + 0.5f;
   const float ddx = fmaxf(0.0f, fmaxf(x0 + 0.5f - u, u - (x0 + 7.5f)));
   const float ddy = fmaxf(0.0f, fmaxf(y0 + 0.5f - v, v - (y0 + 7.5f)));
-  return ddx * ddx + ddy * ddy <= rc * rc ? 1u : 0u;
+  return (ddx * ddx + ddy * ddy <= rc * rc && ellipse_reaches(u, v, A, B, C, cut, x0, y0)) ? 1u : 0u;
 }
 
 // Forward blend.  Each wave owns one 8x8 quadrant of a tile (lane l: pixel (l & 7, l >> 3))
