@@ -368,45 +368,40 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     for (int kk = qcnt - 1; kk >= 0; --kk) {
       const int k = list[wave][kk];
       const uint32_t pos = lo - rg.x + (uint32_t)k;
-      bool contrib = false;
-      float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, ga2 = 0.f, gr = 0.f, gg = 0.f, gb = 0.f;
-      if (pos < last) {
-        const float4 a = s0[k];
-        const float4 c = s1[k];
-        const float2 bc = s2[k];
-        const float cb_ = bc.x;
-        const float dx = a.x - pcx, dy = a.y - pcy;
-        const float hA = -0.5f * a.z, nB = -a.w, hC = -0.5f * c.x;
-        const float power = fmaf_(hA * dx, dx, fmaf_(hC * dy, dy, (nB * dx) * dy));
-        if (power <= 0.0f && power >= bc.y) {
-          const float G = cexp(power);
-          const float prod = c.y * G;
-          const float al = fminf(0.99f, prod);
-          if (al >= kSkip) {
-            contrib = true;
-            const float oma = 1.0f - al;
-            const float Tk = T / oma;
-            const float wgt = al * Tk;
-            gr = g0c * wgt;
-            gg = g1c * wgt;
-            gb = g2c * wgt;
-            const float dLda = Tk * (g0c * (c.z - R0) + g1c * (c.w - R1) + g2c * (cb_ - R2));
-            R0 = c.z * al + oma * R0;
-            R1 = c.w * al + oma * R1;
-            R2 = cb_ * al + oma * R2;
-            T = Tk;
-            if (prod <= 0.99f) {
-              ga2 = dLda * G;
-              const float gp = dLda * prod;
-              gu = -gp * (a.z * dx + a.w * dy);
-              gv = -gp * (c.x * dy + a.w * dx);
-              gA = -0.5f * gp * dx * dx;
-              gB = -gp * dx * dy;
-              gC = -0.5f * gp * dy * dy;
-            }
-          }
-        }
-      }
+      const float4 a = s0[k];
+      const float4 c = s1[k];
+      const float2 bc = s2[k];
+      const float cb_ = bc.x;
+      const float dx = a.x - pcx, dy = a.y - pcy;
+      const float hA = -0.5f * a.z, nB = -a.w, hC = -0.5f * c.x;
+      const float power = fmaf_(hA * dx, dx, fmaf_(hC * dy, dy, (nB * dx) * dy));
+      // Straight-line code under per-lane predicates, as in the forward; lanes that are not
+      // live compute discarded values (live powers lie in [cut, 0], inside cexp_core's range).
+      const bool live = pos < last && power <= 0.0f && power >= bc.y;
+      if (ballot64(live) == 0ull) continue;
+      const float G = cexp_core(power);
+      const float prod = c.y * G;
+      const float al = fminf(0.99f, prod);
+      const bool contrib = live && al >= kSkip;
+      const bool geo = contrib && prod <= 0.99f;
+      const float oma = 1.0f - al;
+      const float Tk = T / oma;
+      const float wgt = al * Tk;
+      const float dLda = Tk * (g0c * (c.z - R0) + g1c * (c.w - R1) + g2c * (cb_ - R2));
+      const float gp = dLda * prod;
+      const float gr = contrib ? g0c * wgt : 0.f;
+      const float gg = contrib ? g1c * wgt : 0.f;
+      const float gb = contrib ? g2c * wgt : 0.f;
+      const float ga2 = geo ? dLda * G : 0.f;
+      const float gu = geo ? -gp * (a.z * dx + a.w * dy) : 0.f;
+      const float gv = geo ? -gp * (c.x * dy + a.w * dx) : 0.f;
+      const float gA = geo ? -0.5f * gp * dx * dx : 0.f;
+      const float gB = geo ? -gp * dx * dy : 0.f;
+      const float gC = geo ? -0.5f * gp * dy * dy : 0.f;
+      R0 = contrib ? c.z * al + oma * R0 : R0;
+      R1 = contrib ? c.w * al + oma * R1 : R1;
+      R2 = contrib ? cb_ * al + oma * R2 : R2;
+      T = contrib ? Tk : T;
       if (ballot64(contrib) != 0ull) {
         // Wave totals (uniform), then lane q adds partial q: one LDS atomic instruction.
         const float s0_ = wave_sum_dpp(gu), s1_ = wave_sum_dpp(gv), s2_ = wave_sum_dpp(gA);
