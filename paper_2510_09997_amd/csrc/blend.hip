@@ -403,14 +403,14 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
       R2 = contrib ? cb_ * al + oma * R2 : R2;
       T = contrib ? Tk : T;
       if (ballot64(contrib) != 0ull) {
-        // Wave totals (uniform), then lane q adds partial q: one LDS atomic instruction.
-        const float s0_ = wave_sum_dpp(gu), s1_ = wave_sum_dpp(gv), s2_ = wave_sum_dpp(gA);
-        const float s3_ = wave_sum_dpp(gB), s4_ = wave_sum_dpp(gC), s5_ = wave_sum_dpp(ga2);
-        const float s6_ = wave_sum_dpp(gr), s7_ = wave_sum_dpp(gg), s8_ = wave_sum_dpp(gb);
-        if (lane < (uint32_t)kGscreen) {
-          const float val = lane == 0 ? s0_ : lane == 1 ? s1_ : lane == 2 ? s2_ : lane == 3 ? s3_ :
-                            lane == 4 ? s4_ : lane == 5 ? s5_ : lane == 6 ? s6_ : lane == 7 ? s7_ : s8_;
-          atomicAdd(&acc[lane][k], val);
+        // Wave totals of the nine partials (eight reduced together: lanes 8q.. hold partial q;
+        // the ninth on its own), then one LDS atomic instruction over nine lanes.
+        const float g8[8] = {gu, gv, gA, gB, gC, ga2, gr, gg};
+        const float t8 = wave_sum8(g8);
+        const float tb = wave_sum_dpp(gb);
+        if ((lane & 7u) == 0u || lane == 1u) {
+          const uint32_t q = lane == 1u ? 8u : lane >> 3;
+          atomicAdd(&acc[q][k], lane == 1u ? tb : t8);
         }
       }
     }

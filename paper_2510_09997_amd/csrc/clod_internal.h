@@ -327,6 +327,31 @@ __device__ __forceinline__ float dpp_read(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, kRowMask, 0xF, false));
 }
 
+// Totals over the wave of eight per-lane values at once: lanes 8g .. 8g+7 end with the total of
+// v[g].  Each exchange halves the number of live values: permlane32 swaps (halves of the wave),
+// permlane16 swaps (rows of a half), a rotation by 8 within rows, then three DPP steps within
+// groups of 8 lanes.  18 instructions instead of eight separate reductions.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ float wave_sum8(const float (&v)[8]) {
+  auto swap32 = [](float a, float b) {   // [a_lo + a_hi | b_lo + b_hi]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  };
+  auto swap16 = [](float a, float b) {   // rows [a0 + a1 | b0 + b1 | a2 + a3 | b2 + b3]
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  };
+  const float r0 = swap32(v[0], v[4]), r1 = swap32(v[1], v[5]), r2 = swap32(v[2], v[6]), r3 = swap32(v[3], v[7]);
+  const float s0 = swap16(r0, r2), s1 = swap16(r1, r3);   // rows: (v0 v2 v4 v6), (v1 v3 v5 v7)
+  const bool hi8 = (__lane_id() & 8u) != 0u;
+  const float keep = hi8 ? s1 : s0, send = hi8 ? s0 : s1;
+  float u = keep + dpp_read<0x128, 0xF>(send);           // row_ror:8; lanes 8g..8g+7 hold v[g]
+  u += dpp_read<0x141, 0xF>(u);                          // row_half_mirror
+  u += dpp_read<0x4E, 0xF>(u);                           // quad_perm (2, 3, 0, 1)
+  u += dpp_read<0xB1, 0xF>(u);                           // quad_perm (1, 0, 3, 2)
+  return u;
+}
+
 // Sum over the 64 lanes of a wave with DPP lane moves fused into the adds (no LDS traffic):
 // quad swaps give quad sums, the half-row and row mirrors give row (16-lane) sums, and the
 // two row broadcasts fold rows 0-2 into row 3.  Returns the total as a wave-uniform value.
