@@ -99,6 +99,7 @@ __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, fl
 // LDS reads issued before the current entry's arithmetic.  A wave stops as soon as its 64
 // pixels are saturated, independently of the other quadrants; the only block barrier is the
 // final reduction of the optional pair counters.
+template <bool kCount>
 __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
     const float4* __restrict__ rec, const uint2* __restrict__ ranges,
@@ -177,10 +178,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
         cb = blend ? fmaf_(bc.x, w, cb) : cb;
         T = blend ? Tn : T;
         last = blend ? pos + 1u : last;
-        term = stop ? pos : term;
         done = done || stop;
-        nexp += live ? 1u : 0u;
-        nblend += blend ? 1u : 0u;
+        if (kCount) {   // work counters only when asked for (they cost the per-entry loop)
+          term = stop ? pos : term;
+          nexp += live ? 1u : 0u;
+          nblend += blend ? 1u : 0u;
+        }
       }
     };
     // Two register sets in alternation: the LDS reads of the next entry are in flight while
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     Tout[P + p] = T;
     lastout[P + p] = last;
   }
-  if (pair_part) {
+  if (kCount) {
     // Pairs the contract's per-pixel loop evaluates: up to and including the terminating
     // entry, else the whole list.  One partial per tile (no same-address atomics).
     const unsigned long long ev = !inside ? 0ull : (term != 0xFFFFFFFFu ? (unsigned long long)term + 1ull
@@ -254,7 +257,7 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
     hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_blend_fwd, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
+  hipLaunchKernelGGL(part ? k_blend_fwd<true> : k_blend_fwd<false>, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
                      L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
                      sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
                      prm.bg[2], rgb, T, last, part, (const uint32_t*)(w + L.order));
