@@ -61,7 +61,7 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     n = 3_000_000
     log(f"[bench] scene: {n} Gaussians, SH degree 3, mixture")
     sc = synth.make_scene(n, 3, "mixture", seed=0)
-    scene = Scene(sc)
+    scene = Scene(sc, packed_sh=True)   # static scene: per-Gaussian SH copy
     del sc
     K, W = args.steps, args.warmup
     steps = pose_views(0, K + W)
@@ -373,7 +373,7 @@ def run_lod_sweep(args, torch, C, Batch, Scene, synth):
     the nearest pose."""
     n = 6_000_000
     sc = synth.make_scene(n, 3, "mixture", seed=0)
-    scene = Scene(sc)
+    scene = Scene(sc, packed_sh=True)   # static scene: per-Gaussian SH copy
     del sc
     ds = synth.sweep_distances(64, 2.0, 200.0)
     ray = [synth.look_at((0.0, 0.0, -float(d)), width=1920, height=1080) for d in ds]
@@ -422,7 +422,7 @@ def run_serve_stream(args, torch, Scene, synth):
     from paper_2510_09997_amd.serve import serve, summarize
     n = 3_000_000
     sc = synth.make_scene(n, 3, "mixture", seed=0)
-    scene = Scene(sc)
+    scene = Scene(sc, packed_sh=True)   # static scene: per-Gaussian SH copy
     del sc
     warm = args.serve_warmup
     reqs = synth.poisson_requests(1, warm + args.serve_requests, rate_hz=200.0)

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 7
+#define CLOD_ABI_VERSION 8
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -53,6 +53,11 @@ typedef struct clod_scene {
   int32_t sh_degree;      /* 0..3 */
   int32_t reserved;
   const float *mean, *log_scale, *quat, *opacity, *decay, *sh;
+  const float *sh_packed; /* NULL, or the same SH coefficients laid out per Gaussian,
+                             [n][(sh_degree+1)^2][3]; when set, clod_project reads colours from
+                             it (one contiguous block per Gaussian instead of 3 (deg+1)^2 planes:
+                             far fewer memory lines for the sparse set of rendered Gaussians).
+                             For static scenes (serving); the caller keeps it equal to sh. */
 } clod_scene;
 
 /* Gradient planes, same layout as clod_scene; all must be non-NULL. */

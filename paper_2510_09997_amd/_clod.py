@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 7
+ABI_VERSION = 8
 
 
 class ClodError(RuntimeError):
@@ -36,7 +36,8 @@ P = ctypes.c_void_p
 
 class clod_scene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("mean", P), ("log_scale", P), ("quat", P), ("opacity", P), ("decay", P), ("sh", P)]
+                ("mean", P), ("log_scale", P), ("quat", P), ("opacity", P), ("decay", P), ("sh", P),
+                ("sh_packed", P)]
 
 
 class clod_scene_grad(ctypes.Structure):
@@ -143,6 +144,7 @@ def make_scene(planes: dict) -> clod_scene:
     s.sh_degree = int(planes["sh_degree"])
     for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh"):
         setattr(s, k, _ptr(planes[k]))
+    s.sh_packed = _ptr(planes.get("sh_packed"))
     return s
 
 

@@ -282,8 +282,23 @@ __global__ __launch_bounds__(kBlock) void k_project(
       }
       if (kWriteRecords && rmask) {
         float shc[3 * K];
+        if (sc.sh_packed) {
+          // One contiguous block per Gaussian: [K][3] floats (16-byte aligned when 3K % 4 == 0).
+          const float* src = sc.sh_packed + (int64_t)i * (3 * K);
+          if constexpr ((3 * K) % 4 == 0) {
 #pragma unroll
-        for (int k = 0; k < 3 * K; ++k) shc[k] = sc.sh[(int64_t)k * n + i];
+            for (int k = 0; k < 3 * K; k += 4) {
+              const float4 q = *reinterpret_cast<const float4*>(src + k);
+              shc[k] = q.x; shc[k + 1] = q.y; shc[k + 2] = q.z; shc[k + 3] = q.w;
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < 3 * K; ++k) shc[k] = src[k];
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 3 * K; ++k) shc[k] = sc.sh[(int64_t)k * n + i];
+        }
         uint32_t m = rmask;
         while (m) {
           const int vv = __builtin_ctz(m);

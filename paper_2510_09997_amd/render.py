@@ -19,7 +19,7 @@ PLANES = ("mean", "log_scale", "quat", "opacity", "decay", "sh")
 class Scene:
     """A device-resident scene in the C layout (float32 planes, see include/clod.h)."""
 
-    def __init__(self, planes: dict, device="cuda"):
+    def __init__(self, planes: dict, device="cuda", packed_sh: bool = False):
         self.n = int(planes["n"])
         self.sh_degree = int(planes["sh_degree"])
         self.t = {}
@@ -28,17 +28,26 @@ class Scene:
             if isinstance(v, np.ndarray):
                 v = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32))
             self.t[k] = v.to(device=device, dtype=torch.float32).contiguous()
+        # Static scenes (serving) may also keep the SH coefficients per Gaussian
+        # ([n][K][3]), which the projection gathers far more cheaply for its sparse set.
+        self.sh_packed = None
+        if packed_sh:
+            K = (self.sh_degree + 1) ** 2
+            self.sh_packed = self.t["sh"].view(K, 3, self.n).permute(2, 0, 1).contiguous()
 
     def c_struct(self, planes: dict | None = None) -> C.clod_scene:
         d = dict(self.t if planes is None else planes)
         d["n"], d["sh_degree"] = self.n, self.sh_degree
+        if planes is None and self.sh_packed is not None:
+            d["sh_packed"] = self.sh_packed
         return C.make_scene(d)
 
     def zeros_like(self) -> dict:
         return {k: torch.zeros_like(v) for k, v in self.t.items()}
 
     def nbytes(self) -> int:
-        return sum(v.numel() * 4 for v in self.t.values())
+        extra = 0 if self.sh_packed is None else self.sh_packed.numel() * 4
+        return sum(v.numel() * 4 for v in self.t.values()) + extra
 
 
 def default_params(**kw) -> C.clod_params:

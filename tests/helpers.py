@@ -16,9 +16,9 @@ def params_struct(p: dict | None):
                          dilation=p["dilation"], bg=p["bg"])
 
 
-def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None):
+def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None, packed_sh: bool = False):
     """Runs clod_project, clod_bin_sort and clod_render_fwd; returns host copies."""
-    scene = Scene(sc)
+    scene = Scene(sc, packed_sh=packed_sh)
     b = Batch(sc["n"], views, params_struct(params), dup_capacity=dup_capacity)
     b.project(scene)
     D = b.bin_sort()

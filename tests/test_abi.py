@@ -32,7 +32,7 @@ def test_library_exports_every_declared_entry_point():
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(C.clod_view) == 112
     assert ctypes.sizeof(C.clod_params) == 32
-    assert ctypes.sizeof(C.clod_scene) == 8 + 4 + 4 + 6 * 8
+    assert ctypes.sizeof(C.clod_scene) == 8 + 4 + 4 + 7 * 8
     assert C.clod_batch.ws.offset % 8 == 0
 
 

@@ -55,6 +55,17 @@ def test_multiview_ragged_forward_bitexact():
     compare_forward(g, sc, views, fp64=True)
 
 
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
+def test_packed_sh_forward_bitexact(deg):
+    """The per-Gaussian SH copy of a static scene gives the same bits as the planes."""
+    log(f"case: packed sh deg {deg}")
+    sc = synth.make_scene(15000, deg, "mixture", seed=40 + deg)
+    views = [synth.look_at((2.0, 1.0, -9.0), width=211, height=97, s_v=1.5),
+             synth.look_at((-3.0, 2.0, -8.0), width=120, height=140, s_v=3.0)]
+    g = gpu_forward(sc, views, packed_sh=True)
+    compare_forward(g, sc, views)
+
+
 def test_edge_cases_empty_scene_frustum_and_mask():
     log("case: edges")
     bg = dict(bg=(0.1, 0.2, 0.3))
