@@ -197,12 +197,12 @@ __global__ __launch_bounds__(kBlock) void k_list_scan(const uint32_t* __restrict
 
 // Pass 2 over the work list (entries spread evenly over the blocks): per listed Gaussian the
 // geometry of every view again (cheap), then for in-frustum kept views the EWA projection,
-// cull and rectangle, remembering which views render it; then its SH coefficients are
-// loaded once and the colour of each rendering view is evaluated.  Records, depth, rectangle
+// cull and rectangle, remembering which views render it; then the colour of each rendering
+// view is evaluated from its SH coefficients.  Records, depth, rectangle
 // and tiles touched are written for rendered (view, Gaussian) pairs only.
-template <int DEG, bool kWriteRecords>
-__global__ __launch_bounds__(kBlock) void k_project(
-    clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
+template <int DEG, bool kWriteRecords, bool kPacked>
+__device__ __forceinline__ void project_body(
+    const clod_scene& sc, const DevView* __restrict__ views, int V, const clod_params& prm,
     const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
     const uint32_t* __restrict__ list, const uint32_t* __restrict__ loff, const unsigned long long* __restrict__ hdr,
     uint8_t* __restrict__ flags_out, float* __restrict__ depth_out, float4* __restrict__ rec,
@@ -281,21 +281,12 @@ __global__ __launch_bounds__(kBlock) void k_project(
         if (lane_id() == 0 && bR) atomicAdd(&scnt[v], (uint32_t)__popcll(bR));
       }
       if (kWriteRecords && rmask) {
-        float shc[3 * K];
-        if (sc.sh_packed) {
-          // One contiguous block per Gaussian: [K][3] floats (16-byte aligned when 3K % 4 == 0).
-          const float* src = sc.sh_packed + (int64_t)i * (3 * K);
-          if constexpr ((3 * K) % 4 == 0) {
-#pragma unroll
-            for (int k = 0; k < 3 * K; k += 4) {
-              const float4 q = *reinterpret_cast<const float4*>(src + k);
-              shc[k] = q.x; shc[k + 1] = q.y; shc[k + 2] = q.z; shc[k + 3] = q.w;
-            }
-          } else {
-#pragma unroll
-            for (int k = 0; k < 3 * K; ++k) shc[k] = src[k];
-          }
-        } else {
+        // Plane-major coefficients are gathered once into registers; a packed per-Gaussian
+        // block is instead re-read for every rendering view (cache hits after the first one,
+        // float4 chunks when 3K % 4 == 0), which keeps the kernel at half the registers.
+        // Either way each channel accumulates in coefficient order.
+        float shc[kPacked ? 1 : 3 * K];
+        if constexpr (!kPacked) {
 #pragma unroll
           for (int k = 0; k < 3 * K; ++k) shc[k] = sc.sh[(int64_t)k * n + i];
         }
@@ -311,14 +302,42 @@ __global__ __launch_bounds__(kBlock) void k_project(
           const float id = 1.0f / d;
           float Yb[16];
           sh_basis(DEG, ex * id, ey * id, ez * id, Yb);
+          float acc[3];
+          if constexpr (kPacked) {
+            const float* src = sc.sh_packed + (int64_t)i * (3 * K);
+            if constexpr ((3 * K) % 4 == 0) {
+              const float4* src4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+              for (int q = 0; q < (3 * K) / 4; ++q) {
+                const float4 c4 = src4[q];
+                const float cv[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                  const int idx = 4 * q + e, k = idx / 3, ch = idx % 3;
+                  acc[ch] = k == 0 ? cv[e] * Yb[0] : fmaf_(cv[e], Yb[k], acc[ch]);
+                }
+              }
+            } else {
+#pragma unroll
+              for (int idx = 0; idx < 3 * K; ++idx) {
+                const int k = idx / 3, ch = idx % 3;
+                acc[ch] = k == 0 ? src[idx] * Yb[0] : fmaf_(src[idx], Yb[k], acc[ch]);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+              float a = shc[ch] * Yb[0];
+#pragma unroll
+              for (int k = 1; k < K; ++k) a = fmaf_(shc[3 * k + ch], Yb[k], a);
+              acc[ch] = a;
+            }
+          }
           uint8_t fl = 1u | 2u | 4u;   // rendered implies in frustum and kept
           float col[3];
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) {
-            float acc = shc[ch] * Yb[0];
-#pragma unroll
-            for (int k = 1; k < K; ++k) acc = fmaf_(shc[3 * k + ch], Yb[k], acc);
-            const float cv = acc + 0.5f;
+            const float cv = acc[ch] + 0.5f;
             if (!(cv > 0.0f)) fl |= (uint8_t)(8 << ch);
             col[ch] = fmaxf(cv, 0.0f);
           }
@@ -331,6 +350,30 @@ __global__ __launch_bounds__(kBlock) void k_project(
   __syncthreads();
   for (int j = threadIdx.x; j < V; j += kBlock) cpart[((int64_t)blockIdx.x * V + j) * 3 + 2] = scnt[j];
 }
+
+#define CLOD_PROJECT_ARGS                                                                              \
+  clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,                           \
+      const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart,                  \
+      const uint32_t* __restrict__ list, const uint32_t* __restrict__ loff,                           \
+      const unsigned long long* __restrict__ hdr, uint8_t* __restrict__ flags_out,                    \
+      float* __restrict__ depth_out, float4* __restrict__ rec, uint2* __restrict__ rect_out,          \
+      uint32_t* __restrict__ tiles_out
+
+// Plane-major coefficients (or no records).
+template <int DEG, bool kWriteRecords>
+__global__ __launch_bounds__(kBlock) void k_project(CLOD_PROJECT_ARGS) {
+  project_body<DEG, kWriteRecords, false>(sc, views, V, prm, dmax_key, cpart, list, loff, hdr, flags_out,
+                                          depth_out, rec, rect_out, tiles_out);
+}
+
+// Packed coefficients: fits 128 registers, so four waves per SIMD hide the gather latency.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_project_packed(
+    CLOD_PROJECT_ARGS) {
+  project_body<DEG, true, true>(sc, views, V, prm, dmax_key, cpart, list, loff, hdr, flags_out, depth_out, rec,
+                                rect_out, tiles_out);
+}
+#undef CLOD_PROJECT_ARGS
 
 // Budgeted LoD (a view with budget K, 0 < K < n): the K-th largest selection key, by an MSD
 // radix select over the eight bytes of the 64-bit key.  Pass p histograms byte p (from the top)
@@ -504,11 +547,13 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
   hipLaunchKernelGGL(k_classify<kWrite>, dim3(G), dim3(kBlock), (size_t)(2 * V * sizeof(uint32_t)), s, sc, vinfo,
                      V, prm, dmax_key, cpart, flags, alpha, tiles, list, lcount);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(kBlock), 0, s, (const uint32_t*)lcount, G, loff, hdr);
-  auto kern = k_project<3, kWrite>;
+  // Packed SH is only read when records are written.
+  const bool packed = kWrite && sc.sh_packed != nullptr;
+  auto kern = packed ? k_project_packed<3> : k_project<3, kWrite>;
   switch (sc.sh_degree) {
-    case 0: kern = k_project<0, kWrite>; break;
-    case 1: kern = k_project<1, kWrite>; break;
-    case 2: kern = k_project<2, kWrite>; break;
+    case 0: kern = packed ? k_project_packed<0> : k_project<0, kWrite>; break;
+    case 1: kern = packed ? k_project_packed<1> : k_project<1, kWrite>; break;
+    case 2: kern = packed ? k_project_packed<2> : k_project<2, kWrite>; break;
     default: break;
   }
   hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), (size_t)((G + V) * sizeof(uint32_t)), s, sc, vinfo, V, prm,
