@@ -119,7 +119,7 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.rec = o; o = align256(o + (size_t)L.VN * kRecBytes);
   L.rect = o; o = align256(o + (size_t)L.VN * 8);
   L.tiles = o; o = align256(o + (size_t)L.VN * 4);
-  L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4 * 3);   // pairs, records, emission
+  L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4 * 2);   // records, emission
   L.ranges = o; o = align256(o + (size_t)tiles_total * 8);
   L.order = o; o = align256(o + (size_t)tiles_total * 4);
   L.tord = o; o = align256(o + (size_t)kTileOrderWords * 4);
@@ -270,8 +270,8 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
   const Layout& L = cx.L;
   char* w = (char*)batch->ws;
   DevView* vinfo = (DevView*)(w + L.vinfo);
-  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, s), "view setup");
-  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.hdr), 0u, kHdrWords * 2, s), "clear header");
+  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, (unsigned long long*)(w + L.hdr), s),
+          "view setup");
   HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.kpart),
                              (unsigned long long*)(w + L.dmax_key), s),
           "frustum max");
@@ -375,7 +375,7 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
   const Layout& L = cx.L;
   char* w = (char*)batch->ws;
   DevView* vinfo = (DevView*)(w + L.vinfo);
-  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, s), "view setup");
+  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, nullptr, s), "view setup");
   HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.kpart),
                              (unsigned long long*)(w + L.dmax_key), s),
           "frustum max");

@@ -394,7 +394,7 @@ __device__ __forceinline__ bool lod_kept(const DevView& Vw, float a2, int64_t i)
 // Launchers (each returns hipGetLastError()).
 // ----------------------------------------------------------------------------------------
 hipError_t launch_view_setup(const clod_view* views_dev, int V, clod_params prm, DevView* vinfo,
-                             hipStream_t s);
+                             unsigned long long* hdr /* cleared when non-NULL */, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 int proj_blocks(int64_t n);
 hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V, float near_z,

@@ -10,8 +10,10 @@
 namespace clod {
 
 // Derives per-view constants on the device (graph-replay safe: reads only views_dev).
+// With `hdr` non-NULL the workspace header is cleared as well (a new projection).
 __global__ void k_view_setup(const clod_view* __restrict__ views, int V, clod_params prm,
-                             DevView* __restrict__ out) {
+                             DevView* __restrict__ out, unsigned long long* __restrict__ hdr) {
+  if (hdr && blockIdx.x == 0 && threadIdx.x < (unsigned)kHdrWords) hdr[threadIdx.x] = 0ull;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   uint32_t tile_base = 0, pix_base = 0, loss_base = 0;
   for (int v = 0; v < V; ++v) {
@@ -64,34 +66,60 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
 __global__ __launch_bounds__(kBlock) void k_frustum_max(
     const float* __restrict__ mean, int64_t n, const DevView* __restrict__ views, int V,
     float near_z, unsigned long long* __restrict__ part /* [G][V] */) {
-  __shared__ unsigned long long sm[4];
+  constexpr int kVG = 8;      // views per group (keys held in registers)
+  constexpr int kItems = 8;   // Gaussians per thread per round, loaded before any is used
+  __shared__ unsigned long long sm[kVG][4];
   int64_t lo, hi;
   block_chunk(n, lo, hi);
-  for (int v = 0; v < V; ++v) {
-    const DevView& Vw = views[v];
-    unsigned long long key = 0ull;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-      const float mx = mean[i], my = mean[n + i], mz = mean[2 * n + i];
-      float x, y, z, ex, ey, ez;
-      to_camera(Vw, mx, my, mz, x, y, z);
-      if (in_frustum(Vw, x, y, z, near_z)) {
-        const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
-        const unsigned long long k =
-            ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
-        key = k > key ? k : key;
+  for (int v0 = 0; v0 < V; v0 += kVG) {
+    const int vn = V - v0 < kVG ? V - v0 : kVG;
+    unsigned long long key[kVG];
+#pragma unroll
+    for (int vv = 0; vv < kVG; ++vv) key[vv] = 0ull;
+    for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kItems * kBlock) {
+      float px[kItems], py[kItems], pz[kItems];
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const int64_t i = b0 + (int64_t)k * kBlock + threadIdx.x;
+        const bool valid = i < hi;
+        px[k] = valid ? mean[i] : 0.f;
+        py[k] = valid ? mean[n + i] : 0.f;
+        pz[k] = valid ? mean[2 * n + i] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < kItems; ++k) {
+        const int64_t i = b0 + (int64_t)k * kBlock + threadIdx.x;
+        if (i >= hi) continue;
+#pragma unroll
+        for (int vv = 0; vv < kVG; ++vv) {
+          if (vv >= vn) break;
+          const DevView& Vw = views[v0 + vv];
+          float x, y, z, ex, ey, ez;
+          to_camera(Vw, px[k], py[k], pz[k], x, y, z);
+          if (in_frustum(Vw, x, y, z, near_z)) {
+            const float d = cam_distance(Vw, px[k], py[k], pz[k], ex, ey, ez);
+            const unsigned long long kk =
+                ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+            key[vv] = kk > key[vv] ? kk : key[vv];
+          }
+        }
       }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long other = __shfl_xor(key, o, 64);
-      key = other > key ? other : key;
+    for (int vv = 0; vv < kVG; ++vv) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(key[vv], o, 64);
+        key[vv] = other > key[vv] ? other : key[vv];
+      }
+      if (lane_id() == 0) sm[vv][threadIdx.x >> 6] = key[vv];
     }
-    if (lane_id() == 0) sm[threadIdx.x >> 6] = key;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long m = sm[0];
-      for (int w = 1; w < 4; ++w) m = sm[w] > m ? sm[w] : m;
-      part[(int64_t)blockIdx.x * V + v] = m;
+    if (threadIdx.x < (unsigned)vn) {
+      const int vv = threadIdx.x;
+      unsigned long long m = sm[vv][0];
+      for (int w = 1; w < 4; ++w) m = sm[vv][w] > m ? sm[vv][w] : m;
+      part[(int64_t)blockIdx.x * V + v0 + vv] = m;
     }
     __syncthreads();
   }
@@ -99,7 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
 
 // Pass 1 over every Gaussian (block b owns the chunk [b*C, (b+1)*C)): per view the frustum
 // flag, Eq. (2) and the LoD mask (alpha'' and the F/M flags written for every (view,
-// Gaussian), tiles touched zeroed), F and M counts, and the Gaussians that are in some view's
+// Gaussian)), F and M counts, and the Gaussians that are in some view's
 // frustum and kept by its mask appended to the block's segment of the work list (order
 // within a segment is arbitrary).  Outside those, nothing else is computed, so the heavy
 // pass below runs on full waves instead of the ~40% of lanes a whole-scene pass keeps busy.
@@ -107,7 +135,7 @@ template <bool kWrite>
 __global__ __launch_bounds__(kBlock) void k_classify(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
     const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
-    uint8_t* __restrict__ flags_out, float* __restrict__ alpha_out, uint32_t* __restrict__ tiles_out,
+    uint8_t* __restrict__ flags_out, float* __restrict__ alpha_out,
     uint32_t* __restrict__ list /* [n] */, uint32_t* __restrict__ lcount /* [G] */) {
   extern __shared__ uint32_t scnt[];   // [V][2]
   __shared__ uint32_t sbase;
@@ -143,7 +171,6 @@ __global__ __launch_bounds__(kBlock) void k_classify(
           const int64_t f = (int64_t)v * n + i;
           alpha_out[f] = a2;
           flags_out[f] = (uint8_t)((F ? 1 : 0) | (M ? 2 : 0));
-          tiles_out[f] = 0u;
         }
       }
       any = any || (F && M);
@@ -512,8 +539,8 @@ int proj_blocks(int64_t n) {
 }
 
 hipError_t launch_view_setup(const clod_view* views_dev, int V, clod_params prm, DevView* vinfo,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_view_setup, dim3(1), dim3(64), 0, s, views_dev, V, prm, vinfo);
+                             unsigned long long* hdr, hipStream_t s) {
+  hipLaunchKernelGGL(k_view_setup, dim3(1), dim3(64), 0, s, views_dev, V, prm, vinfo, hdr);
   return hipGetLastError();
 }
 
@@ -545,7 +572,7 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
   const int G = proj_blocks(sc.n);
   uint32_t* loff = lcount + G;
   hipLaunchKernelGGL(k_classify<kWrite>, dim3(G), dim3(kBlock), (size_t)(2 * V * sizeof(uint32_t)), s, sc, vinfo,
-                     V, prm, dmax_key, cpart, flags, alpha, tiles, list, lcount);
+                     V, prm, dmax_key, cpart, flags, alpha, list, lcount);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(kBlock), 0, s, (const uint32_t*)lcount, G, loff, hdr);
   // Packed SH is only read when records are written.
   const bool packed = kWrite && sc.sh_packed != nullptr;

@@ -73,112 +73,104 @@ __device__ __forceinline__ int owner_of(const uint32_t* loff, uint32_t o) {
 }
 
 // ------------------------------------------------------------ step 1: counts and compaction
-// Per chunk of records: tile pairs (sum of tiles touched) and rendered records (tiles > 0).
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ tiles, int64_t count,
-                                                        uint32_t* __restrict__ partD, uint32_t* __restrict__ partR) {
-  __shared__ uint32_t sm[2][4];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  uint32_t s = 0, r = 0;
+// The rendered records are the (view, Gaussian) pairs whose flag byte has bit 2 set (the
+// projection sets it exactly where it writes a tile rectangle).  Thread t of a block owns the
+// 16 records [base + 16t, base + 16t + 16) and reads their flags in one 16-byte load; the
+// result is a 16-bit mask, bit k = record base + 16t + k is rendered.
+__device__ __forceinline__ uint32_t rendered_mask(const uint8_t* __restrict__ flags, int64_t count, int64_t j0) {
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  if (j0 + 16 <= count) {
+    const uint4 q = *reinterpret_cast<const uint4*>(flags + j0);
+    w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+  } else {
+    for (int k = 0; k < 16 && j0 + k < count; ++k) w[k >> 2] |= (uint32_t)flags[j0 + k] << (8 * (k & 3));
+  }
+  uint32_t m = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-    const uint32_t c = j < count ? tiles[j] : 0u;
-    s += c;
-    r += c ? 1u : 0u;
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t b = (w[q] >> 2) & 0x01010101u;   // bit 2 of each byte, at bits 0, 8, 16, 24
+    m |= ((b | (b >> 7) | (b >> 14) | (b >> 21)) & 0xFu) << (4 * q);
   }
-  s = wave_sum(s);
-  r = wave_sum(r);
-  if (lane_id() == 0) { sm[0][threadIdx.x >> 6] = s; sm[1][threadIdx.x >> 6] = r; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    partD[blockIdx.x] = sm[0][0] + sm[0][1] + sm[0][2] + sm[0][3];
-    partR[blockIdx.x] = sm[1][0] + sm[1][1] + sm[1][2] + sm[1][3];
-  }
+  return m;
 }
 
-// Single block: exclusive scans of both partial arrays; D, R and the overflow flag to the
-// header (D is summed in 64 bits, so an overflowing total is still detected).
-__global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__ partD, uint32_t* __restrict__ partR,
-                                                          int nparts, unsigned long long* __restrict__ hdr,
-                                                          int64_t cap) {
+// Per chunk of kScanChunk records: the number of rendered records.  Also clears the per-tile
+// ranges (2 * tiles words) for k_ranges, which writes only the non-empty tiles.
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint8_t* __restrict__ flags, int64_t count,
+                                                        uint32_t* __restrict__ partR, uint32_t* __restrict__ ranges,
+                                                        int64_t range_words) {
   __shared__ uint32_t sm[4];
-  unsigned long long carry = 0;
-  uint32_t rcarry = 0;
-  // kScanItems consecutive partials per thread per round (one block scan per array per round).
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < range_words; q += (int64_t)gridDim.x * kBlock)
+    ranges[q] = 0u;
+  const int64_t j0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  const uint32_t r = wave_sum((uint32_t)__popc(rendered_mask(flags, count, j0)));
+  if (lane_id() == 0) sm[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) partR[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+}
+
+// Single block: exclusive scan of the per-chunk rendered counts; R and the overflow flag
+// (R above the capacity) to the header.  D is not known yet: k_emit_partials stores it.
+// Also clears the counters of the tile ordering (tord).
+__global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__ partR, int nparts,
+                                                          unsigned long long* __restrict__ hdr, int64_t cap,
+                                                          uint32_t* __restrict__ tord) {
+  __shared__ uint32_t sm[4];
+  if (threadIdx.x < kTileOrderWords) tord[threadIdx.x] = 0u;
+  uint32_t carry = 0;
+  // kScanItems consecutive partials per thread per round (one block scan per round).
   for (int base = 0; base < nparts; base += kScanChunk) {
     const int j0 = base + (int)threadIdx.x * kScanItems;
-    uint32_t d[kScanItems], r[kScanItems];
-    unsigned long long sd = 0;
+    uint32_t r[kScanItems];
     uint32_t sr = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-      d[k] = j0 + k < nparts ? partD[j0 + k] : 0u;
       r[k] = j0 + k < nparts ? partR[j0 + k] : 0u;
-      sd += d[k];
       sr += r[k];
     }
-    // Thread sums of pair counts may exceed 32 bits only when the total does; the overflow
-    // flag below is computed from the 64-bit total either way.
-    uint32_t totd, totr;
-    uint32_t exd = block_exclusive_scan((uint32_t)sd, sm, totd);
-    uint32_t exr = block_exclusive_scan(sr, sm, totr);
-    unsigned long long wide = 0;   // 64-bit block total of the pair counts
-    {
-      __shared__ unsigned long long sw[4];
-      const unsigned long long ws = wave_sum(sd);
-      if (lane_id() == 0) sw[threadIdx.x >> 6] = ws;
-      __syncthreads();
-      wide = sw[0] + sw[1] + sw[2] + sw[3];
-      __syncthreads();
-    }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(sr, sm, tot);
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-      if (j0 + k < nparts) {
-        partD[j0 + k] = (uint32_t)carry + exd;
-        partR[j0 + k] = rcarry + exr;
-      }
-      exd += d[k];
-      exr += r[k];
+      if (j0 + k < nparts) partR[j0 + k] = carry + ex;
+      ex += r[k];
     }
-    carry += wide;
-    rcarry += totr;
+    carry += tot;
   }
   if (threadIdx.x == 0) {
-    hdr[kHdrDup] = carry;
-    hdr[kHdrOverflow] = (long long)carry > cap ? 1ull : 0ull;
-    hdr[kHdrRend] = rcarry;
+    hdr[kHdrDup] = 0ull;
+    hdr[kHdrOverflow] = (int64_t)carry > cap ? 1ull : 0ull;
+    hdr[kHdrRend] = carry;
   }
 }
 
 // Rendered records of the chunk, in index order, to [partR[b], ...): key bits(depth), value f.
 // Positions are formed in LDS so the stores are coalesced.
-__global__ __launch_bounds__(kBlock) void k_compact(const uint32_t* __restrict__ tiles, int64_t count,
+__global__ __launch_bounds__(kBlock) void k_compact(const uint8_t* __restrict__ flags, int64_t count,
                                                     const uint32_t* __restrict__ partR,
                                                     const float* __restrict__ depth,
                                                     const unsigned long long* __restrict__ hdr,
                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   __shared__ uint32_t sm[4];
-  __shared__ uint32_t loff[kScanChunk];
   __shared__ uint32_t sf[kScanChunk];
   if (hdr[kHdrOverflow] != 0ull) return;
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   const int t = threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t j = base + (int64_t)k * kBlock + t;
-    loff[k * kBlock + t] = (j < count && tiles[j] != 0u) ? 1u : 0u;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const int64_t j0 = base + (int64_t)t * kScanItems;
+  uint32_t m = rendered_mask(flags, count, j0);
+  uint32_t total;
+  uint32_t o = block_exclusive_scan((uint32_t)__popc(m), sm, total);
+  while (m) {
+    const int k = __builtin_ctz(m);
+    m &= m - 1;
+    sf[o++] = (uint32_t)(j0 + k);
   }
-  uint32_t loc[kScanItems];
-  const uint32_t total = chunk_offsets(loff, sm, loc);
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (loc[k]) sf[loff[t * kScanItems + k]] = (uint32_t)(base + t * kScanItems + k);
   __syncthreads();
   const int64_t out0 = (int64_t)partR[blockIdx.x];
-  for (uint32_t o = (uint32_t)t; o < total; o += kBlock) {
-    const uint32_t f = sf[o];
-    kout[out0 + o] = __float_as_uint(depth[f]);
-    vout[out0 + o] = f;
+  for (uint32_t q = (uint32_t)t; q < total; q += kBlock) {
+    const uint32_t f = sf[q];
+    kout[out0 + q] = __float_as_uint(depth[f]);
+    vout[out0 + q] = f;
   }
 }
 
@@ -361,42 +353,75 @@ static void radix_passes(const unsigned long long* hdr, int cw, int G, int first
 }
 
 // ---------------------------------------------------------------- step 3: ordered emission
-// Per chunk of the depth-sorted records: tile pairs of the chunk.
+// Per chunk of the depth-sorted records: tile pairs of the chunk (saturated at 2^32 - 1,
+// which only a total far beyond any capacity reaches).  If R alone exceeded the capacity
+// (the only way the overflow flag can be set at this point) the records were never sorted;
+// the pair count is then summed over chunk b of all records instead, so that D is still
+// reported.
 __global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restrict__ sorted_f,
                                                         const uint32_t* __restrict__ tiles,
+                                                        const uint8_t* __restrict__ flags, int64_t count,
                                                         const unsigned long long* __restrict__ hdr,
                                                         uint32_t* __restrict__ partE) {
-  __shared__ uint32_t sm[4];
-  if (hdr[kHdrOverflow] != 0ull) return;
+  __shared__ unsigned long long sm[4];
+  const bool over = hdr[kHdrOverflow] != 0ull;
   const int64_t R = (int64_t)hdr[kHdrRend];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  if (base >= R) return;
-  uint32_t s = 0;
+  if (!over && base >= R) return;
+  unsigned long long s = 0;
+  if (!over) {
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-    if (j < R) s += tiles[sorted_f[j]];
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
+      if (j < R) s += tiles[sorted_f[j]];
+    }
+  } else {
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
+      if (j < count && (flags[j] & 4u)) s += tiles[j];
+    }
   }
   s = wave_sum(s);
   if (lane_id() == 0) sm[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) partE[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+  if (threadIdx.x == 0) {
+    const unsigned long long c = sm[0] + sm[1] + sm[2] + sm[3];
+    partE[blockIdx.x] = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
+  }
 }
 
-// Single block: exclusive scan of the chunk totals (ceil(R / chunk) of them).
+// Single block: D (summed in 64 bits) and the overflow flag (D above the capacity) to the
+// header, and, unless overflowed, the exclusive scan of the chunk totals in place.
 __global__ __launch_bounds__(kBlock) void k_emit_partials(uint32_t* __restrict__ partE,
-                                                          const unsigned long long* __restrict__ hdr) {
-  __shared__ uint32_t sm[4];
-  if (hdr[kHdrOverflow] != 0ull) return;
-  const int nparts = (int)(((int64_t)hdr[kHdrRend] + kScanChunk - 1) / kScanChunk);
-  uint32_t carry = 0;
+                                                          unsigned long long* __restrict__ hdr, int nb,
+                                                          int64_t cap) {
+  __shared__ unsigned long long sm[4];
+  const bool over = hdr[kHdrOverflow] != 0ull;
+  const int nparts = over ? nb : (int)(((int64_t)hdr[kHdrRend] + kScanChunk - 1) / kScanChunk);
+  const uint32_t lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  unsigned long long carry = 0;
   for (int base = 0; base < nparts; base += kBlock) {
     const int j = base + threadIdx.x;
-    const uint32_t v = j < nparts ? partE[j] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan(v, sm, total);
-    if (j < nparts) partE[j] = carry + ex;
-    carry += total;
+    const unsigned long long v = j < nparts ? partE[j] : 0ull;
+    unsigned long long inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long up = __shfl_up(inc, o, 64);
+      if (lane >= (uint32_t)o) inc += up;
+    }
+    if (lane == 63) sm[wave] = inc;
+    __syncthreads();
+    unsigned long long wb = 0;
+    for (int w = 0; w < wave; ++w) wb += sm[w];
+    const unsigned long long tot = sm[0] + sm[1] + sm[2] + sm[3];
+    __syncthreads();
+    if (!over && j < nparts) partE[j] = (uint32_t)(carry + wb + inc - v);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    hdr[kHdrDup] = carry;
+    if ((int64_t)carry > cap) hdr[kHdrOverflow] = 1ull;
   }
 }
 
@@ -503,23 +528,31 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
   uint32_t* const v[2] = {(uint32_t*)(dp + D.vals0), (uint32_t*)(dp + D.vals1)};
   uint32_t* hist = (uint32_t*)(dp + D.hist);
   const int nb = L.scan_blocks;
-  if (nb == 0) return launch_fill_u32((uint32_t*)hdr, 0u, 2 * kHdrWords, s);
-  uint32_t* partD = (uint32_t*)(w + L.scan_part);
-  uint32_t* partR = partD + (nb + 1);
+  uint32_t* ranges = (uint32_t*)(w + L.ranges);
+  uint32_t* tord = (uint32_t*)(w + L.tord);
+  if (nb == 0) {
+    hipError_t e = launch_fill_u32((uint32_t*)hdr, 0u, 2 * kHdrWords, s);
+    if (e == hipSuccess) e = launch_fill_u32(ranges, 0u, 2 * (int64_t)L.tiles_total, s);
+    if (e == hipSuccess) e = launch_fill_u32(tord, 0u, kTileOrderWords, s);
+    return e;
+  }
+  uint32_t* partR = (uint32_t*)(w + L.scan_part);
   uint32_t* partE = partR + (nb + 1);
   const uint32_t* tiles = (const uint32_t*)(w + L.tiles);
+  const uint8_t* flags = (const uint8_t*)(w + L.flags);
   const int G = sort_blocks(D.cap);
-  // 1. counts, D, R, overflow; compaction of the rendered records into buffer 0.
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, tiles, L.VN, partD, partR);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partD, partR, nb, hdr, D.cap);
-  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(kBlock), 0, s, tiles, L.VN, (const uint32_t*)partR,
+  // 1. R and its overflow; compaction of the rendered records into buffer 0.
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, flags, L.VN, partR, ranges,
+                     2 * (int64_t)L.tiles_total);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partR, nb, hdr, D.cap, tord);
+  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(kBlock), 0, s, flags, L.VN, (const uint32_t*)partR,
                      (const float*)(w + L.depth), (const unsigned long long*)hdr, k[0], v[0]);
   // 2. depth sort of the R records: 4 passes, back in buffer 0.
   radix_passes(hdr, kHdrRend, G, 0, 4, k, v, 0, hist, s);
   // 3. emission in depth order into buffer 1.
-  hipLaunchKernelGGL(k_emit_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], tiles,
+  hipLaunchKernelGGL(k_emit_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], tiles, flags, L.VN,
                      (const unsigned long long*)hdr, partE);
-  hipLaunchKernelGGL(k_emit_partials, dim3(1), dim3(kBlock), 0, s, partE, (const unsigned long long*)hdr);
+  hipLaunchKernelGGL(k_emit_partials, dim3(1), dim3(kBlock), 0, s, partE, hdr, nb, D.cap);
   uint32_t* owner = (uint32_t*)(dp + D.owner);
   hipLaunchKernelGGL(k_emit_offsets, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], tiles,
                      (const uint32_t*)partE, (const unsigned long long*)hdr, k[0], owner);
@@ -603,8 +636,8 @@ hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* du
                          hipStream_t s) {
   char* w = (char*)ws;
   char* dp = (char*)dup;
-  hipError_t e = launch_fill_u32((uint32_t*)(w + L.ranges), 0u, 2 * (int64_t)L.tiles_total, s);
-  if (e != hipSuccess) return e;
+  // The ranges and the ordering counters were cleared by launch_bin_sort.
+  hipError_t e = hipSuccess;
   const uint32_t* keys = (const uint32_t*)(dp + (parity ? D.keys1 : D.keys0));
   int64_t g = (D.cap + kBlock - 1) / kBlock;
   if (g > 8192) g = 8192;
@@ -613,8 +646,6 @@ hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* du
                      (const unsigned long long*)(w + L.hdr), L.tiles_total, (uint2*)(w + L.ranges));
   if (L.tiles_total > 0) {
     uint32_t* tord = (uint32_t*)(w + L.tord);
-    e = launch_fill_u32(tord, 0u, kTileOrderWords, s);
-    if (e != hipSuccess) return e;
     const unsigned nb = (L.tiles_total + kTileOrderChunk - 1) / kTileOrderChunk;
     hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(kBlock), 0, s, (const uint2*)(w + L.ranges), L.tiles_total,
                        (const unsigned long long*)(w + L.hdr), tord);

@@ -146,6 +146,7 @@ def test_capacity_overflow_is_reported_and_retry_succeeds():
     scene = Scene(sc)
     b = Batch(sc["n"], [v], params_struct(None), dup_capacity=100)
     b.project(scene)
+    assert int(b.counts[:, 2].sum().item()) > b.capacity   # even the rendered records overflow
     with pytest.raises(C.CapacityError):
         C.clod_bin_sort(b.c_struct(), sync_count=True)
     info = C.clod_read_info(b.c_struct())
@@ -155,6 +156,32 @@ def test_capacity_overflow_is_reported_and_retry_succeeds():
     g = gpu_forward(sc, [v])
     rgb, T, last = b.render_fwd()
     assert torch.equal(last, g["last_flat"]) and torch.equal(rgb, g["rgb_flat"])
+
+
+def test_capacity_between_rendered_and_pair_counts():
+    """Capacity at least R (the depth sort of the rendered records fits) but below D (the
+    emission does not): the overflow and the exact D are still reported, and a retry with a
+    larger buffer renders exactly."""
+    log("case: capacity between R and D")
+    sc = synth.make_scene(8000, 0, "uniform", seed=7)
+    v = synth.look_at((0, 0, -3), width=200, height=160)
+    scene = Scene(sc)
+    full = Batch(sc["n"], [v], params_struct(None))
+    full.project(scene)
+    D = full.bin_sort()
+    R = int(full.counts[:, 2].sum().item())
+    assert 0 < R < D
+    b = Batch(sc["n"], [v], params_struct(None), dup_capacity=(R + D) // 2)
+    assert R <= b.capacity < D
+    b.project(scene)
+    with pytest.raises(C.CapacityError):
+        C.clod_bin_sort(b.c_struct(), sync_count=True)
+    info = C.clod_read_info(b.c_struct())
+    assert info["overflow"] and info["n_dup"] == D
+    assert b.bin_sort() == D
+    rgb, T, last = b.render_fwd()
+    rgb0, T0, last0 = full.render_fwd()
+    assert torch.equal(last, last0) and torch.equal(rgb, rgb0) and torch.equal(T, T0)
 
 
 # --------------------------------------------------------------------------- gradients
