@@ -107,7 +107,7 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.ssim_acc = o; o = align256(o + (size_t)V * 4);
   L.loss_part = o; o = align256(o + ((size_t)tiles_total * 3 + (size_t)pixels_total * 3 / kLossChunk + V) * 4);
   L.kpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 8);
-  L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 3 * 4);
+  L.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4 * 4);
   L.gpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4);
   L.sel_state = o; o = align256(o + (size_t)V * sizeof(SelState));
   L.sel_hist = o; o = align256(o + (L.any_budget ? (size_t)V * kSelBlocks * 256 * 4 : 0));
@@ -279,7 +279,7 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
     HIP_TRY(launch_lod_select(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
                               (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
             "budget select");
-  HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
+  HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
                          (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags),
                          (float*)(w + L.alpha), (float*)(w + L.depth), (float4*)(w + L.rec), (uint2*)(w + L.rect),
                          (uint32_t*)(w + L.tiles), (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount),
@@ -383,7 +383,7 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
     HIP_TRY(launch_lod_select(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
                               (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
             "budget select");
-  HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
+  HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
                            (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts),
                            (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), (unsigned long long*)(w + L.hdr), s),
           "lod count");

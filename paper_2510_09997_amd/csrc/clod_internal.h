@@ -176,12 +176,19 @@ __device__ __forceinline__ bool in_frustum(const DevView& V, float x, float y, f
   return (z > near_z) && (fabsf(x) <= V.limx * z) && (fabsf(y) <= V.limy * z);
 }
 
-__device__ __forceinline__ float cam_distance(const DevView& V, float mx, float my, float mz,
-                                              float& ex, float& ey, float& ez) {
+// Squared camera distance; cam_distance is its correctly rounded square root, so the maximum
+// distance over a set is the root of the maximum of these.
+__device__ __forceinline__ float cam_distance2(const DevView& V, float mx, float my, float mz,
+                                               float& ex, float& ey, float& ez) {
   ex = mx - V.c[0];
   ey = my - V.c[1];
   ez = mz - V.c[2];
-  return __builtin_sqrtf(fmaf_(ex, ex, fmaf_(ey, ey, ez * ez)));
+  return fmaf_(ex, ex, fmaf_(ey, ey, ez * ez));
+}
+
+__device__ __forceinline__ float cam_distance(const DevView& V, float mx, float my, float mz,
+                                              float& ex, float& ey, float& ez) {
+  return __builtin_sqrtf(cam_distance2(V, mx, my, mz, ex, ey, ez));
 }
 
 __device__ __forceinline__ float sigmoid_c(float o) { return 1.0f / (1.0f + cexp(-o)); }
@@ -400,12 +407,12 @@ int proj_blocks(int64_t n);
 hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V, float near_z,
                               unsigned long long* kpart, unsigned long long* dmax_key, hipStream_t s);
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                          const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
+                          unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                           uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
                           uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
                           hipStream_t s);
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                            const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
+                            unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s);
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s);
 

@@ -61,8 +61,11 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
 // counts); k_reduce_partials folds them per view.  Same-address atomics from every wave
 // serialise in L2 and would dominate these otherwise bandwidth-bound kernels.
 
-// Frustum maximum of d per view: key = bits(d) << 32 | (2^32 - 1 - i), so the 64-bit
-// maximum is the largest distance and, among equal distances, the lowest index.
+// Frustum maximum of the squared distance per view, as the float bits (order-preserving for
+// non-negative values; 0 = no Gaussian in the frustum).  k_reduce_partials turns the maximum
+// into the key bits(d_max) << 32 (d_max its correctly rounded root, the largest distance),
+// and k_classify finds the lowest index at that distance, which completes the key with
+// 2^32 - 1 - index (so that ties resolve to the lowest index).
 __global__ __launch_bounds__(kBlock) void k_frustum_max(
     const float* __restrict__ mean, int64_t n, const DevView* __restrict__ views, int V,
     float near_z, unsigned long long* __restrict__ part /* [G][V] */) {
@@ -73,9 +76,9 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
   block_chunk(n, lo, hi);
   for (int v0 = 0; v0 < V; v0 += kVG) {
     const int vn = V - v0 < kVG ? V - v0 : kVG;
-    unsigned long long key[kVG];
+    uint32_t key[kVG];
 #pragma unroll
-    for (int vv = 0; vv < kVG; ++vv) key[vv] = 0ull;
+    for (int vv = 0; vv < kVG; ++vv) key[vv] = 0u;
     for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kItems * kBlock) {
       float px[kItems], py[kItems], pz[kItems];
 #pragma unroll
@@ -97,9 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
           float x, y, z, ex, ey, ez;
           to_camera(Vw, px[k], py[k], pz[k], x, y, z);
           if (in_frustum(Vw, x, y, z, near_z)) {
-            const float d = cam_distance(Vw, px[k], py[k], pz[k], ex, ey, ez);
-            const unsigned long long kk =
-                ((unsigned long long)__float_as_uint(d) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+            const uint32_t kk = __float_as_uint(cam_distance2(Vw, px[k], py[k], pz[k], ex, ey, ez));
             key[vv] = kk > key[vv] ? kk : key[vv];
           }
         }
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
     for (int vv = 0; vv < kVG; ++vv) {
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long other = __shfl_xor(key[vv], o, 64);
+        const uint32_t other = __shfl_xor(key[vv], o, 64);
         key[vv] = other > key[vv] ? other : key[vv];
       }
       if (lane_id() == 0) sm[vv][threadIdx.x >> 6] = key[vv];
@@ -134,13 +135,13 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
 template <bool kWrite>
 __global__ __launch_bounds__(kBlock) void k_classify(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
-    const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
+    const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][4] */,
     uint8_t* __restrict__ flags_out, float* __restrict__ alpha_out,
     uint32_t* __restrict__ list /* [n] */, uint32_t* __restrict__ lcount /* [G] */) {
-  extern __shared__ uint32_t scnt[];   // [V][2]
+  extern __shared__ uint32_t scnt[];   // [V][3]: F count, M count, lowest index at d_max
   __shared__ uint32_t sbase;
   const int64_t n = sc.n;
-  for (int j = threadIdx.x; j < 2 * V; j += kBlock) scnt[j] = 0;
+  for (int j = threadIdx.x; j < 3 * V; j += kBlock) scnt[j] = j % 3 == 2 ? 0xFFFFFFFFu : 0u;
   if (threadIdx.x == 0) sbase = 0;
   __syncthreads();
   int64_t lo, hi;
@@ -164,8 +165,10 @@ __global__ __launch_bounds__(kBlock) void k_classify(
         to_camera(Vw, mx, my, mz, x, y, z);
         F = in_frustum(Vw, x, y, z, prm.near_z);
         const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
+        const unsigned long long dk = dmax_key[v];
+        if (F && dk != 0ull && __float_as_uint(d) == (uint32_t)(dk >> 32)) atomicMin(&scnt[3 * v + 2], (uint32_t)i);
         float alpha, q;
-        const float a2 = attenuated(d, dmax_from_key(dmax_key[v]), Vw.s_v, dc, op, prm.eps, alpha, q);
+        const float a2 = attenuated(d, dmax_from_key(dk), Vw.s_v, dc, op, prm.eps, alpha, q);
         M = lod_kept(Vw, a2, i);
         if (kWrite) {
           const int64_t f = (int64_t)v * n + i;
@@ -176,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(
       any = any || (F && M);
       const uint64_t bF = ballot64(F), bM = ballot64(M);
       if (lane_id() == 0) {
-        if (bF) atomicAdd(&scnt[2 * v + 0], (uint32_t)__popcll(bF));
-        if (bM) atomicAdd(&scnt[2 * v + 1], (uint32_t)__popcll(bM));
+        if (bF) atomicAdd(&scnt[3 * v + 0], (uint32_t)__popcll(bF));
+        if (bM) atomicAdd(&scnt[3 * v + 1], (uint32_t)__popcll(bM));
       }
     }
     const uint64_t bw = ballot64(any);
@@ -188,8 +191,9 @@ __global__ __launch_bounds__(kBlock) void k_classify(
   }
   __syncthreads();
   for (int j = threadIdx.x; j < V; j += kBlock) {
-    cpart[((int64_t)blockIdx.x * V + j) * 3 + 0] = scnt[2 * j];
-    cpart[((int64_t)blockIdx.x * V + j) * 3 + 1] = scnt[2 * j + 1];
+    cpart[((int64_t)blockIdx.x * V + j) * 4 + 0] = scnt[3 * j];
+    cpart[((int64_t)blockIdx.x * V + j) * 4 + 1] = scnt[3 * j + 1];
+    cpart[((int64_t)blockIdx.x * V + j) * 4 + 3] = scnt[3 * j + 2];
   }
   if (threadIdx.x == 0) lcount[blockIdx.x] = sbase;
 }
@@ -230,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_list_scan(const uint32_t* __restrict
 template <int DEG, bool kWriteRecords, bool kPacked>
 __device__ __forceinline__ void project_body(
     const clod_scene& sc, const DevView* __restrict__ views, int V, const clod_params& prm,
-    const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][3] */,
+    const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][4] */,
     const uint32_t* __restrict__ list, const uint32_t* __restrict__ loff, const unsigned long long* __restrict__ hdr,
     uint8_t* __restrict__ flags_out, float* __restrict__ depth_out, float4* __restrict__ rec,
     uint2* __restrict__ rect_out, uint32_t* __restrict__ tiles_out) {
@@ -375,7 +379,7 @@ __device__ __forceinline__ void project_body(
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < V; j += kBlock) cpart[((int64_t)blockIdx.x * V + j) * 3 + 2] = scnt[j];
+  for (int j = threadIdx.x; j < V; j += kBlock) cpart[((int64_t)blockIdx.x * V + j) * 4 + 2] = scnt[j];
 }
 
 #define CLOD_PROJECT_ARGS                                                                              \
@@ -486,23 +490,29 @@ hipError_t launch_lod_select(const clod_scene& sc, DevView* vinfo, int V, clod_p
   return hipGetLastError();
 }
 
-// Block v folds the G partials of view v: the frustum-max key (max) and the counts (sum).
+// Block v folds the G partials of view v.  With kpart: the maximum squared distance, stored
+// as the key bits(sqrt(max)) << 32 (0 if the frustum is empty).  With cpart: the counts (sum)
+// and the lowest index at d_max (min), which completes the low half of that key.
 __global__ __launch_bounds__(kBlock) void k_reduce_partials(const unsigned long long* __restrict__ kpart,
                                                             const uint32_t* __restrict__ cpart, int G, int V,
                                                             unsigned long long* __restrict__ dmax_key,
                                                             unsigned long long* __restrict__ counts) {
   __shared__ unsigned long long sm[4][4];
+  __shared__ uint32_t smin[4];
   const int v = blockIdx.x;
   unsigned long long key = 0ull, c0 = 0, c1 = 0, c2 = 0;
+  uint32_t imin = 0xFFFFFFFFu;
   for (int b = threadIdx.x; b < G; b += kBlock) {
     if (kpart) {
       const unsigned long long k = kpart[(int64_t)b * V + v];
       key = k > key ? k : key;
     }
     if (cpart) {
-      c0 += cpart[((int64_t)b * V + v) * 3 + 0];
-      c1 += cpart[((int64_t)b * V + v) * 3 + 1];
-      c2 += cpart[((int64_t)b * V + v) * 3 + 2];
+      const uint32_t* c = cpart + ((int64_t)b * V + v) * 4;
+      c0 += c[0];
+      c1 += c[1];
+      c2 += c[2];
+      imin = c[3] < imin ? c[3] : imin;
     }
   }
 #pragma unroll
@@ -512,17 +522,27 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const unsigned long 
     c0 += __shfl_xor(c0, o, 64);
     c1 += __shfl_xor(c1, o, 64);
     c2 += __shfl_xor(c2, o, 64);
+    const uint32_t om = __shfl_xor(imin, o, 64);
+    imin = om < imin ? om : imin;
   }
   const int w = threadIdx.x >> 6;
-  if (lane_id() == 0) { sm[w][0] = key; sm[w][1] = c0; sm[w][2] = c1; sm[w][3] = c2; }
+  if (lane_id() == 0) { sm[w][0] = key; sm[w][1] = c0; sm[w][2] = c1; sm[w][3] = c2; smin[w] = imin; }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int j = 1; j < 4; ++j) {
       key = sm[j][0] > key ? sm[j][0] : key;
       c0 += sm[j][1]; c1 += sm[j][2]; c2 += sm[j][3];
+      imin = smin[j] < imin ? smin[j] : imin;
     }
-    if (kpart) dmax_key[v] = key;
-    if (cpart) { counts[3 * v] = c0; counts[3 * v + 1] = c1; counts[3 * v + 2] = c2; }
+    if (kpart) {
+      const float d2 = __uint_as_float((uint32_t)key);
+      dmax_key[v] = key ? (unsigned long long)__float_as_uint(__builtin_sqrtf(d2)) << 32 : 0ull;
+    }
+    if (cpart) {
+      counts[3 * v] = c0; counts[3 * v + 1] = c1; counts[3 * v + 2] = c2;
+      const unsigned long long dk = dmax_key[v];
+      if (dk) dmax_key[v] = (dk & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - imin);
+    }
   }
 }
 
@@ -564,14 +584,14 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
 
 template <bool kWrite>
 static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                               const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
+                               unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                                uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
                                uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
                                hipStream_t s) {
   if (sc.n == 0) return launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
   const int G = proj_blocks(sc.n);
   uint32_t* loff = lcount + G;
-  hipLaunchKernelGGL(k_classify<kWrite>, dim3(G), dim3(kBlock), (size_t)(2 * V * sizeof(uint32_t)), s, sc, vinfo,
+  hipLaunchKernelGGL(k_classify<kWrite>, dim3(G), dim3(kBlock), (size_t)(3 * V * sizeof(uint32_t)), s, sc, vinfo,
                      V, prm, dmax_key, cpart, flags, alpha, list, lcount);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(kBlock), 0, s, (const uint32_t*)lcount, G, loff, hdr);
   // Packed SH is only read when records are written.
@@ -587,12 +607,12 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
                      dmax_key, cpart, (const uint32_t*)list, (const uint32_t*)loff,
                      (const unsigned long long*)hdr, flags, depth, rec, rect, tiles);
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
-                     (const uint32_t*)cpart, G, V, (unsigned long long*)nullptr, counts);
+                     (const uint32_t*)cpart, G, V, dmax_key, counts);
   return hipGetLastError();
 }
 
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                          const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
+                          unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                           uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
                           uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
                           hipStream_t s) {
@@ -601,7 +621,7 @@ hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clo
 }
 
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
-                            const unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
+                            unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s) {
   return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, nullptr,
                              nullptr, nullptr, list, lcount, hdr, s);

@@ -354,7 +354,8 @@ static void radix_passes(const unsigned long long* hdr, int cw, int G, int first
 
 // ---------------------------------------------------------------- step 3: ordered emission
 // Per chunk of the depth-sorted records: tile pairs of the chunk (saturated at 2^32 - 1,
-// which only a total far beyond any capacity reaches).  If R alone exceeded the capacity
+// which only a total far beyond any capacity reaches); the gathered counts are also stored in
+// sorted order (tsorted) for k_emit_offsets.  If R alone exceeded the capacity
 // (the only way the overflow flag can be set at this point) the records were never sorted;
 // the pair count is then summed over chunk b of all records instead, so that D is still
 // reported.
@@ -362,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restri
                                                         const uint32_t* __restrict__ tiles,
                                                         const uint8_t* __restrict__ flags, int64_t count,
                                                         const unsigned long long* __restrict__ hdr,
-                                                        uint32_t* __restrict__ partE) {
+                                                        uint32_t* __restrict__ partE, uint32_t* __restrict__ tsorted) {
   __shared__ unsigned long long sm[4];
   const bool over = hdr[kHdrOverflow] != 0ull;
   const int64_t R = (int64_t)hdr[kHdrRend];
@@ -373,7 +374,11 @@ __global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restri
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
       const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-      if (j < R) s += tiles[sorted_f[j]];
+      if (j < R) {
+        const uint32_t c = tiles[sorted_f[j]];
+        tsorted[j] = c;
+        s += c;
+      }
     }
   } else {
     for (int k = 0; k < kScanItems; ++k) {
@@ -429,8 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_partials(uint32_t* __restrict__
 // exclusive scan of their tile counts, over the R positions of the record keys, which the
 // sort no longer needs), and for every output chunk of kEmitTile pairs the record that owns
 // its first position.
-__global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restrict__ sorted_f,
-                                                         const uint32_t* __restrict__ tiles,
+__global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restrict__ tsorted,
                                                          const uint32_t* __restrict__ partE,
                                                          const unsigned long long* __restrict__ hdr,
                                                          uint32_t* __restrict__ eoff, uint32_t* __restrict__ owner) {
@@ -444,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restr
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t j = base + (int64_t)k * kBlock + t;
-    loff[k * kBlock + t] = j < R ? tiles[sorted_f[j]] : 0u;
+    loff[k * kBlock + t] = j < R ? tsorted[j] : 0u;
   }
   uint32_t loc[kScanItems];
   const uint32_t total = chunk_offsets(loff, sm, loc);
@@ -461,10 +465,11 @@ __global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restr
 
 // Output chunk q (pairs [q*M, q*M + M), M = kEmitTile) is produced by the records between
 // the owner of its first pair and the owner of the next chunk's first pair (at most M + 1
-// of them, since every record has at least one pair); their offsets and indices are staged
-// in LDS, and pair o belongs to the last staged record whose offset is <= o, as that
-// record's (o - offset)-th covered tile in row-major order.  Chunks are equal-sized whatever
-// the rectangle sizes, and every store is coalesced.
+// of them, since every record has at least one pair).  Each of them is staged in LDS once:
+// its first output offset, its index f, the id of the first tile of its rectangle, the
+// rectangle width, the view's tile row length and 1/width.  Pair o belongs to the last staged
+// record whose offset is <= o, as that record's (o - offset)-th covered tile in row-major
+// order.  Chunks are equal-sized whatever the rectangle sizes, and every store is coalesced.
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ sorted_f,
                                                  const uint32_t* __restrict__ eoff,
                                                  const uint32_t* __restrict__ owner,
@@ -473,6 +478,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ so
                                                  uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   __shared__ uint32_t se[kEmitTile + 1];
   __shared__ uint32_t sf[kEmitTile + 1];
+  __shared__ uint32_t sb[kEmitTile + 1];   // tile id of the rectangle's first tile
+  __shared__ uint32_t sw[kEmitTile + 1];   // width | tiles_x << 16
+  __shared__ float sr[kEmitTile + 1];      // 1 / width
   if (hdr[kHdrOverflow] != 0ull) return;
   const int64_t R = (int64_t)hdr[kHdrRend];
   const int64_t D = (int64_t)hdr[kHdrDup];
@@ -484,8 +492,16 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ so
     int cnt = (int)(k1 - k0 + 1);
     if (cnt > kEmitTile + 1) cnt = kEmitTile + 1;   // cannot happen (see above); keeps LDS in bounds
     for (int i = threadIdx.x; i < cnt; i += kBlock) {
+      const uint32_t f = sorted_f[k0 + i];
+      const DevView& Vw = views[f / nn];
+      const uint2 rc = rect[f];
+      const uint32_t x0 = rc.x & 0xFFFFu, x1 = rc.x >> 16, y0 = rc.y & 0xFFFFu;
+      const uint32_t w = x1 - x0, tx = (uint32_t)Vw.tiles_x;
       se[i] = eoff[k0 + i];
-      sf[i] = sorted_f[k0 + i];
+      sf[i] = f;
+      sb[i] = Vw.tile_base + y0 * tx + x0;
+      sw[i] = w | (tx << 16);
+      sr[i] = 1.0f / (float)w;
     }
     __syncthreads();
     const int64_t o0 = q * kEmitTile;
@@ -498,14 +514,16 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ so
         if (se[mid] <= o) lo = mid; else hi = mid - 1;
       }
       const uint32_t rel = o - se[lo];
-      const uint32_t f = sf[lo];
-      const DevView& Vw = views[f / nn];
-      const uint2 rc = rect[f];
-      const uint32_t x0 = rc.x & 0xFFFFu, x1 = rc.x >> 16, y0 = rc.y & 0xFFFFu;
-      const uint32_t w = x1 - x0;
-      const uint32_t ty = y0 + rel / w, tx = x0 + rel % w;
-      kout[og] = Vw.tile_base + ty * (uint32_t)Vw.tiles_x + tx;
-      vout[og] = f;
+      const uint32_t wx = sw[lo];
+      const uint32_t w = wx & 0xFFFFu;
+      // Row of the pair: rel / w from the rounded reciprocal (off by at most one for
+      // quotients below 2^16, as rectangle rows are), then corrected exactly.
+      uint32_t ty = (uint32_t)((float)rel * sr[lo]);
+      int32_t rem = (int32_t)(rel - ty * w);
+      if (rem < 0) { --ty; rem += (int32_t)w; }
+      else if (rem >= (int32_t)w) { ++ty; rem -= (int32_t)w; }
+      kout[og] = sb[lo] + ty * (wx >> 16) + (uint32_t)rem;
+      vout[og] = sf[lo];
     }
     __syncthreads();
   }
@@ -550,11 +568,12 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
   // 2. depth sort of the R records: 4 passes, back in buffer 0.
   radix_passes(hdr, kHdrRend, G, 0, 4, k, v, 0, hist, s);
   // 3. emission in depth order into buffer 1.
+  // The emission output buffer 1 holds the sorted tile counts until k_emit overwrites it.
   hipLaunchKernelGGL(k_emit_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], tiles, flags, L.VN,
-                     (const unsigned long long*)hdr, partE);
+                     (const unsigned long long*)hdr, partE, k[1]);
   hipLaunchKernelGGL(k_emit_partials, dim3(1), dim3(kBlock), 0, s, partE, hdr, nb, D.cap);
   uint32_t* owner = (uint32_t*)(dp + D.owner);
-  hipLaunchKernelGGL(k_emit_offsets, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], tiles,
+  hipLaunchKernelGGL(k_emit_offsets, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)k[1],
                      (const uint32_t*)partE, (const unsigned long long*)hdr, k[0], owner);
   int64_t ge = (D.cap + kEmitTile - 1) / kEmitTile;
   if (ge > 4096) ge = 4096;
@@ -571,13 +590,30 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
 __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ keys,
                                                    const unsigned long long* __restrict__ hdr,
                                                    uint32_t tiles_total, uint2* __restrict__ ranges) {
+  constexpr uint32_t kNone = 0xFFFFFFFFu;   // no neighbour (never a tile id)
   if (hdr[kHdrOverflow]) return;
   const int64_t D = (int64_t)hdr[kHdrDup];
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < D; i += (int64_t)gridDim.x * kBlock) {
-    const uint32_t t = keys[i];
-    if (t >= tiles_total) continue;
-    if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
-    if (i == D - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  // Four consecutive keys per thread (one 16-byte load), plus the key before and after.
+  for (int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x); i0 < D;
+       i0 += 4 * (int64_t)gridDim.x * kBlock) {
+    uint32_t k[6];
+    k[0] = i0 > 0 ? keys[i0 - 1] : kNone;
+    if (i0 + 4 <= D) {
+      const uint4 q = *reinterpret_cast<const uint4*>(keys + i0);
+      k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) k[j + 1] = i0 + j < D ? keys[i0 + j] : kNone;
+    }
+    k[5] = i0 + 4 < D ? keys[i0 + 4] : kNone;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t = k[j + 1];
+      if (t >= tiles_total) continue;   // also past the end (kNone)
+      const int64_t i = i0 + j;
+      if (k[j] != t) ranges[t].x = (uint32_t)i;
+      if (k[j + 2] != t) ranges[t].y = (uint32_t)(i + 1);
+    }
   }
 }
 
@@ -639,7 +675,7 @@ hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* du
   // The ranges and the ordering counters were cleared by launch_bin_sort.
   hipError_t e = hipSuccess;
   const uint32_t* keys = (const uint32_t*)(dp + (parity ? D.keys1 : D.keys0));
-  int64_t g = (D.cap + kBlock - 1) / kBlock;
+  int64_t g = (D.cap + 4 * kBlock - 1) / (4 * kBlock);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)g), dim3(kBlock), 0, s, keys,
