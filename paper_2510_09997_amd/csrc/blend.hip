@@ -22,18 +22,24 @@ __device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_
 // Per-entry power cut.  An entry contributes to a pixel only if alpha'' E(power) >= fl(1/255).
 // E(p) <= 1 for p <= 0 and E never decreases by more than 2^-23 relative between neighbouring
 // inputs, so for power < cut = ln(1 / (255 alpha'')) - 0.01 the product is below
-// (1/255) e^-0.01 (1 + 3 2^-23) < 1/255: the contract skips the pair.  The 0.01 margin also
-// absorbs the error of logf.  cut > 0 means the entry is skipped at every pixel.
+// (1/255) e^-0.01 (1 + 3 2^-23) < 1/255: the contract skips the pair.  The cut is formed as
+// (ln(1/255) - 0.01) - ln 2 log2(alpha'') with the hardware log2, whose error here (about
+// 1e-6 absolute for alpha'' in [1/255, 1]) the 0.01 margin absorbs.  cut > 0 means the entry
+// is skipped at every pixel; alpha'' = 0 (or a flushed subnormal) gives cut = +inf.
 __device__ __forceinline__ float entry_cut(float a2) {
-  return logf(0.0039215686274509803f / a2) - 0.01f;
+  constexpr float kC0 = -5.551263545158426f;   // ln(1/255) - 0.01
+  constexpr float kLn2 = 0.6931471805599453f;
+  return kC0 - kLn2 * __builtin_amdgcn_logf(a2);
 }
 
 // Minimum over the box [X0, X1] x [Y0, Y1] of q(dx, dy) = A dx^2 + 2 B dx dy + C dy^2 (the
 // conic's quadratic form, positive definite): 0 if the box holds the origin, else the least of
-// the four edge minima (each a clamped 1-D vertex).
+// the four edge minima (each a clamped 1-D vertex).  The vertices use the hardware reciprocal:
+// q along an edge exceeds its minimum by a term quadratic in the vertex offset, so a
+// relative offset of a few 2^-24 stays negligible next to the allowance below.
 __device__ __forceinline__ float box_qmin(float A, float B, float C, float X0, float X1, float Y0, float Y1) {
   if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return 0.0f;
-  const float bc = B / C, ba = B / A;
+  const float bc = B * __builtin_amdgcn_rcpf(C), ba = B * __builtin_amdgcn_rcpf(A);
   auto qf = [&](float dx, float dy) { return fmaf(A * dx, dx, fmaf(C * dy, dy, 2.0f * B * dx * dy)); };
   const float yx0 = fminf(fmaxf(-bc * X0, Y0), Y1), yx1 = fminf(fmaxf(-bc * X1, Y0), Y1);
   const float xy0 = fminf(fmaxf(-ba * Y0, X0), X1), xy1 = fminf(fmaxf(-ba * Y1, X0), X1);
@@ -58,7 +64,8 @@ __device__ __forceinline__ bool ellipse_reaches(float u, float v, float A, float
 // power differs from the exact one by a factor common to the conic (the rounding of det,
 // <= 2u r) plus independent roundings amplified by at most r = AC / (AC - B^2); with
 // r <= 5e4 the total stays below 4%, so the evaluated power is below cut and the pair is
-// skipped.  Culled pairs are therefore exactly pairs the pixel loop would have skipped.
+// skipped.  (The radius uses the hardware square root: its relative error of a few 2^-24
+// is far inside that slack.)  Culled pairs are therefore exactly pairs the pixel loop would have skipped.
 // Entries with a worse conditioned conic are never culled spatially.
 __device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float A, float B, float C, float rad,
                                                   float cut, float x0, float y0) {
@@ -66,7 +73,7 @@ __device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float A, flo
   const float ac = A * C;
   const float det = ac - B * B;
   if (!(det > 2e-5f * ac) || !(rad < 1e6f)) return 0xFu;
-  const float rc = __builtin_sqrtf(2.4f * -cut) * rad * (1.0f / 3.0f) + 0.5f;
+  const float rc = __builtin_amdgcn_sqrtf(2.4f * -cut) * rad * (1.0f / 3.0f) + 0.5f;
   const float rc2 = rc * rc;
   uint32_t m = 0;
 #pragma unroll
@@ -86,7 +93,7 @@ __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, fl
   const float ac = A * C;
   const float det = ac - B * B;
   if (!(det > 2e-5f * ac) || !(rad < 1e6f)) return 1u;
-  const float rc = __builtin_sqrtf(2.4f * -cut) * rad * (1.0f / 3.0f) + 0.5f;
+  const float rc = __builtin_amdgcn_sqrtf(2.4f * -cut) * rad * (1.0f / 3.0f) + 0.5f;
   const float ddx = fmaxf(0.0f, fmaxf(x0 + 0.5f - u, u - (x0 + 7.5f)));
   const float ddy = fmaxf(0.0f, fmaxf(y0 + 0.5f - v, v - (y0 + 7.5f)));
   return (ddx * ddx + ddy * ddy <= rc * rc && ellipse_reaches(u, v, A, B, C, cut, x0, y0)) ? 1u : 0u;
@@ -164,7 +171,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
       const float dx = a.x - pcx, dy = a.y - pcy;
       const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
       const bool live = !done && power <= 0.0f && power >= bc.y;
-      if (ballot64(live) != 0ull) {
+      // Divergent: only live lanes run the rest, and the wave skips it when none is live.
+      if (live) {
         const float prod = c.y * cexp_core(power);
         const float al = fminf(0.99f, prod);
         const bool use = live && al >= kSkip;
@@ -172,10 +180,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
         const bool stop = use && Tn < kTmin;
         const bool blend = use && !stop;
         const uint32_t pos = base - rg.x + (uint32_t)e;
-        const float w = al * T;
-        cr = blend ? fmaf_(c.z, w, cr) : cr;
-        cg = blend ? fmaf_(c.w, w, cg) : cg;
-        cb = blend ? fmaf_(bc.x, w, cb) : cb;
+        // A zero weight leaves the sums unchanged (colours are finite and >= 0), so the
+        // select is taken once, on the weight.
+        const float w = blend ? al * T : 0.0f;
+        cr = fmaf_(c.z, w, cr);
+        cg = fmaf_(c.w, w, cg);
+        cb = fmaf_(bc.x, w, cb);
         T = blend ? Tn : T;
         last = blend ? pos + 1u : last;
         done = done || stop;

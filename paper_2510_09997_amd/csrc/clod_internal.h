@@ -113,8 +113,8 @@ __device__ __forceinline__ float cexp_core(float x) {
   p = fmaf_(p, r, 0.5f);
   p = fmaf_(p, r, 1.0f);
   p = fmaf_(p, r, 1.0f);
-  int ki = (int)k;
-  return p * __uint_as_float((uint32_t)(ki + 127) << 23);
+  // p * 2^k, exact for every k that cexp's clamped range produces (the result stays normal).
+  return __builtin_amdgcn_ldexpf(p, (int)k);
 }
 
 __device__ __forceinline__ float cexp(float x) {
@@ -314,7 +314,7 @@ __device__ __forceinline__ void block_chunk(int64_t n, int64_t& lo, int64_t& hi)
 }
 
 // Wave64 helpers.
-__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const uint32_t l = __lane_id();
