@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 8
+#define CLOD_ABI_VERSION 9
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -226,22 +226,22 @@ clod_status clod_read_info(const clod_batch *batch, int64_t *info_host, void *st
                        first D are valid, D from clod_bin_sort or clod_read_info)
      CLOD_SEC_VALUES   uint32 sorted record indices v*n + i (count as above)
      CLOD_SEC_RANGES   uint32 pairs [start, end) per tile of the batch (count = tiles)
-     CLOD_SEC_REC      64-byte records per (view, Gaussian), float4 x 4: (u, v, alpha'',
-                       radius), (conic A, B, C, 0), (r, g, b, 0), unused; written for
-                       rendered Gaussians only (count = n_views * n)
+     CLOD_SEC_REC      64-byte records per (view, Gaussian), four 16-byte quads: float (u, v,
+                       alpha'', radius), float (conic A, B, C, 0), float (r, g, b, 0), then
+                       (float camera depth, uint32 x0 | x1 << 16, uint32 y0 | y1 << 16, uint32
+                       tiles touched) -- the tile rectangle [x0, x1) x [y0, y1) in the view's
+                       tiles; written whole for rendered Gaussians only (count = n_views * n)
      CLOD_SEC_ALPHA    float per (view, Gaussian): alpha'' of Eq. (2), every Gaussian
-     CLOD_SEC_DEPTH    float per (view, Gaussian): camera depth, rendered Gaussians only
      CLOD_SEC_FLAGS    uint8 per (view, Gaussian): bit0 frustum, bit1 mask, bit2 rendered,
                        bits 3..5 colour clamped
      CLOD_SEC_DMAX     uint64 per view: bits(d_max) << 32 | (2^32 - 1 - argmax), 0 if empty
-     CLOD_SEC_RECT     uint32 pairs per (view, Gaussian): x0 | x1 << 16, y0 | y1 << 16
      CLOD_SEC_GSCREEN  float [9][n_views * n] screen-space partials of the last backward
      CLOD_SEC_HEADER   uint64 [2] = {D of the last clod_bin_sort, overflow flag} (count = 2);
                        an asynchronous copy of it avoids the synchronisation of clod_read_info */
 enum {
   CLOD_SEC_KEYS = 0, CLOD_SEC_VALUES = 1, CLOD_SEC_RANGES = 2, CLOD_SEC_REC = 3, CLOD_SEC_ALPHA = 4,
-  CLOD_SEC_DEPTH = 5, CLOD_SEC_FLAGS = 6, CLOD_SEC_DMAX = 7, CLOD_SEC_RECT = 8, CLOD_SEC_GSCREEN = 9,
-  CLOD_SEC_HEADER = 10
+  CLOD_SEC_FLAGS = 6, CLOD_SEC_DMAX = 7, CLOD_SEC_GSCREEN = 9, CLOD_SEC_HEADER = 10
+  /* 5 and 8 are not used (depth and rectangle live in the fourth quad of a record) */
 };
 clod_status clod_inspect(const clod_batch *batch, int32_t section, const void **dev_ptr,
                          int64_t *count);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 8
+ABI_VERSION = 9
 
 
 class ClodError(RuntimeError):
@@ -74,8 +74,8 @@ EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
            "clod_inspect", "clod_last_error", "clod_abi_version", "clod_adam_step"]
 
-(SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC, SEC_ALPHA, SEC_DEPTH, SEC_FLAGS, SEC_DMAX, SEC_RECT, SEC_GSCREEN,
- SEC_HEADER) = range(11)
+SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC, SEC_ALPHA = 0, 1, 2, 3, 4
+SEC_FLAGS, SEC_DMAX, SEC_GSCREEN, SEC_HEADER = 6, 7, 9, 10
 
 _lib = None
 

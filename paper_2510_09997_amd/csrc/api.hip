@@ -115,10 +115,7 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.list = o; o = align256(o + (size_t)n * 4);                        // work list of the projection
   L.flags = o; o = align256(o + (size_t)L.VN);
   L.alpha = o; o = align256(o + (size_t)L.VN * 4);
-  L.depth = o; o = align256(o + (size_t)L.VN * 4);
   L.rec = o; o = align256(o + (size_t)L.VN * kRecBytes);
-  L.rect = o; o = align256(o + (size_t)L.VN * 8);
-  L.tiles = o; o = align256(o + (size_t)L.VN * 4);
   L.scan_part = o; o = align256(o + ((size_t)L.scan_blocks + 1) * 4 * 2);   // records, emission
   L.ranges = o; o = align256(o + (size_t)tiles_total * 8);
   L.order = o; o = align256(o + (size_t)tiles_total * 4);
@@ -281,8 +278,8 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
             "budget select");
   HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
                          (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags),
-                         (float*)(w + L.alpha), (float*)(w + L.depth), (float4*)(w + L.rec), (uint2*)(w + L.rect),
-                         (uint32_t*)(w + L.tiles), (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount),
+                         (float*)(w + L.alpha), (float4*)(w + L.rec), (uint32_t*)(w + L.list),
+                         (uint32_t*)(w + L.lcount),
                          (unsigned long long*)(w + L.hdr), s),
           "project");
   if (counts_dev)
@@ -496,10 +493,8 @@ clod_status clod_inspect(const clod_batch* batch, int32_t section, const void** 
     case CLOD_SEC_RANGES: *dev_ptr = w + L.ranges; *count = L.tiles_total; break;
     case CLOD_SEC_REC: *dev_ptr = w + L.rec; *count = L.VN; break;
     case CLOD_SEC_ALPHA: *dev_ptr = w + L.alpha; *count = L.VN; break;
-    case CLOD_SEC_DEPTH: *dev_ptr = w + L.depth; *count = L.VN; break;
     case CLOD_SEC_FLAGS: *dev_ptr = w + L.flags; *count = L.VN; break;
     case CLOD_SEC_DMAX: *dev_ptr = w + L.dmax_key; *count = L.V; break;
-    case CLOD_SEC_RECT: *dev_ptr = w + L.rect; *count = L.VN; break;
     case CLOD_SEC_GSCREEN: *dev_ptr = w + L.gscreen; *count = L.VN; break;
     case CLOD_SEC_HEADER: *dev_ptr = w + L.hdr; *count = 2; break;
     default: return fail(CLOD_E_ARG, "unknown section %d", section);

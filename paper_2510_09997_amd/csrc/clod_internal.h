@@ -60,8 +60,8 @@ struct Layout {
   int32_t scan_blocks = 0;
   bool any_budget = false;    // some view selects by budget (allocates the select histograms)
   // byte offsets into ws
-  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, ssim_acc, loss_part, sel_state, sel_hist, lcount, list, flags, alpha, depth, rec,
-      rect, tiles, scan_part, ranges, order, tord, pair_part, gscreen, total;
+  size_t hdr, vinfo, dmax_key, counts, gdmax, loss_acc, kpart, cpart, gpart, ssim_acc, loss_part, sel_state, sel_hist, lcount, list, flags, alpha, rec,
+      scan_part, ranges, order, tord, pair_part, gscreen, total;
 };
 
 // Host-side per-view geometry (must agree with k_view_setup).
@@ -408,8 +408,8 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
                               unsigned long long* kpart, unsigned long long* dmax_key, hipStream_t s);
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                          uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
-                          uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
+                          uint8_t* flags, float* alpha, float4* rec, uint32_t* list, uint32_t* lcount,
+                          unsigned long long* hdr,
                           hipStream_t s);
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,

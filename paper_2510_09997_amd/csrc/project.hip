@@ -229,15 +229,14 @@ __global__ __launch_bounds__(kBlock) void k_list_scan(const uint32_t* __restrict
 // Pass 2 over the work list (entries spread evenly over the blocks): per listed Gaussian the
 // geometry of every view again (cheap), then for in-frustum kept views the EWA projection,
 // cull and rectangle, remembering which views render it; then the colour of each rendering
-// view is evaluated from its SH coefficients.  Records, depth, rectangle
-// and tiles touched are written for rendered (view, Gaussian) pairs only.
+// view is evaluated from its SH coefficients.  Records (with depth, rectangle and tiles
+// touched in their fourth quad) are written for rendered (view, Gaussian) pairs only.
 template <int DEG, bool kWriteRecords, bool kPacked>
 __device__ __forceinline__ void project_body(
     const clod_scene& sc, const DevView* __restrict__ views, int V, const clod_params& prm,
     const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][4] */,
     const uint32_t* __restrict__ list, const uint32_t* __restrict__ loff, const unsigned long long* __restrict__ hdr,
-    uint8_t* __restrict__ flags_out, float* __restrict__ depth_out, float4* __restrict__ rec,
-    uint2* __restrict__ rect_out, uint32_t* __restrict__ tiles_out) {
+    uint8_t* __restrict__ flags_out, float4* __restrict__ rec) {
   extern __shared__ uint32_t sdyn[];   // [G] segment offsets, then [V] rendered counts
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t n = sc.n;
@@ -300,9 +299,12 @@ __device__ __forceinline__ void project_body(
                 const int64_t f = (int64_t)v * n + i;
                 rec[kRecQuads * f] = make_float4(P.u, P.v, a2, P.rad);
                 rec[kRecQuads * f + 1] = make_float4(P.A, P.B, P.C, 0.f);
-                depth_out[f] = z;
-                rect_out[f] = make_uint2((uint32_t)P.x0 | ((uint32_t)P.x1 << 16), (uint32_t)P.y0 | ((uint32_t)P.y1 << 16));
-                tiles_out[f] = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+                // Depth, tile rectangle and tiles touched: the fourth quad, so the record is
+                // written whole (no partial 64-byte segments, no separate scattered planes).
+                rec[kRecQuads * f + 3] =
+                    make_float4(z, __uint_as_float((uint32_t)P.x0 | ((uint32_t)P.x1 << 16)),
+                                __uint_as_float((uint32_t)P.y0 | ((uint32_t)P.y1 << 16)),
+                                __uint_as_float((uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0))));
               }
             }
           }
@@ -387,22 +389,19 @@ __device__ __forceinline__ void project_body(
       const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart,                  \
       const uint32_t* __restrict__ list, const uint32_t* __restrict__ loff,                           \
       const unsigned long long* __restrict__ hdr, uint8_t* __restrict__ flags_out,                    \
-      float* __restrict__ depth_out, float4* __restrict__ rec, uint2* __restrict__ rect_out,          \
-      uint32_t* __restrict__ tiles_out
+      float4* __restrict__ rec
 
 // Plane-major coefficients (or no records).
 template <int DEG, bool kWriteRecords>
 __global__ __launch_bounds__(kBlock) void k_project(CLOD_PROJECT_ARGS) {
-  project_body<DEG, kWriteRecords, false>(sc, views, V, prm, dmax_key, cpart, list, loff, hdr, flags_out,
-                                          depth_out, rec, rect_out, tiles_out);
+  project_body<DEG, kWriteRecords, false>(sc, views, V, prm, dmax_key, cpart, list, loff, hdr, flags_out, rec);
 }
 
 // Packed coefficients: fits 128 registers, so four waves per SIMD hide the gather latency.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_project_packed(
     CLOD_PROJECT_ARGS) {
-  project_body<DEG, true, true>(sc, views, V, prm, dmax_key, cpart, list, loff, hdr, flags_out, depth_out, rec,
-                                rect_out, tiles_out);
+  project_body<DEG, true, true>(sc, views, V, prm, dmax_key, cpart, list, loff, hdr, flags_out, rec);
 }
 #undef CLOD_PROJECT_ARGS
 
@@ -585,8 +584,8 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
 template <bool kWrite>
 static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                                unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                               uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
-                               uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
+                               uint8_t* flags, float* alpha, float4* rec, uint32_t* list, uint32_t* lcount,
+                               unsigned long long* hdr,
                                hipStream_t s) {
   if (sc.n == 0) return launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
   const int G = proj_blocks(sc.n);
@@ -605,7 +604,7 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
   }
   hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), (size_t)((G + V) * sizeof(uint32_t)), s, sc, vinfo, V, prm,
                      dmax_key, cpart, (const uint32_t*)list, (const uint32_t*)loff,
-                     (const unsigned long long*)hdr, flags, depth, rec, rect, tiles);
+                     (const unsigned long long*)hdr, flags, rec);
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
                      (const uint32_t*)cpart, G, V, dmax_key, counts);
   return hipGetLastError();
@@ -613,18 +612,16 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
 
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                          uint8_t* flags, float* alpha, float* depth, float4* rec, uint2* rect,
-                          uint32_t* tiles, uint32_t* list, uint32_t* lcount, unsigned long long* hdr,
-                          hipStream_t s) {
-  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, flags, alpha, depth, rec, rect, tiles,
-                            list, lcount, hdr, s);
+                          uint8_t* flags, float* alpha, float4* rec, uint32_t* list, uint32_t* lcount,
+                          unsigned long long* hdr, hipStream_t s) {
+  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, flags, alpha, rec, list, lcount, hdr, s);
 }
 
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s) {
-  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, nullptr,
-                             nullptr, nullptr, list, lcount, hdr, s);
+  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, list, lcount,
+                             hdr, s);
 }
 
 hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s) {

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__
 // Positions are formed in LDS so the stores are coalesced.
 __global__ __launch_bounds__(kBlock) void k_compact(const uint8_t* __restrict__ flags, int64_t count,
                                                     const uint32_t* __restrict__ partR,
-                                                    const float* __restrict__ depth,
+                                                    const float4* __restrict__ rec,
                                                     const unsigned long long* __restrict__ hdr,
                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   __shared__ uint32_t sm[4];
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint8_t* __restrict__ 
   const int64_t out0 = (int64_t)partR[blockIdx.x];
   for (uint32_t q = (uint32_t)t; q < total; q += kBlock) {
     const uint32_t f = sf[q];
-    kout[out0 + q] = __float_as_uint(depth[f]);
+    kout[out0 + q] = __float_as_uint(rec[kRecQuads * (int64_t)f + 3].x);   // camera depth
     vout[out0 + q] = f;
   }
 }
@@ -353,6 +353,11 @@ static void radix_passes(const unsigned long long* hdr, int cw, int G, int first
 }
 
 // ---------------------------------------------------------------- step 3: ordered emission
+// Tiles touched by record f (the last word of its fourth quad).
+__device__ __forceinline__ uint32_t rec_tiles(const float4* __restrict__ rec, uint32_t f) {
+  return __float_as_uint(rec[kRecQuads * (int64_t)f + 3].w);
+}
+
 // Per chunk of the depth-sorted records: tile pairs of the chunk (saturated at 2^32 - 1,
 // which only a total far beyond any capacity reaches); the gathered counts are also stored in
 // sorted order (tsorted) for k_emit_offsets.  If R alone exceeded the capacity
@@ -360,7 +365,7 @@ static void radix_passes(const unsigned long long* hdr, int cw, int G, int first
 // the pair count is then summed over chunk b of all records instead, so that D is still
 // reported.
 __global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restrict__ sorted_f,
-                                                        const uint32_t* __restrict__ tiles,
+                                                        const float4* __restrict__ rec,
                                                         const uint8_t* __restrict__ flags, int64_t count,
                                                         const unsigned long long* __restrict__ hdr,
                                                         uint32_t* __restrict__ partE, uint32_t* __restrict__ tsorted) {
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restri
     for (int k = 0; k < kScanItems; ++k) {
       const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
       if (j < R) {
-        const uint32_t c = tiles[sorted_f[j]];
+        const uint32_t c = rec_tiles(rec, sorted_f[j]);
         tsorted[j] = c;
         s += c;
       }
@@ -383,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restri
   } else {
     for (int k = 0; k < kScanItems; ++k) {
       const int64_t j = base + (int64_t)k * kBlock + threadIdx.x;
-      if (j < count && (flags[j] & 4u)) s += tiles[j];
+      if (j < count && (flags[j] & 4u)) s += rec_tiles(rec, (uint32_t)j);
     }
   }
   s = wave_sum(s);
@@ -473,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restr
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ sorted_f,
                                                  const uint32_t* __restrict__ eoff,
                                                  const uint32_t* __restrict__ owner,
-                                                 const uint2* __restrict__ rect, const DevView* __restrict__ views,
+                                                 const float4* __restrict__ rec, const DevView* __restrict__ views,
                                                  int64_t n, const unsigned long long* __restrict__ hdr,
                                                  uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   __shared__ uint32_t se[kEmitTile + 1];
@@ -494,8 +499,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ so
     for (int i = threadIdx.x; i < cnt; i += kBlock) {
       const uint32_t f = sorted_f[k0 + i];
       const DevView& Vw = views[f / nn];
-      const uint2 rc = rect[f];
-      const uint32_t x0 = rc.x & 0xFFFFu, x1 = rc.x >> 16, y0 = rc.y & 0xFFFFu;
+      const float4 q3 = rec[kRecQuads * (int64_t)f + 3];
+      const uint32_t rx = __float_as_uint(q3.y), ry = __float_as_uint(q3.z);
+      const uint32_t x0 = rx & 0xFFFFu, x1 = rx >> 16, y0 = ry & 0xFFFFu;
       const uint32_t w = x1 - x0, tx = (uint32_t)Vw.tiles_x;
       se[i] = eoff[k0 + i];
       sf[i] = f;
@@ -556,7 +562,6 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
   }
   uint32_t* partR = (uint32_t*)(w + L.scan_part);
   uint32_t* partE = partR + (nb + 1);
-  const uint32_t* tiles = (const uint32_t*)(w + L.tiles);
   const uint8_t* flags = (const uint8_t*)(w + L.flags);
   const int G = sort_blocks(D.cap);
   // 1. R and its overflow; compaction of the rendered records into buffer 0.
@@ -564,12 +569,13 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
                      2 * (int64_t)L.tiles_total);
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partR, nb, hdr, D.cap, tord);
   hipLaunchKernelGGL(k_compact, dim3(nb), dim3(kBlock), 0, s, flags, L.VN, (const uint32_t*)partR,
-                     (const float*)(w + L.depth), (const unsigned long long*)hdr, k[0], v[0]);
+                     (const float4*)(w + L.rec), (const unsigned long long*)hdr, k[0], v[0]);
   // 2. depth sort of the R records: 4 passes, back in buffer 0.
   radix_passes(hdr, kHdrRend, G, 0, 4, k, v, 0, hist, s);
   // 3. emission in depth order into buffer 1.
   // The emission output buffer 1 holds the sorted tile counts until k_emit overwrites it.
-  hipLaunchKernelGGL(k_emit_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], tiles, flags, L.VN,
+  hipLaunchKernelGGL(k_emit_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], (const float4*)(w + L.rec),
+                     flags, L.VN,
                      (const unsigned long long*)hdr, partE, k[1]);
   hipLaunchKernelGGL(k_emit_partials, dim3(1), dim3(kBlock), 0, s, partE, hdr, nb, D.cap);
   uint32_t* owner = (uint32_t*)(dp + D.owner);
@@ -579,7 +585,7 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
   if (ge > 4096) ge = 4096;
   if (ge < 1) ge = 1;
   hipLaunchKernelGGL(k_emit, dim3((unsigned)ge), dim3(kBlock), 0, s, (const uint32_t*)v[0], (const uint32_t*)k[0],
-                     (const uint32_t*)owner, (const uint2*)(w + L.rect), (const DevView*)(w + L.vinfo), L.n,
+                     (const uint32_t*)owner, (const float4*)(w + L.rec), (const DevView*)(w + L.vinfo), L.n,
                      (const unsigned long long*)hdr, k[1], v[1]);
   // 4. stable sort of the D pairs by tile id.
   radix_passes(hdr, kHdrDup, G, 0, tile_passes(L.tiles_total), k, v, 1, hist, s);

@@ -153,7 +153,7 @@ class Batch:
         if count is not None:
             n = min(n, int(count))
         elem = {C.SEC_KEYS: 4, C.SEC_VALUES: 4, C.SEC_RANGES: 8, C.SEC_REC: 64, C.SEC_ALPHA: 4,
-                C.SEC_DEPTH: 4, C.SEC_FLAGS: 1, C.SEC_DMAX: 8, C.SEC_RECT: 8, C.SEC_GSCREEN: 36}[section]
+                C.SEC_FLAGS: 1, C.SEC_DMAX: 8, C.SEC_GSCREEN: 36}[section]
         base = self.dup if section in (C.SEC_KEYS, C.SEC_VALUES) else self.ws
         off = ptr - base.data_ptr()
         assert 0 <= off and off + n * elem <= base.numel()
@@ -164,12 +164,12 @@ class Batch:
             raw = base[off:off + 9 * vn * 4].clone()
             return raw.view(torch.float32).view(9, vn)
         dt = {8: torch.int64, 4: torch.int32, 64: torch.float32, 1: torch.uint8}[elem]
-        if section in (C.SEC_ALPHA, C.SEC_DEPTH):
+        if section == C.SEC_ALPHA:
             dt = torch.float32
         t = raw.view(dt)
         if section == C.SEC_REC:
             t = t.view(n, 4, 4)
-        if section in (C.SEC_RANGES, C.SEC_RECT):
+        if section == C.SEC_RANGES:
             t = raw.view(torch.int32).view(n, 2)
         return t
 

@@ -35,14 +35,17 @@ def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None, 
     out["ranges"] = b.section(C.SEC_RANGES).cpu().numpy().view(np.uint32)
     out["rec"] = b.section(C.SEC_REC).cpu().numpy()
     out["alpha"] = b.section(C.SEC_ALPHA).cpu().numpy()
-    out["depth"] = b.section(C.SEC_DEPTH).cpu().numpy()
+    # Fourth quad of a record: depth, rectangle words, tiles touched.
+    q3 = out["rec"][:, 3, :]
+    out["depth"] = q3[:, 0].copy()
     # The sorted pairs as (tile << 32 | bits(depth)) keys, from the tile ids and the depth of
     # each pair's record.
     dbits = out["depth"].view(np.uint32).astype(np.uint64)
     out["keys"] = (out["tile_ids"].astype(np.uint64) << np.uint64(32)) | dbits[out["vals"].astype(np.int64)]
     out["flags"] = b.section(C.SEC_FLAGS).cpu().numpy()
     out["dmax"] = b.section(C.SEC_DMAX).cpu().numpy().view(np.uint64)
-    out["rect"] = b.section(C.SEC_RECT).cpu().numpy().view(np.uint32)
+    out["rect"] = np.ascontiguousarray(q3[:, 1:3]).view(np.uint32)
+    out["tiles_touched"] = np.ascontiguousarray(q3[:, 3]).view(np.uint32)
     return out
 
 
@@ -84,6 +87,9 @@ def compare_forward(g: dict, sc: dict, views, params: dict | None = None, fp64: 
             rc = g["rect"][v * n:(v + 1) * n][rend]
             rect = np.stack([rc[:, 0] & 0xFFFF, rc[:, 0] >> 16, rc[:, 1] & 0xFFFF, rc[:, 1] >> 16], 1)
             assert np.array_equal(rect.astype(np.int32), r["rect"][rend]), v
+            tt = g["tiles_touched"][v * n:(v + 1) * n][rend].astype(np.int64)
+            area = (rect[:, 1].astype(np.int64) - rect[:, 0]) * (rect[:, 3].astype(np.int64) - rect[:, 2])
+            assert np.array_equal(tt, area), v
         # Keys, values and ranges of this view's tiles.
         all_keys.append(O.sorted_keys(r, tb[v]))
         all_vals.append(r["entries"].astype(np.uint64) + np.uint64(v * n))
