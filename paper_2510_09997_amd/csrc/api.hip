@@ -111,7 +111,7 @@ static Layout make_layout(int64_t n, int32_t V, uint32_t tiles_total, int64_t pi
   L.gpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4);
   L.sel_state = o; o = align256(o + (size_t)V * sizeof(SelState));
   L.sel_hist = o; o = align256(o + (L.any_budget ? (size_t)V * kSelBlocks * 256 * 4 : 0));
-  L.lcount = o; o = align256(o + (size_t)kMaxProjBlocks * 2 * 4);   // work-list segment counts, offsets
+  L.lcount = o; o = align256(o + (size_t)kMaxProjBlocks * 4);   // work-list segment counts
   L.list = o; o = align256(o + (size_t)n * 4);                        // work list of the projection
   L.flags = o; o = align256(o + (size_t)L.VN);
   L.alpha = o; o = align256(o + (size_t)L.VN * 4);
@@ -267,8 +267,8 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
   const Layout& L = cx.L;
   char* w = (char*)batch->ws;
   DevView* vinfo = (DevView*)(w + L.vinfo);
-  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, (unsigned long long*)(w + L.hdr), s),
-          "view setup");
+  unsigned long long* hdr = (unsigned long long*)(w + L.hdr);
+  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, hdr, s), "view setup");
   HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.kpart),
                              (unsigned long long*)(w + L.dmax_key), s),
           "frustum max");
@@ -277,13 +277,10 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
                               (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
             "budget select");
   HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
-                         (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), (uint8_t*)(w + L.flags),
-                         (float*)(w + L.alpha), (float4*)(w + L.rec), (uint32_t*)(w + L.list),
-                         (uint32_t*)(w + L.lcount),
-                         (unsigned long long*)(w + L.hdr), s),
+                         (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), counts_dev,
+                         (uint8_t*)(w + L.flags), (float*)(w + L.alpha), (float4*)(w + L.rec),
+                         (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), s),
           "project");
-  if (counts_dev)
-    HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
   return CLOD_OK;
 }
 
@@ -381,10 +378,9 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
                               (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
             "budget select");
   HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
-                           (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts),
-                           (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), (unsigned long long*)(w + L.hdr), s),
+                           (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), counts_dev,
+                           (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), s),
           "lod count");
-  HIP_TRY(launch_counts_out((const unsigned long long*)(w + L.counts), L.V, counts_dev, s), "counts");
   return CLOD_OK;
 }
 

@@ -49,7 +49,7 @@ struct SelState {
 constexpr int kSelBlocks = 128;   // blocks per view of the select histograms
 
 // Workspace header words (uint64).
-enum : int { kHdrDup = 0, kHdrOverflow = 1, kHdrRend = 2, kHdrList = 3, kHdrWords = 8 };
+enum : int { kHdrDup = 0, kHdrOverflow = 1, kHdrRend = 2, kHdrWords = 8 };
 
 struct Layout {
   int64_t n = 0;
@@ -328,6 +328,27 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Exclusive scan of one uint32 per thread over the 256-thread block; returns the block total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* smem /*[4]*/,
+                                                          uint32_t& total) {
+  const uint32_t lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t up = __shfl_up(inc, o, 64);
+    if (lane >= (uint32_t)o) inc += up;
+  }
+  if (lane == 63) smem[wave] = inc;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (int w = 0; w < wave; ++w) wbase += smem[w];
+  total = smem[0] + smem[1] + smem[2] + smem[3];
+  __syncthreads();
+  return wbase + inc - v;
+}
+
+
 template <int kCtrl, int kRowMask>
 __device__ __forceinline__ float dpp_read(float x) {
   // Lanes of rows outside kRowMask receive 0.
@@ -406,15 +427,15 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 int proj_blocks(int64_t n);
 hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V, float near_z,
                               unsigned long long* kpart, unsigned long long* dmax_key, hipStream_t s);
+// counts (workspace) and counts_dev (caller's int64 [V][3], nullable) receive the per-view
+// {frustum, mask, rendered} counts.
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                          uint8_t* flags, float* alpha, float4* rec, uint32_t* list, uint32_t* lcount,
-                          unsigned long long* hdr,
-                          hipStream_t s);
+                          int64_t* counts_dev, uint8_t* flags, float* alpha, float4* rec, uint32_t* list,
+                          uint32_t* lcount, hipStream_t s);
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                            uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s);
-hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s);
+                            int64_t* counts_dev, uint32_t* list, uint32_t* lcount, hipStream_t s);
 
 // Fused Adam: one segment per learning-rate group.
 constexpr int kAdamGroups = 7;

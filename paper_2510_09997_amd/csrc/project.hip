@@ -56,13 +56,82 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
     p[i] = value;
 }
 
+// Folds the G per-block partials of view v (every thread of the block takes part).  With kpart: the maximum squared distance, stored as the key
+// bits(sqrt(max)) << 32 (0 if the frustum is empty).  With cpart: the counts (sum; also to
+// counts_dev when non-NULL) and the lowest index at d_max (min), which completes the low half
+// of that key.
+__device__ void fold_view(int v, const unsigned long long* __restrict__ kpart, const uint32_t* __restrict__ cpart,
+                          int G, int V, unsigned long long* __restrict__ dmax_key,
+                          unsigned long long* __restrict__ counts, int64_t* __restrict__ counts_dev) {
+  __shared__ unsigned long long sm[4][4];
+  __shared__ uint32_t smin[4];
+  unsigned long long key = 0ull, c0 = 0, c1 = 0, c2 = 0;
+  uint32_t imin = 0xFFFFFFFFu;
+  for (int b = threadIdx.x; b < G; b += kBlock) {
+    if (kpart) {
+      const unsigned long long k = kpart[(int64_t)b * V + v];
+      key = k > key ? k : key;
+    }
+    if (cpart) {
+      const uint32_t* c = cpart + ((int64_t)b * V + v) * 4;
+      c0 += c[0];
+      c1 += c[1];
+      c2 += c[2];
+      imin = c[3] < imin ? c[3] : imin;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long ok = __shfl_xor(key, o, 64);
+    key = ok > key ? ok : key;
+    c0 += __shfl_xor(c0, o, 64);
+    c1 += __shfl_xor(c1, o, 64);
+    c2 += __shfl_xor(c2, o, 64);
+    const uint32_t om = __shfl_xor(imin, o, 64);
+    imin = om < imin ? om : imin;
+  }
+  const int w = threadIdx.x >> 6;
+  if (lane_id() == 0) { sm[w][0] = key; sm[w][1] = c0; sm[w][2] = c1; sm[w][3] = c2; smin[w] = imin; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 1; j < 4; ++j) {
+      key = sm[j][0] > key ? sm[j][0] : key;
+      c0 += sm[j][1]; c1 += sm[j][2]; c2 += sm[j][3];
+      imin = smin[j] < imin ? smin[j] : imin;
+    }
+    if (kpart) {
+      const float d2 = __uint_as_float((uint32_t)key);
+      dmax_key[v] = key ? (unsigned long long)__float_as_uint(__builtin_sqrtf(d2)) << 32 : 0ull;
+    }
+    if (cpart) {
+      counts[3 * v] = c0; counts[3 * v + 1] = c1; counts[3 * v + 2] = c2;
+      if (counts_dev) {
+        counts_dev[3 * v] = (int64_t)c0; counts_dev[3 * v + 1] = (int64_t)c1; counts_dev[3 * v + 2] = (int64_t)c2;
+      }
+      const unsigned long long dk = dmax_key[v];
+      if (dk) dmax_key[v] = (dk & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - imin);
+    }
+  }
+  __syncthreads();
+}
+
+// Block v folds view v.
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const unsigned long long* __restrict__ kpart,
+                                                            const uint32_t* __restrict__ cpart, int G, int V,
+                                                            unsigned long long* __restrict__ dmax_key,
+                                                            unsigned long long* __restrict__ counts,
+                                                            int64_t* __restrict__ counts_dev) {
+  fold_view(blockIdx.x, kpart, cpart, G, V, dmax_key, counts, counts_dev);
+}
+
 // Per-block partials instead of global atomics: block b owns the contiguous chunk
 // [b*C, (b+1)*C) of Gaussians and writes one partial per view (the frustum-max key, the three
-// counts); k_reduce_partials folds them per view.  Same-address atomics from every wave
+// counts); k_reduce_partials folds them per view (one block per view).  Same-address atomics
+// from every wave
 // serialise in L2 and would dominate these otherwise bandwidth-bound kernels.
 
 // Frustum maximum of the squared distance per view, as the float bits (order-preserving for
-// non-negative values; 0 = no Gaussian in the frustum).  k_reduce_partials turns the maximum
+// non-negative values; 0 = no Gaussian in the frustum).  fold_view turns the maximum
 // into the key bits(d_max) << 32 (d_max its correctly rounded root, the largest distance),
 // and k_classify finds the lowest index at that distance, which completes the key with
 // 2^32 - 1 - index (so that ties resolve to the lowest index).
@@ -198,34 +267,6 @@ __global__ __launch_bounds__(kBlock) void k_classify(
   if (threadIdx.x == 0) lcount[blockIdx.x] = sbase;
 }
 
-// Single block: lcount[G] -> exclusive offsets loff[G] and the list length into the header.
-__global__ __launch_bounds__(kBlock) void k_list_scan(const uint32_t* __restrict__ lcount, int G,
-                                                      uint32_t* __restrict__ loff,
-                                                      unsigned long long* __restrict__ hdr) {
-  __shared__ uint32_t sm[4];
-  uint32_t carry = 0;
-  for (int base = 0; base < G; base += kBlock) {
-    const int j = base + threadIdx.x;
-    uint32_t v = j < G ? lcount[j] : 0u;
-    // Inclusive scan over the wave, then across the four waves.
-    uint32_t inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t up = __shfl_up(inc, o, 64);
-      if (lane_id() >= (uint32_t)o) inc += up;
-    }
-    if (lane_id() == 63) sm[threadIdx.x >> 6] = inc;
-    __syncthreads();
-    uint32_t wb = 0;
-    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wb += sm[w];
-    const uint32_t tot = sm[0] + sm[1] + sm[2] + sm[3];
-    __syncthreads();
-    if (j < G) loff[j] = carry + wb + inc - v;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) hdr[kHdrList] = carry;
-}
-
 // Pass 2 over the work list (entries spread evenly over the blocks): per listed Gaussian the
 // geometry of every view again (cheap), then for in-frustum kept views the EWA projection,
 // cull and rectangle, remembering which views render it; then the colour of each rendering
@@ -235,18 +276,39 @@ template <int DEG, bool kWriteRecords, bool kPacked>
 __device__ __forceinline__ void project_body(
     const clod_scene& sc, const DevView* __restrict__ views, int V, const clod_params& prm,
     const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][4] */,
-    const uint32_t* __restrict__ list, const uint32_t* __restrict__ loff, const unsigned long long* __restrict__ hdr,
-    uint8_t* __restrict__ flags_out, float4* __restrict__ rec) {
+    const uint32_t* __restrict__ list, const uint32_t* __restrict__ lcount, uint8_t* __restrict__ flags_out,
+    float4* __restrict__ rec) {
   extern __shared__ uint32_t sdyn[];   // [G] segment offsets, then [V] rendered counts
+  __shared__ uint32_t sm[4];
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t n = sc.n;
   const int G = gridDim.x;
   uint32_t* soff = sdyn;
   uint32_t* scnt = sdyn + G;
-  for (int j = threadIdx.x; j < G; j += kBlock) soff[j] = loff[j];
+  // Exclusive offsets of the G list segments and the list length: every block scans the
+  // segment counts itself (G <= 2048: eight per thread, blocked).
+  int64_t L;
+  {
+    constexpr int kPer = kMaxProjBlocks / kBlock;
+    static_assert(kPer * kBlock == kMaxProjBlocks, "segment scan layout");
+    const int j0 = threadIdx.x * kPer;
+    uint32_t c[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      c[k] = j0 + k < G ? lcount[j0 + k] : 0u;
+      sum += c[k];
+    }
+    uint32_t tot;
+    uint32_t off = block_exclusive_scan(sum, sm, tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (j0 + k < G) soff[j0 + k] = off;
+      off += c[k];
+    }
+    L = tot;
+  }
   for (int j = threadIdx.x; j < V; j += kBlock) scnt[j] = 0;
   __syncthreads();
-  const int64_t L = (int64_t)hdr[kHdrList];
   const int64_t per = (n + G - 1) / G;   // chunk length of the first pass
   const int64_t stride = (int64_t)G * kBlock;
   // Every lane of the block runs the same number of rounds (ballots stay uniform).
@@ -387,21 +449,20 @@ __device__ __forceinline__ void project_body(
 #define CLOD_PROJECT_ARGS                                                                              \
   clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,                           \
       const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart,                  \
-      const uint32_t* __restrict__ list, const uint32_t* __restrict__ loff,                           \
-      const unsigned long long* __restrict__ hdr, uint8_t* __restrict__ flags_out,                    \
-      float4* __restrict__ rec
+      const uint32_t* __restrict__ list, const uint32_t* __restrict__ lcount,                         \
+      uint8_t* __restrict__ flags_out, float4* __restrict__ rec
 
 // Plane-major coefficients (or no records).
 template <int DEG, bool kWriteRecords>
 __global__ __launch_bounds__(kBlock) void k_project(CLOD_PROJECT_ARGS) {
-  project_body<DEG, kWriteRecords, false>(sc, views, V, prm, dmax_key, cpart, list, loff, hdr, flags_out, rec);
+  project_body<DEG, kWriteRecords, false>(sc, views, V, prm, dmax_key, cpart, list, lcount, flags_out, rec);
 }
 
 // Packed coefficients: fits 128 registers, so four waves per SIMD hide the gather latency.
 template <int DEG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_project_packed(
     CLOD_PROJECT_ARGS) {
-  project_body<DEG, true, true>(sc, views, V, prm, dmax_key, cpart, list, loff, hdr, flags_out, rec);
+  project_body<DEG, true, true>(sc, views, V, prm, dmax_key, cpart, list, lcount, flags_out, rec);
 }
 #undef CLOD_PROJECT_ARGS
 
@@ -489,67 +550,6 @@ hipError_t launch_lod_select(const clod_scene& sc, DevView* vinfo, int V, clod_p
   return hipGetLastError();
 }
 
-// Block v folds the G partials of view v.  With kpart: the maximum squared distance, stored
-// as the key bits(sqrt(max)) << 32 (0 if the frustum is empty).  With cpart: the counts (sum)
-// and the lowest index at d_max (min), which completes the low half of that key.
-__global__ __launch_bounds__(kBlock) void k_reduce_partials(const unsigned long long* __restrict__ kpart,
-                                                            const uint32_t* __restrict__ cpart, int G, int V,
-                                                            unsigned long long* __restrict__ dmax_key,
-                                                            unsigned long long* __restrict__ counts) {
-  __shared__ unsigned long long sm[4][4];
-  __shared__ uint32_t smin[4];
-  const int v = blockIdx.x;
-  unsigned long long key = 0ull, c0 = 0, c1 = 0, c2 = 0;
-  uint32_t imin = 0xFFFFFFFFu;
-  for (int b = threadIdx.x; b < G; b += kBlock) {
-    if (kpart) {
-      const unsigned long long k = kpart[(int64_t)b * V + v];
-      key = k > key ? k : key;
-    }
-    if (cpart) {
-      const uint32_t* c = cpart + ((int64_t)b * V + v) * 4;
-      c0 += c[0];
-      c1 += c[1];
-      c2 += c[2];
-      imin = c[3] < imin ? c[3] : imin;
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long ok = __shfl_xor(key, o, 64);
-    key = ok > key ? ok : key;
-    c0 += __shfl_xor(c0, o, 64);
-    c1 += __shfl_xor(c1, o, 64);
-    c2 += __shfl_xor(c2, o, 64);
-    const uint32_t om = __shfl_xor(imin, o, 64);
-    imin = om < imin ? om : imin;
-  }
-  const int w = threadIdx.x >> 6;
-  if (lane_id() == 0) { sm[w][0] = key; sm[w][1] = c0; sm[w][2] = c1; sm[w][3] = c2; smin[w] = imin; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int j = 1; j < 4; ++j) {
-      key = sm[j][0] > key ? sm[j][0] : key;
-      c0 += sm[j][1]; c1 += sm[j][2]; c2 += sm[j][3];
-      imin = smin[j] < imin ? smin[j] : imin;
-    }
-    if (kpart) {
-      const float d2 = __uint_as_float((uint32_t)key);
-      dmax_key[v] = key ? (unsigned long long)__float_as_uint(__builtin_sqrtf(d2)) << 32 : 0ull;
-    }
-    if (cpart) {
-      counts[3 * v] = c0; counts[3 * v + 1] = c1; counts[3 * v + 2] = c2;
-      const unsigned long long dk = dmax_key[v];
-      if (dk) dmax_key[v] = (dk & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - imin);
-    }
-  }
-}
-
-__global__ void k_counts_out(const unsigned long long* __restrict__ c, int V, int64_t* __restrict__ out) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < 3 * V) out[j] = (int64_t)c[j];
-}
-
 int proj_blocks(int64_t n) {
   int64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
   if (g < 1) g = 1;
@@ -577,22 +577,23 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
   const int G = proj_blocks(sc.n);
   hipLaunchKernelGGL(k_frustum_max, dim3(G), dim3(kBlock), 0, s, sc.mean, sc.n, vinfo, V, near_z, kpart);
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)kpart,
-                     (const uint32_t*)nullptr, G, V, dmax_key, (unsigned long long*)nullptr);
+                     (const uint32_t*)nullptr, G, V, dmax_key, (unsigned long long*)nullptr, (int64_t*)nullptr);
   return hipGetLastError();
 }
 
 template <bool kWrite>
 static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                                unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                               uint8_t* flags, float* alpha, float4* rec, uint32_t* list, uint32_t* lcount,
-                               unsigned long long* hdr,
-                               hipStream_t s) {
-  if (sc.n == 0) return launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
+                               int64_t* counts_dev, uint8_t* flags, float* alpha, float4* rec, uint32_t* list,
+                               uint32_t* lcount, hipStream_t s) {
+  if (sc.n == 0) {
+    hipError_t e = launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
+    if (e == hipSuccess && counts_dev) e = launch_fill_u32((uint32_t*)counts_dev, 0u, 6 * (int64_t)V, s);
+    return e;
+  }
   const int G = proj_blocks(sc.n);
-  uint32_t* loff = lcount + G;
   hipLaunchKernelGGL(k_classify<kWrite>, dim3(G), dim3(kBlock), (size_t)(3 * V * sizeof(uint32_t)), s, sc, vinfo,
                      V, prm, dmax_key, cpart, flags, alpha, list, lcount);
-  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(kBlock), 0, s, (const uint32_t*)lcount, G, loff, hdr);
   // Packed SH is only read when records are written.
   const bool packed = kWrite && sc.sh_packed != nullptr;
   auto kern = packed ? k_project_packed<3> : k_project<3, kWrite>;
@@ -603,30 +604,27 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
     default: break;
   }
   hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), (size_t)((G + V) * sizeof(uint32_t)), s, sc, vinfo, V, prm,
-                     dmax_key, cpart, (const uint32_t*)list, (const uint32_t*)loff,
-                     (const unsigned long long*)hdr, flags, rec);
+                     (const unsigned long long*)dmax_key, cpart, (const uint32_t*)list, (const uint32_t*)lcount, flags,
+                     rec);
+  // Counts to the workspace and the caller, and the argmax index into the d_max key.
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
-                     (const uint32_t*)cpart, G, V, dmax_key, counts);
+                     (const uint32_t*)cpart, G, V, dmax_key, counts, counts_dev);
   return hipGetLastError();
 }
 
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                          uint8_t* flags, float* alpha, float4* rec, uint32_t* list, uint32_t* lcount,
-                          unsigned long long* hdr, hipStream_t s) {
-  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, flags, alpha, rec, list, lcount, hdr, s);
+                          int64_t* counts_dev, uint8_t* flags, float* alpha, float4* rec, uint32_t* list,
+                          uint32_t* lcount, hipStream_t s) {
+  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, counts_dev, flags, alpha, rec, list, lcount,
+                            s);
 }
 
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                            uint32_t* list, uint32_t* lcount, unsigned long long* hdr, hipStream_t s) {
-  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, nullptr, nullptr, nullptr, list, lcount,
-                             hdr, s);
-}
-
-hipError_t launch_counts_out(const unsigned long long* counts, int V, int64_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_counts_out, dim3((3 * V + 255) / 256), dim3(256), 0, s, counts, V, out);
-  return hipGetLastError();
+                            int64_t* counts_dev, uint32_t* list, uint32_t* lcount, hipStream_t s) {
+  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, counts_dev, nullptr, nullptr, nullptr,
+                             list, lcount, s);
 }
 
 }  // namespace clod

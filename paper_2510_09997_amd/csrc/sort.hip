@@ -19,27 +19,6 @@
 
 namespace clod {
 
-// ---------------------------------------------------------------------------- block scan
-// Exclusive scan of one uint32 per thread over the 256-thread block; returns the block total.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* smem /*[4]*/,
-                                                          uint32_t& total) {
-  const uint32_t lane = lane_id();
-  const int wave = threadIdx.x >> 6;
-  uint32_t inc = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t up = __shfl_up(inc, o, 64);
-    if (lane >= (uint32_t)o) inc += up;
-  }
-  if (lane == 63) smem[wave] = inc;
-  __syncthreads();
-  uint32_t wbase = 0;
-  for (int w = 0; w < wave; ++w) wbase += smem[w];
-  total = smem[0] + smem[1] + smem[2] + smem[3];
-  __syncthreads();
-  return wbase + inc - v;
-}
-
 // Loads a chunk of kScanChunk uint32 counts (coalesced) into LDS and replaces them by their
 // block-exclusive offsets (blocked: thread t owns items t*16 .. t*16+15).  Returns the total.
 __device__ __forceinline__ uint32_t chunk_offsets(uint32_t* loff, uint32_t* sm, uint32_t (&loc)[kScanItems]) {
@@ -94,24 +73,9 @@ __device__ __forceinline__ uint32_t rendered_mask(const uint8_t* __restrict__ fl
   return m;
 }
 
-// Per chunk of kScanChunk records: the number of rendered records.  Also clears the per-tile
-// ranges (2 * tiles words) for k_ranges, which writes only the non-empty tiles.
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint8_t* __restrict__ flags, int64_t count,
-                                                        uint32_t* __restrict__ partR, uint32_t* __restrict__ ranges,
-                                                        int64_t range_words) {
-  __shared__ uint32_t sm[4];
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < range_words; q += (int64_t)gridDim.x * kBlock)
-    ranges[q] = 0u;
-  const int64_t j0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  const uint32_t r = wave_sum((uint32_t)__popc(rendered_mask(flags, count, j0)));
-  if (lane_id() == 0) sm[threadIdx.x >> 6] = r;
-  __syncthreads();
-  if (threadIdx.x == 0) partR[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
-}
-
-// Single block: exclusive scan of the per-chunk rendered counts; R and the overflow flag
-// (R above the capacity) to the header.  D is not known yet: k_emit_partials stores it.
-// Also clears the counters of the tile ordering (tord).
+// Single block: exclusive scan of the per-chunk rendered counts; R and the overflow flag (R
+// above the capacity) to the header.  D is not known yet: k_emit_partials stores it.  Also
+// clears the counters of the tile ordering (tord).
 __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__ partR, int nparts,
                                                           unsigned long long* __restrict__ hdr, int64_t cap,
                                                           uint32_t* __restrict__ tord) {
@@ -142,6 +106,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__
     hdr[kHdrOverflow] = (int64_t)carry > cap ? 1ull : 0ull;
     hdr[kHdrRend] = carry;
   }
+}
+
+// Per chunk of kScanChunk records: the number of rendered records.  Also clears the per-tile
+// ranges (2 * tiles words) for k_ranges, which writes only the non-empty tiles.
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint8_t* __restrict__ flags, int64_t count,
+                                                        uint32_t* __restrict__ partR, uint32_t* __restrict__ ranges,
+                                                        int64_t range_words) {
+  __shared__ uint32_t sm[4];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < range_words; q += (int64_t)gridDim.x * kBlock)
+    ranges[q] = 0u;
+  const int64_t j0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  const uint32_t r = wave_sum((uint32_t)__popc(rendered_mask(flags, count, j0)));
+  if (lane_id() == 0) sm[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) partR[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
 }
 
 // Rendered records of the chunk, in index order, to [partR[b], ...): key bits(depth), value f.
@@ -358,6 +337,41 @@ __device__ __forceinline__ uint32_t rec_tiles(const float4* __restrict__ rec, ui
   return __float_as_uint(rec[kRecQuads * (int64_t)f + 3].w);
 }
 
+// Single block: D (summed in 64 bits) and the overflow flag (D above the capacity) to the
+// header, and, unless overflowed, the exclusive scan of the chunk totals in place.
+__global__ __launch_bounds__(kBlock) void k_emit_partials(uint32_t* __restrict__ partE,
+                                                          unsigned long long* __restrict__ hdr, int nb,
+                                                          int64_t cap) {
+  __shared__ unsigned long long sm[4];
+  const bool over = hdr[kHdrOverflow] != 0ull;
+  const int nparts = over ? nb : (int)(((int64_t)hdr[kHdrRend] + kScanChunk - 1) / kScanChunk);
+  const uint32_t lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  unsigned long long carry = 0;
+  for (int base = 0; base < nparts; base += kBlock) {
+    const int j = base + threadIdx.x;
+    const unsigned long long v = j < nparts ? partE[j] : 0ull;
+    unsigned long long inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long up = __shfl_up(inc, o, 64);
+      if (lane >= (uint32_t)o) inc += up;
+    }
+    if (lane == 63) sm[wave] = inc;
+    __syncthreads();
+    unsigned long long wb = 0;
+    for (int w = 0; w < wave; ++w) wb += sm[w];
+    const unsigned long long tot = sm[0] + sm[1] + sm[2] + sm[3];
+    __syncthreads();
+    if (!over && j < nparts) partE[j] = (uint32_t)(carry + wb + inc - v);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    hdr[kHdrDup] = carry;
+    if ((int64_t)carry > cap) hdr[kHdrOverflow] = 1ull;
+  }
+}
+
 // Per chunk of the depth-sorted records: tile pairs of the chunk (saturated at 2^32 - 1,
 // which only a total far beyond any capacity reaches); the gathered counts are also stored in
 // sorted order (tsorted) for k_emit_offsets.  If R alone exceeded the capacity
@@ -397,41 +411,6 @@ __global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restri
   if (threadIdx.x == 0) {
     const unsigned long long c = sm[0] + sm[1] + sm[2] + sm[3];
     partE[blockIdx.x] = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
-  }
-}
-
-// Single block: D (summed in 64 bits) and the overflow flag (D above the capacity) to the
-// header, and, unless overflowed, the exclusive scan of the chunk totals in place.
-__global__ __launch_bounds__(kBlock) void k_emit_partials(uint32_t* __restrict__ partE,
-                                                          unsigned long long* __restrict__ hdr, int nb,
-                                                          int64_t cap) {
-  __shared__ unsigned long long sm[4];
-  const bool over = hdr[kHdrOverflow] != 0ull;
-  const int nparts = over ? nb : (int)(((int64_t)hdr[kHdrRend] + kScanChunk - 1) / kScanChunk);
-  const uint32_t lane = lane_id();
-  const int wave = threadIdx.x >> 6;
-  unsigned long long carry = 0;
-  for (int base = 0; base < nparts; base += kBlock) {
-    const int j = base + threadIdx.x;
-    const unsigned long long v = j < nparts ? partE[j] : 0ull;
-    unsigned long long inc = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned long long up = __shfl_up(inc, o, 64);
-      if (lane >= (uint32_t)o) inc += up;
-    }
-    if (lane == 63) sm[wave] = inc;
-    __syncthreads();
-    unsigned long long wb = 0;
-    for (int w = 0; w < wave; ++w) wb += sm[w];
-    const unsigned long long tot = sm[0] + sm[1] + sm[2] + sm[3];
-    __syncthreads();
-    if (!over && j < nparts) partE[j] = (uint32_t)(carry + wb + inc - v);
-    carry += tot;
-  }
-  if (threadIdx.x == 0) {
-    hdr[kHdrDup] = carry;
-    if ((int64_t)carry > cap) hdr[kHdrOverflow] = 1ull;
   }
 }
 
@@ -575,8 +554,7 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
   // 3. emission in depth order into buffer 1.
   // The emission output buffer 1 holds the sorted tile counts until k_emit overwrites it.
   hipLaunchKernelGGL(k_emit_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], (const float4*)(w + L.rec),
-                     flags, L.VN,
-                     (const unsigned long long*)hdr, partE, k[1]);
+                     flags, L.VN, (const unsigned long long*)hdr, partE, k[1]);
   hipLaunchKernelGGL(k_emit_partials, dim3(1), dim3(kBlock), 0, s, partE, hdr, nb, D.cap);
   uint32_t* owner = (uint32_t*)(dp + D.owner);
   hipLaunchKernelGGL(k_emit_offsets, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)k[1],
