@@ -124,32 +124,41 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint8_t* __restric
 }
 
 // Rendered records of the chunk, in index order, to [partR[b], ...): key bits(depth), value f.
-// Positions are formed in LDS so the stores are coalesced.
+// The depth gathers (one per rendered record, from the record's fourth quad) are issued right
+// after the flag load, so their latency overlaps the block scan; keys and indices are then
+// placed in LDS so the stores are coalesced.
 __global__ __launch_bounds__(kBlock) void k_compact(const uint8_t* __restrict__ flags, int64_t count,
                                                     const uint32_t* __restrict__ partR,
                                                     const float4* __restrict__ rec,
                                                     const unsigned long long* __restrict__ hdr,
                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
   __shared__ uint32_t sm[4];
+  __shared__ uint32_t sk[kScanChunk];
   __shared__ uint32_t sf[kScanChunk];
   if (hdr[kHdrOverflow] != 0ull) return;
   const int t = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   const int64_t j0 = base + (int64_t)t * kScanItems;
-  uint32_t m = rendered_mask(flags, count, j0);
+  const uint32_t m = rendered_mask(flags, count, j0);
+  uint32_t dk[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    dk[k] = ((m >> k) & 1u) ? __float_as_uint(rec[kRecQuads * (j0 + k) + 3].x) : 0u;   // camera depth
   uint32_t total;
   uint32_t o = block_exclusive_scan((uint32_t)__popc(m), sm, total);
-  while (m) {
-    const int k = __builtin_ctz(m);
-    m &= m - 1;
-    sf[o++] = (uint32_t)(j0 + k);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if ((m >> k) & 1u) {
+      sk[o] = dk[k];
+      sf[o] = (uint32_t)(j0 + k);
+      ++o;
+    }
   }
   __syncthreads();
   const int64_t out0 = (int64_t)partR[blockIdx.x];
   for (uint32_t q = (uint32_t)t; q < total; q += kBlock) {
-    const uint32_t f = sf[q];
-    kout[out0 + q] = __float_as_uint(rec[kRecQuads * (int64_t)f + 3].x);   // camera depth
-    vout[out0 + q] = f;
+    kout[out0 + q] = sk[q];
+    vout[out0 + q] = sf[q];
   }
 }
 
@@ -454,6 +463,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restr
 // rectangle width, the view's tile row length and 1/width.  Pair o belongs to the last staged
 // record whose offset is <= o, as that record's (o - offset)-th covered tile in row-major
 // order.  Chunks are equal-sized whatever the rectangle sizes, and every store is coalesced.
+constexpr int kEmitPer = kEmitTile / kBlock;   // consecutive pairs per thread
+static_assert(kEmitPer == 8, "the stores below write eight pairs per thread");
 __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ sorted_f,
                                                  const uint32_t* __restrict__ eoff,
                                                  const uint32_t* __restrict__ owner,
@@ -489,26 +500,57 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ so
       sr[i] = 1.0f / (float)w;
     }
     __syncthreads();
+    // Thread t writes the eight consecutive pairs [o0 + 8t, o0 + 8t + 8): one search for the
+    // first, then a walk that steps the tile column (and row) and, at a record's end, moves
+    // to the next record (each record has at least one pair, so one step never skips one).
     const int64_t o0 = q * kEmitTile;
     const int64_t o1 = o0 + kEmitTile < D ? o0 + kEmitTile : D;
-    for (int64_t og = o0 + threadIdx.x; og < o1; og += kBlock) {
-      const uint32_t o = (uint32_t)og;
+    const int64_t ob = o0 + (int64_t)threadIdx.x * kEmitPer;
+    if (ob < o1) {
+      const uint32_t o = (uint32_t)ob;
       int lo = 0, hi = cnt - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (se[mid] <= o) lo = mid; else hi = mid - 1;
       }
       const uint32_t rel = o - se[lo];
-      const uint32_t wx = sw[lo];
-      const uint32_t w = wx & 0xFFFFu;
-      // Row of the pair: rel / w from the rounded reciprocal (off by at most one for
+      uint32_t wx = sw[lo];
+      uint32_t w = wx & 0xFFFFu;
+      // Row of the first pair: rel / w from the rounded reciprocal (off by at most one for
       // quotients below 2^16, as rectangle rows are), then corrected exactly.
       uint32_t ty = (uint32_t)((float)rel * sr[lo]);
       int32_t rem = (int32_t)(rel - ty * w);
       if (rem < 0) { --ty; rem += (int32_t)w; }
       else if (rem >= (int32_t)w) { ++ty; rem -= (int32_t)w; }
-      kout[og] = sb[lo] + ty * (wx >> 16) + (uint32_t)rem;
-      vout[og] = sf[lo];
+      uint32_t tx = (uint32_t)rem;
+      uint32_t next = lo + 1 < cnt ? se[lo + 1] : 0xFFFFFFFFu;
+      uint32_t key[kEmitPer], val[kEmitPer];
+#pragma unroll
+      for (int k = 0; k < kEmitPer; ++k) {
+        if ((uint32_t)(o + k) == next) {   // the next record starts here
+          ++lo;
+          wx = sw[lo];
+          w = wx & 0xFFFFu;
+          tx = 0;
+          ty = 0;
+          next = lo + 1 < cnt ? se[lo + 1] : 0xFFFFFFFFu;
+        }
+        key[k] = sb[lo] + ty * (wx >> 16) + tx;
+        val[k] = sf[lo];
+        if (++tx == w) { tx = 0; ++ty; }
+      }
+      if (ob + kEmitPer <= o1) {
+        uint4* kq = reinterpret_cast<uint4*>(kout + ob);
+        uint4* vq = reinterpret_cast<uint4*>(vout + ob);
+        kq[0] = make_uint4(key[0], key[1], key[2], key[3]);
+        kq[1] = make_uint4(key[4], key[5], key[6], key[7]);
+        vq[0] = make_uint4(val[0], val[1], val[2], val[3]);
+        vq[1] = make_uint4(val[4], val[5], val[6], val[7]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kEmitPer; ++k)
+          if (ob + k < o1) { kout[ob + k] = key[k]; vout[ob + k] = val[k]; }
+      }
     }
     __syncthreads();
   }
