@@ -398,7 +398,10 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
       const bool contrib = live && al >= kSkip;
       const bool geo = contrib && prod <= 0.99f;
       const float oma = 1.0f - al;
-      const float Tk = T / oma;
+      // T before the entry, T / (1 - a): only gradients use it, so a hardware reciprocal with
+      // one Newton step (within an ulp) replaces the correctly rounded division.
+      const float r0 = __builtin_amdgcn_rcpf(oma);
+      const float Tk = T * fmaf(fmaf(-oma, r0, 1.0f), r0, r0);
       const float wgt = al * Tk;
       const float dLda = Tk * (g0c * (c.z - R0) + g1c * (c.w - R1) + g2c * (cb_ - R2));
       const float gp = dLda * prod;

@@ -297,7 +297,8 @@ __device__ __forceinline__ bool ewa(const DevView& V, float x, float y, float z,
 }
 
 // Record written by the projection for each rendered (view, Gaussian), kRecQuads float4:
-//   (u, v, alpha'', radius), (A, B, C, 0), (r, g, b, 0), unused; (u, v) in frame pixels.
+//   (u, v, alpha'', radius), (A, B, C, 0), (r, g, b, 0), (depth, x0 | x1 << 16, y0 | y1 << 16,
+//   tiles touched) with the last three as uint32 bits; (u, v) in frame pixels.
 // flags: bit0 F, bit1 M, bit2 rendered, bits3..5 colour clamp per channel.
 
 __device__ __forceinline__ float dmax_from_key(unsigned long long key) {

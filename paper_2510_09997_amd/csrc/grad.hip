@@ -6,7 +6,8 @@
 // reduced per view here and applied to the argmax Gaussian by k_dmax_fix.
 //
 // One thread per Gaussian loops over the batch's views and writes each gradient plane once
-// (coalesced, no atomics).  Forward intermediates of rendered (view, Gaussian) pairs are
+// (coalesced, no atomics): k_gauss_bwd everything but the SH colour, k_sh_bwd the SH
+// coefficients and the view-direction part of the mean's gradient.  Forward intermediates of rendered (view, Gaussian) pairs are
 // recomputed with the contract arithmetic of the projection.  The Eq. (2) adjoint, which the
 // point-count term needs for every (view, Gaussian), uses the hardware reciprocal, square root
 // and exp2 instead (relative errors of a few 1e-7, far inside the gradients' 1e-4 tolerance),
@@ -47,19 +48,15 @@ __device__ __forceinline__ void sh_basis_grad(int deg, float X, float Y, float Z
   gX += SHK::k3a * (3.f * xx - 3.f * yy) * gY[15]; gYo += -6.f * SHK::k3a * X * Y * gY[15];
 }
 
-template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
     const unsigned long long* __restrict__ dmax_key, const uint8_t* __restrict__ flags,
     const float* __restrict__ gscreen, int64_t VN, const float* __restrict__ dL_deta,
     float* __restrict__ gpart /* [G][V] */, int accumulate, clod_scene_grad g) {
-  // Dynamic LDS: [3K][256] SH-gradient accumulators (one column per thread, so the 48
-  // accumulators of degree 3 do not occupy registers), then [V] per-block sums of the
-  // frustum-maximum partial.
+  // Dynamic LDS: [V] per-block sums of the frustum-maximum partial.  The SH coefficients'
+  // gradients and the view-direction term of the mean's are left to k_sh_bwd.
   extern __shared__ float lds[];
-  constexpr int K = (DEG + 1) * (DEG + 1);
-  float* gshl = lds;
-  float* gsum = lds + 3 * K * kBlock;
+  float* gsum = lds;
   const int64_t n = sc.n;
   const float inv_n = 1.0f / (float)n;
   for (int v = threadIdx.x; v < V; v += kBlock) gsum[v] = 0.f;
@@ -81,8 +78,6 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
   const float alpha = frcp(1.0f + fexp(-op));
   const float r = fmaxf(dc, 0.0f);
   const float iden = frcp(2.f * r * r + prm.eps);
-#pragma unroll
-  for (int k = 0; k < 3 * K; ++k) gshl[k * kBlock + threadIdx.x] = 0.f;
   bool have_cov = false;
   float s[3], Rm[9], S[9], qn[4], rn = 0.f;
   for (int v = 0; v < V; ++v) {
@@ -104,7 +99,6 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
         const float gu = gscreen[f], gv = gscreen[VN + f];
         const float gA = gscreen[2 * VN + f], gB = gscreen[3 * VN + f], gC = gscreen[4 * VN + f];
         ga2 += gscreen[5 * VN + f];
-        const float gcol[3] = {gscreen[6 * VN + f], gscreen[7 * VN + f], gscreen[8 * VN + f]};
         float x, y, z;
         to_camera(Vw, mx, my, mz, x, y, z);
         if (!have_cov) {
@@ -113,32 +107,6 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
           cov3(Rm, s[0], s[1], s[2], S);
           have_cov = true;
         }
-        // Colour: SH coefficients and view direction.
-        const float id = frcp(d);
-        const float X = ex * id, Y = ey * id, Z = ez * id;
-        float Yb[16], gY[16];
-        sh_basis(DEG, X, Y, Z, Yb);
-        const float gc0 = (fl & 8) ? 0.f : gcol[0];
-        const float gc1 = (fl & 16) ? 0.f : gcol[1];
-        const float gc2 = (fl & 32) ? 0.f : gcol[2];
-        // One coefficient triple at a time keeps few values live.
-#pragma unroll 4
-        for (int k = 0; k < K; ++k) {
-          const float yk = Yb[k];
-          const float c0 = sc.sh[((int64_t)k * 3 + 0) * n + i];
-          const float c1 = sc.sh[((int64_t)k * 3 + 1) * n + i];
-          const float c2 = sc.sh[((int64_t)k * 3 + 2) * n + i];
-          gshl[(3 * k + 0) * kBlock + threadIdx.x] += gc0 * yk;
-          gshl[(3 * k + 1) * kBlock + threadIdx.x] += gc1 * yk;
-          gshl[(3 * k + 2) * kBlock + threadIdx.x] += gc2 * yk;
-          gY[k] = gc0 * c0 + gc1 * c1 + gc2 * c2;
-        }
-        float gX, gYd, gZ;
-        sh_basis_grad(DEG, X, Y, Z, gY, gX, gYd, gZ);
-        const float dot = X * gX + Y * gYd + Z * gZ;
-        gex += (gX - X * dot) * id;
-        gey += (gYd - Y * dot) * id;
-        gez += (gZ - Z * dot) * id;
         // Mean in screen space.
         const float iz = 1.0f / z;
         gx += gu * Vw.fx * iz;
@@ -249,14 +217,69 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
     for (int l = 0; l < 4; ++l) put(g.quat, l * n + i, gq[l]);
     put(g.opacity, i, gop);
     put(g.decay, i, gdc);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) put(g.sh, ((int64_t)k * 3 + ch) * n + i, gshl[(3 * k + ch) * kBlock + threadIdx.x]);
   }
   }
   __syncthreads();
   for (int v = threadIdx.x; v < V; v += kBlock) gpart[(int64_t)blockIdx.x * V + v] = gsum[v];
+}
+
+// SH colour adjoint per Gaussian: the coefficients are loaded once and their gradients
+// accumulated in registers over the rendering views (dL/dc_k = sum over views of the colour
+// gradient times the basis value; clamped channels pass no gradient); the view-direction term
+// dL/dmu = (dL/dd_hat - d_hat (d_hat . dL/dd_hat)) / |mu - c| is added to the mean's gradient
+// written by k_gauss_bwd.  Same reciprocal/square-root tolerance argument as there.
+template <int DEG>
+__global__ __launch_bounds__(kBlock) void k_sh_bwd(clod_scene sc, const DevView* __restrict__ views, int V,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const float* __restrict__ gscreen, int64_t VN, int accumulate,
+                                                   clod_scene_grad g) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t n = sc.n;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const float mx = sc.mean[i], my = sc.mean[n + i], mz = sc.mean[2 * n + i];
+    float c[3 * K], acc[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) {
+      c[k] = sc.sh[(int64_t)k * n + i];
+      acc[k] = 0.f;
+    }
+    float gmx = 0.f, gmy = 0.f, gmz = 0.f;
+    for (int v = 0; v < V; ++v) {
+      const int64_t f = (int64_t)v * n + i;
+      const uint8_t fl = flags[f];
+      if (!(fl & 4)) continue;
+      const DevView& Vw = views[v];
+      const float gc0 = (fl & 8) ? 0.f : gscreen[6 * VN + f];
+      const float gc1 = (fl & 16) ? 0.f : gscreen[7 * VN + f];
+      const float gc2 = (fl & 32) ? 0.f : gscreen[8 * VN + f];
+      float ex, ey, ez;
+      const float id = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(cam_distance2(Vw, mx, my, mz, ex, ey, ez)));
+      const float X = ex * id, Y = ey * id, Z = ez * id;
+      float Yb[16], gY[16];
+      sh_basis(DEG, X, Y, Z, Yb);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        acc[3 * k + 0] += gc0 * Yb[k];
+        acc[3 * k + 1] += gc1 * Yb[k];
+        acc[3 * k + 2] += gc2 * Yb[k];
+        gY[k] = gc0 * c[3 * k + 0] + gc1 * c[3 * k + 1] + gc2 * c[3 * k + 2];
+      }
+      float gX, gYd, gZ;
+      sh_basis_grad(DEG, X, Y, Z, gY, gX, gYd, gZ);
+      const float dot = X * gX + Y * gYd + Z * gZ;
+      gmx += (gX - X * dot) * id;
+      gmy += (gYd - Y * dot) * id;
+      gmz += (gZ - Z * dot) * id;
+    }
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) {
+      float* p = g.sh + (int64_t)k * n + i;
+      *p = accumulate ? *p + acc[k] : acc[k];
+    }
+    g.mean[i] += gmx;
+    g.mean[n + i] += gmy;
+    g.mean[2 * n + i] += gmz;
+  }
 }
 
 // Frustum-maximum path: d_max = d_k for the argmax k, so dL/dmu_k += dL/ddmax (mu_k - c) / d_k.
@@ -301,18 +324,21 @@ hipError_t launch_gauss_bwd(const clod_scene& sc, const Layout& L, void* ws, clo
   float* gpart = (float*)(w + L.gpart);
   // One partial per block and view: the grid is capped and each block walks a chunk.
   const int grid = proj_blocks(sc.n);
-  const int K = (sc.sh_degree + 1) * (sc.sh_degree + 1);
-  const size_t lds = ((size_t)3 * K * kBlock + (size_t)L.V) * sizeof(float);
-  auto kern = k_gauss_bwd<3>;
+  hipLaunchKernelGGL(k_gauss_bwd, dim3(grid), dim3(kBlock), (size_t)L.V * sizeof(float), s, sc,
+                     (const DevView*)(w + L.vinfo), L.V, prm, (const unsigned long long*)(w + L.dmax_key),
+                     (const uint8_t*)(w + L.flags), (const float*)(w + L.gscreen), L.VN, dL_deta, gpart,
+                     accumulate, g);
+  auto sh_kern = k_sh_bwd<3>;
   switch (sc.sh_degree) {
-    case 0: kern = k_gauss_bwd<0>; break;
-    case 1: kern = k_gauss_bwd<1>; break;
-    case 2: kern = k_gauss_bwd<2>; break;
-    default: kern = k_gauss_bwd<3>; break;
+    case 0: sh_kern = k_sh_bwd<0>; break;
+    case 1: sh_kern = k_sh_bwd<1>; break;
+    case 2: sh_kern = k_sh_bwd<2>; break;
+    default: break;
   }
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, sc, (const DevView*)(w + L.vinfo), L.V,
-                     prm, (const unsigned long long*)(w + L.dmax_key), (const uint8_t*)(w + L.flags),
-                     (const float*)(w + L.gscreen), L.VN, dL_deta, gpart, accumulate, g);
+  int64_t gs = (sc.n + kBlock - 1) / kBlock;
+  if (gs > 8192) gs = 8192;
+  hipLaunchKernelGGL(sh_kern, dim3((unsigned)gs), dim3(kBlock), 0, s, sc, (const DevView*)(w + L.vinfo), L.V,
+                     (const uint8_t*)(w + L.flags), (const float*)(w + L.gscreen), L.VN, accumulate, g);
   hipLaunchKernelGGL(k_dmax_fix, dim3(1), dim3(kBlock), 0, s, sc, (const DevView*)(w + L.vinfo), L.V,
                      (const unsigned long long*)(w + L.dmax_key), (const float*)gpart, grid, gdmax, g);
   return hipGetLastError();
