@@ -217,13 +217,26 @@ __global__ __launch_bounds__(kBlock) void k_classify(
   block_chunk(n, lo, hi);
   const uint64_t lt = lanemask_lt();
   const int64_t iters = (hi - lo + kBlock - 1) / kBlock;
+  // Software pipelined: the next round's parameters are loaded before this round's views are
+  // evaluated, so their latency overlaps the arithmetic.
+  float nmx = 0.f, nmy = 0.f, nmz = 0.f, nop = 0.f, ndc = 0.f;
+  {
+    const int64_t i = lo + threadIdx.x;
+    if (iters > 0 && i < hi) {
+      nmx = sc.mean[i]; nmy = sc.mean[n + i]; nmz = sc.mean[2 * n + i];
+      nop = sc.opacity[i]; ndc = sc.decay[i];
+    }
+  }
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t i = lo + it * kBlock + threadIdx.x;
     const bool valid = i < hi;
-    float mx = 0.f, my = 0.f, mz = 0.f, op = 0.f, dc = 0.f;
-    if (valid) {
-      mx = sc.mean[i]; my = sc.mean[n + i]; mz = sc.mean[2 * n + i];
-      op = sc.opacity[i]; dc = sc.decay[i];
+    const float mx = nmx, my = nmy, mz = nmz, op = nop, dc = ndc;
+    {
+      const int64_t i2 = i + kBlock;
+      if (it + 1 < iters && i2 < hi) {
+        nmx = sc.mean[i2]; nmy = sc.mean[n + i2]; nmz = sc.mean[2 * n + i2];
+        nop = sc.opacity[i2]; ndc = sc.decay[i2];
+      }
     }
     bool any = false;
     for (int v = 0; v < V; ++v) {
