@@ -194,6 +194,8 @@ static clod_status prepare(const clod_batch* b, bool need_full_ws, Ctx& cx) {
   bool any_budget = false;
   for (int v = 0; v < b->n_views; ++v) any_budget = any_budget || b->views_host[v].budget > 0;
   cx.L = make_layout(n, b->n_views, tiles_total, pixels_total, any_budget);
+  for (int v = 0; v < b->n_views; ++v)
+    cx.L.ssim_regions += (uint32_t)(((cx.hv[v].tiles_x + 1) / 2) * ((cx.hv[v].tiles_y + 1) / 2));
   // The per-view area and the projection work list precede the per-(view, Gaussian) planes.
   const size_t need = need_full_ws ? cx.L.total : cx.L.flags;
   if (b->ws_bytes < need) return fail(CLOD_E_ARG, "ws_bytes %zu < required %zu", b->ws_bytes, need);

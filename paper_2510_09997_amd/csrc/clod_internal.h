@@ -34,7 +34,7 @@ struct DevView {
   float fx, fy, cx, cy;
   float s_v, limx, limy, tau_sv;
   int32_t width, height, tiles_x, tiles_y;
-  uint32_t tile_base, pix_base, loss_block_base, pad0;
+  uint32_t tile_base, pix_base, loss_block_base, rgn_base;   // rgn_base: first 32 x 32 SSIM region
   int32_t ftiles_x, ftiles_y;    // tiles of the frame (the view's own when it is not a viewport)
   int32_t vx, vy;                // viewport origin in the frame, pixels (multiples of 16)
   int64_t budget;                // 0: threshold mask; K > 0: the K largest selection keys
@@ -56,6 +56,7 @@ struct Layout {
   int32_t V = 0;
   int64_t VN = 0;
   uint32_t tiles_total = 0;   // sum over views of tiles_x * tiles_y
+  uint32_t ssim_regions = 0;  // sum over views of ceil(tiles_x / 2) * ceil(tiles_y / 2)
   int64_t pixels_total = 0;
   int32_t scan_blocks = 0;
   bool any_budget = false;    // some view selects by budget (allocates the select histograms)
@@ -473,5 +474,6 @@ hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, c
                        float* dL_drgb, float* dL_deta, uint32_t loss_blocks, hipStream_t s);
 hipError_t launch_ssim(const Layout& L, void* ws, const float* rgb, const float* target, float lambda,
                        float s_max, float* coef, float* ssim_part, float* dL_drgb, hipStream_t s);
+constexpr int kSsimRegion = 32;   // output edge of one SSIM block (2 x 2 tiles)
 
 }  // namespace clod

@@ -42,10 +42,11 @@ __global__ __launch_bounds__(kBlock) void k_loss_l1(const DevView* __restrict__ 
 }
 
 // Block v folds view v's partial sums: its L1 blocks and, with the D-SSIM term, the three
-// channel partials of each of its tiles.
+// channel partials of each of its SSIM regions.
 __global__ __launch_bounds__(kBlock) void k_loss_reduce(const DevView* __restrict__ views, int V,
                                                         uint32_t loss_blocks, const float* __restrict__ l1_part,
                                                         const float* __restrict__ ssim_part, int with_ssim,
+                                                        uint32_t ssim_regions,
                                                         float* __restrict__ l1_acc, float* __restrict__ ssim_acc) {
   __shared__ float sm[2][4];
   const int v = blockIdx.x;
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_reduce(const DevView* __restric
   float a = 0.f, s = 0.f;
   for (uint32_t j = b0 + threadIdx.x; j < b1; j += kBlock) a += l1_part[j];
   if (with_ssim) {
-    const int64_t t0 = 3ll * Vw.tile_base, t1 = t0 + 3ll * Vw.tiles_x * Vw.tiles_y;
+    const int64_t t0 = 3ll * Vw.rgn_base, t1 = 3ll * (v + 1 < V ? views[v + 1].rgn_base : ssim_regions);
     for (int64_t j = t0 + threadIdx.x; j < t1; j += kBlock) s += ssim_part[j];
   }
   a = wave_sum(a);
@@ -96,7 +97,7 @@ hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, c
   char* w = (char*)ws;
   float* acc = (float*)(w + L.loss_acc);
   float* sacc = (float*)(w + L.ssim_acc);
-  float* spart = (float*)(w + L.loss_part);                   // [tiles][3] SSIM partials
+  float* spart = (float*)(w + L.loss_part);                   // [regions][3] SSIM partials
   float* lpart = spart + 3 * (int64_t)L.tiles_total;          // [loss blocks] L1 partials
   const DevView* views = (const DevView*)(w + L.vinfo);
   if (loss_blocks > 0)
@@ -107,7 +108,7 @@ hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, c
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_loss_reduce, dim3(L.V), dim3(kBlock), 0, s, views, L.V, loss_blocks, (const float*)lpart,
-                     (const float*)spart, lambda_dssim > 0.f ? 1 : 0, acc, sacc);
+                     (const float*)spart, lambda_dssim > 0.f ? 1 : 0, L.ssim_regions, acc, sacc);
   hipLaunchKernelGGL(k_loss_scalars, dim3((L.V + 63) / 64), dim3(64), 0, s, views, L.V, n,
                      (const unsigned long long*)(w + L.counts), (const float*)acc, (const float*)sacc, s_max,
                      lambda_reg, lambda_dssim, loss, dL_deta);

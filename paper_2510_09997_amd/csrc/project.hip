@@ -15,7 +15,7 @@ __global__ void k_view_setup(const clod_view* __restrict__ views, int V, clod_pa
                              DevView* __restrict__ out, unsigned long long* __restrict__ hdr) {
   if (hdr && blockIdx.x == 0 && threadIdx.x < (unsigned)kHdrWords) hdr[threadIdx.x] = 0ull;
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t tile_base = 0, pix_base = 0, loss_base = 0;
+  uint32_t tile_base = 0, pix_base = 0, loss_base = 0, rgn_base = 0;
   for (int v = 0; v < V; ++v) {
     const clod_view& cv = views[v];
     DevView d;
@@ -40,10 +40,11 @@ __global__ void k_view_setup(const clod_view* __restrict__ views, int V, clod_pa
     d.tile_base = tile_base;
     d.pix_base = pix_base;
     d.loss_block_base = loss_base;
-    d.pad0 = 0;
+    d.rgn_base = rgn_base;
     d.budget = cv.budget;
     d.mkey = 0ull;
     tile_base += (uint32_t)(d.tiles_x * d.tiles_y);
+    rgn_base += (uint32_t)(((d.tiles_x + 1) / 2) * ((d.tiles_y + 1) / 2));
     pix_base += (uint32_t)(cv.width * cv.height);
     loss_base += (uint32_t)((3u * (uint32_t)(cv.width * cv.height) + kLossChunk - 1) / kLossChunk);
     out[v] = d;
