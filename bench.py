@@ -4,6 +4,9 @@ Headline: 1080p frames/s at 3,000,000 Gaussians (SH degree 3, 64-cluster mixture
 the LoD sweep s_v in {1, 2, 4, 8, 16}.  One step renders the five LoD frames of one random
 pose (radius U(3, 30), direction uniform) as one batched pass of the forward path
 (clod_project, clod_bin_sort, clod_render_fwd).  Inputs are resident in HBM before timing.
+The timed steps run pipelined over three streams, each with its own workspace (the overlap
+a continuous-batching server gets); the same steps also run once sequentially on one stream,
+which gives the per-stage times and the roofline of the blend launched alone.
 
 Also reported on the same line: the plain per-request path (one view per pass), the
 training step (1,000,000 Gaussians, 1297x840, forward + loss + backward, ms/iter), the
@@ -77,40 +80,63 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     b._alloc_dup(cap)
     log(f"[bench] max pairs per 5-frame step {dmax}, capacity {cap}")
     pairs = torch.zeros(3, dtype=torch.int64, device="cuda")
-    rgb = torch.empty(3 * b.pixels, device="cuda")
-    T = torch.empty(b.pixels, device="cuda")
-    last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
-    cs = b.c_struct
+    # Pipelined serving: consecutive steps rotate over NS streams, each with its own batch
+    # workspace and output buffers, so one step's projection and binning (latency-bound, few
+    # waves) overlap the previous step's blend (issue-bound).  Slot 0 also runs the sequential
+    # pass that times each stage in isolation.
+    NS = max(1, args.streams)
+    slots = [b] + [Batch(n, steps[0], dup_capacity=cap) for _ in range(NS - 1)]
+    outs = [(torch.empty(3 * b.pixels, device="cuda"), torch.empty(b.pixels, device="cuda"),
+             torch.empty(b.pixels, dtype=torch.int32, device="cuda")) for _ in range(NS)]
+    streams = [torch.cuda.Stream() for _ in range(NS)]
+    rgb, T, last = outs[0]
+    scs = scene.c_struct()
 
-    def step(j, ev=None):
-        b.views_host, b.views_dev = tables.host[j], tables.dev[j]
-        bs = cs()
-        C.clod_project(scene.c_struct(), bs, b.counts)
+    def step(j, ev=None, slot=0, stream=None):
+        sb = slots[slot]
+        sb.views_host, sb.views_dev = tables.host[j], tables.dev[j]
+        bs = sb.c_struct()
+        C.clod_project(scs, bs, sb.counts, stream=stream)
         if ev is not None:
             ev[0].record()
-        C.clod_bin_sort(bs, sync_count=False)
+        C.clod_bin_sort(bs, sync_count=False, stream=stream)
         if ev is not None:
             ev[1].record()
-        C.clod_render_fwd(bs, rgb, T, last, None)
+        C.clod_render_fwd(bs, *outs[slot], None, stream=stream)
         if ev is not None:
             ev[2].record()
 
-    for j in range(W):
-        step(j)
+    def pipelined(j0, count):
+        cur = torch.cuda.current_stream()
+        for st in streams:
+            st.wait_stream(cur)
+        for k in range(count):
+            i = k % NS
+            step(j0 + k, slot=i, stream=streams[i])
+        for st in streams:
+            cur.wait_stream(st)
+
+    pipelined(0, max(W, NS))
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    pairs.zero_()
-    torch.cuda.synchronize()
+    # Sequential pass over the timed steps (one stream, events around every stage).
     start.record()
     for k in range(K):
         evs[k][3].record()
         step(W + k, evs[k])
     end.record()
     torch.cuda.synchronize()
+    seq_ms = start.elapsed_time(end)
+    # Headline timed region: the same K steps, pipelined over the NS streams.
+    start.record()
+    pipelined(W, K)
+    end.record()
+    torch.cuda.synchronize()
     total_ms = start.elapsed_time(end)
-    info = C.clod_read_info(b.c_struct())
-    assert not info["overflow"], "duplicate buffer overflow inside the timed region"
+    for sb in slots:
+        info = C.clod_read_info(sb.c_struct())
+        assert not info["overflow"], "duplicate buffer overflow inside the timed region"
     proj_ms = sum(e[3].elapsed_time(e[0]) for e in evs) / K
     sort_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / K
     blend_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / K
@@ -122,14 +148,15 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     if not args.no_count:
         for k in range(K):
             b.views_host, b.views_dev = tables.host[W + k], tables.dev[W + k]
-            bs = cs()
-            C.clod_project(scene.c_struct(), bs, b.counts)
+            bs = b.c_struct()
+            C.clod_project(scs, bs, b.counts)
             C.clod_bin_sort(bs, sync_count=False)
             C.clod_render_fwd(bs, rgb, T, last, pairs)
             dups.append(C.clod_read_info(bs)["n_dup"])
         torch.cuda.synchronize()
         pairs_per_step = (pairs.cpu().numpy() / K).tolist()
-    res = dict(total_ms=total_ms, ms_per_step=total_ms / K, fps=frames / (total_ms / 1e3),
+    res = dict(total_ms=total_ms, ms_per_step=total_ms / K, fps=frames / (total_ms / 1e3), streams=NS,
+               sequential_fps=frames / (seq_ms / 1e3), sequential_ms_per_step=seq_ms / K,
                stage_ms=dict(project=proj_ms, bin_sort=sort_ms, blend_fwd=blend_ms),
                pairs_per_step=pairs_per_step, max_dup=dmax, blend_launches=K,
                dup_per_step=float(np.mean(dups)) if dups else None, pixels_per_step=b.pixels)
@@ -481,6 +508,8 @@ def main():
     ap.add_argument("--no-count", action="store_true", help="skip the untimed work-counting re-run")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="streams the headline serving steps are pipelined over (1 = sequential)")
     ap.add_argument("--serve-requests", type=int, default=4000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     args = ap.parse_args()
@@ -535,7 +564,8 @@ def main():
         "data": "synthetic (seeded 64-cluster mixture scenes; random poses)",
         "config": {"workload": "serve-1080p-3M-lod-sweep", "gaussians": 3_000_000, "sh_degree": 3,
                    "resolution": [1920, 1080], "s_v": list(SV_SWEEP), "frames_per_step": len(SV_SWEEP),
-                   "pose_radius": [3.0, 30.0]},
+                   "pose_radius": [3.0, 30.0], "streams": serve["streams"]},
+        "sequential_fps": round(serve["sequential_fps"], 2),
         "plain_path_fps": round(serve["plain_fps"], 2) if "plain_fps" in serve else None,
         "stage_ms": {k: round(v, 4) for k, v in serve["stage_ms"].items()},
         "pairs_per_step": {"evaluated": e, "exp_evaluated": x, "blended": bl},
