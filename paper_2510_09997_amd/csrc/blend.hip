@@ -140,9 +140,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
   float4* s2 = st[wave][2];
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
   uint32_t last = 0, term = 0xFFFFFFFFu, nexp = 0, nblend = 0;
-  bool done = !inside;
+  // Lanes whose pixel has terminated (or lies outside the frame), as a wave-uniform mask: the
+  // per-entry predicates below are formed as lane masks and turned back into execution masks
+  // with inverse ballots, so the termination bookkeeping stays in scalar registers.
+  uint64_t dm = ballot64(!inside);
   for (uint32_t base = rg.x; base < rg.y; base += 64) {
-    if (ballot64(!done) == 0ull) break;
+    if (dm == ~0ull) break;
     const uint32_t j = base + lane;
     bool rel = false;
     if (j < rg.y) {
@@ -163,37 +166,43 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (mask == 0ull) continue;
-    // One entry: the contract's skip, exponential, clamp, termination and blend, as
-    // straight-line code under per-lane predicates.  Below the entry's cut (or above 0) the
-    // contract skips the pair whatever E returns; live pairs have power in [cut, 0] with
-    // cut >= ln(1/255) - 0.01, inside cexp_core's range (other lanes' values are discarded).
+    // One entry: the contract's skip, exponential, clamp, termination and blend.  Below the
+    // entry's cut (or above 0) the contract skips the pair whatever E returns; live pairs have
+    // power in [cut, 0] with cut >= ln(1/255) - 0.01, inside cexp_core's range.  Only live
+    // lanes evaluate E (the wave skips it when none is live); the skip and termination tests
+    // then run on the whole wave and are masked with the live set, so al and Tn of other
+    // lanes are never used.
     auto pair = [&](const float4& a, const float4& c, const float4& bc, int e) {
       const float dx = a.x - pcx, dy = a.y - pcy;
       const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
-      const bool live = !done && power <= 0.0f && power >= bc.y;
-      // Divergent: only live lanes run the rest, and the wave skips it when none is live.
-      if (live) {
-        const float prod = c.y * cexp_core(power);
-        const float al = fminf(0.99f, prod);
-        const bool use = live && al >= kSkip;
-        const float Tn = T * (1.0f - al);
-        const bool stop = use && Tn < kTmin;
-        const bool blend = use && !stop;
-        const uint32_t pos = base - rg.x + (uint32_t)e;
-        // A zero weight leaves the sums unchanged (colours are finite and >= 0), so the
-        // select is taken once, on the weight.
-        const float w = blend ? al * T : 0.0f;
+      const uint64_t lm = ballot64(power <= 0.0f) & ballot64(power >= bc.y) & ~dm;
+      if (lm == 0ull) return;
+      // Lanes outside the live set keep placeholder values (dead registers, so no copies);
+      // their tests below are masked off.
+      float al = power, Tn = dx;
+      if (__builtin_amdgcn_inverse_ballot_w64(lm)) {
+        al = fminf(0.99f, c.y * cexp_core(power));
+        Tn = T * (1.0f - al);
+      }
+      // al is never NaN (fminf returns 0.99 for a NaN product) and T is in (0, 1], so
+      // Tn >= fl(1e-4) is exactly the negation of the contract's termination test.
+      const uint64_t um = ballot64(al >= kSkip) & lm;
+      const uint64_t km = ballot64(Tn >= kTmin);
+      const uint64_t bm = um & km;
+      dm |= um & ~km;
+      const uint32_t pos = base - rg.x + (uint32_t)e;
+      if (__builtin_amdgcn_inverse_ballot_w64(bm)) {
+        const float w = al * T;
         cr = fmaf_(c.z, w, cr);
         cg = fmaf_(c.w, w, cg);
         cb = fmaf_(bc.x, w, cb);
-        T = blend ? Tn : T;
-        last = blend ? pos + 1u : last;
-        done = done || stop;
-        if (kCount) {   // work counters only when asked for (they cost the per-entry loop)
-          term = stop ? pos : term;
-          nexp += live ? 1u : 0u;
-          nblend += blend ? 1u : 0u;
-        }
+        T = Tn;
+        last = pos + 1u;
+      }
+      if (kCount) {   // work counters only when asked for (they cost the per-entry loop)
+        if (__builtin_amdgcn_inverse_ballot_w64(um & ~km)) term = pos;
+        nexp += __builtin_amdgcn_inverse_ballot_w64(lm) ? 1u : 0u;
+        nblend += __builtin_amdgcn_inverse_ballot_w64(bm) ? 1u : 0u;
       }
     };
     // Two register sets in alternation: the LDS reads of the next entry are in flight while
@@ -213,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
       mask &= mask - 1;
       a0 = s0[e0]; c0 = s1[e0]; b0 = s2[e0];
       pair(a1, c1, b1, e1);
-      if (!more || ballot64(!done) == 0ull) break;
+      if (!more || dm == ~0ull) break;
     }
   }
   if (inside) {
