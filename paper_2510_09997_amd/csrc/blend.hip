@@ -304,15 +304,13 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     float* __restrict__ gscreen, const uint32_t* __restrict__ order) {
   __shared__ float4 s0[kBlock];   // u, v, A, B
   __shared__ float4 s1[kBlock];   // C, alpha'', r, g
-  __shared__ float2 s2[kBlock];   // b, power cut
+  __shared__ float4 s2[kBlock];   // b, power cut, -, - (same stride as s0, s1: one address)
   __shared__ float acc[kGscreen][kBlock + 1];   // padded: the 9 partials of one entry hit 9 banks
   __shared__ uint32_t sidx[kBlock];
-  __shared__ uint16_t list[4][kBlock];
-  __shared__ uint32_t wc[4][4];
+  __shared__ unsigned long long qmask[4][4];    // [staging wave][quadrant]: entries that may reach it
   __shared__ uint32_t smax[4];
   if (blockIdx.x >= tiles_total) return;
   const int tile_i = (int)order[blockIdx.x];
-  
   if (hdr[kHdrOverflow]) return;
   const int v = view_of_tile(views, V, (uint32_t)tile_i);
   const DevView& Vw = views[v];
@@ -330,7 +328,6 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   const int64_t P = (int64_t)Vw.pix_base;
   const int64_t HW = (int64_t)Vw.width * Vw.height;
   const int64_t p = (int64_t)py * Vw.width + px;
-  const uint64_t lt = lanemask_lt();
   uint32_t last = 0;
   float T = 1.0f, g0c = 0.f, g1c = 0.f, g2c = 0.f;
   if (inside) {
@@ -363,71 +360,64 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
       const float cut = entry_cut(a0.z);
       s0[threadIdx.x] = make_float4(a0.x, a0.y, a1.x, a1.y);
       s1[threadIdx.x] = make_float4(a1.z, a0.z, a2.x, a2.y);
-      s2[threadIdx.x] = make_float2(a2.z, cut);
+      s2[threadIdx.x] = make_float4(a2.z, cut, 0.f, 0.f);
       sidx[threadIdx.x] = f;
       qm = quadrant_mask(a0.x, a0.y, a1.x, a1.y, a1.z, a0.w, cut, tx0, ty0);
     }
 #pragma unroll
     for (int q = 0; q < kGscreen; ++q) acc[q][threadIdx.x] = 0.0f;
-    uint32_t pre[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint64_t b = ballot64((qm >> q) & 1u);
-      pre[q] = (uint32_t)__popcll(b & lt);
-      if (lane == 0) wc[q][wave] = (uint32_t)__popcll(b);
+      if (lane == 0) qmask[wave][q] = b;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if ((qm >> q) & 1u) {
-        uint32_t off = pre[q];
-        for (int w = 0; w < wave; ++w) off += wc[q][w];
-        list[q][off] = (uint16_t)threadIdx.x;
-      }
-    }
-    __syncthreads();
-    const int qcnt = (int)(wc[wave][0] + wc[wave][1] + wc[wave][2] + wc[wave][3]);
-    for (int kk = qcnt - 1; kk >= 0; --kk) {
-      const int k = list[wave][kk];
-      const uint32_t pos = lo - rg.x + (uint32_t)k;
-      const float4 a = s0[k];
-      const float4 c = s1[k];
-      const float2 bc = s2[k];
-      const float cb_ = bc.x;
-      const float dx = a.x - pcx, dy = a.y - pcy;
-      const float hA = -0.5f * a.z, nB = -a.w, hC = -0.5f * c.x;
-      const float power = fmaf_(hA * dx, dx, fmaf_(hC * dy, dy, (nB * dx) * dy));
-      // Straight-line code under per-lane predicates, as in the forward; lanes that are not
-      // live compute discarded values (live powers lie in [cut, 0], inside cexp_core's range).
-      const bool live = pos < last && power <= 0.0f && power >= bc.y;
-      if (ballot64(live) == 0ull) continue;
-      const float G = cexp_core(power);
-      const float prod = c.y * G;
-      const float al = fminf(0.99f, prod);
-      const bool contrib = live && al >= kSkip;
-      const bool geo = contrib && prod <= 0.99f;
-      const float oma = 1.0f - al;
-      // T before the entry, T / (1 - a): only gradients use it, so a hardware reciprocal with
-      // one Newton step (within an ulp) replaces the correctly rounded division.
-      const float r0 = __builtin_amdgcn_rcpf(oma);
-      const float Tk = T * fmaf(fmaf(-oma, r0, 1.0f), r0, r0);
-      const float wgt = al * Tk;
-      const float dLda = Tk * (g0c * (c.z - R0) + g1c * (c.w - R1) + g2c * (cb_ - R2));
-      const float gp = dLda * prod;
-      const float gr = contrib ? g0c * wgt : 0.f;
-      const float gg = contrib ? g1c * wgt : 0.f;
-      const float gb = contrib ? g2c * wgt : 0.f;
-      const float ga2 = geo ? dLda * G : 0.f;
-      const float gu = geo ? -gp * (a.z * dx + a.w * dy) : 0.f;
-      const float gv = geo ? -gp * (c.x * dy + a.w * dx) : 0.f;
-      const float gA = geo ? -0.5f * gp * dx * dx : 0.f;
-      const float gB = geo ? -gp * dx * dy : 0.f;
-      const float gC = geo ? -0.5f * gp * dy * dy : 0.f;
-      R0 = contrib ? c.z * al + oma * R0 : R0;
-      R1 = contrib ? c.w * al + oma * R1 : R1;
-      R2 = contrib ? cb_ * al + oma * R2 : R2;
-      T = contrib ? Tk : T;
-      if (ballot64(contrib) != 0ull) {
+    // Walk this quadrant's entries back to front: staging waves 3..0, each mask from its
+    // highest bit down.  Masks, entry index and position are wave-uniform (scalar registers).
+    for (int c = 3; c >= 0; --c) {
+      const unsigned long long mv = qmask[c][wave];
+      uint64_t mk = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(mv >> 32)) << 32) |
+                    (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)mv);
+      while (mk != 0ull) {
+        const int e = 63 - __builtin_clzll(mk);
+        mk &= ~(1ull << e);
+        const int k = c * 64 + e;
+        const uint32_t pos = lo - rg.x + (uint32_t)k;
+        const float4 a = s0[k];
+        const float4 c4 = s1[k];
+        const float4 bc = s2[k];
+        const float dx = a.x - pcx, dy = a.y - pcy;
+        const float hA = -0.5f * a.z, nB = -a.w, hC = -0.5f * c4.x;
+        const float power = fmaf_(hA * dx, dx, fmaf_(hC * dy, dy, (nB * dx) * dy));
+        // Live: blended in the forward (position < last) with power in [cut, 0].  Other lanes
+        // compute discarded values (finite: their powers are tiny positives or below cut).
+        const uint64_t lm = ballot64(pos < last) & ballot64(power <= 0.0f) & ballot64(power >= bc.y);
+        if (lm == 0ull) continue;
+        const float G = cexp_core(power);
+        const float prod = c4.y * G;
+        const float al = fminf(0.99f, prod);
+        const uint64_t cm = ballot64(al >= kSkip) & lm;       // contributing lanes
+        if (cm == 0ull) continue;
+        const uint64_t gm = ballot64(prod <= 0.99f) & cm;     // ... below the clamp
+        const bool contrib = __builtin_amdgcn_inverse_ballot_w64(cm);
+        const bool geo = __builtin_amdgcn_inverse_ballot_w64(gm);
+        const float oma = 1.0f - al;
+        // T before the entry, T / (1 - a): only gradients use it, so a hardware reciprocal with
+        // one Newton step (within an ulp) replaces the correctly rounded division.
+        const float r0 = __builtin_amdgcn_rcpf(oma);
+        const float Tk = T * fmaf(fmaf(-oma, r0, 1.0f), r0, r0);
+        const float dLda = Tk * (g0c * (c4.z - R0) + g1c * (c4.w - R1) + g2c * (bc.x - R2));
+        // Zeroing the three factors zeroes every partial of the lanes that do not take part
+        // (the other factors are finite).
+        const float gp = geo ? dLda * prod : 0.f;
+        const float ga2 = geo ? dLda * G : 0.f;
+        const float wgt = contrib ? al * Tk : 0.f;
+        const float gr = g0c * wgt, gg = g1c * wgt, gb = g2c * wgt;
+        const float gu = -gp * (a.z * dx + a.w * dy);
+        const float gv = -gp * (c4.x * dy + a.w * dx);
+        const float gA = -0.5f * gp * dx * dx;
+        const float gB = -gp * dx * dy;
+        const float gC = -0.5f * gp * dy * dy;
         // Wave totals of the nine partials (eight reduced together: lanes 8q.. hold partial q;
         // the ninth on its own), then one LDS atomic instruction over nine lanes.
         const float g8[8] = {gu, gv, gA, gB, gC, ga2, gr, gg};
@@ -436,6 +426,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
         if ((lane & 7u) == 0u || lane == 1u) {
           const uint32_t q = lane == 1u ? 8u : lane >> 3;
           atomicAdd(&acc[q][k], lane == 1u ? tb : t8);
+        }
+        if (contrib) {
+          R0 = c4.z * al + oma * R0;
+          R1 = c4.w * al + oma * R1;
+          R2 = bc.x * al + oma * R2;
+          T = Tk;
         }
       }
     }
