@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 9
+ABI_VERSION = 10
 
 
 class ClodError(RuntimeError):

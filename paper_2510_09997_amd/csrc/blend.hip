@@ -294,7 +294,8 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
 // dC/da_k = T_k (c_k - R_k).  Same quadrant mapping and per-quadrant compaction as the
 // forward (culled entries are ones the forward skipped).  Per entry the 9 screen-space
 // partials are reduced over the wave, summed over the 4 waves in LDS, and added to the
-// global accumulator once per tile.
+// global accumulator once per tile.  The accumulator holds the nine partials of a record as
+// consecutive floats, so the flush sends each entry's nine atomics to one 36-byte span.
 __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
     const float4* __restrict__ rec, const uint2* __restrict__ ranges,
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   __shared__ float4 s0[kBlock];   // u, v, A, B
   __shared__ float4 s1[kBlock];   // C, alpha'', r, g
   __shared__ float4 s2[kBlock];   // b, power cut, -, - (same stride as s0, s1: one address)
-  __shared__ float acc[kGscreen][kBlock + 1];   // padded: the 9 partials of one entry hit 9 banks
+  __shared__ float acc[kBlock * kGscreen];   // [entry][9]: odd stride, conflict-free
   __shared__ uint32_t sidx[kBlock];
   __shared__ unsigned long long qmask[4][4];    // [staging wave][quadrant]: entries that may reach it
   __shared__ uint32_t smax[4];
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
       qm = quadrant_mask(a0.x, a0.y, a1.x, a1.y, a1.z, a0.w, cut, tx0, ty0);
     }
 #pragma unroll
-    for (int q = 0; q < kGscreen; ++q) acc[q][threadIdx.x] = 0.0f;
+    for (int q = 0; q < kGscreen; ++q) acc[q * kBlock + threadIdx.x] = 0.0f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint64_t b = ballot64((qm >> q) & 1u);
@@ -425,7 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
         const float tb = wave_sum_dpp(gb);
         if ((lane & 7u) == 0u || lane == 1u) {
           const uint32_t q = lane == 1u ? 8u : lane >> 3;
-          atomicAdd(&acc[q][k], lane == 1u ? tb : t8);
+          atomicAdd(&acc[k * kGscreen + q], lane == 1u ? tb : t8);
         }
         if (contrib) {
           R0 = c4.z * al + oma * R0;
@@ -436,13 +437,11 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
       }
     }
     __syncthreads();
-    if ((int)threadIdx.x < cnt) {
-      const uint32_t f = sidx[threadIdx.x];
-#pragma unroll
-      for (int q = 0; q < kGscreen; ++q) {
-        const float val = acc[q][threadIdx.x];
-        if (val != 0.0f) atomicAdd(gscreen + (int64_t)q * VN + f, val);
-      }
+    // Flush: consecutive threads take consecutive (entry, partial) items.
+    for (int it = threadIdx.x; it < cnt * kGscreen; it += kBlock) {
+      const int t = it / kGscreen;
+      const float val = acc[it];
+      if (val != 0.0f) atomicAdd(gscreen + (int64_t)sidx[t] * kGscreen + (it - t * kGscreen), val);
     }
     hi = lo;
   }

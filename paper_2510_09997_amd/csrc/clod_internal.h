@@ -26,7 +26,7 @@ constexpr int kSortItems = 8;              // keys per thread per radix tile
 constexpr int kSortTile = kBlock * kSortItems;   // 2048 keys per radix tile
 constexpr int kMaxSortBlocks = 1024;
 constexpr int kMaxProjBlocks = 2048;      // per-block partial reductions of the per-Gaussian passes
-constexpr int kGscreen = 9;                // du, dv, dA, dB, dC, dalpha'', dr, dg, db
+constexpr int kGscreen = 9;                // du, dv, dA, dB, dC, dalpha'', dr, dg, db (interleaved per record)
 
 // Per-view constants derived on the device from clod_view (k_view_setup).
 struct DevView {

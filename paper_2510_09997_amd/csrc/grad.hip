@@ -96,9 +96,10 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
       float gx = 0.f, gy = 0.f, gz = 0.f;     // camera-space position
       float gex = 0.f, gey = 0.f, gez = 0.f;  // world offset mu - c
       if (fl & 4) {
-        const float gu = gscreen[f], gv = gscreen[VN + f];
-        const float gA = gscreen[2 * VN + f], gB = gscreen[3 * VN + f], gC = gscreen[4 * VN + f];
-        ga2 += gscreen[5 * VN + f];
+        const float* gs = gscreen + f * kGscreen;
+        const float gu = gs[0], gv = gs[1];
+        const float gA = gs[2], gB = gs[3], gC = gs[4];
+        ga2 += gs[5];
         float x, y, z;
         to_camera(Vw, mx, my, mz, x, y, z);
         if (!have_cov) {
@@ -249,9 +250,9 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(clod_scene sc, const DevView*
       const uint8_t fl = flags[f];
       if (!(fl & 4)) continue;
       const DevView& Vw = views[v];
-      const float gc0 = (fl & 8) ? 0.f : gscreen[6 * VN + f];
-      const float gc1 = (fl & 16) ? 0.f : gscreen[7 * VN + f];
-      const float gc2 = (fl & 32) ? 0.f : gscreen[8 * VN + f];
+      const float gc0 = (fl & 8) ? 0.f : gscreen[f * kGscreen + 6];
+      const float gc1 = (fl & 16) ? 0.f : gscreen[f * kGscreen + 7];
+      const float gc2 = (fl & 32) ? 0.f : gscreen[f * kGscreen + 8];
       float ex, ey, ez;
       const float id = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(cam_distance2(Vw, mx, my, mz, ex, ey, ez)));
       const float X = ex * id, Y = ey * id, Z = ez * id;

@@ -159,10 +159,8 @@ class Batch:
         assert 0 <= off and off + n * elem <= base.numel()
         raw = base[off:off + n * elem].clone()
         if section == C.SEC_GSCREEN:
-            # [9][VN] planes: rebuild from the 9 planes of VN floats each.
-            vn = n
-            raw = base[off:off + 9 * vn * 4].clone()
-            return raw.view(torch.float32).view(9, vn)
+            # Nine partials per (view, Gaussian), interleaved: returned as [VN, 9].
+            return raw.view(torch.float32).view(n, 9)
         dt = {8: torch.int64, 4: torch.int32, 64: torch.float32, 1: torch.uint8}[elem]
         if section == C.SEC_ALPHA:
             dt = torch.float32
