@@ -194,17 +194,28 @@ __device__ __forceinline__ float cam_distance(const DevView& V, float mx, float 
 
 __device__ __forceinline__ float sigmoid_c(float o) { return 1.0f / (1.0f + cexp(-o)); }
 
-// Attenuated opacity of Eq. (2) (also returns alpha and q for the adjoint).
-__device__ __forceinline__ float attenuated(float d, float dmax, float s_v, float decay, float opac,
-                                            float eps, float& alpha, float& q) {
+// The view-independent denominator of Eq. (2): 2 max(sigma_d, 0)^2 + eps.
+__device__ __forceinline__ float decay_den(float decay, float eps) {
+  const float r = fmaxf(decay, 0.0f);
+  return fmaf_(2.0f * r, r, eps);
+}
+
+// Eq. (2) for one view with the per-Gaussian parts (alpha = sigmoid of the opacity logit and
+// the decay denominator) computed once and passed in; returns alpha'' and q.
+__device__ __forceinline__ float attenuated_pre(float d, float dmax, float s_v, float alpha, float den,
+                                                float& q) {
   const float dn = d / dmax;
   const float u = dn * s_v;
   const float num = u * u;
-  const float r = fmaxf(decay, 0.0f);
-  const float den = fmaf_(2.0f * r, r, eps);
   q = num / den;
-  alpha = sigmoid_c(opac);
   return alpha * cexp(-q);
+}
+
+// Attenuated opacity of Eq. (2) (also returns alpha and q for the adjoint).
+__device__ __forceinline__ float attenuated(float d, float dmax, float s_v, float decay, float opac,
+                                            float eps, float& alpha, float& q) {
+  alpha = sigmoid_c(opac);
+  return attenuated_pre(d, dmax, s_v, alpha, decay_den(decay, eps), q);
 }
 
 // EWA projection of one Gaussian.  Returns false when culled (det <= 0 or empty rect).

@@ -231,7 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(
   for (int64_t it = 0; it < iters; ++it) {
     const int64_t i = lo + it * kBlock + threadIdx.x;
     const bool valid = i < hi;
-    const float mx = nmx, my = nmy, mz = nmz, op = nop, dc = ndc;
+    const float mx = nmx, my = nmy, mz = nmz;
+    const float alpha = sigmoid_c(nop), den = decay_den(ndc, prm.eps);   // view independent
     {
       const int64_t i2 = i + kBlock;
       if (it + 1 < iters && i2 < hi) {
@@ -250,8 +251,8 @@ __global__ __launch_bounds__(kBlock) void k_classify(
         const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
         const unsigned long long dk = dmax_key[v];
         if (F && dk != 0ull && __float_as_uint(d) == (uint32_t)(dk >> 32)) atomicMin(&scnt[3 * v + 2], (uint32_t)i);
-        float alpha, q;
-        const float a2 = attenuated(d, dmax_from_key(dk), Vw.s_v, dc, op, prm.eps, alpha, q);
+        float q;
+        const float a2 = attenuated_pre(d, dmax_from_key(dk), Vw.s_v, alpha, den, q);
         M = lod_kept(Vw, a2, i);
         if (kWrite) {
           const int64_t f = (int64_t)v * n + i;
@@ -343,6 +344,7 @@ __device__ __forceinline__ void project_body(
       mx = sc.mean[i]; my = sc.mean[n + i]; mz = sc.mean[2 * n + i];
       op = sc.opacity[i]; dc = sc.decay[i];
     }
+    const float alpha = sigmoid_c(op), den = decay_den(dc, prm.eps);   // view independent
     // Rotation and 3D covariance are view independent: computed on first use.
     bool have_cov = false;
     float S[9];
@@ -358,8 +360,8 @@ __device__ __forceinline__ void project_body(
           to_camera(Vw, mx, my, mz, x, y, z);
           const bool F = in_frustum(Vw, x, y, z, prm.near_z);
           const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
-          float alpha, q;
-          const float a2 = attenuated(d, dmax_from_key(dmax_key[v]), Vw.s_v, dc, op, prm.eps, alpha, q);
+          float q;
+          const float a2 = attenuated_pre(d, dmax_from_key(dmax_key[v]), Vw.s_v, alpha, den, q);
           if (F && lod_kept(Vw, a2, i)) {
             if (!have_cov) {
               const float s0 = cexp(sc.log_scale[i]), s1 = cexp(sc.log_scale[n + i]), s2 = cexp(sc.log_scale[2 * n + i]);
