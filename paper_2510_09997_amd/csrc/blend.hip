@@ -291,10 +291,12 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
 // decision exactly as the forward; transmittance is recovered by division
 // (T_k = T_{k+1} / (1 - a_k)); the normalised colour of everything behind entry k obeys
 // R_{k-1} = c_k a_k + (1 - a_k) R_k with R = background after the last entry, so
-// dC/da_k = T_k (c_k - R_k).  Same quadrant mapping and per-quadrant compaction as the
-// forward (culled entries are ones the forward skipped).  Per entry the 9 screen-space
-// partials are reduced over the wave, summed over the 4 waves in LDS, and added to the
-// global accumulator once per tile.  The accumulator holds the nine partials of a record as
+// dC/da_k = T_k (c_k - R_k); only g . R (g = dL/dC of the pixel) is needed, and it obeys the
+// same recurrence.  Same quadrant mapping and per-quadrant compaction as the forward (culled
+// entries are ones the forward skipped).  Per entry nine sums (five moments of dL/dpower, the
+// alpha'' partial and three colour partials) are reduced over the wave, summed over the 4
+// waves in LDS, turned into the 9 screen-space partials and added to the global accumulator
+// once per tile.  The accumulator holds the nine partials of a record as
 // consecutive floats, so the flush sends each entry's nine atomics to one 36-byte span.
 __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
@@ -338,7 +340,9 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     g1c = dL_drgb[3 * P + HW + p];
     g2c = dL_drgb[3 * P + 2 * HW + p];
   }
-  float R0 = bg0, R1 = bg1, R2 = bg2;
+  // g . R: the pixel's colour gradient dotted with the normalised colour behind the current
+  // entry (R starts as the background), kept as one scalar through the same recurrence.
+  float gR = fmaf_(g0c, bg0, fmaf_(g1c, bg1, g2c * bg2));
   // Largest last in the tile bounds the walk.
   uint32_t m = last;
 #pragma unroll
@@ -407,21 +411,21 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
         // one Newton step (within an ulp) replaces the correctly rounded division.
         const float r0 = __builtin_amdgcn_rcpf(oma);
         const float Tk = T * fmaf(fmaf(-oma, r0, 1.0f), r0, r0);
-        const float dLda = Tk * (g0c * (c4.z - R0) + g1c * (c4.w - R1) + g2c * (bc.x - R2));
+        const float gc = fmaf_(g0c, c4.z, fmaf_(g1c, c4.w, g2c * bc.x));   // g . c_k
+        const float dLda = Tk * (gc - gR);
         // Zeroing the three factors zeroes every partial of the lanes that do not take part
         // (the other factors are finite).
-        const float gp = geo ? dLda * prod : 0.f;
+        const float gp = geo ? dLda * prod : 0.f;   // dL/dpower
         const float ga2 = geo ? dLda * G : 0.f;
         const float wgt = contrib ? al * Tk : 0.f;
         const float gr = g0c * wgt, gg = g1c * wgt, gb = g2c * wgt;
-        const float gu = -gp * (a.z * dx + a.w * dy);
-        const float gv = -gp * (c4.x * dy + a.w * dx);
-        const float gA = -0.5f * gp * dx * dx;
-        const float gB = -gp * dx * dy;
-        const float gC = -0.5f * gp * dy * dy;
-        // Wave totals of the nine partials (eight reduced together: lanes 8q.. hold partial q;
-        // the ninth on its own), then one LDS atomic instruction over nine lanes.
-        const float g8[8] = {gu, gv, gA, gB, gC, ga2, gr, gg};
+        // The partials of u, v and the conic are linear in five moments of dL/dpower over the
+        // pixels (sums of gp dx, gp dy, gp dx^2, gp dx dy, gp dy^2); the moments are reduced and
+        // the conic coefficients applied once per entry at the flush.
+        const float gpx = gp * dx, gpy = gp * dy;
+        // Wave totals of the nine sums (eight reduced together: lanes 8q.. hold sum q; the
+        // ninth on its own), then one LDS atomic instruction over nine lanes.
+        const float g8[8] = {gpx, gpy, gpx * dx, gpx * dy, gpy * dy, ga2, gr, gg};
         const float t8 = wave_sum8(g8);
         const float tb = wave_sum_dpp(gb);
         if ((lane & 7u) == 0u || lane == 1u) {
@@ -429,19 +433,27 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
           atomicAdd(&acc[k * kGscreen + q], lane == 1u ? tb : t8);
         }
         if (contrib) {
-          R0 = c4.z * al + oma * R0;
-          R1 = c4.w * al + oma * R1;
-          R2 = bc.x * al + oma * R2;
+          gR = fmaf_(al, gc, oma * gR);   // R_{k-1} = c_k a_k + (1 - a_k) R_k, dotted with g
           T = Tk;
         }
       }
     }
     __syncthreads();
-    // Flush: consecutive threads take consecutive (entry, partial) items.
+    // Flush: consecutive threads take consecutive (entry, partial) items; the first five
+    // items of an entry turn its moments into the partials of u, v, A, B and C:
+    // du = -(A m0 + B m1), dv = -(C m1 + B m0), dA = -m2 / 2, dB = -m3, dC = -m4 / 2.
     for (int it = threadIdx.x; it < cnt * kGscreen; it += kBlock) {
       const int t = it / kGscreen;
-      const float val = acc[it];
-      if (val != 0.0f) atomicAdd(gscreen + (int64_t)sidx[t] * kGscreen + (it - t * kGscreen), val);
+      const int q = it - t * kGscreen;
+      float val = acc[it];
+      if (q < 5) {
+        const float m0 = acc[t * kGscreen], m1 = acc[t * kGscreen + 1];
+        const float A = s0[t].z, B = s0[t].w, C = s1[t].x;
+        val = q == 0 ? -fmaf_(A, m0, B * m1)
+            : q == 1 ? -fmaf_(C, m1, B * m0)
+            : q == 3 ? -val : -0.5f * val;
+      }
+      if (val != 0.0f) atomicAdd(gscreen + (int64_t)sidx[t] * kGscreen + q, val);
     }
     hi = lo;
   }
