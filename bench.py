@@ -137,6 +137,17 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     for sb in slots:
         info = C.clod_read_info(sb.c_struct())
         assert not info["overflow"], "duplicate buffer overflow inside the timed region"
+    # Each slot's output of its last pipelined step against a sequential re-render of the same
+    # step on the default stream (untimed): the overlap must not change a single byte.
+    identical = True
+    for i in range(NS):
+        ks = [k for k in range(K) if k % NS == i]
+        if not ks:
+            continue
+        got = [o.clone() for o in outs[i]]
+        step(W + ks[-1], slot=i)
+        torch.cuda.synchronize()
+        identical = identical and all(torch.equal(a, b_) for a, b_ in zip(got, outs[i]))
     proj_ms = sum(e[3].elapsed_time(e[0]) for e in evs) / K
     sort_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / K
     blend_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / K
@@ -156,6 +167,7 @@ def run_serving(args, torch, C, Batch, Scene, synth):
         torch.cuda.synchronize()
         pairs_per_step = (pairs.cpu().numpy() / K).tolist()
     res = dict(total_ms=total_ms, ms_per_step=total_ms / K, fps=frames / (total_ms / 1e3), streams=NS,
+               pipelined_identical=identical,
                sequential_fps=frames / (seq_ms / 1e3), sequential_ms_per_step=seq_ms / K,
                stage_ms=dict(project=proj_ms, bin_sort=sort_ms, blend_fwd=blend_ms),
                pairs_per_step=pairs_per_step, max_dup=dmax, blend_launches=K,
@@ -566,6 +578,7 @@ def main():
         "config": {"workload": "serve-1080p-3M-lod-sweep", "gaussians": 3_000_000, "sh_degree": 3,
                    "resolution": [1920, 1080], "s_v": list(SV_SWEEP), "frames_per_step": len(SV_SWEEP),
                    "pose_radius": [3.0, 30.0], "streams": serve["streams"]},
+        "pipelined_matches_sequential": serve["pipelined_identical"],
         "sequential_fps": round(serve["sequential_fps"], 2),
         "plain_path_fps": round(serve["plain_fps"], 2) if "plain_fps" in serve else None,
         "stage_ms": {k: round(v, 4) for k, v in serve["stage_ms"].items()},
