@@ -80,6 +80,9 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
   const float iden = frcp(2.f * r * r + prm.eps);
   bool have_cov = false;
   float s[3], Rm[9], S[9], qn[4], rn = 0.f;
+  // dL/dSigma summed over the rendering views (Sigma is view independent, so the chain
+  // Sigma -> M -> (scale, rotation) -> quaternion runs once, after the view loop).
+  float gSig[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
   for (int v = 0; v < V; ++v) {
     const DevView& Vw = views[v];
     float gdm = 0.f;
@@ -141,11 +144,17 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
           gT[k] = 2.f * (Gp00 * TS[k] + Gp01 * TS[3 + k]);
           gT[3 + k] = 2.f * (Gp01 * TS[k] + Gp11 * TS[3 + k]);
         }
-        // dL/dSigma = T^T G' T (symmetric 3x3)
-        float gS[9];
-        for (int j = 0; j < 3; ++j)
-          for (int k = 0; k < 3; ++k)
-            gS[3 * j + k] = T[j] * (Gp00 * T[k] + Gp01 * T[3 + k]) + T[3 + j] * (Gp01 * T[k] + Gp11 * T[3 + k]);
+        // dL/dSigma = T^T G' T (symmetric 3x3), accumulated over the views.
+        {
+          const float u0 = Gp00 * T[0] + Gp01 * T[3], u1 = Gp00 * T[1] + Gp01 * T[4], u2 = Gp00 * T[2] + Gp01 * T[5];
+          const float w0 = Gp01 * T[0] + Gp11 * T[3], w1 = Gp01 * T[1] + Gp11 * T[4], w2 = Gp01 * T[2] + Gp11 * T[5];
+          gSig[0] += T[0] * u0 + T[3] * w0;
+          gSig[1] += T[0] * u1 + T[3] * w1;
+          gSig[2] += T[0] * u2 + T[3] * w2;
+          gSig[3] += T[1] * u1 + T[4] * w1;
+          gSig[4] += T[1] * u2 + T[4] * w2;
+          gSig[5] += T[2] * u2 + T[5] * w2;
+        }
         // dL/dJ = dL/dT W^T; J depends on (x, y, z).
         float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f;
         for (int k = 0; k < 3; ++k) {
@@ -158,34 +167,6 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
         gz += -Vw.fx * iz2 * gJ00 + 2.f * Vw.fx * x * iz3 * gJ02 - Vw.fy * iz2 * gJ11 + 2.f * Vw.fy * y * iz3 * gJ12;
         gx += -Vw.fx * iz2 * gJ02;
         gy += -Vw.fy * iz2 * gJ12;
-        // Sigma = M M^T, M = R diag(s): dL/dM = 2 gS M.
-        float Mm[9];
-        for (int j = 0; j < 3; ++j)
-          for (int l = 0; l < 3; ++l) Mm[3 * j + l] = Rm[3 * j + l] * s[l];
-        float gM[9];
-        for (int j = 0; j < 3; ++j)
-          for (int l = 0; l < 3; ++l)
-            gM[3 * j + l] = 2.f * (gS[3 * j] * Mm[l] + gS[3 * j + 1] * Mm[3 + l] + gS[3 * j + 2] * Mm[6 + l]);
-        float gR[9];
-        for (int l = 0; l < 3; ++l) {
-          float gs_l = 0.f;
-          for (int j = 0; j < 3; ++j) {
-            gs_l += gM[3 * j + l] * Rm[3 * j + l];
-            gR[3 * j + l] = gM[3 * j + l] * s[l];
-          }
-          gls[l] += gs_l * s[l];
-        }
-        // Rotation matrix of the unit quaternion (w, x, y, z).
-        const float w_ = qn[0], x_ = qn[1], y_ = qn[2], z_ = qn[3];
-        const float gw = 2.f * (-z_ * gR[1] + y_ * gR[2] + z_ * gR[3] - x_ * gR[5] - y_ * gR[6] + x_ * gR[7]);
-        const float gxq = 2.f * (-2.f * x_ * gR[4] - 2.f * x_ * gR[8] + y_ * gR[1] + z_ * gR[2] + y_ * gR[3] - w_ * gR[5] + z_ * gR[6] + w_ * gR[7]);
-        const float gyq = 2.f * (-2.f * y_ * gR[0] - 2.f * y_ * gR[8] + x_ * gR[1] + w_ * gR[2] + x_ * gR[3] + z_ * gR[5] - w_ * gR[6] + z_ * gR[7]);
-        const float gzq = 2.f * (-2.f * z_ * gR[0] - 2.f * z_ * gR[4] - w_ * gR[1] + x_ * gR[2] + w_ * gR[3] + y_ * gR[5] + x_ * gR[6] + y_ * gR[7]);
-        const float qdot = w_ * gw + x_ * gxq + y_ * gyq + z_ * gzq;
-        gq[0] += (gw - w_ * qdot) * rn;
-        gq[1] += (gxq - x_ * qdot) * rn;
-        gq[2] += (gyq - y_ * qdot) * rn;
-        gq[3] += (gzq - z_ * qdot) * rn;
       }
       // Eq. (2): alpha'' = sigmoid(o) exp(-q), q = (d' s_v)^2 / (2 relu(sigma)^2 + eps).
       gop += ga2 * a2 * (1.0f - alpha);
@@ -208,6 +189,37 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
     // Per-view, per-block sum of the frustum-maximum partial (LDS, one add per wave).
     gdm = wave_sum(gdm);
     if (lane_id() == 0 && gdm != 0.f) atomicAdd(&gsum[v], gdm);
+  }
+  if (have_cov) {
+    // Sigma = M M^T, M = R diag(s): dL/dM = 2 (dL/dSigma) M.
+    const float gS[9] = {gSig[0], gSig[1], gSig[2], gSig[1], gSig[3], gSig[4], gSig[2], gSig[4], gSig[5]};
+    float Mm[9];
+    for (int j = 0; j < 3; ++j)
+      for (int l = 0; l < 3; ++l) Mm[3 * j + l] = Rm[3 * j + l] * s[l];
+    float gM[9];
+    for (int j = 0; j < 3; ++j)
+      for (int l = 0; l < 3; ++l)
+        gM[3 * j + l] = 2.f * (gS[3 * j] * Mm[l] + gS[3 * j + 1] * Mm[3 + l] + gS[3 * j + 2] * Mm[6 + l]);
+    float gR[9];
+    for (int l = 0; l < 3; ++l) {
+      float gs_l = 0.f;
+      for (int j = 0; j < 3; ++j) {
+        gs_l += gM[3 * j + l] * Rm[3 * j + l];
+        gR[3 * j + l] = gM[3 * j + l] * s[l];
+      }
+      gls[l] += gs_l * s[l];
+    }
+    // Rotation matrix of the unit quaternion (w, x, y, z).
+    const float w_ = qn[0], x_ = qn[1], y_ = qn[2], z_ = qn[3];
+    const float gw = 2.f * (-z_ * gR[1] + y_ * gR[2] + z_ * gR[3] - x_ * gR[5] - y_ * gR[6] + x_ * gR[7]);
+    const float gxq = 2.f * (-2.f * x_ * gR[4] - 2.f * x_ * gR[8] + y_ * gR[1] + z_ * gR[2] + y_ * gR[3] - w_ * gR[5] + z_ * gR[6] + w_ * gR[7]);
+    const float gyq = 2.f * (-2.f * y_ * gR[0] - 2.f * y_ * gR[8] + x_ * gR[1] + w_ * gR[2] + x_ * gR[3] + z_ * gR[5] - w_ * gR[6] + z_ * gR[7]);
+    const float gzq = 2.f * (-2.f * z_ * gR[0] - 2.f * z_ * gR[4] - w_ * gR[1] + x_ * gR[2] + w_ * gR[3] + y_ * gR[5] + x_ * gR[6] + y_ * gR[7]);
+    const float qdot = w_ * gw + x_ * gxq + y_ * gyq + z_ * gzq;
+    gq[0] += (gw - w_ * qdot) * rn;
+    gq[1] += (gxq - x_ * qdot) * rn;
+    gq[2] += (gyq - y_ * qdot) * rn;
+    gq[3] += (gzq - z_ * qdot) * rn;
   }
   if (valid) {
     auto put = [&](float* p, int64_t idx, float val) { p[idx] = accumulate ? p[idx] + val : val; };
