@@ -236,7 +236,8 @@ clod_status clod_read_info(const clod_batch *batch, int64_t *info_host, void *st
                        bits 3..5 colour clamped
      CLOD_SEC_DMAX     uint64 per view: bits(d_max) << 32 | (2^32 - 1 - argmax), 0 if empty
      CLOD_SEC_GSCREEN  float [n_views * n][9] screen-space partials of the last backward
-                       (u, v, conic A, B, C, alpha'', r, g, b), nine per (view, Gaussian)
+                       (u, v, conic A, B, C, alpha'', r, g, b), nine per (view, Gaussian);
+                       only rendered records are cleared and accumulated, others unspecified
      CLOD_SEC_HEADER   uint64 [2] = {D of the last clod_bin_sort, overflow flag} (count = 2);
                        an asynchronous copy of it avoids the synchronisation of clod_read_info */
 enum {

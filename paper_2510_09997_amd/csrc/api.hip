@@ -350,7 +350,7 @@ clod_status clod_render_bwd(const clod_scene* scene, const clod_batch* batch, co
   hipStream_t s = (hipStream_t)stream;
   const Layout& L = cx.L;
   char* w = (char*)batch->ws;
-  HIP_TRY(launch_fill_u32((uint32_t*)(w + L.gscreen), 0u, (int64_t)kGscreen * L.VN, s), "clear gscreen");
+  HIP_TRY(launch_clear_rendered(L, batch->ws, s), "clear gscreen");
   HIP_TRY(launch_blend_bwd(L, batch->ws, sorted_vals(batch, L, D), batch->params, T, last, dL_drgb, s),
           "blend backward");
   HIP_TRY(launch_gauss_bwd(*scene, L, batch->ws, batch->params, dL_deta, accumulate, *grad, s),

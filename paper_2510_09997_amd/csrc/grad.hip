@@ -328,6 +328,46 @@ __global__ __launch_bounds__(kBlock) void k_dmax_fix(clod_scene sc, const DevVie
   }
 }
 
+// Zeroes the nine screen-space partials of every rendered (view, Gaussian) record, the only
+// ones the blend adjoint accumulates into and the per-Gaussian adjoints read (a few percent of
+// V*n in a multi-view batch, so clearing the whole accumulator would mostly write unused
+// memory).  Sixteen flags per thread, one 16-byte load where all sixteen lie inside V*n.
+__global__ __launch_bounds__(kBlock) void k_clear_rendered(const uint8_t* __restrict__ flags, int64_t VN,
+                                                           float* __restrict__ gscreen) {
+  const int64_t chunks = (VN + 15) / 16;
+  for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < chunks; c += (int64_t)gridDim.x * kBlock) {
+    const int64_t f0 = c * 16;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    if (f0 + 16 <= VN) {
+      const uint4 q = *(const uint4*)(flags + f0);
+      w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+    } else {
+      for (int j = 0; f0 + j < VN; ++j) w[j >> 2] |= (uint32_t)flags[f0 + j] << (8 * (j & 3));
+    }
+    // Bit 2 of each flag byte: rendered.
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) m |= ((w[j >> 2] >> (8 * (j & 3) + 2)) & 1u) << j;
+    while (m) {
+      const int j = __builtin_ctz(m);
+      m &= m - 1;
+      float* g = gscreen + (f0 + j) * kGscreen;
+#pragma unroll
+      for (int q = 0; q < kGscreen; ++q) g[q] = 0.0f;
+    }
+  }
+}
+
+hipError_t launch_clear_rendered(const Layout& L, void* ws, hipStream_t s) {
+  if (L.VN == 0) return hipSuccess;
+  char* w = (char*)ws;
+  int64_t g = ((L.VN + 15) / 16 + kBlock - 1) / kBlock;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_clear_rendered, dim3((unsigned)g), dim3(kBlock), 0, s, (const uint8_t*)(w + L.flags), L.VN,
+                     (float*)(w + L.gscreen));
+  return hipGetLastError();
+}
+
 hipError_t launch_gauss_bwd(const clod_scene& sc, const Layout& L, void* ws, clod_params prm,
                             const float* dL_deta, int accumulate, const clod_scene_grad& g,
                             hipStream_t s) {
