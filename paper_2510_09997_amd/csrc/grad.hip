@@ -257,32 +257,42 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(clod_scene sc, const DevView*
       acc[k] = 0.f;
     }
     float gmx = 0.f, gmy = 0.f, gmz = 0.f;
-    for (int v = 0; v < V; ++v) {
-      const int64_t f = (int64_t)v * n + i;
-      const uint8_t fl = flags[f];
-      if (!(fl & 4)) continue;
-      const DevView& Vw = views[v];
-      const float gc0 = (fl & 8) ? 0.f : gscreen[f * kGscreen + 6];
-      const float gc1 = (fl & 16) ? 0.f : gscreen[f * kGscreen + 7];
-      const float gc2 = (fl & 32) ? 0.f : gscreen[f * kGscreen + 8];
-      float ex, ey, ez;
-      const float id = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(cam_distance2(Vw, mx, my, mz, ex, ey, ez)));
-      const float X = ex * id, Y = ey * id, Z = ez * id;
-      float Yb[16], gY[16];
-      sh_basis(DEG, X, Y, Z, Yb);
+    // Rendering views, 32 at a time: the flag loads of a group are independent (issued
+    // together), and only the set bits are walked; most (view, Gaussian) pairs of a batch
+    // are not rendered.
+    for (int v0 = 0; v0 < V; v0 += 32) {
+      const int vn = V - v0 < 32 ? V - v0 : 32;
+      uint32_t rmask = 0;
+#pragma unroll 8
+      for (int j = 0; j < vn; ++j) rmask |= (uint32_t)((flags[(int64_t)(v0 + j) * n + i] >> 2) & 1u) << j;
+      while (rmask) {
+        const int v = v0 + __builtin_ctz(rmask);
+        rmask &= rmask - 1;
+        const int64_t f = (int64_t)v * n + i;
+        const uint8_t fl = flags[f];
+        const DevView& Vw = views[v];
+        const float gc0 = (fl & 8) ? 0.f : gscreen[f * kGscreen + 6];
+        const float gc1 = (fl & 16) ? 0.f : gscreen[f * kGscreen + 7];
+        const float gc2 = (fl & 32) ? 0.f : gscreen[f * kGscreen + 8];
+        float ex, ey, ez;
+        const float id = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(cam_distance2(Vw, mx, my, mz, ex, ey, ez)));
+        const float X = ex * id, Y = ey * id, Z = ez * id;
+        float Yb[16], gY[16];
+        sh_basis(DEG, X, Y, Z, Yb);
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        acc[3 * k + 0] += gc0 * Yb[k];
-        acc[3 * k + 1] += gc1 * Yb[k];
-        acc[3 * k + 2] += gc2 * Yb[k];
-        gY[k] = gc0 * c[3 * k + 0] + gc1 * c[3 * k + 1] + gc2 * c[3 * k + 2];
+        for (int k = 0; k < K; ++k) {
+          acc[3 * k + 0] += gc0 * Yb[k];
+          acc[3 * k + 1] += gc1 * Yb[k];
+          acc[3 * k + 2] += gc2 * Yb[k];
+          gY[k] = gc0 * c[3 * k + 0] + gc1 * c[3 * k + 1] + gc2 * c[3 * k + 2];
+        }
+        float gX, gYd, gZ;
+        sh_basis_grad(DEG, X, Y, Z, gY, gX, gYd, gZ);
+        const float dot = X * gX + Y * gYd + Z * gZ;
+        gmx += (gX - X * dot) * id;
+        gmy += (gYd - Y * dot) * id;
+        gmz += (gZ - Z * dot) * id;
       }
-      float gX, gYd, gZ;
-      sh_basis_grad(DEG, X, Y, Z, gY, gX, gYd, gZ);
-      const float dot = X * gX + Y * gYd + Z * gZ;
-      gmx += (gX - X * dot) * id;
-      gmy += (gYd - Y * dot) * id;
-      gmz += (gZ - Z * dot) * id;
     }
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) {
