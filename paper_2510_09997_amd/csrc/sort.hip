@@ -191,13 +191,15 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
 __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const uint32_t* __restrict__ keys,
                                                           const unsigned long long* __restrict__ hdr, int cw,
                                                           int G, int shift, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t cnt[4][256];   // per-wave digit counts
+  // Digit counts per 16-lane group of each wave (16 copies, rows padded to 257 words): lanes
+  // of one atomic instruction that share a digit serialise on its address, and high digits
+  // take few values, so splitting the wave four ways shortens those chains.
+  __shared__ uint32_t cnt[16][257];
   if (hdr[kHdrOverflow]) return;
   const int64_t N = (int64_t)hdr[cw];
   const int t = threadIdx.x;
-  const int wave = t >> 6;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) cnt[w][t] = 0;
+  const int copy = t >> 4;
+  for (int j = t; j < 16 * 257; j += kBlock) (&cnt[0][0])[j] = 0;
   __syncthreads();
   int64_t lo, hi;
   sort_chunk(N, G, blockIdx.x, lo, hi);
@@ -211,10 +213,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const uint32_t* __rest
     }
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j)
-      if (d8[j] < 256u) atomicAdd(&cnt[wave][d8[j]], 1u);
+      if (d8[j] < 256u) atomicAdd(&cnt[copy][d8[j]], 1u);
   }
   __syncthreads();
-  hist[(int64_t)t * G + blockIdx.x] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
+  uint32_t total = 0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) total += cnt[c][t];
+  hist[(int64_t)t * G + blockIdx.x] = total;
 }
 
 // Block d: exclusive scan of digit d's per-block counts hist[d*G .. d*G+G) in place, and
