@@ -202,6 +202,41 @@ def test_gradients_match_fp64_oracle(deg):
         assert err <= 1e-4 and l2 <= 1e-4, (k, err, l2)
 
 
+def test_backward_after_other_poses_matches_fresh_batch():
+    """The adjoint clears only the partials of the records rendered now: a batch whose earlier
+    backward rendered other poses (other records) must give the gradients of a fresh batch.
+    n = 3001 with two views, so V*n is not a multiple of the 16 flags a clearing thread takes."""
+    log("case: backward after other poses")
+    sc = synth.make_scene(3001, 2, "uniform", seed=14, log_scale_mean=-3.5)
+    scene = Scene(sc)
+    va = [synth.look_at((0.4, 0.3, -3.2), width=96, height=64, s_v=1.3),
+          synth.look_at((2.5, -1.0, -2.0), width=80, height=80, s_v=2.0)]
+    vb = [synth.look_at((-0.6, 0.2, -3.0), width=96, height=64, s_v=1.0),
+          synth.look_at((0.1, 2.2, -2.4), width=80, height=80, s_v=1.6)]
+    rng = np.random.default_rng(3)
+
+    def step(b):
+        b.project(scene)
+        b.bin_sort()
+        rgb, T, last = b.render_fwd()
+        g = torch.from_numpy(rng.normal(size=3 * b.pixels).astype(np.float32)).cuda()
+        return b.render_bwd(scene, T, last, g, torch.tensor([0.2, -0.1], device="cuda")), g
+
+    reused = Batch(sc["n"], va, params_struct(None))
+    step(reused)
+    reused.update_views(vb)
+    state = rng.bit_generator.state
+    got, _ = step(reused)
+    rng.bit_generator.state = state
+    want, _ = step(Batch(sc["n"], vb, params_struct(None)))
+    torch.cuda.synchronize()
+    # Same records and upstream gradient; only the FP32 atomic order may differ.
+    for k in want:
+        err = O.grad_rel_error(got[k].cpu().numpy(), want[k].cpu().numpy())
+        log(f"  {k}: {err:.2e}")
+        assert err <= 1e-5, (k, err)
+
+
 def test_autograd_function_matches_direct_backward():
     log("case: autograd")
     sc = synth.make_scene(2000, 2, "uniform", seed=12, log_scale_mean=-3.5)
