@@ -4,6 +4,10 @@
   the five LoD frames s_v = 1, 2, 4, 8, 16 of one pose as one batch at 1920x1080: counts, pair
   count, last-contributor indices, transmittance and colour of every pixel of every frame
   bit-identical to the oracle.
+* Training step: 1,000,000 Gaussians at 1297x840 (L1 + point-count regulariser) and the
+  16-view step over 2,000,000 Gaussians (640x480 / 1297x840 / 1920x1080): counts bit-identical;
+  for sampled Gaussians every parameter gradient within 1e-4 of FP64 autograd restricted to
+  the tiles they cover.
 * Continuous-LoD sweep: 6,000,000 Gaussians, 64 distances log-spaced in [2, 200] along one ray
   and the virtual sweep s_v = D_k / 2 at the nearest pose, each sweep's counts from one launch:
   bit-identical to the oracle on eight sampled distances of each sweep (the oracle takes about
@@ -15,6 +19,7 @@ import torch
 from oracle import oracle as O
 from paper_2510_09997_amd import _clod as C, synth
 from paper_2510_09997_amd.render import Batch, Scene
+from paper_2510_09997_amd.train import MultiViewTrainer
 
 from helpers import gpu_forward, params_struct
 
@@ -71,3 +76,66 @@ def test_lod_sweep_6m_counts_sampled_bitexact_and_monotone():
         if name == "virtual":
             assert np.all(np.diff(cnt[:, 1]) <= 0) and np.all(np.diff(cnt[:, 2]) <= 0)
             assert cnt[0, 1] > cnt[-1, 1]
+
+
+def _sampled_gradient_parity(sc, views, pix, counts, dL, deta, got, rng, per_view_min=1, samples=12):
+    """Counts bit-exact per view; for sampled rendered Gaussians (no frustum argmax) the
+    gradients summed over the views against FP64 autograd over the tiles they cover."""
+    vps = [O.render32(sc, v) for v in views]
+    for j, vp in enumerate(vps):
+        assert np.array_equal(counts[j], vp["counts"]), (j, counts[j], vp["counts"])
+    rendered = np.stack([(vp["flags"] & 4) > 0 for vp in vps])
+    argmaxes = {vp["argmax"] for vp in vps}
+    cand = np.array([g for g in np.nonzero(rendered.sum(0) >= per_view_min)[0] if g not in argmaxes])
+    sample = rng.choice(cand, size=min(samples, cand.size), replace=False)
+    want = {k: np.zeros(got[k][..., sample].shape) for k in got}
+    for j, (view, vp) in enumerate(zip(views, vps)):
+        TW = (view.width + 15) // 16
+        tiles = set()
+        for g in sample:
+            if vp["flags"][g] & 4:
+                x0, x1, y0, y1 = vp["rect"][g]
+                tiles.update(int(ty * TW + tx) for ty in range(y0, y1) for tx in range(x0, x1))
+        h, w = view.height, view.width
+        a = int(pix[j])
+        gv = dL[3 * a:3 * a + 3 * h * w].reshape(3, h, w)
+        ref = O.fp64_grads(sc, view, vp, gv, float(deta[j]), tiles=sorted(tiles))
+        for k in want:
+            want[k] += ref[k][..., sample]
+    for k in want:
+        err = O.grad_rel_error(got[k][..., sample], want[k])
+        log(f"  {k}: max-norm rel err {err:.3e}")
+        assert err <= 1e-4, (k, err)
+
+
+def test_training_step_1m_full_size_sampled_gradients():
+    log("case: 1M single-view training step at 1297x840")
+    sc = synth.make_scene(1_000_000, 3, "mixture", seed=0)
+    scene = Scene(sc)
+    view = synth.random_views(0, 1, radius=(4.0, 6.0), resolutions=((1297, 840),), sv_range=(1.0, 8.0))[0]
+    target = torch.from_numpy(synth.random_target(0, 840, 1297).reshape(-1)).cuda()
+    b = Batch(sc["n"], [view], params_struct(None))
+    b.project(scene)
+    b.bin_sort()
+    rgb, T, last = b.render_fwd()
+    _, dL, deta = b.loss(rgb, target, 8.0, 1.0)
+    grads = b.render_bwd(scene, T, last, dL, deta)
+    torch.cuda.synchronize()
+    _sampled_gradient_parity(sc, [view], b.pix_base, b.counts.cpu().numpy(), dL.cpu().numpy(), deta.cpu().numpy(),
+                             {k: v.cpu().numpy() for k, v in grads.items()}, np.random.default_rng(1))
+
+
+def test_sixteen_view_step_2m_full_size_sampled_gradients():
+    log("case: 2M 16-view training step")
+    sc = synth.make_scene(2_000_000, 3, "mixture", seed=0)
+    scene = Scene(sc)
+    res = ((640, 480), (1297, 840), (1920, 1080))
+    views = synth.random_views(7, 16, radius=(4.0, 6.0), resolutions=res, sv_range=(1.0, 8.0))
+    tr = MultiViewTrainer(scene, views, s_max=8.0)
+    tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0)))
+    tr.step()
+    assert not tr.overflowed()
+    torch.cuda.synchronize()
+    _sampled_gradient_parity(sc, views, tr.batch.pix_base, tr.batch.counts.cpu().numpy(), tr.dL.cpu().numpy(), tr.deta.cpu().numpy(),
+                             {k: v.cpu().numpy() for k, v in tr.grads.items()}, np.random.default_rng(2),
+                             per_view_min=2)
