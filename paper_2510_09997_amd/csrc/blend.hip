@@ -10,6 +10,25 @@
 
 namespace clod {
 
+// XCD-aware launch order.  Consecutive workgroups are dispatched round-robin over the eight
+// XCDs, each with its own L2, so tiles next to each other in the launch order (the same list
+// length class, neighbours in the frame, sharing many records) would each fetch the shared
+// records into a different L2.  Block b instead takes position
+// ((b/8/C)*8 + b%8)*C + (b/8)%C of the tile order: runs of C consecutive positions stay on one
+// XCD while the launch as a whole still proceeds in order (longest lists first).  The grid is
+// rounded up to a multiple of 8C; the map is a bijection on it and blocks past the last tile
+// exit at once.
+constexpr uint32_t kXcds = 8, kXcdRun = 16;
+
+__device__ __forceinline__ uint32_t xcd_tile_pos(uint32_t b) {
+  const uint32_t x = b % kXcds, j = b / kXcds, r = j / kXcdRun, i = j % kXcdRun;
+  return (r * kXcds + x) * kXcdRun + i;
+}
+
+static inline uint32_t xcd_grid(uint32_t tiles) {
+  return (tiles + kXcds * kXcdRun - 1) / (kXcds * kXcdRun) * (kXcds * kXcdRun);
+}
+
 __device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_t tile) {
   int lo = 0, hi = V - 1;
   while (lo < hi) {
@@ -116,8 +135,9 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
     const uint32_t* __restrict__ order) {
   __shared__ float4 st[4][3][64];   // per wave: (u, v, hA, nB), (hC, alpha'', r, g), (b, cut, -, -)
   __shared__ unsigned long long sp[4][3];
-  if (blockIdx.x >= tiles_total) return;
-  const int tile_i = (int)order[blockIdx.x];
+  const uint32_t pos = xcd_tile_pos(blockIdx.x);
+  if (pos >= tiles_total) return;
+  const int tile_i = (int)order[pos];
   if (hdr[kHdrOverflow]) return;
   const int v = view_of_tile(views, V, (uint32_t)tile_i);
   const DevView& Vw = views[v];
@@ -270,7 +290,7 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
                             hipStream_t s) {
   if (L.tiles_total == 0) return hipSuccess;
   char* w = (char*)ws;
-  const int nb = (int)L.tiles_total;
+  const int nb = (int)xcd_grid(L.tiles_total);
   unsigned long long* part = pairs ? (unsigned long long*)(w + L.pair_part) : nullptr;
   if (part) {
     hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, s);
@@ -312,8 +332,9 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   __shared__ uint32_t sidx[kBlock];
   __shared__ unsigned long long qmask[4][4];    // [staging wave][quadrant]: entries that may reach it
   __shared__ uint32_t smax[4];
-  if (blockIdx.x >= tiles_total) return;
-  const int tile_i = (int)order[blockIdx.x];
+  const uint32_t pos = xcd_tile_pos(blockIdx.x);
+  if (pos >= tiles_total) return;
+  const int tile_i = (int)order[pos];
   if (hdr[kHdrOverflow]) return;
   const int v = view_of_tile(views, V, (uint32_t)tile_i);
   const DevView& Vw = views[v];
@@ -464,7 +485,7 @@ hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_va
                             hipStream_t s) {
   if (L.tiles_total == 0) return hipSuccess;
   char* w = (char*)ws;
-  const int nb = (int)L.tiles_total;
+  const int nb = (int)xcd_grid(L.tiles_total);
   hipLaunchKernelGGL(k_blend_bwd, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
                      L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
                      sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
