@@ -452,6 +452,7 @@ hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, c
 
 // Fused Adam: one segment per learning-rate group.
 constexpr int kAdamGroups = 7;
+constexpr int kAdamChunk = 8192;   // parameters per block of the Adam launch
 struct AdamSeg {
   float* p;
   const float* g;
@@ -459,9 +460,11 @@ struct AdamSeg {
   float* v;
   int64_t count;
   float lr;
+  int vec;   // all four planes 16-byte aligned: float4 accesses
 };
 struct AdamSegs {
   AdamSeg s[kAdamGroups];
+  int64_t first_block[kAdamGroups + 1];   // blocks of segment j: [first_block[j], first_block[j+1])
 };
 hipError_t launch_adam(const AdamSegs& segs, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t launch_lod_select(const clod_scene& sc, DevView* vinfo, int V, clod_params prm,
