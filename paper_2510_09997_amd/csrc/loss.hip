@@ -26,13 +26,44 @@ __global__ __launch_bounds__(kBlock) void k_loss_l1(const DevView* __restrict__ 
   const float ws = w_s_weight(Vw.s_v, s_max);
   const float scale = l1_weight * ws / (float)cnt;
   float s = 0.f;
+  auto one = [&](float r, float t, float& g) {
+    const float diff = r - t;
+    s += fabsf(diff);
+    g = diff > 0.f ? scale : (diff < 0.f ? -scale : 0.f);
+  };
+  const float* rp = rgb + base;
+  const float* tp = target + base;
+  float* gp = dL_drgb + base;
+  const bool vec = (((uintptr_t)rp | (uintptr_t)tp | (uintptr_t)gp) & 15u) == 0u;   // uniform per view
+  if (vec) {
+    // kLossItems / 4 float4 groups per thread, all loads issued before use.
+    static_assert(kLossItems % 4 == 0, "float4 groups");
+    constexpr int kV = kLossItems / 4;
+    float4 r4[kV], t4[kV];
 #pragma unroll
-  for (int k = 0; k < kLossItems; ++k) {
-    const int64_t j = j0 + (int64_t)k * kBlock + threadIdx.x;
-    if (j < cnt) {
-      const float diff = rgb[base + j] - target[base + j];
-      s += fabsf(diff);
-      dL_drgb[base + j] = diff > 0.f ? scale : (diff < 0.f ? -scale : 0.f);
+    for (int k = 0; k < kV; ++k) {
+      const int64_t j = j0 + 4 * ((int64_t)k * kBlock + threadIdx.x);
+      if (j + 4 <= cnt) { r4[k] = *(const float4*)(rp + j); t4[k] = *(const float4*)(tp + j); }
+    }
+#pragma unroll
+    for (int k = 0; k < kV; ++k) {
+      const int64_t j = j0 + 4 * ((int64_t)k * kBlock + threadIdx.x);
+      if (j + 4 <= cnt) {
+        float4 g4;
+        one(r4[k].x, t4[k].x, g4.x);
+        one(r4[k].y, t4[k].y, g4.y);
+        one(r4[k].z, t4[k].z, g4.z);
+        one(r4[k].w, t4[k].w, g4.w);
+        *(float4*)(gp + j) = g4;
+      } else {
+        for (int64_t q = j; q < cnt && q < j + 4; ++q) one(rp[q], tp[q], gp[q]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kLossItems; ++k) {
+      const int64_t j = j0 + (int64_t)k * kBlock + threadIdx.x;
+      if (j < cnt) one(rp[j], tp[j], gp[j]);
     }
   }
   s = wave_sum(s);
