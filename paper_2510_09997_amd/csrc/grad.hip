@@ -306,35 +306,82 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(clod_scene sc, const DevView*
 }
 
 // Frustum-maximum path: d_max = d_k for the argmax k, so dL/dmu_k += dL/ddmax (mu_k - c) / d_k.
-// One block: sums the per-block partials of each view, then thread 0 applies them.
+// One block.  The per-block partials gpart[b][v] are summed with coalesced reads: thread
+// (p, v) of P phases (P the largest power of two with P*V <= 256) sums rows b = p, p + P, ...,
+// then a fixed tree over the phases; views above 256 are summed one thread each.  The
+// contribution of every view is formed in parallel and each distinct argmax Gaussian gets the
+// sum of its views' contributions in view order (deterministic).
 __global__ __launch_bounds__(kBlock) void k_dmax_fix(clod_scene sc, const DevView* __restrict__ views, int V,
                            const unsigned long long* __restrict__ dmax_key,
                            const float* __restrict__ gpart, int G, float* __restrict__ gdmax,
                            clod_scene_grad g) {
-  __shared__ float sred[4];
-  for (int v = 0; v < V; ++v) {
-    float t = 0.f;
-    for (int b = threadIdx.x; b < G; b += kBlock) t += gpart[(int64_t)b * V + v];
-    t = wave_sum(t);
-    if (lane_id() == 0) sred[threadIdx.x >> 6] = t;
+  __shared__ float red[kBlock];
+  __shared__ uint32_t sk[CLOD_MAX_VIEWS];
+  __shared__ float sx[CLOD_MAX_VIEWS], sy[CLOD_MAX_VIEWS], sz[CLOD_MAX_VIEWS];
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  const int t = threadIdx.x;
+  const int64_t n = sc.n;
+  for (int v0 = 0; v0 < V; v0 += kBlock) {
+    const int vn = V - v0 < kBlock ? V - v0 : kBlock;
+    int P = 1;
+    while (2 * P * vn <= kBlock) P *= 2;
+    const int p = t / vn, v = v0 + t % vn;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    if (p < P) {
+      const float* gp = gpart + v;
+      int b = p;
+      for (; b + 3 * P < G; b += 4 * P) {   // four independent loads in flight
+        a0 += gp[(int64_t)b * V];
+        a1 += gp[(int64_t)(b + P) * V];
+        a2 += gp[(int64_t)(b + 2 * P) * V];
+        a3 += gp[(int64_t)(b + 3 * P) * V];
+      }
+      for (; b < G; b += P) a0 += gp[(int64_t)b * V];
+    }
+    red[t] = p < P ? (a0 + a1) + (a2 + a3) : 0.f;
+    if (vn == 1) {
+      // One view: a wave sum and the four wave totals instead of eight tree levels.
+      const float ws = wave_sum(red[t]);
+      __syncthreads();
+      if (lane_id() == 0) red[t] = ws;
+      __syncthreads();
+      if (t == 0) red[0] = (red[0] + red[64]) + (red[128] + red[192]);
+      __syncthreads();
+    } else {
+      __syncthreads();
+      for (int h = P / 2; h > 0; h /= 2) {
+        if (p < h) red[t] += red[t + h * vn];
+        __syncthreads();
+      }
+    }
+    if (t < vn) gdmax[v0 + t] = red[t];
     __syncthreads();
-    if (threadIdx.x == 0) gdmax[v] = sred[0] + sred[1] + sred[2] + sred[3];
+    if (t < vn) {
+      const int vv = v0 + t;
+      const unsigned long long key = dmax_key[vv];
+      const int64_t kk = key == 0ull ? n : (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
+      sk[vv] = kk < n ? (uint32_t)kk : kNone;
+      if (kk < n) {
+        float ex, ey, ez;
+        const float d = cam_distance(views[vv], sc.mean[kk], sc.mean[n + kk], sc.mean[2 * n + kk], ex, ey, ez);
+        const float gd = red[t] / d;
+        sx[vv] = gd * ex; sy[vv] = gd * ey; sz[vv] = gd * ez;
+      }
+    }
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
-  const int64_t n = sc.n;
-  for (int v = 0; v < V; ++v) {
-    const unsigned long long key = dmax_key[v];
-    if (key == 0ull) continue;
-    const int64_t k = (int64_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFull));
-    if (k >= n) continue;
-    const DevView& Vw = views[v];
-    float ex, ey, ez;
-    const float d = cam_distance(Vw, sc.mean[k], sc.mean[n + k], sc.mean[2 * n + k], ex, ey, ez);
-    const float gd = gdmax[v] / d;
-    g.mean[k] += gd * ex;
-    g.mean[n + k] += gd * ey;
-    g.mean[2 * n + k] += gd * ez;
+  for (int v = t; v < V; v += kBlock) {
+    const uint32_t k = sk[v];
+    if (k == kNone) continue;
+    bool first = true;
+    for (int u = 0; u < v && first; ++u) first = sk[u] != k;
+    if (!first) continue;
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    for (int w = v; w < V; ++w)
+      if (sk[w] == k) { ax += sx[w]; ay += sy[w]; az += sz[w]; }
+    g.mean[k] += ax;
+    g.mean[n + k] += ay;
+    g.mean[2 * n + k] += az;
   }
 }
 
