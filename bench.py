@@ -502,7 +502,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE on the
 # same launches as the default run (profiles/k_blend_fwd_serve1080p_3M_hbm.txt), each scaled by
 # the same counter's reading for a 1 GiB device copy.  Emptied whenever the kernel changes.
-TRAFFIC = {"k_blend_fwd": 1234641545}
+TRAFFIC = {"k_blend_fwd": 1233971775}
 
 
 def main():
