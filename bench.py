@@ -527,7 +527,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2510_09997_amd import _clod as C, synth
