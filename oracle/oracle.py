@@ -440,28 +440,73 @@ def fp64_view_forward(sc: dict, view, vp: dict, params: dict | None = None,
 
 
 def fp64_grads(scene: dict, view, vp: dict, dL_drgb: np.ndarray, dL_deta: float,
-               params: dict | None = None, tiles: list[int] | None = None) -> dict:
+               params: dict | None = None, tiles: list[int] | None = None, abs_terms: bool = False) -> dict:
     """Gradients of  sum(dL_drgb * rgb) + dL_deta * eta  with respect to every parameter
     plane, by autograd of the FP64 forward.  Returns float64 numpy arrays in the scene's
-    layout, plus the FP64 rgb and T."""
+    layout, plus the FP64 rgb and T.  With ``abs_terms`` also ``out["abs"][plane]``: the
+    absolute adjoint of each element (the sum over chain-rule paths of the products of absolute
+    partials, with |dL_drgb| and |dL_deta|; see abs_adjoint.py), the scale of its terms."""
     sc = scene_to_torch64(scene)
     rgb, T, eta, _ = fp64_view_forward(sc, view, vp, params, tiles)
     g = torch.from_numpy(np.asarray(dL_drgb, dtype=np.float64))
     L = (rgb * g).sum() + dL_deta * eta
     L.backward()
     out = {k: (sc[k].grad.detach().numpy().copy() if sc[k].grad is not None else np.zeros(sc[k].shape))
-           for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")}
+           for k in PLANES}
     out["rgb"] = rgb.detach().numpy()
     out["T"] = T.detach().numpy()
+    if abs_terms:
+        out["abs"] = fp64_abs_adjoint(scene, view, vp, dL_drgb, dL_deta, params, tiles)
     return out
+
+
+PLANES = ("mean", "log_scale", "quat", "opacity", "decay", "sh")
+
+
+def fp64_abs_adjoint(scene: dict, view, vp: dict, dL_drgb: np.ndarray, dL_deta: float,
+                     params: dict | None = None, tiles: list[int] | None = None) -> dict:
+    """Per element of every parameter plane, the sum of the magnitudes of the chain-rule terms
+    of its gradient (the same forward as fp64_grads, differentiated with absolute partials)."""
+    from .abs_adjoint import AbsAdjointMode
+    sc = scene_to_torch64(scene)
+    g = torch.from_numpy(np.abs(np.asarray(dL_drgb, dtype=np.float64)))
+    with AbsAdjointMode():
+        rgb, _, eta, _ = fp64_view_forward(sc, view, vp, params, tiles)
+        L = (rgb * g).sum() + abs(float(dL_deta)) * eta
+    L.backward()
+    return {k: (sc[k].grad.detach().numpy().copy() if sc[k].grad is not None else np.zeros(sc[k].shape))
+            for k in PLANES}
+
+
+# Smallest normal binary32 number: differences below it are below the format's normal range.
+FLT_MIN = float(np.finfo(np.float32).tiny)
+
+
+def grad_elem_terms(g: np.ndarray, r: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """Per element, (|g_i - r_i| - FLT_MIN)+ / S_i: the error measured against the magnitude of
+    the element's terms (S_i, the absolute adjoint: S_i >= |r_i|, equal where the terms do not
+    cancel, so this is the plain relative error there), less the binary32 underflow threshold
+    (a binary32 evaluation cannot resolve differences below the smallest normal number).  An
+    element with S_i = 0 has no terms: its error must stay below FLT_MIN (else inf)."""
+    g = np.asarray(g, dtype=np.float64).ravel()
+    r = np.asarray(r, dtype=np.float64).ravel()
+    S = np.asarray(S, dtype=np.float64).ravel()
+    d = np.maximum(np.abs(g - r) - FLT_MIN, 0.0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        e = np.where(S > 0.0, d / np.where(S > 0.0, S, 1.0), np.where(d > 0.0, np.inf, 0.0))
+    return e
+
+
+def grad_elem_error(g: np.ndarray, r: np.ndarray, S: np.ndarray) -> float:
+    """max over elements of grad_elem_terms (0 for an empty plane)."""
+    e = grad_elem_terms(g, r, S)
+    return float(e.max()) if e.size else 0.0
 
 
 def grad_rel_error(g: np.ndarray, r: np.ndarray) -> float:
     """Relative error of a gradient tensor in the max norm: max_i |g_i - r_i| / max_j |r_j|.
-
-    An element-wise relative error is not meaningful for gradients that are sums of many
-    binary32 terms of both signs: the rounding bound of such a sum scales with sum |terms|,
-    not with the (possibly much smaller) result."""
+    Reported beside grad_elem_error; used alone only to compare two GPU runs of the same
+    arithmetic (graph replay against the eager step)."""
     g = np.asarray(g, dtype=np.float64).ravel()
     r = np.asarray(r, dtype=np.float64).ravel()
     if r.size == 0:
@@ -470,6 +515,19 @@ def grad_rel_error(g: np.ndarray, r: np.ndarray) -> float:
     if scale == 0.0:
         return float(np.abs(g).max())
     return float(np.abs(g - r).max() / scale)
+
+
+def grad_floor_error(g: np.ndarray, r: np.ndarray, floor: float = 1e-3) -> float:
+    """Element-wise relative error with a floor: max_i |g_i - r_i| / max(|r_i|, floor max_j |r_j|)
+    (reported, not a gate: it ignores how strongly an element's terms cancel)."""
+    g = np.asarray(g, dtype=np.float64).ravel()
+    r = np.asarray(r, dtype=np.float64).ravel()
+    if r.size == 0:
+        return 0.0
+    den = np.maximum(np.abs(r), floor * np.abs(r).max())
+    if den.max() == 0.0:
+        return float(np.abs(g).max())
+    return float((np.abs(g - r) / np.where(den > 0, den, 1.0)).max())
 
 
 def grad_l2_error(g: np.ndarray, r: np.ndarray) -> float:

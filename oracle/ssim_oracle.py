@@ -73,11 +73,22 @@ def dssim_torch64(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     return 1.0 - s.mean()
 
 
-def render_loss64(x: np.ndarray, y: np.ndarray, lambda_dssim: float = LAMBDA_DSSIM):
-    """L_render and its gradient with respect to x ([C][H][W]), float64."""
-    xt = torch.tensor(np.asarray(x, np.float64), requires_grad=True)
-    yt = torch.tensor(np.asarray(y, np.float64))
-    l1 = (xt - yt).abs().mean()
-    loss = (1.0 - lambda_dssim) * l1 + lambda_dssim * dssim_torch64(xt, yt)
-    loss.backward()
-    return float(loss.detach()), xt.grad.numpy()
+def render_loss64(x: np.ndarray, y: np.ndarray, lambda_dssim: float = LAMBDA_DSSIM, abs_terms: bool = False):
+    """L_render and its gradient with respect to x ([C][H][W]), float64.  With ``abs_terms``
+    also the absolute adjoint of the gradient (per pixel, the sum of the magnitudes of its
+    chain-rule terms; see abs_adjoint.py) as a third result."""
+    def run(mode):
+        xt = torch.tensor(np.asarray(x, np.float64), requires_grad=True)
+        yt = torch.tensor(np.asarray(y, np.float64))
+        with mode:
+            l1 = (xt - yt).abs().mean()
+            loss = (1.0 - lambda_dssim) * l1 + lambda_dssim * dssim_torch64(xt, yt)
+        loss.backward()
+        return float(loss.detach()), xt.grad.numpy()
+
+    import contextlib
+    loss, g = run(contextlib.nullcontext())
+    if not abs_terms:
+        return loss, g
+    from .abs_adjoint import AbsAdjointMode
+    return loss, g, run(AbsAdjointMode())[1]
