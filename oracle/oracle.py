@@ -342,6 +342,9 @@ def fp64_view_forward(sc: dict, view, vp: dict, params: dict | None = None,
     q = (dn * view.s_v) ** 2 / (2.0 * r * r + p["eps"])
     alpha = torch.sigmoid(sc["opacity"])
     alpha2 = alpha * torch.exp(-q)                       # Eq. (2)
+    # Where the binary32 alpha'' is exactly 0 (the contract exponential returns 0 below -86, or
+    # the product underflows), the replay takes that value too: no gradient flows through it.
+    alpha2 = torch.where(torch.from_numpy(vp["rec"][:, 6] == 0), torch.zeros_like(alpha2), alpha2)
     mask_m = torch.from_numpy((vp["flags"] & 2) != 0)
     n_m = int(mask_m.sum())
     mass = alpha2.sum()
