@@ -83,6 +83,19 @@ def scene_adam_step32(scene: dict, grads: dict, m: dict, v: dict, lrs: dict, t: 
 
 def position_lr(step: int, lr_init: float = 1.6e-4, lr_final: float = 1.6e-6, max_steps: int = 30000,
                 extent: float = 1.0) -> float:
-    """Log-linear decay of the position learning rate over training (3DGS schedule)."""
+    """Position learning rate of the 3DGS recipe: a geometric interpolation from lr_init to
+    lr_final over max_steps (constant outside), i.e. lr_init (lr_final / lr_init)^t with
+    t = step / max_steps clamped to [0, 1]; both ends scaled by the scene extent."""
     t = min(max(step / max_steps, 0.0), 1.0)
-    return float(np.exp(np.log(lr_init * extent) * (1 - t) + np.log(lr_final * extent) * t))
+    return (lr_init * extent) * ((lr_final * extent) / (lr_init * extent)) ** t
+
+
+def schedule_lrs(step: int, base: dict, enable_at: int, total: int) -> dict:
+    """Learning rates of training iteration `step` (Sec. 4.1): the 3DGS per-group rates, the
+    position rate decaying to 1/100 of its start over `total` iterations, and sigma_d frozen
+    (rate 0) until the LoD mechanism is switched on at iteration `enable_at`."""
+    out = dict(base)
+    out["mean"] = position_lr(step, lr_init=base["mean"], lr_final=base["mean"] / 100.0, max_steps=total)
+    if step < enable_at:
+        out["decay"] = 0.0
+    return out

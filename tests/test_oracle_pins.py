@@ -609,6 +609,44 @@ def test_ssim_identical_images_is_one_and_constant_images_closed_form():
     assert abs(SO.window1d().sum() - 1.0) < 1e-15 and np.allclose(SO.window1d(), SO.window1d()[::-1])
 
 
+def test_ssim_linear_ramp_closed_form_pins_c1_c2_and_window():
+    """x = a + g1 i + g2 j and y = c + s x.  More than 5 px from the zero padding the
+    window-weighted moments are exact: mean_x = x (the window is symmetric), var_x =
+    (g1^2 + g2^2) m2, var_y = s^2 var_x, cov_xy = s var_x, with m2 = sum_k w_k k^2 the second
+    moment of the normalised 11-tap Gaussian window of standard deviation 1.5 (the 3DGS rendering
+    loss), so SSIM = (2 mx my + C1)(2 s var_x + C2) / ((mx^2 + my^2 + C1)((1 + s^2) var_x + C2))
+    with C1 = 0.01^2 and C2 = 0.03^2.  Unlike constant images, the variances are not zero here,
+    so C2 and the window width both enter (checked: other values move SSIM far outside the
+    tolerance)."""
+    from oracle import ssim_oracle as SO
+
+    def closed_form(x, y, s, grad2, sigma, c1, c2):
+        k = np.arange(-5, 6, dtype=np.float64)
+        w = np.exp(-k * k / (2.0 * sigma * sigma))
+        m2 = float((w * k * k).sum() / w.sum())
+        var = grad2 * m2
+        return (2 * x * y + c1) * (2 * s * var + c2) / ((x * x + y * y + c1) * ((1 + s * s) * var + c2))
+
+    H, W = 40, 48
+    i, j = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64), indexing="ij")
+    g1, g2, a, c, s = 0.004, 0.011, 0.1, 0.95, -0.5
+    x = a + g1 * i + g2 * j
+    y = c + s * x
+    got = SO.ssim_map64(x[None], y[None])[0][5:-5, 5:-5]
+    inner = np.s_[5:-5, 5:-5]
+    want = closed_form(x[inner], y[inner], s, g1 * g1 + g2 * g2, 1.5, 0.01 ** 2, 0.03 ** 2)
+    assert np.allclose(got, want, rtol=1e-10, atol=0)
+    # The same images under other constants: each differs from the oracle by far more than
+    # the tolerance, so a wrong C1, C2 or window width fails the check above.
+    for sigma, c1, c2 in ((1.0, 0.01 ** 2, 0.03 ** 2), (2.0, 0.01 ** 2, 0.03 ** 2),
+                          (1.5, 0.01 ** 2, 0.02 ** 2), (1.5, 0.01 ** 2, 0.05 ** 2), (1.5, 0.02 ** 2, 0.03 ** 2)):
+        other = closed_form(x[inner], y[inner], s, g1 * g1 + g2 * g2, sigma, c1, c2)
+        assert np.abs(other - got).max() > 1e-4, (sigma, c1, c2)
+    # The differentiable implementation gives the same mean over the whole image.
+    d = float(SO.dssim_torch64(torch.from_numpy(x[None]), torch.from_numpy(y[None])))
+    assert abs((1.0 - d) - SO.ssim_map64(x[None], y[None]).mean()) < 1e-12
+
+
 def test_render_loss_gradient_matches_central_differences():
     from oracle import ssim_oracle as SO
     rng = np.random.default_rng(62)
