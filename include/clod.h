@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 10
+#define CLOD_ABI_VERSION 11
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -128,10 +128,12 @@ int64_t clod_dup_capacity(size_t dup_bytes);
    frustum uses 1), normalised distance d'_i, attenuated opacity of Eq. (2), LoD mask
    M_i = alpha''_i > tau s_v, and for M_i and in-frustum Gaussians the EWA projection, cull,
    16x16-tile rectangle and SH colour.  counts_dev (nullable, device int64 [n_views][3])
-   receives {n_frustum, n_mask, n_rendered}; eta_actual of Sec. 3.3 is n_mask / n.
-   The results stay in batch->ws for the calls below. */
+   receives {n_frustum, n_mask, n_rendered}; eta_dev (nullable, device float [n_views]) receives
+   the kept ratio eta_actual = n_mask / n of Sec. 3.3, Eq. (4) (binary32 quotient of the two
+   counts rounded to binary32; 0 when n = 0).  The results stay in batch->ws for the calls
+   below. */
 clod_status clod_project(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
-                         void *stream);
+                         float *eta_dev, void *stream);
 
 /* Sec. 3.1 (splats sorted by depth per tile): the (rendered Gaussian, covered tile) pairs in
    the stable order of the keys (tile_base[view] + tile) << 32 | bits(depth) emitted per
@@ -202,7 +204,10 @@ typedef struct clod_adam {
                              SH degree 0 (sh[0 .. 3n)), SH degree >= 1 (sh[3n ..)); >= 0 */
   float beta1, beta2;     /* in [0, 1) */
   float eps;              /* > 0 */
-  float bias1, bias2;     /* 1 - beta1^t and 1 - beta2^t of step t >= 1, in (0, 1] */
+  int32_t reserved;
+  int64_t step;           /* t >= 1: the library forms the bias corrections bias1 = 1 - beta1^t and
+                             bias2 = 1 - beta2^t in double precision from the binary32 betas and
+                             rounds each once to binary32 */
 } clod_adam;
 
 /* Sec. 4.1 (training follows the 3DGS recipe, with sigma_d as one more per-Gaussian parameter

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
-ABI_VERSION = 10
+ABI_VERSION = 11
 
 
 class ClodError(RuntimeError):
@@ -54,7 +54,7 @@ class clod_view(ctypes.Structure):
 
 class clod_adam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float * 7), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
-                ("eps", ctypes.c_float), ("bias1", ctypes.c_float), ("bias2", ctypes.c_float)]
+                ("eps", ctypes.c_float), ("reserved", ctypes.c_int32), ("step", ctypes.c_int64)]
 
 
 class clod_params(ctypes.Structure):
@@ -93,7 +93,7 @@ def load(path: str = LIB_PATH):
     L.clod_ws_bytes.argtypes = [i64, i32, P]; L.clod_ws_bytes.restype = sz
     L.clod_dup_bytes.argtypes = [i64]; L.clod_dup_bytes.restype = sz
     L.clod_dup_capacity.argtypes = [sz]; L.clod_dup_capacity.restype = i64
-    L.clod_project.argtypes = [P, P, P, P]; L.clod_project.restype = i32
+    L.clod_project.argtypes = [P, P, P, P, P]; L.clod_project.restype = i32
     L.clod_bin_sort.argtypes = [P, P, P]; L.clod_bin_sort.restype = i32
     L.clod_render_fwd.argtypes = [P, P, P, P, P, P]; L.clod_render_fwd.restype = i32
     L.clod_render_bwd.argtypes = [P, P, P, P, P, P, i32, P, P]; L.clod_render_bwd.restype = i32
@@ -119,12 +119,22 @@ def _check(status: int):
         raise ClodError(status, msg)
 
 
-def _ptr(t) -> int | None:
+F32, I32, I64 = torch.float32, (torch.int32, torch.uint32), torch.int64
+
+
+def _ptr(t, dtype=None) -> int | None:
+    """Device address of a contiguous tensor (or a raw address); with `dtype` (a dtype or a
+    tuple of accepted dtypes) the tensor's element type is checked against the C type the
+    entry point reads or writes."""
     if t is None:
         return None
     if isinstance(t, torch.Tensor):
         if not t.is_contiguous():
             raise ValueError("tensor must be contiguous")
+        if dtype is not None:
+            ok = dtype if isinstance(dtype, tuple) else (dtype,)
+            if t.dtype not in ok:
+                raise TypeError(f"tensor of dtype {t.dtype} where the C ABI expects {ok[0]}")
         return t.data_ptr()
     return int(t)
 
@@ -143,15 +153,15 @@ def make_scene(planes: dict) -> clod_scene:
     s.n = int(planes["n"])
     s.sh_degree = int(planes["sh_degree"])
     for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh"):
-        setattr(s, k, _ptr(planes[k]))
-    s.sh_packed = _ptr(planes.get("sh_packed"))
+        setattr(s, k, _ptr(planes[k], F32))
+    s.sh_packed = _ptr(planes.get("sh_packed"), F32)
     return s
 
 
 def make_grad(planes: dict) -> clod_scene_grad:
     g = clod_scene_grad()
     for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh"):
-        setattr(g, k, _ptr(planes[k]))
+        setattr(g, k, _ptr(planes[k], F32))
     return g
 
 
@@ -204,8 +214,9 @@ def clod_dup_capacity(nbytes: int) -> int:
     return int(load().clod_dup_capacity(nbytes))
 
 
-def clod_project(scene: clod_scene, batch: clod_batch, counts=None, stream=None):
-    _check(load().clod_project(ctypes.byref(scene), ctypes.byref(batch), _ptr(counts), _stream(stream)))
+def clod_project(scene: clod_scene, batch: clod_batch, counts=None, stream=None, eta=None):
+    _check(load().clod_project(ctypes.byref(scene), ctypes.byref(batch), _ptr(counts, I64), _ptr(eta, F32),
+                               _stream(stream)))
 
 
 def clod_bin_sort(batch: clod_batch, sync_count: bool = False, stream=None) -> int | None:
@@ -215,35 +226,31 @@ def clod_bin_sort(batch: clod_batch, sync_count: bool = False, stream=None) -> i
 
 
 def clod_render_fwd(batch: clod_batch, rgb, T, last, pairs=None, stream=None):
-    _check(load().clod_render_fwd(ctypes.byref(batch), _ptr(rgb), _ptr(T), _ptr(last), _ptr(pairs),
+    _check(load().clod_render_fwd(ctypes.byref(batch), _ptr(rgb, F32), _ptr(T, F32), _ptr(last, I32), _ptr(pairs, I64),
                                   _stream(stream)))
 
 
 def clod_render_bwd(scene: clod_scene, batch: clod_batch, T, last, dL_drgb, dL_deta, accumulate: bool,
                     grad: clod_scene_grad, stream=None):
-    _check(load().clod_render_bwd(ctypes.byref(scene), ctypes.byref(batch), _ptr(T), _ptr(last),
-                                  _ptr(dL_drgb), _ptr(dL_deta), int(bool(accumulate)), ctypes.byref(grad),
+    _check(load().clod_render_bwd(ctypes.byref(scene), ctypes.byref(batch), _ptr(T, F32), _ptr(last, I32),
+                                  _ptr(dL_drgb, F32), _ptr(dL_deta, F32), int(bool(accumulate)), ctypes.byref(grad),
                                   _stream(stream)))
 
 
 def clod_lod_count(scene: clod_scene, batch: clod_batch, counts, stream=None):
-    _check(load().clod_lod_count(ctypes.byref(scene), ctypes.byref(batch), _ptr(counts), _stream(stream)))
+    _check(load().clod_lod_count(ctypes.byref(scene), ctypes.byref(batch), _ptr(counts, I64), _stream(stream)))
 
 
 ADAM_GROUPS = ("mean", "log_scale", "quat", "opacity", "decay", "sh_dc", "sh_rest")
 
 
 def make_adam(lrs: dict, t: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15) -> clod_adam:
-    """Hyperparameters of step t >= 1: binary32 roundings of beta1, beta2, eps and the group
-    learning rates; the bias corrections 1 - beta^t evaluated in float64 from the binary32
-    betas and rounded once."""
+    """Hyperparameters of step t >= 1 (the library forms the bias corrections)."""
     hp = clod_adam()
     for j, k in enumerate(ADAM_GROUPS):
         hp.lr[j] = float(lrs[k])
-    b1, b2 = float(np.float32(beta1)), float(np.float32(beta2))
-    hp.beta1, hp.beta2, hp.eps = b1, b2, float(eps)
-    hp.bias1 = float(np.float32(1.0 - b1 ** t))
-    hp.bias2 = float(np.float32(1.0 - b2 ** t))
+    hp.beta1, hp.beta2, hp.eps = float(beta1), float(beta2), float(eps)
+    hp.step = int(t)
     return hp
 
 
@@ -256,9 +263,9 @@ def clod_adam_step(n: int, sh_degree: int, param: clod_scene_grad, grad: clod_sc
 def clod_loss(batch: clod_batch, rgb, target, s_max: float, lambda_reg: float, loss, dL_drgb, dL_deta,
               stream=None, lambda_dssim: float = 0.0, ssim_scratch=None):
     nbytes = 0 if ssim_scratch is None else ssim_scratch.numel() * ssim_scratch.element_size()
-    _check(load().clod_loss(ctypes.byref(batch), _ptr(rgb), _ptr(target), float(s_max), float(lambda_reg),
-                            float(lambda_dssim), _ptr(ssim_scratch), nbytes, _ptr(loss), _ptr(dL_drgb),
-                            _ptr(dL_deta), _stream(stream)))
+    _check(load().clod_loss(ctypes.byref(batch), _ptr(rgb, F32), _ptr(target, F32), float(s_max), float(lambda_reg),
+                            float(lambda_dssim), _ptr(ssim_scratch, F32), nbytes, _ptr(loss, F32), _ptr(dL_drgb, F32),
+                            _ptr(dL_deta, F32), _stream(stream)))
 
 
 def clod_read_info(batch: clod_batch, stream=None) -> dict:

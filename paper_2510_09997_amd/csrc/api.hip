@@ -257,7 +257,7 @@ int64_t clod_dup_capacity(size_t dup_bytes) {
 }
 
 clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64_t* counts_dev,
-                         void* stream) {
+                         float* eta_dev, void* stream) {
   g_err[0] = 0;
   clod_status st = check_scene(scene);
   if (st != CLOD_OK) return st;
@@ -279,7 +279,7 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
                               (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
             "budget select");
   HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
-                         (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), counts_dev,
+                         (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), counts_dev, eta_dev,
                          (uint8_t*)(w + L.flags), (float*)(w + L.alpha), (float4*)(w + L.rec),
                          (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), s),
           "project");
@@ -380,7 +380,7 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
                               (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
             "budget select");
   HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
-                           (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), counts_dev,
+                           (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), counts_dev, nullptr,
                            (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), s),
           "lod count");
   return CLOD_OK;
@@ -423,8 +423,11 @@ clod_status clod_adam_step(int64_t n, int32_t sh_degree, const clod_scene_grad* 
   if (!(hp->beta1 >= 0.f && hp->beta1 < 1.f && hp->beta2 >= 0.f && hp->beta2 < 1.f))
     return fail(CLOD_E_ARG, "betas must be in [0, 1)");
   if (!(finite_f(hp->eps) && hp->eps > 0.f)) return fail(CLOD_E_ARG, "eps must be finite and > 0");
-  if (!(hp->bias1 > 0.f && hp->bias1 <= 1.f && hp->bias2 > 0.f && hp->bias2 <= 1.f))
-    return fail(CLOD_E_ARG, "bias corrections must be in (0, 1]");
+  if (hp->step < 1) return fail(CLOD_E_ARG, "hp->step must be >= 1");
+  // Bias corrections 1 - beta^t of Adam, in double from the binary32 betas, rounded once.
+  const float bias1 = (float)(1.0 - pow((double)hp->beta1, (double)hp->step));
+  const float bias2 = (float)(1.0 - pow((double)hp->beta2, (double)hp->step));
+  if (!(bias1 > 0.f && bias2 > 0.f)) return fail(CLOD_E_ARG, "bias corrections must be > 0");
   if (n == 0) return CLOD_OK;
   const clod_scene_grad* planes[4] = {param, grad, m, v};
   for (const clod_scene_grad* q : planes)
@@ -447,7 +450,7 @@ clod_status clod_adam_step(int64_t n, int32_t sh_degree, const clod_scene_grad* 
   seg(4, &clod_scene_grad::decay, 0, n);
   seg(5, &clod_scene_grad::sh, 0, 3 * n);
   seg(6, &clod_scene_grad::sh, 3 * n, 3 * (K - 1) * n);
-  HIP_TRY(launch_adam(S, hp->beta1, hp->beta2, hp->eps, hp->bias1, hp->bias2, (hipStream_t)stream), "adam");
+  HIP_TRY(launch_adam(S, hp->beta1, hp->beta2, hp->eps, bias1, bias2, (hipStream_t)stream), "adam");
   return CLOD_OK;
 }
 

@@ -444,11 +444,11 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
 // {frustum, mask, rendered} counts.
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                          int64_t* counts_dev, uint8_t* flags, float* alpha, float4* rec, uint32_t* list,
+                          int64_t* counts_dev, float* eta_dev, uint8_t* flags, float* alpha, float4* rec, uint32_t* list,
                           uint32_t* lcount, hipStream_t s);
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                            int64_t* counts_dev, uint32_t* list, uint32_t* lcount, hipStream_t s);
+                            int64_t* counts_dev, float* eta_dev, uint32_t* list, uint32_t* lcount, hipStream_t s);
 
 // Fused Adam: one segment per learning-rate group.
 constexpr int kAdamGroups = 7;

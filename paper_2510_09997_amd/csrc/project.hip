@@ -59,11 +59,13 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t cou
 
 // Folds the G per-block partials of view v (every thread of the block takes part).  With kpart: the maximum squared distance, stored as the key
 // bits(sqrt(max)) << 32 (0 if the frustum is empty).  With cpart: the counts (sum; also to
-// counts_dev when non-NULL) and the lowest index at d_max (min), which completes the low half
-// of that key.
+// counts_dev when non-NULL), the kept ratio eta = n_mask / n of Eq. (4) (to eta_dev when
+// non-NULL; binary32 quotient of the counts converted to binary32) and the lowest index at d_max
+// (min), which completes the low half of that key.
 __device__ void fold_view(int v, const unsigned long long* __restrict__ kpart, const uint32_t* __restrict__ cpart,
-                          int G, int V, unsigned long long* __restrict__ dmax_key,
-                          unsigned long long* __restrict__ counts, int64_t* __restrict__ counts_dev) {
+                          int G, int V, int64_t n, unsigned long long* __restrict__ dmax_key,
+                          unsigned long long* __restrict__ counts, int64_t* __restrict__ counts_dev,
+                          float* __restrict__ eta_dev) {
   __shared__ unsigned long long sm[4][4];
   __shared__ uint32_t smin[4];
   unsigned long long key = 0ull, c0 = 0, c1 = 0, c2 = 0;
@@ -109,6 +111,7 @@ __device__ void fold_view(int v, const unsigned long long* __restrict__ kpart, c
       if (counts_dev) {
         counts_dev[3 * v] = (int64_t)c0; counts_dev[3 * v + 1] = (int64_t)c1; counts_dev[3 * v + 2] = (int64_t)c2;
       }
+      if (eta_dev) eta_dev[v] = n > 0 ? (float)c1 / (float)n : 0.0f;
       const unsigned long long dk = dmax_key[v];
       if (dk) dmax_key[v] = (dk & 0xFFFFFFFF00000000ull) | (unsigned long long)(0xFFFFFFFFu - imin);
     }
@@ -121,8 +124,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const unsigned long 
                                                             const uint32_t* __restrict__ cpart, int G, int V,
                                                             unsigned long long* __restrict__ dmax_key,
                                                             unsigned long long* __restrict__ counts,
-                                                            int64_t* __restrict__ counts_dev) {
-  fold_view(blockIdx.x, kpart, cpart, G, V, dmax_key, counts, counts_dev);
+                                                            int64_t* __restrict__ counts_dev, int64_t n,
+                                                            float* __restrict__ eta_dev) {
+  fold_view(blockIdx.x, kpart, cpart, G, V, n, dmax_key, counts, counts_dev, eta_dev);
 }
 
 // Per-block partials instead of global atomics: block b owns the contiguous chunk
@@ -593,18 +597,20 @@ hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V,
   const int G = proj_blocks(sc.n);
   hipLaunchKernelGGL(k_frustum_max, dim3(G), dim3(kBlock), 0, s, sc.mean, sc.n, vinfo, V, near_z, kpart);
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)kpart,
-                     (const uint32_t*)nullptr, G, V, dmax_key, (unsigned long long*)nullptr, (int64_t*)nullptr);
+                     (const uint32_t*)nullptr, G, V, dmax_key, (unsigned long long*)nullptr, (int64_t*)nullptr,
+                     sc.n, (float*)nullptr);
   return hipGetLastError();
 }
 
 template <bool kWrite>
 static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                                unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                               int64_t* counts_dev, uint8_t* flags, float* alpha, float4* rec, uint32_t* list,
-                               uint32_t* lcount, hipStream_t s) {
+                               int64_t* counts_dev, float* eta_dev, uint8_t* flags, float* alpha, float4* rec,
+                               uint32_t* list, uint32_t* lcount, hipStream_t s) {
   if (sc.n == 0) {
     hipError_t e = launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
     if (e == hipSuccess && counts_dev) e = launch_fill_u32((uint32_t*)counts_dev, 0u, 6 * (int64_t)V, s);
+    if (e == hipSuccess && eta_dev) e = launch_fill_u32((uint32_t*)eta_dev, 0u, (int64_t)V, s);
     return e;
   }
   const int G = proj_blocks(sc.n);
@@ -624,23 +630,24 @@ static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V
                      rec);
   // Counts to the workspace and the caller, and the argmax index into the d_max key.
   hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
-                     (const uint32_t*)cpart, G, V, dmax_key, counts, counts_dev);
+                     (const uint32_t*)cpart, G, V, dmax_key, counts, counts_dev, sc.n, eta_dev);
   return hipGetLastError();
 }
 
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                          int64_t* counts_dev, uint8_t* flags, float* alpha, float4* rec, uint32_t* list,
-                          uint32_t* lcount, hipStream_t s) {
-  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, counts_dev, flags, alpha, rec, list, lcount,
-                            s);
+                          int64_t* counts_dev, float* eta_dev, uint8_t* flags, float* alpha, float4* rec,
+                          uint32_t* list, uint32_t* lcount, hipStream_t s) {
+  return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, counts_dev, eta_dev, flags, alpha, rec, list,
+                            lcount, s);
 }
 
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                            int64_t* counts_dev, uint32_t* list, uint32_t* lcount, hipStream_t s) {
-  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, counts_dev, nullptr, nullptr, nullptr,
-                             list, lcount, s);
+                            int64_t* counts_dev, float* eta_dev, uint32_t* list, uint32_t* lcount,
+                            hipStream_t s) {
+  return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, counts_dev, eta_dev, nullptr, nullptr,
+                             nullptr, list, lcount, s);
 }
 
 }  // namespace clod

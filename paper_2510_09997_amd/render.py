@@ -78,6 +78,7 @@ class Batch:
         self._alloc_dup(dup_capacity)
         self.n_views = V
         self.counts = torch.zeros(V, 3, dtype=torch.int64, device=device)
+        self.eta = torch.zeros(V, dtype=torch.float32, device=device)   # eta_actual per view (Eq. 4)
 
     def _alloc_dup(self, capacity: int):
         nbytes = C.clod_dup_bytes(int(capacity))
@@ -117,7 +118,7 @@ class Batch:
 
     # ---- stages --------------------------------------------------------------------------
     def project(self, scene: Scene):
-        C.clod_project(scene.c_struct(), self.c_struct(), self.counts)
+        C.clod_project(scene.c_struct(), self.c_struct(), self.counts, eta=self.eta)
 
     def bin_sort(self, sync: bool = True, grow: float = 1.5) -> int | None:
         """Bins and sorts; with sync=True reads the pair count and grows the duplicate
@@ -209,10 +210,10 @@ class ClodRender(torch.autograd.Function):
                       opacity=opacity.contiguous(), decay=decay.contiguous(), sh=sh.contiguous(),
                       n=mean.shape[1], sh_degree=sh_degree)
         scene = C.make_scene(planes)
-        C.clod_project(scene, batch.c_struct(), batch.counts)
+        C.clod_project(scene, batch.c_struct(), batch.counts, eta=batch.eta)
         batch.bin_sort()
         rgb, T, last = batch.render_fwd()
-        eta = batch.counts[:, 1].to(torch.float32) / float(max(batch.n, 1))
+        eta = batch.eta.clone()
         ctx.batch = batch
         ctx.sh_degree = sh_degree
         ctx.save_for_backward(planes["mean"], planes["log_scale"], planes["quat"], planes["opacity"],
