@@ -19,35 +19,6 @@ namespace clod {
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 
-// dY_k/d(X, Y, Z) of the basis polynomials in sh_basis (independent coordinates).
-__device__ __forceinline__ void sh_basis_grad(int deg, float X, float Y, float Z, const float* gY,
-                                              float& gX, float& gYo, float& gZ) {
-  gX = 0.f; gYo = 0.f; gZ = 0.f;
-  if (deg < 1) return;
-  gYo += SHK::k1 * gY[1];
-  gZ += SHK::k1 * gY[2];
-  gX += SHK::k1 * gY[3];
-  if (deg < 2) return;
-  gX += SHK::k2a * Y * gY[4]; gYo += SHK::k2a * X * gY[4];
-  gYo += SHK::k2a * Z * gY[5]; gZ += SHK::k2a * Y * gY[5];
-  gX += -2.f * SHK::k2b * X * gY[6]; gYo += -2.f * SHK::k2b * Y * gY[6]; gZ += 4.f * SHK::k2b * Z * gY[6];
-  gX += SHK::k2a * Z * gY[7]; gZ += SHK::k2a * X * gY[7];
-  gX += 2.f * SHK::k2c * X * gY[8]; gYo += -2.f * SHK::k2c * Y * gY[8];
-  if (deg < 3) return;
-  const float xx = X * X, yy = Y * Y, zz = Z * Z;
-  gX += 6.f * SHK::k3a * X * Y * gY[9]; gYo += SHK::k3a * (3.f * xx - 3.f * yy) * gY[9];
-  gX += SHK::k3b * Y * Z * gY[10]; gYo += SHK::k3b * X * Z * gY[10]; gZ += SHK::k3b * X * Y * gY[10];
-  gX += -2.f * SHK::k3c * X * Y * gY[11]; gYo += SHK::k3c * (4.f * zz - xx - 3.f * yy) * gY[11];
-  gZ += 8.f * SHK::k3c * Y * Z * gY[11];
-  gX += -6.f * SHK::k3d * X * Z * gY[12]; gYo += -6.f * SHK::k3d * Y * Z * gY[12];
-  gZ += SHK::k3d * (6.f * zz - 3.f * xx - 3.f * yy) * gY[12];
-  gX += SHK::k3c * (4.f * zz - 3.f * xx - yy) * gY[13]; gYo += -2.f * SHK::k3c * X * Y * gY[13];
-  gZ += 8.f * SHK::k3c * X * Z * gY[13];
-  gX += 2.f * SHK::k3e * X * Z * gY[14]; gYo += -2.f * SHK::k3e * Y * Z * gY[14];
-  gZ += SHK::k3e * (xx - yy) * gY[14];
-  gX += SHK::k3a * (3.f * xx - 3.f * yy) * gY[15]; gYo += -6.f * SHK::k3a * X * Y * gY[15];
-}
-
 __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
     clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
     const unsigned long long* __restrict__ dmax_key, const uint8_t* __restrict__ flags,
@@ -236,11 +207,64 @@ __global__ __launch_bounds__(kBlock) void k_gauss_bwd(
   for (int v = threadIdx.x; v < V; v += kBlock) gpart[(int64_t)blockIdx.x * V + v] = gsum[v];
 }
 
+// The SH colour's adjoint for one rendering view, in double precision: the basis values Y_k of
+// the exact unit direction (dL/dc_k = dL/dcolour * Y_k) and the direction gradient
+// sum_k gY_k dY_k/d(X, Y, Z).  Several basis polynomials cancel near their zero sets (for
+// example X (X^2 - 3 Y^2)), where a binary32 evaluation loses relative accuracy in proportion to
+// 1 / |polynomial|; evaluated in double from the double direction and then rounded once, each
+// basis value and partial is within an ulp of the exact one.  The sums over k and channels stay
+// in binary32 (their rounding is relative to the magnitude of their terms).  The forward
+// colour keeps the binary32 contract; the adjoint is that of the exact basis.  Cartesian
+// forms and closed-form normalisations as in the forward (sh_basis).
+template <int DEG>
+__device__ __forceinline__ void sh_adjoint_d(double X, double Y, double Z, float gc0, float gc1, float gc2,
+                                             const float* c, float* acc, float& gX, float& gY, float& gZ) {
+  constexpr double k0 = 0.28209479177387814, k1 = 0.4886025119029199, k2a = 1.0925484305920792,
+                   k2b = 0.31539156525252005, k2c = 0.5462742152960396, k3a = 0.5900435899266435,
+                   k3b = 2.890611442640554, k3c = 0.4570457994644658, k3d = 0.3731763325901154,
+                   k3e = 1.445305721320277;
+  gX = 0.f; gY = 0.f; gZ = 0.f;
+  // One basis function: its value feeds the coefficient gradients, its partials the direction.
+  auto term = [&](int k, double y, double dx, double dy, double dz) {
+    const float yf = (float)y;
+    acc[3 * k + 0] += gc0 * yf;
+    acc[3 * k + 1] += gc1 * yf;
+    acc[3 * k + 2] += gc2 * yf;
+    const float gk = gc0 * c[3 * k + 0] + gc1 * c[3 * k + 1] + gc2 * c[3 * k + 2];
+    gX += gk * (float)dx;
+    gY += gk * (float)dy;
+    gZ += gk * (float)dz;
+  };
+  term(0, k0, 0.0, 0.0, 0.0);
+  if (DEG < 1) return;
+  term(1, k1 * Y, 0.0, k1, 0.0);
+  term(2, k1 * Z, 0.0, 0.0, k1);
+  term(3, k1 * X, k1, 0.0, 0.0);
+  if (DEG < 2) return;
+  const double xx = X * X, yy = Y * Y, zz = Z * Z;
+  term(4, k2a * X * Y, k2a * Y, k2a * X, 0.0);
+  term(5, k2a * Y * Z, 0.0, k2a * Z, k2a * Y);
+  term(6, k2b * (2.0 * zz - xx - yy), -2.0 * k2b * X, -2.0 * k2b * Y, 4.0 * k2b * Z);
+  term(7, k2a * X * Z, k2a * Z, 0.0, k2a * X);
+  term(8, k2c * (xx - yy), 2.0 * k2c * X, -2.0 * k2c * Y, 0.0);
+  if (DEG < 3) return;
+  const double t4 = 4.0 * zz - xx - yy;
+  term(9, k3a * Y * (3.0 * xx - yy), 6.0 * k3a * X * Y, k3a * (3.0 * xx - 3.0 * yy), 0.0);
+  term(10, k3b * X * Y * Z, k3b * Y * Z, k3b * X * Z, k3b * X * Y);
+  term(11, k3c * Y * t4, -2.0 * k3c * X * Y, k3c * (4.0 * zz - xx - 3.0 * yy), 8.0 * k3c * Y * Z);
+  term(12, k3d * Z * (2.0 * zz - 3.0 * xx - 3.0 * yy), -6.0 * k3d * X * Z, -6.0 * k3d * Y * Z,
+       k3d * (6.0 * zz - 3.0 * xx - 3.0 * yy));
+  term(13, k3c * X * t4, k3c * (4.0 * zz - 3.0 * xx - yy), -2.0 * k3c * X * Y, 8.0 * k3c * X * Z);
+  term(14, k3e * Z * (xx - yy), 2.0 * k3e * X * Z, -2.0 * k3e * Y * Z, k3e * (xx - yy));
+  term(15, k3a * X * (xx - 3.0 * yy), k3a * (3.0 * xx - 3.0 * yy), -6.0 * k3a * X * Y, 0.0);
+}
+
+
 // SH colour adjoint per Gaussian: the coefficients are loaded once and their gradients
 // accumulated in registers over the rendering views (dL/dc_k = sum over views of the colour
 // gradient times the basis value; clamped channels pass no gradient); the view-direction term
 // dL/dmu = (dL/dd_hat - d_hat (d_hat . dL/dd_hat)) / |mu - c| is added to the mean's gradient
-// written by k_gauss_bwd.  Same reciprocal/square-root tolerance argument as there.
+// written by k_gauss_bwd.  Direction, basis and its partials in double (sh_adjoint_d).
 template <int DEG>
 __global__ __launch_bounds__(kBlock) void k_sh_bwd(clod_scene sc, const DevView* __restrict__ views, int V,
                                                    const uint8_t* __restrict__ flags,
@@ -274,24 +298,18 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(clod_scene sc, const DevView*
         const float gc0 = (fl & 8) ? 0.f : gscreen[f * kGscreen + 6];
         const float gc1 = (fl & 16) ? 0.f : gscreen[f * kGscreen + 7];
         const float gc2 = (fl & 32) ? 0.f : gscreen[f * kGscreen + 8];
-        float ex, ey, ez;
-        const float id = __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(cam_distance2(Vw, mx, my, mz, ex, ey, ez)));
-        const float X = ex * id, Y = ey * id, Z = ez * id;
-        float Yb[16], gY[16];
-        sh_basis(DEG, X, Y, Z, Yb);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          acc[3 * k + 0] += gc0 * Yb[k];
-          acc[3 * k + 1] += gc1 * Yb[k];
-          acc[3 * k + 2] += gc2 * Yb[k];
-          gY[k] = gc0 * c[3 * k + 0] + gc1 * c[3 * k + 1] + gc2 * c[3 * k + 2];
-        }
+        // Exact offset and unit direction (binary32 inputs, double arithmetic).
+        const double ex = (double)mx - (double)Vw.c[0], ey = (double)my - (double)Vw.c[1],
+                     ez = (double)mz - (double)Vw.c[2];
+        const double id = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
+        const double X = ex * id, Y = ey * id, Z = ez * id;
         float gX, gYd, gZ;
-        sh_basis_grad(DEG, X, Y, Z, gY, gX, gYd, gZ);
-        const float dot = X * gX + Y * gYd + Z * gZ;
-        gmx += (gX - X * dot) * id;
-        gmy += (gYd - Y * dot) * id;
-        gmz += (gZ - Z * dot) * id;
+        sh_adjoint_d<DEG>(X, Y, Z, gc0, gc1, gc2, c, acc, gX, gYd, gZ);
+        const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z, idf = (float)id;
+        const float dot = Xf * gX + Yf * gYd + Zf * gZ;
+        gmx += (gX - Xf * dot) * idf;
+        gmy += (gYd - Yf * dot) * idf;
+        gmz += (gZ - Zf * dot) * idf;
       }
     }
 #pragma unroll
