@@ -86,7 +86,7 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     # pass that times each stage in isolation.
     NS = max(1, args.streams)
     slots = [b] + [Batch(n, steps[0], dup_capacity=cap) for _ in range(NS - 1)]
-    outs = [(torch.empty(3 * b.pixels, device="cuda"), torch.empty(b.pixels, device="cuda"),
+    outs = [(torch.empty(3 * b.pixels, device="cuda", dtype=torch.float32), torch.empty(b.pixels, device="cuda", dtype=torch.float32),
              torch.empty(b.pixels, dtype=torch.int32, device="cuda")) for _ in range(NS)]
     streams = [torch.cuda.Stream() for _ in range(NS)]
     rgb, T, last = outs[0]
@@ -181,7 +181,7 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     single = [Batch(n, [steps[0][i]], dup_capacity=cap) for i in range(len(SV_SWEEP))]
     singles_host = [[C.make_views([v]) for v in vs] for vs in steps]
     singles_dev = [[C.views_to_device(h, "cuda") for h in hs] for hs in singles_host]
-    outs = [(torch.empty(3 * sb.pixels, device="cuda"), torch.empty(sb.pixels, device="cuda"),
+    outs = [(torch.empty(3 * sb.pixels, device="cuda", dtype=torch.float32), torch.empty(sb.pixels, device="cuda", dtype=torch.float32),
              torch.empty(sb.pixels, dtype=torch.int32, device="cuda")) for sb in single]
 
     def plain(j):
@@ -225,12 +225,12 @@ def run_train(args, torch, C, Batch, Scene, synth):
         dmax = max(dmax, b.bin_sort())
     b._alloc_dup(int(dmax * 1.1) + 4096)
     grads = scene.zeros_like()
-    rgb = torch.empty(3 * b.pixels, device="cuda")
-    T = torch.empty(b.pixels, device="cuda")
+    rgb = torch.empty(3 * b.pixels, device="cuda", dtype=torch.float32)
+    T = torch.empty(b.pixels, device="cuda", dtype=torch.float32)
     last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
-    loss = torch.empty(1, device="cuda")
+    loss = torch.empty(1, device="cuda", dtype=torch.float32)
     dL = torch.empty_like(rgb)
-    deta = torch.empty(1, device="cuda")
+    deta = torch.empty(1, device="cuda", dtype=torch.float32)
     gs = C.make_grad(grads)
 
     def it(j, ev=None):
@@ -288,7 +288,7 @@ def run_multiview_train(args, torch, C, Scene, synth):
     tr = MultiViewTrainer(scene, first, s_max=8.0, dup_capacity=1)
     dmax = tr.size_capacity(sets)
     tables = [C.views_to_device(C.make_views(vs), "cuda") for vs in sets]
-    tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0)))
+    tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0), dtype=torch.float32))
     tr.capture()
     for j in range(W):
         tr.set_views_dev(tables[j])
@@ -347,8 +347,8 @@ def run_budget_sweep(args, torch, C, Batch, scene, pose):
     out = {"budgets": [], "kept": [], "rendered": [], "fps": []}
     budgets = [25_000, 50_000, 100_000, 200_000, 400_000, 800_000, 1_600_000, n]
     b = Batch(n, [dataclasses.replace(pose, budget=budgets[0])])
-    rgb = torch.empty(3 * b.pixels, device="cuda")
-    T = torch.empty(b.pixels, device="cuda")
+    rgb = torch.empty(3 * b.pixels, device="cuda", dtype=torch.float32)
+    T = torch.empty(b.pixels, device="cuda", dtype=torch.float32)
     last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
     for k in budgets:
         b.update_views([dataclasses.replace(pose, budget=k)])
@@ -381,8 +381,8 @@ def run_strips(args, torch, C, Batch, scene, pose, synth):
         b = Batch(scene.n, views)
         b.project(scene)
         b.bin_sort()
-        rgb = torch.empty(3 * b.pixels, device="cuda")
-        T = torch.empty(b.pixels, device="cuda")
+        rgb = torch.empty(3 * b.pixels, device="cuda", dtype=torch.float32)
+        T = torch.empty(b.pixels, device="cuda", dtype=torch.float32)
         last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
         bs = b.c_struct()
         reps = 10
@@ -433,8 +433,8 @@ def run_lod_sweep(args, torch, C, Batch, Scene, synth):
     # Frames per distance (one view per pass), capacity sized per pose.
     fps = []
     b = Batch(n, [ray[0]])
-    rgb = torch.empty(3 * b.pixels, device="cuda")
-    T = torch.empty(b.pixels, device="cuda")
+    rgb = torch.empty(3 * b.pixels, device="cuda", dtype=torch.float32)
+    T = torch.empty(b.pixels, device="cuda", dtype=torch.float32)
     last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
     for k, v in enumerate(ray):
         b.update_views([v])

@@ -187,8 +187,8 @@ class GpuExecutor:
         with torch.cuda.stream(st):
             ws, dup = self._buffers(slot, C.clod_ws_bytes(self.scene.n, vh), int(self.dup_per_pixel * pixels) + 65536)
             vd = C.views_to_device(vh, "cuda")
-            rgb = torch.empty(3 * pixels, device="cuda")
-            T = torch.empty(pixels, device="cuda")
+            rgb = torch.empty(3 * pixels, device="cuda", dtype=torch.float32)
+            T = torch.empty(pixels, device="cuda", dtype=torch.float32)
             last = torch.empty(pixels, dtype=torch.int32, device="cuda")
             bs = self._batch_struct(vh, vd, ws, dup)
             C.clod_project(self.scene.c_struct(), bs, None, st)
@@ -234,13 +234,17 @@ class GpuExecutor:
             return None
         done = self.t0_event.elapsed_time(h["ev"]) / 1e3
         if self.keep:
+            # Copies on the stream that owns the outputs (ordered before any reuse of their
+            # memory by the slot's next batch), finished before the handle is dropped.
             rgb, T, last = h["out"]
             off = 0
-            for r in h["batch"]:
-                px = r.view.width * r.view.height
-                self.outputs[r.rid] = (rgb[3 * off:3 * (off + px)].clone(), T[off:off + px].clone(),
-                                       last[off:off + px].clone())
-                off += px
+            with self.torch.cuda.stream(h["stream"]):
+                for r in h["batch"]:
+                    px = r.view.width * r.view.height
+                    self.outputs[r.rid] = (rgb[3 * off:3 * (off + px)].clone(), T[off:off + px].clone(),
+                                           last[off:off + px].clone())
+                    off += px
+            h["stream"].synchronize()
         return done
 
     def finish(self):

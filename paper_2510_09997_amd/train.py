@@ -29,17 +29,17 @@ class MultiViewTrainer:
         self.batch = Batch(scene.n, views, params, dup_capacity=dup_capacity or 1)
         b = self.batch
         dev = "cuda"
-        self.rgb = torch.empty(3 * b.pixels, device=dev)
-        self.T = torch.empty(b.pixels, device=dev)
+        self.rgb = torch.empty(3 * b.pixels, device=dev, dtype=torch.float32)
+        self.T = torch.empty(b.pixels, device=dev, dtype=torch.float32)
         self.last = torch.empty(b.pixels, dtype=torch.int32, device=dev)
-        self.target = torch.zeros(3 * b.pixels, device=dev)
-        self.loss = torch.empty(len(views), device=dev)
+        self.target = torch.zeros(3 * b.pixels, device=dev, dtype=torch.float32)
+        self.loss = torch.empty(len(views), device=dev, dtype=torch.float32)
         self.dL = torch.empty_like(self.rgb)
-        self.deta = torch.empty(len(views), device=dev)
+        self.deta = torch.empty(len(views), device=dev, dtype=torch.float32)
         self.grads = {k: torch.zeros_like(v) for k, v in scene.t.items()}
         self.hdr = torch.empty(16, dtype=torch.uint8, pin_memory=True)
         # Per-pixel SSIM derivatives (36 B per pixel), only when the D-SSIM term is on.
-        self.ssim_scratch = torch.empty(9 * b.pixels, device=dev) if self.lambda_dssim > 0 else None
+        self.ssim_scratch = torch.empty(9 * b.pixels, device=dev, dtype=torch.float32) if self.lambda_dssim > 0 else None
         self.graph = None
         if dup_capacity is None:
             self.size_capacity()
@@ -82,7 +82,7 @@ class MultiViewTrainer:
         C.clod_bin_sort(bs, sync_count=False)
         C.clod_render_fwd(bs, self.rgb, self.T, self.last, None)
         if self.lambda_dssim > 0 and self.ssim_scratch is None:
-            self.ssim_scratch = torch.empty(9 * b.pixels, device=self.rgb.device)
+            self.ssim_scratch = torch.empty(9 * b.pixels, device=self.rgb.device, dtype=torch.float32)
         C.clod_loss(bs, self.rgb, self.target, self.s_max, self.lambda_reg, self.loss, self.dL, self.deta,
                     lambda_dssim=self.lambda_dssim, ssim_scratch=self.ssim_scratch)
         C.clod_render_bwd(s, bs, self.T, self.last, self.dL, self.deta, False, C.make_grad(self.grads))

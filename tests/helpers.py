@@ -16,9 +16,12 @@ def params_struct(p: dict | None):
                          dilation=p["dilation"], bg=p["bg"])
 
 
-def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None, packed_sh: bool = False):
-    """Runs clod_project, clod_bin_sort and clod_render_fwd; returns host copies."""
-    scene = Scene(sc, packed_sh=packed_sh)
+def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None, packed_sh: bool = False,
+                scene: Scene | None = None):
+    """Runs clod_project, clod_bin_sort and clod_render_fwd; returns host copies.  `scene`
+    reuses a device-resident scene built from `sc`."""
+    if scene is None:
+        scene = Scene(sc, packed_sh=packed_sh)
     b = Batch(sc["n"], views, params_struct(params), dup_capacity=dup_capacity)
     b.project(scene)
     D = b.bin_sort()
@@ -118,6 +121,9 @@ def compare_forward(g: dict, sc: dict, views, params: dict | None = None, fp64: 
 
 
 def _grad_case(sc, views, seed=0, dL_deta=None):
+    """GPU gradients of sum(g * rgb) + sum_v dL_deta[v] eta_v for a random g, and the FP64
+    oracle's gradients and absolute adjoints (per element, the magnitude of its terms) summed
+    over the views.  Returns (got, want, S, vps)."""
     scene = Scene(sc)
     b = Batch(sc["n"], views, params_struct(None))
     b.project(scene)
@@ -129,16 +135,50 @@ def _grad_case(sc, views, seed=0, dL_deta=None):
     grads = b.render_bwd(scene, T, last, torch.from_numpy(g_rgb).cuda(), eta_g)
     torch.cuda.synchronize()
     got = {k: v.cpu().numpy() for k, v in grads.items()}
-    want = None
+    want = {k: np.zeros(v.shape) for k, v in got.items()}
+    S = {k: np.zeros(v.shape) for k, v in got.items()}
+    vps = []
     for v, view in enumerate(views):
         r = O.render32(sc, view)
+        vps.append(r)
         a = int(b.pix_base[v])
         h, w = view.height, view.width
         gv = g_rgb[3 * a:3 * a + 3 * h * w].reshape(3, h, w)
-        ref = O.fp64_grads(sc, view, r, gv, 0.0 if dL_deta is None else float(dL_deta[v]))
-        if want is None:
-            want = {k: ref[k].copy() for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")}
-        else:
-            for k in want:
-                want[k] += ref[k]
-    return got, want
+        ref = O.fp64_grads(sc, view, r, gv, 0.0 if dL_deta is None else float(dL_deta[v]), abs_terms=True)
+        for k in want:
+            want[k] += ref[k]
+            S[k] += ref["abs"][k]
+    return got, want, S, vps
+
+
+def check_grads(got: dict, want: dict, S: dict, tol: float = 1e-4, log=print, argmaxes=()):
+    """Element-wise gradient parity: |g_i - r_i| <= tol * S_i for every element of every plane
+    (S_i = the magnitude of element i's chain-rule terms, = |r_i| where they do not cancel).
+    Logs the bound's worst ratio, the floor-relative error max|g-r| / max(|r|, 1e-3 max|r|) and
+    the L2 error for reference, and the element that is worst under the floor metric."""
+    worst = {}
+    for k in want:
+        g = np.asarray(got[k], np.float64)
+        r = np.asarray(want[k], np.float64)
+        s = np.asarray(S[k], np.float64)
+        e = O.grad_elem_error(g, r, s)
+        fl = O.grad_floor_error(g, r)
+        l2 = O.grad_l2_error(g, r)
+        d = np.abs(g - r).ravel()
+        den = np.maximum(np.abs(r).ravel(), 1e-3 * np.abs(r).max()) if r.size else d
+        i = int(np.argmax(d / np.where(den > 0, den, 1.0))) if r.size else 0
+        where = np.unravel_index(i, r.shape) if r.size else ()
+        gauss = int(where[-1]) if r.size else -1
+        note = " (frustum argmax)" if gauss in argmaxes else ""
+        log(f"  {k}: elem/S {e:.3e}  floor-rel {fl:.3e}  l2 {l2:.3e}  worst-floor at {tuple(int(x) for x in where)}"
+            f"{note}: got {g.ravel()[i]:.6e} want {r.ravel()[i]:.6e} S {s.ravel()[i]:.3e}" if r.size else f"  {k}: empty")
+        if r.size:
+            j = int(np.argmax(O.grad_elem_terms(g, r, s)))
+            wj = np.unravel_index(j, r.shape)
+            log(f"      worst elem/S at {tuple(int(x) for x in wj)}"
+                f"{' (frustum argmax)' if int(wj[-1]) in argmaxes else ''}: got {g.ravel()[j]:.6e} "
+                f"want {r.ravel()[j]:.6e} S {s.ravel()[j]:.3e}")
+        worst[k] = e
+    bad = {k: e for k, e in worst.items() if not e <= tol}
+    assert not bad, bad
+    return worst

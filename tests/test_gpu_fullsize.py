@@ -21,7 +21,7 @@ from paper_2510_09997_amd import _clod as C, synth
 from paper_2510_09997_amd.render import Batch, Scene
 from paper_2510_09997_amd.train import MultiViewTrainer
 
-from helpers import gpu_forward, params_struct
+from helpers import check_grads, gpu_forward, params_struct
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +57,58 @@ def test_headline_batch_full_size_bitexact():
     assert np.all(np.diff(g["counts"][:, 1]) <= 0)
 
 
+def _images_bitexact(g, v, r):
+    assert np.array_equal(g["counts"][v], r["counts"]), (v, g["counts"][v], r["counts"])
+    assert np.array_equal(g["last"][v], r["last"]), v
+    assert np.array_equal(g["T"][v].view(np.uint32), r["T"].view(np.uint32)), v
+    assert np.array_equal(g["rgb"][v].view(np.uint32), r["rgb"].view(np.uint32)), v
+
+
+def test_4k_request_alone_and_in_mixed_serving_batch_bitexact():
+    """The serving stream's 3840x2160 requests (32,400 tiles per view) over the resident 3M scene:
+    a 4K view rendered alone and inside a batch with a 1280x720 and a 1920x1080 request, every
+    pixel of every view bit-identical to the oracle, and the 4K frame of the mix byte for byte
+    the frame rendered alone."""
+    log("case: 3M, 4K alone and in a 720p / 4K / 1080p batch")
+    sc = synth.make_scene(3_000_000, 3, "mixture", seed=0)
+    scene = Scene(sc, packed_sh=True)
+    v4k = synth.look_at((2.0, 1.5, -7.0), width=3840, height=2160, s_v=1.7)
+    v720 = synth.look_at((-9.0, 4.0, 12.0), width=1280, height=720, s_v=5.0)
+    v1080 = synth.look_at((15.0, -2.0, -20.0), width=1920, height=1080, s_v=1.0)
+    alone = gpu_forward(sc, [v4k], scene=scene)
+    r4k = O.render32(sc, v4k)
+    log(f"  4K alone: counts {alone['counts'][0].tolist()}, pairs {alone['D']}")
+    _images_bitexact(alone, 0, r4k)
+    assert alone["D"] == r4k["entries"].size
+    del alone["batch"]
+    mixed = gpu_forward(sc, [v720, v4k, v1080], scene=scene)
+    log(f"  mix: counts {mixed['counts'].tolist()}, pairs {mixed['D']}")
+    _images_bitexact(mixed, 1, r4k)
+    for v, view in ((0, v720), (2, v1080)):
+        _images_bitexact(mixed, v, O.render32(sc, view))
+    for key in ("last", "T", "rgb"):
+        assert np.array_equal(mixed[key][1].view(np.uint32), alone[key][0].view(np.uint32)), key
+
+
+def test_lod_sweep_6m_frames_bitexact_at_four_distances():
+    """Frames of the continuous-LoD sweep (6M Gaussians, 1920x1080, camera at D_k = 2 100^(k/63)
+    on the -z axis) at k = 0, 21, 42, 63: the far frames hold the longest tile lists of any
+    workload.  Counts, pair count, last index, T and colour of every pixel bit-identical."""
+    log("case: 6M LoD sweep frames")
+    sc = synth.make_scene(6_000_000, 3, "mixture", seed=0)
+    scene = Scene(sc, packed_sh=True)
+    ds = synth.sweep_distances(64, 2.0, 200.0)
+    for k in (0, 21, 42, 63):
+        view = synth.look_at((0.0, 0.0, -float(ds[k])), width=1920, height=1080)
+        g = gpu_forward(sc, [view], scene=scene)
+        r = O.render32(sc, view)
+        lists = np.diff(r["tile_off"])
+        log(f"  k={k} d={ds[k]:.2f}: counts {g['counts'][0].tolist()}, pairs {g['D']}, longest list {lists.max()}")
+        _images_bitexact(g, 0, r)
+        assert g["D"] == r["entries"].size
+        del g
+
+
 def test_lod_sweep_6m_counts_sampled_bitexact_and_monotone():
     log("case: 6M LoD sweep, 64 distances")
     sc = synth.make_scene(6_000_000, 3, "mixture", seed=0)
@@ -89,6 +141,7 @@ def _sampled_gradient_parity(sc, views, pix, counts, dL, deta, got, rng, per_vie
     cand = np.array([g for g in np.nonzero(rendered.sum(0) >= per_view_min)[0] if g not in argmaxes])
     sample = rng.choice(cand, size=min(samples, cand.size), replace=False)
     want = {k: np.zeros(got[k][..., sample].shape) for k in got}
+    S = {k: np.zeros(got[k][..., sample].shape) for k in got}
     for j, (view, vp) in enumerate(zip(views, vps)):
         TW = (view.width + 15) // 16
         tiles = set()
@@ -99,13 +152,11 @@ def _sampled_gradient_parity(sc, views, pix, counts, dL, deta, got, rng, per_vie
         h, w = view.height, view.width
         a = int(pix[j])
         gv = dL[3 * a:3 * a + 3 * h * w].reshape(3, h, w)
-        ref = O.fp64_grads(sc, view, vp, gv, float(deta[j]), tiles=sorted(tiles))
+        ref = O.fp64_grads(sc, view, vp, gv, float(deta[j]), tiles=sorted(tiles), abs_terms=True)
         for k in want:
             want[k] += ref[k][..., sample]
-    for k in want:
-        err = O.grad_rel_error(got[k][..., sample], want[k])
-        log(f"  {k}: max-norm rel err {err:.3e}")
-        assert err <= 1e-4, (k, err)
+            S[k] += ref["abs"][k][..., sample]
+    check_grads({k: got[k][..., sample] for k in got}, want, S, 1e-4, log=log)
 
 
 def test_training_step_1m_full_size_sampled_gradients():
@@ -132,7 +183,7 @@ def test_sixteen_view_step_2m_full_size_sampled_gradients():
     res = ((640, 480), (1297, 840), (1920, 1080))
     views = synth.random_views(7, 16, radius=(4.0, 6.0), resolutions=res, sv_range=(1.0, 8.0))
     tr = MultiViewTrainer(scene, views, s_max=8.0)
-    tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0)))
+    tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0), dtype=torch.float32))
     tr.step()
     assert not tr.overflowed()
     torch.cuda.synchronize()

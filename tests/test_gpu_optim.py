@@ -66,7 +66,7 @@ def test_scheduled_training_run_updates_match_oracle():
     views = synth.random_views(53, 4, radius=(5.0, 7.0), resolutions=((160, 120), (128, 96)), sv_range=(1.0, 1.0))
     sched = LodSchedule(s_max=6.0, enable_at=2, total=10, seed=54)
     tr = MultiViewTrainer(scene, views, s_max=6.0, lambda_reg=0.0)
-    tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0)))
+    tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0), dtype=torch.float32))
     opt = FusedAdam(scene)
     ref_m = {k: np.zeros_like(v) for k, v in host(scene.t).items()}
     ref_v = {k: np.zeros_like(v) for k, v in ref_m.items()}
@@ -83,9 +83,11 @@ def test_scheduled_training_run_updates_match_oracle():
         lrs = sched.lrs_at(it)
         opt.step(tr.grads, lrs)
         torch.cuda.synchronize()
+        # The oracle side takes its own schedule (Sec. 4.1 readings), not the product's.
+        ref_lrs = TO.schedule_lrs(it, sched.lrs, enable_at=2, total=10)
         ref_p = dict(p_before, n=n, sh_degree=3)
         TO.scene_adam_step32(ref_p, dict(g, n=n, sh_degree=3), dict(ref_m, n=n, sh_degree=3),
-                             dict(ref_v, n=n, sh_degree=3), lrs, it + 1)
+                             dict(ref_v, n=n, sh_degree=3), ref_lrs, it + 1)
         got = host(scene.t)
         for k in ref_m:
             assert same_bits(got[k], ref_p[k]), (it, k)

@@ -2,9 +2,10 @@
 
 Integer results (counts, frustum argmax, flags, tile rectangles, keys, sort order, ranges,
 last-contributor indices) and the binary32 contract values (records, T, colour) must be
-bit-identical; colour is also checked within 1e-5 of the FP64 replay, gradients within 1e-4
-relative of FP64 autograd per parameter plane (max-norm: max|g - r| / max|r|; also
-L2-relative <= 1e-4)."""
+bit-identical; colour is also checked within 1e-5 of the FP64 replay, and every gradient
+element within 1e-4 relative of FP64 autograd, relative to the magnitude of its chain-rule terms
+(|g_i - r_i| <= 1e-4 S_i, S_i the oracle's absolute adjoint; S_i = |r_i| where the terms do not
+cancel)."""
 import math
 
 import numpy as np
@@ -15,7 +16,7 @@ from oracle import oracle as O
 from paper_2510_09997_amd import _clod as C, synth
 from paper_2510_09997_amd.render import Batch, ClodRender, Scene
 
-from helpers import _grad_case, compare_forward, gpu_forward, params_struct
+from helpers import _grad_case, check_grads, compare_forward, gpu_forward, params_struct
 
 pytestmark = pytest.mark.gpu
 
@@ -194,12 +195,8 @@ def test_gradients_match_fp64_oracle(deg):
     sc = synth.make_scene(3000, deg, "uniform", seed=8 + deg, log_scale_mean=-3.5)
     views = [synth.look_at((0.4, 0.3, -3.2), width=96, height=64, s_v=1.3),
              synth.look_at((2.5, -1.0, -2.0), width=80, height=80, s_v=2.0)]
-    got, want = _grad_case(sc, views, seed=1, dL_deta=[0.3, -0.2])
-    for k in want:
-        err = O.grad_rel_error(got[k], want[k])
-        l2 = O.grad_l2_error(got[k], want[k])
-        log(f"  {k}: max-norm rel err {err:.3e}  l2 rel err {l2:.3e}")
-        assert err <= 1e-4 and l2 <= 1e-4, (k, err, l2)
+    got, want, S, vps = _grad_case(sc, views, seed=1, dL_deta=[0.3, -0.2])
+    check_grads(got, want, S, 1e-4, log=log, argmaxes={vp["argmax"] for vp in vps})
 
 
 def test_backward_after_other_poses_matches_fresh_batch():
@@ -228,13 +225,20 @@ def test_backward_after_other_poses_matches_fresh_batch():
     state = rng.bit_generator.state
     got, _ = step(reused)
     rng.bit_generator.state = state
-    want, _ = step(Batch(sc["n"], vb, params_struct(None)))
+    fresh = Batch(sc["n"], vb, params_struct(None))
+    want, g = step(fresh)
     torch.cuda.synchronize()
-    # Same records and upstream gradient; only the FP32 atomic order may differ.
-    for k in want:
-        err = O.grad_rel_error(got[k].cpu().numpy(), want[k].cpu().numpy())
-        log(f"  {k}: {err:.2e}")
-        assert err <= 1e-5, (k, err)
+    # Same records and upstream gradient; only the FP32 atomic order may differ: element-wise
+    # within 1e-5 of the magnitude of each element's terms (the oracle's absolute adjoint).
+    gh = g.cpu().numpy()
+    S = {k: 0.0 for k in want}
+    for v, view in enumerate(vb):
+        a = int(fresh.pix_base[v])
+        gv = gh[3 * a:3 * a + 3 * view.height * view.width].reshape(3, view.height, view.width)
+        ab = O.fp64_abs_adjoint(sc, view, O.render32(sc, view), gv, [0.2, -0.1][v])
+        S = {k: S[k] + ab[k] for k in S}
+    check_grads({k: v.cpu().numpy() for k, v in got.items()}, {k: v.cpu().numpy() for k, v in want.items()}, S,
+                1e-5, log=log)
 
 
 def test_autograd_function_matches_direct_backward():
@@ -246,14 +250,16 @@ def test_autograd_function_matches_direct_backward():
     b = Batch(sc["n"], views, params_struct(None))
     rgb, eta, T, last = ClodRender.apply(leaves["mean"], leaves["log_scale"], leaves["quat"], leaves["opacity"],
                                          leaves["decay"], leaves["sh"], b, sc["sh_degree"])
-    gr = torch.linspace(-1, 1, rgb.numel(), device="cuda")
+    gr = torch.linspace(-1, 1, rgb.numel(), device="cuda", dtype=torch.float32)
     (rgb * gr).sum().add_(0.5 * eta.sum()).backward()
-    direct = b.render_bwd(scene, T, last, gr, torch.full((1,), 0.5, device="cuda"))
-    # The adjoint sums with FP32 atomics, whose order differs from run to run.
-    for k in leaves:
-        err = O.grad_rel_error(leaves[k].grad.cpu().numpy(), direct[k].cpu().numpy())
-        assert err <= 1e-5, (k, err)
-    assert abs(float(eta.detach()[0]) - float(b.counts[0, 1]) / sc["n"]) < 1e-7
+    direct = b.render_bwd(scene, T, last, gr, torch.full((1,), 0.5, device="cuda", dtype=torch.float32))
+    # The adjoint sums with FP32 atomics, whose order differs from run to run: element-wise
+    # within 1e-5 of the magnitude of each element's terms.
+    S = O.fp64_abs_adjoint(sc, views[0], O.render32(sc, views[0]), gr.cpu().numpy().reshape(3, 48, 64), 0.5)
+    check_grads({k: leaves[k].grad.cpu().numpy() for k in leaves}, {k: direct[k].cpu().numpy() for k in leaves}, S,
+                1e-5, log=log)
+    # eta of Eq. (4) comes from the library: the binary32 quotient n_mask / n.
+    assert float(eta.detach()[0]) == float(np.float32(np.float32(float(b.counts[0, 1])) / np.float32(sc["n"])))
 
 
 def test_loss_matches_closed_forms():

@@ -45,10 +45,13 @@ def test_loss_with_dssim_matches_fp64_oracle(lam):
     loss = loss.cpu().numpy()
     dLs = b.split(dL, 3)
     for v, view in enumerate(views):
-        ref, g = SO.render_loss64(xs[v], ys[v], lam)
+        ref, g, terms = SO.render_loss64(xs[v], ys[v], lam, abs_terms=True)
         ws = O.w_s(view.s_v, s_max)
         assert abs(loss[v] - ws * ref) <= 2e-6 * max(1.0, abs(ws * ref)), (v, loss[v], ws * ref)
         got = dLs[v].cpu().numpy()
-        err = O.grad_rel_error(got, ws * g)
-        log(f"  view {v}: loss {loss[v]:.7f} ref {ws * ref:.7f}  grad max-norm rel err {err:.2e}")
+        # Every pixel's gradient within 1e-4 of the magnitude of its chain-rule terms (the
+        # 11 x 11 window sums of the SSIM map's derivatives cancel strongly).
+        err = O.grad_elem_error(got, ws * g, ws * terms)
+        log(f"  view {v}: loss {loss[v]:.7f} ref {ws * ref:.7f}  grad elem/S {err:.2e}  "
+            f"floor-rel {O.grad_floor_error(got, ws * g):.2e}")
         assert err <= 1e-4, (v, err)
