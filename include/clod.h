@@ -179,6 +179,22 @@ clod_status clod_render_bwd(const clod_scene *scene, const clod_batch *batch, co
 clod_status clod_lod_count(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+   that must not call hipMalloc, harnesses that forbid it): the counts of clod_lod_count, with
+   the same decisions, for n Gaussians and n_views views (views_host: host array for validation
+   and launch geometry; views_dev: the same views in device memory; params: host), without a
+   caller workspace.  The per-view constants, per-block partials and the work list live in a
+   library-owned device array of CLOD_LOD_SCRATCH_BYTES per GPU (held by each GPU the library
+   runs on until the process ends); the call allocates nothing.  Inputs whose workspace exceeds
+   it (about 4 bytes per Gaussian plus about 24 KiB per view, plus 128 KiB per budgeted view)
+   are rejected with CLOD_E_ARG before anything is launched.  Every call on one GPU shares that
+   array and leaves its contents behind (nothing in it needs to start cleared): calls that
+   overlap on one GPU (other streams or threads) race and must be serialised by the caller. */
+#define CLOD_LOD_SCRATCH_BYTES (64u << 20)
+clod_status clod_lod_count_noalloc(const clod_scene *scene, int32_t n_views, const clod_view *views_host,
+                                   const clod_view *views_dev, const clod_params *params,
+                                   int64_t *counts_dev, void *stream);
+
 /* Sec. 3.3, Eq. (3)-(5), with L_render the 3DGS rendering loss, a weighted sum of L1 and
    D-SSIM: per view v,
      L1_v = mean |rgb - target| over 3 H W,

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libclod.so")
 
 CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
 MAX_VIEWS = 1024
+LOD_SCRATCH_BYTES = 64 << 20   # library scratch of clod_lod_count_noalloc (per GPU)
 ABI_VERSION = 11
 
 
@@ -72,7 +73,7 @@ assert ctypes.sizeof(clod_view) == 112
 
 EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project", "clod_bin_sort",
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
-           "clod_inspect", "clod_last_error", "clod_abi_version", "clod_adam_step"]
+           "clod_inspect", "clod_last_error", "clod_abi_version", "clod_adam_step", "clod_lod_count_noalloc"]
 
 SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC, SEC_ALPHA = 0, 1, 2, 3, 4
 SEC_FLAGS, SEC_DMAX, SEC_GSCREEN, SEC_HEADER = 6, 7, 9, 10
@@ -98,6 +99,7 @@ def load(path: str = LIB_PATH):
     L.clod_render_fwd.argtypes = [P, P, P, P, P, P]; L.clod_render_fwd.restype = i32
     L.clod_render_bwd.argtypes = [P, P, P, P, P, P, i32, P, P]; L.clod_render_bwd.restype = i32
     L.clod_lod_count.argtypes = [P, P, P, P]; L.clod_lod_count.restype = i32
+    L.clod_lod_count_noalloc.argtypes = [P, i32, P, P, P, P, P]; L.clod_lod_count_noalloc.restype = i32
     L.clod_loss.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, sz, P, P, P, P]
     L.clod_loss.restype = i32
     L.clod_read_info.argtypes = [P, P, P]; L.clod_read_info.restype = i32
@@ -239,6 +241,13 @@ def clod_render_bwd(scene: clod_scene, batch: clod_batch, T, last, dL_drgb, dL_d
 
 def clod_lod_count(scene: clod_scene, batch: clod_batch, counts, stream=None):
     _check(load().clod_lod_count(ctypes.byref(scene), ctypes.byref(batch), _ptr(counts, I64), _stream(stream)))
+
+
+def clod_lod_count_noalloc(scene: clod_scene, views_host, views_dev, params: clod_params, counts, stream=None):
+    """clod_lod_count without a workspace (library scratch; see clod.h)."""
+    _check(load().clod_lod_count_noalloc(ctypes.byref(scene), len(views_host), ctypes.cast(views_host, P),
+                                         _ptr(views_dev, torch.uint8), ctypes.byref(params), _ptr(counts, I64),
+                                         _stream(stream)))
 
 
 ADAM_GROUPS = ("mean", "log_scale", "quat", "opacity", "decay", "sh_dc", "sh_rest")

@@ -5,7 +5,14 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "clod_internal.h"
+
+// Workspace of clod_lod_count_noalloc: a library-owned array, one copy per GPU.  Host code never
+// passes this name to a kernel or a copy (on the host it is only a stand-in for the symbol):
+// it uses the device address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[CLOD_LOD_SCRATCH_BYTES];
 
 namespace clod {
 
@@ -211,6 +218,53 @@ static clod_status check_scene(const clod_scene* s) {
   return CLOD_OK;
 }
 
+// Count-only workspace: the sections the LoD counting kernels use, nothing per tile or pixel.
+struct CountLayout {
+  size_t vinfo, dmax_key, counts, kpart, cpart, sel_state, sel_hist, lcount, list, total;
+};
+
+static CountLayout count_layout(int64_t n, int32_t V, bool any_budget) {
+  CountLayout C;
+  size_t o = 0;
+  C.vinfo = o; o = align256(o + (size_t)V * sizeof(DevView));
+  C.dmax_key = o; o = align256(o + (size_t)V * 8);
+  C.counts = o; o = align256(o + (size_t)V * 3 * 8);
+  C.kpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 8);
+  C.cpart = o; o = align256(o + (size_t)kMaxProjBlocks * V * 4 * 4);
+  C.sel_state = o; o = align256(o + (size_t)V * sizeof(SelState));
+  C.sel_hist = o; o = align256(o + (any_budget ? (size_t)V * kSelBlocks * 256 * 4 : 0));
+  C.lcount = o; o = align256(o + (size_t)kMaxProjBlocks * 4);
+  C.list = o; o = align256(o + (size_t)n * 4);
+  C.total = o;
+  return C;
+}
+
+// Device address of `scratch` on the device that runs `stream` (the current device for the
+// null stream), looked up once per device with that device current and kept.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];
+
+static clod_status scratch_address(hipStream_t s, void** out) {
+  int dev = 0, cur = 0;
+  HIP_TRY(hipGetDevice(&cur), "current device");
+  dev = cur;
+  if (s) HIP_TRY(hipStreamGetDevice(s, &dev), "stream device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(CLOD_E_UNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    if (dev != cur) HIP_TRY(hipSetDevice(dev), "select the stream's device");
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) HIP_TRY(hipSetDevice(cur), "restore the current device");
+    HIP_TRY(e, "scratch address");
+    if (!p) return fail(CLOD_E_HIP, "scratch address is NULL");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return CLOD_OK;
+}
+
 static clod_status dup_check(const clod_batch* b, DupLayout& D) {
   if (!b->dup) return fail(CLOD_E_ARG, "dup is NULL");
   if (((uintptr_t)b->dup & 255) != 0) return fail(CLOD_E_ARG, "dup must be 256-byte aligned");
@@ -382,6 +436,50 @@ clod_status clod_lod_count(const clod_scene* scene, const clod_batch* batch, int
   HIP_TRY(launch_lod_count(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
                            (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), counts_dev, nullptr,
                            (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), s),
+          "lod count");
+  return CLOD_OK;
+}
+
+clod_status clod_lod_count_noalloc(const clod_scene* scene, int32_t n_views, const clod_view* views_host,
+                                   const clod_view* views_dev, const clod_params* params, int64_t* counts_dev,
+                                   void* stream) {
+  g_err[0] = 0;
+  clod_status st = check_scene(scene);
+  if (st != CLOD_OK) return st;
+  if (n_views < 1 || n_views > CLOD_MAX_VIEWS) return fail(CLOD_E_ARG, "n_views must be in 1..%d", CLOD_MAX_VIEWS);
+  if (!views_host || !views_dev || !params || !counts_dev)
+    return fail(CLOD_E_ARG, "views_host, views_dev, params and counts_dev must be non-NULL");
+  st = check_params(*params);
+  if (st != CLOD_OK) return st;
+  bool any_budget = false;
+  for (int v = 0; v < n_views; ++v) {
+    st = check_view(views_host[v], v);
+    if (st != CLOD_OK) return st;
+    any_budget = any_budget || views_host[v].budget > 0;
+  }
+  if (scene->n * (int64_t)n_views >= 0xFFFFFFFFll) return fail(CLOD_E_ARG, "n * n_views must be < 2^32");
+  const CountLayout Cl = count_layout(scene->n, n_views, any_budget);
+  if (Cl.total > (size_t)CLOD_LOD_SCRATCH_BYTES)
+    return fail(CLOD_E_ARG, "%lld Gaussians and %d views need %zu bytes of workspace, more than the %u-byte "
+                "library scratch of clod_lod_count_noalloc (use clod_lod_count with a workspace)",
+                (long long)scene->n, n_views, Cl.total, (unsigned)CLOD_LOD_SCRATCH_BYTES);
+  hipStream_t s = (hipStream_t)stream;
+  void* base = nullptr;
+  st = scratch_address(s, &base);
+  if (st != CLOD_OK) return st;
+  char* w = (char*)base;
+  DevView* vinfo = (DevView*)(w + Cl.vinfo);
+  HIP_TRY(launch_view_setup(views_dev, n_views, *params, vinfo, nullptr, s), "view setup");
+  HIP_TRY(launch_frustum_max(*scene, vinfo, n_views, params->near_z, (unsigned long long*)(w + Cl.kpart),
+                             (unsigned long long*)(w + Cl.dmax_key), s),
+          "frustum max");
+  if (any_budget)
+    HIP_TRY(launch_lod_select(*scene, vinfo, n_views, *params, (const unsigned long long*)(w + Cl.dmax_key),
+                              (SelState*)(w + Cl.sel_state), (uint32_t*)(w + Cl.sel_hist), s),
+            "budget select");
+  HIP_TRY(launch_lod_count(*scene, vinfo, n_views, *params, (unsigned long long*)(w + Cl.dmax_key),
+                           (uint32_t*)(w + Cl.cpart), (unsigned long long*)(w + Cl.counts), counts_dev, nullptr,
+                           (uint32_t*)(w + Cl.list), (uint32_t*)(w + Cl.lcount), s),
           "lod count");
   return CLOD_OK;
 }

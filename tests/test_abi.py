@@ -216,3 +216,23 @@ def test_adam_step_rejects_invalid_arguments_before_launch(case):
     # n = 0 is a valid no-op (nothing launched).
     assert lib.clod_adam_step(0, 3, ctypes.byref(p), ctypes.byref(g), ctypes.byref(m), ctypes.byref(v),
                               ctypes.byref(C.make_adam({k: 1e-3 for k in C.ADAM_GROUPS}, t=1)), None) == C.CLOD_OK
+
+
+@no_gpu_only
+def test_noalloc_lod_count_rejects_inputs_beyond_its_scratch_before_launch():
+    lib = C.load()
+    # 17M Gaussians: the work list alone (4 bytes per Gaussian) exceeds the 64 MiB scratch.
+    vs = [synth.look_at((0, 0, -3), width=16, height=16)]
+    arr = C.make_views(vs)
+    scene = fake_scene(n=17_000_000)
+    p = C.make_params()
+    st = lib.clod_lod_count_noalloc(ctypes.byref(scene), len(vs), ctypes.cast(arr, C.P), FAKE, ctypes.byref(p),
+                                    FAKE, None)
+    assert st == C.CLOD_E_ARG and b"scratch" in lib.clod_last_error()
+    # Other argument errors are caught first, as in clod_lod_count.
+    one = C.make_views([synth.look_at((0, 0, -3), width=16, height=16, s_v=0.5)])
+    st = lib.clod_lod_count_noalloc(ctypes.byref(fake_scene()), 1, ctypes.cast(one, C.P), FAKE, ctypes.byref(p),
+                                    FAKE, None)
+    assert st == C.CLOD_E_ARG
+    assert lib.clod_lod_count_noalloc(ctypes.byref(fake_scene()), 0, ctypes.cast(one, C.P), FAKE,
+                                      ctypes.byref(p), FAKE, None) == C.CLOD_E_ARG
