@@ -45,6 +45,28 @@ def test_config1_forward_bitexact():
     assert 0 < g["pairs"][1] <= r["pair_classes"][1]
 
 
+def test_long_tile_lists_bitexact_and_counted():
+    """A dense cluster of 380k Gaussians seen from far away falls into two tiles with lists of
+    more than 65,536 entries (beside short lists from a sparse cluster): bit-identical to the
+    oracle at every pixel, with the contract's evaluated and blended pair counts."""
+    log("case: long tile lists")
+    dense = synth.make_scene(380_000, 0, "uniform", seed=33, log_scale_mean=-5.0)
+    spread = synth.make_scene(20_000, 0, "uniform", seed=34, log_scale_mean=-2.5)
+    spread["mean"] = (spread["mean"] * np.float32(12.0)).astype(np.float32)
+    sc = dict(n=400_000, sh_degree=0, **{k: np.ascontiguousarray(np.concatenate([dense[k], spread[k]], axis=-1))
+                                        for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")})
+    v = synth.look_at((0.0, 0.0, -40.0), width=96, height=80, s_v=1.0)
+    g = gpu_forward(sc, [v])
+    r = O.render32(sc, v)
+    lists = np.diff(r["tile_off"])
+    log(f"  counts {g['counts'][0].tolist()}, pairs {g['D']}, longest list {lists.max()}, "
+        f"lists >= 65536: {(lists >= 65536).sum()}")
+    assert (lists >= 65536).sum() >= 2 and (lists[(lists > 0) & (lists < 65536)]).size >= 1
+    compare_forward(g, sc, [v])
+    assert g["pairs"][0] == r["pair_classes"][0] and g["pairs"][2] == r["pair_classes"][2]
+    assert 0 < g["pairs"][1] <= r["pair_classes"][1]
+
+
 def test_multiview_ragged_forward_bitexact():
     """Three views of different (ragged) resolutions and LoD scales in one batch."""
     log("case: multiview ragged")
