@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 11
+#define CLOD_ABI_VERSION 12
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -43,7 +43,8 @@ typedef enum {
   CLOD_E_ARG = -1,       /* invalid argument (host check, nothing launched)           */
   CLOD_E_CAPACITY = -2,  /* more tile duplicates than the duplicate buffer holds       */
   CLOD_E_HIP = -3,       /* a HIP runtime call or kernel launch failed                  */
-  CLOD_E_UNSUPPORTED = -4
+  CLOD_E_UNSUPPORTED = -4,
+  CLOD_E_BUSY = -5       /* every slot of the persistent server holds an unfinished job    */
 } clod_status;
 
 /* A scene: n Gaussians (Sec. 3.1: mean, covariance from scale and rotation, opacity, SH
@@ -268,6 +269,57 @@ enum {
 };
 clod_status clod_inspect(const clod_batch *batch, int32_t section, const void **dev_ptr,
                          int64_t *count);
+
+/* Persistent serving launch (Sec. 4.2: real-time rendering of a resident scene at any viewing
+   distance; requests are batched continuously).  One kernel stays resident on the stream given
+   to clod_server_start until clod_server_stop.  A job is one batch of views: the stages that
+   clod_project, clod_bin_sort and clod_render_fwd launch one kernel at a time, run instead by
+   the resident workgroups, which take blocks of the open stage of the oldest unfinished job;
+   stages of different jobs overlap.  Results are bit-identical to those three calls.
+
+   Threading: one host thread drives a server.  Jobs complete in any order; up to
+   CLOD_SERVER_SLOTS are in flight.  Each job's scene, workspace, duplicate buffer and outputs
+   must stay valid and untouched until clod_server_poll reports the job done.  While the server
+   runs, work of other streams still gets the device capacity the server leaves free (one
+   workgroup slot per compute unit by default); never synchronise the whole device, free device
+   memory (which synchronises it) or wait on the server's stream before clod_server_stop. */
+#define CLOD_SERVER_SLOTS 16
+#define CLOD_SERVER_MAX_VIEWS 16
+typedef struct clod_server clod_server;
+
+/* Allocates the server's queue state (device memory, and coherent pinned host memory for the
+   job ring and completion records) and launches the resident kernel on `stream`.  workers: 0
+   fills the device's resident capacity but one workgroup per compute unit, else that many
+   worker workgroups.  max_seconds in (0, 3600]: the kernel ends by itself after this long (a
+   bound on every wait; jobs still open then never complete).  *server receives the handle,
+   *workers_used (nullable) the worker count. */
+clod_status clod_server_start(int32_t workers, double max_seconds, void *stream, clod_server **server,
+                              int32_t *workers_used);
+
+/* Publishes one job: the views of `batch` rendered as clod_project + clod_bin_sort +
+   clod_render_fwd would (no counters), into rgb / T / last with their layouts.  Same checks as
+   those calls, plus: batch->n_views <= CLOD_SERVER_MAX_VIEWS, scene->sh_packed set (the
+   server's projection reads the packed coefficients); batch->views_dev is not read (the job
+   carries its own copy of views_host).  Never blocks: CLOD_E_BUSY when the next slot's job has
+   not completed yet (poll, then retry).  *seq receives the job's sequence number (0, 1, ...). */
+clod_status clod_server_submit(clod_server *server, const clod_scene *scene, const clod_batch *batch, float *rgb,
+                               float *T, uint32_t *last, int64_t *seq);
+
+/* *done = 1 once job seq is complete (its outputs are then visible to later work on any
+   stream), else 0.  info (nullable) receives {overflow flag, tile pairs D, completion time in ns
+   of the device clock since the server started}.  A job whose duplicate buffer overflowed
+   completes with the flag set and its outputs unwritten; submit it again with a larger buffer.
+   CLOD_E_ARG if seq was never published or its slot already holds a later job. */
+clod_status clod_server_poll(clod_server *server, int64_t seq, int32_t *done, int64_t *info);
+
+/* Device clock in ns since the server started, as of the server's last poll of the host (it
+   polls continuously while idle); -1 before the kernel runs. */
+clod_status clod_server_clock(clod_server *server, int64_t *ns);
+
+/* Raises the stop flag, waits for the kernel to end and frees the server.  *status (nullable):
+   1 stopped on request, 2 deadline reached, 3 protocol error, 4 unsupported stage; anything
+   but 1 also returns CLOD_E_HIP.  Jobs not complete by then are abandoned. */
+clod_status clod_server_stop(clod_server *server, int32_t *status);
 
 /* Message of the last error on this thread ("" if none). */
 const char *clod_last_error(void);

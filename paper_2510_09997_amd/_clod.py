@@ -16,10 +16,11 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libclod.so")
 
-CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED = 0, -1, -2, -3, -4
+CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED, CLOD_E_BUSY = 0, -1, -2, -3, -4, -5
 MAX_VIEWS = 1024
 LOD_SCRATCH_BYTES = 64 << 20   # library scratch of clod_lod_count_noalloc (per GPU)
-ABI_VERSION = 11
+SERVER_SLOTS, SERVER_MAX_VIEWS = 16, 16
+ABI_VERSION = 12
 
 
 class ClodError(RuntimeError):
@@ -29,6 +30,10 @@ class ClodError(RuntimeError):
 
 
 class CapacityError(ClodError):
+    pass
+
+
+class BusyError(ClodError):
     pass
 
 
@@ -73,7 +78,8 @@ assert ctypes.sizeof(clod_view) == 112
 
 EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project", "clod_bin_sort",
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
-           "clod_inspect", "clod_last_error", "clod_abi_version", "clod_adam_step", "clod_lod_count_noalloc"]
+           "clod_inspect", "clod_last_error", "clod_abi_version", "clod_adam_step", "clod_lod_count_noalloc",
+           "clod_server_start", "clod_server_submit", "clod_server_poll", "clod_server_clock", "clod_server_stop"]
 
 SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC, SEC_ALPHA = 0, 1, 2, 3, 4
 SEC_FLAGS, SEC_DMAX, SEC_GSCREEN, SEC_HEADER = 6, 7, 9, 10
@@ -107,6 +113,11 @@ def load(path: str = LIB_PATH):
     L.clod_inspect.argtypes = [P, i32, P, P]; L.clod_inspect.restype = i32
     L.clod_last_error.argtypes = []; L.clod_last_error.restype = ctypes.c_char_p
     L.clod_abi_version.argtypes = []; L.clod_abi_version.restype = i32
+    L.clod_server_start.argtypes = [i32, ctypes.c_double, P, P, P]; L.clod_server_start.restype = i32
+    L.clod_server_submit.argtypes = [P, P, P, P, P, P, P]; L.clod_server_submit.restype = i32
+    L.clod_server_poll.argtypes = [P, i64, P, P]; L.clod_server_poll.restype = i32
+    L.clod_server_clock.argtypes = [P, P]; L.clod_server_clock.restype = i32
+    L.clod_server_stop.argtypes = [P, P]; L.clod_server_stop.restype = i32
     if L.clod_abi_version() != ABI_VERSION:
         raise RuntimeError("libclod ABI version mismatch")
     _lib = L
@@ -118,6 +129,8 @@ def _check(status: int):
         msg = load().clod_last_error().decode()
         if status == CLOD_E_CAPACITY:
             raise CapacityError(status, msg)
+        if status == CLOD_E_BUSY:
+            raise BusyError(status, msg)
         raise ClodError(status, msg)
 
 
@@ -289,3 +302,43 @@ def clod_inspect(batch: clod_batch, section: int) -> tuple[int, int]:
     cnt = ctypes.c_int64(0)
     _check(load().clod_inspect(ctypes.byref(batch), int(section), ctypes.byref(ptr), ctypes.byref(cnt)))
     return int(ptr.value or 0), int(cnt.value)
+
+
+# ------------------------------------------------------------------------------- persistent server
+
+def clod_server_start(workers: int = 0, max_seconds: float = 60.0, stream=None) -> tuple[int, int]:
+    """Launches the resident serving kernel on `stream`; returns (handle, workers used)."""
+    h = ctypes.c_void_p(0)
+    used = ctypes.c_int32(0)
+    _check(load().clod_server_start(int(workers), float(max_seconds), _stream(stream), ctypes.byref(h),
+                                    ctypes.byref(used)))
+    return int(h.value), int(used.value)
+
+
+def clod_server_submit(server: int, scene: clod_scene, batch: clod_batch, rgb, T, last) -> int:
+    seq = ctypes.c_int64(-1)
+    _check(load().clod_server_submit(P(server), ctypes.byref(scene), ctypes.byref(batch), _ptr(rgb, F32), _ptr(T, F32),
+                                     _ptr(last, I32), ctypes.byref(seq)))
+    return int(seq.value)
+
+
+def clod_server_poll(server: int, seq: int) -> dict | None:
+    """None while job `seq` runs, else {overflow, n_dup, t_ns} (device clock since start)."""
+    done = ctypes.c_int32(0)
+    info = (ctypes.c_int64 * 3)()
+    _check(load().clod_server_poll(P(server), int(seq), ctypes.byref(done), info))
+    if not done.value:
+        return None
+    return dict(overflow=bool(info[0]), n_dup=int(info[1]), t_ns=int(info[2]))
+
+
+def clod_server_clock(server: int) -> int:
+    ns = ctypes.c_int64(0)
+    _check(load().clod_server_clock(P(server), ctypes.byref(ns)))
+    return int(ns.value)
+
+
+def clod_server_stop(server: int) -> int:
+    st = ctypes.c_int32(0)
+    _check(load().clod_server_stop(P(server), ctypes.byref(st)))
+    return int(st.value)

@@ -15,7 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libclod.so")
-SOURCES = ["api.hip", "project.hip", "sort.hip", "blend.hip", "grad.hip", "loss.hip", "optim.hip", "ssim.hip"]
+# server.hip includes project.hip, sort.hip and blend.hip: the persistent server and the
+# per-stage kernels are compiled from the same stage bodies in one translation unit.
+SOURCES = ["api.hip", "server.hip", "grad.hip", "loss.hip", "optim.hip", "ssim.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -1,5 +1,5 @@
 // C ABI of libclod: host-side validation, workspace carving and launch sequencing.
-// Nothing here allocates device memory; both workspaces belong to the caller.
+// Workspaces belong to the caller; only the persistent server allocates (its queue state).
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -274,6 +274,36 @@ static clod_status dup_check(const clod_batch* b, DupLayout& D) {
   return CLOD_OK;
 }
 
+// The stage sequences of the forward path, shared by the per-stage entry points (a Sink on
+// the caller's stream) and the persistent server (a Sink that records a Program).
+static hipError_t project_stages(const clod_scene& sc, const clod_view* views_dev, const clod_params& prm,
+                                 const Layout& L, void* ws, int64_t* counts_dev, float* eta_dev, const Sink& out) {
+  char* w = (char*)ws;
+  DevView* vinfo = (DevView*)(w + L.vinfo);
+  unsigned long long* dmax_key = (unsigned long long*)(w + L.dmax_key);
+  hipError_t e = launch_view_setup(views_dev, L.V, prm, vinfo, (unsigned long long*)(w + L.hdr), out);
+  if (e == hipSuccess)
+    e = launch_frustum_max(sc, vinfo, L.V, prm.near_z, (unsigned long long*)(w + L.kpart), dmax_key, out);
+  if (e == hipSuccess && L.any_budget)
+    e = launch_lod_select(sc, vinfo, L.V, prm, dmax_key, (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist),
+                          out);
+  if (e == hipSuccess)
+    e = launch_project(sc, vinfo, L.V, prm, dmax_key, (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts),
+                       counts_dev, eta_dev, (uint8_t*)(w + L.flags), (float*)(w + L.alpha), (float4*)(w + L.rec),
+                       (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), out);
+  return e;
+}
+
+static hipError_t bin_stages(const Layout& L, void* ws, const DupLayout& D, void* dup, const Sink& out) {
+  hipError_t e = launch_bin_sort(L, ws, D, dup, out);
+  if (e == hipSuccess) e = launch_ranges(L, ws, D, dup, sorted_buffer(L.tiles_total), out);
+  return e;
+}
+
+static const uint32_t* sorted_vals(const clod_batch* b, const Layout& L, const DupLayout& D) {
+  return (const uint32_t*)((const char*)b->dup + (sorted_buffer(L.tiles_total) ? D.vals1 : D.vals0));
+}
+
 }  // namespace clod
 
 using namespace clod;
@@ -319,23 +349,8 @@ clod_status clod_project(const clod_scene* scene, const clod_batch* batch, int64
   st = prepare(batch, true, cx);
   if (st != CLOD_OK) return st;
   if (scene->n != batch->n) return fail(CLOD_E_ARG, "scene->n (%lld) != batch->n (%lld)", (long long)scene->n, (long long)batch->n);
-  hipStream_t s = (hipStream_t)stream;
-  const Layout& L = cx.L;
-  char* w = (char*)batch->ws;
-  DevView* vinfo = (DevView*)(w + L.vinfo);
-  unsigned long long* hdr = (unsigned long long*)(w + L.hdr);
-  HIP_TRY(launch_view_setup(batch->views_dev, L.V, batch->params, vinfo, hdr, s), "view setup");
-  HIP_TRY(launch_frustum_max(*scene, vinfo, L.V, batch->params.near_z, (unsigned long long*)(w + L.kpart),
-                             (unsigned long long*)(w + L.dmax_key), s),
-          "frustum max");
-  if (L.any_budget)
-    HIP_TRY(launch_lod_select(*scene, vinfo, L.V, batch->params, (const unsigned long long*)(w + L.dmax_key),
-                              (SelState*)(w + L.sel_state), (uint32_t*)(w + L.sel_hist), s),
-            "budget select");
-  HIP_TRY(launch_project(*scene, vinfo, L.V, batch->params, (unsigned long long*)(w + L.dmax_key),
-                         (uint32_t*)(w + L.cpart), (unsigned long long*)(w + L.counts), counts_dev, eta_dev,
-                         (uint8_t*)(w + L.flags), (float*)(w + L.alpha), (float4*)(w + L.rec),
-                         (uint32_t*)(w + L.list), (uint32_t*)(w + L.lcount), s),
+  HIP_TRY(project_stages(*scene, batch->views_dev, batch->params, cx.L, batch->ws, counts_dev, eta_dev,
+                         Sink((hipStream_t)stream)),
           "project");
   return CLOD_OK;
 }
@@ -351,8 +366,7 @@ clod_status clod_bin_sort(const clod_batch* batch, int64_t* n_dup_host, void* st
   hipStream_t s = (hipStream_t)stream;
   const Layout& L = cx.L;
   char* w = (char*)batch->ws;
-  HIP_TRY(launch_bin_sort(L, batch->ws, D, batch->dup, s), "binning sort");
-  HIP_TRY(launch_ranges(L, batch->ws, D, batch->dup, sorted_buffer(L.tiles_total), s), "ranges");
+  HIP_TRY(bin_stages(L, batch->ws, D, batch->dup, Sink(s)), "binning sort");
   if (n_dup_host) {
     unsigned long long h[2];
     HIP_TRY(hipMemcpyAsync(h, w + L.hdr, sizeof(h), hipMemcpyDeviceToHost, s), "read count");
@@ -362,10 +376,6 @@ clod_status clod_bin_sort(const clod_batch* batch, int64_t* n_dup_host, void* st
                           (long long)h[0], (long long)D.cap);
   }
   return CLOD_OK;
-}
-
-static const uint32_t* sorted_vals(const clod_batch* b, const Layout& L, const DupLayout& D) {
-  return (const uint32_t*)((const char*)b->dup + (sorted_buffer(L.tiles_total) ? D.vals1 : D.vals0));
 }
 
 clod_status clod_render_fwd(const clod_batch* batch, float* rgb, float* T, uint32_t* last,
@@ -379,7 +389,7 @@ clod_status clod_render_fwd(const clod_batch* batch, float* rgb, float* T, uint3
   if (st != CLOD_OK) return st;
   if (!rgb || !T || !last) return fail(CLOD_E_ARG, "rgb, T and last must be non-NULL");
   HIP_TRY(launch_blend_fwd(cx.L, batch->ws, sorted_vals(batch, cx.L, D), batch->params, rgb, T, last,
-                           pairs_dev, (hipStream_t)stream),
+                           pairs_dev, Sink((hipStream_t)stream)),
           "blend forward");
   return CLOD_OK;
 }
@@ -598,6 +608,86 @@ clod_status clod_inspect(const clod_batch* batch, int32_t section, const void** 
     case CLOD_SEC_HEADER: *dev_ptr = w + L.hdr; *count = 2; break;
     default: return fail(CLOD_E_ARG, "unknown section %d", section);
   }
+  return CLOD_OK;
+}
+
+// ---------------------------------------------------------------------------- persistent server
+clod_status clod_server_start(int32_t workers, double max_seconds, void* stream, clod_server** server,
+                              int32_t* workers_used) {
+  g_err[0] = 0;
+  if (!server) return fail(CLOD_E_ARG, "server is NULL");
+  *server = nullptr;
+  if (workers < 0) return fail(CLOD_E_ARG, "workers must be >= 0");
+  if (!(max_seconds > 0.0 && max_seconds <= 3600.0)) return fail(CLOD_E_ARG, "max_seconds must be in (0, 3600]");
+  Server* S = nullptr;
+  HIP_TRY(server_start(workers, max_seconds, (hipStream_t)stream, &S, workers_used), "server start");
+  *server = reinterpret_cast<clod_server*>(S);
+  return CLOD_OK;
+}
+
+clod_status clod_server_submit(clod_server* server, const clod_scene* scene, const clod_batch* batch, float* rgb,
+                               float* T, uint32_t* last, int64_t* seq) {
+  g_err[0] = 0;
+  if (!server || !seq) return fail(CLOD_E_ARG, "server and seq must be non-NULL");
+  Server* S = reinterpret_cast<Server*>(server);
+  clod_status st = check_scene(scene);
+  if (st != CLOD_OK) return st;
+  if (scene->n > 0 && !scene->sh_packed)
+    return fail(CLOD_E_ARG, "the server reads packed SH coefficients: scene->sh_packed must be set");
+  if (!batch) return fail(CLOD_E_ARG, "batch is NULL");
+  if (batch->n_views < 1 || batch->n_views > kSrvMaxViews)
+    return fail(CLOD_E_ARG, "n_views must be in 1..%d for the server", kSrvMaxViews);
+  // The server keeps its own device copy of the views; batch->views_dev is not read.
+  clod_batch b = *batch;
+  b.views_dev = server_views_dev(S, server_next_seq(S));
+  Ctx cx;
+  st = prepare(&b, true, cx);
+  if (st != CLOD_OK) return st;
+  if (scene->n != b.n) return fail(CLOD_E_ARG, "scene->n (%lld) != batch->n (%lld)", (long long)scene->n, (long long)b.n);
+  DupLayout D;
+  st = dup_check(&b, D);
+  if (st != CLOD_OK) return st;
+  if (!rgb || !T || !last) return fail(CLOD_E_ARG, "rgb, T and last must be non-NULL");
+  if (!server_slot_free(S)) return fail(CLOD_E_BUSY, "all %d server slots hold unfinished jobs", kSrvSlots);
+  static thread_local Program P;
+  P.n = 0;
+  P.full = false;
+  const Sink out(&P);
+  hipError_t e = project_stages(*scene, b.views_dev, b.params, cx.L, b.ws, nullptr, nullptr, out);
+  if (e == hipSuccess) e = bin_stages(cx.L, b.ws, D, b.dup, out);
+  if (e == hipSuccess)
+    e = launch_blend_fwd(cx.L, b.ws, sorted_vals(&b, cx.L, D), b.params, rgb, T, last, nullptr, out);
+  if (P.full) return fail(CLOD_E_UNSUPPORTED, "the job needs more than %d stages", kMaxStages);
+  HIP_TRY(e, "job stages");
+  HIP_TRY(server_publish(S, P, b.n_views, b.views_host, (const char*)b.ws + cx.L.hdr, seq), "publish");
+  return CLOD_OK;
+}
+
+clod_status clod_server_poll(clod_server* server, int64_t seq, int32_t* done, int64_t* info) {
+  g_err[0] = 0;
+  if (!server || !done) return fail(CLOD_E_ARG, "server and done must be non-NULL");
+  const int r = server_poll(reinterpret_cast<Server*>(server), seq, info);
+  if (r < 0) return fail(CLOD_E_ARG, "job %lld was not published or its slot was reused", (long long)seq);
+  *done = r;
+  return CLOD_OK;
+}
+
+clod_status clod_server_clock(clod_server* server, int64_t* ns) {
+  g_err[0] = 0;
+  if (!server || !ns) return fail(CLOD_E_ARG, "server and ns must be non-NULL");
+  *ns = server_clock_ns(reinterpret_cast<Server*>(server));
+  return CLOD_OK;
+}
+
+clod_status clod_server_stop(clod_server* server, int32_t* status) {
+  g_err[0] = 0;
+  if (!server) return fail(CLOD_E_ARG, "server is NULL");
+  int32_t code = 0;
+  HIP_TRY(server_stop(reinterpret_cast<Server*>(server), &code), "server stop");
+  if (status) *status = code;
+  if (code != (int32_t)kSrvStopped)
+    return fail(CLOD_E_HIP, "the server ended with status %d (2: deadline reached, 3: protocol error, "
+                "4: unsupported stage)", code);
   return CLOD_OK;
 }
 

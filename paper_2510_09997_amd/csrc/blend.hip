@@ -125,25 +125,37 @@ __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, fl
 // LDS reads issued before the current entry's arithmetic.  A wave stops as soon as its 64
 // pixels are saturated, independently of the other quadrants; the only block barrier is the
 // final reduction of the optional pair counters.
+struct TileLds {
+  float4 st[4][3][64];   // per wave: (u, v, hA, nB), (hC, alpha'', r, g), (b, cut, -, -)
+};
+
+// One tile, at position pos of the batch's tile order, by the 256 threads of the block (four
+// independent waves).  Shared by the per-batch launch (k_blend_fwd) and the persistent server.
 template <bool kCount>
-__global__ __launch_bounds__(kBlock) void k_blend_fwd(
-    const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
-    const float4* __restrict__ rec, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ svals, const unsigned long long* __restrict__ hdr,
-    float bg0, float bg1, float bg2, float* __restrict__ rgb, float* __restrict__ Tout,
-    uint32_t* __restrict__ lastout, unsigned long long* __restrict__ pair_part,
-    const uint32_t* __restrict__ order) {
-  __shared__ float4 st[4][3][64];   // per wave: (u, v, hA, nB), (hC, alpha'', r, g), (b, cut, -, -)
-  __shared__ unsigned long long sp[4][3];
-  const uint32_t pos = xcd_tile_pos(blockIdx.x);
+__device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, TileLds& S) {
+  auto& st = S.st;
+  const DevView* __restrict__ views = a.views;
+  const int V = a.V;
+  const uint32_t tiles_total = a.tiles_total;
+  const int64_t VN = a.VN;
+  const float4* __restrict__ rec = a.rec;
+  const uint2* __restrict__ ranges = a.ranges;
+  const uint32_t* __restrict__ svals = a.svals;
+  const float bg0 = a.bg0, bg1 = a.bg1, bg2 = a.bg2;
+  float* __restrict__ rgb = a.rgb;
+  float* __restrict__ Tout = a.T;
+  uint32_t* __restrict__ lastout = a.last;
+  unsigned long long* __restrict__ pair_part = a.pair_part;
+  const uint32_t* __restrict__ order = a.order;
+  const uint32_t t = threadIdx.x;
+  if (a.hdr[kHdrOverflow]) return;
   if (pos >= tiles_total) return;
   const int tile_i = (int)order[pos];
-  if (hdr[kHdrOverflow]) return;
   const int v = view_of_tile(views, V, (uint32_t)tile_i);
   const DevView& Vw = views[v];
   const int local = tile_i - (int)Vw.tile_base;
   const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
-  const int wave = threadIdx.x >> 6;
+  const int wave = (int)(t >> 6);
   const uint32_t lane = lane_id();
   const int qx0 = tx * kTile + (wave & 1) * 8, qy0 = ty * kTile + (wave >> 1) * 8;
   const int px = qx0 + (int)(lane & 7);
@@ -257,26 +269,35 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(
   }
   if (kCount) {
     // Pairs the contract's per-pixel loop evaluates: up to and including the terminating
-    // entry, else the whole list.  One partial per tile (no same-address atomics).
+    // entry, else the whole list.  The four wave totals are added to the tile's (zeroed)
+    // partials.
     const unsigned long long ev = !inside ? 0ull : (term != 0xFFFFFFFFu ? (unsigned long long)term + 1ull
                                                                          : (unsigned long long)(rg.y - rg.x));
     const unsigned long long es = wave_sum(ev);
     const unsigned long long x = wave_sum((unsigned long long)nexp);
     const unsigned long long bl = wave_sum((unsigned long long)nblend);
-    if (lane == 0) { sp[wave][0] = es; sp[wave][1] = x; sp[wave][2] = bl; }
-    __syncthreads();
-    if (threadIdx.x < 3)
-      pair_part[3 * (int64_t)tile_i + threadIdx.x] =
-          sp[0][threadIdx.x] + sp[1][threadIdx.x] + sp[2][threadIdx.x] + sp[3][threadIdx.x];
+    if (lane == 0) {
+      atomicAdd(pair_part + 3 * (int64_t)tile_i, es);
+      atomicAdd(pair_part + 3 * (int64_t)tile_i + 1, x);
+      atomicAdd(pair_part + 3 * (int64_t)tile_i + 2, bl);
+    }
   }
 }
 
+// Per-batch launch: one workgroup per tile, in the XCD-aware order.
+template <bool kCount>
+__global__ __launch_bounds__(kBlock) void k_blend_fwd(BlendArgs a) {
+  __shared__ TileLds S;
+  blend_tile<kCount>(a, xcd_tile_pos(blockIdx.x), S);
+}
+
 // Sums the per-tile pair partials into the caller's counters (one block, three atomics).
-__global__ __launch_bounds__(kBlock) void k_reduce_pairs(const unsigned long long* __restrict__ part,
-                                                         uint32_t tiles, unsigned long long* __restrict__ out) {
+__device__ __forceinline__ void reduce_pairs_body(const ReducePairsArgs& r, Blk) {
   __shared__ unsigned long long sm[4][3];
+  const unsigned long long* __restrict__ part = r.part;
+  unsigned long long* __restrict__ out = r.out;
   unsigned long long a = 0, b = 0, c = 0;
-  for (uint32_t t = threadIdx.x; t < tiles; t += kBlock) {
+  for (uint32_t t = threadIdx.x; t < r.tiles; t += kBlock) {
     a += part[3 * (int64_t)t]; b += part[3 * (int64_t)t + 1]; c += part[3 * (int64_t)t + 2];
   }
   a = wave_sum(a); b = wave_sum(b); c = wave_sum(c);
@@ -284,25 +305,47 @@ __global__ __launch_bounds__(kBlock) void k_reduce_pairs(const unsigned long lon
   __syncthreads();
   if (threadIdx.x < 3) atomicAdd(out + threadIdx.x, sm[0][threadIdx.x] + sm[1][threadIdx.x] + sm[2][threadIdx.x] + sm[3][threadIdx.x]);
 }
+__global__ __launch_bounds__(kBlock) void k_reduce_pairs(ReducePairsArgs r) { reduce_pairs_body(r, grid_blk()); }
 
 hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals,
                             clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
-                            hipStream_t s) {
+                            const Sink& out) {
   if (L.tiles_total == 0) return hipSuccess;
   char* w = (char*)ws;
-  const int nb = (int)xcd_grid(L.tiles_total);
   unsigned long long* part = pairs ? (unsigned long long*)(w + L.pair_part) : nullptr;
   if (part) {
-    hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, s);
+    hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, out);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(part ? k_blend_fwd<true> : k_blend_fwd<false>, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
-                     L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
-                     sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
-                     prm.bg[2], rgb, T, last, part, (const uint32_t*)(w + L.order));
-  if (part)
-    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlock), 0, s, (const unsigned long long*)part, L.tiles_total,
-                       (unsigned long long*)pairs);
+  Stage st{};
+  st.kind = kStBlend;
+  st.items = xcd_grid(L.tiles_total);
+  st.block = kBlock;
+  st.a.blend = BlendArgs{(const DevView*)(w + L.vinfo), L.V, L.tiles_total, L.VN, (const float4*)(w + L.rec),
+                         (const uint2*)(w + L.ranges), sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0],
+                         prm.bg[1], prm.bg[2], rgb, T, last, part, (const uint32_t*)(w + L.order), part ? 1 : 0};
+  hipError_t e = out.put(st);
+  if (e == hipSuccess && part) {
+    Stage r{};
+    r.kind = kStReducePairs;
+    r.items = 1;
+    r.block = kBlock;
+    r.a.reduce_pairs = ReducePairsArgs{(const unsigned long long*)part, L.tiles_total, (unsigned long long*)pairs};
+    e = out.put(r);
+  }
+  return e;
+}
+
+hipError_t launch_blend_stage(const Stage& st, hipStream_t s) {
+  const dim3 g(st.items), blk(st.block);
+  switch (st.kind) {
+    case kStBlend:
+      if (st.a.blend.count) hipLaunchKernelGGL(k_blend_fwd<true>, g, blk, 0, s, st.a.blend);
+      else hipLaunchKernelGGL(k_blend_fwd<false>, g, blk, 0, s, st.a.blend);
+      break;
+    case kStReducePairs: hipLaunchKernelGGL(k_reduce_pairs, g, blk, 0, s, st.a.reduce_pairs); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -317,14 +317,22 @@ __device__ __forceinline__ float dmax_from_key(unsigned long long key) {
   return key == 0ull ? 1.0f : __uint_as_float((uint32_t)(key >> 32));
 }
 
-// Contiguous chunk [lo, hi) of n items owned by this block (grids capped at kMaxProjBlocks).
-__device__ __forceinline__ void block_chunk(int64_t n, int64_t& lo, int64_t& hi) {
-  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-  lo = (int64_t)blockIdx.x * per;
+// Block b of a stage: its index and the stage's block count.  A per-stage launch takes them
+// from blockIdx.x and gridDim.x; the persistent server passes the item it claimed.
+struct Blk {
+  uint32_t id, n;
+};
+__device__ __forceinline__ Blk grid_blk() { return Blk{blockIdx.x, gridDim.x}; }
+
+// Contiguous chunk [lo, hi) of n items owned by block b (grids capped at kMaxProjBlocks).
+__device__ __forceinline__ void block_chunk(int64_t n, Blk b, int64_t& lo, int64_t& hi) {
+  const int64_t per = (n + b.n - 1) / b.n;
+  lo = (int64_t)b.id * per;
   hi = lo + per;
   if (lo > n) lo = n;
   if (hi > n) hi = n;
 }
+__device__ __forceinline__ void block_chunk(int64_t n, int64_t& lo, int64_t& hi) { block_chunk(n, grid_blk(), lo, hi); }
 
 // Wave64 helpers.
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -432,23 +440,150 @@ __device__ __forceinline__ bool lod_kept(const DevView& Vw, float a2, int64_t i)
 }
 
 // ----------------------------------------------------------------------------------------
-// Launchers (each returns hipGetLastError()).
+// Stages of the forward path.  Projection, binning and blending run as a fixed sequence of
+// stages; a stage is a grid of independent 256-thread blocks that may start once the previous
+// stage has finished.  The launchers below describe each stage (kind, block count, arguments)
+// to a Sink, which either launches it at once as its own kernel on a stream or appends it to a
+// Program; the persistent server executes such programs from its device queue.  Both
+// executors therefore run the same sequence with the same arguments.
+// ----------------------------------------------------------------------------------------
+enum StageKind : int32_t {
+  kStViewSetup = 1, kStFill, kStFrustumMax, kStFold, kStClassify, kStProject, kStSelectHist, kStSelectPick,
+  kStScanReduce, kStScanPartials, kStCompact, kStRadixUp, kStRadixScan, kStRadixDown, kStEmitReduce,
+  kStEmitPartials, kStEmitOffsets, kStEmit, kStRanges, kStTileCount, kStTileScatter, kStBlend, kStReducePairs
+};
+
+struct ViewSetupArgs {
+  const clod_view* views; int32_t V; clod_params prm; DevView* out; unsigned long long* hdr;
+};
+struct FillArgs {
+  uint32_t* p; uint32_t value; int64_t count;
+};
+struct FrustumArgs {
+  const float* mean; int64_t n; const DevView* views; int32_t V; float near_z; unsigned long long* part;
+};
+struct FoldArgs {   // per-view folds of the per-block partials (frustum maximum or counts)
+  const unsigned long long* kpart; const uint32_t* cpart; int32_t G, V; unsigned long long* dmax_key;
+  unsigned long long* counts; int64_t* counts_dev; int64_t n; float* eta_dev;
+};
+struct ClassifyArgs {
+  clod_scene sc; const DevView* views; int32_t V, write; clod_params prm; const unsigned long long* dmax_key;
+  uint32_t* cpart; uint8_t* flags; float* alpha; uint32_t* list; uint32_t* lcount;
+};
+struct ProjectArgs {
+  clod_scene sc; const DevView* views; int32_t V; clod_params prm; const unsigned long long* dmax_key;
+  uint32_t* cpart; const uint32_t* list; const uint32_t* lcount; uint8_t* flags; float4* rec;
+  int32_t write, packed;   // records written; colours from the packed coefficients
+};
+struct SelectArgs {
+  clod_scene sc; DevView* views; int32_t V; clod_params prm; const unsigned long long* dmax_key;
+  SelState* state; uint32_t* hist; int32_t pass;
+};
+struct ScanReduceArgs {
+  const uint8_t* flags; int64_t count; uint32_t* partR; uint32_t* ranges; int64_t range_words;
+};
+struct ScanPartialsArgs {
+  uint32_t* partR; int32_t nparts; unsigned long long* hdr; int64_t cap; uint32_t* tord;
+};
+struct CompactArgs {
+  const uint8_t* flags; int64_t count; const uint32_t* partR; const float4* rec; const unsigned long long* hdr;
+  uint32_t* kout; uint32_t* vout;
+};
+struct RadixArgs {   // one pass: upsweep, digit scan and downsweep share it
+  const uint32_t* kin; const uint32_t* vin; uint32_t* kout; uint32_t* vout; uint32_t* hist;
+  const unsigned long long* hdr; int32_t cw, G, shift;
+};
+struct EmitReduceArgs {
+  const uint32_t* sorted_f; const float4* rec; const uint8_t* flags; int64_t count; const unsigned long long* hdr;
+  uint32_t* partE; uint32_t* tsorted;
+};
+struct EmitPartialsArgs {
+  uint32_t* partE; unsigned long long* hdr; int32_t nb; int64_t cap;
+};
+struct EmitOffsetsArgs {
+  const uint32_t* tsorted; const uint32_t* partE; const unsigned long long* hdr; uint32_t* eoff; uint32_t* owner;
+};
+struct EmitArgs {
+  const uint32_t* sorted_f; const uint32_t* eoff; const uint32_t* owner; const float4* rec; const DevView* views;
+  int64_t n; const unsigned long long* hdr; uint32_t* kout; uint32_t* vout;
+};
+struct RangesArgs {
+  const uint32_t* keys; const unsigned long long* hdr; uint32_t tiles_total; uint2* ranges;
+};
+struct TileOrderArgs {
+  const uint2* ranges; uint32_t tiles; const unsigned long long* hdr; uint32_t* tord; uint32_t* order;
+};
+struct BlendArgs {
+  const DevView* views; int32_t V; uint32_t tiles_total; int64_t VN; const float4* rec; const uint2* ranges;
+  const uint32_t* svals; const unsigned long long* hdr; float bg0, bg1, bg2; float* rgb; float* T; uint32_t* last;
+  unsigned long long* pair_part; const uint32_t* order; int32_t count;
+};
+struct ReducePairsArgs {
+  const unsigned long long* part; uint32_t tiles; unsigned long long* out;
+};
+
+struct Stage {
+  int32_t kind;
+  uint32_t items;   // blocks
+  uint32_t block;   // threads per block of the per-stage launch (the server always runs 256)
+  uint32_t lds;     // dynamic LDS bytes of the per-stage launch
+  union {
+    ViewSetupArgs view_setup; FillArgs fill; FrustumArgs frustum; FoldArgs fold; ClassifyArgs classify;
+    ProjectArgs project; SelectArgs select; ScanReduceArgs scan_reduce; ScanPartialsArgs scan_partials;
+    CompactArgs compact; RadixArgs radix; EmitReduceArgs emit_reduce; EmitPartialsArgs emit_partials;
+    EmitOffsetsArgs emit_offsets; EmitArgs emit; RangesArgs ranges; TileOrderArgs tile_order; BlendArgs blend;
+    ReducePairsArgs reduce_pairs;
+  } a;
+};
+
+constexpr int kMaxStages = 80;
+struct Program {
+  int32_t n = 0;
+  bool full = false;
+  Stage st[kMaxStages];
+};
+
+hipError_t launch_stage(const Stage& st, hipStream_t s);
+hipError_t launch_project_stage(const Stage& st, hipStream_t s);
+hipError_t launch_sort_stage(const Stage& st, hipStream_t s);
+hipError_t launch_blend_stage(const Stage& st, hipStream_t s);
+
+// Where the launchers send their stages: launched at once on `stream`, or appended to `prog`.
+struct Sink {
+  hipStream_t stream = nullptr;
+  Program* prog = nullptr;
+  Sink(hipStream_t s) : stream(s) {}
+  explicit Sink(Program* p) : prog(p) {}
+  hipError_t put(const Stage& st) const {
+    if (st.items == 0) return hipSuccess;
+    if (!prog) return launch_stage(st, stream);
+    if (prog->n >= kMaxStages) {
+      prog->full = true;
+      return hipErrorInvalidValue;
+    }
+    prog->st[prog->n++] = st;
+    return hipSuccess;
+  }
+};
+
+// ----------------------------------------------------------------------------------------
+// Launchers (each returns the first launch error, or hipSuccess).
 // ----------------------------------------------------------------------------------------
 hipError_t launch_view_setup(const clod_view* views_dev, int V, clod_params prm, DevView* vinfo,
-                             unsigned long long* hdr /* cleared when non-NULL */, hipStream_t s);
-hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+                             unsigned long long* hdr /* cleared when non-NULL */, const Sink& out);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, const Sink& out);
 int proj_blocks(int64_t n);
 hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V, float near_z,
-                              unsigned long long* kpart, unsigned long long* dmax_key, hipStream_t s);
+                              unsigned long long* kpart, unsigned long long* dmax_key, const Sink& out);
 // counts (workspace) and counts_dev (caller's int64 [V][3], nullable) receive the per-view
 // {frustum, mask, rendered} counts.
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                           int64_t* counts_dev, float* eta_dev, uint8_t* flags, float* alpha, float4* rec, uint32_t* list,
-                          uint32_t* lcount, hipStream_t s);
+                          uint32_t* lcount, const Sink& out);
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
-                            int64_t* counts_dev, float* eta_dev, uint32_t* list, uint32_t* lcount, hipStream_t s);
+                            int64_t* counts_dev, float* eta_dev, uint32_t* list, uint32_t* lcount, const Sink& out);
 
 // Fused Adam: one segment per learning-rate group.
 constexpr int kAdamGroups = 7;
@@ -468,15 +603,15 @@ struct AdamSegs {
 };
 hipError_t launch_adam(const AdamSegs& segs, float b1, float b2, float eps, float bc1, float bc2, hipStream_t s);
 hipError_t launch_lod_select(const clod_scene& sc, DevView* vinfo, int V, clod_params prm,
-                             const unsigned long long* dmax_key, SelState* state, uint32_t* hist, hipStream_t s);
+                             const unsigned long long* dmax_key, SelState* state, uint32_t* hist, const Sink& out);
 
-hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s);
+hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, const Sink& out);
 hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
-                         hipStream_t s);
+                         const Sink& out);
 
 hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals,
                             clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
-                            hipStream_t s);
+                            const Sink& out);
 hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_vals, clod_params prm,
                             const float* T, const uint32_t* last, const float* dL_drgb,
                             hipStream_t s);
@@ -487,6 +622,21 @@ hipError_t launch_gauss_bwd(const clod_scene& sc, const Layout& L, void* ws, clo
 hipError_t launch_loss(const Layout& L, void* ws, int64_t n, const float* rgb, const float* target,
                        float s_max, float lambda_reg, float lambda_dssim, float* ssim_scratch, float* loss,
                        float* dL_drgb, float* dL_deta, uint32_t loss_blocks, hipStream_t s);
+// Persistent server (server.hip): jobs are forward-render Programs.
+constexpr int kSrvSlots = 16;      // jobs in flight
+constexpr int kSrvMaxViews = 16;   // views per job
+enum SrvStatus : uint32_t { kSrvRunning = 0, kSrvStopped = 1, kSrvDeadline = 2, kSrvProtocol = 3, kSrvUnsupported = 4 };
+struct Server;
+hipError_t server_start(int32_t workers, double max_seconds, hipStream_t s, Server** out, int32_t* used_workers);
+const clod_view* server_views_dev(Server* S, int64_t seq);   // device copy of job seq's views
+int64_t server_next_seq(Server* S);
+bool server_slot_free(Server* S);                             // the next job's slot is free
+hipError_t server_publish(Server* S, const Program& P, int32_t n_views, const clod_view* views_host,
+                          const void* hdr_dev, int64_t* seq);
+int server_poll(Server* S, int64_t seq, int64_t* info);
+int64_t server_clock_ns(Server* S);
+hipError_t server_stop(Server* S, int32_t* status);
+
 hipError_t launch_ssim(const Layout& L, void* ws, const float* rgb, const float* target, float lambda,
                        float s_max, float* coef, float* ssim_part, float* dL_drgb, hipStream_t s);
 constexpr int kSsimRegion = 32;   // output edge of one SSIM block (2 x 2 tiles)

@@ -11,10 +11,13 @@ namespace clod {
 
 // Derives per-view constants on the device (graph-replay safe: reads only views_dev).
 // With `hdr` non-NULL the workspace header is cleared as well (a new projection).
-__global__ void k_view_setup(const clod_view* __restrict__ views, int V, clod_params prm,
-                             DevView* __restrict__ out, unsigned long long* __restrict__ hdr) {
-  if (hdr && blockIdx.x == 0 && threadIdx.x < (unsigned)kHdrWords) hdr[threadIdx.x] = 0ull;
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void view_setup_body(const ViewSetupArgs& a, Blk b) {
+  const clod_view* __restrict__ views = a.views;
+  const int V = a.V;
+  const clod_params& prm = a.prm;
+  DevView* __restrict__ out = a.out;
+  if (a.hdr && b.id == 0 && threadIdx.x < (unsigned)kHdrWords) a.hdr[threadIdx.x] = 0ull;
+  if (threadIdx.x != 0 || b.id != 0) return;
   uint32_t tile_base = 0, pix_base = 0, loss_base = 0, rgn_base = 0;
   for (int v = 0; v < V; ++v) {
     const clod_view& cv = views[v];
@@ -50,19 +53,19 @@ __global__ void k_view_setup(const clod_view* __restrict__ views, int V, clod_pa
     out[v] = d;
   }
 }
+__global__ void k_view_setup(ViewSetupArgs a) { view_setup_body(a, grid_blk()); }
 
-__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t value, int64_t count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = value;
+__device__ __forceinline__ void fill_body(const FillArgs& a, Blk b) {
+  for (int64_t i = (int64_t)b.id * kBlock + threadIdx.x; i < a.count; i += (int64_t)b.n * kBlock) a.p[i] = a.value;
 }
+__global__ __launch_bounds__(kBlock) void k_fill_u32(FillArgs a) { fill_body(a, grid_blk()); }
 
 // Folds the G per-block partials of view v (every thread of the block takes part).  With kpart: the maximum squared distance, stored as the key
 // bits(sqrt(max)) << 32 (0 if the frustum is empty).  With cpart: the counts (sum; also to
 // counts_dev when non-NULL), the kept ratio eta = n_mask / n of Eq. (4) (to eta_dev when
 // non-NULL; binary32 quotient of the counts converted to binary32) and the lowest index at d_max
 // (min), which completes the low half of that key.
-__device__ void fold_view(int v, const unsigned long long* __restrict__ kpart, const uint32_t* __restrict__ cpart,
+__device__ __forceinline__ void fold_view(int v, const unsigned long long* __restrict__ kpart, const uint32_t* __restrict__ cpart,
                           int G, int V, int64_t n, unsigned long long* __restrict__ dmax_key,
                           unsigned long long* __restrict__ counts, int64_t* __restrict__ counts_dev,
                           float* __restrict__ eta_dev) {
@@ -120,14 +123,10 @@ __device__ void fold_view(int v, const unsigned long long* __restrict__ kpart, c
 }
 
 // Block v folds view v.
-__global__ __launch_bounds__(kBlock) void k_reduce_partials(const unsigned long long* __restrict__ kpart,
-                                                            const uint32_t* __restrict__ cpart, int G, int V,
-                                                            unsigned long long* __restrict__ dmax_key,
-                                                            unsigned long long* __restrict__ counts,
-                                                            int64_t* __restrict__ counts_dev, int64_t n,
-                                                            float* __restrict__ eta_dev) {
-  fold_view(blockIdx.x, kpart, cpart, G, V, n, dmax_key, counts, counts_dev, eta_dev);
+__device__ __forceinline__ void fold_body(const FoldArgs& a, Blk b) {
+  fold_view((int)b.id, a.kpart, a.cpart, a.G, a.V, a.n, a.dmax_key, a.counts, a.counts_dev, a.eta_dev);
 }
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(FoldArgs a) { fold_body(a, grid_blk()); }
 
 // Per-block partials instead of global atomics: block b owns the contiguous chunk
 // [b*C, (b+1)*C) of Gaussians and writes one partial per view (the frustum-max key, the three
@@ -140,14 +139,18 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const unsigned long 
 // into the key bits(d_max) << 32 (d_max its correctly rounded root, the largest distance),
 // and k_classify finds the lowest index at that distance, which completes the key with
 // 2^32 - 1 - index (so that ties resolve to the lowest index).
-__global__ __launch_bounds__(kBlock) void k_frustum_max(
-    const float* __restrict__ mean, int64_t n, const DevView* __restrict__ views, int V,
-    float near_z, unsigned long long* __restrict__ part /* [G][V] */) {
+__device__ __forceinline__ void frustum_max_body(const FrustumArgs& a, Blk b) {
   constexpr int kVG = 8;      // views per group (keys held in registers)
   constexpr int kItems = 8;   // Gaussians per thread per round, loaded before any is used
   __shared__ unsigned long long sm[kVG][4];
+  const float* __restrict__ mean = a.mean;
+  const int64_t n = a.n;
+  const DevView* __restrict__ views = a.views;
+  const int V = a.V;
+  const float near_z = a.near_z;
+  unsigned long long* __restrict__ part = a.part;   // [G][V]
   int64_t lo, hi;
-  block_chunk(n, lo, hi);
+  block_chunk(n, b, lo, hi);
   for (int v0 = 0; v0 < V; v0 += kVG) {
     const int vn = V - v0 < kVG ? V - v0 : kVG;
     uint32_t key[kVG];
@@ -194,11 +197,12 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
       const int vv = threadIdx.x;
       unsigned long long m = sm[vv][0];
       for (int w = 1; w < 4; ++w) m = sm[vv][w] > m ? sm[vv][w] : m;
-      part[(int64_t)blockIdx.x * V + v0 + vv] = m;
+      part[(int64_t)b.id * V + v0 + vv] = m;
     }
     __syncthreads();
   }
 }
+__global__ __launch_bounds__(kBlock) void k_frustum_max(FrustumArgs a) { frustum_max_body(a, grid_blk()); }
 
 // Pass 1 over every Gaussian (block b owns the chunk [b*C, (b+1)*C)): per view the frustum
 // flag, Eq. (2) and the LoD mask (alpha'' and the F/M flags written for every (view,
@@ -206,20 +210,26 @@ __global__ __launch_bounds__(kBlock) void k_frustum_max(
 // frustum and kept by its mask appended to the block's segment of the work list (order
 // within a segment is arbitrary).  Outside those, nothing else is computed, so the heavy
 // pass below runs on full waves instead of the ~40% of lanes a whole-scene pass keeps busy.
+// scnt: LDS of 3 V words ([V][3]: F count, M count, lowest index at d_max).
 template <bool kWrite>
-__global__ __launch_bounds__(kBlock) void k_classify(
-    clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,
-    const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][4] */,
-    uint8_t* __restrict__ flags_out, float* __restrict__ alpha_out,
-    uint32_t* __restrict__ list /* [n] */, uint32_t* __restrict__ lcount /* [G] */) {
-  extern __shared__ uint32_t scnt[];   // [V][3]: F count, M count, lowest index at d_max
+__device__ __forceinline__ void classify_body(const ClassifyArgs& a, Blk b, uint32_t* scnt) {
   __shared__ uint32_t sbase;
+  const clod_scene& sc = a.sc;
+  const DevView* __restrict__ views = a.views;
+  const int V = a.V;
+  const clod_params& prm = a.prm;
+  const unsigned long long* __restrict__ dmax_key = a.dmax_key;
+  uint32_t* __restrict__ cpart = a.cpart;   // [G][V][4]
+  uint8_t* __restrict__ flags_out = a.flags;
+  float* __restrict__ alpha_out = a.alpha;
+  uint32_t* __restrict__ list = a.list;       // [n]
+  uint32_t* __restrict__ lcount = a.lcount;   // [G]
   const int64_t n = sc.n;
   for (int j = threadIdx.x; j < 3 * V; j += kBlock) scnt[j] = j % 3 == 2 ? 0xFFFFFFFFu : 0u;
   if (threadIdx.x == 0) sbase = 0;
   __syncthreads();
   int64_t lo, hi;
-  block_chunk(n, lo, hi);
+  block_chunk(n, b, lo, hi);
   const uint64_t lt = lanemask_lt();
   const int64_t iters = (hi - lo + kBlock - 1) / kBlock;
   // Software pipelined: the next round's parameters are loaded before this round's views are
@@ -279,11 +289,16 @@ __global__ __launch_bounds__(kBlock) void k_classify(
   }
   __syncthreads();
   for (int j = threadIdx.x; j < V; j += kBlock) {
-    cpart[((int64_t)blockIdx.x * V + j) * 4 + 0] = scnt[3 * j];
-    cpart[((int64_t)blockIdx.x * V + j) * 4 + 1] = scnt[3 * j + 1];
-    cpart[((int64_t)blockIdx.x * V + j) * 4 + 3] = scnt[3 * j + 2];
+    cpart[((int64_t)b.id * V + j) * 4 + 0] = scnt[3 * j];
+    cpart[((int64_t)b.id * V + j) * 4 + 1] = scnt[3 * j + 1];
+    cpart[((int64_t)b.id * V + j) * 4 + 3] = scnt[3 * j + 2];
   }
-  if (threadIdx.x == 0) lcount[blockIdx.x] = sbase;
+  if (threadIdx.x == 0) lcount[b.id] = sbase;
+}
+template <bool kWrite>
+__global__ __launch_bounds__(kBlock) void k_classify(ClassifyArgs a) {
+  extern __shared__ uint32_t scnt_dyn[];
+  classify_body<kWrite>(a, grid_blk(), scnt_dyn);
 }
 
 // Pass 2 over the work list (entries spread evenly over the blocks): per listed Gaussian the
@@ -291,17 +306,23 @@ __global__ __launch_bounds__(kBlock) void k_classify(
 // cull and rectangle, remembering which views render it; then the colour of each rendering
 // view is evaluated from its SH coefficients.  Records (with depth, rectangle and tiles
 // touched in their fourth quad) are written for rendered (view, Gaussian) pairs only.
+// sdyn: LDS of G + V words ([G] segment offsets, then [V] rendered counts).
 template <int DEG, bool kWriteRecords, bool kPacked>
-__device__ __forceinline__ void project_body(
-    const clod_scene& sc, const DevView* __restrict__ views, int V, const clod_params& prm,
-    const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart /* [G][V][4] */,
-    const uint32_t* __restrict__ list, const uint32_t* __restrict__ lcount, uint8_t* __restrict__ flags_out,
-    float4* __restrict__ rec) {
-  extern __shared__ uint32_t sdyn[];   // [G] segment offsets, then [V] rendered counts
+__device__ __forceinline__ void project_body(const ProjectArgs& a, Blk b, uint32_t* sdyn) {
   __shared__ uint32_t sm[4];
+  const clod_scene& sc = a.sc;
+  const DevView* __restrict__ views = a.views;
+  const int V = a.V;
+  const clod_params& prm = a.prm;
+  const unsigned long long* __restrict__ dmax_key = a.dmax_key;
+  uint32_t* __restrict__ cpart = a.cpart;   // [G][V][4]
+  const uint32_t* __restrict__ list = a.list;
+  const uint32_t* __restrict__ lcount = a.lcount;
+  uint8_t* __restrict__ flags_out = a.flags;
+  float4* __restrict__ rec = a.rec;
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t n = sc.n;
-  const int G = gridDim.x;
+  const int G = (int)b.n;
   uint32_t* soff = sdyn;
   uint32_t* scnt = sdyn + G;
   // Exclusive offsets of the G list segments and the list length: every block scans the
@@ -331,7 +352,7 @@ __device__ __forceinline__ void project_body(
   const int64_t per = (n + G - 1) / G;   // chunk length of the first pass
   const int64_t stride = (int64_t)G * kBlock;
   // Every lane of the block runs the same number of rounds (ballots stay uniform).
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < L; base += stride) {
+  for (int64_t base = (int64_t)b.id * kBlock; base < L; base += stride) {
     const int64_t e = base + threadIdx.x;
     const bool valid = e < L;
     int64_t i = 0;
@@ -463,28 +484,22 @@ __device__ __forceinline__ void project_body(
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < V; j += kBlock) cpart[((int64_t)blockIdx.x * V + j) * 4 + 2] = scnt[j];
+  for (int j = threadIdx.x; j < V; j += kBlock) cpart[((int64_t)b.id * V + j) * 4 + 2] = scnt[j];
 }
-
-#define CLOD_PROJECT_ARGS                                                                              \
-  clod_scene sc, const DevView* __restrict__ views, int V, clod_params prm,                           \
-      const unsigned long long* __restrict__ dmax_key, uint32_t* __restrict__ cpart,                  \
-      const uint32_t* __restrict__ list, const uint32_t* __restrict__ lcount,                         \
-      uint8_t* __restrict__ flags_out, float4* __restrict__ rec
 
 // Plane-major coefficients (or no records).
 template <int DEG, bool kWriteRecords>
-__global__ __launch_bounds__(kBlock) void k_project(CLOD_PROJECT_ARGS) {
-  project_body<DEG, kWriteRecords, false>(sc, views, V, prm, dmax_key, cpart, list, lcount, flags_out, rec);
+__global__ __launch_bounds__(kBlock) void k_project(ProjectArgs a) {
+  extern __shared__ uint32_t sdyn[];
+  project_body<DEG, kWriteRecords, false>(a, grid_blk(), sdyn);
 }
 
 // Packed coefficients: fits 128 registers, so four waves per SIMD hide the gather latency.
 template <int DEG>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_project_packed(
-    CLOD_PROJECT_ARGS) {
-  project_body<DEG, true, true>(sc, views, V, prm, dmax_key, cpart, list, lcount, flags_out, rec);
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_project_packed(ProjectArgs a) {
+  extern __shared__ uint32_t sdyn[];
+  project_body<DEG, true, true>(a, grid_blk(), sdyn);
 }
-#undef CLOD_PROJECT_ARGS
 
 // Budgeted LoD (a view with budget K, 0 < K < n): the K-th largest selection key, by an MSD
 // radix select over the eight bytes of the 64-bit key.  Pass p histograms byte p (from the top)
@@ -492,13 +507,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // view; alpha'' is recomputed from the scene exactly as the projection computes it), then
 // k_select_pick finds the byte value holding the wanted rank and narrows the prefix.  After
 // eight passes the prefix is the threshold key.  K >= n keeps everything (threshold 0).
-__global__ __launch_bounds__(kBlock) void k_select_hist(clod_scene sc, const DevView* __restrict__ views,
-                                                        clod_params prm,
-                                                        const unsigned long long* __restrict__ dmax_key,
-                                                        const SelState* __restrict__ state, int pass,
-                                                        uint32_t* __restrict__ hist /* [V][kSelBlocks][256] */) {
+// Block b of V * kSelBlocks: chunk b % kSelBlocks of view b / kSelBlocks.
+__device__ __forceinline__ void select_hist_body(const SelectArgs& a, Blk b) {
   __shared__ uint32_t h[256];
-  const int v = blockIdx.y;
+  const clod_scene& sc = a.sc;
+  const DevView* __restrict__ views = a.views;
+  const clod_params& prm = a.prm;
+  const unsigned long long* __restrict__ dmax_key = a.dmax_key;
+  const SelState* __restrict__ state = a.state;
+  const int pass = a.pass;
+  uint32_t* __restrict__ hist = a.hist;   // [V][kSelBlocks][256]
+  const int v = (int)(b.id / kSelBlocks);
+  const uint32_t chunk = b.id % kSelBlocks;
   const DevView& Vw = views[v];
   const int64_t n = sc.n;
   if (Vw.budget <= 0 || Vw.budget >= n) return;
@@ -508,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_select_hist(clod_scene sc, const Dev
   const unsigned long long pre = pass == 0 ? 0ull : state[v].prefix >> (shift + 8);
   const float dmax = dmax_from_key(dmax_key[v]);
   int64_t lo, hi;
-  block_chunk(n, lo, hi);
+  block_chunk(n, Blk{chunk, (uint32_t)kSelBlocks}, lo, hi);
   for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
     float ex, ey, ez;
     const float d = cam_distance(Vw, sc.mean[i], sc.mean[n + i], sc.mean[2 * n + i], ex, ey, ez);
@@ -518,14 +538,18 @@ __global__ __launch_bounds__(kBlock) void k_select_hist(clod_scene sc, const Dev
     if (pass == 0 || (key >> (shift + 8)) == pre) atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[((int64_t)v * kSelBlocks + blockIdx.x) * 256 + threadIdx.x] = h[threadIdx.x];
+  hist[((int64_t)v * kSelBlocks + chunk) * 256 + threadIdx.x] = h[threadIdx.x];
 }
+__global__ __launch_bounds__(kBlock) void k_select_hist(SelectArgs a) { select_hist_body(a, grid_blk()); }
 
-__global__ __launch_bounds__(kBlock) void k_select_pick(DevView* __restrict__ views, int64_t n, int pass,
-                                                        SelState* __restrict__ state,
-                                                        const uint32_t* __restrict__ hist) {
+__device__ __forceinline__ void select_pick_body(const SelectArgs& a, Blk b) {
   __shared__ uint32_t sm[4];
-  const int v = blockIdx.x;
+  DevView* __restrict__ views = a.views;
+  const int64_t n = a.sc.n;
+  const int pass = a.pass;
+  SelState* __restrict__ state = a.state;
+  const uint32_t* __restrict__ hist = a.hist;
+  const int v = (int)b.id;
   DevView& Vw = views[v];
   if (Vw.budget <= 0) return;
   if (Vw.budget >= n) {
@@ -557,17 +581,25 @@ __global__ __launch_bounds__(kBlock) void k_select_pick(DevView* __restrict__ vi
     if (pass == 7) Vw.mkey = np;
   }
 }
+__global__ __launch_bounds__(kBlock) void k_select_pick(SelectArgs a) { select_pick_body(a, grid_blk()); }
 
 hipError_t launch_lod_select(const clod_scene& sc, DevView* vinfo, int V, clod_params prm,
-                             const unsigned long long* dmax_key, SelState* state, uint32_t* hist, hipStream_t s) {
+                             const unsigned long long* dmax_key, SelState* state, uint32_t* hist, const Sink& out) {
   if (sc.n == 0) return hipSuccess;
   for (int pass = 0; pass < 8; ++pass) {
-    hipLaunchKernelGGL(k_select_hist, dim3(kSelBlocks, V), dim3(kBlock), 0, s, sc, (const DevView*)vinfo, prm,
-                       dmax_key, (const SelState*)state, pass, hist);
-    hipLaunchKernelGGL(k_select_pick, dim3(V), dim3(kBlock), 0, s, vinfo, sc.n, pass, state,
-                       (const uint32_t*)hist);
+    Stage h{};
+    h.kind = kStSelectHist;
+    h.items = (uint32_t)(kSelBlocks * V);
+    h.block = kBlock;
+    h.a.select = SelectArgs{sc, vinfo, V, prm, dmax_key, state, hist, pass};
+    Stage p = h;
+    p.kind = kStSelectPick;
+    p.items = (uint32_t)V;
+    hipError_t e = out.put(h);
+    if (e == hipSuccess) e = out.put(p);
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 int proj_blocks(int64_t n) {
@@ -578,76 +610,132 @@ int proj_blocks(int64_t n) {
 }
 
 hipError_t launch_view_setup(const clod_view* views_dev, int V, clod_params prm, DevView* vinfo,
-                             unsigned long long* hdr, hipStream_t s) {
-  hipLaunchKernelGGL(k_view_setup, dim3(1), dim3(64), 0, s, views_dev, V, prm, vinfo, hdr);
-  return hipGetLastError();
+                             unsigned long long* hdr, const Sink& out) {
+  Stage st{};
+  st.kind = kStViewSetup;
+  st.items = 1;
+  st.block = 64;
+  st.a.view_setup = ViewSetupArgs{views_dev, V, prm, vinfo, hdr};
+  return out.put(st);
 }
 
-hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s) {
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, const Sink& out) {
   if (count <= 0) return hipSuccess;
   int64_t g = (count + kBlock - 1) / kBlock;
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(kBlock), 0, s, p, value, count);
-  return hipGetLastError();
+  Stage st{};
+  st.kind = kStFill;
+  st.items = (uint32_t)g;
+  st.block = kBlock;
+  st.a.fill = FillArgs{p, value, count};
+  return out.put(st);
+}
+
+static Stage fold_stage(const unsigned long long* kpart, const uint32_t* cpart, int G, int V,
+                        unsigned long long* dmax_key, unsigned long long* counts, int64_t* counts_dev, int64_t n,
+                        float* eta_dev) {
+  Stage st{};
+  st.kind = kStFold;
+  st.items = (uint32_t)V;
+  st.block = kBlock;
+  st.a.fold = FoldArgs{kpart, cpart, G, V, dmax_key, counts, counts_dev, n, eta_dev};
+  return st;
 }
 
 hipError_t launch_frustum_max(const clod_scene& sc, const DevView* vinfo, int V, float near_z,
-                              unsigned long long* kpart, unsigned long long* dmax_key, hipStream_t s) {
-  if (sc.n == 0) return launch_fill_u32((uint32_t*)dmax_key, 0u, 2 * (int64_t)V, s);
+                              unsigned long long* kpart, unsigned long long* dmax_key, const Sink& out) {
+  if (sc.n == 0) return launch_fill_u32((uint32_t*)dmax_key, 0u, 2 * (int64_t)V, out);
   const int G = proj_blocks(sc.n);
-  hipLaunchKernelGGL(k_frustum_max, dim3(G), dim3(kBlock), 0, s, sc.mean, sc.n, vinfo, V, near_z, kpart);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)kpart,
-                     (const uint32_t*)nullptr, G, V, dmax_key, (unsigned long long*)nullptr, (int64_t*)nullptr,
-                     sc.n, (float*)nullptr);
-  return hipGetLastError();
+  Stage st{};
+  st.kind = kStFrustumMax;
+  st.items = (uint32_t)G;
+  st.block = kBlock;
+  st.a.frustum = FrustumArgs{sc.mean, sc.n, vinfo, V, near_z, kpart};
+  hipError_t e = out.put(st);
+  if (e == hipSuccess)
+    e = out.put(fold_stage(kpart, nullptr, G, V, dmax_key, nullptr, nullptr, sc.n, nullptr));
+  return e;
 }
 
 template <bool kWrite>
 static hipError_t project_impl(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                                unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                                int64_t* counts_dev, float* eta_dev, uint8_t* flags, float* alpha, float4* rec,
-                               uint32_t* list, uint32_t* lcount, hipStream_t s) {
+                               uint32_t* list, uint32_t* lcount, const Sink& out) {
   if (sc.n == 0) {
-    hipError_t e = launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, s);
-    if (e == hipSuccess && counts_dev) e = launch_fill_u32((uint32_t*)counts_dev, 0u, 6 * (int64_t)V, s);
-    if (e == hipSuccess && eta_dev) e = launch_fill_u32((uint32_t*)eta_dev, 0u, (int64_t)V, s);
+    hipError_t e = launch_fill_u32((uint32_t*)counts, 0u, 6 * (int64_t)V, out);
+    if (e == hipSuccess && counts_dev) e = launch_fill_u32((uint32_t*)counts_dev, 0u, 6 * (int64_t)V, out);
+    if (e == hipSuccess && eta_dev) e = launch_fill_u32((uint32_t*)eta_dev, 0u, (int64_t)V, out);
     return e;
   }
   const int G = proj_blocks(sc.n);
-  hipLaunchKernelGGL(k_classify<kWrite>, dim3(G), dim3(kBlock), (size_t)(3 * V * sizeof(uint32_t)), s, sc, vinfo,
-                     V, prm, dmax_key, cpart, flags, alpha, list, lcount);
+  Stage c{};
+  c.kind = kStClassify;
+  c.items = (uint32_t)G;
+  c.block = kBlock;
+  c.lds = (uint32_t)(3 * V * sizeof(uint32_t));
+  c.a.classify = ClassifyArgs{sc, vinfo, V, kWrite ? 1 : 0, prm, dmax_key, cpart, flags, alpha, list, lcount};
+  hipError_t e = out.put(c);
+  if (e != hipSuccess) return e;
   // Packed SH is only read when records are written.
-  const bool packed = kWrite && sc.sh_packed != nullptr;
-  auto kern = packed ? k_project_packed<3> : k_project<3, kWrite>;
-  switch (sc.sh_degree) {
-    case 0: kern = packed ? k_project_packed<0> : k_project<0, kWrite>; break;
-    case 1: kern = packed ? k_project_packed<1> : k_project<1, kWrite>; break;
-    case 2: kern = packed ? k_project_packed<2> : k_project<2, kWrite>; break;
-    default: break;
-  }
-  hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), (size_t)((G + V) * sizeof(uint32_t)), s, sc, vinfo, V, prm,
-                     (const unsigned long long*)dmax_key, cpart, (const uint32_t*)list, (const uint32_t*)lcount, flags,
-                     rec);
+  Stage p{};
+  p.kind = kStProject;
+  p.items = (uint32_t)G;
+  p.block = kBlock;
+  p.lds = (uint32_t)((G + V) * sizeof(uint32_t));
+  p.a.project = ProjectArgs{sc, vinfo, V, prm, dmax_key, cpart, list, lcount, flags, rec, kWrite ? 1 : 0,
+                            kWrite && sc.sh_packed != nullptr ? 1 : 0};
+  e = out.put(p);
+  if (e != hipSuccess) return e;
   // Counts to the workspace and the caller, and the argmax index into the d_max key.
-  hipLaunchKernelGGL(k_reduce_partials, dim3(V), dim3(kBlock), 0, s, (const unsigned long long*)nullptr,
-                     (const uint32_t*)cpart, G, V, dmax_key, counts, counts_dev, sc.n, eta_dev);
-  return hipGetLastError();
+  return out.put(fold_stage(nullptr, cpart, G, V, dmax_key, counts, counts_dev, sc.n, eta_dev));
 }
 
 hipError_t launch_project(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                           unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                           int64_t* counts_dev, float* eta_dev, uint8_t* flags, float* alpha, float4* rec,
-                          uint32_t* list, uint32_t* lcount, hipStream_t s) {
+                          uint32_t* list, uint32_t* lcount, const Sink& out) {
   return project_impl<true>(sc, vinfo, V, prm, dmax_key, cpart, counts, counts_dev, eta_dev, flags, alpha, rec, list,
-                            lcount, s);
+                            lcount, out);
 }
 
 hipError_t launch_lod_count(const clod_scene& sc, const DevView* vinfo, int V, clod_params prm,
                             unsigned long long* dmax_key, uint32_t* cpart, unsigned long long* counts,
                             int64_t* counts_dev, float* eta_dev, uint32_t* list, uint32_t* lcount,
-                            hipStream_t s) {
+                            const Sink& out) {
   return project_impl<false>(sc, vinfo, V, prm, dmax_key, cpart, counts, counts_dev, eta_dev, nullptr, nullptr,
-                             nullptr, list, lcount, s);
+                             nullptr, list, lcount, out);
+}
+
+// One kernel per stage kind of this file (the template instance the arguments select).
+hipError_t launch_project_stage(const Stage& st, hipStream_t s) {
+  const dim3 g(st.items), blk(st.block);
+  switch (st.kind) {
+    case kStViewSetup: hipLaunchKernelGGL(k_view_setup, g, blk, 0, s, st.a.view_setup); break;
+    case kStFill: hipLaunchKernelGGL(k_fill_u32, g, blk, 0, s, st.a.fill); break;
+    case kStFrustumMax: hipLaunchKernelGGL(k_frustum_max, g, blk, 0, s, st.a.frustum); break;
+    case kStFold: hipLaunchKernelGGL(k_reduce_partials, g, blk, 0, s, st.a.fold); break;
+    case kStClassify:
+      if (st.a.classify.write) hipLaunchKernelGGL(k_classify<true>, g, blk, st.lds, s, st.a.classify);
+      else hipLaunchKernelGGL(k_classify<false>, g, blk, st.lds, s, st.a.classify);
+      break;
+    case kStProject: {
+      const ProjectArgs& a = st.a.project;
+      auto kern = a.packed ? k_project_packed<3> : (a.write ? k_project<3, true> : k_project<3, false>);
+      switch (a.sc.sh_degree) {
+        case 0: kern = a.packed ? k_project_packed<0> : (a.write ? k_project<0, true> : k_project<0, false>); break;
+        case 1: kern = a.packed ? k_project_packed<1> : (a.write ? k_project<1, true> : k_project<1, false>); break;
+        case 2: kern = a.packed ? k_project_packed<2> : (a.write ? k_project<2, true> : k_project<2, false>); break;
+        default: break;
+      }
+      hipLaunchKernelGGL(kern, g, blk, st.lds, s, a);
+      break;
+    }
+    case kStSelectHist: hipLaunchKernelGGL(k_select_hist, g, blk, 0, s, st.a.select); break;
+    case kStSelectPick: hipLaunchKernelGGL(k_select_pick, g, blk, 0, s, st.a.select); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace clod

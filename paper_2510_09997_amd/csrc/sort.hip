@@ -76,10 +76,13 @@ __device__ __forceinline__ uint32_t rendered_mask(const uint8_t* __restrict__ fl
 // Single block: exclusive scan of the per-chunk rendered counts; R and the overflow flag (R
 // above the capacity) to the header.  D is not known yet: k_emit_partials stores it.  Also
 // clears the counters of the tile ordering (tord).
-__global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__ partR, int nparts,
-                                                          unsigned long long* __restrict__ hdr, int64_t cap,
-                                                          uint32_t* __restrict__ tord) {
+__device__ __forceinline__ void scan_partials_body(const ScanPartialsArgs& a, Blk) {
   __shared__ uint32_t sm[4];
+  uint32_t* __restrict__ partR = a.partR;
+  const int nparts = a.nparts;
+  unsigned long long* __restrict__ hdr = a.hdr;
+  const int64_t cap = a.cap;
+  uint32_t* __restrict__ tord = a.tord;
   if (threadIdx.x < kTileOrderWords) tord[threadIdx.x] = 0u;
   uint32_t carry = 0;
   // kScanItems consecutive partials per thread per round (one block scan per round).
@@ -107,37 +110,41 @@ __global__ __launch_bounds__(kBlock) void k_scan_partials(uint32_t* __restrict__
     hdr[kHdrRend] = carry;
   }
 }
+__global__ __launch_bounds__(kBlock) void k_scan_partials(ScanPartialsArgs a) { scan_partials_body(a, grid_blk()); }
 
 // Per chunk of kScanChunk records: the number of rendered records.  Also clears the per-tile
 // ranges (2 * tiles words) for k_ranges, which writes only the non-empty tiles.
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint8_t* __restrict__ flags, int64_t count,
-                                                        uint32_t* __restrict__ partR, uint32_t* __restrict__ ranges,
-                                                        int64_t range_words) {
+__device__ __forceinline__ void scan_reduce_body(const ScanReduceArgs& a, Blk b) {
   __shared__ uint32_t sm[4];
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < range_words; q += (int64_t)gridDim.x * kBlock)
-    ranges[q] = 0u;
-  const int64_t j0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  const uint32_t r = wave_sum((uint32_t)__popc(rendered_mask(flags, count, j0)));
+  for (int64_t q = (int64_t)b.id * kBlock + threadIdx.x; q < a.range_words; q += (int64_t)b.n * kBlock)
+    a.ranges[q] = 0u;
+  const int64_t j0 = (int64_t)b.id * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  const uint32_t r = wave_sum((uint32_t)__popc(rendered_mask(a.flags, a.count, j0)));
   if (lane_id() == 0) sm[threadIdx.x >> 6] = r;
   __syncthreads();
-  if (threadIdx.x == 0) partR[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+  if (threadIdx.x == 0) a.partR[b.id] = sm[0] + sm[1] + sm[2] + sm[3];
 }
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(ScanReduceArgs a) { scan_reduce_body(a, grid_blk()); }
 
 // Rendered records of the chunk, in index order, to [partR[b], ...): key bits(depth), value f.
 // The depth gathers (one per rendered record, from the record's fourth quad) are issued right
 // after the flag load, so their latency overlaps the block scan; keys and indices are then
 // placed in LDS so the stores are coalesced.
-__global__ __launch_bounds__(kBlock) void k_compact(const uint8_t* __restrict__ flags, int64_t count,
-                                                    const uint32_t* __restrict__ partR,
-                                                    const float4* __restrict__ rec,
-                                                    const unsigned long long* __restrict__ hdr,
-                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
+struct CompactLds {
+  uint32_t sk[kScanChunk], sf[kScanChunk];
+};
+__device__ __forceinline__ void compact_body(const CompactArgs& a, Blk b, CompactLds& S) {
   __shared__ uint32_t sm[4];
-  __shared__ uint32_t sk[kScanChunk];
-  __shared__ uint32_t sf[kScanChunk];
-  if (hdr[kHdrOverflow] != 0ull) return;
+  uint32_t* sk = S.sk;
+  uint32_t* sf = S.sf;
+  const uint8_t* __restrict__ flags = a.flags;
+  const int64_t count = a.count;
+  const float4* __restrict__ rec = a.rec;
+  uint32_t* __restrict__ kout = a.kout;
+  uint32_t* __restrict__ vout = a.vout;
+  if (a.hdr[kHdrOverflow] != 0ull) return;
   const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const int64_t base = (int64_t)b.id * kScanChunk;
   const int64_t j0 = base + (int64_t)t * kScanItems;
   const uint32_t m = rendered_mask(flags, count, j0);
   uint32_t dk[kScanItems];
@@ -155,11 +162,15 @@ __global__ __launch_bounds__(kBlock) void k_compact(const uint8_t* __restrict__ 
     }
   }
   __syncthreads();
-  const int64_t out0 = (int64_t)partR[blockIdx.x];
+  const int64_t out0 = (int64_t)a.partR[b.id];
   for (uint32_t q = (uint32_t)t; q < total; q += kBlock) {
     kout[out0 + q] = sk[q];
     vout[out0 + q] = sf[q];
   }
+}
+__global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
+  __shared__ CompactLds S;
+  compact_body(a, grid_blk(), S);
 }
 
 // ---------------------------------------------------------------------------- radix sort
@@ -188,21 +199,26 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, uint64_t active) {
   return m;
 }
 
-__global__ __launch_bounds__(kBlock) void k_radix_upsweep(const uint32_t* __restrict__ keys,
-                                                          const unsigned long long* __restrict__ hdr, int cw,
-                                                          int G, int shift, uint32_t* __restrict__ hist) {
-  // Digit counts per 16-lane group of each wave (16 copies, rows padded to 257 words): lanes
-  // of one atomic instruction that share a digit serialise on its address, and high digits
-  // take few values, so splitting the wave four ways shortens those chains.
-  __shared__ uint32_t cnt[16][257];
+// Digit counts per 16-lane group of each wave (16 copies, rows padded to 257 words): lanes
+// of one atomic instruction that share a digit serialise on its address, and high digits
+// take few values, so splitting the wave four ways shortens those chains.
+struct UpsweepLds {
+  uint32_t cnt[16][257];
+};
+__device__ __forceinline__ void radix_upsweep_body(const RadixArgs& a, Blk b, UpsweepLds& S) {
+  auto& cnt = S.cnt;
+  const uint32_t* __restrict__ keys = a.kin;
+  const unsigned long long* __restrict__ hdr = a.hdr;
+  const int G = a.G, shift = a.shift;
+  uint32_t* __restrict__ hist = a.hist;
   if (hdr[kHdrOverflow]) return;
-  const int64_t N = (int64_t)hdr[cw];
+  const int64_t N = (int64_t)hdr[a.cw];
   const int t = threadIdx.x;
   const int copy = t >> 4;
   for (int j = t; j < 16 * 257; j += kBlock) (&cnt[0][0])[j] = 0;
   __syncthreads();
   int64_t lo, hi;
-  sort_chunk(N, G, blockIdx.x, lo, hi);
+  sort_chunk(N, G, (int)b.id, lo, hi);
   // kSortItems keys per thread per step, all loads issued before any is used.
   for (int64_t base = lo; base < hi; base += kSortTile) {
     uint32_t d8[kSortItems];
@@ -219,16 +235,21 @@ __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const uint32_t* __rest
   uint32_t total = 0;
 #pragma unroll
   for (int c = 0; c < 16; ++c) total += cnt[c][t];
-  hist[(int64_t)t * G + blockIdx.x] = total;
+  hist[(int64_t)t * G + b.id] = total;
+}
+__global__ __launch_bounds__(kBlock) void k_radix_upsweep(RadixArgs a) {
+  __shared__ UpsweepLds S;
+  radix_upsweep_body(a, grid_blk(), S);
 }
 
 // Block d: exclusive scan of digit d's per-block counts hist[d*G .. d*G+G) in place, and
 // the digit total in hist[256*G + d].
-__global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t* __restrict__ hist, int G,
-                                                             const unsigned long long* __restrict__ hdr) {
+__device__ __forceinline__ void radix_digit_scan_body(const RadixArgs& a, Blk b) {
   __shared__ uint32_t sm[4];
-  if (hdr[kHdrOverflow]) return;
-  uint32_t* h = hist + (int64_t)blockIdx.x * G;
+  uint32_t* __restrict__ hist = a.hist;
+  const int G = a.G;
+  if (a.hdr[kHdrOverflow]) return;
+  uint32_t* h = hist + (int64_t)b.id * G;
   uint32_t carry = 0;
   for (int base = 0; base < G; base += kBlock) {
     const int j = base + threadIdx.x;
@@ -238,30 +259,42 @@ __global__ __launch_bounds__(kBlock) void k_radix_digit_scan(uint32_t* __restric
     if (j < G) h[j] = carry + ex;
     carry += tot;
   }
-  if (threadIdx.x == 0) hist[(int64_t)256 * G + blockIdx.x] = carry;
+  if (threadIdx.x == 0) hist[(int64_t)256 * G + b.id] = carry;
 }
+__global__ __launch_bounds__(kBlock) void k_radix_digit_scan(RadixArgs a) { radix_digit_scan_body(a, grid_blk()); }
 
-__global__ __launch_bounds__(kBlock) void k_radix_downsweep(
-    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
-    uint32_t* __restrict__ vout, const uint32_t* __restrict__ hist, const unsigned long long* __restrict__ hdr,
-    int cw, int G, int shift) {
-  __shared__ uint32_t running[256];      // global output position of the next key per digit
-  __shared__ uint32_t wcnt[4][256];      // per-wave digit counts within the tile
-  __shared__ uint32_t tstart[256];       // tile-local start of each digit
+struct DownsweepLds {
+  uint32_t running[256];      // global output position of the next key per digit
+  uint32_t wcnt[4][256];      // per-wave digit counts within the tile
+  uint32_t tstart[256];       // tile-local start of each digit
+  uint32_t skey[kSortTile];
+  uint32_t sval[kSortTile];
+};
+__device__ __forceinline__ void radix_downsweep_body(const RadixArgs& a, Blk b, DownsweepLds& S) {
   __shared__ uint32_t sm[4];
-  __shared__ uint32_t skey[kSortTile];
-  __shared__ uint32_t sval[kSortTile];
+  auto& running = S.running;
+  auto& wcnt = S.wcnt;
+  auto& tstart = S.tstart;
+  auto& skey = S.skey;
+  auto& sval = S.sval;
+  const uint32_t* __restrict__ kin = a.kin;
+  const uint32_t* __restrict__ vin = a.vin;
+  uint32_t* __restrict__ kout = a.kout;
+  uint32_t* __restrict__ vout = a.vout;
+  const uint32_t* __restrict__ hist = a.hist;
+  const unsigned long long* __restrict__ hdr = a.hdr;
+  const int G = a.G, shift = a.shift;
   if (hdr[kHdrOverflow]) return;
-  const int64_t N = (int64_t)hdr[cw];
+  const int64_t N = (int64_t)hdr[a.cw];
   int64_t lo, hi;
-  sort_chunk(N, G, blockIdx.x, lo, hi);
+  sort_chunk(N, G, (int)b.id, lo, hi);
   const int t = threadIdx.x;
   const int wave = t >> 6;
   const uint32_t lane = lane_id();
   {
     uint32_t tall;
     const uint32_t digit_base = block_exclusive_scan(hist[(int64_t)256 * G + t], sm, tall);
-    running[t] = digit_base + hist[(int64_t)t * G + blockIdx.x];
+    running[t] = digit_base + hist[(int64_t)t * G + b.id];
   }
   const uint64_t lt = lanemask_lt();
   for (int64_t base = lo; base < hi; base += kSortTile) {
@@ -332,17 +365,30 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(
     __syncthreads();
   }
 }
+__global__ __launch_bounds__(kBlock) void k_radix_downsweep(RadixArgs a) {
+  __shared__ DownsweepLds S;
+  radix_downsweep_body(a, grid_blk(), S);
+}
 
-static void radix_passes(const unsigned long long* hdr, int cw, int G, int first_shift, int passes,
-                         uint32_t* const k[2], uint32_t* const v[2], int src0, uint32_t* hist, hipStream_t s) {
+static hipError_t radix_passes(const unsigned long long* hdr, int cw, int G, int first_shift, int passes,
+                               uint32_t* const k[2], uint32_t* const v[2], int src0, uint32_t* hist, const Sink& out) {
   for (int p = 0; p < passes; ++p) {
     const int src = (src0 + p) & 1, dst = src ^ 1;
-    const int shift = first_shift + 8 * p;
-    hipLaunchKernelGGL(k_radix_upsweep, dim3(G), dim3(kBlock), 0, s, k[src], hdr, cw, G, shift, hist);
-    hipLaunchKernelGGL(k_radix_digit_scan, dim3(256), dim3(kBlock), 0, s, hist, G, hdr);
-    hipLaunchKernelGGL(k_radix_downsweep, dim3(G), dim3(kBlock), 0, s, k[src], v[src], k[dst], v[dst],
-                       hist, hdr, cw, G, shift);
+    Stage st{};
+    st.block = kBlock;
+    st.a.radix = RadixArgs{k[src], v[src], k[dst], v[dst], hist, hdr, cw, G, first_shift + 8 * p};
+    st.kind = kStRadixUp;
+    st.items = (uint32_t)G;
+    hipError_t e = out.put(st);
+    st.kind = kStRadixScan;
+    st.items = 256;
+    if (e == hipSuccess) e = out.put(st);
+    st.kind = kStRadixDown;
+    st.items = (uint32_t)G;
+    if (e == hipSuccess) e = out.put(st);
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------- step 3: ordered emission
@@ -353,10 +399,12 @@ __device__ __forceinline__ uint32_t rec_tiles(const float4* __restrict__ rec, ui
 
 // Single block: D (summed in 64 bits) and the overflow flag (D above the capacity) to the
 // header, and, unless overflowed, the exclusive scan of the chunk totals in place.
-__global__ __launch_bounds__(kBlock) void k_emit_partials(uint32_t* __restrict__ partE,
-                                                          unsigned long long* __restrict__ hdr, int nb,
-                                                          int64_t cap) {
+__device__ __forceinline__ void emit_partials_body(const EmitPartialsArgs& a, Blk) {
   __shared__ unsigned long long sm[4];
+  uint32_t* __restrict__ partE = a.partE;
+  unsigned long long* __restrict__ hdr = a.hdr;
+  const int nb = a.nb;
+  const int64_t cap = a.cap;
   const bool over = hdr[kHdrOverflow] != 0ull;
   const int nparts = over ? nb : (int)(((int64_t)hdr[kHdrRend] + kScanChunk - 1) / kScanChunk);
   const uint32_t lane = lane_id();
@@ -385,6 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_partials(uint32_t* __restrict__
     if ((int64_t)carry > cap) hdr[kHdrOverflow] = 1ull;
   }
 }
+__global__ __launch_bounds__(kBlock) void k_emit_partials(EmitPartialsArgs a) { emit_partials_body(a, grid_blk()); }
 
 // Per chunk of the depth-sorted records: tile pairs of the chunk (saturated at 2^32 - 1,
 // which only a total far beyond any capacity reaches); the gathered counts are also stored in
@@ -392,15 +441,17 @@ __global__ __launch_bounds__(kBlock) void k_emit_partials(uint32_t* __restrict__
 // (the only way the overflow flag can be set at this point) the records were never sorted;
 // the pair count is then summed over chunk b of all records instead, so that D is still
 // reported.
-__global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restrict__ sorted_f,
-                                                        const float4* __restrict__ rec,
-                                                        const uint8_t* __restrict__ flags, int64_t count,
-                                                        const unsigned long long* __restrict__ hdr,
-                                                        uint32_t* __restrict__ partE, uint32_t* __restrict__ tsorted) {
+__device__ __forceinline__ void emit_reduce_body(const EmitReduceArgs& a, Blk b) {
   __shared__ unsigned long long sm[4];
+  const uint32_t* __restrict__ sorted_f = a.sorted_f;
+  const float4* __restrict__ rec = a.rec;
+  const uint8_t* __restrict__ flags = a.flags;
+  const int64_t count = a.count;
+  const unsigned long long* __restrict__ hdr = a.hdr;
+  uint32_t* __restrict__ tsorted = a.tsorted;
   const bool over = hdr[kHdrOverflow] != 0ull;
   const int64_t R = (int64_t)hdr[kHdrRend];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const int64_t base = (int64_t)b.id * kScanChunk;
   if (!over && base >= R) return;
   unsigned long long s = 0;
   if (!over) {
@@ -424,23 +475,28 @@ __global__ __launch_bounds__(kBlock) void k_emit_reduce(const uint32_t* __restri
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned long long c = sm[0] + sm[1] + sm[2] + sm[3];
-    partE[blockIdx.x] = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
+    a.partE[b.id] = c > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)c;
   }
 }
+__global__ __launch_bounds__(kBlock) void k_emit_reduce(EmitReduceArgs a) { emit_reduce_body(a, grid_blk()); }
 
 // Per chunk of the depth-sorted records: each record's first output position (the global
 // exclusive scan of their tile counts, over the R positions of the record keys, which the
 // sort no longer needs), and for every output chunk of kEmitTile pairs the record that owns
 // its first position.
-__global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restrict__ tsorted,
-                                                         const uint32_t* __restrict__ partE,
-                                                         const unsigned long long* __restrict__ hdr,
-                                                         uint32_t* __restrict__ eoff, uint32_t* __restrict__ owner) {
+struct OffsetsLds {
+  uint32_t loff[kScanChunk];
+};
+__device__ __forceinline__ void emit_offsets_body(const EmitOffsetsArgs& a, Blk b, OffsetsLds& S) {
   __shared__ uint32_t sm[4];
-  __shared__ uint32_t loff[kScanChunk];
+  uint32_t* loff = S.loff;
+  const uint32_t* __restrict__ tsorted = a.tsorted;
+  const unsigned long long* __restrict__ hdr = a.hdr;
+  uint32_t* __restrict__ eoff = a.eoff;
+  uint32_t* __restrict__ owner = a.owner;
   if (hdr[kHdrOverflow] != 0ull) return;
   const int64_t R = (int64_t)hdr[kHdrRend];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  const int64_t base = (int64_t)b.id * kScanChunk;
   if (base >= R) return;
   const int t = threadIdx.x;
 #pragma unroll
@@ -450,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restr
   }
   uint32_t loc[kScanItems];
   const uint32_t total = chunk_offsets(loff, sm, loc);
-  const uint32_t cb = partE[blockIdx.x];
+  const uint32_t cb = a.partE[b.id];
   for (int i = t; i < kScanChunk; i += kBlock) {
     const int64_t j = base + i;
     if (j >= R) break;
@@ -459,6 +515,10 @@ __global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restr
     eoff[j] = first;
     for (uint32_t q = (first + kEmitTile - 1) / kEmitTile; q * (uint64_t)kEmitTile < end; ++q) owner[q] = (uint32_t)j;
   }
+}
+__global__ __launch_bounds__(kBlock) void k_emit_offsets(EmitOffsetsArgs a) {
+  __shared__ OffsetsLds S;
+  emit_offsets_body(a, grid_blk(), S);
 }
 
 // Output chunk q (pairs [q*M, q*M + M), M = kEmitTile) is produced by the records between
@@ -470,23 +530,34 @@ __global__ __launch_bounds__(kBlock) void k_emit_offsets(const uint32_t* __restr
 // order.  Chunks are equal-sized whatever the rectangle sizes, and every store is coalesced.
 constexpr int kEmitPer = kEmitTile / kBlock;   // consecutive pairs per thread
 static_assert(kEmitPer == 8, "the stores below write eight pairs per thread");
-__global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ sorted_f,
-                                                 const uint32_t* __restrict__ eoff,
-                                                 const uint32_t* __restrict__ owner,
-                                                 const float4* __restrict__ rec, const DevView* __restrict__ views,
-                                                 int64_t n, const unsigned long long* __restrict__ hdr,
-                                                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout) {
-  __shared__ uint32_t se[kEmitTile + 1];
-  __shared__ uint32_t sf[kEmitTile + 1];
-  __shared__ uint32_t sb[kEmitTile + 1];   // tile id of the rectangle's first tile
-  __shared__ uint32_t sw[kEmitTile + 1];   // width | tiles_x << 16
-  __shared__ float sr[kEmitTile + 1];      // 1 / width
+struct EmitLds {
+  uint32_t se[kEmitTile + 1];
+  uint32_t sf[kEmitTile + 1];
+  uint32_t sb[kEmitTile + 1];   // tile id of the rectangle's first tile
+  uint32_t sw[kEmitTile + 1];   // width | tiles_x << 16
+  float sr[kEmitTile + 1];      // 1 / width
+};
+__device__ __forceinline__ void emit_body(const EmitArgs& a, Blk b, EmitLds& S) {
+  auto& se = S.se;
+  auto& sf = S.sf;
+  auto& sb = S.sb;
+  auto& sw = S.sw;
+  auto& sr = S.sr;
+  const uint32_t* __restrict__ sorted_f = a.sorted_f;
+  const uint32_t* __restrict__ eoff = a.eoff;
+  const uint32_t* __restrict__ owner = a.owner;
+  const float4* __restrict__ rec = a.rec;
+  const DevView* __restrict__ views = a.views;
+  const int64_t n = a.n;
+  const unsigned long long* __restrict__ hdr = a.hdr;
+  uint32_t* __restrict__ kout = a.kout;
+  uint32_t* __restrict__ vout = a.vout;
   if (hdr[kHdrOverflow] != 0ull) return;
   const int64_t R = (int64_t)hdr[kHdrRend];
   const int64_t D = (int64_t)hdr[kHdrDup];
   const int64_t nch = (D + kEmitTile - 1) / kEmitTile;
   const uint32_t nn = (uint32_t)n;
-  for (int64_t q = blockIdx.x; q < nch; q += gridDim.x) {
+  for (int64_t q = b.id; q < nch; q += b.n) {
     const int64_t k0 = owner[q];
     const int64_t k1 = q + 1 < nch ? (int64_t)owner[q + 1] : R - 1;
     int cnt = (int)(k1 - k0 + 1);
@@ -560,6 +631,10 @@ __global__ __launch_bounds__(kBlock) void k_emit(const uint32_t* __restrict__ so
     __syncthreads();
   }
 }
+__global__ __launch_bounds__(kBlock) void k_emit(EmitArgs a) {
+  __shared__ EmitLds S;
+  emit_body(a, grid_blk(), S);
+}
 
 int tile_passes(uint32_t tiles_total) {
   int tb = 0;
@@ -570,7 +645,7 @@ int tile_passes(uint32_t tiles_total) {
 
 int sorted_buffer(uint32_t tiles_total) { return (tile_passes(tiles_total) & 1) ? 0 : 1; }
 
-hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, hipStream_t s) {
+hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* dup, const Sink& out) {
   char* w = (char*)ws;
   char* dp = (char*)dup;
   unsigned long long* hdr = (unsigned long long*)(w + L.hdr);
@@ -581,52 +656,64 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
   uint32_t* ranges = (uint32_t*)(w + L.ranges);
   uint32_t* tord = (uint32_t*)(w + L.tord);
   if (nb == 0) {
-    hipError_t e = launch_fill_u32((uint32_t*)hdr, 0u, 2 * kHdrWords, s);
-    if (e == hipSuccess) e = launch_fill_u32(ranges, 0u, 2 * (int64_t)L.tiles_total, s);
-    if (e == hipSuccess) e = launch_fill_u32(tord, 0u, kTileOrderWords, s);
+    hipError_t e = launch_fill_u32((uint32_t*)hdr, 0u, 2 * kHdrWords, out);
+    if (e == hipSuccess) e = launch_fill_u32(ranges, 0u, 2 * (int64_t)L.tiles_total, out);
+    if (e == hipSuccess) e = launch_fill_u32(tord, 0u, kTileOrderWords, out);
     return e;
   }
   uint32_t* partR = (uint32_t*)(w + L.scan_part);
   uint32_t* partE = partR + (nb + 1);
   const uint8_t* flags = (const uint8_t*)(w + L.flags);
+  const float4* rec = (const float4*)(w + L.rec);
   const int G = sort_blocks(D.cap);
+  Stage st{};
+  st.block = kBlock;
+  hipError_t e = hipSuccess;
+  auto put = [&](int32_t kind, int64_t items) {
+    st.kind = kind;
+    st.items = (uint32_t)items;
+    if (e == hipSuccess) e = out.put(st);
+  };
   // 1. R and its overflow; compaction of the rendered records into buffer 0.
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, flags, L.VN, partR, ranges,
-                     2 * (int64_t)L.tiles_total);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kBlock), 0, s, partR, nb, hdr, D.cap, tord);
-  hipLaunchKernelGGL(k_compact, dim3(nb), dim3(kBlock), 0, s, flags, L.VN, (const uint32_t*)partR,
-                     (const float4*)(w + L.rec), (const unsigned long long*)hdr, k[0], v[0]);
+  st.a.scan_reduce = ScanReduceArgs{flags, L.VN, partR, ranges, 2 * (int64_t)L.tiles_total};
+  put(kStScanReduce, nb);
+  st.a.scan_partials = ScanPartialsArgs{partR, nb, hdr, D.cap, tord};
+  put(kStScanPartials, 1);
+  st.a.compact = CompactArgs{flags, L.VN, (const uint32_t*)partR, rec, (const unsigned long long*)hdr, k[0], v[0]};
+  put(kStCompact, nb);
   // 2. depth sort of the R records: 4 passes, back in buffer 0.
-  radix_passes(hdr, kHdrRend, G, 0, 4, k, v, 0, hist, s);
+  if (e == hipSuccess) e = radix_passes(hdr, kHdrRend, G, 0, 4, k, v, 0, hist, out);
   // 3. emission in depth order into buffer 1.
   // The emission output buffer 1 holds the sorted tile counts until k_emit overwrites it.
-  hipLaunchKernelGGL(k_emit_reduce, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)v[0], (const float4*)(w + L.rec),
-                     flags, L.VN, (const unsigned long long*)hdr, partE, k[1]);
-  hipLaunchKernelGGL(k_emit_partials, dim3(1), dim3(kBlock), 0, s, partE, hdr, nb, D.cap);
+  st.a.emit_reduce = EmitReduceArgs{(const uint32_t*)v[0], rec, flags, L.VN, (const unsigned long long*)hdr, partE, k[1]};
+  put(kStEmitReduce, nb);
+  st.a.emit_partials = EmitPartialsArgs{partE, hdr, nb, D.cap};
+  put(kStEmitPartials, 1);
   uint32_t* owner = (uint32_t*)(dp + D.owner);
-  hipLaunchKernelGGL(k_emit_offsets, dim3(nb), dim3(kBlock), 0, s, (const uint32_t*)k[1],
-                     (const uint32_t*)partE, (const unsigned long long*)hdr, k[0], owner);
+  st.a.emit_offsets = EmitOffsetsArgs{(const uint32_t*)k[1], (const uint32_t*)partE, (const unsigned long long*)hdr,
+                                      k[0], owner};
+  put(kStEmitOffsets, nb);
   int64_t ge = (D.cap + kEmitTile - 1) / kEmitTile;
   if (ge > 4096) ge = 4096;
   if (ge < 1) ge = 1;
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)ge), dim3(kBlock), 0, s, (const uint32_t*)v[0], (const uint32_t*)k[0],
-                     (const uint32_t*)owner, (const float4*)(w + L.rec), (const DevView*)(w + L.vinfo), L.n,
-                     (const unsigned long long*)hdr, k[1], v[1]);
+  st.a.emit = EmitArgs{(const uint32_t*)v[0], (const uint32_t*)k[0], (const uint32_t*)owner, rec,
+                       (const DevView*)(w + L.vinfo), L.n, (const unsigned long long*)hdr, k[1], v[1]};
+  put(kStEmit, ge);
   // 4. stable sort of the D pairs by tile id.
-  radix_passes(hdr, kHdrDup, G, 0, tile_passes(L.tiles_total), k, v, 1, hist, s);
-  return hipGetLastError();
+  if (e == hipSuccess) e = radix_passes(hdr, kHdrDup, G, 0, tile_passes(L.tiles_total), k, v, 1, hist, out);
+  return e;
 }
 
 // ---------------------------------------------------------------------------- ranges
-__global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ keys,
-                                                   const unsigned long long* __restrict__ hdr,
-                                                   uint32_t tiles_total, uint2* __restrict__ ranges) {
+__device__ __forceinline__ void ranges_body(const RangesArgs& a, Blk b) {
   constexpr uint32_t kNone = 0xFFFFFFFFu;   // no neighbour (never a tile id)
-  if (hdr[kHdrOverflow]) return;
-  const int64_t D = (int64_t)hdr[kHdrDup];
+  const uint32_t* __restrict__ keys = a.keys;
+  const uint32_t tiles_total = a.tiles_total;
+  uint2* __restrict__ ranges = a.ranges;
+  if (a.hdr[kHdrOverflow]) return;
+  const int64_t D = (int64_t)a.hdr[kHdrDup];
   // Four consecutive keys per thread (one 16-byte load), plus the key before and after.
-  for (int64_t i0 = 4 * ((int64_t)blockIdx.x * kBlock + threadIdx.x); i0 < D;
-       i0 += 4 * (int64_t)gridDim.x * kBlock) {
+  for (int64_t i0 = 4 * ((int64_t)b.id * kBlock + threadIdx.x); i0 < D; i0 += 4 * (int64_t)b.n * kBlock) {
     uint32_t k[6];
     k[0] = i0 > 0 ? keys[i0 - 1] : kNone;
     if (i0 + 4 <= D) {
@@ -647,6 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_ranges(const uint32_t* __restrict__ 
     }
   }
 }
+__global__ __launch_bounds__(kBlock) void k_ranges(RangesArgs a) { ranges_body(a, grid_blk()); }
 
 // Longest-list-first order of the tiles: a counting sort of the tiles by the bit length of
 // their list length, longest first (order within a bucket is arbitrary: tiles are
@@ -658,31 +746,34 @@ __device__ __forceinline__ uint32_t len_bucket(const uint2 r, bool ovf) {
 }
 
 // Bucket totals: per-block LDS counts, then one global atomic per non-empty bucket.
-__global__ __launch_bounds__(kBlock) void k_tile_count(const uint2* __restrict__ ranges, uint32_t tiles,
-                                                       const unsigned long long* __restrict__ hdr,
-                                                       uint32_t* __restrict__ tord) {
+__device__ __forceinline__ void tile_count_body(const TileOrderArgs& a, Blk b) {
   __shared__ uint32_t cnt[kTileBuckets];
+  const uint2* __restrict__ ranges = a.ranges;
+  const uint32_t tiles = a.tiles;
   if (threadIdx.x < kTileBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const bool ovf = hdr[kHdrOverflow] != 0ull;
-  const uint32_t t0 = blockIdx.x * kTileOrderChunk;
+  const bool ovf = a.hdr[kHdrOverflow] != 0ull;
+  const uint32_t t0 = b.id * kTileOrderChunk;
   for (uint32_t t = t0 + threadIdx.x; t < tiles && t < t0 + kTileOrderChunk; t += kBlock)
     atomicAdd(&cnt[len_bucket(ranges[t], ovf)], 1u);
   __syncthreads();
-  if (threadIdx.x < kTileBuckets && cnt[threadIdx.x]) atomicAdd(&tord[threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x < kTileBuckets && cnt[threadIdx.x]) atomicAdd(&a.tord[threadIdx.x], cnt[threadIdx.x]);
 }
+__global__ __launch_bounds__(kBlock) void k_tile_count(TileOrderArgs a) { tile_count_body(a, grid_blk()); }
 
 // Scatter: bucket b starts after all longer buckets; each block reserves its slice of every
 // bucket with one global atomic (tord[33 + b]) and places its tiles with LDS cursors.
-__global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint2* __restrict__ ranges, uint32_t tiles,
-                                                         const unsigned long long* __restrict__ hdr,
-                                                         uint32_t* __restrict__ tord, uint32_t* __restrict__ order) {
+__device__ __forceinline__ void tile_scatter_body(const TileOrderArgs& a, Blk b) {
   __shared__ uint32_t cnt[kTileBuckets];
   __shared__ uint32_t cur[kTileBuckets];
+  const uint2* __restrict__ ranges = a.ranges;
+  const uint32_t tiles = a.tiles;
+  uint32_t* __restrict__ tord = a.tord;
+  uint32_t* __restrict__ order = a.order;
   if (threadIdx.x < kTileBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const bool ovf = hdr[kHdrOverflow] != 0ull;
-  const uint32_t t0 = blockIdx.x * kTileOrderChunk;
+  const bool ovf = a.hdr[kHdrOverflow] != 0ull;
+  const uint32_t t0 = b.id * kTileOrderChunk;
   for (uint32_t t = t0 + threadIdx.x; t < tiles && t < t0 + kTileOrderChunk; t += kBlock)
     atomicAdd(&cnt[len_bucket(ranges[t], ovf)], 1u);
   __syncthreads();
@@ -699,25 +790,52 @@ __global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint2* __restrict
   }
 }
 
-hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
-                         hipStream_t s) {
+__global__ __launch_bounds__(kBlock) void k_tile_scatter(TileOrderArgs a) { tile_scatter_body(a, grid_blk()); }
+
+hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity, const Sink& out) {
   char* w = (char*)ws;
   char* dp = (char*)dup;
   // The ranges and the ordering counters were cleared by launch_bin_sort.
-  hipError_t e = hipSuccess;
   const uint32_t* keys = (const uint32_t*)(dp + (parity ? D.keys1 : D.keys0));
+  const unsigned long long* hdr = (const unsigned long long*)(w + L.hdr);
   int64_t g = (D.cap + 4 * kBlock - 1) / (4 * kBlock);
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)g), dim3(kBlock), 0, s, keys,
-                     (const unsigned long long*)(w + L.hdr), L.tiles_total, (uint2*)(w + L.ranges));
-  if (L.tiles_total > 0) {
-    uint32_t* tord = (uint32_t*)(w + L.tord);
-    const unsigned nb = (L.tiles_total + kTileOrderChunk - 1) / kTileOrderChunk;
-    hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(kBlock), 0, s, (const uint2*)(w + L.ranges), L.tiles_total,
-                       (const unsigned long long*)(w + L.hdr), tord);
-    hipLaunchKernelGGL(k_tile_scatter, dim3(nb), dim3(kBlock), 0, s, (const uint2*)(w + L.ranges), L.tiles_total,
-                       (const unsigned long long*)(w + L.hdr), tord, (uint32_t*)(w + L.order));
+  Stage st{};
+  st.block = kBlock;
+  st.kind = kStRanges;
+  st.items = (uint32_t)g;
+  st.a.ranges = RangesArgs{keys, hdr, L.tiles_total, (uint2*)(w + L.ranges)};
+  hipError_t e = out.put(st);
+  if (e == hipSuccess && L.tiles_total > 0) {
+    st.items = (L.tiles_total + kTileOrderChunk - 1) / kTileOrderChunk;
+    st.a.tile_order = TileOrderArgs{(const uint2*)(w + L.ranges), L.tiles_total, hdr, (uint32_t*)(w + L.tord),
+                                    (uint32_t*)(w + L.order)};
+    st.kind = kStTileCount;
+    e = out.put(st);
+    st.kind = kStTileScatter;
+    if (e == hipSuccess) e = out.put(st);
+  }
+  return e;
+}
+
+hipError_t launch_sort_stage(const Stage& st, hipStream_t s) {
+  const dim3 g(st.items), blk(st.block);
+  switch (st.kind) {
+    case kStScanReduce: hipLaunchKernelGGL(k_scan_reduce, g, blk, 0, s, st.a.scan_reduce); break;
+    case kStScanPartials: hipLaunchKernelGGL(k_scan_partials, g, blk, 0, s, st.a.scan_partials); break;
+    case kStCompact: hipLaunchKernelGGL(k_compact, g, blk, 0, s, st.a.compact); break;
+    case kStRadixUp: hipLaunchKernelGGL(k_radix_upsweep, g, blk, 0, s, st.a.radix); break;
+    case kStRadixScan: hipLaunchKernelGGL(k_radix_digit_scan, g, blk, 0, s, st.a.radix); break;
+    case kStRadixDown: hipLaunchKernelGGL(k_radix_downsweep, g, blk, 0, s, st.a.radix); break;
+    case kStEmitReduce: hipLaunchKernelGGL(k_emit_reduce, g, blk, 0, s, st.a.emit_reduce); break;
+    case kStEmitPartials: hipLaunchKernelGGL(k_emit_partials, g, blk, 0, s, st.a.emit_partials); break;
+    case kStEmitOffsets: hipLaunchKernelGGL(k_emit_offsets, g, blk, 0, s, st.a.emit_offsets); break;
+    case kStEmit: hipLaunchKernelGGL(k_emit, g, blk, 0, s, st.a.emit); break;
+    case kStRanges: hipLaunchKernelGGL(k_ranges, g, blk, 0, s, st.a.ranges); break;
+    case kStTileCount: hipLaunchKernelGGL(k_tile_count, g, blk, 0, s, st.a.tile_order); break;
+    case kStTileScatter: hipLaunchKernelGGL(k_tile_scatter, g, blk, 0, s, st.a.tile_order); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -9,6 +9,11 @@ on the device.  Memory of a batch returns to the budget when its completion even
 
 The plain path serves one request per forward render, in arrival order.
 
+The persistent path hands each admitted batch to the resident serving kernel of libclod
+(clod_server_*): no kernel launches per batch, and the stages of successive batches overlap
+inside the one kernel.  Its device memory is one arena carved per batch on the host, so nothing
+is allocated while the kernel runs.
+
 The scheduling core (``Scheduler``) is independent of the GPU: ``GpuExecutor`` runs batches
 through libclod; tests drive the same core with a CPU stand-in executor.
 """
@@ -59,6 +64,8 @@ class Scheduler:
                 raise ValueError(f"request {r.rid} needs {c} bytes, more than the whole budget {self.budget}")
         pending = collections.deque(reqs)
         inflight = collections.deque()          # (handle, [requests], bytes)
+        if hasattr(self.ex, "prepare"):
+            self.ex.prepare(reqs, self.max_batch, self.budget)
         # The executor's time origin precedes the host origin (completion times are measured
         # from it), so latencies are never understated.
         self.ex.start()
@@ -251,6 +258,203 @@ class GpuExecutor:
         self.torch.cuda.synchronize()
 
 
+class Arena:
+    """First-fit sub-allocation of one device buffer (256-byte aligned blocks)."""
+
+    def __init__(self, nbytes: int):
+        self.size = int(nbytes)
+        self.free = [(0, self.size)]   # sorted, coalesced (offset, size)
+
+    def alloc(self, nbytes: int) -> int | None:
+        need = (int(nbytes) + 255) & ~255
+        for j, (off, sz) in enumerate(self.free):
+            if sz >= need:
+                if sz == need:
+                    del self.free[j]
+                else:
+                    self.free[j] = (off + need, sz - need)
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int):
+        need = (int(nbytes) + 255) & ~255
+        blocks = sorted(self.free + [(off, need)])
+        merged = []
+        for o, z in blocks:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + z)
+            else:
+                merged.append((o, z))
+        self.free = merged
+
+
+def _out_bytes(pixels: int) -> int:
+    a = lambda x: (x + 255) & ~255
+    return a(12 * pixels) + a(4 * pixels) + a(4 * pixels)
+
+
+def _out_views(mem, off: int, pixels: int, torch):
+    """rgb (float32 [3 pixels]), T (float32), last (int32) carved from a uint8 device buffer."""
+    a = lambda x: (x + 255) & ~255
+    o_t, o_l = off + a(12 * pixels), off + a(12 * pixels) + a(4 * pixels)
+    return (mem[off:off + 12 * pixels].view(torch.float32), mem[o_t:o_t + 4 * pixels].view(torch.float32),
+            mem[o_l:o_l + 4 * pixels].view(torch.int32))
+
+
+class PersistentExecutor:
+    """Serves batches through the resident serving kernel (clod_server_*).
+
+    ``prepare`` allocates, before the kernel starts, one device arena for the workspaces,
+    duplicate buffers and outputs of the batches in flight (the admission budget plus one
+    largest batch of slack), and with ``keep_outputs`` one output set per request; batches
+    then take and return arena blocks on the host only."""
+
+    def __init__(self, scene, params=None, dup_per_pixel: float = 12.0, keep_outputs: bool = False,
+                 workers: int = 0, max_seconds: float = 120.0):
+        import torch
+        from . import _clod as C
+        if scene.sh_packed is None:
+            raise ValueError("the persistent server reads packed SH coefficients: build the Scene with packed_sh=True")
+        self.torch, self.C = torch, C
+        self.scene = scene
+        self.params = params if params is not None else C.make_params()
+        self.dup_per_pixel = dup_per_pixel
+        self.keep = keep_outputs
+        self.workers_req = workers
+        self.max_seconds = max_seconds
+        self.outputs = {}
+        self.retries = 0
+        self.server = None
+        self.workers = 0
+        self.arena = None
+        self.mem = None
+        self.req_out = {}
+        self.stream = torch.cuda.Stream()
+        self.origin_ns = 0
+
+    def cost(self, req) -> int:
+        n = self.scene.n
+        px = req.view.width * req.view.height
+        return int(n * 121 + px * (20 + 12) + 16 * self.dup_per_pixel * px)
+
+    def _batch_bytes(self, views, pixels):
+        C = self.C
+        vh = C.make_views(views)
+        ws = C.clod_ws_bytes(self.scene.n, vh)
+        dup = C.clod_dup_bytes(int(self.dup_per_pixel * pixels) + 65536)
+        out = _out_bytes(pixels)
+        return vh, ws, dup, out
+
+    def prepare(self, requests, max_batch: int, budget: int):
+        torch = self.torch
+        big = sorted(requests, key=lambda r: r.view.width * r.view.height)[-max_batch:]
+        _, ws, dup, out = self._batch_bytes([r.view for r in big], sum(r.view.width * r.view.height for r in big))
+        total = int(budget) + ws + dup + out
+        self.arena = Arena(total)
+        self.mem = torch.empty(total, dtype=torch.uint8, device="cuda")
+        if self.keep:
+            for r in requests:
+                px = r.view.width * r.view.height
+                self.req_out[r.rid] = (torch.empty(3 * px, dtype=torch.float32, device="cuda"),
+                                       torch.empty(px, dtype=torch.float32, device="cuda"),
+                                       torch.empty(px, dtype=torch.int32, device="cuda"))
+        torch.cuda.synchronize()
+
+    def start(self):
+        import time
+        C = self.C
+        self.server, self.workers = C.clod_server_start(self.workers_req, self.max_seconds, self.stream)
+        t0 = time.perf_counter()
+        while C.clod_server_clock(self.server) < 0:
+            if time.perf_counter() - t0 > 30.0:
+                raise RuntimeError("the serving kernel did not start within 30 s")
+            time.sleep(1e-4)
+        self.origin_ns = C.clod_server_clock(self.server)
+
+    def _take(self, nbytes):
+        off = self.arena.alloc(nbytes)
+        if off is None:
+            raise RuntimeError(f"serving arena exhausted ({nbytes} bytes requested)")
+        return off
+
+    def _submit(self, h):
+        C = self.C
+        b = C.clod_batch()
+        b.n = self.scene.n
+        b.n_views = len(h["vh"])
+        b.views_host = C.ctypes.cast(h["vh"], C.P)
+        b.views_dev = None
+        b.params = self.params
+        base = self.mem.data_ptr()
+        b.ws, b.ws_bytes = base + h["blocks"]["ws"][0], h["blocks"]["ws"][1]
+        b.dup, b.dup_bytes = base + h["blocks"]["dup"][0], h["blocks"]["dup"][1]
+        rgb, T, last = h["out"]
+        h["seq"] = C.clod_server_submit(self.server, self.scene.c_struct(), b, rgb, T, last)
+
+    def launch(self, batch):
+        views = [r.view for r in batch]
+        pixels = sum(v.width * v.height for v in views)
+        vh, ws, dup, out = self._batch_bytes(views, pixels)
+        blocks = {"ws": (self._take(ws), ws), "dup": (self._take(dup), dup)}
+        if self.keep and len(batch) == 1:
+            outs = self.req_out[batch[0].rid]   # rendered in place
+        else:
+            # A batch renders into one output set (requests back to back); with keep_outputs the
+            # requests' parts are copied out at completion.
+            blocks["out"] = (self._take(out), out)
+            outs = _out_views(self.mem, blocks["out"][0], pixels, self.torch)
+        h = dict(batch=batch, vh=vh, blocks=blocks, out=outs, pixels=pixels)
+        self._submit(h)
+        return h
+
+    def poll(self, h):
+        C = self.C
+        info = C.clod_server_poll(self.server, h["seq"])
+        if info is None:
+            return None
+        if info["overflow"]:
+            # Larger duplicate buffer from the arena, then the same job again.
+            self.retries += 1
+            off, nb = h["blocks"]["dup"]
+            self.arena.release(off, nb)
+            nb = C.clod_dup_bytes(int(info["n_dup"] * 1.25) + 65536)
+            h["blocks"]["dup"] = (self._take(nb), nb)
+            self._submit(h)
+            return None
+        if self.keep and "out" in h["blocks"]:
+            # Device-to-device copies into each request's own outputs (after completion).
+            rgb, T, last = h["out"]
+            off = 0
+            with self.torch.cuda.stream(self.stream_copy()):
+                for r in h["batch"]:
+                    px = r.view.width * r.view.height
+                    d = self.req_out[r.rid]
+                    d[0].copy_(rgb[3 * off:3 * (off + px)], non_blocking=True)
+                    d[1].copy_(T[off:off + px], non_blocking=True)
+                    d[2].copy_(last[off:off + px], non_blocking=True)
+                    off += px
+            self._copy_stream.synchronize()
+        if self.keep:
+            for r in h["batch"]:
+                self.outputs[r.rid] = self.req_out[r.rid]
+        for off, nb in h["blocks"].values():
+            self.arena.release(off, nb)
+        return (info["t_ns"] - self.origin_ns) / 1e9
+
+    def stream_copy(self):
+        if not hasattr(self, "_copy_stream"):
+            self._copy_stream = self.torch.cuda.Stream()
+        return self._copy_stream
+
+    def finish(self):
+        if self.server is not None:
+            status = self.C.clod_server_stop(self.server)
+            self.server = None
+            if status != 1:
+                raise RuntimeError(f"serving kernel ended with status {status}")
+        self.torch.cuda.synchronize()
+
+
 class PlainExecutor(GpuExecutor):
     """The plain path: one request per forward render, on one stream, in arrival order."""
 
@@ -267,7 +471,14 @@ def serve(scene, requests, mode: str = "continuous", budget_bytes: int = 24 << 3
     elif mode == "plain":
         ex = PlainExecutor(scene, params, keep_outputs=keep_outputs)
         sch = Scheduler(ex, budget_bytes, max_batch=1, max_inflight=1)
+    elif mode == "persistent":
+        ex = PersistentExecutor(scene, params, keep_outputs=keep_outputs)
+        sch = Scheduler(ex, budget_bytes, max_batch=max_batch, max_inflight=max_inflight)
     else:
         raise ValueError(mode)
-    recs = sch.run(requests)
+    try:
+        recs = sch.run(requests)
+    finally:
+        if mode == "persistent" and ex.server is not None:
+            ex.finish()
     return recs, ex, sch
