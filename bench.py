@@ -456,24 +456,121 @@ def run_lod_sweep(args, torch, C, Batch, Scene, synth):
 
 
 def run_serve_stream(args, torch, Scene, synth):
-    """Poisson stream at 200 req/s over the 3M scene, mixed resolutions {720p, 1080p, 4K},
-    s_v log-uniform in [1, 16]: continuous batching and the plain path, p50/p99 latency."""
+    """Request streams over the resident 3M scene, resolutions uniform over {720p, 1080p, 4K},
+    s_v log-uniform in [1, 16], served three ways: plain (one forward render per request, in
+    arrival order), multi-stream continuous batching (host-launched stages on three streams)
+    and the persistent serving kernel (up to eight batches in flight inside one resident
+    kernel).  The plain path's capacity is measured first (every request queued at once); the
+    overload stream then arrives at 1.25 times that rate, a light stream at 200 requests/s.
+    Latency is measured from arrival to the device completion of the request's batch."""
     from paper_2510_09997_amd.serve import serve, summarize
     n = 3_000_000
     sc = synth.make_scene(n, 3, "mixture", seed=0)
     scene = Scene(sc, packed_sh=True)   # static scene: per-Gaussian SH copy
     del sc
-    warm = args.serve_warmup
-    reqs = synth.poisson_requests(1, warm + args.serve_requests, rate_hz=200.0)
-    out = {}
-    for mode in ("continuous", "plain"):
-        recs, ex, sch = serve(scene, reqs, mode=mode, budget_bytes=24 << 30, max_batch=8, max_inflight=3)
+    budget = 24 << 30
+    inflight = {"plain": 1, "continuous": 3, "persistent": 8}
+
+    def run(reqs, mode, warm):
+        recs, ex, sch = serve(scene, reqs, mode=mode, budget_bytes=budget, max_batch=8, max_inflight=inflight[mode])
         s = summarize(recs, first=warm)
         s["retries"] = ex.retries
         s["batches"] = sch.batches
         s["peak_hbm_gib"] = round(sch.peak_in_use / 2 ** 30, 3)
-        out[mode] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
-        log(f"[bench] serve {mode}: {out[mode]}")
+        if mode == "persistent":
+            s["workers"] = ex.workers
+        torch.cuda.synchronize()
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()}
+
+    out = {"persistent_timeline": server_timeline(torch, scene, synth)}
+    burst = synth.poisson_requests(2, args.serve_capacity_requests, rate_hz=1e9)
+    cap = run(burst, "plain", 0)
+    capacity = cap["frames_per_s"]
+    out["plain_capacity_fps"] = round(capacity, 2)
+    log(f"[bench] serve: plain capacity {capacity:.1f} frames/s")
+    rate = 1.25 * capacity
+    warm = args.serve_warmup
+    over = synth.poisson_requests(1, warm + args.serve_requests, rate_hz=rate)
+    light = synth.poisson_requests(3, warm + args.serve_light_requests, rate_hz=200.0)
+    out["overload"] = {"rate_hz": round(rate, 2), "requests": args.serve_requests}
+    out["light"] = {"rate_hz": 200.0, "requests": args.serve_light_requests}
+    for name, reqs in (("overload", over), ("light", light)):
+        for mode in ("plain", "continuous", "persistent"):
+            out[name][mode] = run(reqs, mode, warm)
+            log(f"[bench] serve {name} {mode}: {out[name][mode]}")
+    return out
+
+
+STAGE_NAMES = ["end", "view_setup", "fill", "frustum_max", "fold", "classify", "project", "select_hist",
+               "select_pick", "scan_reduce", "scan_partials", "compact", "radix_up", "radix_scan", "radix_down",
+               "emit_reduce", "emit_partials", "emit_offsets", "emit", "ranges", "tile_count", "tile_scatter", "blend",
+               "reduce_pairs"]
+
+
+def server_timeline(torch, scene, synth, reps=12):
+    """One job at a time through the resident serving kernel (1080p, 4K) at 3M Gaussians: the
+    median time from each stage's opening to the next one's, against the same job launched
+    stage by stage (events around ten back-to-back jobs on one stream)."""
+    import ctypes
+    from paper_2510_09997_amd import _clod as C
+    from paper_2510_09997_amd.render import Batch
+    n = scene.n
+    cases = {"1920x1080": synth.look_at((4.0, 1.0, -9.0), width=1920, height=1080, s_v=1.0),
+             "3840x2160": synth.look_at((2.0, 1.5, -7.0), width=3840, height=2160, s_v=1.7)}
+    out = {}
+    for name, view in cases.items():
+        b = Batch(n, [view])
+        for _ in range(3):
+            b.project(scene); b.bin_sort(); b.render_fwd()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.project(scene); b.bin_sort(sync=False); b.render_fwd()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"per_stage_launches_ms": round(e0.elapsed_time(e1) / 10, 4)}
+        del b
+    bufs = {}
+    for name, view in cases.items():
+        px = view.width * view.height
+        vh = C.make_views([view])
+        cb = C.clod_batch()
+        ws = torch.empty(C.clod_ws_bytes(n, vh), dtype=torch.uint8, device="cuda")
+        dup = torch.empty(C.clod_dup_bytes(16 * px + 65536), dtype=torch.uint8, device="cuda")
+        o = (torch.empty(3 * px, device="cuda"), torch.empty(px, device="cuda"),
+             torch.empty(px, dtype=torch.int32, device="cuda"))
+        cb.n, cb.n_views, cb.views_host, cb.views_dev, cb.params = n, 1, ctypes.cast(vh, C.P), None, C.make_params()
+        cb.ws, cb.ws_bytes, cb.dup, cb.dup_bytes = ws.data_ptr(), ws.numel(), dup.data_ptr(), dup.numel()
+        bufs[name] = (vh, ws, dup, o, cb)
+    torch.cuda.synchronize()
+    srv, workers = C.clod_server_start(0, 60.0, torch.cuda.Stream())
+    try:
+        t0 = time.perf_counter()
+        while C.clod_server_clock(srv) < 0:
+            assert time.perf_counter() - t0 < 30.0, "serving kernel did not start"
+            time.sleep(1e-4)
+        for name in cases:
+            _, _, _, o, cb = bufs[name]
+            tot, per = [], {}
+            for rep in range(reps):
+                seq = C.clod_server_submit(srv, scene.c_struct(), cb, *o)
+                t0 = time.perf_counter()
+                while C.clod_server_poll(srv, seq) is None:
+                    assert time.perf_counter() - t0 < 30.0, "serving job did not complete"
+                tl = C.clod_server_stage_times(srv, seq)
+                if rep < 2:
+                    continue
+                tot.append((tl[-1][1] - tl[0][1]) / 1e6)
+                for j in range(len(tl) - 1):
+                    per.setdefault(f"{j:02d}_{STAGE_NAMES[tl[j][0]]}", []).append((tl[j + 1][1] - tl[j][1]) / 1e3)
+            out[name].update(persistent_job_ms=round(float(np.median(tot)), 4), workers=workers,
+                             stage_us={k: round(float(np.median(v)), 1) for k, v in per.items()})
+            log(f"[bench] persistent timeline {name}: job {np.median(tot):.3f} ms vs "
+                f"{out[name]['per_stage_launches_ms']:.3f} ms launched stage by stage")
+    finally:
+        C.clod_server_stop(srv)
+    torch.cuda.synchronize()
     return out
 
 
@@ -523,7 +620,9 @@ def main():
                     help="also run a 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--streams", type=int, default=3,
                     help="streams the headline serving steps are pipelined over (1 = sequential)")
-    ap.add_argument("--serve-requests", type=int, default=4000)
+    ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-light-requests", type=int, default=1000)
+    ap.add_argument("--serve-capacity-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -621,11 +720,10 @@ def main():
     if not args.no_serve:
         torch.cuda.empty_cache()
         st = run_serve_stream(args, torch, Scene, synth)
-        out["serve_stream"] = {"rate_hz": 200.0, "requests": args.serve_requests,
-                               "resolutions": ["1280x720", "1920x1080", "3840x2160"], "s_v": "log-uniform [1, 16]",
-                               **st}
-        out["p99_ms"] = st["continuous"]["p99_ms"]
-        out["p50_ms"] = st["continuous"]["p50_ms"]
+        out["serve_stream"] = {"resolutions": ["1280x720", "1920x1080", "3840x2160"], "s_v": "log-uniform [1, 16]",
+                               "gaussians": 3_000_000, **st}
+        out["p99_ms"] = st["light"]["persistent"]["p99_ms"]
+        out["p50_ms"] = st["light"]["persistent"]["p50_ms"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(steps)
     print(json.dumps(out), flush=True)

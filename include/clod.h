@@ -316,6 +316,14 @@ clod_status clod_server_poll(clod_server *server, int64_t seq, int32_t *done, in
    polls continuously while idle); -1 before the kernel runs. */
 clod_status clod_server_clock(clod_server *server, int64_t *ns);
 
+/* Timeline of completed job seq (for profiling the resident kernel): ns[k] = device clock in ns
+   since the server started when stage k opened (stage 0: when the job was activated) and
+   kinds[k] (nullable) its stage kind (an internal enumeration), for the job's stages, then
+   its completion time with kind 0; *count receives the entries written (at most max).  Valid
+   until the slot takes a later job; CLOD_E_ARG if the job is not complete. */
+clod_status clod_server_stage_times(clod_server *server, int64_t seq, int64_t *ns, int32_t *kinds, int32_t max,
+                                    int32_t *count);
+
 /* Raises the stop flag, waits for the kernel to end and frees the server.  *status (nullable):
    1 stopped on request, 2 deadline reached, 3 protocol error, 4 unsupported stage; anything
    but 1 also returns CLOD_E_HIP.  Jobs not complete by then are abandoned. */

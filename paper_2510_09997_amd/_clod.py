@@ -79,7 +79,8 @@ assert ctypes.sizeof(clod_view) == 112
 EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project", "clod_bin_sort",
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
            "clod_inspect", "clod_last_error", "clod_abi_version", "clod_adam_step", "clod_lod_count_noalloc",
-           "clod_server_start", "clod_server_submit", "clod_server_poll", "clod_server_clock", "clod_server_stop"]
+           "clod_server_start", "clod_server_submit", "clod_server_poll", "clod_server_clock", "clod_server_stop",
+           "clod_server_stage_times"]
 
 SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC, SEC_ALPHA = 0, 1, 2, 3, 4
 SEC_FLAGS, SEC_DMAX, SEC_GSCREEN, SEC_HEADER = 6, 7, 9, 10
@@ -118,6 +119,7 @@ def load(path: str = LIB_PATH):
     L.clod_server_poll.argtypes = [P, i64, P, P]; L.clod_server_poll.restype = i32
     L.clod_server_clock.argtypes = [P, P]; L.clod_server_clock.restype = i32
     L.clod_server_stop.argtypes = [P, P]; L.clod_server_stop.restype = i32
+    L.clod_server_stage_times.argtypes = [P, i64, P, P, i32, P]; L.clod_server_stage_times.restype = i32
     if L.clod_abi_version() != ABI_VERSION:
         raise RuntimeError("libclod ABI version mismatch")
     _lib = L
@@ -342,3 +344,12 @@ def clod_server_stop(server: int) -> int:
     st = ctypes.c_int32(0)
     _check(load().clod_server_stop(P(server), ctypes.byref(st)))
     return int(st.value)
+
+
+def clod_server_stage_times(server: int, seq: int, max_entries: int = 96) -> list[tuple[int, int]]:
+    """[(stage kind, ns since start when it opened)] of a completed job, then (0, completion ns)."""
+    ns = (ctypes.c_int64 * max_entries)()
+    kinds = (ctypes.c_int32 * max_entries)()
+    cnt = ctypes.c_int32(0)
+    _check(load().clod_server_stage_times(P(server), int(seq), ns, kinds, int(max_entries), ctypes.byref(cnt)))
+    return [(int(kinds[k]), int(ns[k])) for k in range(cnt.value)]

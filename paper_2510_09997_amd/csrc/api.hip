@@ -679,6 +679,16 @@ clod_status clod_server_clock(clod_server* server, int64_t* ns) {
   return CLOD_OK;
 }
 
+clod_status clod_server_stage_times(clod_server* server, int64_t seq, int64_t* ns, int32_t* kinds, int32_t max,
+                                    int32_t* count) {
+  g_err[0] = 0;
+  if (!server || !ns || !count || max < 1) return fail(CLOD_E_ARG, "server, ns and count must be non-NULL, max >= 1");
+  const int k = server_stage_times(reinterpret_cast<Server*>(server), seq, ns, kinds, max);
+  if (k < 0) return fail(CLOD_E_ARG, "job %lld is not complete, was not published or its slot was reused", (long long)seq);
+  *count = k;
+  return CLOD_OK;
+}
+
 clod_status clod_server_stop(clod_server* server, int32_t* status) {
   g_err[0] = 0;
   if (!server) return fail(CLOD_E_ARG, "server is NULL");

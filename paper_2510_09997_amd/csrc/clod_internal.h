@@ -635,6 +635,7 @@ hipError_t server_publish(Server* S, const Program& P, int32_t n_views, const cl
                           const void* hdr_dev, int64_t* seq);
 int server_poll(Server* S, int64_t seq, int64_t* info);
 int64_t server_clock_ns(Server* S);
+int server_stage_times(Server* S, int64_t seq, int64_t* ns, int32_t* kinds, int32_t max);
 hipError_t server_stop(Server* S, int32_t* status);
 
 hipError_t launch_ssim(const Layout& L, void* ws, const float* rgb, const float* target, float lambda,

@@ -16,9 +16,16 @@
 // Waits are bounded.  Every loop polls the stop flag (raised by the dispatcher when the host
 // asks to stop, or by any workgroup on an error) and a deadline on the device's constant-rate
 // clock; no workgroup ever waits for another particular workgroup, and a claimed item always
-// runs to its end.  Visibility across the per-XCD L2 caches follows the agent-scope memory
-// model: items are released (agent scope) before they are counted done, and a worker acquires
-// after each claim, before it reads the stage's arguments and inputs.
+// runs to its end.
+//
+// Visibility across the per-XCD L2 caches follows the agent-scope memory model, and its
+// fences are the expensive part on this device (each one writes back or invalidates an L2;
+// they serialise device-wide at tens of ns each).  So a worker fences once per stage it takes
+// part in, not per item: it acquires when it enters a stage (before reading the stage's
+// arguments and inputs), keeps claiming items of that stage, and releases its items and counts
+// them done when the stage has none left to claim.  One wave fences for the workgroup, after a
+// barrier (the scoped model makes the other waves' writes visible through it).  Idle workers
+// poll one epoch word, bumped whenever a job or a stage opens, instead of the claim words.
 #include "project.hip"
 #include "sort.hip"
 #include "blend.hip"
@@ -59,6 +66,7 @@ struct SrvDone {
   uint64_t t_end;      // device clock at its completion
   uint64_t overflow;   // the job's duplicate buffer overflowed (outputs not written)
   uint64_t n_dup;      // tile pairs of the job
+  uint64_t t_open[kMaxStages];   // device clock when each stage opened (stage 0: activation)
 };
 
 // Pinned host memory (coherent, mapped).
@@ -73,14 +81,17 @@ struct SrvHost {
   SrvJob ring[kSrvSlots];
 };
 
-// Device memory.
+// Device memory.  Words written by many workgroups sit on cache lines of their own.
+struct alignas(128) SrvSlot {
+  unsigned long long claim;   // open stage and claim cursor (claim_word)
+  uint32_t done;              // items of the open stage completed
+  uint32_t active;            // (sequence number mod 2^32 - 1) + 1 of the job, 0 = free
+};
+constexpr unsigned long long kStopBit = 1ull << 63;
 struct SrvDev {
-  unsigned long long claim[kSrvSlots];   // open stage and claim cursor of each slot (claim_word)
-  uint32_t done[kSrvSlots];              // items of the open stage completed
-  uint32_t active[kSrvSlots];            // (sequence number mod 2^32 - 1) + 1 of the job, 0 = free
-  uint32_t stop;
-  uint32_t status;                       // largest SrvStatus raised
-  uint64_t reserved[7];
+  alignas(128) unsigned long long epoch;   // bumped when a job or a stage opens; kStopBit: stop
+  alignas(128) uint32_t status;            // largest SrvStatus raised
+  alignas(128) SrvSlot slot[kSrvSlots];
   SrvJob job[kSrvSlots];
 };
 
@@ -95,10 +106,12 @@ __device__ __forceinline__ uint32_t cw_lchunk(unsigned long long w) { return (ui
 __device__ __forceinline__ uint32_t cw_stage(unsigned long long w) { return (uint32_t)(w >> 56); }
 
 // Items per claim: one tile at a time for the blend (tiles come longest first and vary a lot),
-// else about two claims per worker, a power of two.
+// else about one claim per worker, a power of two.  (Fewer, larger claims cost more than they
+// save: consecutive blocks of the radix passes and the emission hold most of the real work, so
+// concentrating them on few workers lengthens the stage.)
 __device__ __forceinline__ uint32_t claim_lchunk(int32_t kind, uint32_t items, uint32_t workers) {
   if (kind == kStBlend) return 0;
-  const uint32_t per = items / (2 * workers);
+  const uint32_t per = items / workers;
   if (per <= 1) return 0;
   const uint32_t l = 31u - (uint32_t)__clz(per);
   return l > 15u ? 15u : l;
@@ -124,7 +137,10 @@ __device__ __forceinline__ uint64_t dev_clock() { return (uint64_t)wall_clock64(
 
 __device__ __forceinline__ void raise_stop(SrvDev* D, uint32_t status) {
   atomicMax(&D->status, status);
-  __hip_atomic_store(&D->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_or(&D->epoch, kStopBit, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void bump_epoch(SrvDev* D) {
+  __hip_atomic_fetch_add(&D->epoch, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------- dispatcher
@@ -148,14 +164,14 @@ __device__ void srv_dispatch(SrvDev* D, SrvHost* H, uint64_t deadline) {
       if (lane == 0) raise_stop(D, kSrvDeadline);
       return;
     }
-    if (ld_agent(&D->stop)) return;   // a worker raised an error
+    if (ld_agent(&D->epoch) & kStopBit) return;   // a worker raised an error
     const uint64_t pub = ld_sys_acquire(&H->published);
     const uint32_t hstop = ld_sys_acquire(&H->stop);
     while (next < pub) {
       const uint32_t slot = (uint32_t)(next % kSrvSlots);
       const SrvJob& src = H->ring[slot];
       const uint32_t ns = src.n_stages, nv = src.n_views;
-      if (ld_agent(&D->active[slot]) != 0u || src.seq != next || ns < 1 || ns > (uint32_t)kMaxStages ||
+      if (ld_agent(&D->slot[slot].active) != 0u || src.seq != next || ns < 1 || ns > (uint32_t)kMaxStages ||
           nv > (uint32_t)kSrvMaxViews) {
         if (lane == 0) raise_stop(D, kSrvProtocol);
         return;
@@ -180,11 +196,14 @@ __device__ void srv_dispatch(SrvDev* D, SrvHost* H, uint64_t deadline) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (lane == 0) {
         const uint32_t items = src.st[0].items;
-        atomicExch(&D->done[slot], 0u);
-        __hip_atomic_exchange(&D->claim[slot], claim_word(0, claim_lchunk(src.st[0].kind, items, workers), items),
-                              __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&D->active[slot], (uint32_t)(next % 0xFFFFFFFFull) + 1u, __ATOMIC_RELEASE,
+        SrvSlot& S = D->slot[slot];
+        atomicExch(&S.done, 0u);
+        __hip_atomic_store(&S.active, (uint32_t)(next % 0xFFFFFFFFull) + 1u, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_exchange(&S.claim, claim_word(0, claim_lchunk(src.st[0].kind, items, workers), items),
+                              __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        bump_epoch(D);
+        st_sys(&H->done[slot].t_open[0], dev_clock());
       }
       ++next;
     }
@@ -275,7 +294,8 @@ __device__ bool srv_run(int32_t kind, const Stage& st, Blk b, SrvLds& U) {
 // that completes the stage opens the next one, or completes the job.
 __device__ void srv_complete(SrvDev* D, SrvHost* H, uint32_t slot, uint32_t stage, uint32_t n, uint32_t limit,
                              uint32_t workers) {
-  const uint32_t prev = atomicAdd(&D->done[slot], n);
+  SrvSlot& S = D->slot[slot];
+  const uint32_t prev = atomicAdd(&S.done, n);
   if (prev + n != limit) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const SrvJob& job = D->job[slot];
@@ -284,9 +304,11 @@ __device__ void srv_complete(SrvDev* D, SrvHost* H, uint32_t slot, uint32_t stag
   if (next < ns) {
     const uint32_t items = ld_agent(&job.st[next].items);
     const int32_t kind = ld_agent(&job.st[next].kind);
-    atomicExch(&D->done[slot], 0u);
-    __hip_atomic_exchange(&D->claim[slot], claim_word(next, claim_lchunk(kind, items, workers), items),
-                          __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    atomicExch(&S.done, 0u);
+    __hip_atomic_exchange(&S.claim, claim_word(next, claim_lchunk(kind, items, workers), items), __ATOMIC_RELEASE,
+                          __HIP_MEMORY_SCOPE_AGENT);
+    bump_epoch(D);
+    st_sys(&H->done[slot].t_open[next], dev_clock());
     return;
   }
   // The job is complete.  The slot is freed before the record is written: the host reuses a
@@ -294,8 +316,8 @@ __device__ void srv_complete(SrvDev* D, SrvHost* H, uint32_t slot, uint32_t stag
   const unsigned long long* hdr =
       reinterpret_cast<const unsigned long long*>(ld_agent(reinterpret_cast<const uint64_t*>(&job.hdr)));
   const uint64_t ovf = ld_agent(hdr + kHdrOverflow), nd = ld_agent(hdr + kHdrDup), seq = ld_agent(&job.seq);
-  __hip_atomic_exchange(&D->claim[slot], claim_word(kNoStage, 0, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&D->active[slot], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_exchange(&S.claim, claim_word(kNoStage, 0, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&S.active, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   SrvDone& r = H->done[slot];
   st_sys(&r.overflow, ovf);
   st_sys(&r.n_dup, nd);
@@ -304,27 +326,70 @@ __device__ void srv_complete(SrvDev* D, SrvHost* H, uint32_t slot, uint32_t stag
 }
 
 __device__ void srv_work(SrvDev* D, SrvHost* H, uint64_t deadline, SrvLds& U) {
-  __shared__ uint32_t c_go, c_slot, c_stage, c_i0, c_i1, c_limit;
+  __shared__ uint32_t c_go, c_fresh, c_slot, c_stage, c_i0, c_i1;
   __shared__ Stage c_st;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
   const uint32_t workers = gridDim.x - 1;
+  // Wave 0's view of the stage this worker is in (kNone: none) and its items not yet counted.
+  uint32_t cur_slot = kNone, cur_stage = 0, cur_limit = 0, pending = 0;
   for (;;) {
-    // Wave 0 looks for work: lane j inspects slot j; the oldest job with unclaimed items wins.
     if (threadIdx.x < 64) {
       const uint32_t lane = lane_id();
-      uint32_t go = 0, idle = 0;
+      uint32_t go = 0, fresh = 0, idle = 0, slot = 0, stage = 0, i0 = 0, i1 = 0;
+      unsigned long long seen = ~0ull;   // epoch of the last scan that found nothing
       for (;;) {
-        if (ld_agent(&D->stop)) break;
+        if (cur_slot != kNone) {
+          // More items of the current stage?
+          unsigned long long old = 0;
+          uint32_t add = 0;
+          if (lane == 0) {
+            const unsigned long long w = ld_agent(&D->slot[cur_slot].claim);
+            if (cw_stage(w) == cur_stage && cw_cursor(w) < cw_limit(w)) {
+              add = 1u << cw_lchunk(w);
+              old = atomicAdd(&D->slot[cur_slot].claim, (unsigned long long)add);
+            }
+          }
+          add = __shfl(add, 0, 64);
+          old = __shfl(old, 0, 64);
+          if (add != 0u && cw_stage(old) == cur_stage && cw_cursor(old) < cw_limit(old)) {
+            slot = cur_slot;
+            stage = cur_stage;
+            i0 = cw_cursor(old);
+            i1 = i0 + add < cw_limit(old) ? i0 + add : cw_limit(old);
+            go = 1;
+            break;
+          }
+          // None left to claim: release this worker's items of the stage and count them.
+          if (pending) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0) srv_complete(D, H, cur_slot, cur_stage, pending, cur_limit, workers);
+            pending = 0;
+          }
+          cur_slot = kNone;
+        }
+        const unsigned long long e = ld_agent(&D->epoch);
+        if (e & kStopBit) break;
         if (dev_clock() > deadline) {
           if (lane == 0) raise_stop(D, kSrvDeadline);
           break;
         }
-        // A free slot's claim word has no items, so only slots with unclaimed items read
-        // their job's sequence number.
+        if (e == seen) {
+          // Back off while idle: about 0.2 us, growing to about 3 us.
+          idle = idle < 16 ? idle + 1 : 16;
+          for (uint32_t k = 0; k < idle; ++k) __builtin_amdgcn_s_sleep(8);
+          continue;
+        }
+        // Lane j inspects slot j; the oldest job with unclaimed items wins.  A free slot's
+        // claim word has no items, so only slots with items read their job's number (a number
+        // not yet visible ranks the slot last, it does not hide its items).
         unsigned long long w = 0;
         uint32_t act = 0;
         if (lane < (uint32_t)kSrvSlots) {
-          w = ld_agent(&D->claim[lane]);
-          if (cw_cursor(w) < cw_limit(w)) act = ld_agent(&D->active[lane]);
+          w = ld_agent(&D->slot[lane].claim);
+          if (cw_cursor(w) < cw_limit(w)) {
+            act = ld_agent(&D->slot[lane].active);
+            if (act == 0u) act = 0xFFFFFFFFu;
+          }
         }
         unsigned long long key = act != 0u ? ((unsigned long long)act << 8) | lane : ~0ull;
 #pragma unroll
@@ -333,9 +398,7 @@ __device__ void srv_work(SrvDev* D, SrvHost* H, uint64_t deadline, SrvLds& U) {
           key = other < key ? other : key;
         }
         if (key == ~0ull) {
-          // Back off while idle: about 0.1 us after work, growing to about 2 us.
-          idle = idle < 16 ? idle + 1 : 16;
-          for (uint32_t k = 0; k < idle; ++k) __builtin_amdgcn_s_sleep(8);
+          seen = e;
           continue;
         }
         idle = 0;
@@ -344,36 +407,44 @@ __device__ void srv_work(SrvDev* D, SrvHost* H, uint64_t deadline, SrvLds& U) {
         uint32_t add = 0;
         if (lane == j) {
           add = 1u << cw_lchunk(w);
-          old = atomicAdd(&D->claim[j], (unsigned long long)add);
+          old = atomicAdd(&D->slot[j].claim, (unsigned long long)add);
         }
         old = __shfl(old, (int)j, 64);
         add = __shfl(add, (int)j, 64);
-        const uint32_t i0 = cw_cursor(old), lim = cw_limit(old);
-        if (i0 >= lim) continue;   // another worker took the last items first
-        if (lane == 0) {
-          c_slot = j;
-          c_stage = cw_stage(old);
-          c_i0 = i0;
-          c_i1 = i0 + add < lim ? i0 + add : lim;
-          c_limit = lim;
-        }
+        if (cw_cursor(old) >= cw_limit(old)) continue;   // another worker took the last items first
+        slot = j;
+        stage = cw_stage(old);
+        i0 = cw_cursor(old);
+        i1 = i0 + add < cw_limit(old) ? i0 + add : cw_limit(old);
+        cur_slot = slot;
+        cur_stage = stage;
+        cur_limit = cw_limit(old);
         go = 1;
+        fresh = 1;
         break;
       }
-      if (lane == 0) c_go = go;
+      // Entering a stage: acquire before anything of it is read.
+      if (fresh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (lane == 0) {
+        c_go = go;
+        c_fresh = fresh;
+        c_slot = slot;
+        c_stage = stage;
+        c_i0 = i0;
+        c_i1 = i1;
+      }
+      if (go) pending += i1 - i0;
     }
     __syncthreads();
     if (!c_go) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const uint32_t slot = __builtin_amdgcn_readfirstlane(c_slot), stage = __builtin_amdgcn_readfirstlane(c_stage);
     const uint32_t i0 = __builtin_amdgcn_readfirstlane(c_i0), i1 = __builtin_amdgcn_readfirstlane(c_i1);
-    const uint32_t limit = __builtin_amdgcn_readfirstlane(c_limit);
-    {
+    if (__builtin_amdgcn_readfirstlane(c_fresh)) {
       const uint32_t* src = reinterpret_cast<const uint32_t*>(&D->job[slot].st[stage]);
       uint32_t* dst = reinterpret_cast<uint32_t*>(&c_st);
       for (uint32_t q = threadIdx.x; q < (uint32_t)(sizeof(Stage) / 4); q += kBlock) dst[q] = ld_agent(src + q);
+      __syncthreads();
     }
-    __syncthreads();
     const int32_t kind = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)c_st.kind);
     const uint32_t items = __builtin_amdgcn_readfirstlane(c_st.items);
     bool ok = true;
@@ -381,13 +452,10 @@ __device__ void srv_work(SrvDev* D, SrvHost* H, uint64_t deadline, SrvLds& U) {
       ok = srv_run(kind, c_st, Blk{it, items}, U);
       __syncthreads();
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      if (ok) srv_complete(D, H, slot, stage, i1 - i0, limit, workers);
-      else raise_stop(D, kSrvUnsupported);
+    if (!ok) {
+      if (threadIdx.x == 0) raise_stop(D, kSrvUnsupported);
+      return;
     }
-    __syncthreads();
   }
 }
 
@@ -455,10 +523,10 @@ hipError_t server_start(int32_t workers, double max_seconds, hipStream_t s, Serv
   ::memset(S->host, 0, sizeof(SrvHost));
   e = hipMemsetAsync(S->dev, 0, sizeof(SrvDev), s);
   // Free slots: no stage open.
-  static_assert(sizeof(((SrvDev*)nullptr)->claim) == kSrvSlots * 8, "claim words");
-  unsigned long long init[kSrvSlots];
-  for (int j = 0; j < kSrvSlots; ++j) init[j] = claim_word(kNoStage, 0, 0);
-  if (e == hipSuccess) e = hipMemcpyAsync(S->dev->claim, init, sizeof(init), hipMemcpyHostToDevice, s);
+  SrvSlot init[kSrvSlots];
+  ::memset(init, 0, sizeof(init));
+  for (int j = 0; j < kSrvSlots; ++j) init[j].claim = claim_word(kNoStage, 0, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->dev->slot, init, sizeof(init), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     server_free(S);
@@ -532,6 +600,29 @@ int server_poll(Server* S, int64_t seq, int64_t* info) {
   // A slot is only reused after its job was seen complete (server_slot_free), so the fields
   // read above belong to this job unless the slot's next job finished in between.
   return __atomic_load_n(&r.seq1, __ATOMIC_ACQUIRE) == (uint64_t)seq + 1 ? 1 : -1;
+}
+
+// Stage opening times of completed job seq in ns since the server started and the stage kinds
+// (n_stages of them, at most max), followed by its completion time (kind 0); returns the count
+// written, -1 as server_poll.  Valid until the slot takes its next job.
+int server_stage_times(Server* S, int64_t seq, int64_t* ns, int32_t* kinds, int32_t max) {
+  int64_t info[3];
+  if (server_poll(S, seq, info) != 1) return -1;
+  const SrvDone& r = S->host->done[seq % kSrvSlots];
+  const SrvJob& J = S->host->ring[seq % kSrvSlots];
+  const uint64_t t0 = __atomic_load_n(&S->host->t_start, __ATOMIC_RELAXED);
+  const int n = (int)J.n_stages;
+  int k = 0;
+  for (; k < n && k < max; ++k) {
+    ns[k] = (int64_t)((double)(__atomic_load_n(&r.t_open[k], __ATOMIC_RELAXED) - t0) * 1e9 / S->tick_hz);
+    if (kinds) kinds[k] = J.st[k].kind;
+  }
+  if (k < max) {
+    ns[k] = info[2];
+    if (kinds) kinds[k] = 0;
+    ++k;
+  }
+  return k;
 }
 
 // Device clock in ns since the server started (the dispatcher's last heartbeat), -1 before it runs.
