@@ -40,6 +40,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Algorithmic HBM bytes of the path (what the method must move, not what a design moves):
+# N Gaussians, R rendered (view, Gaussian) records, D tile pairs, P pixels, SH degree 3.
+#   forward  = 20 N (means, opacity, decay: read once per batch) + 280 R (scale, rotation and 48
+#              SH coefficients read, 52-byte record written, 8-byte scan entry) + 84 D (keys
+#              written, one sort pass read + write, ranges, record and index reads of the blend)
+#              + 20 P (colour, T, last index written)
+#   backward = 20 P (dL/dC, T, last read) + 76 D (records re-read, screen-space partials
+#              accumulated) + 36 R (partials read) + 480 N (all parameters read, all gradients
+#              written: the point-count term reaches every Gaussian)
+#   loss     = 36 P (rendered colour and target read, dL/dC written)
+def fwd_bytes(N, R, D, P):
+    return 20 * N + 280 * R + 84 * D + 20 * P
+
+
+def bwd_bytes(N, R, D, P):
+    return 20 * P + 76 * D + 36 * R + 480 * N
+
+
+LOSS_BYTES_PER_PIXEL = 36
+# Flops per pair of the adjoint loop's live pairs (power, alpha, transmittance recovery, colour
+# dot product, the nine partial sums and the colour recurrence).
+FLOPS_PER_PAIR_BWD = 45
+
+
 def pose_views(seed: int, k: int, width=1920, height=1080, radius=(3.0, 30.0)):
     from paper_2510_09997_amd import synth
     rng = np.random.default_rng(seed + 1000)
@@ -67,7 +91,9 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     scene = Scene(sc, packed_sh=True)   # static scene: per-Gaussian SH copy
     del sc
     K, W = args.steps, args.warmup
-    steps = pose_views(0, K + W)
+    # Timed poses depend on K only (warm-up poses are drawn apart), so any warm-up count times
+    # the same launches.
+    steps = pose_views(7, W) + pose_views(0, K)
     tables = StepTables(steps)
     # Batched path: one Batch with five 1080p views; capacity sized by a sizing pass.
     b = Batch(n, steps[0])
@@ -116,6 +142,16 @@ def run_serving(args, torch, C, Batch, Scene, synth):
         for st in streams:
             cur.wait_stream(st)
 
+    if args.profile == "timed-blend":
+        # Only the launches whose blend time the roofline uses: the timed steps, one after the
+        # other on one stream (the sequential pass below), for hardware counters of exactly them.
+        evp = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+        for k in range(K):
+            evp[k][3].record()
+            step(W + k, evp[k])
+        torch.cuda.synchronize()
+        blend = sum(e[1].elapsed_time(e[2]) for e in evp) / K
+        return dict(profile="timed-blend", blend_fwd_ms=blend, steps=K), scene, b, steps
     pipelined(0, max(W, NS))
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
@@ -155,7 +191,7 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     # Work counters of the blend, from an untimed re-run of the timed steps (the timed
     # launches carry no counters, so their duration is the blend kernel alone).
     pairs_per_step = None
-    dups = []
+    dups, rend = [], []
     if not args.no_count:
         for k in range(K):
             b.views_host, b.views_dev = tables.host[W + k], tables.dev[W + k]
@@ -164,6 +200,7 @@ def run_serving(args, torch, C, Batch, Scene, synth):
             C.clod_bin_sort(bs, sync_count=False)
             C.clod_render_fwd(bs, rgb, T, last, pairs)
             dups.append(C.clod_read_info(bs)["n_dup"])
+            rend.append(int(b.counts[:, 2].sum().item()))
         torch.cuda.synchronize()
         pairs_per_step = (pairs.cpu().numpy() / K).tolist()
     res = dict(total_ms=total_ms, ms_per_step=total_ms / K, fps=frames / (total_ms / 1e3), streams=NS,
@@ -171,7 +208,13 @@ def run_serving(args, torch, C, Batch, Scene, synth):
                sequential_fps=frames / (seq_ms / 1e3), sequential_ms_per_step=seq_ms / K,
                stage_ms=dict(project=proj_ms, bin_sort=sort_ms, blend_fwd=blend_ms),
                pairs_per_step=pairs_per_step, max_dup=dmax, blend_launches=K,
-               dup_per_step=float(np.mean(dups)) if dups else None, pixels_per_step=b.pixels)
+               dup_per_step=float(np.mean(dups)) if dups else None, pixels_per_step=b.pixels,
+               rendered_per_step=float(np.mean(rend)) if rend else None)
+    if dups:
+        nb = fwd_bytes(n, res["rendered_per_step"], res["dup_per_step"], b.pixels)
+        res["hbm"] = {"algorithmic_bytes_per_step": int(nb),
+                      "frac_pipelined": round(nb / (res["ms_per_step"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                      "frac_sequential": round(nb / (res["sequential_ms_per_step"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
     # Per-view kept counts of the last step (mask counts fall with s_v).
     res["counts_last_step"] = b.counts.cpu().numpy().tolist()
 
@@ -264,8 +307,36 @@ def run_train(args, torch, C, Batch, Scene, synth):
     bwd_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / K
     info = C.clod_read_info(b.c_struct())
     assert not info["overflow"]
-    return dict(ms_per_iter=total / K, p50_ms=float(np.percentile(it_ms, 50)), p99_ms=float(np.percentile(it_ms, 99)),
-                bwd_ms=bwd_ms, max_dup=dmax)
+    res = dict(ms_per_iter=total / K, p50_ms=float(np.percentile(it_ms, 50)), p99_ms=float(np.percentile(it_ms, 99)),
+               bwd_ms=bwd_ms, max_dup=dmax)
+    # Work of the timed iterations, from an untimed re-run of the first ten of them: records,
+    # tile pairs and the pairs of both per-pixel loops (the kernels count them exactly).
+    fp = torch.zeros(3, dtype=torch.int64, device="cuda")
+    bp = torch.zeros(3, dtype=torch.int64, device="cuda")
+    R, D, S = [], [], min(K, 10)
+    for k in range(S):
+        b.views_host, b.views_dev = hosts[W + k], devs[W + k]
+        bs = b.c_struct()
+        s = scene.c_struct()
+        C.clod_project(s, bs, b.counts)
+        C.clod_bin_sort(bs, sync_count=False)
+        C.clod_render_fwd(bs, rgb, T, last, fp)
+        C.clod_loss(bs, rgb, target, 8.0, 1.0, loss, dL, deta)
+        C.clod_render_bwd(s, bs, T, last, dL, deta, False, gs, pairs=bp)
+        D.append(C.clod_read_info(bs)["n_dup"])
+        R.append(int(b.counts[0, 2].item()))
+    torch.cuda.synchronize()
+    Rm, Dm, P = float(np.mean(R)), float(np.mean(D)), b.pixels
+    fb, bb = fwd_bytes(n, Rm, Dm, P), bwd_bytes(n, Rm, Dm, P)
+    tot = fb + bb + LOSS_BYTES_PER_PIXEL * P
+    fpairs, bpairs = (fp.cpu().numpy() / S).tolist(), (bp.cpu().numpy() / S).tolist()
+    res.update(rendered=Rm, pairs=Dm, pixels=P, fwd_pairs=fpairs, bwd_pairs=bpairs,
+               hbm={"algorithmic_bytes_per_iter": int(tot), "fwd_bytes": int(fb), "bwd_bytes": int(bb),
+                    "frac": round(tot / (res["ms_per_iter"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                    "bwd_frac": round(bb / (bwd_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)},
+               bwd_alu={"flops_per_pair": FLOPS_PER_PAIR_BWD, "live_pairs": bpairs[1],
+                        "tflops_over_clod_render_bwd": round(FLOPS_PER_PAIR_BWD * bpairs[1] / (bwd_ms * 1e-3) / 1e12, 3)})
+    return res
 
 
 def run_multiview_train(args, torch, C, Scene, synth):
@@ -289,7 +360,9 @@ def run_multiview_train(args, torch, C, Scene, synth):
     dmax = tr.size_capacity(sets)
     tables = [C.views_to_device(C.make_views(vs), "cuda") for vs in sets]
     tr.set_target(torch.rand(3 * tr.batch.pixels, device="cuda", generator=torch.Generator("cuda").manual_seed(0), dtype=torch.float32))
-    tr.capture()
+    eager = args.profile == "multiview-eager"
+    if not eager:
+        tr.capture()
     for j in range(W):
         tr.set_views_dev(tables[j])
         tr.step()
@@ -303,6 +376,22 @@ def run_multiview_train(args, torch, C, Scene, synth):
     torch.cuda.synchronize()
     per = [evs[k].elapsed_time(evs[k + 1]) for k in range(K)]
     assert not tr.overflowed(), "duplicate buffer overflow inside the timed region"
+    # Records and tile pairs of the timed steps (untimed eager re-run of the first five).
+    R, D = [], []
+    graph, tr.graph = tr.graph, None
+    for k in range(min(K, 5)):
+        tr.set_views_dev(tables[W + k])
+        tr.step()
+        D.append(tr.n_dup())
+        R.append(int(tr.batch.counts[:, 2].sum().item()))
+    tr.graph = graph
+    Rm, Dm, P = float(np.mean(R)), float(np.mean(D)), tr.batch.pixels
+    step_bytes = fwd_bytes(n, Rm, Dm, P) + bwd_bytes(n, Rm, Dm, P) + LOSS_BYTES_PER_PIXEL * P
+    hbm = {"algorithmic_bytes_per_step": int(step_bytes), "rendered": Rm, "pairs": Dm,
+           "frac": round(step_bytes / (float(np.mean(per)) * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+    if eager:
+        return dict(ms_per_step=float(np.mean(per)), p50_ms=float(np.percentile(per, 50)), eager=True, views=16,
+                    gaussians=n, pixels_per_step=P, hbm=hbm)
     # The same step with the full 3DGS rendering loss (0.8 L1 + 0.2 D-SSIM), re-captured.
     tr.lambda_dssim = 0.2
     tr.capture()
@@ -335,7 +424,7 @@ def run_multiview_train(args, torch, C, Scene, synth):
     return dict(ms_per_step=float(np.mean(per)), p50_ms=float(np.percentile(per, 50)),
                 p99_ms=float(np.percentile(per, 99)), views=16, gaussians=n, max_dup=dmax,
                 pixels_per_step=tr.batch.pixels, ms_per_step_with_dssim=dssim_ms, adam_ms=adam_ms, adam_params=nparam,
-                adam_hbm_frac=adam_bytes / (adam_ms * 1e-3) / 8e12)
+                adam_hbm_frac=adam_bytes / (adam_ms * 1e-3) / 8e12, hbm=hbm)
 
 
 def run_budget_sweep(args, torch, C, Batch, scene, pose):
@@ -436,22 +525,41 @@ def run_lod_sweep(args, torch, C, Batch, Scene, synth):
     rgb = torch.empty(3 * b.pixels, device="cuda", dtype=torch.float32)
     T = torch.empty(b.pixels, device="cuda", dtype=torch.float32)
     last = torch.empty(b.pixels, dtype=torch.int32, device="cuda")
+    stage = {"project": [], "bin_sort": [], "blend_fwd": []}
+    work = {"rendered": [], "pairs": [], "longest_list": [], "evaluated": [], "blended": []}
+    pairs = torch.zeros(3, dtype=torch.int64, device="cuda")
     for k, v in enumerate(ray):
         b.update_views([v])
         b.project(scene)
         b.bin_sort()
         bs = b.c_struct()
         reps = 3
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(reps)]
+        for r in range(reps):
+            ev[r][0].record()
             C.clod_project(scene.c_struct(), bs, None)
+            ev[r][1].record()
             C.clod_bin_sort(bs, sync_count=False)
+            ev[r][2].record()
             C.clod_render_fwd(bs, rgb, T, last, None)
-        e1.record()
+            ev[r][3].record()
         torch.cuda.synchronize()
-        fps.append(round(reps / (e0.elapsed_time(e1) / 1e3), 2))
+        fps.append(round(reps / (ev[0][0].elapsed_time(ev[-1][3]) / 1e3), 2))
+        for j, key in enumerate(("project", "bin_sort", "blend_fwd")):
+            stage[key].append(round(float(np.mean([e[j].elapsed_time(e[j + 1]) for e in ev])), 4))
+        # Work of the frame (untimed counting re-run of the blend).
+        pairs.zero_()
+        C.clod_render_fwd(bs, rgb, T, last, pairs)
+        rg = b.section(C.SEC_RANGES).view(-1, 2).to(torch.int64)
+        pc = pairs.cpu().numpy()
+        work["rendered"].append(int(b.counts[0, 2].item()))
+        work["pairs"].append(int(C.clod_read_info(bs)["n_dup"]))
+        work["longest_list"].append(int((rg[:, 1] - rg[:, 0]).max().item()))
+        work["evaluated"].append(int(pc[0]))
+        work["blended"].append(int(pc[2]))
     out["ray_fps"] = fps
+    out["ray_stage_ms"] = stage
+    out["ray_work"] = work
     return out
 
 
@@ -574,21 +682,90 @@ def server_timeline(torch, scene, synth, reps=12):
     return out
 
 
-def cpu_baseline(steps, poses=3):
+def cpu_info() -> dict:
+    """Host CPU of the run: usable cores (affinity), logical CPUs and the model name."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "logical_cpus": os.cpu_count(), "model": model}
+
+
+def cpu_baseline(timed_steps, poses=3):
     """The oracle (binary32 contract, OpenMP over tiles) on a bounded sample of the headline
-    workload: the five LoD frames of each of the first three poses (about 10 s of CPU work)."""
+    workload: the five LoD frames of each of the first three timed poses (about 10 s of CPU
+    work); also the small parity scene (10,000 Gaussians, 256x256)."""
     from oracle import oracle as O
     from paper_2510_09997_amd import synth
     sc = synth.make_scene(3_000_000, 3, "mixture", seed=0)
-    frames = [view for j in range(poses) for view in steps[j]]
+    frames = [view for vs in timed_steps[:poses] for view in vs]
     t0 = time.perf_counter()
     for view in frames:
         O.render32(sc, view)
     dt = time.perf_counter() - t0
     svs = ", ".join(f"{v:g}" for v in SV_SWEEP)
+    sc1 = synth.make_scene(10_000, 0, "uniform", seed=0)
+    v1 = synth.look_at((0.0, 0.0, -3.0), width=256, height=256)
+    t1 = []
+    for _ in range(3):
+        t = time.perf_counter()
+        O.render32(sc1, v1)
+        t1.append(time.perf_counter() - t)
     return dict(value=round(len(frames) / dt, 4), unit="frames/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{len(frames)} frames of 1920x1080 at 3M Gaussians (poses 0-{poses - 1}, s_v = {svs} each): "
-                       f"{dt:.1f} s")
+                sample=f"{len(frames)} frames of 1920x1080 at 3M Gaussians (the first {poses} timed poses, s_v = "
+                       f"{svs} each): {dt:.1f} s",
+                small_scene_ms=round(1e3 * float(np.median(t1)), 3), cpu=cpu_info())
+
+
+def cpu_suite(one_core: bool) -> dict:
+    """The oracle on the parity configurations (median of three runs where cheap): the 10,000-
+    Gaussian scene; one forward + backward of the 1M training configuration with the FP64
+    gradient oracle; the LoD-sweep frames at 6M, k = 0, 21, 42, 63 (one core: k = 0 and 63, and
+    the backward at 648x420, a quarter of the pixels, to stay within a few minutes)."""
+    import torch
+    from oracle import oracle as O
+    from paper_2510_09997_amd import synth
+    if one_core:
+        torch.set_num_threads(1)
+    out = {"threads": O.num_threads(), "torch_threads": torch.get_num_threads(), "cpu": cpu_info()}
+
+    def timed(f, reps):
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            f()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    sc1 = synth.make_scene(10_000, 0, "uniform", seed=0)
+    v1 = synth.look_at((0.0, 0.0, -3.0), width=256, height=256)
+    out["c1_fwd_ms"] = round(1e3 * timed(lambda: O.render32(sc1, v1), 3), 3)
+    log(f"[cpu] c1 forward {out['c1_fwd_ms']} ms")
+    sc2 = synth.make_scene(1_000_000, 3, "mixture", seed=0)
+    w, h = (648, 420) if one_core else (1297, 840)
+    v2 = synth.look_at((1.5, 2.0, -4.5), width=w, height=h, s_v=2.0)
+    out["c2_resolution"] = [w, h]
+    out["c2_fwd_s"] = round(timed(lambda: O.render32(sc2, v2), 1 if one_core else 3), 3)
+    log(f"[cpu] c2 forward {out['c2_fwd_s']} s")
+    vp = O.render32(sc2, v2)
+    g = np.random.default_rng(1).normal(size=(3, h, w))
+    out["c2_bwd_fp64_s"] = round(timed(lambda: O.fp64_grads(sc2, v2, vp, g, 0.5), 1), 3)
+    out["c2_fwd_bwd_s"] = round(out["c2_fwd_s"] + out["c2_bwd_fp64_s"], 3)
+    log(f"[cpu] c2 FP64 backward {out['c2_bwd_fp64_s']} s")
+    del sc2, vp, g
+    sc4 = synth.make_scene(6_000_000, 3, "mixture", seed=0)
+    ds = synth.sweep_distances(64, 2.0, 200.0)
+    out["c4_frame_s"] = {}
+    for k in ((0, 63) if one_core else (0, 21, 42, 63)):
+        v = synth.look_at((0.0, 0.0, -float(ds[k])), width=1920, height=1080)
+        out["c4_frame_s"][str(k)] = round(timed(lambda: O.render32(sc4, v), 1), 3)
+        log(f"[cpu] c4 k={k} {out['c4_frame_s'][str(k)]} s")
+    return out
 
 
 # Algorithmic work of the blend: 18 flops per evaluated (pixel, entry) pair of the per-pixel
@@ -596,10 +773,20 @@ def cpu_baseline(steps, poses=3):
 # oracle's).  FP32 vector peak of MI355X: 256 CUs x 128 lanes x 2 flops x 2.4 GHz.
 FLOPS_PER_PAIR = 18
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE on the
-# same launches as the default run (profiles/k_blend_fwd_serve1080p_3M_hbm.txt), each scaled by
-# the same counter's reading for a 1 GiB device copy.  Emptied whenever the kernel changes.
-TRAFFIC = {"k_blend_fwd": 1233971775}
+# HBM bytes per launch of the dominant kernel: rocprofv3 FETCH_SIZE and WRITE_SIZE over the 20
+# timed launches (bench.py --profile timed-blend runs exactly those launches; the timed poses do
+# not depend on the warm-up count), each scaled by the same counter's reading for a 1 GiB device
+# copy (profiles/k_blend_fwd_serve1080p_3M_hbm.txt).  Emptied whenever the kernel changes.
+TRAFFIC = {"k_blend_fwd": 1130422841}
+
+
+def probe_copy(torch):
+    """One 1 GiB device-to-device copy: the reference reading for the HBM byte counters."""
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def main():
@@ -624,16 +811,40 @@ def main():
     ap.add_argument("--serve-light-requests", type=int, default=1000)
     ap.add_argument("--serve-capacity-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--profile", choices=("timed-blend", "multiview-eager", "train"), default=None,
+                    help="run one part only (for rocprofv3): the headline's timed launches, the 16-view "
+                         "step without the graph, or the 1M training iterations")
+    ap.add_argument("--cpu-suite", choices=("all", "one"), default=None,
+                    help="time the oracle on the parity configurations on all cores or one core, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: there is no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_suite:
+        if args.cpu_suite == "one":
+            os.environ["OMP_NUM_THREADS"] = "1"   # before any OpenMP runtime starts
+        print(json.dumps({"cpu_suite": args.cpu_suite, **cpu_suite(args.cpu_suite == "one")}), flush=True)
+        return
     import torch
     from paper_2510_09997_amd import _clod as C, synth
     from paper_2510_09997_amd.render import Batch, Scene
     C.load()
     assert torch.cuda.is_available()
+    if args.profile == "multiview-eager":
+        res = run_multiview_train(args, torch, C, Scene, synth)
+        if args.probe_copy:
+            probe_copy(torch)
+        print(json.dumps({"profile": args.profile, **res}), flush=True)
+        return
+    if args.profile == "train":
+        print(json.dumps({"profile": args.profile, **run_train(args, torch, C, Batch, Scene, synth)}), flush=True)
+        return
     serve, scene, b, steps = run_serving(args, torch, C, Batch, Scene, synth)
+    if args.profile == "timed-blend":
+        if args.probe_copy:
+            probe_copy(torch)
+        print(json.dumps(serve), flush=True)
+        return
     log(f"[bench] serving: {serve['fps']:.1f} frames/s batched, {serve.get('plain_fps', float('nan')):.1f} plain; "
         f"stages {serve['stage_ms']}")
     budget = None
@@ -690,6 +901,8 @@ def main():
                      "algorithmic_bytes": alg_bytes,
                      "avg_launch_ms": round(blend_ms, 4)},
         "dup_per_step": serve["dup_per_step"],
+        "rendered_per_step": serve.get("rendered_per_step"),
+        "hbm_served_step": serve.get("hbm"),
     }
     if train is not None:
         out["fwd_bwd_ms_per_iter"] = round(train["ms_per_iter"], 3)
@@ -697,6 +910,8 @@ def main():
         out["fwd_bwd_p99_ms"] = round(train["p99_ms"], 3)
         out["train_config"] = {"gaussians": 1_000_000, "sh_degree": 3, "resolution": [1297, 840],
                                "s_v": "log-uniform [1, 8]", "loss": "L1 + point-count regulariser"}
+        out["train_work"] = {k: train[k] for k in ("bwd_ms", "rendered", "pairs", "pixels", "fwd_pairs", "bwd_pairs",
+                                                   "hbm", "bwd_alu")}
     if budget is not None:
         out["budget_sweep"] = budget
     if strips is not None:
@@ -712,20 +927,16 @@ def main():
         log(f"[bench] LoD sweep fps (k=0,21,42,63): {[sw['ray_fps'][k] for k in (0, 21, 42, 63)]}")
         out["lod_sweep"] = sw
     if args.probe_copy:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        probe_copy(torch)
     if not args.no_serve:
         torch.cuda.empty_cache()
         st = run_serve_stream(args, torch, Scene, synth)
         out["serve_stream"] = {"resolutions": ["1280x720", "1920x1080", "3840x2160"], "s_v": "log-uniform [1, 16]",
                                "gaussians": 3_000_000, **st}
-        out["p99_ms"] = st["light"]["persistent"]["p99_ms"]
-        out["p50_ms"] = st["light"]["persistent"]["p50_ms"]
+        out["p99_ms"] = st["light"]["continuous"]["p99_ms"]
+        out["p50_ms"] = st["light"]["continuous"]["p50_ms"]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(steps)
+        out["cpu_baseline"] = cpu_baseline(steps[len(steps) - args.steps:])
     print(json.dumps(out), flush=True)
 
 

@@ -167,10 +167,13 @@ clod_status clod_render_fwd(const clod_batch *batch, float *rgb, float *T, uint3
    (accumulate != 0) the gradients of all parameter planes, including the decay factor and the
    normalised distance through the virtual distance scale and the frustum maximum.
    Requires the same scene and batch as the preceding clod_project / clod_bin_sort /
-   clod_render_fwd. */
+   clod_render_fwd.  pairs_dev (nullable, device int64 [3]) receives, added to its contents
+   (zero it first), the work of the per-pixel adjoint loop: (pixel, entry) lanes walked, pairs
+   whose exponential was evaluated (blended in the forward, power in range) and pairs that
+   contribute to the gradients; counting costs an extra pass over the per-tile partials. */
 clod_status clod_render_bwd(const clod_scene *scene, const clod_batch *batch, const float *T,
                             const uint32_t *last, const float *dL_drgb, const float *dL_deta,
-                            int32_t accumulate, const clod_scene_grad *grad, void *stream);
+                            int32_t accumulate, const clod_scene_grad *grad, int64_t *pairs_dev, void *stream);
 
 /* Sec. 3.2 mask and Sec. 3.3 eta_actual for many views without rendering: counts_dev
    (device int64 [n_views][3]) receives {n_frustum, n_mask, n_rendered} per view, with the

@@ -104,7 +104,7 @@ def load(path: str = LIB_PATH):
     L.clod_project.argtypes = [P, P, P, P, P]; L.clod_project.restype = i32
     L.clod_bin_sort.argtypes = [P, P, P]; L.clod_bin_sort.restype = i32
     L.clod_render_fwd.argtypes = [P, P, P, P, P, P]; L.clod_render_fwd.restype = i32
-    L.clod_render_bwd.argtypes = [P, P, P, P, P, P, i32, P, P]; L.clod_render_bwd.restype = i32
+    L.clod_render_bwd.argtypes = [P, P, P, P, P, P, i32, P, P, P]; L.clod_render_bwd.restype = i32
     L.clod_lod_count.argtypes = [P, P, P, P]; L.clod_lod_count.restype = i32
     L.clod_lod_count_noalloc.argtypes = [P, i32, P, P, P, P, P]; L.clod_lod_count_noalloc.restype = i32
     L.clod_loss.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, sz, P, P, P, P]
@@ -248,10 +248,10 @@ def clod_render_fwd(batch: clod_batch, rgb, T, last, pairs=None, stream=None):
 
 
 def clod_render_bwd(scene: clod_scene, batch: clod_batch, T, last, dL_drgb, dL_deta, accumulate: bool,
-                    grad: clod_scene_grad, stream=None):
+                    grad: clod_scene_grad, stream=None, pairs=None):
     _check(load().clod_render_bwd(ctypes.byref(scene), ctypes.byref(batch), _ptr(T, F32), _ptr(last, I32),
                                   _ptr(dL_drgb, F32), _ptr(dL_deta, F32), int(bool(accumulate)), ctypes.byref(grad),
-                                  _stream(stream)))
+                                  _ptr(pairs, I64), _stream(stream)))
 
 
 def clod_lod_count(scene: clod_scene, batch: clod_batch, counts, stream=None):

@@ -396,7 +396,7 @@ clod_status clod_render_fwd(const clod_batch* batch, float* rgb, float* T, uint3
 
 clod_status clod_render_bwd(const clod_scene* scene, const clod_batch* batch, const float* T,
                             const uint32_t* last, const float* dL_drgb, const float* dL_deta,
-                            int32_t accumulate, const clod_scene_grad* grad, void* stream) {
+                            int32_t accumulate, const clod_scene_grad* grad, int64_t* pairs_dev, void* stream) {
   g_err[0] = 0;
   clod_status st = check_scene(scene);
   if (st != CLOD_OK) return st;
@@ -415,7 +415,7 @@ clod_status clod_render_bwd(const clod_scene* scene, const clod_batch* batch, co
   const Layout& L = cx.L;
   char* w = (char*)batch->ws;
   HIP_TRY(launch_clear_rendered(L, batch->ws, s), "clear gscreen");
-  HIP_TRY(launch_blend_bwd(L, batch->ws, sorted_vals(batch, L, D), batch->params, T, last, dL_drgb, s),
+  HIP_TRY(launch_blend_bwd(L, batch->ws, sorted_vals(batch, L, D), batch->params, T, last, dL_drgb, pairs_dev, s),
           "blend backward");
   HIP_TRY(launch_gauss_bwd(*scene, L, batch->ws, batch->params, dL_deta, accumulate, *grad, s),
           "gaussian backward");

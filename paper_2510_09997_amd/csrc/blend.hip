@@ -176,16 +176,12 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   // per-entry predicates below are formed as lane masks and turned back into execution masks
   // with inverse ballots, so the termination bookkeeping stays in scalar registers.
   uint64_t dm = ballot64(!inside);
-  for (uint32_t base = rg.x; base < rg.y; base += 64) {
-    if (dm == ~0ull) break;
+  // One 64-entry batch at list position base, its records (g0, g1, g2) already in registers:
+  // staged in this wave's LDS slice, culled against the quadrant, then walked.
+  auto batch = [&](const uint32_t base, const float4& g0, const float4& g1, const float4& g2) {
     const uint32_t j = base + lane;
     bool rel = false;
     if (j < rg.y) {
-      uint32_t f = svals[j];
-      if ((int64_t)f >= VN) f = 0;   // defensive: the sort only emits indices < V*n
-      const float4 g0 = rec[kRecQuads * (int64_t)f];       // u, v, alpha'', radius
-      const float4 g1 = rec[kRecQuads * (int64_t)f + 1];   // conic A, B, C
-      const float4 g2 = rec[kRecQuads * (int64_t)f + 2];   // r, g, b
       const float cut = entry_cut(g0.z);
       s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
       s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
@@ -197,7 +193,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (mask == 0ull) continue;
+    if (mask == 0ull) return;
     // One entry: the contract's skip, exponential, clamp, termination and blend.  Below the
     // entry's cut (or above 0) the contract skips the pair whatever E returns; live pairs have
     // power in [cut, 0] with cut >= ln(1/255) - 0.01, inside cexp_core's range.  Only live
@@ -255,6 +251,37 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       a0 = s0[e0]; c0 = s1[e0]; b0 = s2[e0];
       pair(a1, c1, b1, e1);
       if (!more || dm == ~0ull) break;
+    }
+  };
+  // Software pipeline over the batches, unrolled by two with a register set each (A, B), so
+  // that nothing is copied between batches: while one batch is staged and walked, the records
+  // of the next and the sorted indices of the one after are in flight (index -> record is two
+  // dependent memory latencies per batch, which few resident waves -- a far frame's handful of
+  // long tiles -- cannot hide).  Every load is issued (positions past the list end read its
+  // last entry, which is not staged), so the wait counts stay static.
+  if (rg.y > rg.x) {
+    const uint32_t jmax = rg.y - 1;
+    auto index_at = [&](uint32_t q) {
+      const uint32_t f = svals[q < jmax ? q : jmax];
+      return (int64_t)f < VN ? f : 0u;   // defensive: the sort only emits indices < V*n
+    };
+    uint32_t ia = index_at(rg.x + lane);
+    uint32_t ib = index_at(rg.x + 64 + lane);
+    float4 a0 = rec[kRecQuads * (int64_t)ia], a1 = rec[kRecQuads * (int64_t)ia + 1], a2 = rec[kRecQuads * (int64_t)ia + 2];
+    float4 b0, b1, b2;
+    ia = index_at(rg.x + 128 + lane);
+    for (uint32_t base = rg.x; base < rg.y && dm != ~0ull; base += 128) {
+      b0 = rec[kRecQuads * (int64_t)ib];
+      b1 = rec[kRecQuads * (int64_t)ib + 1];
+      b2 = rec[kRecQuads * (int64_t)ib + 2];
+      ib = index_at(base + 192 + lane);
+      batch(base, a0, a1, a2);
+      if (base + 64 >= rg.y || dm == ~0ull) break;
+      a0 = rec[kRecQuads * (int64_t)ia];
+      a1 = rec[kRecQuads * (int64_t)ia + 1];
+      a2 = rec[kRecQuads * (int64_t)ia + 2];
+      ia = index_at(base + 256 + lane);
+      batch(base + 64, b0, b1, b2);
     }
   }
   if (inside) {
@@ -361,13 +388,18 @@ hipError_t launch_blend_stage(const Stage& st, hipStream_t s) {
 // waves in LDS, turned into the 9 screen-space partials and added to the global accumulator
 // once per tile.  The accumulator holds the nine partials of a record as
 // consecutive floats, so the flush sends each entry's nine atomics to one 36-byte span.
+// With kCount, each wave adds to the tile's (zeroed) partials the (pixel, entry) lanes its walk
+// visits, the pairs whose exponential it evaluates (blended in the forward, power in range) and
+// the pairs that contribute to the gradients.
+template <bool kCount>
 __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     const DevView* __restrict__ views, int V, uint32_t tiles_total, int64_t VN,
     const float4* __restrict__ rec, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ svals, const unsigned long long* __restrict__ hdr,
     float bg0, float bg1, float bg2, const float* __restrict__ Tin,
     const uint32_t* __restrict__ lastin, const float* __restrict__ dL_drgb,
-    float* __restrict__ gscreen, const uint32_t* __restrict__ order) {
+    float* __restrict__ gscreen, const uint32_t* __restrict__ order,
+    unsigned long long* __restrict__ pair_part) {
   __shared__ float4 s0[kBlock];   // u, v, A, B
   __shared__ float4 s1[kBlock];   // C, alpha'', r, g
   __shared__ float4 s2[kBlock];   // b, power cut, -, - (same stride as s0, s1: one address)
@@ -415,6 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
   __syncthreads();
   const uint32_t tmax = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
   const uint32_t end = rg.x + tmax;   // exclusive
+  unsigned long long n_walk = 0, n_live = 0, n_contrib = 0;   // wave-uniform (kCount)
   for (uint32_t hi = end; hi > rg.x;) {
     const uint32_t lo = hi > rg.x + kBlock ? hi - kBlock : rg.x;
     const int cnt = (int)(hi - lo);
@@ -461,11 +494,16 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
         // Live: blended in the forward (position < last) with power in [cut, 0].  Other lanes
         // compute discarded values (finite: their powers are tiny positives or below cut).
         const uint64_t lm = ballot64(pos < last) & ballot64(power <= 0.0f) & ballot64(power >= bc.y);
+        if (kCount) {
+          n_walk += 64;
+          n_live += (unsigned long long)__popcll(lm);
+        }
         if (lm == 0ull) continue;
         const float G = cexp_core(power);
         const float prod = c4.y * G;
         const float al = fminf(0.99f, prod);
         const uint64_t cm = ballot64(al >= kSkip) & lm;       // contributing lanes
+        if (kCount) n_contrib += (unsigned long long)__popcll(cm);
         if (cm == 0ull) continue;
         const uint64_t gm = ballot64(prod <= 0.99f) & cm;     // ... below the clamp
         const bool contrib = __builtin_amdgcn_inverse_ballot_w64(cm);
@@ -521,18 +559,32 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     }
     hi = lo;
   }
+  if (kCount && lane == 0) {
+    atomicAdd(pair_part + 3 * (int64_t)tile_i, n_walk);
+    atomicAdd(pair_part + 3 * (int64_t)tile_i + 1, n_live);
+    atomicAdd(pair_part + 3 * (int64_t)tile_i + 2, n_contrib);
+  }
 }
 
 hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_vals, clod_params prm,
-                            const float* T, const uint32_t* last, const float* dL_drgb,
+                            const float* T, const uint32_t* last, const float* dL_drgb, int64_t* pairs,
                             hipStream_t s) {
   if (L.tiles_total == 0) return hipSuccess;
   char* w = (char*)ws;
   const int nb = (int)xcd_grid(L.tiles_total);
-  hipLaunchKernelGGL(k_blend_bwd, dim3(nb), dim3(kBlock), 0, s, (const DevView*)(w + L.vinfo), L.V,
-                     L.tiles_total, L.VN, (const float4*)(w + L.rec), (const uint2*)(w + L.ranges),
-                     sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0], prm.bg[1],
-                     prm.bg[2], T, last, dL_drgb, (float*)(w + L.gscreen), (const uint32_t*)(w + L.order));
+  unsigned long long* part = pairs ? (unsigned long long*)(w + L.pair_part) : nullptr;
+  if (part) {
+    hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(part ? k_blend_bwd<true> : k_blend_bwd<false>, dim3(nb), dim3(kBlock), 0, s,
+                     (const DevView*)(w + L.vinfo), L.V, L.tiles_total, L.VN, (const float4*)(w + L.rec),
+                     (const uint2*)(w + L.ranges), sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0],
+                     prm.bg[1], prm.bg[2], T, last, dL_drgb, (float*)(w + L.gscreen), (const uint32_t*)(w + L.order),
+                     part);
+  if (part)
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(kBlock), 0, s,
+                       ReducePairsArgs{(const unsigned long long*)part, L.tiles_total, (unsigned long long*)pairs});
   return hipGetLastError();
 }
 

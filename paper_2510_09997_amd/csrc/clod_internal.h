@@ -613,7 +613,7 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
                             clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
                             const Sink& out);
 hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_vals, clod_params prm,
-                            const float* T, const uint32_t* last, const float* dL_drgb,
+                            const float* T, const uint32_t* last, const float* dL_drgb, int64_t* pairs,
                             hipStream_t s);
 hipError_t launch_clear_rendered(const Layout& L, void* ws, hipStream_t s);
 hipError_t launch_gauss_bwd(const clod_scene& sc, const Layout& L, void* ws, clod_params prm,

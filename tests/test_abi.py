@@ -156,7 +156,7 @@ def test_other_entry_points_validate_arguments():
     assert lib.clod_render_fwd(ctypes.byref(batch), FAKE, FAKE, FAKE, None, None) == C.CLOD_E_ARG
     g = C.clod_scene_grad()
     assert lib.clod_render_bwd(ctypes.byref(fake_scene()), ctypes.byref(batch), FAKE, FAKE, FAKE, None, 0,
-                               ctypes.byref(g), None) == C.CLOD_E_ARG
+                               ctypes.byref(g), None, None) == C.CLOD_E_ARG
     assert lib.clod_lod_count(ctypes.byref(fake_scene()), ctypes.byref(batch), FAKE, None) == C.CLOD_E_ARG
     assert lib.clod_loss(ctypes.byref(batch), FAKE, FAKE, ctypes.c_float(8.0), ctypes.c_float(1.0),
                          ctypes.c_float(0.0), None, 0, FAKE, FAKE, FAKE, None) == C.CLOD_E_ARG
@@ -171,7 +171,7 @@ def test_other_entry_points_validate_arguments():
                              ctypes.c_float(lam), scratch, nbytes, FAKE, FAKE, FAKE, None) == C.CLOD_E_ARG, lam
     # Missing gradient planes.
     assert lib.clod_render_bwd(ctypes.byref(fake_scene()), ctypes.byref(ok_batch), FAKE, FAKE, FAKE, None, 0,
-                               ctypes.byref(g), None) == C.CLOD_E_ARG
+                               ctypes.byref(g), None, None) == C.CLOD_E_ARG
     # Unknown inspection section.
     p, c = ctypes.c_void_p(0), ctypes.c_int64(0)
     assert lib.clod_inspect(ctypes.byref(ok_batch), 99, ctypes.byref(p), ctypes.byref(c)) == C.CLOD_E_ARG
