@@ -141,11 +141,13 @@ class Batch:
         return rgb, T, last
 
     def render_bwd(self, scene: Scene, T, last, dL_drgb, dL_deta=None, grads: dict | None = None,
-                   accumulate: bool = False) -> dict:
+                   accumulate: bool = False, pairs: torch.Tensor | None = None) -> dict:
+        """pairs (int64 [3], zeroed by the caller) receives the adjoint loop's work counters."""
         if grads is None:
             grads = {k: torch.empty_like(v) for k, v in scene.t.items()}
         C.clod_render_bwd(scene.c_struct(), self.c_struct(), T, last, dL_drgb.contiguous(),
-                          None if dL_deta is None else dL_deta.contiguous(), accumulate, C.make_grad(grads))
+                          None if dL_deta is None else dL_deta.contiguous(), accumulate, C.make_grad(grads),
+                          pairs=pairs)
         return grads
 
     def section(self, section: int, count: int | None = None) -> torch.Tensor:

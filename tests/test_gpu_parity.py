@@ -67,6 +67,35 @@ def test_long_tile_lists_bitexact_and_counted():
     assert 0 < g["pairs"][1] <= r["pair_classes"][1]
 
 
+@pytest.mark.parametrize("case", ["config1", "sh3_two_views"])
+def test_backward_pair_counters_match_the_contract(case):
+    """clod_render_bwd's work counters: the pairs that contribute to the gradients are exactly the
+    pairs the forward blended (the oracle's count), the live pairs (blended in the forward's
+    order before the pixel's last index, power in range) lie between those and the oracle's pairs
+    with power in [-5.6, 0], and the lanes walked cover the live pairs."""
+    log(f"case: backward counters {case}")
+    if case == "config1":
+        sc = synth.make_scene(10000, 0, "uniform", seed=0)
+        views = [synth.look_at((0, 0, -3), width=256, height=256, s_v=1.0)]
+    else:
+        sc = synth.make_scene(30000, 3, "mixture", seed=8)
+        views = [synth.look_at((0.5, 1.0, -6.0), width=144, height=112, s_v=1.5),
+                 synth.look_at((-4.0, 0.5, 3.0), width=97, height=75, s_v=3.0)]
+    g = gpu_forward(sc, views)
+    want = np.zeros(3, dtype=np.int64)
+    for v in views:
+        want += np.asarray(O.render32(sc, v)["pair_classes"], dtype=np.int64)
+    b = g["batch"]
+    dL = torch.from_numpy(np.random.default_rng(9).normal(size=3 * b.pixels).astype(np.float32)).cuda()
+    bp = torch.zeros(3, dtype=torch.int64, device="cuda")
+    b.render_bwd(g["scene"], g["T_flat"], g["last_flat"], dL, pairs=bp)
+    walked, live, contrib = (int(x) for x in bp.cpu().numpy())
+    log(f"  oracle {want.tolist()}, forward {g['pairs'].tolist()}, backward {[walked, live, contrib]}")
+    assert contrib == want[2] == g["pairs"][2]
+    assert contrib <= live <= want[1]
+    assert live <= walked
+
+
 def test_multiview_ragged_forward_bitexact():
     """Three views of different (ragged) resolutions and LoD scales in one batch."""
     log("case: multiview ragged")
