@@ -388,7 +388,7 @@ clod_status clod_render_fwd(const clod_batch* batch, float* rgb, float* T, uint3
   st = dup_check(batch, D);
   if (st != CLOD_OK) return st;
   if (!rgb || !T || !last) return fail(CLOD_E_ARG, "rgb, T and last must be non-NULL");
-  HIP_TRY(launch_blend_fwd(cx.L, batch->ws, sorted_vals(batch, cx.L, D), batch->params, rgb, T, last,
+  HIP_TRY(launch_blend_fwd(cx.L, batch->ws, sorted_vals(batch, cx.L, D), D.cap, batch->params, rgb, T, last,
                            pairs_dev, Sink((hipStream_t)stream)),
           "blend forward");
   return CLOD_OK;
@@ -656,7 +656,7 @@ clod_status clod_server_submit(clod_server* server, const clod_scene* scene, con
   hipError_t e = project_stages(*scene, b.views_dev, b.params, cx.L, b.ws, nullptr, nullptr, out);
   if (e == hipSuccess) e = bin_stages(cx.L, b.ws, D, b.dup, out);
   if (e == hipSuccess)
-    e = launch_blend_fwd(cx.L, b.ws, sorted_vals(&b, cx.L, D), b.params, rgb, T, last, nullptr, out);
+    e = launch_blend_fwd(cx.L, b.ws, sorted_vals(&b, cx.L, D), D.cap, b.params, rgb, T, last, nullptr, out);
   if (P.full) return fail(CLOD_E_UNSUPPORTED, "the job needs more than %d stages", kMaxStages);
   HIP_TRY(e, "job stages");
   HIP_TRY(server_publish(S, P, b.n_views, b.views_host, (const char*)b.ws + cx.L.hdr, seq), "publish");

@@ -25,8 +25,20 @@ __device__ __forceinline__ uint32_t xcd_tile_pos(uint32_t b) {
   return (r * kXcds + x) * kXcdRun + i;
 }
 
-static inline uint32_t xcd_grid(uint32_t tiles) {
+__host__ __device__ inline uint32_t xcd_grid(uint32_t tiles) {
   return (tiles + kXcds * kXcdRun - 1) / (kXcds * kXcdRun) * (kXcds * kXcdRun);
+}
+
+// Long tiles are taken by four workgroups each, in runs of eight tiles (one tile per XCD).
+__host__ __device__ inline uint32_t long_grid(uint32_t long_tiles) {
+  return (4 * long_tiles + 4 * kXcds - 1) / (4 * kXcds) * (4 * kXcds);
+}
+
+// The long tiles of this blend: the first tord[kTileLongWord] positions of the tile order
+// (written by the tile ordering stage), within the bound the launch was sized for.
+__device__ __forceinline__ uint32_t long_tiles(const BlendArgs& a) {
+  const uint32_t nl = a.tord[kTileLongWord];
+  return nl < a.long_max ? nl : a.long_max;
 }
 
 __device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_t tile) {
@@ -70,10 +82,13 @@ __device__ __forceinline__ float box_qmin(float A, float B, float C, float X0, f
 // of the box edges).  With AC / (AC - B^2) <= 5e4 the binary32 evaluation is within 1.2 % of
 // the exact form (and the vertex rounding is negligible), so the exact minimum exceeds
 // 2.4 |cut| and the same argument as the circle test applies.
+// kB x kB pixel block with corner (x0, y0).
+template <int kB = 8>
 __device__ __forceinline__ bool ellipse_reaches(float u, float v, float A, float B, float C, float cut,
                                                 float x0, float y0) {
-  const float X0 = (x0 + 0.499f) - u, X1 = (x0 + 7.501f) - u;
-  const float Y0 = (y0 + 0.499f) - v, Y1 = (y0 + 7.501f) - v;
+  constexpr float kHi = (float)kB - 0.499f;
+  const float X0 = (x0 + 0.499f) - u, X1 = (x0 + kHi) - u;
+  const float Y0 = (y0 + 0.499f) - v, Y1 = (y0 + kHi) - v;
   return box_qmin(A, B, C, X0, X1, Y0, Y1) < 2.5f * -cut;
 }
 
@@ -105,18 +120,26 @@ __device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float A, flo
   return m;
 }
 
-// The same test for one 8x8 pixel block with corner (x0, y0): 1 if the entry may touch it.
+// The same test for one kB x kB pixel block with corner (x0, y0): 1 if the entry may touch it.
+template <int kB>
 __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, float B, float C, float rad,
                                                    float cut, float x0, float y0) {
   if (cut > 0.0f) return 0u;
   const float ac = A * C;
   const float det = ac - B * B;
   if (!(det > 2e-5f * ac) || !(rad < 1e6f)) return 1u;
+  constexpr float kHi = (float)kB - 0.5f;
   const float rc = __builtin_amdgcn_sqrtf(2.4f * -cut) * rad * (1.0f / 3.0f) + 0.5f;
-  const float ddx = fmaxf(0.0f, fmaxf(x0 + 0.5f - u, u - (x0 + 7.5f)));
-  const float ddy = fmaxf(0.0f, fmaxf(y0 + 0.5f - v, v - (y0 + 7.5f)));
-  return (ddx * ddx + ddy * ddy <= rc * rc && ellipse_reaches(u, v, A, B, C, cut, x0, y0)) ? 1u : 0u;
+  const float ddx = fmaxf(0.0f, fmaxf(x0 + 0.5f - u, u - (x0 + kHi)));
+  const float ddy = fmaxf(0.0f, fmaxf(y0 + 0.5f - v, v - (y0 + kHi)));
+  return (ddx * ddx + ddy * ddy <= rc * rc && ellipse_reaches<kB>(u, v, A, B, C, cut, x0, y0)) ? 1u : 0u;
 }
+
+// Tiles whose list holds at least 2^(kLongBucket - 1) entries (the dense far views of a large
+// scene) are blended with 4x4-pixel blocks per wave: a wave walks only the entries that may
+// reach its block, and sixteen waves share the tile instead of four.  The tile order puts them
+// first (longest first): they are the first tord[kTileLongWord] positions, taken by the leading
+// workgroups of the launch.
 
 // Forward blend.  Each wave owns one 8x8 quadrant of a tile (lane l: pixel (l & 7, l >> 3))
 // and runs on its own: it stages 64 entries of the tile's sorted list at a time in its
@@ -131,8 +154,11 @@ struct TileLds {
 
 // One tile, at position pos of the batch's tile order, by the 256 threads of the block (four
 // independent waves).  Shared by the per-batch launch (k_blend_fwd) and the persistent server.
-template <bool kCount>
-__device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, TileLds& S) {
+// kB = 8: the four waves take the tile's four 8x8 quadrants.  kB = 4: the four waves take the
+// 4x4 blocks 4 sub .. 4 sub + 3 of the tile (row-major over its 4 x 4 blocks), lanes 0..15
+// one pixel each.
+template <bool kCount, int kB = 8>
+__device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, TileLds& S, uint32_t sub = 0) {
   auto& st = S.st;
   const DevView* __restrict__ views = a.views;
   const int V = a.V;
@@ -150,6 +176,8 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   const uint32_t t = threadIdx.x;
   if (a.hdr[kHdrOverflow]) return;
   if (pos >= tiles_total) return;
+  // The long tiles are taken as 4x4 blocks.
+  if ((kB == 8) != (pos >= long_tiles(a))) return;
   const int tile_i = (int)order[pos];
   const int v = view_of_tile(views, V, (uint32_t)tile_i);
   const DevView& Vw = views[v];
@@ -157,10 +185,11 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
   const int wave = (int)(t >> 6);
   const uint32_t lane = lane_id();
-  const int qx0 = tx * kTile + (wave & 1) * 8, qy0 = ty * kTile + (wave >> 1) * 8;
-  const int px = qx0 + (int)(lane & 7);
-  const int py = qy0 + (int)(lane >> 3);
-  const bool inside = px < Vw.width && py < Vw.height;
+  const int blk = kB == 8 ? wave : (int)sub * 4 + wave;
+  const int qx0 = tx * kTile + (blk % (kTile / kB)) * kB, qy0 = ty * kTile + (blk / (kTile / kB)) * kB;
+  const int px = qx0 + (int)(lane % kB);
+  const int py = qy0 + (int)(lane / kB);
+  const bool inside = lane < (uint32_t)(kB * kB) && px < Vw.width && py < Vw.height;
   // Pixel centres and quadrant corners in frame coordinates (the viewport origin added).
   const float pcx = (float)(px + Vw.vx) + 0.5f, pcy = (float)(py + Vw.vy) + 0.5f;
   const float fqx = (float)(qx0 + Vw.vx), fqy = (float)(qy0 + Vw.vy);
@@ -186,7 +215,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
       s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
       s2[lane] = make_float4(g2.z, cut, 0.f, 0.f);
-      rel = (quadrant_mask1(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, fqx, fqy)) != 0u;
+      rel = (quadrant_mask1<kB>(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, fqx, fqy)) != 0u;
     }
     uint64_t mask = ballot64(rel);
     // The staged entries are read by other lanes of this wave: wait for the LDS writes.
@@ -311,11 +340,41 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   }
 }
 
-// Per-batch launch: one workgroup per tile, in the XCD-aware order.
+// Long tiles: four workgroups per tile, on one XCD (workgroups b, b + 8, b + 16, b + 24 take
+// the same tile: consecutive workgroups go round-robin to the eight XCDs).
+__device__ __forceinline__ void long_item(uint32_t b, uint32_t& pos, uint32_t& sub) {
+  const uint32_t x = b % kXcds, j = b / kXcds;
+  sub = j % 4;
+  pos = x + kXcds * (j / 4);
+}
+
+// Item b of the blend stage: the leading long_grid(long_tiles) items take the long tiles as
+// 4x4 blocks, the next xcd_grid(tiles) items one tile each in the XCD-aware order (both in one
+// launch, so that the long tiles run beside the others).  Items past these (the launch is
+// sized for the most long tiles the pair capacity allows) map past the last tile and exit.
+template <bool kCount>
+__device__ __forceinline__ void blend_item(const BlendArgs& a, uint32_t b, TileLds& S) {
+  const uint32_t lb = long_grid(long_tiles(a));
+  if (b < lb) {
+    uint32_t pos, sub;
+    long_item(b, pos, sub);
+    blend_tile<kCount, 4>(a, pos, S, sub);
+  } else {
+    blend_tile<kCount>(a, xcd_tile_pos(b - lb), S);
+  }
+}
+
+// Items a blend stage needs once the tile order is known (the resident kernel sizes its
+// claims by it; a per-stage launch covers the bound instead).
+__device__ __forceinline__ uint32_t blend_items(const BlendArgs& a) {
+  return long_grid(long_tiles(a)) + xcd_grid(a.tiles_total);
+}
+
+// Per-batch launch: one workgroup per tile (four per long tile).
 template <bool kCount>
 __global__ __launch_bounds__(kBlock) void k_blend_fwd(BlendArgs a) {
   __shared__ TileLds S;
-  blend_tile<kCount>(a, xcd_tile_pos(blockIdx.x), S);
+  blend_item<kCount>(a, blockIdx.x, S);
 }
 
 // Sums the per-tile pair partials into the caller's counters (one block, three atomics).
@@ -334,7 +393,7 @@ __device__ __forceinline__ void reduce_pairs_body(const ReducePairsArgs& r, Blk)
 }
 __global__ __launch_bounds__(kBlock) void k_reduce_pairs(ReducePairsArgs r) { reduce_pairs_body(r, grid_blk()); }
 
-hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals,
+hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals, int64_t dup_cap,
                             clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
                             const Sink& out) {
   if (L.tiles_total == 0) return hipSuccess;
@@ -344,13 +403,17 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
     hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, out);
     if (e != hipSuccess) return e;
   }
+  // At most dup_cap / 2^(kLongBucket - 1) tiles can be long: the launch covers that many.
+  const int64_t cap_long = dup_cap / (1ll << (kLongBucket - 1));
+  const uint32_t long_max = (uint32_t)(cap_long < (int64_t)L.tiles_total ? cap_long : (int64_t)L.tiles_total);
   Stage st{};
   st.kind = kStBlend;
-  st.items = xcd_grid(L.tiles_total);
+  st.items = long_grid(long_max) + xcd_grid(L.tiles_total);
   st.block = kBlock;
   st.a.blend = BlendArgs{(const DevView*)(w + L.vinfo), L.V, L.tiles_total, L.VN, (const float4*)(w + L.rec),
                          (const uint2*)(w + L.ranges), sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0],
-                         prm.bg[1], prm.bg[2], rgb, T, last, part, (const uint32_t*)(w + L.order), part ? 1 : 0};
+                         prm.bg[1], prm.bg[2], rgb, T, last, part, (const uint32_t*)(w + L.order),
+                         (const uint32_t*)(w + L.tord), long_max, part ? 1 : 0};
   hipError_t e = out.put(st);
   if (e == hipSuccess && part) {
     Stage r{};

@@ -17,10 +17,13 @@ constexpr int kRecQuads = 4;
 constexpr int kRecBytes = kRecQuads * 16;
 constexpr int kScanItems = 16;             // items per thread in the tiles-touched scan
 constexpr int kScanChunk = kBlock * kScanItems;
-// Tile ordering by list length: 33 bucket counts + 33 bucket cursors (u32).
+// Tile ordering by list length: 33 bucket counts + 33 bucket cursors + the number of long
+// tiles (lists of at least 2^(kLongBucket - 1) entries, the leading positions of the order).
 constexpr int kEmitTile = 2048;            // tile pairs per output chunk of the emission
 constexpr int kTileBuckets = 33;
-constexpr int kTileOrderWords = 2 * kTileBuckets;
+constexpr int kLongBucket = 14;            // long tiles: 8,192 entries or more
+constexpr int kTileLongWord = 2 * kTileBuckets;
+constexpr int kTileOrderWords = 2 * kTileBuckets + 1;
 constexpr int kTileOrderChunk = 1024;       // tiles per block in the ordering kernels
 constexpr int kSortItems = 8;              // keys per thread per radix tile
 constexpr int kSortTile = kBlock * kSortItems;   // 2048 keys per radix tile
@@ -516,7 +519,9 @@ struct TileOrderArgs {
 struct BlendArgs {
   const DevView* views; int32_t V; uint32_t tiles_total; int64_t VN; const float4* rec; const uint2* ranges;
   const uint32_t* svals; const unsigned long long* hdr; float bg0, bg1, bg2; float* rgb; float* T; uint32_t* last;
-  unsigned long long* pair_part; const uint32_t* order; int32_t count;
+  unsigned long long* pair_part; const uint32_t* order; const uint32_t* tord;
+  uint32_t long_max;      // most long tiles the launch covers (the pair capacity's bound)
+  int32_t count;
 };
 struct ReducePairsArgs {
   const unsigned long long* part; uint32_t tiles; unsigned long long* out;
@@ -609,7 +614,7 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
 hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
                          const Sink& out);
 
-hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals,
+hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals, int64_t dup_cap,
                             clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
                             const Sink& out);
 hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_vals, clod_params prm,

@@ -279,15 +279,28 @@ __device__ bool srv_run(int32_t kind, const Stage& st, Blk b, SrvLds& U) {
     case kStTileCount: tile_count_body(uniform_copy(st.a.tile_order), b); return true;
     case kStTileScatter: tile_scatter_body(uniform_copy(st.a.tile_order), b); return true;
     case kStBlend: {
-      // Tiles in claim order: the longest-first order of the tile ordering stage.
+      // Items in claim order: the long tiles' blocks first, then the tiles.
       const BlendArgs a = uniform_copy(st.a.blend);
-      if (a.count) blend_tile<true>(a, b.id, U.tile);
-      else blend_tile<false>(a, b.id, U.tile);
+      if (a.count) blend_item<true>(a, b.id, U.tile);
+      else blend_item<false>(a, b.id, U.tile);
       return true;
     }
     case kStReducePairs: reduce_pairs_body(uniform_copy(st.a.reduce_pairs), b); return true;
     default: return false;
   }
+}
+
+// Items of stage k of a job as it opens (after an acquire of the stages before it).  A
+// blend claims only the items its tile order needs, not the bound its per-stage launch covers.
+__device__ uint32_t open_items(const SrvJob& job, uint32_t k, int32_t kind) {
+  if (kind == kStBlend) {
+    const BlendArgs& a = job.st[k].a.blend;
+    const uint32_t* tord =
+        reinterpret_cast<const uint32_t*>(ld_agent(reinterpret_cast<const uint64_t*>(&a.tord)));
+    const uint32_t nl = ld_agent(tord + kTileLongWord), lmax = ld_agent(&a.long_max);
+    return long_grid(nl < lmax ? nl : lmax) + xcd_grid(ld_agent(&a.tiles_total));
+  }
+  return ld_agent(&job.st[k].items);
 }
 
 // Thread 0 of a worker: n items of `stage` in `slot` are done (and released).  The worker
@@ -302,8 +315,8 @@ __device__ void srv_complete(SrvDev* D, SrvHost* H, uint32_t slot, uint32_t stag
   const uint32_t ns = ld_agent(&job.n_stages);
   const uint32_t next = stage + 1;
   if (next < ns) {
-    const uint32_t items = ld_agent(&job.st[next].items);
     const int32_t kind = ld_agent(&job.st[next].kind);
+    const uint32_t items = open_items(job, next, kind);
     atomicExch(&S.done, 0u);
     __hip_atomic_exchange(&S.claim, claim_word(next, claim_lchunk(kind, items, workers), items), __ATOMIC_RELEASE,
                           __HIP_MEMORY_SCOPE_AGENT);

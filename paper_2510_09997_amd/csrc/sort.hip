@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(TileOrderArgs a) { tile_c
 
 // Scatter: bucket b starts after all longer buckets; each block reserves its slice of every
 // bucket with one global atomic (tord[33 + b]) and places its tiles with LDS cursors.
-__device__ __forceinline__ void tile_scatter_body(const TileOrderArgs& a, Blk b) {
+__device__ __forceinline__ void tile_scatter_body(const TileOrderArgs& a, Blk blk) {
   __shared__ uint32_t cnt[kTileBuckets];
   __shared__ uint32_t cur[kTileBuckets];
   const uint2* __restrict__ ranges = a.ranges;
@@ -773,7 +773,7 @@ __device__ __forceinline__ void tile_scatter_body(const TileOrderArgs& a, Blk b)
   if (threadIdx.x < kTileBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
   const bool ovf = a.hdr[kHdrOverflow] != 0ull;
-  const uint32_t t0 = b.id * kTileOrderChunk;
+  const uint32_t t0 = blk.id * kTileOrderChunk;
   for (uint32_t t = t0 + threadIdx.x; t < tiles && t < t0 + kTileOrderChunk; t += kBlock)
     atomicAdd(&cnt[len_bucket(ranges[t], ovf)], 1u);
   __syncthreads();
@@ -782,6 +782,8 @@ __device__ __forceinline__ void tile_scatter_body(const TileOrderArgs& a, Blk b)
     uint32_t start = 0;
     for (uint32_t c = b + 1; c < (uint32_t)kTileBuckets; ++c) start += tord[c];
     cur[b] = cnt[b] ? start + atomicAdd(&tord[kTileBuckets + b], cnt[b]) : 0u;
+    // The long tiles' count (the start of the first short bucket), for the blend launches.
+    if (b == kLongBucket - 1 && blk.id == 0) tord[kTileLongWord] = start;
   }
   __syncthreads();
   for (uint32_t t = t0 + threadIdx.x; t < tiles && t < t0 + kTileOrderChunk; t += kBlock) {
