@@ -155,8 +155,8 @@ struct TileLds {
 // One tile, at position pos of the batch's tile order, by the 256 threads of the block (four
 // independent waves).  Shared by the per-batch launch (k_blend_fwd) and the persistent server.
 // kB = 8: the four waves take the tile's four 8x8 quadrants.  kB = 4: the four waves take the
-// 4x4 blocks 4 sub .. 4 sub + 3 of the tile (row-major over its 4 x 4 blocks), lanes 0..15
-// one pixel each.
+// 4x4 blocks 4 sub .. 4 sub + 3 of the tile (row-major over its 4 x 4 blocks); lane 16 g + p
+// takes pixel p of the block, and the lanes of row 0 (g = 0) own the results.
 template <bool kCount, int kB = 8>
 __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, TileLds& S, uint32_t sub = 0) {
   auto& st = S.st;
@@ -187,9 +187,11 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   const uint32_t lane = lane_id();
   const int blk = kB == 8 ? wave : (int)sub * 4 + wave;
   const int qx0 = tx * kTile + (blk % (kTile / kB)) * kB, qy0 = ty * kTile + (blk / (kTile / kB)) * kB;
-  const int px = qx0 + (int)(lane % kB);
-  const int py = qy0 + (int)(lane / kB);
-  const bool inside = lane < (uint32_t)(kB * kB) && px < Vw.width && py < Vw.height;
+  const uint32_t pl = kB == 4 ? (lane & 15u) : lane;   // the lane's pixel within the block
+  const int px = qx0 + (int)(pl % kB);
+  const int py = qy0 + (int)(pl / kB);
+  const bool inside = px < Vw.width && py < Vw.height;
+  const bool own = inside && (kB == 8 || lane < 16u);
   // Pixel centres and quadrant corners in frame coordinates (the viewport origin added).
   const float pcx = (float)(px + Vw.vx) + 0.5f, pcy = (float)(py + Vw.vy) + 0.5f;
   const float fqx = (float)(qx0 + Vw.vx), fqy = (float)(qy0 + Vw.vy);
@@ -204,7 +206,79 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   // Lanes whose pixel has terminated (or lies outside the frame), as a wave-uniform mask: the
   // per-entry predicates below are formed as lane masks and turned back into execution masks
   // with inverse ballots, so the termination bookkeeping stays in scalar registers.
-  uint64_t dm = ballot64(!inside);
+  uint64_t dm = ballot64(!own);
+  // 4x4 blocks: the entries of a batch that may reach the block, four at a time.  Row g of the
+  // wave evaluates entry g of the group for the block's 16 pixels (power, live test,
+  // exponential, clamp: the four exponentials are computed side by side); row 0 then takes the
+  // four entries in list order through the contract's termination test and blend, the same
+  // operations in the same order as one entry at a time.  Terminated pixels (dm, bits 0..15)
+  // drop out of the later entries of a group; their values for those entries are never used.
+  auto walk4 = [&](const uint32_t base, uint64_t mask) {
+    const uint32_t row = lane >> 4;
+    const uint32_t p0 = base - rg.x;
+    // One entry of the group for row 0's pixels: alpha (valid on the live lanes lv, bits
+    // 0..15), the entry's colour and list position.
+    auto step = [&](const float al, const uint64_t lv, const float c0, const float c1, const float c2,
+                    const uint32_t pos) {
+      const uint64_t lm = lv & ~dm & 0xFFFFull;
+      if (lm == 0ull) return;
+      float Tn = al;
+      if (__builtin_amdgcn_inverse_ballot_w64(lm)) Tn = T * (1.0f - al);
+      const uint64_t um = ballot64(al >= kSkip) & lm;
+      const uint64_t km = ballot64(Tn >= kTmin);
+      const uint64_t bm = um & km;
+      dm |= um & ~km;
+      if (__builtin_amdgcn_inverse_ballot_w64(bm)) {
+        const float w = al * T;
+        cr = fmaf_(c0, w, cr);
+        cg = fmaf_(c1, w, cg);
+        cb = fmaf_(c2, w, cb);
+        T = Tn;
+        last = pos + 1u;
+      }
+      if (kCount) {
+        if (__builtin_amdgcn_inverse_ballot_w64(um & ~km)) term = pos;
+        nexp += __builtin_amdgcn_inverse_ballot_w64(lm) ? 1u : 0u;
+        nblend += __builtin_amdgcn_inverse_ballot_w64(bm) ? 1u : 0u;
+      }
+    };
+    while (mask != 0ull && dm != ~0ull) {
+      const int f0 = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const bool h1 = mask != 0ull;
+      const int f1 = h1 ? __builtin_ctzll(mask) : f0;
+      mask &= mask - 1;
+      const bool h2 = mask != 0ull;
+      const int f2 = h2 ? __builtin_ctzll(mask) : f0;
+      mask &= mask - 1;
+      const bool h3 = mask != 0ull;
+      const int f3 = h3 ? __builtin_ctzll(mask) : f0;
+      mask &= mask - 1;
+      const int fr = row == 0u ? f0 : row == 1u ? f1 : row == 2u ? f2 : f3;
+      const float4 a = s0[fr], c = s1[fr];
+      const float4 bc = s2[fr];
+      // Colours of entries 1..3 for row 0 (LDS broadcasts).
+      const float4 q1 = s1[f1], q2 = s1[f2], q3 = s1[f3];
+      const float b1 = s2[f1].x, b2 = s2[f2].x, b3 = s2[f3].x;
+      const float dx = a.x - pcx, dy = a.y - pcy;
+      const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
+      const uint64_t slots = 0xFFFFull | (h1 ? 0xFFFF0000ull : 0ull) | (h2 ? 0xFFFF00000000ull : 0ull) |
+                             (h3 ? 0xFFFF000000000000ull : 0ull);
+      const uint64_t dm4 = (dm & 0xFFFFull) * 0x0001000100010001ull;
+      const uint64_t live = ballot64(power <= 0.0f) & ballot64(power >= bc.y) & ~dm4 & slots;
+      if (live == 0ull) continue;
+      float al = power;
+      if (__builtin_amdgcn_inverse_ballot_w64(live)) al = fminf(0.99f, c.y * cexp_core(power));
+      // Rows 1, 2, 3 of al into row 0 (whole-wave row swaps).
+      const auto x16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(al), __float_as_uint(al), false, false);
+      const auto x32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(al), __float_as_uint(al), false, false);
+      const auto x48 = __builtin_amdgcn_permlane32_swap(x16[1], x16[1], false, false);
+      step(al, live, c.z, c.w, bc.x, p0 + (uint32_t)f0);
+      step(__uint_as_float(x16[1]), live >> 16, q1.z, q1.w, b1, p0 + (uint32_t)f1);
+      step(__uint_as_float(x32[1]), live >> 32, q2.z, q2.w, b2, p0 + (uint32_t)f2);
+      step(__uint_as_float(x48[1]), live >> 48, q3.z, q3.w, b3, p0 + (uint32_t)f3);
+    }
+  };
   // One 64-entry batch at list position base, its records (g0, g1, g2) already in registers:
   // staged in this wave's LDS slice, culled against the quadrant, then walked.
   auto batch = [&](const uint32_t base, const float4& g0, const float4& g1, const float4& g2) {
@@ -223,6 +297,10 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (mask == 0ull) return;
+    if constexpr (kB == 4) {
+      walk4(base, mask);
+      return;
+    }
     // One entry: the contract's skip, exponential, clamp, termination and blend.  Below the
     // entry's cut (or above 0) the contract skips the pair whatever E returns; live pairs have
     // power in [cut, 0] with cut >= ln(1/255) - 0.01, inside cexp_core's range.  Only live
@@ -313,7 +391,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       batch(base + 64, b0, b1, b2);
     }
   }
-  if (inside) {
+  if (own) {
     const int64_t P = (int64_t)Vw.pix_base;
     const int64_t HW = (int64_t)Vw.width * Vw.height;
     const int64_t p = (int64_t)py * Vw.width + px;
@@ -327,7 +405,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     // Pairs the contract's per-pixel loop evaluates: up to and including the terminating
     // entry, else the whole list.  The four wave totals are added to the tile's (zeroed)
     // partials.
-    const unsigned long long ev = !inside ? 0ull : (term != 0xFFFFFFFFu ? (unsigned long long)term + 1ull
+    const unsigned long long ev = !own ? 0ull : (term != 0xFFFFFFFFu ? (unsigned long long)term + 1ull
                                                                          : (unsigned long long)(rg.y - rg.x));
     const unsigned long long es = wave_sum(ev);
     const unsigned long long x = wave_sum((unsigned long long)nexp);
