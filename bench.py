@@ -612,7 +612,7 @@ def run_serve_stream(args, torch, Scene, synth):
 STAGE_NAMES = ["end", "view_setup", "fill", "frustum_max", "fold", "classify", "project", "select_hist",
                "select_pick", "scan_reduce", "scan_partials", "compact", "radix_up", "radix_scan", "radix_down",
                "emit_reduce", "emit_partials", "emit_offsets", "emit", "ranges", "tile_count", "tile_scatter", "blend",
-               "reduce_pairs"]
+               "reduce_pairs", "long_mask"]
 
 
 def server_timeline(torch, scene, synth, reps=12):

@@ -304,6 +304,12 @@ static const uint32_t* sorted_vals(const clod_batch* b, const Layout& L, const D
   return (const uint32_t*)((const char*)b->dup + (sorted_buffer(L.tiles_total) ? D.vals1 : D.vals0));
 }
 
+static BlendBufs blend_bufs(const clod_batch* b, const Layout& L, const DupLayout& D) {
+  const bool odd = sorted_buffer(L.tiles_total) != 0;
+  char* dp = (char*)b->dup;
+  return BlendBufs{sorted_vals(b, L, D), (uint32_t*)(dp + (odd ? D.vals0 : D.vals1)), D.cap};
+}
+
 }  // namespace clod
 
 using namespace clod;
@@ -388,8 +394,8 @@ clod_status clod_render_fwd(const clod_batch* batch, float* rgb, float* T, uint3
   st = dup_check(batch, D);
   if (st != CLOD_OK) return st;
   if (!rgb || !T || !last) return fail(CLOD_E_ARG, "rgb, T and last must be non-NULL");
-  HIP_TRY(launch_blend_fwd(cx.L, batch->ws, sorted_vals(batch, cx.L, D), D.cap, batch->params, rgb, T, last,
-                           pairs_dev, Sink((hipStream_t)stream)),
+  HIP_TRY(launch_blend_fwd(cx.L, batch->ws, blend_bufs(batch, cx.L, D), batch->params, rgb, T, last, pairs_dev,
+                           Sink((hipStream_t)stream)),
           "blend forward");
   return CLOD_OK;
 }
@@ -656,7 +662,7 @@ clod_status clod_server_submit(clod_server* server, const clod_scene* scene, con
   hipError_t e = project_stages(*scene, b.views_dev, b.params, cx.L, b.ws, nullptr, nullptr, out);
   if (e == hipSuccess) e = bin_stages(cx.L, b.ws, D, b.dup, out);
   if (e == hipSuccess)
-    e = launch_blend_fwd(cx.L, b.ws, sorted_vals(&b, cx.L, D), D.cap, b.params, rgb, T, last, nullptr, out);
+    e = launch_blend_fwd(cx.L, b.ws, blend_bufs(&b, cx.L, D), b.params, rgb, T, last, nullptr, out);
   if (P.full) return fail(CLOD_E_UNSUPPORTED, "the job needs more than %d stages", kMaxStages);
   HIP_TRY(e, "job stages");
   HIP_TRY(server_publish(S, P, b.n_views, b.views_host, (const char*)b.ws + cx.L.hdr, seq), "publish");

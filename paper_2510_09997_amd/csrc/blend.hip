@@ -19,6 +19,7 @@ namespace clod {
 // rounded up to a multiple of 8C; the map is a bijection on it and blocks past the last tile
 // exit at once.
 constexpr uint32_t kXcds = 8, kXcdRun = 16;
+constexpr uint32_t kLongMaskBlocks = 1024;   // grid of the very-long-tile mask stage
 
 __device__ __forceinline__ uint32_t xcd_tile_pos(uint32_t b) {
   const uint32_t x = b % kXcds, j = b / kXcds, r = j / kXcdRun, i = j % kXcdRun;
@@ -35,10 +36,15 @@ __host__ __device__ inline uint32_t long_grid(uint32_t long_tiles) {
 }
 
 // The long tiles of this blend: the first tord[kTileLongWord] positions of the tile order
-// (written by the tile ordering stage), within the bound the launch was sized for.
+// (written by the tile ordering stage), within the bound the launch was sized for; the very
+// long ones (65,536 entries or more) are the first tord[kTileVeryLongWord] of them.
 __device__ __forceinline__ uint32_t long_tiles(const BlendArgs& a) {
   const uint32_t nl = a.tord[kTileLongWord];
   return nl < a.long_max ? nl : a.long_max;
+}
+__device__ __forceinline__ uint32_t very_long_tiles(const uint32_t* tord, uint32_t long_max) {
+  const uint32_t nv = tord[kTileVeryLongWord];
+  return nv < long_max ? nv : long_max;
 }
 
 __device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_t tile) {
@@ -281,10 +287,20 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   };
   // One 64-entry batch at list position base, its records (g0, g1, g2) already in registers:
   // staged in this wave's LDS slice, culled against the quadrant, then walked.
-  auto batch = [&](const uint32_t base, const float4& g0, const float4& g1, const float4& g2) {
+  // On very long tiles whether the entry may reach the 4x4 block comes precomputed (rel4: the
+  // mask stage); elsewhere it is tested here.
+  const bool pre = kB == 4 && pos < very_long_tiles(a.tord, a.long_max);
+  auto batch = [&](const uint32_t base, const float4& g0, const float4& g1, const float4& g2, const bool rel4) {
     const uint32_t j = base + lane;
     bool rel = false;
-    if (j < rg.y) {
+    if (kB == 4 && pre) {
+      rel = rel4;
+      if (rel) {
+        s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
+        s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
+        s2[lane] = make_float4(g2.z, entry_cut(g0.z), 0.f, 0.f);
+      }
+    } else if (j < rg.y) {
       const float cut = entry_cut(g0.z);
       s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
       s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
@@ -372,6 +388,36 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       const uint32_t f = svals[q < jmax ? q : jmax];
       return (int64_t)f < VN ? f : 0u;   // defensive: the sort only emits indices < V*n
     };
+    if constexpr (kB == 4) {
+      // The block mask of a batch is loaded with its records (one batch ahead, into the same
+      // register set, every load issued so the wait counts stay static); the block bit is
+      // tested when the batch is staged.
+      const uint32_t* __restrict__ lmask = a.lmask;
+      auto clampq = [&](uint32_t q) { return q < jmax ? q : jmax; };
+      auto rel_at = [&](uint32_t q, uint32_t m) { return (q < rg.y) & (((m >> (uint32_t)blk) & 1u) != 0u); };
+      uint32_t ia = index_at(rg.x + lane);
+      uint32_t ib = index_at(rg.x + 64 + lane);
+      float4 a0 = rec[kRecQuads * (int64_t)ia], a1 = rec[kRecQuads * (int64_t)ia + 1], a2 = rec[kRecQuads * (int64_t)ia + 2];
+      uint32_t ma = lmask[clampq(rg.x + lane)];
+      float4 b0, b1, b2;
+      uint32_t mb;
+      ia = index_at(rg.x + 128 + lane);
+      for (uint32_t base = rg.x; base < rg.y && dm != ~0ull; base += 128) {
+        b0 = rec[kRecQuads * (int64_t)ib];
+        b1 = rec[kRecQuads * (int64_t)ib + 1];
+        b2 = rec[kRecQuads * (int64_t)ib + 2];
+        mb = lmask[clampq(base + 64 + lane)];
+        ib = index_at(base + 192 + lane);
+        batch(base, a0, a1, a2, rel_at(base + lane, ma));
+        if (base + 64 >= rg.y || dm == ~0ull) break;
+        a0 = rec[kRecQuads * (int64_t)ia];
+        a1 = rec[kRecQuads * (int64_t)ia + 1];
+        a2 = rec[kRecQuads * (int64_t)ia + 2];
+        ma = lmask[clampq(base + 128 + lane)];
+        ia = index_at(base + 256 + lane);
+        batch(base + 64, b0, b1, b2, rel_at(base + 64 + lane, mb));
+      }
+    } else {
     uint32_t ia = index_at(rg.x + lane);
     uint32_t ib = index_at(rg.x + 64 + lane);
     float4 a0 = rec[kRecQuads * (int64_t)ia], a1 = rec[kRecQuads * (int64_t)ia + 1], a2 = rec[kRecQuads * (int64_t)ia + 2];
@@ -382,13 +428,14 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       b1 = rec[kRecQuads * (int64_t)ib + 1];
       b2 = rec[kRecQuads * (int64_t)ib + 2];
       ib = index_at(base + 192 + lane);
-      batch(base, a0, a1, a2);
+      batch(base, a0, a1, a2, false);
       if (base + 64 >= rg.y || dm == ~0ull) break;
       a0 = rec[kRecQuads * (int64_t)ia];
       a1 = rec[kRecQuads * (int64_t)ia + 1];
       a2 = rec[kRecQuads * (int64_t)ia + 2];
       ia = index_at(base + 256 + lane);
-      batch(base + 64, b0, b1, b2);
+      batch(base + 64, b0, b1, b2, false);
+    }
     }
   }
   if (own) {
@@ -417,6 +464,41 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     }
   }
 }
+
+// Very long tiles, per entry of their lists: the 4x4 blocks of the tile the entry may reach (the
+// blend's own block test, run once per entry here instead of once per entry in each of the
+// tile's sixteen waves, which all walk these lists to the end in the far views of a large
+// scene).  Block b.id takes the units b.id, b.id + b.n, ... of the lists cut into `parts`
+// interleaved parts each.
+__device__ __forceinline__ void long_mask_body(const LongMaskArgs& a, Blk b) {
+  if (a.hdr[kHdrOverflow]) return;
+  const uint32_t nl = very_long_tiles(a.tord, a.long_max);
+  if (nl == 0u) return;
+  const uint32_t parts = b.n >= nl ? b.n / nl : 1u;
+  for (uint32_t u = b.id; u < nl * parts; u += b.n) {
+    const uint32_t pos = u % nl, part = u / nl;
+    const int tile_i = (int)a.order[pos];
+    const int v = view_of_tile(a.views, a.V, (uint32_t)tile_i);
+    const DevView& Vw = a.views[v];
+    const int local = tile_i - (int)Vw.tile_base;
+    const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
+    const uint2 rg = a.ranges[tile_i];
+    for (uint32_t j = rg.x + part * kBlock + threadIdx.x; j < rg.y; j += parts * kBlock) {
+      uint32_t f = a.svals[j];
+      if ((int64_t)f >= a.VN) f = 0u;   // defensive: the sort only emits indices < V*n
+      const float4 g0 = a.rec[kRecQuads * (int64_t)f], g1 = a.rec[kRecQuads * (int64_t)f + 1];
+      const float cut = entry_cut(g0.z);
+      uint32_t m = 0u;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const float x0 = (float)(tx * kTile + (q % 4) * 4 + Vw.vx), y0 = (float)(ty * kTile + (q / 4) * 4 + Vw.vy);
+        m |= quadrant_mask1<4>(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, x0, y0) << q;
+      }
+      a.lmask[j] = m;
+    }
+  }
+}
+__global__ __launch_bounds__(kBlock) void k_long_mask(LongMaskArgs a) { long_mask_body(a, grid_blk()); }
 
 // Long tiles: four workgroups per tile, on one XCD (workgroups b, b + 8, b + 16, b + 24 take
 // the same tile: consecutive workgroups go round-robin to the eight XCDs).
@@ -471,9 +553,8 @@ __device__ __forceinline__ void reduce_pairs_body(const ReducePairsArgs& r, Blk)
 }
 __global__ __launch_bounds__(kBlock) void k_reduce_pairs(ReducePairsArgs r) { reduce_pairs_body(r, grid_blk()); }
 
-hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals, int64_t dup_cap,
-                            clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
-                            const Sink& out) {
+hipError_t launch_blend_fwd(const Layout& L, void* ws, const BlendBufs& bb, clod_params prm, float* rgb, float* T,
+                            uint32_t* last, int64_t* pairs, const Sink& out) {
   if (L.tiles_total == 0) return hipSuccess;
   char* w = (char*)ws;
   unsigned long long* part = pairs ? (unsigned long long*)(w + L.pair_part) : nullptr;
@@ -481,17 +562,29 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_va
     hipError_t e = launch_fill_u32((uint32_t*)part, 0u, 6 * (int64_t)L.tiles_total, out);
     if (e != hipSuccess) return e;
   }
-  // At most dup_cap / 2^(kLongBucket - 1) tiles can be long: the launch covers that many.
-  const int64_t cap_long = dup_cap / (1ll << (kLongBucket - 1));
+  // At most cap / 2^(kLongBucket - 1) tiles can be long: the launch covers that many.
+  const int64_t cap_long = bb.cap / (1ll << (kLongBucket - 1));
   const uint32_t long_max = (uint32_t)(cap_long < (int64_t)L.tiles_total ? cap_long : (int64_t)L.tiles_total);
+  if (long_max > 0) {
+    Stage m{};
+    m.kind = kStLongMask;
+    m.items = kLongMaskBlocks;
+    m.block = kBlock;
+    m.a.long_mask = LongMaskArgs{(const DevView*)(w + L.vinfo), L.V, (const uint2*)(w + L.ranges),
+                                 (const uint32_t*)(w + L.order), (const uint32_t*)(w + L.tord), bb.svals,
+                                 (const float4*)(w + L.rec), L.VN, (const unsigned long long*)(w + L.hdr), long_max,
+                                 bb.lmask};
+    const hipError_t e = out.put(m);
+    if (e != hipSuccess) return e;
+  }
   Stage st{};
   st.kind = kStBlend;
   st.items = long_grid(long_max) + xcd_grid(L.tiles_total);
   st.block = kBlock;
   st.a.blend = BlendArgs{(const DevView*)(w + L.vinfo), L.V, L.tiles_total, L.VN, (const float4*)(w + L.rec),
-                         (const uint2*)(w + L.ranges), sorted_vals, (const unsigned long long*)(w + L.hdr), prm.bg[0],
+                         (const uint2*)(w + L.ranges), bb.svals, (const unsigned long long*)(w + L.hdr), prm.bg[0],
                          prm.bg[1], prm.bg[2], rgb, T, last, part, (const uint32_t*)(w + L.order),
-                         (const uint32_t*)(w + L.tord), long_max, part ? 1 : 0};
+                         (const uint32_t*)(w + L.tord), long_max, part ? 1 : 0, bb.lmask};
   hipError_t e = out.put(st);
   if (e == hipSuccess && part) {
     Stage r{};
@@ -512,6 +605,7 @@ hipError_t launch_blend_stage(const Stage& st, hipStream_t s) {
       else hipLaunchKernelGGL(k_blend_fwd<false>, g, blk, 0, s, st.a.blend);
       break;
     case kStReducePairs: hipLaunchKernelGGL(k_reduce_pairs, g, blk, 0, s, st.a.reduce_pairs); break;
+    case kStLongMask: hipLaunchKernelGGL(k_long_mask, g, blk, 0, s, st.a.long_mask); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -22,8 +22,10 @@ constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int kEmitTile = 2048;            // tile pairs per output chunk of the emission
 constexpr int kTileBuckets = 33;
 constexpr int kLongBucket = 14;            // long tiles: 8,192 entries or more
+constexpr int kVeryLongBucket = 17;        // very long tiles: 65,536 entries or more
 constexpr int kTileLongWord = 2 * kTileBuckets;
-constexpr int kTileOrderWords = 2 * kTileBuckets + 1;
+constexpr int kTileVeryLongWord = 2 * kTileBuckets + 1;
+constexpr int kTileOrderWords = 2 * kTileBuckets + 2;
 constexpr int kTileOrderChunk = 1024;       // tiles per block in the ordering kernels
 constexpr int kSortItems = 8;              // keys per thread per radix tile
 constexpr int kSortTile = kBlock * kSortItems;   // 2048 keys per radix tile
@@ -453,7 +455,8 @@ __device__ __forceinline__ bool lod_kept(const DevView& Vw, float a2, int64_t i)
 enum StageKind : int32_t {
   kStViewSetup = 1, kStFill, kStFrustumMax, kStFold, kStClassify, kStProject, kStSelectHist, kStSelectPick,
   kStScanReduce, kStScanPartials, kStCompact, kStRadixUp, kStRadixScan, kStRadixDown, kStEmitReduce,
-  kStEmitPartials, kStEmitOffsets, kStEmit, kStRanges, kStTileCount, kStTileScatter, kStBlend, kStReducePairs
+  kStEmitPartials, kStEmitOffsets, kStEmit, kStRanges, kStTileCount, kStTileScatter, kStBlend, kStReducePairs,
+  kStLongMask
 };
 
 struct ViewSetupArgs {
@@ -522,6 +525,14 @@ struct BlendArgs {
   unsigned long long* pair_part; const uint32_t* order; const uint32_t* tord;
   uint32_t long_max;      // most long tiles the launch covers (the pair capacity's bound)
   int32_t count;
+  const uint32_t* lmask;  // very long tiles: per list position, from kStLongMask
+};
+// Very long tiles: the 4x4 blocks of its tile each entry may reach (bit b: block b, row-major),
+// per position of the sorted pair list.
+struct LongMaskArgs {
+  const DevView* views; int32_t V; const uint2* ranges; const uint32_t* order; const uint32_t* tord;
+  const uint32_t* svals; const float4* rec; int64_t VN; const unsigned long long* hdr; uint32_t long_max;
+  uint32_t* lmask;
 };
 struct ReducePairsArgs {
   const unsigned long long* part; uint32_t tiles; unsigned long long* out;
@@ -537,7 +548,7 @@ struct Stage {
     ProjectArgs project; SelectArgs select; ScanReduceArgs scan_reduce; ScanPartialsArgs scan_partials;
     CompactArgs compact; RadixArgs radix; EmitReduceArgs emit_reduce; EmitPartialsArgs emit_partials;
     EmitOffsetsArgs emit_offsets; EmitArgs emit; RangesArgs ranges; TileOrderArgs tile_order; BlendArgs blend;
-    ReducePairsArgs reduce_pairs;
+    ReducePairsArgs reduce_pairs; LongMaskArgs long_mask;
   } a;
 };
 
@@ -614,9 +625,13 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
 hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
                          const Sink& out);
 
-hipError_t launch_blend_fwd(const Layout& L, void* ws, const uint32_t* sorted_vals, int64_t dup_cap,
-                            clod_params prm, float* rgb, float* T, uint32_t* last, int64_t* pairs,
-                            const Sink& out);
+// The pair buffers the forward blend reads: the sorted record indices, and an array the
+// tile-id sort left free (it holds the very long tiles' per-entry block masks).
+struct BlendBufs {
+  const uint32_t* svals; uint32_t* lmask; int64_t cap;
+};
+hipError_t launch_blend_fwd(const Layout& L, void* ws, const BlendBufs& bb, clod_params prm, float* rgb, float* T,
+                            uint32_t* last, int64_t* pairs, const Sink& out);
 hipError_t launch_blend_bwd(const Layout& L, void* ws, const uint32_t* sorted_vals, clod_params prm,
                             const float* T, const uint32_t* last, const float* dL_drgb, int64_t* pairs,
                             hipStream_t s);

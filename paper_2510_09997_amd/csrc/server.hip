@@ -44,7 +44,7 @@ hipError_t launch_stage(const Stage& st, hipStream_t s) {
     case kStRadixDown: case kStEmitReduce: case kStEmitPartials: case kStEmitOffsets: case kStEmit:
     case kStRanges: case kStTileCount: case kStTileScatter:
       return launch_sort_stage(st, s);
-    case kStBlend: case kStReducePairs:
+    case kStBlend: case kStReducePairs: case kStLongMask:
       return launch_blend_stage(st, s);
     default:
       return hipErrorInvalidValue;
@@ -286,6 +286,7 @@ __device__ bool srv_run(int32_t kind, const Stage& st, Blk b, SrvLds& U) {
       return true;
     }
     case kStReducePairs: reduce_pairs_body(uniform_copy(st.a.reduce_pairs), b); return true;
+    case kStLongMask: long_mask_body(uniform_copy(st.a.long_mask), b); return true;
     default: return false;
   }
 }

@@ -782,8 +782,10 @@ __device__ __forceinline__ void tile_scatter_body(const TileOrderArgs& a, Blk bl
     uint32_t start = 0;
     for (uint32_t c = b + 1; c < (uint32_t)kTileBuckets; ++c) start += tord[c];
     cur[b] = cnt[b] ? start + atomicAdd(&tord[kTileBuckets + b], cnt[b]) : 0u;
-    // The long tiles' count (the start of the first short bucket), for the blend launches.
+    // The counts of the long and of the very long tiles (the starts of the first buckets below
+    // them), for the blend.
     if (b == kLongBucket - 1 && blk.id == 0) tord[kTileLongWord] = start;
+    if (b == kVeryLongBucket - 1 && blk.id == 0) tord[kTileVeryLongWord] = start;
   }
   __syncthreads();
   for (uint32_t t = t0 + threadIdx.x; t < tiles && t < t0 + kTileOrderChunk; t += kBlock) {
