@@ -1,7 +1,8 @@
 """Persistent serving launch (clod_server_*): jobs run by the resident kernel give the same bytes
 as the per-stage launches of clod_project / clod_bin_sort / clod_render_fwd, whether a request
 is rendered alone or inside a mixed batch, with several jobs in flight at once; a 4K request
-inside a 720p / 4K / 1080p job is checked against the oracle.  Also: stop on request, the
+inside a 720p / 4K / 1080p job and a frame with very long tile lists are checked against the
+oracle.  Also: stop on request, the
 kernel's own deadline, overflow and resubmission, and the argument checks."""
 import ctypes
 import time
@@ -153,6 +154,40 @@ def test_jobs_in_flight_match_per_stage_launches_and_4k_matches_oracle():
     assert np.array_equal(T.cpu().numpy().reshape(o["T"].shape).view(np.uint32), o["T"].view(np.uint32))
     assert np.array_equal(rgb.cpu().numpy().reshape(o["rgb"].shape).view(np.uint32), o["rgb"].view(np.uint32))
     assert infos[1]["n_dup"] >= infos[0]["n_dup"]
+
+
+def test_very_long_tile_lists_in_a_job_match_per_stage_and_oracle():
+    """A dense cluster seen from far away (two tile lists of more than 65,536 entries beside
+    short ones): the job's stages include the per-entry block masks of the very long tiles and
+    the 4x4-block blend; the result is byte-identical to the per-stage launches and to the
+    oracle."""
+    log("case: persistent very long tile lists")
+    dense = synth.make_scene(380_000, 0, "uniform", seed=33, log_scale_mean=-5.0)
+    spread = synth.make_scene(20_000, 0, "uniform", seed=34, log_scale_mean=-2.5)
+    spread["mean"] = (spread["mean"] * np.float32(12.0)).astype(np.float32)
+    sc = dict(n=400_000, sh_degree=0, **{k: np.ascontiguousarray(np.concatenate([dense[k], spread[k]], axis=-1))
+                                        for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")})
+    scene = Scene(sc, packed_sh=True)
+    view = synth.look_at((0.0, 0.0, -40.0), width=96, height=80, s_v=1.0)
+    job = Job(None, scene, sc["n"], [view], dup_pairs=1 << 22)
+    srv = start()
+    try:
+        job.srv = srv
+        job.submit()
+        info = job.wait()
+    finally:
+        C.clod_server_stop(srv)
+    torch.cuda.synchronize()
+    assert not info["overflow"]
+    o = O.render32(sc, view)
+    lists = np.diff(o["tile_off"])
+    log(f"  pairs {info['n_dup']}, longest list {lists.max()}, lists >= 65536: {(lists >= 65536).sum()}")
+    assert (lists >= 65536).sum() >= 2 and info["n_dup"] == o["entries"].size
+    rgb, T, last = per_stage(sc, scene, [view])
+    assert same_bits(job.rgb, rgb) and same_bits(job.T, T) and torch.equal(job.last, last)
+    assert np.array_equal(job.last.cpu().numpy().reshape(o["last"].shape), o["last"])
+    assert np.array_equal(job.T.cpu().numpy().reshape(o["T"].shape).view(np.uint32), o["T"].view(np.uint32))
+    assert np.array_equal(job.rgb.cpu().numpy().reshape(o["rgb"].shape).view(np.uint32), o["rgb"].view(np.uint32))
 
 
 def test_overflowing_job_completes_flagged_and_resubmits():
