@@ -307,7 +307,8 @@ static const uint32_t* sorted_vals(const clod_batch* b, const Layout& L, const D
 static BlendBufs blend_bufs(const clod_batch* b, const Layout& L, const DupLayout& D) {
   const bool odd = sorted_buffer(L.tiles_total) != 0;
   char* dp = (char*)b->dup;
-  return BlendBufs{sorted_vals(b, L, D), (uint32_t*)(dp + (odd ? D.vals0 : D.vals1)), D.cap};
+  const size_t k = odd ? D.keys0 : D.keys1, v = odd ? D.vals0 : D.vals1;   // adjacent: keys, then values
+  return BlendBufs{sorted_vals(b, L, D), (unsigned long long*)(dp + k), v + (size_t)D.cap * 4 - k, D.cap};
 }
 
 }  // namespace clod

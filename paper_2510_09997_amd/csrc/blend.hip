@@ -155,7 +155,8 @@ __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, fl
 // pixels are saturated, independently of the other quadrants; the only block barrier is the
 // final reduction of the optional pair counters.
 struct TileLds {
-  float4 st[4][3][64];   // per wave: (u, v, hA, nB), (hC, alpha'', r, g), (b, cut, -, -)
+  float4 st[4][3][64];   // per wave: (u, v, hA, nB), (hC, alpha'', r, g), (b, cut, list position, -)
+  uint32_t q[4][256];    // per wave: ring of the list positions that reach its 4x4 block (very long tiles)
 };
 
 // One tile, at position pos of the batch's tile order, by the 256 threads of the block (four
@@ -219,9 +220,8 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   // four entries in list order through the contract's termination test and blend, the same
   // operations in the same order as one entry at a time.  Terminated pixels (dm, bits 0..15)
   // drop out of the later entries of a group; their values for those entries are never used.
-  auto walk4 = [&](const uint32_t base, uint64_t mask) {
+  auto walk4 = [&](uint64_t mask) {
     const uint32_t row = lane >> 4;
-    const uint32_t p0 = base - rg.x;
     // One entry of the group for row 0's pixels: alpha (valid on the live lanes lv, bits
     // 0..15), the entry's colour and list position.
     auto step = [&](const float al, const uint64_t lv, const float c0, const float c1, const float c2,
@@ -263,9 +263,9 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       const int fr = row == 0u ? f0 : row == 1u ? f1 : row == 2u ? f2 : f3;
       const float4 a = s0[fr], c = s1[fr];
       const float4 bc = s2[fr];
-      // Colours of entries 1..3 for row 0 (LDS broadcasts).
+      // Colours and list positions of entries 1..3 for row 0 (LDS broadcasts).
       const float4 q1 = s1[f1], q2 = s1[f2], q3 = s1[f3];
-      const float b1 = s2[f1].x, b2 = s2[f2].x, b3 = s2[f3].x;
+      const float4 r1 = s2[f1], r2 = s2[f2], r3 = s2[f3];
       const float dx = a.x - pcx, dy = a.y - pcy;
       const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
       const uint64_t slots = 0xFFFFull | (h1 ? 0xFFFF0000ull : 0ull) | (h2 ? 0xFFFF00000000ull : 0ull) |
@@ -279,32 +279,32 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       const auto x16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(al), __float_as_uint(al), false, false);
       const auto x32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(al), __float_as_uint(al), false, false);
       const auto x48 = __builtin_amdgcn_permlane32_swap(x16[1], x16[1], false, false);
-      step(al, live, c.z, c.w, bc.x, p0 + (uint32_t)f0);
-      step(__uint_as_float(x16[1]), live >> 16, q1.z, q1.w, b1, p0 + (uint32_t)f1);
-      step(__uint_as_float(x32[1]), live >> 32, q2.z, q2.w, b2, p0 + (uint32_t)f2);
-      step(__uint_as_float(x48[1]), live >> 48, q3.z, q3.w, b3, p0 + (uint32_t)f3);
+      step(al, live, c.z, c.w, bc.x, __float_as_uint(bc.z));
+      step(__uint_as_float(x16[1]), live >> 16, q1.z, q1.w, r1.x, __float_as_uint(r1.z));
+      step(__uint_as_float(x32[1]), live >> 32, q2.z, q2.w, r2.x, __float_as_uint(r2.z));
+      step(__uint_as_float(x48[1]), live >> 48, q3.z, q3.w, r3.x, __float_as_uint(r3.z));
     }
   };
-  // One 64-entry batch at list position base, its records (g0, g1, g2) already in registers:
-  // staged in this wave's LDS slice, culled against the quadrant, then walked.
-  // On very long tiles whether the entry may reach the 4x4 block comes precomputed (rel4: the
-  // mask stage); elsewhere it is tested here.
-  const bool pre = kB == 4 && pos < very_long_tiles(a.tord, a.long_max);
-  auto batch = [&](const uint32_t base, const float4& g0, const float4& g1, const float4& g2, const bool rel4) {
-    const uint32_t j = base + lane;
+  // One batch of up to 64 entries, its records (g0, g1, g2) already in registers, lane l's
+  // at list position j: staged in this wave's LDS slice, culled against the quadrant, then
+  // walked.  The entries of a very long tile arrive already compacted to those that may reach
+  // the 4x4 block (relc); elsewhere the batch is the 64 entries from base and is culled here.
+  const bool pre = kB == 4 && pos < very_long_tiles(a.tord, a.vl_max);
+  auto batch = [&](const uint32_t base, const uint32_t j, const float4& g0, const float4& g1, const float4& g2,
+                   const bool relc) {
     bool rel = false;
     if (kB == 4 && pre) {
-      rel = rel4;
+      rel = relc;
       if (rel) {
         s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
         s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
-        s2[lane] = make_float4(g2.z, entry_cut(g0.z), 0.f, 0.f);
+        s2[lane] = make_float4(g2.z, entry_cut(g0.z), __uint_as_float(j - rg.x), 0.f);
       }
     } else if (j < rg.y) {
       const float cut = entry_cut(g0.z);
       s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
       s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
-      s2[lane] = make_float4(g2.z, cut, 0.f, 0.f);
+      s2[lane] = make_float4(g2.z, cut, __uint_as_float(j - rg.x), 0.f);
       rel = (quadrant_mask1<kB>(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, fqx, fqy)) != 0u;
     }
     uint64_t mask = ballot64(rel);
@@ -314,7 +314,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (mask == 0ull) return;
     if constexpr (kB == 4) {
-      walk4(base, mask);
+      walk4(mask);
       return;
     }
     // One entry: the contract's skip, exponential, clamp, termination and blend.  Below the
@@ -388,34 +388,77 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       const uint32_t f = svals[q < jmax ? q : jmax];
       return (int64_t)f < VN ? f : 0u;   // defensive: the sort only emits indices < V*n
     };
-    if constexpr (kB == 4) {
-      // The block mask of a batch is loaded with its records (one batch ahead, into the same
-      // register set, every load issued so the wait counts stay static); the block bit is
-      // tested when the batch is staged.
-      const uint32_t* __restrict__ lmask = a.lmask;
-      auto clampq = [&](uint32_t q) { return q < jmax ? q : jmax; };
-      auto rel_at = [&](uint32_t q, uint32_t m) { return (q < rg.y) & (((m >> (uint32_t)blk) & 1u) != 0u); };
-      uint32_t ia = index_at(rg.x + lane);
-      uint32_t ib = index_at(rg.x + 64 + lane);
+    if (kB == 4 && pre) {
+      // Very long tile: the wave scans its block's bit plane (64 words, 4,096 entries per
+      // load), appends the positions of the entries that may reach the block to its LDS ring,
+      // and takes them 64 at a time into the same two-set pipeline (indices two batches ahead,
+      // records one), so that it gathers, stages and walks only those entries.
+      const unsigned long long* __restrict__ plane =
+          a.lplane + (int64_t)blk * a.pw + (rg.x >> 6) + (uint32_t)tile_i;
+      const uint32_t nwords = ((rg.y - rg.x) + 63u) >> 6;
+      uint32_t* __restrict__ ring = S.q[wave];
+      uint32_t head = 0, tail = 0, wi = 0, wb = 0;
+      auto word_at = [&](uint32_t w) { return plane[w < nwords ? w : nwords - 1u]; };
+      unsigned long long wv = word_at(lane), wn = word_at(64u + lane);
+      auto fill = [&]() {
+        while (tail - head < 192u && wi < nwords) {
+          if (wi - wb == 64u) {
+            wb += 64u;
+            wv = wn;
+            wn = word_at(wb + 64u + lane);
+          }
+          const uint32_t k = wi - wb;
+          const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)wv, k);
+          const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(wv >> 32), k);
+          const unsigned long long word = ((unsigned long long)hi << 32) | lo;
+          if ((word >> lane) & 1ull)
+            ring[(tail + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u))) & 255u] =
+                rg.x + 64u * wi + lane;
+          tail += (uint32_t)__builtin_popcountll(word);
+          ++wi;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      };
+      // The next (up to) 64 positions of the ring, one per lane (v: the lane holds one).
+      auto take = [&](uint32_t& q, bool& v) {
+        fill();
+        const uint32_t n = tail - head < 64u ? tail - head : 64u;
+        v = lane < n;
+        q = v ? ring[(head + lane) & 255u] : rg.x;
+        head += n;
+      };
+      uint32_t qa, qb, ja, jb;
+      bool va, vb, ra, rb;
+      take(qa, va);
+      uint32_t ia = index_at(qa);
+      take(qb, vb);
+      uint32_t ib = index_at(qb);
       float4 a0 = rec[kRecQuads * (int64_t)ia], a1 = rec[kRecQuads * (int64_t)ia + 1], a2 = rec[kRecQuads * (int64_t)ia + 2];
-      uint32_t ma = lmask[clampq(rg.x + lane)];
       float4 b0, b1, b2;
-      uint32_t mb;
-      ia = index_at(rg.x + 128 + lane);
-      for (uint32_t base = rg.x; base < rg.y && dm != ~0ull; base += 128) {
+      ja = qa;
+      ra = va;
+      take(qa, va);
+      ia = index_at(qa);
+      while (ballot64(ra) != 0ull && dm != ~0ull) {
         b0 = rec[kRecQuads * (int64_t)ib];
         b1 = rec[kRecQuads * (int64_t)ib + 1];
         b2 = rec[kRecQuads * (int64_t)ib + 2];
-        mb = lmask[clampq(base + 64 + lane)];
-        ib = index_at(base + 192 + lane);
-        batch(base, a0, a1, a2, rel_at(base + lane, ma));
-        if (base + 64 >= rg.y || dm == ~0ull) break;
+        jb = qb;
+        rb = vb;
+        take(qb, vb);
+        ib = index_at(qb);
+        batch(0u, ja, a0, a1, a2, ra);
+        if (ballot64(rb) == 0ull || dm == ~0ull) break;
         a0 = rec[kRecQuads * (int64_t)ia];
         a1 = rec[kRecQuads * (int64_t)ia + 1];
         a2 = rec[kRecQuads * (int64_t)ia + 2];
-        ma = lmask[clampq(base + 128 + lane)];
-        ia = index_at(base + 256 + lane);
-        batch(base + 64, b0, b1, b2, rel_at(base + 64 + lane, mb));
+        ja = qa;
+        ra = va;
+        take(qa, va);
+        ia = index_at(qa);
+        batch(0u, jb, b0, b1, b2, rb);
       }
     } else {
     uint32_t ia = index_at(rg.x + lane);
@@ -428,13 +471,13 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       b1 = rec[kRecQuads * (int64_t)ib + 1];
       b2 = rec[kRecQuads * (int64_t)ib + 2];
       ib = index_at(base + 192 + lane);
-      batch(base, a0, a1, a2, false);
+      batch(base, base + lane, a0, a1, a2, false);
       if (base + 64 >= rg.y || dm == ~0ull) break;
       a0 = rec[kRecQuads * (int64_t)ia];
       a1 = rec[kRecQuads * (int64_t)ia + 1];
       a2 = rec[kRecQuads * (int64_t)ia + 2];
       ia = index_at(base + 256 + lane);
-      batch(base + 64, b0, b1, b2, false);
+      batch(base + 64, base + 64 + lane, b0, b1, b2, false);
     }
     }
   }
@@ -468,33 +511,45 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
 // Very long tiles, per entry of their lists: the 4x4 blocks of the tile the entry may reach (the
 // blend's own block test, run once per entry here instead of once per entry in each of the
 // tile's sixteen waves, which all walk these lists to the end in the far views of a large
-// scene).  Block b.id takes the units b.id, b.id + b.n, ... of the lists cut into `parts`
-// interleaved parts each.
+// scene), as sixteen bit planes: per block, one bit per entry, 64 entries per word.  Wave w of
+// the grid takes the 64-entry chunks w, w + W, ... of each very long tile and writes the
+// chunk's sixteen words (lane b the word of block b).
 __device__ __forceinline__ void long_mask_body(const LongMaskArgs& a, Blk b) {
   if (a.hdr[kHdrOverflow]) return;
-  const uint32_t nl = very_long_tiles(a.tord, a.long_max);
+  const uint32_t nl = very_long_tiles(a.tord, a.vl_max);
   if (nl == 0u) return;
-  const uint32_t parts = b.n >= nl ? b.n / nl : 1u;
-  for (uint32_t u = b.id; u < nl * parts; u += b.n) {
-    const uint32_t pos = u % nl, part = u / nl;
-    const int tile_i = (int)a.order[pos];
+  const uint32_t lane = lane_id();
+  const uint32_t gw = b.id * (kBlock / 64u) + (threadIdx.x >> 6), GW = b.n * (kBlock / 64u);
+  for (uint32_t p = 0; p < nl; ++p) {
+    const int tile_i = (int)a.order[p];
     const int v = view_of_tile(a.views, a.V, (uint32_t)tile_i);
     const DevView& Vw = a.views[v];
     const int local = tile_i - (int)Vw.tile_base;
     const int tx = local % Vw.tiles_x, ty = local / Vw.tiles_x;
     const uint2 rg = a.ranges[tile_i];
-    for (uint32_t j = rg.x + part * kBlock + threadIdx.x; j < rg.y; j += parts * kBlock) {
-      uint32_t f = a.svals[j];
-      if ((int64_t)f >= a.VN) f = 0u;   // defensive: the sort only emits indices < V*n
-      const float4 g0 = a.rec[kRecQuads * (int64_t)f], g1 = a.rec[kRecQuads * (int64_t)f + 1];
-      const float cut = entry_cut(g0.z);
+    const uint32_t nchunks = ((rg.y - rg.x) + 63u) >> 6;
+    unsigned long long* __restrict__ out = a.lplane + (rg.x >> 6) + (uint32_t)tile_i;
+    for (uint32_t c = gw; c < nchunks; c += GW) {
+      const uint32_t j = rg.x + 64u * c + lane;
       uint32_t m = 0u;
+      if (j < rg.y) {
+        uint32_t f = a.svals[j];
+        if ((int64_t)f >= a.VN) f = 0u;   // defensive: the sort only emits indices < V*n
+        const float4 g0 = a.rec[kRecQuads * (int64_t)f], g1 = a.rec[kRecQuads * (int64_t)f + 1];
+        const float cut = entry_cut(g0.z);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const float x0 = (float)(tx * kTile + (q % 4) * 4 + Vw.vx), y0 = (float)(ty * kTile + (q / 4) * 4 + Vw.vy);
+          m |= quadrant_mask1<4>(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, x0, y0) << q;
+        }
+      }
+      unsigned long long mine = 0ull;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const float x0 = (float)(tx * kTile + (q % 4) * 4 + Vw.vx), y0 = (float)(ty * kTile + (q / 4) * 4 + Vw.vy);
-        m |= quadrant_mask1<4>(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, x0, y0) << q;
+        const unsigned long long w = ballot64(((m >> q) & 1u) != 0u);
+        if (lane == (uint32_t)q) mine = w;
       }
-      a.lmask[j] = m;
+      if (lane < 16u) out[(int64_t)lane * a.pw + c] = mine;
     }
   }
 }
@@ -565,15 +620,23 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const BlendBufs& bb, clod
   // At most cap / 2^(kLongBucket - 1) tiles can be long: the launch covers that many.
   const int64_t cap_long = bb.cap / (1ll << (kLongBucket - 1));
   const uint32_t long_max = (uint32_t)(cap_long < (int64_t)L.tiles_total ? cap_long : (int64_t)L.tiles_total);
-  if (long_max > 0) {
+  // Very long tiles: at most cap / 2^(kVeryLongBucket - 1); their bit planes (16 planes of
+  // pw words) must fit the arrays the tile-id sort left free, else they are blended like the
+  // other long tiles.
+  const int64_t cap_vl = bb.cap / (1ll << (kVeryLongBucket - 1));
+  const uint32_t pw = (uint32_t)((bb.cap + 63) / 64 + (int64_t)L.tiles_total + 1);
+  const bool planes_fit = (size_t)16 * pw * sizeof(unsigned long long) <= bb.spare_bytes;
+  const uint32_t vl_max =
+      planes_fit ? (uint32_t)(cap_vl < (int64_t)L.tiles_total ? cap_vl : (int64_t)L.tiles_total) : 0u;
+  if (vl_max > 0) {
     Stage m{};
     m.kind = kStLongMask;
     m.items = kLongMaskBlocks;
     m.block = kBlock;
     m.a.long_mask = LongMaskArgs{(const DevView*)(w + L.vinfo), L.V, (const uint2*)(w + L.ranges),
                                  (const uint32_t*)(w + L.order), (const uint32_t*)(w + L.tord), bb.svals,
-                                 (const float4*)(w + L.rec), L.VN, (const unsigned long long*)(w + L.hdr), long_max,
-                                 bb.lmask};
+                                 (const float4*)(w + L.rec), L.VN, (const unsigned long long*)(w + L.hdr),
+                                 bb.spare, pw, vl_max};
     const hipError_t e = out.put(m);
     if (e != hipSuccess) return e;
   }
@@ -584,7 +647,7 @@ hipError_t launch_blend_fwd(const Layout& L, void* ws, const BlendBufs& bb, clod
   st.a.blend = BlendArgs{(const DevView*)(w + L.vinfo), L.V, L.tiles_total, L.VN, (const float4*)(w + L.rec),
                          (const uint2*)(w + L.ranges), bb.svals, (const unsigned long long*)(w + L.hdr), prm.bg[0],
                          prm.bg[1], prm.bg[2], rgb, T, last, part, (const uint32_t*)(w + L.order),
-                         (const uint32_t*)(w + L.tord), long_max, part ? 1 : 0, bb.lmask};
+                         (const uint32_t*)(w + L.tord), long_max, part ? 1 : 0, bb.spare, pw, vl_max};
   hipError_t e = out.put(st);
   if (e == hipSuccess && part) {
     Stage r{};

@@ -525,14 +525,15 @@ struct BlendArgs {
   unsigned long long* pair_part; const uint32_t* order; const uint32_t* tord;
   uint32_t long_max;      // most long tiles the launch covers (the pair capacity's bound)
   int32_t count;
-  const uint32_t* lmask;  // very long tiles: per list position, from kStLongMask
+  // Very long tiles (at most vl_max of them): per 4x4 block b of the tile, one bit per list
+  // entry (set if the entry may reach the block), 64 entries per word, the tile's words at
+  // lplane[b * pw + rg.x / 64 + tile + w] (from kStLongMask).
+  const unsigned long long* lplane; uint32_t pw; uint32_t vl_max;
 };
-// Very long tiles: the 4x4 blocks of its tile each entry may reach (bit b: block b, row-major),
-// per position of the sorted pair list.
 struct LongMaskArgs {
   const DevView* views; int32_t V; const uint2* ranges; const uint32_t* order; const uint32_t* tord;
-  const uint32_t* svals; const float4* rec; int64_t VN; const unsigned long long* hdr; uint32_t long_max;
-  uint32_t* lmask;
+  const uint32_t* svals; const float4* rec; int64_t VN; const unsigned long long* hdr;
+  unsigned long long* lplane; uint32_t pw; uint32_t vl_max;
 };
 struct ReducePairsArgs {
   const unsigned long long* part; uint32_t tiles; unsigned long long* out;
@@ -625,10 +626,10 @@ hipError_t launch_bin_sort(const Layout& L, void* ws, const DupLayout& D, void* 
 hipError_t launch_ranges(const Layout& L, void* ws, const DupLayout& D, void* dup, int parity,
                          const Sink& out);
 
-// The pair buffers the forward blend reads: the sorted record indices, and an array the
-// tile-id sort left free (it holds the very long tiles' per-entry block masks).
+// The pair buffers the forward blend reads: the sorted record indices, and the two arrays the
+// tile-id sort left free (they hold the very long tiles' block bit planes).
 struct BlendBufs {
-  const uint32_t* svals; uint32_t* lmask; int64_t cap;
+  const uint32_t* svals; unsigned long long* spare; size_t spare_bytes; int64_t cap;
 };
 hipError_t launch_blend_fwd(const Layout& L, void* ws, const BlendBufs& bb, clod_params prm, float* rgb, float* T,
                             uint32_t* last, int64_t* pairs, const Sink& out);
