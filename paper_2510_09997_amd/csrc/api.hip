@@ -662,8 +662,14 @@ clod_status clod_server_submit(clod_server* server, const clod_scene* scene, con
   const Sink out(&P);
   hipError_t e = project_stages(*scene, b.views_dev, b.params, cx.L, b.ws, nullptr, nullptr, out);
   if (e == hipSuccess) e = bin_stages(cx.L, b.ws, D, b.dup, out);
-  if (e == hipSuccess)
-    e = launch_blend_fwd(cx.L, b.ws, blend_bufs(&b, cx.L, D), b.params, rgb, T, last, nullptr, out);
+  if (e == hipSuccess) {
+    // Not the very-long-tile path: it reads the block bit planes with scalar loads, and the
+    // scalar cache is invalidated only when a launch starts, not between the stages that the
+    // resident kernel runs in one launch.
+    BlendBufs bb = blend_bufs(&b, cx.L, D);
+    bb.spare_bytes = 0;
+    e = launch_blend_fwd(cx.L, b.ws, bb, b.params, rgb, T, last, nullptr, out);
+  }
   if (P.full) return fail(CLOD_E_UNSUPPORTED, "the job needs more than %d stages", kMaxStages);
   HIP_TRY(e, "job stages");
   HIP_TRY(server_publish(S, P, b.n_views, b.views_host, (const char*)b.ws + cx.L.hdr, seq), "publish");

@@ -389,28 +389,28 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       return (int64_t)f < VN ? f : 0u;   // defensive: the sort only emits indices < V*n
     };
     if (kB == 4 && pre) {
-      // Very long tile: the wave scans its block's bit plane (64 words, 4,096 entries per
-      // load), appends the positions of the entries that may reach the block to its LDS ring,
-      // and takes them 64 at a time into the same two-set pipeline (indices two batches ahead,
-      // records one), so that it gathers, stages and walks only those entries.
-      const unsigned long long* __restrict__ plane =
-          a.lplane + (int64_t)blk * a.pw + (rg.x >> 6) + (uint32_t)tile_i;
+      // Very long tile: the wave scans its block's bit plane (one word per 64 entries, read
+      // with scalar loads: they do not enter the vector-memory wait count, so the pipeline's
+      // gathers stay in flight while it scans), appends the positions of the entries that may
+      // reach the block to its LDS ring, and takes them 64 at a time into the same two-set
+      // pipeline (indices two batches ahead, records one), so that it gathers, stages and walks
+      // only those entries.  (The planes are written by an earlier launch, and the scalar
+      // cache is invalidated when a launch starts; the resident serving kernel, which runs a
+      // job's stages in one launch, does not take this path.)
+      typedef const __attribute__((address_space(4))) unsigned long long* ConstWords;
+      // (readfirstlane returns int: each half goes through uint32_t so that the low half is
+      // not sign-extended into the high one.)
+      const uint64_t pa = (uint64_t)(uintptr_t)(a.lplane + (int64_t)blk * a.pw + (rg.x >> 6) + (uint32_t)tile_i);
+      const uint64_t pu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(pa >> 32)) << 32) |
+                          (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)pa);
+      const ConstWords plane = (ConstWords)(uintptr_t)pu;
       const uint32_t nwords = ((rg.y - rg.x) + 63u) >> 6;
       uint32_t* __restrict__ ring = S.q[wave];
-      uint32_t head = 0, tail = 0, wi = 0, wb = 0;
-      auto word_at = [&](uint32_t w) { return plane[w < nwords ? w : nwords - 1u]; };
-      unsigned long long wv = word_at(lane), wn = word_at(64u + lane);
+      uint32_t head = 0, tail = 0, wi = 0;
       auto fill = [&]() {
         while (tail - head < 192u && wi < nwords) {
-          if (wi - wb == 64u) {
-            wb += 64u;
-            wv = wn;
-            wn = word_at(wb + 64u + lane);
-          }
-          const uint32_t k = wi - wb;
-          const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)wv, k);
-          const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(wv >> 32), k);
-          const unsigned long long word = ((unsigned long long)hi << 32) | lo;
+          const unsigned long long word = plane[wi];
+          const uint32_t lo = (uint32_t)word, hi = (uint32_t)(word >> 32);
           if ((word >> lane) & 1ull)
             ring[(tail + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u))) & 255u] =
                 rg.x + 64u * wi + lane;
@@ -429,18 +429,23 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
         q = v ? ring[(head + lane) & 255u] : rg.x;
         head += n;
       };
+      // Ring positions lie in [rg.x, rg.y) (clamped all the same: they come from LDS, so the
+      // clamp costs no memory wait); the record indices read there are the sort's own and are
+      // not clamped (a clamp of each loaded index would make the wave wait for every gather in
+      // flight).
+      auto index_of = [&](uint32_t q) { return svals[q < jmax ? q : jmax]; };
       uint32_t qa, qb, ja, jb;
       bool va, vb, ra, rb;
       take(qa, va);
-      uint32_t ia = index_at(qa);
+      uint32_t ia = index_of(qa);
       take(qb, vb);
-      uint32_t ib = index_at(qb);
+      uint32_t ib = index_of(qb);
       float4 a0 = rec[kRecQuads * (int64_t)ia], a1 = rec[kRecQuads * (int64_t)ia + 1], a2 = rec[kRecQuads * (int64_t)ia + 2];
       float4 b0, b1, b2;
       ja = qa;
       ra = va;
       take(qa, va);
-      ia = index_at(qa);
+      ia = index_of(qa);
       while (ballot64(ra) != 0ull && dm != ~0ull) {
         b0 = rec[kRecQuads * (int64_t)ib];
         b1 = rec[kRecQuads * (int64_t)ib + 1];
@@ -448,7 +453,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
         jb = qb;
         rb = vb;
         take(qb, vb);
-        ib = index_at(qb);
+        ib = index_of(qb);
         batch(0u, ja, a0, a1, a2, ra);
         if (ballot64(rb) == 0ull || dm == ~0ull) break;
         a0 = rec[kRecQuads * (int64_t)ia];
@@ -457,7 +462,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
         ja = qa;
         ra = va;
         take(qa, va);
-        ia = index_at(qa);
+        ia = index_of(qa);
         batch(0u, jb, b0, b1, b2, rb);
       }
     } else {
