@@ -67,6 +67,37 @@ def test_long_tile_lists_bitexact_and_counted():
     assert 0 < g["pairs"][1] <= r["pair_classes"][1]
 
 
+def _dense_cluster_scene():
+    dense = synth.make_scene(380_000, 0, "uniform", seed=33, log_scale_mean=-5.0)
+    spread = synth.make_scene(20_000, 0, "uniform", seed=34, log_scale_mean=-2.5)
+    spread["mean"] = (spread["mean"] * np.float32(12.0)).astype(np.float32)
+    return dict(n=400_000, sh_degree=0, **{k: np.ascontiguousarray(np.concatenate([dense[k], spread[k]], axis=-1))
+                                          for k in ("mean", "log_scale", "quat", "opacity", "decay", "sh")})
+
+
+def test_very_long_lists_without_room_for_block_planes_bitexact():
+    """The lists of more than 65,536 entries of test_long_tile_lists_bitexact_and_counted in a
+    batch that also holds a 4K view culled almost entirely by its LoD scale (32,400 more tiles,
+    no pairs), at a pair capacity barely above the pair count: the very long tiles' block bit
+    planes (2 B per pair and 128 B per tile) then exceed the arrays the tile-id sort leaves
+    free, so the blend takes its ordinary 4x4 path for them.  Bit-identical to the oracle."""
+    log("case: very long lists, no room for bit planes")
+    sc = _dense_cluster_scene()
+    v0 = synth.look_at((0.0, 0.0, -40.0), width=96, height=80, s_v=1.0)
+    v1 = synth.look_at((0.0, 0.0, -40.0), width=3840, height=2160, s_v=1e4)
+    r0 = O.render32(sc, v0)
+    lists = np.diff(r0["tile_off"])
+    assert (lists >= 65536).sum() >= 2
+    cap = int(r0["entries"].size) + 64
+    tiles = 6 * 5 + 240 * 135
+    assert 16 * 8 * ((cap + 63) // 64 + tiles + 1) > 8 * cap   # the planes cannot fit
+    g = gpu_forward(sc, [v0, v1], dup_capacity=cap)
+    log(f"  pairs {g['D']} of capacity {cap}, tiles {tiles}")
+    assert g["D"] == r0["entries"].size
+    compare_forward(g, sc, [v0, v1])
+    assert g["pairs"][2] == r0["pair_classes"][2]
+
+
 @pytest.mark.parametrize("case", ["config1", "sh3_two_views"])
 def test_backward_pair_counters_match_the_contract(case):
     """clod_render_bwd's work counters: the pairs that contribute to the gradients are exactly the
