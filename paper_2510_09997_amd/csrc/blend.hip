@@ -5,7 +5,10 @@
 // are staged in LDS (one per lane or thread, a coalesced gather of the records) and read back
 // as LDS broadcasts; entries that provably cannot reach a quadrant are dropped for it (see
 // quadrant_mask).  Blocks take tiles longest list first (the order clod_bin_sort computes),
-// so the long tiles, not stragglers, start the launch.
+// so the long tiles, not stragglers, start the launch.  Lists of 8,192 entries or more are
+// blended with 4x4-pixel blocks per wave (four workgroups per tile); for lists of 65,536 or
+// more, a stage before the blend marks per entry the blocks it may reach, and each block's
+// wave walks only those entries.
 #include "clod_internal.h"
 
 namespace clod {
@@ -42,9 +45,9 @@ __device__ __forceinline__ uint32_t long_tiles(const BlendArgs& a) {
   const uint32_t nl = a.tord[kTileLongWord];
   return nl < a.long_max ? nl : a.long_max;
 }
-__device__ __forceinline__ uint32_t very_long_tiles(const uint32_t* tord, uint32_t long_max) {
+__device__ __forceinline__ uint32_t very_long_tiles(const uint32_t* tord, uint32_t vl_max) {
   const uint32_t nv = tord[kTileVeryLongWord];
-  return nv < long_max ? nv : long_max;
+  return nv < vl_max ? nv : vl_max;
 }
 
 __device__ __forceinline__ int view_of_tile(const DevView* views, int V, uint32_t tile) {
@@ -145,7 +148,9 @@ __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, fl
 // scene) are blended with 4x4-pixel blocks per wave: a wave walks only the entries that may
 // reach its block, and sixteen waves share the tile instead of four.  The tile order puts them
 // first (longest first): they are the first tord[kTileLongWord] positions, taken by the leading
-// workgroups of the launch.
+// workgroups of the launch.  Of these, the tiles of at least 2^(kVeryLongBucket - 1) entries
+// (the first tord[kTileVeryLongWord]) get their block tests from k_long_mask and their waves
+// walk compacted lists.
 
 // Forward blend.  Each wave owns one 8x8 quadrant of a tile (lane l: pixel (l & 7, l >> 3))
 // and runs on its own: it stages 64 entries of the tile's sorted list at a time in its
