@@ -92,13 +92,14 @@ def test_4k_request_alone_and_in_mixed_serving_batch_bitexact():
 
 def test_lod_sweep_6m_frames_bitexact_at_four_distances():
     """Frames of the continuous-LoD sweep (6M Gaussians, 1920x1080, camera at D_k = 2 100^(k/63)
-    on the -z axis) at k = 0, 21, 42, 63: the far frames hold the longest tile lists of any
-    workload.  Counts, pair count, last index, T and colour of every pixel bit-identical."""
+    on the -z axis) at k = 0, 21, 42, 56, 63: the far frames hold the longest tile lists of any
+    workload (at k = 56 and 63 lists of 65,536 entries or more, walked compacted per 4x4 block).
+    Counts, pair count, last index, T and colour of every pixel bit-identical."""
     log("case: 6M LoD sweep frames")
     sc = synth.make_scene(6_000_000, 3, "mixture", seed=0)
     scene = Scene(sc, packed_sh=True)
     ds = synth.sweep_distances(64, 2.0, 200.0)
-    for k in (0, 21, 42, 63):
+    for k in (0, 21, 42, 56, 63):
         view = synth.look_at((0.0, 0.0, -float(ds[k])), width=1920, height=1080)
         g = gpu_forward(sc, [view], scene=scene)
         r = O.render32(sc, view)
