@@ -153,10 +153,10 @@ __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, fl
 // walk compacted lists.
 
 // Forward blend.  Each wave owns one 8x8 quadrant of a tile (lane l: pixel (l & 7, l >> 3))
-// and runs on its own: it stages 64 entries of the tile's sorted list at a time in its
-// private LDS slice (one entry per lane, a coalesced gather), keeps the ones that can touch
-// its quadrant as a ballot mask, and walks the mask in list order with the next entry's
-// LDS reads issued before the current entry's arithmetic.  A wave stops as soon as its 64
+// and runs on its own: it takes 64 entries of the tile's sorted list at a time (one entry per
+// lane, a coalesced gather), stages the ones that can touch its quadrant in its private LDS
+// slice, compacted in list order, and walks them with the next entry's LDS reads issued
+// before the current entry's arithmetic.  A wave stops as soon as its 64
 // pixels are saturated, independently of the other quadrants; the only block barrier is the
 // final reduction of the optional pair counters.
 struct TileLds {
@@ -293,11 +293,12 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   // One batch of up to 64 entries, its records (g0, g1, g2) already in registers, lane l's
   // at list position j: staged in this wave's LDS slice, culled against the quadrant, then
   // walked.  The entries of a very long tile arrive already compacted to those that may reach
-  // the 4x4 block (relc); elsewhere the batch is the 64 entries from base and is culled here.
+  // the 4x4 block (relc); elsewhere the batch is 64 consecutive entries and is culled here.
   const bool pre = kB == 4 && pos < very_long_tiles(a.tord, a.vl_max);
-  auto batch = [&](const uint32_t base, const uint32_t j, const float4& g0, const float4& g1, const float4& g2,
+  auto batch = [&](const uint32_t j, const float4& g0, const float4& g1, const float4& g2,
                    const bool relc) {
     bool rel = false;
+    float cut = 0.0f;
     if (kB == 4 && pre) {
       rel = relc;
       if (rel) {
@@ -306,13 +307,27 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
         s2[lane] = make_float4(g2.z, entry_cut(g0.z), __uint_as_float(j - rg.x), 0.f);
       }
     } else if (j < rg.y) {
-      const float cut = entry_cut(g0.z);
-      s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
-      s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
-      s2[lane] = make_float4(g2.z, cut, __uint_as_float(j - rg.x), 0.f);
+      cut = entry_cut(g0.z);
+      if constexpr (kB == 4) {
+        s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
+        s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
+        s2[lane] = make_float4(g2.z, cut, __uint_as_float(j - rg.x), 0.f);
+      }
       rel = (quadrant_mask1<kB>(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, fqx, fqy)) != 0u;
     }
     uint64_t mask = ballot64(rel);
+    // 8x8 quadrants: the entries that may reach the quadrant are staged compacted, in list
+    // order (slot = rank of the lane among them), so that the walk below steps a counter.
+    if constexpr (kB == 8) {
+      if (rel) {
+        const uint32_t slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        s0[slot] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
+        s1[slot] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
+        s2[slot] = make_float4(g2.z, cut, __uint_as_float(j - rg.x), 0.f);
+      }
+    }
+    const uint32_t n = (uint32_t)__builtin_popcountll(mask);
+    if (kB == 8 && (n & 1u) && lane == 63u) s2[n] = make_float4(0.0f, __builtin_inff(), 0.0f, 0.0f);
     // The staged entries are read by other lanes of this wave: wait for the LDS writes.
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -328,7 +343,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     // lanes evaluate E (the wave skips it when none is live); the skip and termination tests
     // then run on the whole wave and are masked with the live set, so al and Tn of other
     // lanes are never used.
-    auto pair = [&](const float4& a, const float4& c, const float4& bc, int e) {
+    auto pair = [&](const float4& a, const float4& c, const float4& bc) {
       const float dx = a.x - pcx, dy = a.y - pcy;
       const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
       const uint64_t lm = ballot64(power <= 0.0f) & ballot64(power >= bc.y) & ~dm;
@@ -346,7 +361,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       const uint64_t km = ballot64(Tn >= kTmin);
       const uint64_t bm = um & km;
       dm |= um & ~km;
-      const uint32_t pos = base - rg.x + (uint32_t)e;
+      const uint32_t pos = __float_as_uint(bc.z);
       if (__builtin_amdgcn_inverse_ballot_w64(bm)) {
         const float w = al * T;
         cr = fmaf_(c.z, w, cr);
@@ -362,23 +377,18 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       }
     };
     // Two register sets in alternation: the LDS reads of the next entry are in flight while
-    // the current one is evaluated, with no copies between iterations.
-    int e0 = __builtin_ctzll(mask);
-    mask &= mask - 1;
-    float4 a0 = s0[e0], c0 = s1[e0], b0 = s2[e0];
-    for (;;) {
-      bool more = mask != 0ull;
-      const int e1 = more ? __builtin_ctzll(mask) : e0;
-      mask &= mask - 1;
-      const float4 a1 = s0[e1], c1 = s1[e1], b1 = s2[e1];
-      pair(a0, c0, b0, e0);
-      if (!more) break;
-      more = mask != 0ull;
-      e0 = more ? __builtin_ctzll(mask) : e1;
-      mask &= mask - 1;
-      a0 = s0[e0]; c0 = s1[e0]; b0 = s2[e0];
-      pair(a1, c1, b1, e1);
-      if (!more || dm == ~0ull) break;
+    // the current one is evaluated, with no copies between iterations.  The walk takes the
+    // slots two at a time; an odd count is padded with slot n, given a cut of +inf (so no
+    // pixel is live for it) before the wave barrier above.  (Slots past that hold stale
+    // entries: they may be read ahead, within the slice, but are never walked.)
+    float4 a0 = s0[0], c0 = s1[0], b0 = s2[0];
+    for (uint32_t k = 0; k < n; k += 2) {
+      const float4 a1 = s0[k + 1u], c1 = s1[k + 1u], b1 = s2[k + 1u];
+      pair(a0, c0, b0);
+      const uint32_t k2 = k + 2u < 63u ? k + 2u : 63u;
+      a0 = s0[k2]; c0 = s1[k2]; b0 = s2[k2];
+      pair(a1, c1, b1);
+      if (dm == ~0ull) break;
     }
   };
   // Software pipeline over the batches, unrolled by two with a register set each (A, B), so
@@ -459,7 +469,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
         rb = vb;
         take(qb, vb);
         ib = index_of(qb);
-        batch(0u, ja, a0, a1, a2, ra);
+        batch(ja, a0, a1, a2, ra);
         if (ballot64(rb) == 0ull || dm == ~0ull) break;
         a0 = rec[kRecQuads * (int64_t)ia];
         a1 = rec[kRecQuads * (int64_t)ia + 1];
@@ -468,7 +478,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
         ra = va;
         take(qa, va);
         ia = index_of(qa);
-        batch(0u, jb, b0, b1, b2, rb);
+        batch(jb, b0, b1, b2, rb);
       }
     } else {
     uint32_t ia = index_at(rg.x + lane);
@@ -481,13 +491,13 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       b1 = rec[kRecQuads * (int64_t)ib + 1];
       b2 = rec[kRecQuads * (int64_t)ib + 2];
       ib = index_at(base + 192 + lane);
-      batch(base, base + lane, a0, a1, a2, false);
+      batch(base + lane, a0, a1, a2, false);
       if (base + 64 >= rg.y || dm == ~0ull) break;
       a0 = rec[kRecQuads * (int64_t)ia];
       a1 = rec[kRecQuads * (int64_t)ia + 1];
       a2 = rec[kRecQuads * (int64_t)ia + 2];
       ia = index_at(base + 256 + lane);
-      batch(base + 64, base + 64 + lane, b0, b1, b2, false);
+      batch(base + 64 + lane, b0, b1, b2, false);
     }
     }
   }
