@@ -133,7 +133,7 @@ __device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float A, flo
 template <int kB>
 __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, float B, float C, float rad,
                                                    float cut, float x0, float y0) {
-  if (cut > 0.0f) return 0u;
+  if (!(cut <= 0.0f)) return 0u;   // never live (a NaN cut included: no power reaches it)
   const float ac = A * C;
   const float det = ac - B * B;
   if (!(det > 2e-5f * ac) || !(rad < 1e6f)) return 1u;
@@ -327,7 +327,10 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       }
     }
     const uint32_t n = (uint32_t)__builtin_popcountll(mask);
-    if (kB == 8 && (n & 1u) && lane == 63u) s2[n] = make_float4(0.0f, __builtin_inff(), 0.0f, 0.0f);
+    if (kB == 8 && (n & 1u) && lane == 63u) {
+      s0[n] = make_float4(__builtin_nanf(""), __builtin_nanf(""), 0.0f, 0.0f);
+      s2[n] = make_float4(0.0f, __builtin_inff(), 0.0f, 0.0f);
+    }
     // The staged entries are read by other lanes of this wave: wait for the LDS writes.
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -339,22 +342,20 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     }
     // One entry: the contract's skip, exponential, clamp, termination and blend.  Below the
     // entry's cut (or above 0) the contract skips the pair whatever E returns; live pairs have
-    // power in [cut, 0] with cut >= ln(1/255) - 0.01, inside cexp_core's range.  Only live
-    // lanes evaluate E (the wave skips it when none is live); the skip and termination tests
-    // then run on the whole wave and are masked with the live set, so al and Tn of other
-    // lanes are never used.
+    // power in [cut, 0] with cut >= ln(1/255) - 0.01, inside cexp_core's range.  Once some
+    // lane is live, every lane evaluates E (an exec-mask region around it would cost scalar
+    // instructions and save no vector ones); the skip and termination tests then run on the
+    // whole wave and are masked with the live set, so al and Tn of other lanes are never used.
     auto pair = [&](const float4& a, const float4& c, const float4& bc) {
       const float dx = a.x - pcx, dy = a.y - pcy;
       const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
-      const uint64_t lm = ballot64(power <= 0.0f) & ballot64(power >= bc.y) & ~dm;
+      // cut <= power <= 0 as one test: a staged entry has cut <= 0 (quadrant_mask1 culls the
+      // others), so the median of (power, cut, 0) is power exactly then; a NaN power (the
+      // padding entry) compares unequal.
+      const uint64_t lm = ballot64(__builtin_amdgcn_fmed3f(power, bc.y, 0.0f) == power) & ~dm;
       if (lm == 0ull) return;
-      // Lanes outside the live set keep placeholder values (dead registers, so no copies);
-      // their tests below are masked off.
-      float al = power, Tn = dx;
-      if (__builtin_amdgcn_inverse_ballot_w64(lm)) {
-        al = fminf(0.99f, c.y * cexp_core(power));
-        Tn = T * (1.0f - al);
-      }
+      const float al = fminf(0.99f, c.y * cexp_core<true>(power));
+      const float Tn = T * (1.0f - al);
       // al is never NaN (fminf returns 0.99 for a NaN product) and T is in (0, 1], so
       // Tn >= fl(1e-4) is exactly the negation of the contract's termination test.
       const uint64_t um = ballot64(al >= kSkip) & lm;
@@ -378,9 +379,11 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     };
     // Two register sets in alternation: the LDS reads of the next entry are in flight while
     // the current one is evaluated, with no copies between iterations.  The walk takes the
-    // slots two at a time; an odd count is padded with slot n, given a cut of +inf (so no
-    // pixel is live for it) before the wave barrier above.  (Slots past that hold stale
+    // slots two at a time; an odd count is padded with slot n, given a NaN position and a cut
+    // of +inf (so no pixel is live for it) before the wave barrier above.  (Slots past that hold stale
     // entries: they may be read ahead, within the slice, but are never walked.)
+    // The saturation of all 64 pixels is checked per batch, by the caller: within a batch the
+    // loop has no exit test but its count.
     float4 a0 = s0[0], c0 = s1[0], b0 = s2[0];
     for (uint32_t k = 0; k < n; k += 2) {
       const float4 a1 = s0[k + 1u], c1 = s1[k + 1u], b1 = s2[k + 1u];
@@ -388,7 +391,6 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       const uint32_t k2 = k + 2u < 63u ? k + 2u : 63u;
       a0 = s0[k2]; c0 = s1[k2]; b0 = s2[k2];
       pair(a1, c1, b1);
-      if (dm == ~0ull) break;
     }
   };
   // Software pipeline over the batches, unrolled by two with a register set each (A, B), so

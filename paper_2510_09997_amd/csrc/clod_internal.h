@@ -95,10 +95,22 @@ int sorted_buffer(uint32_t tiles_total);   // ping-pong buffer (0/1) holding the
 // ----------------------------------------------------------------------------------------
 __device__ __forceinline__ float fmaf_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Float to int32 as the hardware converts (saturating; NaN gives 0).  A C++ conversion of a
+// value outside the int32 range is undefined, which matters where lanes outside the live set
+// evaluate the exponential on arbitrary arguments (their results are discarded).
+__device__ __forceinline__ int cvt_i32_sat(float k) {
+  int r;
+  asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(k));
+  return r;
+}
+
 // Contract exponential: Cody-Waite reduction with a 16-bit head of ln 2, degree-7 Taylor
 // polynomial (1/j! rounded to binary32) in Horner form, scale by 2^k; zero below -86.
 // The contract exponential for x in [-86, 88] (no range or NaN handling): cexp below adds
-// those; the blend calls this directly on arguments it has already bounded.
+// those; the blend calls this directly on arguments it has already bounded (kAnyArg: or on any
+// argument, for lanes whose result it discards; the result is then unspecified, but no
+// operation is undefined, and inside the range it is the same).
+template <bool kAnyArg = false>
 __device__ __forceinline__ float cexp_core(float x) {
   constexpr float kL2E = 1.44269502162933349609375f;          // fl(1/ln 2)
   constexpr float kLn2Hi = 0.693145751953125f;                // floor(ln2 * 2^16) / 2^16
@@ -120,7 +132,7 @@ __device__ __forceinline__ float cexp_core(float x) {
   p = fmaf_(p, r, 1.0f);
   p = fmaf_(p, r, 1.0f);
   // p * 2^k, exact for every k that cexp's clamped range produces (the result stays normal).
-  return __builtin_amdgcn_ldexpf(p, (int)k);
+  return __builtin_amdgcn_ldexpf(p, kAnyArg ? cvt_i32_sat(k) : (int)k);
 }
 
 __device__ __forceinline__ float cexp(float x) {
