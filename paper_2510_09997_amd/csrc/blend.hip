@@ -156,8 +156,8 @@ __device__ __forceinline__ uint32_t quadrant_mask1(float u, float v, float A, fl
 // and runs on its own: it takes 64 entries of the tile's sorted list at a time (one entry per
 // lane, a coalesced gather), stages the ones that can touch its quadrant in its private LDS
 // slice, compacted in list order, and walks them with the next entry's LDS reads issued
-// before the current entry's arithmetic.  A wave stops as soon as its 64
-// pixels are saturated, independently of the other quadrants; the only block barrier is the
+// before the current entry's arithmetic.  A wave stops after the batch in which its 64
+// pixels saturate, independently of the other quadrants; the only block barrier is the
 // final reduction of the optional pair counters.
 struct TileLds {
   float4 st[4][3][64];   // per wave: (u, v, hA, nB), (hC, alpha'', r, g), (b, cut, list position, -)
