@@ -88,7 +88,8 @@ def run_serving(args, torch, C, Batch, Scene, synth):
     n = 3_000_000
     log(f"[bench] scene: {n} Gaussians, SH degree 3, mixture")
     sc = synth.make_scene(n, 3, "mixture", seed=0)
-    scene = Scene(sc, packed_sh=True)   # static scene: per-Gaussian SH copy
+    # Static scene: stored in Morton order of the means (clod_scene_reorder), per-Gaussian SH copy.
+    scene = Scene(sc, packed_sh=True, spatial_order=True)
     del sc
     K, W = args.steps, args.warmup
     # Timed poses depend on K only (warm-up poses are drawn apart), so any warm-up count times
@@ -501,7 +502,8 @@ def run_lod_sweep(args, torch, C, Batch, Scene, synth):
     the nearest pose."""
     n = 6_000_000
     sc = synth.make_scene(n, 3, "mixture", seed=0)
-    scene = Scene(sc, packed_sh=True)   # static scene: per-Gaussian SH copy
+    # Static scene: stored in Morton order of the means (clod_scene_reorder), per-Gaussian SH copy.
+    scene = Scene(sc, packed_sh=True, spatial_order=True)
     del sc
     ds = synth.sweep_distances(64, 2.0, 200.0)
     ray = [synth.look_at((0.0, 0.0, -float(d)), width=1920, height=1080) for d in ds]
@@ -574,7 +576,8 @@ def run_serve_stream(args, torch, Scene, synth):
     from paper_2510_09997_amd.serve import serve, summarize
     n = 3_000_000
     sc = synth.make_scene(n, 3, "mixture", seed=0)
-    scene = Scene(sc, packed_sh=True)   # static scene: per-Gaussian SH copy
+    # Static scene: stored in Morton order of the means (clod_scene_reorder), per-Gaussian SH copy.
+    scene = Scene(sc, packed_sh=True, spatial_order=True)
     del sc
     budget = 24 << 30
     inflight = {"plain": 1, "continuous": 3, "persistent": 8}

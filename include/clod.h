@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CLOD_ABI_VERSION 12
+#define CLOD_ABI_VERSION 13
 #define CLOD_MAX_VIEWS 1024
 
 typedef enum {
@@ -182,6 +182,24 @@ clod_status clod_render_bwd(const clod_scene *scene, const clod_batch *batch, co
    shorter one is rejected with CLOD_E_ARG); batch->dup is not used. */
 clod_status clod_lod_count(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
                            void *stream);
+
+/* Scene preparation, not an operation of the method: reorders a scene's Gaussians along a
+   Morton (Z-order) curve of their means, so that Gaussians close in space are close in memory
+   (the per-(view, Gaussian) records that the blend gathers are indexed by Gaussian, and
+   neighbours in memory then tend to serve the same tiles).  Every result of the library is
+   defined on the scene as stored, so a reordered scene renders the Gaussians of the original
+   one (ties in depth fall to the lower index of the new order).
+   The order: 10 bits per axis over the bounding box of the finite mean coordinates (coordinates
+   outside it or not finite clamp to its faces, an axis without extent gives zero bits), bits
+   interleaved x lowest, then a stable sort by the 30-bit code (equal codes keep index order).
+   perm (device uint32 [n]) receives perm[j] = the original index of the Gaussian placed at j;
+   dst (device planes in clod_scene's layout, sh with src's degree) receives src's planes
+   gathered by perm; sh_packed is not read or written (build it from dst's sh).  workspace:
+   device, 256-byte aligned, >= clod_scene_reorder_ws_bytes(n) bytes.  dst must not overlap
+   src; n <= 2^31 - 1.  CLOD_E_ARG on invalid arguments (nothing launched); n = 0 is a no-op. */
+size_t clod_scene_reorder_ws_bytes(int64_t n);
+clod_status clod_scene_reorder(const clod_scene *src, const clod_scene_grad *dst, uint32_t *perm,
+                               void *workspace, size_t workspace_bytes, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
    that must not call hipMalloc, harnesses that forbid it): the counts of clod_lod_count, with

@@ -20,7 +20,7 @@ CLOD_OK, CLOD_E_ARG, CLOD_E_CAPACITY, CLOD_E_HIP, CLOD_E_UNSUPPORTED, CLOD_E_BUS
 MAX_VIEWS = 1024
 LOD_SCRATCH_BYTES = 64 << 20   # library scratch of clod_lod_count_noalloc (per GPU)
 SERVER_SLOTS, SERVER_MAX_VIEWS = 16, 16
-ABI_VERSION = 12
+ABI_VERSION = 13
 
 
 class ClodError(RuntimeError):
@@ -80,7 +80,7 @@ EXPORTS = ["clod_ws_bytes", "clod_dup_bytes", "clod_dup_capacity", "clod_project
            "clod_render_fwd", "clod_render_bwd", "clod_lod_count", "clod_loss", "clod_read_info",
            "clod_inspect", "clod_last_error", "clod_abi_version", "clod_adam_step", "clod_lod_count_noalloc",
            "clod_server_start", "clod_server_submit", "clod_server_poll", "clod_server_clock", "clod_server_stop",
-           "clod_server_stage_times"]
+           "clod_server_stage_times", "clod_scene_reorder_ws_bytes", "clod_scene_reorder"]
 
 SEC_KEYS, SEC_VALUES, SEC_RANGES, SEC_REC, SEC_ALPHA = 0, 1, 2, 3, 4
 SEC_FLAGS, SEC_DMAX, SEC_GSCREEN, SEC_HEADER = 6, 7, 9, 10
@@ -107,6 +107,8 @@ def load(path: str = LIB_PATH):
     L.clod_render_bwd.argtypes = [P, P, P, P, P, P, i32, P, P, P]; L.clod_render_bwd.restype = i32
     L.clod_lod_count.argtypes = [P, P, P, P]; L.clod_lod_count.restype = i32
     L.clod_lod_count_noalloc.argtypes = [P, i32, P, P, P, P, P]; L.clod_lod_count_noalloc.restype = i32
+    L.clod_scene_reorder_ws_bytes.argtypes = [i64]; L.clod_scene_reorder_ws_bytes.restype = sz
+    L.clod_scene_reorder.argtypes = [P, P, P, P, sz, P]; L.clod_scene_reorder.restype = i32
     L.clod_loss.argtypes = [P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, P, sz, P, P, P, P]
     L.clod_loss.restype = i32
     L.clod_read_info.argtypes = [P, P, P]; L.clod_read_info.restype = i32
@@ -263,6 +265,17 @@ def clod_lod_count_noalloc(scene: clod_scene, views_host, views_dev, params: clo
     _check(load().clod_lod_count_noalloc(ctypes.byref(scene), len(views_host), ctypes.cast(views_host, P),
                                          _ptr(views_dev, torch.uint8), ctypes.byref(params), _ptr(counts, I64),
                                          _stream(stream)))
+
+
+
+def clod_scene_reorder_ws_bytes(n: int) -> int:
+    return int(load().clod_scene_reorder_ws_bytes(int(n)))
+
+
+def clod_scene_reorder(src: clod_scene, dst: clod_scene_grad, perm, ws, stream=None):
+    """Spatial (Morton) order of src's Gaussians into dst's planes; perm[j] = original index."""
+    _check(load().clod_scene_reorder(ctypes.byref(src), ctypes.byref(dst), _ptr(perm, I32), _ptr(ws, torch.uint8),
+                                     ws.numel() if isinstance(ws, torch.Tensor) else 0, _stream(stream)))
 
 
 ADAM_GROUPS = ("mean", "log_scale", "quat", "opacity", "decay", "sh_dc", "sh_rest")

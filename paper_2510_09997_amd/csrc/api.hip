@@ -501,6 +501,64 @@ clod_status clod_lod_count_noalloc(const clod_scene* scene, int32_t n_views, con
   return CLOD_OK;
 }
 
+// Scene preparation: the workspace of clod_scene_reorder and the call.
+struct OrderLayout {
+  size_t box, hdr, hist, keys0, keys1, vals1, total;
+  int G;
+};
+static OrderLayout order_layout(int64_t n) {
+  OrderLayout O;
+  size_t o = 0;
+  O.G = sort_blocks(n);
+  O.box = o; o = align256(o + 6 * 4);
+  O.hdr = o; o = align256(o + (size_t)kHdrWords * 8);
+  O.hist = o; o = align256(o + ((size_t)256 * O.G + 256) * 4);
+  O.keys0 = o; o = align256(o + (size_t)n * 4);
+  O.keys1 = o; o = align256(o + (size_t)n * 4);
+  O.vals1 = o; o = align256(o + (size_t)n * 4);
+  O.total = o;
+  return O;
+}
+
+size_t clod_scene_reorder_ws_bytes(int64_t n) {
+  if (n < 0 || n > (int64_t)INT32_MAX) return 0;
+  return order_layout(n).total;
+}
+
+clod_status clod_scene_reorder(const clod_scene* src, const clod_scene_grad* dst, uint32_t* perm, void* ws,
+                               size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  clod_status st = check_scene(src);
+  if (st != CLOD_OK) return st;
+  if (src->n > (int64_t)INT32_MAX) return fail(CLOD_E_ARG, "scene.n must be <= 2^31 - 1");
+  if (!dst || !perm) return fail(CLOD_E_ARG, "dst and perm must be non-NULL");
+  if (src->n == 0) return CLOD_OK;
+  const int64_t n = src->n;
+  const int K = (src->sh_degree + 1) * (src->sh_degree + 1);
+  const float* sp[6] = {src->mean, src->log_scale, src->quat, src->opacity, src->decay, src->sh};
+  float* dp[6] = {dst->mean, dst->log_scale, dst->quat, dst->opacity, dst->decay, dst->sh};
+  const int64_t planes[6] = {3, 3, 4, 1, 1, 3 * (int64_t)K};
+  for (int i = 0; i < 6; ++i)
+    if (!dp[i]) return fail(CLOD_E_ARG, "dst planes must be non-NULL");
+  // No destination array may overlap a source array.
+  for (int i = 0; i < 6; ++i) {
+    const uintptr_t d0 = (uintptr_t)dp[i], d1 = d0 + (uintptr_t)(planes[i] * n * 4);
+    for (int j = 0; j < 6; ++j) {
+      const uintptr_t s0 = (uintptr_t)sp[j], s1 = s0 + (uintptr_t)(planes[j] * n * 4);
+      if (d0 < s1 && s0 < d1) return fail(CLOD_E_ARG, "dst planes must not overlap src planes");
+    }
+  }
+  const OrderLayout O = order_layout(n);
+  if (!ws) return fail(CLOD_E_ARG, "workspace is NULL");
+  if ((uintptr_t)ws % 256) return fail(CLOD_E_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < O.total) return fail(CLOD_E_ARG, "workspace_bytes %zu < required %zu", ws_bytes, O.total);
+  char* w = (char*)ws;
+  OrderBufs ob{(uint32_t*)(w + O.box), (unsigned long long*)(w + O.hdr), (uint32_t*)(w + O.hist),
+               {(uint32_t*)(w + O.keys0), (uint32_t*)(w + O.keys1)}, {perm, (uint32_t*)(w + O.vals1)}, O.G};
+  HIP_TRY(launch_scene_reorder(*src, *dst, ob, (hipStream_t)stream), "scene reorder");
+  return CLOD_OK;
+}
+
 clod_status clod_loss(const clod_batch* batch, const float* rgb, const float* target, float s_max,
                       float lambda_reg, float lambda_dssim, float* ssim_scratch, size_t ssim_scratch_bytes,
                       float* loss_dev, float* dL_drgb, float* dL_deta_dev, void* stream) {

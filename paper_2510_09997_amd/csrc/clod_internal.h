@@ -595,6 +595,21 @@ struct Sink {
   }
 };
 
+// Scene preparation (spatial order): device sections of the caller's workspace, and the gather
+// of the planes.
+struct OrderBufs {
+  uint32_t* box;              // 6 order keys: min x, y, z; max x, y, z
+  unsigned long long* hdr;    // kHdrWords header words (count in kHdrRend)
+  uint32_t* hist;             // (256 G + 256) radix counts
+  uint32_t* keys[2];          // codes, ping-pong
+  uint32_t* vals[2];          // indices, ping-pong; vals[0] is the caller's permutation
+  int G;                      // radix blocks
+};
+struct OrderGatherArgs {
+  const float* src[6]; float* dst[6]; int planes[6]; int64_t n; const uint32_t* perm;
+};
+hipError_t launch_scene_reorder(const clod_scene& src, const clod_scene_grad& dst, const OrderBufs& ob, hipStream_t s);
+
 // ----------------------------------------------------------------------------------------
 // Launchers (each returns the first launch error, or hipSuccess).
 // ----------------------------------------------------------------------------------------

@@ -844,4 +844,125 @@ hipError_t launch_sort_stage(const Stage& st, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ----------------------------------------------------------- scene preparation: spatial order
+// A Morton (Z-order) permutation of a scene's Gaussians by their means, and the gather of every
+// plane into that order.  Not a step of the per-frame path: a one-time preparation that puts
+// Gaussians that are close in space close in memory, so that the records of neighbouring
+// Gaussians (indexed view * n + Gaussian, 64 bytes, gathered by the blend in 128-byte lines)
+// tend to serve the same tiles.
+
+// Float bits mapped to an unsigned key of the same order, and back (the bounding box is kept as
+// keys so that it can be reduced with integer atomics).
+__device__ __forceinline__ uint32_t order_key(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
+}
+__device__ __forceinline__ float order_key_inv(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
+}
+// The 10 low bits of v moved to every third bit (bit b to bit 3b).
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// Empty box (min keys all ones, max keys zero) and the sort header: count n, no overflow.
+__global__ __launch_bounds__(64) void k_order_init(uint32_t* box, unsigned long long* hdr, int64_t n) {
+  const int t = threadIdx.x;
+  if (t < 3) box[t] = 0xFFFFFFFFu;
+  else if (t < 6) box[t] = 0u;
+  else if (t < 6 + kHdrWords) hdr[t - 6] = (t - 6 == kHdrRend) ? (unsigned long long)n : 0ull;
+}
+
+// Bounding box of the finite coordinates of the means (per axis, as order keys).
+__global__ __launch_bounds__(kBlock) void k_order_box(const float* __restrict__ mean, int64_t n, uint32_t* box) {
+  uint32_t mn[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, mx[3] = {0u, 0u, 0u};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float x = mean[a * n + i];
+      if (__builtin_isfinite(x)) {
+        const uint32_t k = order_key(x);
+        mn[a] = k < mn[a] ? k : mn[a];
+        mx[a] = k > mx[a] ? k : mx[a];
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t p = __shfl_xor(mn[a], o, 64), q = __shfl_xor(mx[a], o, 64);
+      mn[a] = p < mn[a] ? p : mn[a];
+      mx[a] = q > mx[a] ? q : mx[a];
+    }
+  }
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(box + a, mn[a]);
+      atomicMax(box + 3 + a, mx[a]);
+    }
+  }
+}
+
+// 30-bit Morton code of each mean (10 bits per axis over the box; x in the lowest bit) and the
+// identity values.  Coordinates outside the box or not finite clamp to its faces; an axis with
+// no extent contributes zero bits.
+__global__ __launch_bounds__(kBlock) void k_order_codes(const float* __restrict__ mean, int64_t n,
+                                                        const uint32_t* __restrict__ box, uint32_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  uint32_t code = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = order_key_inv(box[a]), hi = order_key_inv(box[3 + a]);
+    const float ext = hi - lo;
+    const float sc = ext > 0.0f ? 1024.0f / ext : 0.0f;
+    const float q = fminf(fmaxf((mean[a * n + i] - lo) * sc, 0.0f), 1023.0f);
+    code |= spread3((uint32_t)q) << a;
+  }
+  keys[i] = code;
+  vals[i] = (uint32_t)i;
+}
+
+// Output position j of every plane takes the Gaussian perm[j].
+__global__ __launch_bounds__(kBlock) void k_order_gather(OrderGatherArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (j >= a.n) return;
+  int64_t i = (int64_t)a.perm[j];
+  if (i >= a.n) i = j;   // defensive: the sort emits a permutation of 0 .. n-1
+  for (int p = 0; p < 6; ++p) {
+    const float* __restrict__ src = a.src[p];
+    float* __restrict__ dst = a.dst[p];
+    for (int q = 0; q < a.planes[p]; ++q) dst[(int64_t)q * a.n + j] = src[(int64_t)q * a.n + i];
+  }
+}
+
+hipError_t launch_scene_reorder(const clod_scene& src, const clod_scene_grad& dst, const OrderBufs& ob, hipStream_t s) {
+  const int64_t n = src.n;
+  if (n <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_order_init, dim3(1), dim3(64), 0, s, ob.box, ob.hdr, n);
+  hipLaunchKernelGGL(k_order_box, dim3(nb < 1024u ? nb : 1024u), dim3(kBlock), 0, s, src.mean, n, ob.box);
+  hipLaunchKernelGGL(k_order_codes, dim3(nb), dim3(kBlock), 0, s, src.mean, n, (const uint32_t*)ob.box,
+                     ob.keys[0], ob.vals[0]);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // Stable LSD sort of the 30-bit codes, four 8-bit passes, back in buffer 0 (vals[0] = perm).
+  e = radix_passes(ob.hdr, kHdrRend, ob.G, 0, 4, ob.keys, ob.vals, 0, ob.hist, Sink(s));
+  if (e != hipSuccess) return e;
+  const int K = (src.sh_degree + 1) * (src.sh_degree + 1);
+  OrderGatherArgs g{{src.mean, src.log_scale, src.quat, src.opacity, src.decay, src.sh},
+                    {dst.mean, dst.log_scale, dst.quat, dst.opacity, dst.decay, dst.sh},
+                    {3, 3, 4, 1, 1, 3 * K}, n, ob.vals[0]};
+  hipLaunchKernelGGL(k_order_gather, dim3(nb), dim3(kBlock), 0, s, g);
+  return hipGetLastError();
+}
+
 }  // namespace clod

@@ -19,7 +19,7 @@ PLANES = ("mean", "log_scale", "quat", "opacity", "decay", "sh")
 class Scene:
     """A device-resident scene in the C layout (float32 planes, see include/clod.h)."""
 
-    def __init__(self, planes: dict, device="cuda", packed_sh: bool = False):
+    def __init__(self, planes: dict, device="cuda", packed_sh: bool = False, spatial_order: bool = False):
         self.n = int(planes["n"])
         self.sh_degree = int(planes["sh_degree"])
         self.t = {}
@@ -28,6 +28,18 @@ class Scene:
             if isinstance(v, np.ndarray):
                 v = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32))
             self.t[k] = v.to(device=device, dtype=torch.float32).contiguous()
+        # spatial_order: the Gaussians are stored along a Morton curve of their means
+        # (clod_scene_reorder); self.perm[j] is the caller's index of stored Gaussian j.
+        self.perm = None
+        self.sh_packed = None
+        if spatial_order and self.n > 0:
+            dst = {k: torch.empty_like(v) for k, v in self.t.items()}
+            perm = torch.empty(self.n, dtype=torch.int32, device=device)
+            ws = torch.empty(C.clod_scene_reorder_ws_bytes(self.n), dtype=torch.uint8, device=device)
+            C.clod_scene_reorder(self.c_struct(), C.make_grad(dst), perm, ws)
+            torch.cuda.synchronize()
+            del ws
+            self.t, self.perm = dst, perm
         # Static scenes (serving) may also keep the SH coefficients per Gaussian
         # ([n][K][3]), which the projection gathers far more cheaply for its sparse set.
         self.sh_packed = None

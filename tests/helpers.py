@@ -52,6 +52,14 @@ def gpu_forward(sc: dict, views, params: dict | None = None, dup_capacity=None, 
     return out
 
 
+def stored_planes(scene: Scene) -> dict:
+    """Host copies of a device scene's planes as stored (after any spatial reorder), in the
+    layout of the synthetic scenes, for the oracle."""
+    d = {k: v.cpu().numpy() for k, v in scene.t.items()}
+    d["n"], d["sh_degree"] = scene.n, scene.sh_degree
+    return d
+
+
 def tile_bases(views):
     tb = [0]
     for v in views:

@@ -236,3 +236,41 @@ def test_noalloc_lod_count_rejects_inputs_beyond_its_scratch_before_launch():
     assert st == C.CLOD_E_ARG
     assert lib.clod_lod_count_noalloc(ctypes.byref(fake_scene()), 0, ctypes.cast(one, C.P), FAKE,
                                       ctypes.byref(p), FAKE, None) == C.CLOD_E_ARG
+
+
+def test_scene_reorder_workspace_sizes():
+    a, b = C.clod_scene_reorder_ws_bytes(1000), C.clod_scene_reorder_ws_bytes(3_000_000)
+    assert a % 256 == 0 and b % 256 == 0 and b > a >= 3 * 4 * 1000
+    assert C.clod_scene_reorder_ws_bytes(-1) == 0 and C.clod_scene_reorder_ws_bytes(1 << 31) == 0
+
+
+@pytest.mark.parametrize("case", ["null_dst", "null_perm", "null_plane", "overlap", "no_ws", "misaligned_ws",
+                                  "small_ws", "too_many", "degree_4"])
+@no_gpu_only
+def test_scene_reorder_rejects_invalid_arguments_before_launch(case):
+    n = 1000
+    src = fake_scene(n, 3)
+    dst = C.clod_scene_grad()
+    for j, k in enumerate(("mean", "log_scale", "quat", "opacity", "decay", "sh")):
+        setattr(dst, k, (1 << 30) + j * (1 << 20))
+    perm, ws, nbytes = 1 << 29, 1 << 28, C.clod_scene_reorder_ws_bytes(n)
+    dst_arg = ctypes.byref(dst)
+    if case == "null_dst":
+        dst_arg = None
+    elif case == "null_perm":
+        perm = None
+    elif case == "null_plane":
+        dst.quat = None
+    elif case == "overlap":
+        dst.sh = FAKE + 4 * n
+    elif case == "no_ws":
+        ws = None
+    elif case == "misaligned_ws":
+        ws += 16
+    elif case == "small_ws":
+        nbytes -= 256
+    elif case == "too_many":
+        src.n = 1 << 31
+    elif case == "degree_4":
+        src.sh_degree = 4
+    assert C.load().clod_scene_reorder(ctypes.byref(src), dst_arg, perm, ws, nbytes, None) == C.CLOD_E_ARG, case

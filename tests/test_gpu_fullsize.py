@@ -1,6 +1,8 @@
 """Parity at the benchmark's full sizes, in the launch configurations bench.py times.
 
-* Serving headline: 3,000,000 Gaussians (degree 3, 64-cluster mixture, per-Gaussian SH copy),
+* Serving headline: 3,000,000 Gaussians (degree 3, 64-cluster mixture, per-Gaussian SH copy,
+  stored in Morton order as the benchmark stores its serving scenes; the oracle runs on the
+  stored planes),
   the five LoD frames s_v = 1, 2, 4, 8, 16 of one pose as one batch at 1920x1080: counts, pair
   count, last-contributor indices, transmittance and colour of every pixel of every frame
   bit-identical to the oracle.
@@ -21,7 +23,7 @@ from paper_2510_09997_amd import _clod as C, synth
 from paper_2510_09997_amd.render import Batch, Scene
 from paper_2510_09997_amd.train import MultiViewTrainer
 
-from helpers import check_grads, gpu_forward, params_struct
+from helpers import check_grads, gpu_forward, params_struct, stored_planes
 
 pytestmark = pytest.mark.gpu
 
@@ -39,10 +41,11 @@ def log(*a):
 
 
 def test_headline_batch_full_size_bitexact():
-    log("case: 3M, five LoD frames at 1080p in one packed-SH batch")
-    sc = synth.make_scene(3_000_000, 3, "mixture", seed=0)
+    log("case: 3M, five LoD frames at 1080p in one packed-SH batch, scene in Morton order")
+    scene = Scene(synth.make_scene(3_000_000, 3, "mixture", seed=0), packed_sh=True, spatial_order=True)
+    sc = stored_planes(scene)
     views = [synth.look_at((6.0, -3.5, -9.0), width=1920, height=1080, s_v=s) for s in SV_SWEEP]
-    g = gpu_forward(sc, views, packed_sh=True)
+    g = gpu_forward(sc, views, scene=scene)
     total = 0
     for v, view in enumerate(views):
         r = O.render32(sc, view)
@@ -69,9 +72,9 @@ def test_4k_request_alone_and_in_mixed_serving_batch_bitexact():
     a 4K view rendered alone and inside a batch with a 1280x720 and a 1920x1080 request, every
     pixel of every view bit-identical to the oracle, and the 4K frame of the mix byte for byte
     the frame rendered alone."""
-    log("case: 3M, 4K alone and in a 720p / 4K / 1080p batch")
-    sc = synth.make_scene(3_000_000, 3, "mixture", seed=0)
-    scene = Scene(sc, packed_sh=True)
+    log("case: 3M, 4K alone and in a 720p / 4K / 1080p batch, scene in Morton order")
+    scene = Scene(synth.make_scene(3_000_000, 3, "mixture", seed=0), packed_sh=True, spatial_order=True)
+    sc = stored_planes(scene)
     v4k = synth.look_at((2.0, 1.5, -7.0), width=3840, height=2160, s_v=1.7)
     v720 = synth.look_at((-9.0, 4.0, 12.0), width=1280, height=720, s_v=5.0)
     v1080 = synth.look_at((15.0, -2.0, -20.0), width=1920, height=1080, s_v=1.0)
@@ -95,9 +98,9 @@ def test_lod_sweep_6m_frames_bitexact_at_four_distances():
     on the -z axis) at k = 0, 21, 42, 56, 63: the far frames hold the longest tile lists of any
     workload (at k = 56 and 63 lists of 65,536 entries or more, walked compacted per 4x4 block).
     Counts, pair count, last index, T and colour of every pixel bit-identical."""
-    log("case: 6M LoD sweep frames")
-    sc = synth.make_scene(6_000_000, 3, "mixture", seed=0)
-    scene = Scene(sc, packed_sh=True)
+    log("case: 6M LoD sweep frames, scene in Morton order")
+    scene = Scene(synth.make_scene(6_000_000, 3, "mixture", seed=0), packed_sh=True, spatial_order=True)
+    sc = stored_planes(scene)
     ds = synth.sweep_distances(64, 2.0, 200.0)
     for k in (0, 21, 42, 56, 63):
         view = synth.look_at((0.0, 0.0, -float(ds[k])), width=1920, height=1080)
