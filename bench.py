@@ -254,7 +254,7 @@ def run_train(args, torch, C, Batch, Scene, synth):
     n = 1_000_000
     log(f"[bench] training: {n} Gaussians, SH degree 3, 1297x840")
     sc = synth.make_scene(n, 3, "mixture", seed=0)
-    scene = Scene(sc)
+    scene = Scene(sc, spatial_order=True)   # stored in Morton order of the means (clod_scene_reorder)
     del sc
     K, W = args.train_steps, 5
     views = synth.random_views(0, K + W, radius=(4.0, 6.0), resolutions=((1297, 840),), sv_range=(1.0, 8.0))
@@ -347,7 +347,7 @@ def run_multiview_train(args, torch, C, Scene, synth):
     from paper_2510_09997_amd.train import MultiViewTrainer
     n = 2_000_000
     sc = synth.make_scene(n, 3, "mixture", seed=0)
-    scene = Scene(sc)
+    scene = Scene(sc, spatial_order=True)   # stored in Morton order of the means (clod_scene_reorder)
     del sc
     res = ((640, 480), (1297, 840), (1920, 1080))
     K, W = args.train_steps, 5

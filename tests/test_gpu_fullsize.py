@@ -7,7 +7,8 @@
   count, last-contributor indices, transmittance and colour of every pixel of every frame
   bit-identical to the oracle.
 * Training step: 1,000,000 Gaussians at 1297x840 (L1 + point-count regulariser) and the
-  16-view step over 2,000,000 Gaussians (640x480 / 1297x840 / 1920x1080): counts bit-identical;
+  16-view step over 2,000,000 Gaussians (640x480 / 1297x840 / 1920x1080), both scenes stored in
+  Morton order as the benchmark stores them: counts bit-identical;
   for sampled Gaussians every parameter gradient within 1e-4 of FP64 autograd restricted to
   the tiles they cover.
 * Continuous-LoD sweep: 6,000,000 Gaussians, 64 distances log-spaced in [2, 200] along one ray
@@ -164,9 +165,9 @@ def _sampled_gradient_parity(sc, views, pix, counts, dL, deta, got, rng, per_vie
 
 
 def test_training_step_1m_full_size_sampled_gradients():
-    log("case: 1M single-view training step at 1297x840")
-    sc = synth.make_scene(1_000_000, 3, "mixture", seed=0)
-    scene = Scene(sc)
+    log("case: 1M single-view training step at 1297x840, scene in Morton order")
+    scene = Scene(synth.make_scene(1_000_000, 3, "mixture", seed=0), spatial_order=True)
+    sc = stored_planes(scene)
     view = synth.random_views(0, 1, radius=(4.0, 6.0), resolutions=((1297, 840),), sv_range=(1.0, 8.0))[0]
     target = torch.from_numpy(synth.random_target(0, 840, 1297).reshape(-1)).cuda()
     b = Batch(sc["n"], [view], params_struct(None))
@@ -181,9 +182,9 @@ def test_training_step_1m_full_size_sampled_gradients():
 
 
 def test_sixteen_view_step_2m_full_size_sampled_gradients():
-    log("case: 2M 16-view training step")
-    sc = synth.make_scene(2_000_000, 3, "mixture", seed=0)
-    scene = Scene(sc)
+    log("case: 2M 16-view training step, scene in Morton order")
+    scene = Scene(synth.make_scene(2_000_000, 3, "mixture", seed=0), spatial_order=True)
+    sc = stored_planes(scene)
     res = ((640, 480), (1297, 840), (1920, 1080))
     views = synth.random_views(7, 16, radius=(4.0, 6.0), resolutions=res, sv_range=(1.0, 8.0))
     tr = MultiViewTrainer(scene, views, s_max=8.0)
