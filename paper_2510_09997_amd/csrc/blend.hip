@@ -219,13 +219,15 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
   // per-entry predicates below are formed as lane masks and turned back into execution masks
   // with inverse ballots, so the termination bookkeeping stays in scalar registers.
   uint64_t dm = ballot64(!own);
-  // 4x4 blocks: the entries of a batch that may reach the block, four at a time.  Row g of the
-  // wave evaluates entry g of the group for the block's 16 pixels (power, live test,
-  // exponential, clamp: the four exponentials are computed side by side); row 0 then takes the
-  // four entries in list order through the contract's termination test and blend, the same
-  // operations in the same order as one entry at a time.  Terminated pixels (dm, bits 0..15)
-  // drop out of the later entries of a group; their values for those entries are never used.
-  auto walk4 = [&](uint64_t mask) {
+  // 4x4 blocks: the n entries of a batch that may reach the block (staged compacted in list
+  // order, slots 0 .. n-1), four at a time.  Row g of the wave evaluates entry g of the group
+  // for the block's 16 pixels (power, live test, exponential, clamp: the four exponentials are
+  // computed side by side, on every lane: lanes outside the live set are masked off after);
+  // row 0 then takes the four entries in list order through the contract's termination test
+  // and blend, the same operations in the same order as one entry at a time.  Terminated
+  // pixels (dm, bits 0..15) drop out of the later entries of a group; their values for those
+  // entries are never used.
+  auto walk4 = [&](const uint32_t n) {
     const uint32_t row = lane >> 4;
     // One entry of the group for row 0's pixels: alpha (valid on the live lanes lv, bits
     // 0..15), the entry's colour and list position.
@@ -233,8 +235,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
                     const uint32_t pos) {
       const uint64_t lm = lv & ~dm & 0xFFFFull;
       if (lm == 0ull) return;
-      float Tn = al;
-      if (__builtin_amdgcn_inverse_ballot_w64(lm)) Tn = T * (1.0f - al);
+      const float Tn = T * (1.0f - al);   // used on the live lanes only
       const uint64_t um = ballot64(al >= kSkip) & lm;
       const uint64_t km = ballot64(Tn >= kTmin);
       const uint64_t bm = um & km;
@@ -253,33 +254,23 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
         nblend += __builtin_amdgcn_inverse_ballot_w64(bm) ? 1u : 0u;
       }
     };
-    while (mask != 0ull && dm != ~0ull) {
-      const int f0 = __builtin_ctzll(mask);
-      mask &= mask - 1;
-      const bool h1 = mask != 0ull;
-      const int f1 = h1 ? __builtin_ctzll(mask) : f0;
-      mask &= mask - 1;
-      const bool h2 = mask != 0ull;
-      const int f2 = h2 ? __builtin_ctzll(mask) : f0;
-      mask &= mask - 1;
-      const bool h3 = mask != 0ull;
-      const int f3 = h3 ? __builtin_ctzll(mask) : f0;
-      mask &= mask - 1;
-      const int fr = row == 0u ? f0 : row == 1u ? f1 : row == 2u ? f2 : f3;
+    // Slots k .. k + 3 lie in the wave's 64-entry slice (k is a multiple of 4 below n <= 64);
+    // those at or past n hold stale entries, masked off by `slots`.
+    for (uint32_t k = 0; k < n; k += 4) {
+      const uint32_t fr = k + row;
       const float4 a = s0[fr], c = s1[fr];
       const float4 bc = s2[fr];
       // Colours and list positions of entries 1..3 for row 0 (LDS broadcasts).
-      const float4 q1 = s1[f1], q2 = s1[f2], q3 = s1[f3];
-      const float4 r1 = s2[f1], r2 = s2[f2], r3 = s2[f3];
+      const float4 q1 = s1[k + 1u], q2 = s1[k + 2u], q3 = s1[k + 3u];
+      const float4 r1 = s2[k + 1u], r2 = s2[k + 2u], r3 = s2[k + 3u];
       const float dx = a.x - pcx, dy = a.y - pcy;
       const float power = fmaf_(a.z * dx, dx, fmaf_(c.x * dy, dy, (a.w * dx) * dy));
-      const uint64_t slots = 0xFFFFull | (h1 ? 0xFFFF0000ull : 0ull) | (h2 ? 0xFFFF00000000ull : 0ull) |
-                             (h3 ? 0xFFFF000000000000ull : 0ull);
+      const uint32_t left = n - k;
+      const uint64_t slots = left >= 4u ? ~0ull : (1ull << (16u * left)) - 1ull;
       const uint64_t dm4 = (dm & 0xFFFFull) * 0x0001000100010001ull;
       const uint64_t live = ballot64(power <= 0.0f) & ballot64(power >= bc.y) & ~dm4 & slots;
       if (live == 0ull) continue;
-      float al = power;
-      if (__builtin_amdgcn_inverse_ballot_w64(live)) al = fminf(0.99f, c.y * cexp_core(power));
+      const float al = fminf(0.99f, c.y * cexp_core<true>(power));
       // Rows 1, 2, 3 of al into row 0 (whole-wave row swaps).
       const auto x16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(al), __float_as_uint(al), false, false);
       const auto x32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(al), __float_as_uint(al), false, false);
@@ -288,6 +279,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       step(__uint_as_float(x16[1]), live >> 16, q1.z, q1.w, r1.x, __float_as_uint(r1.z));
       step(__uint_as_float(x32[1]), live >> 32, q2.z, q2.w, r2.x, __float_as_uint(r2.z));
       step(__uint_as_float(x48[1]), live >> 48, q3.z, q3.w, r3.x, __float_as_uint(r3.z));
+      if (dm == ~0ull) break;
     }
   };
   // One batch of up to 64 entries, its records (g0, g1, g2) already in registers, lane l's
@@ -308,17 +300,13 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
       }
     } else if (j < rg.y) {
       cut = entry_cut(g0.z);
-      if constexpr (kB == 4) {
-        s0[lane] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
-        s1[lane] = make_float4(-0.5f * g1.z, g0.z, g2.x, g2.y);
-        s2[lane] = make_float4(g2.z, cut, __uint_as_float(j - rg.x), 0.f);
-      }
       rel = (quadrant_mask1<kB>(g0.x, g0.y, g1.x, g1.y, g1.z, g0.w, cut, fqx, fqy)) != 0u;
     }
     uint64_t mask = ballot64(rel);
-    // 8x8 quadrants: the entries that may reach the quadrant are staged compacted, in list
-    // order (slot = rank of the lane among them), so that the walk below steps a counter.
-    if constexpr (kB == 8) {
+    // The entries that may reach the quadrant (block) are staged compacted, in list order
+    // (slot = rank of the lane among them), so that the walks below step a counter.  (Those of
+    // a very long tile are the leading lanes already.)
+    if (!(kB == 4 && pre)) {
       if (rel) {
         const uint32_t slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
         s0[slot] = make_float4(g0.x, g0.y, -0.5f * g1.x, -g1.y);
@@ -337,7 +325,7 @@ __device__ __forceinline__ void blend_tile(const BlendArgs& a, uint32_t pos, Til
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (mask == 0ull) return;
     if constexpr (kB == 4) {
-      walk4(mask);
+      walk4(n);
       return;
     }
     // One entry: the contract's skip, exponential, clamp, termination and blend.  Below the
