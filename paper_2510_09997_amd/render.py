@@ -33,6 +33,8 @@ class Scene:
         self.perm = None
         self.sh_packed = None
         if spatial_order and self.n > 0:
+            if self.t["mean"].device.type != "cuda":
+                raise ValueError("spatial_order needs the scene on the GPU (clod_scene_reorder takes device planes)")
             dst = {k: torch.empty_like(v) for k, v in self.t.items()}
             perm = torch.empty(self.n, dtype=torch.int32, device=device)
             ws = torch.empty(C.clod_scene_reorder_ws_bytes(self.n), dtype=torch.uint8, device=device)

@@ -274,3 +274,12 @@ def test_scene_reorder_rejects_invalid_arguments_before_launch(case):
     elif case == "degree_4":
         src.sh_degree = 4
     assert C.load().clod_scene_reorder(ctypes.byref(src), dst_arg, perm, ws, nbytes, None) == C.CLOD_E_ARG, case
+
+
+def test_scene_order_refuses_host_planes():
+    """The reorder runs on device planes only: a scene kept in host memory is refused before any
+    library call."""
+    from paper_2510_09997_amd.render import Scene
+    sc = synth.make_scene(100, 0, "uniform", seed=0)
+    with pytest.raises(ValueError):
+        Scene(sc, device="cpu", spatial_order=True)
