@@ -710,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
     unsigned long long* __restrict__ pair_part) {
   __shared__ float4 s0[kBlock];   // u, v, A, B
   __shared__ float4 s1[kBlock];   // C, alpha'', r, g
-  __shared__ float4 s2[kBlock];   // b, power cut, -, - (same stride as s0, s1: one address)
+  __shared__ float4 s2[kBlock];   // b, power cut, -A/2, -C/2 (same stride as s0, s1: one address)
   __shared__ float acc[kBlock * kGscreen];   // [entry][9]: odd stride, conflict-free
   __shared__ uint32_t sidx[kBlock];
   __shared__ unsigned long long qmask[4][4];    // [staging wave][quadrant]: entries that may reach it
@@ -770,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
       const float cut = entry_cut(a0.z);
       s0[threadIdx.x] = make_float4(a0.x, a0.y, a1.x, a1.y);
       s1[threadIdx.x] = make_float4(a1.z, a0.z, a2.x, a2.y);
-      s2[threadIdx.x] = make_float4(a2.z, cut, 0.f, 0.f);
+      s2[threadIdx.x] = make_float4(a2.z, cut, -0.5f * a1.x, -0.5f * a1.z);
       sidx[threadIdx.x] = f;
       qm = quadrant_mask(a0.x, a0.y, a1.x, a1.y, a1.z, a0.w, cut, tx0, ty0);
     }
@@ -797,7 +797,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(
         const float4 c4 = s1[k];
         const float4 bc = s2[k];
         const float dx = a.x - pcx, dy = a.y - pcy;
-        const float hA = -0.5f * a.z, nB = -a.w, hC = -0.5f * c4.x;
+        const float hA = bc.z, nB = -a.w, hC = bc.w;   // -A/2 and -C/2 staged once per entry
         const float power = fmaf_(hA * dx, dx, fmaf_(hC * dy, dy, (nB * dx) * dy));
         // Live: blended in the forward (position < last) with power in [cut, 0].  Other lanes
         // compute discarded values (finite: their powers are tiny positives or below cut).
