@@ -58,11 +58,13 @@ def reorder(sc):
     return scene, perm, planes
 
 
-@pytest.mark.parametrize("n, kind, special", [(100_003, "uniform", True), (250_000, "mixture", False),
-                                              (1, "uniform", False), (4097, "uniform", "same")])
-def test_permutation_is_the_stable_morton_order_and_planes_follow_it(n, kind, special):
-    log(f"case: reorder n={n} {kind} special={special}")
-    sc = synth.make_scene(n, 3, kind, seed=5)
+@pytest.mark.parametrize("n, kind, special, deg", [(100_003, "uniform", True, 3), (250_000, "mixture", False, 3),
+                                                   (1, "uniform", False, 3), (4097, "uniform", "same", 3),
+                                                   (30_001, "mixture", False, 0), (20_000, "uniform", False, 1),
+                                                   (70_000, "mixture", True, 2)])
+def test_permutation_is_the_stable_morton_order_and_planes_follow_it(n, kind, special, deg):
+    log(f"case: reorder n={n} {kind} special={special} degree={deg}")
+    sc = synth.make_scene(n, deg, kind, seed=5)
     if special is True:
         # Non-finite coordinates clamp to the box faces; they do not widen the box.
         rng = np.random.default_rng(3)
