@@ -42,6 +42,9 @@ struct DevView {
   uint32_t tile_base, pix_base, loss_block_base, rgn_base;   // rgn_base: first 32 x 32 SSIM region
   int32_t ftiles_x, ftiles_y;    // tiles of the frame (the view's own when it is not a viewport)
   int32_t vx, vy;                // viewport origin in the frame, pixels (multiples of 16)
+  int32_t cam_lead;              // first view of this view's run of consecutive views with the same
+                                 // camera (pose, intrinsics, size, frame): they differ in s_v or
+                                 // budget only, so positions, projections and colours are shared
   int64_t budget;                // 0: threshold mask; K > 0: the K largest selection keys
   unsigned long long mkey;       // K > 0: smallest kept selection key (set by the radix select)
 };
@@ -219,13 +222,17 @@ __device__ __forceinline__ float decay_den(float decay, float eps) {
 
 // Eq. (2) for one view with the per-Gaussian parts (alpha = sigmoid of the opacity logit and
 // the decay denominator) computed once and passed in; returns alpha'' and q.
-__device__ __forceinline__ float attenuated_pre(float d, float dmax, float s_v, float alpha, float den,
-                                                float& q) {
-  const float dn = d / dmax;
+// From the normalised distance dn = d / d_max (the camera's part, shared by views that differ
+// only in s_v).
+__device__ __forceinline__ float attenuated_dn(float dn, float s_v, float alpha, float den, float& q) {
   const float u = dn * s_v;
   const float num = u * u;
   q = num / den;
   return alpha * cexp(-q);
+}
+__device__ __forceinline__ float attenuated_pre(float d, float dmax, float s_v, float alpha, float den,
+                                                float& q) {
+  return attenuated_dn(d / dmax, s_v, alpha, den, q);
 }
 
 // Attenuated opacity of Eq. (2) (also returns alpha and q for the adjoint).

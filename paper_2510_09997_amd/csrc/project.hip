@@ -19,9 +19,24 @@ __device__ __forceinline__ void view_setup_body(const ViewSetupArgs& a, Blk b) {
   if (a.hdr && b.id == 0 && threadIdx.x < (unsigned)kHdrWords) a.hdr[threadIdx.x] = 0ull;
   if (threadIdx.x != 0 || b.id != 0) return;
   uint32_t tile_base = 0, pix_base = 0, loss_base = 0, rgn_base = 0;
+  // Same camera: every field the positions, projections and colours depend on, bit for bit.
+  auto same_camera = [](const clod_view& p, const clod_view& q) {
+    for (int j = 0; j < 9; ++j)
+      if (__float_as_uint(p.W[j]) != __float_as_uint(q.W[j])) return false;
+    for (int j = 0; j < 3; ++j)
+      if (__float_as_uint(p.t[j]) != __float_as_uint(q.t[j]) || __float_as_uint(p.c[j]) != __float_as_uint(q.c[j]))
+        return false;
+    return __float_as_uint(p.fx) == __float_as_uint(q.fx) && __float_as_uint(p.fy) == __float_as_uint(q.fy) &&
+           __float_as_uint(p.cx) == __float_as_uint(q.cx) && __float_as_uint(p.cy) == __float_as_uint(q.cy) &&
+           p.width == q.width && p.height == q.height && p.frame_width == q.frame_width &&
+           p.frame_height == q.frame_height && p.vx == q.vx && p.vy == q.vy;
+  };
+  int lead = 0;
   for (int v = 0; v < V; ++v) {
     const clod_view& cv = views[v];
     DevView d;
+    if (v == 0 || !same_camera(cv, views[v - 1])) lead = v;
+    d.cam_lead = lead;
     for (int j = 0; j < 9; ++j) d.W[j] = cv.W[j];
     for (int j = 0; j < 3; ++j) { d.t[j] = cv.t[j]; d.c[j] = cv.c[j]; }
     d.fx = cv.fx; d.fy = cv.fy; d.cx = cv.cx; d.cy = cv.cy;
@@ -255,18 +270,28 @@ __device__ __forceinline__ void classify_body(const ClassifyArgs& a, Blk b, uint
       }
     }
     bool any = false;
+    // The camera's part (frustum flag, distance, d / d_max) of the previous view, reused by the
+    // views of the same camera run (which have the same frustum maximum).
+    int lead = -1;
+    bool F = false;
+    float d = 0.f, dn = 0.f;
     for (int v = 0; v < V; ++v) {
       const DevView& Vw = views[v];
-      bool F = false, M = false;
+      bool M = false;
+      if (!valid) F = false;
       if (valid) {
-        float x, y, z, ex, ey, ez;
-        to_camera(Vw, mx, my, mz, x, y, z);
-        F = in_frustum(Vw, x, y, z, prm.near_z);
-        const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
         const unsigned long long dk = dmax_key[v];
+        if (Vw.cam_lead != lead) {
+          float x, y, z, ex, ey, ez;
+          to_camera(Vw, mx, my, mz, x, y, z);
+          F = in_frustum(Vw, x, y, z, prm.near_z);
+          d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
+          dn = d / dmax_from_key(dk);
+          lead = Vw.cam_lead;
+        }
         if (F && dk != 0ull && __float_as_uint(d) == (uint32_t)(dk >> 32)) atomicMin(&scnt[3 * v + 2], (uint32_t)i);
         float q;
-        const float a2 = attenuated_pre(d, dmax_from_key(dk), Vw.s_v, alpha, den, q);
+        const float a2 = attenuated_dn(dn, Vw.s_v, alpha, den, q);
         M = lod_kept(Vw, a2, i);
         if (kWrite) {
           const int64_t f = (int64_t)v * n + i;
@@ -373,6 +398,13 @@ __device__ __forceinline__ void project_body(const ProjectArgs& a, Blk b, uint32
     // Rotation and 3D covariance are view independent: computed on first use.
     bool have_cov = false;
     float S[9];
+    // The projection (and below the colour) of the last camera run evaluated: views of one run
+    // share them (only alpha'' and the mask depend on s_v).
+    int geo_lead = -1, col_lead = -1;
+    Proj P;
+    bool pok = false;
+    float col[3] = {0.f, 0.f, 0.f};
+    uint8_t cfl = 0;
     for (int v0 = 0; v0 < V; v0 += 32) {
       const int vn = V - v0 < 32 ? V - v0 : 32;
       uint32_t rmask = 0;   // rendered views of the group
@@ -395,8 +427,11 @@ __device__ __forceinline__ void project_body(const ProjectArgs& a, Blk b, uint32
               cov3(Rm, s0, s1, s2, S);
               have_cov = true;
             }
-            Proj P;
-            if (ewa(Vw, x, y, z, S, prm.dilation, P)) {
+            if (Vw.cam_lead != geo_lead) {
+              pok = ewa(Vw, x, y, z, S, prm.dilation, P);
+              geo_lead = Vw.cam_lead;
+            }
+            if (pok) {
               R = true;
               if (kWriteRecords) {
                 const int64_t f = (int64_t)v * n + i;
@@ -433,6 +468,8 @@ __device__ __forceinline__ void project_body(const ProjectArgs& a, Blk b, uint32
           const int v = v0 + vv;
           const DevView& Vw = views[v];
           const int64_t f = (int64_t)v * n + i;
+          if (Vw.cam_lead != col_lead) {
+          col_lead = Vw.cam_lead;
           float ex, ey, ez;
           const float d = cam_distance(Vw, mx, my, mz, ex, ey, ez);
           const float id = 1.0f / d;
@@ -469,16 +506,16 @@ __device__ __forceinline__ void project_body(const ProjectArgs& a, Blk b, uint32
               acc[ch] = a;
             }
           }
-          uint8_t fl = 1u | 2u | 4u;   // rendered implies in frustum and kept
-          float col[3];
+          cfl = 1u | 2u | 4u;   // rendered implies in frustum and kept
 #pragma unroll
           for (int ch = 0; ch < 3; ++ch) {
             const float cv = acc[ch] + 0.5f;
-            if (!(cv > 0.0f)) fl |= (uint8_t)(8 << ch);
+            if (!(cv > 0.0f)) cfl |= (uint8_t)(8 << ch);
             col[ch] = fmaxf(cv, 0.0f);
           }
+          }
           rec[kRecQuads * f + 2] = make_float4(col[0], col[1], col[2], 0.f);
-          flags_out[f] = fl;
+          flags_out[f] = cfl;
         }
       }
     }
