@@ -168,6 +168,12 @@ __device__ __forceinline__ void frustum_max_body(const FrustumArgs& a, Blk b) {
   block_chunk(n, b, lo, hi);
   for (int v0 = 0; v0 < V; v0 += kVG) {
     const int vn = V - v0 < kVG ? V - v0 : kVG;
+    // A view whose camera run started earlier in this group takes its lead's maximum (same
+    // camera, same frustum, same distances) instead of evaluating the Gaussians again.
+    uint32_t shared = 0u;   // bit vv: view v0 + vv copies its lead's key
+#pragma unroll
+    for (int vv = 0; vv < kVG; ++vv)
+      if (vv < vn && views[v0 + vv].cam_lead != v0 + vv && views[v0 + vv].cam_lead >= v0) shared |= 1u << vv;
     uint32_t key[kVG];
 #pragma unroll
     for (int vv = 0; vv < kVG; ++vv) key[vv] = 0u;
@@ -188,6 +194,7 @@ __device__ __forceinline__ void frustum_max_body(const FrustumArgs& a, Blk b) {
 #pragma unroll
         for (int vv = 0; vv < kVG; ++vv) {
           if (vv >= vn) break;
+          if ((shared >> vv) & 1u) continue;
           const DevView& Vw = views[v0 + vv];
           float x, y, z, ex, ey, ez;
           to_camera(Vw, px[k], py[k], pz[k], x, y, z);
@@ -198,6 +205,10 @@ __device__ __forceinline__ void frustum_max_body(const FrustumArgs& a, Blk b) {
         }
       }
     }
+    // (A run's views are consecutive: each shared view copies the one before it.)
+#pragma unroll
+    for (int vv = 1; vv < kVG; ++vv)
+      if ((shared >> vv) & 1u) key[vv] = key[vv - 1];
 #pragma unroll
     for (int vv = 0; vv < kVG; ++vv) {
 #pragma unroll
