@@ -780,7 +780,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # timed launches (bench.py --profile timed-blend runs exactly those launches; the timed poses do
 # not depend on the warm-up count), each scaled by the same counter's reading for a 1 GiB device
 # copy (profiles/k_blend_fwd_serve1080p_3M_hbm.txt).  Emptied whenever the kernel changes.
-TRAFFIC = {"k_blend_fwd": 942780875}
+TRAFFIC = {"k_blend_fwd": 944650690}
 
 
 def probe_copy(torch):
