@@ -404,3 +404,27 @@ def test_serving_size_sampled_parity():
     # The whole image, too (the oracle has it anyway).
     assert np.array_equal(g["last"][0], r["last"])
     assert np.abs(g["rgb"][0] - r["rgb"]).max() == 0.0
+
+
+def test_views_sharing_a_camera_bitexact():
+    """Views of one camera that differ in s_v or budget share the camera's positions, projections
+    and colours inside the library (runs of consecutive views).  Cases: a run in decreasing s_v
+    (its first view masks Gaussians that the later ones render), a budgeted view inside a run,
+    a different camera between two views of the first one (which starts a new run), and the
+    frame's viewports with their own s_v (not one camera: different sizes)."""
+    log("case: camera runs")
+    import dataclasses
+    sc = synth.make_scene(30000, 3, "mixture", seed=4)
+    a = synth.look_at((3.0, -2.0, -8.0), width=160, height=120)
+    b = synth.look_at((-7.0, 1.0, 4.0), width=96, height=80, s_v=2.0)
+    views = [dataclasses.replace(a, s_v=s) for s in (16.0, 4.0, 1.0)]
+    views.append(dataclasses.replace(a, s_v=2.0, budget=2500))
+    views.append(b)
+    views.append(dataclasses.replace(a, s_v=1.5))
+    views += synth.strips(synth.look_at((0.5, 3.0, -7.0), width=128, height=128), [8.0, 2.0])
+    g = gpu_forward(sc, views)
+    compare_forward(g, sc, views)
+    # The s_v = 1 view of the run equals the same camera rendered alone.
+    alone = gpu_forward(sc, [views[2]])
+    for key in ("last", "T", "rgb"):
+        assert np.array_equal(g[key][2].view(np.uint32), alone[key][0].view(np.uint32)), key
