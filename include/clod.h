@@ -132,7 +132,10 @@ int64_t clod_dup_capacity(size_t dup_bytes);
    receives {n_frustum, n_mask, n_rendered}; eta_dev (nullable, device float [n_views]) receives
    the kept ratio eta_actual = n_mask / n of Sec. 3.3, Eq. (4) (binary32 quotient of the two
    counts rounded to binary32; 0 when n = 0).  The results stay in batch->ws for the calls
-   below. */
+   below.  Consecutive views with the same camera (pose, intrinsics, size, frame and viewport,
+   bit for bit), such as the LoD frames of one pose at several s_v, share the camera-dependent
+   work (frustum maximum, distances, projection, colour); the results are the same as for
+   separate batches. */
 clod_status clod_project(const clod_scene *scene, const clod_batch *batch, int64_t *counts_dev,
                          float *eta_dev, void *stream);
 
